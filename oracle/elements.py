@@ -1,0 +1,171 @@
+"""Reference elements and the dense operator matrices of the paper.
+Test infrastructure only.
+
+Reference elements
+  hex   [-1,1]^3.  Solution points GL(n)^3 (n = p+1), index i + n(j + n k).
+        Faces 0..5 = xi-, xi+, eta-, eta+, zeta-, zeta+; each carries GL(n)^2
+        flux points, index a + n b over the two tangential coordinates in
+        increasing axis order.
+  prism triangle {xi, eta >= -1, xi + eta <= 0} x zeta in [-1,1].  Solution
+        points = triangle nodes (N_t) x GL(n), index t + N_t k (section 4.1).
+        Faces 0,1 = zeta -1/+1 (flux points at the triangle nodes); faces
+        2,3,4 = the quadrilaterals eta = -1, xi + eta = 0, xi = -1 with GL(n)
+        points along the edge (parameter s, edges run counter-clockwise) times
+        GL(n) in zeta, index a + n b.
+Anti-aliasing quadrature (section 2.1.1): hex GL(m)^3; prism conical triangle
+rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default.
+
+Operators (section 2.2; shapes as implied by the products):
+  M0[f, u]     = l_u(x^f)                               disu
+  Dg[d, s, u]  = d l_u / d xi_d (x^u_s)                 M4 (gradient) and M1
+  M3[u, f]     = (div g_f)(x^u); DG correction functions, i.e. the lifting
+                 Mass^-1 int_face l l^face_f dS_ref     tdivtconf
+  M6[d, u, f]  = n_d(f) M3[u, f]                        tgradcoru
+  M7[q, u]     = l_u(x^q)                               uqpts / gradcoru_qpts
+  M8[u, q]     = L2 projection, Mass^-1 L_q^T W_q       (eq. FR-tdivtpcorfq)
+  wu[u]        = int l_u  (integration weights for conservation checks)
+The correction-function family is not fixed by the paper (it defers to
+Vincent et al. 2011); the DG choice is taken (a reading).
+"""
+
+import numpy as np
+
+from . import basis, quadrature
+
+
+class RefElement:
+    def __init__(self, etype, p, m=None, tri_nodes=None):
+        if m is None:
+            m = p + 3
+        self.etype, self.p, self.n, self.m = etype, p, p + 1, m
+        n = self.n
+        gl, glw = quadrature.gauss_legendre(n)
+        self.gl, self.glw = gl, glw
+        if etype == "hex":
+            self._build_hex(gl)
+        elif etype == "prism":
+            self._build_prism(gl, tri_nodes)
+        else:
+            raise ValueError(etype)
+        self.nu, self.nf, self.nq = len(self.upts), len(self.fpts), len(self.qpts)
+        self._build_operators()
+
+    # ------------------------------------------------------------------ hex
+    def _build_hex(self, gl):
+        n, m = self.n, self.m
+        self.upts = np.array([(gl[i], gl[j], gl[k]) for k in range(n) for j in range(n) for i in range(n)])
+        self.nfaces = 6
+        faces = []
+        for axis in range(3):
+            for sgn in (-1.0, 1.0):
+                tang = [a for a in range(3) if a != axis]
+
+                def fmap(s, t, axis=axis, sgn=sgn, tang=tang):
+                    x = np.zeros((len(s), 3))
+                    x[:, axis] = sgn
+                    x[:, tang[0]] = s
+                    x[:, tang[1]] = t
+                    return x
+
+                nrm = np.zeros(3)
+                nrm[axis] = sgn
+                faces.append(dict(kind="quad", map=fmap, normal=nrm, jac=1.0))
+        self.faces = faces
+        self._quad_face_points(gl)
+        qx, qw = quadrature.gauss_legendre(m)
+        self.qpts = np.array([(qx[i], qx[j], qx[k]) for k in range(m) for j in range(m) for i in range(m)])
+        self.qwts = np.array([qw[i] * qw[j] * qw[k] for k in range(m) for j in range(m) for i in range(m)])
+
+    # ---------------------------------------------------------------- prism
+    def _build_prism(self, gl, tri_nodes):
+        p, n, m = self.p, self.n, self.m
+        tn = quadrature.triangle_nodes(p) if tri_nodes is None else np.asarray(tri_nodes, float)
+        self.tri_nodes = tn
+        self.nt = len(tn)
+        self.upts = np.array([(tn[t, 0], tn[t, 1], gl[k]) for k in range(n) for t in range(self.nt)])
+        self.nfaces = 5
+        faces = []
+        for sgn in (-1.0, 1.0):
+            def tmap(xi, eta, sgn=sgn):
+                return np.stack([xi, eta, np.full_like(xi, sgn)], axis=1)
+            faces.append(dict(kind="tri", map=tmap, normal=np.array([0.0, 0.0, sgn]), jac=1.0))
+        # edges run counter-clockwise: v0=(-1,-1) -> v1=(1,-1) -> v2=(-1,1) -> v0
+        edges = [
+            (lambda s: (s, -np.ones_like(s)), np.array([0.0, -1.0, 0.0]), 1.0),
+            (lambda s: (-s, s), np.array([1.0, 1.0, 0.0]) / np.sqrt(2.0), np.sqrt(2.0)),
+            (lambda s: (-np.ones_like(s), -s), np.array([-1.0, 0.0, 0.0]), 1.0),
+        ]
+        for emap, nrm, jac in edges:
+            def qmap(s, t, emap=emap):
+                xi, eta = emap(s)
+                return np.stack([xi, eta, t], axis=1)
+            faces.append(dict(kind="quad", map=qmap, normal=nrm, jac=jac))
+        self.faces = faces
+        fp, fid = [], []
+        for f, fc in enumerate(faces):
+            if fc["kind"] == "tri":
+                x = fc["map"](tn[:, 0], tn[:, 1])
+            else:
+                s = np.array([gl[a] for b in range(n) for a in range(n)])
+                t = np.array([gl[b] for b in range(n) for a in range(n)])
+                x = fc["map"](s, t)
+            fp.append(x)
+            fid += [f] * len(x)
+        self.fpts = np.concatenate(fp)
+        self.fface = np.array(fid)
+        self.fnorm = np.array([faces[f]["normal"] for f in self.fface])
+        tq, tw = quadrature.triangle_conical(p + 1)
+        lq, lw = quadrature.gauss_legendre(m)
+        self.qpts = np.array([(tq[t, 0], tq[t, 1], lq[k]) for k in range(m) for t in range(len(tq))])
+        self.qwts = np.array([tw[t] * lw[k] for k in range(m) for t in range(len(tq))])
+
+    def _quad_face_points(self, gl):
+        n = self.n
+        s = np.array([gl[a] for b in range(n) for a in range(n)])
+        t = np.array([gl[b] for b in range(n) for a in range(n)])
+        fp, fid = [], []
+        for f, fc in enumerate(self.faces):
+            fp.append(fc["map"](s, t))
+            fid += [f] * (n * n)
+        self.fpts = np.concatenate(fp)
+        self.fface = np.array(fid)
+        self.fnorm = np.array([self.faces[f]["normal"] for f in self.fface])
+
+    # ------------------------------------------------------------ operators
+    def _build_operators(self):
+        et, p, n = self.etype, self.p, self.n
+        up = self.upts
+        self.M0, _ = basis.nodal(et, p, up, self.fpts)
+        _, Dg = basis.nodal(et, p, up, up)
+        self.Dg = Dg
+        Lq, _ = basis.nodal(et, p, up, self.qpts)
+        self.M7 = Lq
+        W = np.diag(self.qwts)
+        mass = Lq.T @ W @ Lq
+        self.mass = mass
+        self.M8 = np.linalg.solve(mass, Lq.T @ W)
+        self.wu = Lq.T @ self.qwts
+
+        # DG lifting: E[u, f] = int_face(f) l_u l^face_f dS_ref
+        E = np.zeros((self.nu, self.nf))
+        gl = self.gl
+        for fidx, fc in enumerate(self.faces):
+            cols = np.nonzero(self.fface == fidx)[0]
+            if fc["kind"] == "quad":
+                g, gw = quadrature.gauss_legendre(n + 1)
+                s = np.array([g[a] for b in range(n + 1) for a in range(n + 1)])
+                t = np.array([g[b] for b in range(n + 1) for a in range(n + 1)])
+                w = np.array([gw[a] * gw[b] for b in range(n + 1) for a in range(n + 1)]) * fc["jac"]
+                xs = fc["map"](s, t)
+                Ls = basis.line_nodal(gl, s)
+                Lt = basis.line_nodal(gl, t)
+                lface = np.stack([Ls[:, a] * Lt[:, b] for b in range(n) for a in range(n)], axis=1)
+            else:
+                tq, tw = quadrature.triangle_conical(p + 1)
+                xs = fc["map"](tq[:, 0], tq[:, 1])
+                w = tw * fc["jac"]
+                lface = basis.tri_nodal(p, self.tri_nodes, tq)
+            Lv, _ = basis.nodal(et, p, up, xs)
+            E[:, cols] = Lv.T @ (w[:, None] * lface)
+        self.M3 = np.linalg.solve(mass, E)
+        self.M6 = self.fnorm.T[:, None, :] * self.M3[None, :, :]

@@ -1,0 +1,160 @@
+"""Periodic box meshes, affine metrics and flux-point pairing.
+Test infrastructure only.
+
+Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
+  kind "hex"   : one axis-aligned hexahedron per cell.
+  kind "prism" : two prisms per cell.  The cell's x-z square is split by the
+                 diagonal from (x0+h, z0) to (x0, z0+h) and extruded along y,
+                 so each z = const cell face is one full prism quadrilateral
+                 (required for conforming hex-prism interfaces).  Prism "A"
+                 holds the corner (x0, z0), prism "B" the corner (x0+h, z0+h).
+                 Maps (positive Jacobian):
+                   A: x = x0 + (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + (xi+1) h/2
+                   B: x = x0 + h - (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + h - (xi+1) h/2
+  kind "mixed" : hexahedra in cells whose centre has z < 0, prisms elsewhere.
+Element numbering: cells in index order; a prism cell yields A then B.  The
+position in that sequence is the global element id; each element type keeps
+its own elements in order of appearance.
+
+Pairing (section 2.1: paired flux points coincide in physical space) is done
+by physical coordinates modulo the period.  Which side of a pair is "L" is
+not fixed by the paper (the common solution is asymmetric, so each pair must
+be visited once); the reading used: L is the element with the lower global
+id; for an element paired with itself across the periodic boundary, L is the
+face whose centroid is lexicographically smaller in (x, y, z).
+"""
+
+import numpy as np
+
+from .elements import RefElement
+
+
+class Mesh:
+    def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None):
+        self.nx, self.ny, self.nz, self.p, self.kind = nx, ny, nz, p, kind
+        self.lo, self.hi = lo, hi
+        L = hi - lo
+        self.period = np.array([L, L, L])
+        h = np.array([L / nx, L / ny, L / nz])
+        self.h = h
+        types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"]}[kind]
+        self.refs = {}
+        for t in types:
+            self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes)
+        org = {t: [] for t in types}
+        A = {t: [] for t in types}
+        gid = {t: [] for t in types}
+        g = 0
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    x0 = lo + np.array([i, j, k]) * h
+                    zc = x0[2] + 0.5 * h[2]
+                    ctype = kind if kind != "mixed" else ("hex" if zc < 0.0 else "prism")
+                    if ctype == "hex":
+                        org["hex"].append(x0 + 0.5 * h)
+                        A["hex"].append(np.diag(0.5 * h))
+                        gid["hex"].append(g)
+                        g += 1
+                    else:
+                        hx, hy, hz = 0.5 * h
+                        # columns: d x / d(xi, eta, zeta)
+                        org["prism"].append(x0 + 0.5 * h)
+                        A["prism"].append(np.array([[0.0, hx, 0.0], [0.0, 0.0, hy], [hz, 0.0, 0.0]]))
+                        gid["prism"].append(g)
+                        g += 1
+                        org["prism"].append(x0 + 0.5 * h)
+                        A["prism"].append(np.array([[0.0, -hx, 0.0], [0.0, 0.0, hy], [-hz, 0.0, 0.0]]))
+                        gid["prism"].append(g)
+                        g += 1
+        self.types = [t for t in types if len(org[t])]
+        self.org = {t: np.array(org[t]) for t in self.types}
+        self.J = {t: np.array(A[t]) for t in self.types}
+        self.gid = {t: np.array(gid[t]) for t in self.types}
+        self.nelem = {t: len(self.org[t]) for t in self.types}
+        self.detJ = {t: np.linalg.det(self.J[t]) for t in self.types}
+        self.Jinv = {t: np.linalg.inv(self.J[t]) for t in self.types}
+        if any(np.any(self.detJ[t] <= 0) for t in self.types):
+            raise ValueError("non-positive Jacobian")
+        self._pair()
+
+    # physical coordinates of reference points for every element of type t
+    def phys(self, t, ref_pts):
+        return self.org[t][:, None, :] + np.einsum("eij,pj->epi", self.J[t], ref_pts)
+
+    def upts_coords(self, t):
+        return self.phys(t, self.refs[t].upts)
+
+    def _pair(self):
+        # flat flux-point numbering: types in order, then element, then point
+        self.foff, off = {}, 0
+        for t in self.types:
+            self.foff[t] = off
+            off += self.nelem[t] * self.refs[t].nf
+        self.nfpts = off
+        # faces: match by centroid modulo the period, then points within a face pair
+        fkeys, finfo, fcent = [], [], []
+        Qk = 1 << 24
+        for ti, t in enumerate(self.types):
+            r = self.refs[t]
+            E = self.nelem[t]
+            fc = np.stack([r.fpts[r.fface == f].mean(axis=0) for f in range(r.nfaces)])
+            c = self.phys(t, fc).reshape(-1, 3)
+            fcent.append(c)
+            fkeys.append(np.mod(np.rint((c - self.lo) / self.period * Qk).astype(np.int64), Qk))
+            finfo.append(np.stack([np.full(E * r.nfaces, ti), np.repeat(np.arange(E), r.nfaces),
+                                   np.tile(np.arange(r.nfaces), E), np.repeat(self.gid[t], r.nfaces)], axis=1))
+        key, info, cent = np.concatenate(fkeys), np.concatenate(finfo), np.concatenate(fcent)
+        order = np.lexsort((key[:, 2], key[:, 1], key[:, 0]))
+        ks = key[order]
+        eq = np.all(ks[1:] == ks[:-1], axis=1)
+        if len(ks) % 2 or not np.all(eq[0::2]) or np.any(eq[1::2]):
+            raise ValueError("faces do not pair up (non-conforming mesh?)")
+        fa, fb = order[0::2], order[1::2]
+        ga, gb = info[fa, 3], info[fb, 3]
+        ca, cb = cent[fa], cent[fb]
+        lex = np.where(ca[:, 0] != cb[:, 0], ca[:, 0] < cb[:, 0],
+                       np.where(ca[:, 1] != cb[:, 1], ca[:, 1] < cb[:, 1], ca[:, 2] < cb[:, 2]))
+        a_first = np.where(ga == gb, lex, ga < gb)
+        fL, fR = np.where(a_first, fa, fb), np.where(a_first, fb, fa)
+        iL, iR = [], []
+        # group face pairs by (type, local face) on both sides; match points in batch
+        cls = np.stack([info[fL, 0], info[fL, 2], info[fR, 0], info[fR, 2]], axis=1)
+        ucls, inv = np.unique(cls, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        for ci, (tl, ffl, tr, ffr) in enumerate(ucls):
+            sel = np.nonzero(inv == ci)[0]
+            tL, tR = self.types[tl], self.types[tr]
+            rL, rR = self.refs[tL], self.refs[tR]
+            pl = np.nonzero(rL.fface == ffl)[0]
+            pr = np.nonzero(rR.fface == ffr)[0]
+            eL, eR = info[fL[sel], 1], info[fR[sel], 1]
+            XL = self.org[tL][eL][:, None, :] + np.einsum("eij,pj->epi", self.J[tL][eL], rL.fpts[pl])
+            XR = self.org[tR][eR][:, None, :] + np.einsum("eij,pj->epi", self.J[tR][eR], rR.fpts[pr])
+            d = XL[:, :, None, :] - XR[:, None, :, :]
+            d -= self.period * np.rint(d / self.period)
+            dist = np.linalg.norm(d, axis=3)
+            j = np.argmin(dist, axis=2)
+            if len(pl) != len(pr) or np.max(np.take_along_axis(dist, j[:, :, None], 2)) > 1e-9 * self.h.min():
+                raise ValueError("flux points of paired faces do not coincide")
+            if np.any(np.sort(j, axis=1) != np.arange(len(pr))[None, :]):
+                raise ValueError("flux-point matching is not one-to-one")
+            iL.append((self.foff[tL] + eL[:, None] * rL.nf + pl[None, :]).reshape(-1))
+            iR.append((self.foff[tR] + eR[:, None] * rR.nf + pr[j]).reshape(-1))
+        self.iL, self.iR = np.concatenate(iL), np.concatenate(iR)
+        if len(self.iL) * 2 != self.nfpts:
+            raise ValueError("flux points left unpaired")
+        self.partner = np.full(self.nfpts, -1, dtype=np.int64)
+        self.partner[self.iL] = self.iR
+        self.partner[self.iR] = self.iL
+        if np.any(self.partner < 0):
+            raise ValueError("flux points left unpaired")
+        # physical unit normals and area factors (Nanson): n = det J J^-T nhat / mag
+        nrm, mag = [], []
+        for t in self.types:
+            r = self.refs[t]
+            v = self.detJ[t][:, None, None] * np.einsum("edc,fd->efc", self.Jinv[t], r.fnorm)
+            mg = np.linalg.norm(v, axis=2)
+            nrm.append((v / mg[:, :, None]).reshape(-1, 3))
+            mag.append(mg.reshape(-1))
+        self.fnrm, self.fmag = np.concatenate(nrm), np.concatenate(mag)

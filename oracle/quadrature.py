@@ -1,0 +1,75 @@
+"""One-dimensional rules, the conical-product triangle rule and the triangle
+node set used by the oracle.  Test infrastructure only (see package header).
+
+Paper: section 2.1 allows any solution/flux point set; hexahedra use
+Gauss-Legendre points (the printed coordinates are the 3- and 4-point
+Gauss-Legendre nodes, figures "ufn" and "prism2toprims3").  Prisms are a
+triangle times a Gauss-Legendre line (section 4.1).  The paper prints
+triangle points only for p = 2 and p = 3, so the triangle node set is a
+reading: the Blyth-Pozrikidis construction on Gauss-Lobatto-Legendre master
+points, used for every order.
+"""
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+from scipy.special import roots_jacobi
+
+
+def gauss_legendre(n):
+    """n-point Gauss-Legendre rule on [-1, 1]; exact to degree 2n-1."""
+    x, w = npleg.leggauss(n)
+    return np.asarray(x, dtype=np.float64), np.asarray(w, dtype=np.float64)
+
+
+def gauss_lobatto_legendre(n):
+    """n-point Gauss-Lobatto-Legendre nodes on [-1, 1] (endpoints included):
+    the endpoints plus the roots of P'_{n-1}."""
+    if n < 2:
+        raise ValueError("GLL needs at least two points")
+    c = np.zeros(n)
+    c[-1] = 1.0
+    interior = np.sort(npleg.legroots(npleg.legder(c))) if n > 2 else np.array([])
+    return np.concatenate([[-1.0], interior, [1.0]])
+
+
+def gauss_jacobi(n, alpha, beta):
+    """n-point Gauss-Jacobi rule for the weight (1-x)^alpha (1+x)^beta."""
+    x, w = roots_jacobi(n, alpha, beta)
+    return np.asarray(x, dtype=np.float64), np.asarray(w, dtype=np.float64)
+
+
+def triangle_conical(k):
+    """Conical-product (collapsed-coordinate) rule on the reference triangle
+    {xi, eta >= -1, xi + eta <= 0} with k*k points, exact for total degree
+    2k-1: Gauss-Legendre in a, Gauss-Jacobi(1,0) in b, with
+    xi = (1+a)(1-b)/2 - 1, eta = b and dxi deta = (1-b)/2 da db.
+    Ordering: b index outer, a index inner."""
+    a, wa = gauss_legendre(k)
+    b, wb = gauss_jacobi(k, 1.0, 0.0)
+    pts = np.empty((k * k, 2))
+    wts = np.empty(k * k)
+    for j in range(k):
+        for i in range(k):
+            pts[j * k + i] = (0.5 * (1.0 + a[i]) * (1.0 - b[j]) - 1.0, b[j])
+            wts[j * k + i] = 0.5 * wa[i] * wb[j]
+    return pts, wts
+
+
+def triangle_nodes(p):
+    """(p+1)(p+2)/2 nodes on the reference triangle, Blyth-Pozrikidis
+    construction on the Gauss-Legendre master grid v_m = (1 + t_m)/2,
+    t_m = GL(p+1) nodes:
+        x = (1 + 2 v_i - v_j - v_k)/3,  y = (1 + 2 v_j - v_i - v_k)/3,
+    k = p - i - j, on the unit right triangle, mapped to (-1,-1),(1,-1),(-1,1).
+    Ordering: j outer (0..p), i inner (0..p-j)."""
+    if p == 0:
+        return np.array([[-1.0 / 3.0, -1.0 / 3.0]])
+    v = 0.5 * (1.0 + gauss_legendre(p + 1)[0])
+    pts = []
+    for j in range(p + 1):
+        for i in range(p + 1 - j):
+            k = p - i - j
+            x = (1.0 + 2.0 * v[i] - v[j] - v[k]) / 3.0
+            y = (1.0 + 2.0 * v[j] - v[i] - v[k]) / 3.0
+            pts.append((2.0 * x - 1.0, 2.0 * y - 1.0))
+    return np.array(pts)

@@ -1,0 +1,121 @@
+"""Semi-discrete right-hand side du/dt = R(u) and RK4.  Test infrastructure only.
+
+Follows the paper's kernel formulation (section 2.2, kernel order of PyFR
+v1.11.0), with dense operators and no fusion:
+   1 disu          U^f  = M0 U
+   2 con_u         C    = (1/2 - beta) uL + (1/2 + beta) uR, written to both sides
+   3,4 tgradpcoru/tgradcoru   Q~ = M4 U + M6 (C - U^f)
+        (eq. Qsubs; its last line carries a sign slip, the first line is used)
+   5 gradcoru      Q    = J^-T Q~
+   6 gradcoru_fpts Q^f  = M5 Q = (I3 x M0) Q
+   7,8 gradcoru_qpts/uqpts   Q^q = M10 Q,  U^q = M7 U
+   9 tdisf         F~^q = det J  J^-1 f(U^q, Q^q)
+  10 tdivtpcorf    R~   = (M1 - M3 M2) M9 F~^q, applied literally:
+                   F~^u = M8 F~^q (per component), then
+                   R~ = sum_d D_d F~^u_d - M3 (sum_d nhat_d M0 F~^u_d)
+  11 comm_flux     D~ = mag F(uL, uR, qL, qR, nL) on L, -mag F on R
+  12 tdivtconf     R~  += M3 D~
+  13 negdivconf    R   = -R~ / det J
+Affine elements: J, det J and J^-1 are constant per element.
+
+Arrays: the state of element type t is U[t] with shape (E_t, 5, N_u)
+(element, variable, solution point).
+"""
+
+import numpy as np
+
+from . import physics
+
+
+class Params:
+    """Physics and scheme parameters.  Defaults are the Taylor-Green setup:
+    gamma 1.4, Pr 0.71, Re 1600 (mu = 1/1600 with rho0 = U0 = L = 1), LDG
+    beta = 1/2, tau = 0.1, reference pressure 0 (textbook form)."""
+
+    def __init__(self, gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0):
+        self.gas = physics.Gas(gamma, prandtl, mu, pref)
+        self.beta, self.tau = beta, tau
+
+
+def _flat(arrs, mesh, tail):
+    return np.concatenate([arrs[t].reshape((-1,) + tail) for t in mesh.types])
+
+
+def _unflat(flat, mesh, t, tail):
+    r = mesh.refs[t]
+    o = mesh.foff[t]
+    return flat[o:o + mesh.nelem[t] * r.nf].reshape((mesh.nelem[t], r.nf) + tail)
+
+
+def rhs(mesh, U, par, dtype=None):
+    """Return du = R(u) for every element type (dict of (E_t, 5, N_u) arrays)."""
+    gas, beta, tau = par.gas, par.beta, par.tau
+    if dtype is None:
+        dtype = U[mesh.types[0]].dtype
+    cast = lambda a: np.asarray(a, dtype=dtype)  # noqa: E731
+    Up, Uf = {}, {}
+    for t in mesh.types:
+        u = cast(U[t]).transpose(0, 2, 1).copy()  # (E, Nu, 5)
+        u[:, :, 4] -= cast(gas.eref)  # reference-state form (E' = E - E_ref)
+        Up[t] = u
+        Uf[t] = np.einsum("fu,euv->efv", cast(mesh.refs[t].M0), u)  # 1 disu
+    ufa = _flat(Uf, mesh, (5,))
+    uL, uR = ufa[mesh.iL], ufa[mesh.iR]
+    ca = np.empty_like(ufa)
+    c = physics.common_solution(uL, uR, beta)  # 2 con_u
+    ca[mesh.iL] = c
+    ca[mesh.iR] = c
+    Q, Qf, Rt = {}, {}, {}
+    for t in mesh.types:
+        r = mesh.refs[t]
+        C = _unflat(ca, mesh, t, (5,))
+        qt = np.einsum("dsu,euv->edsv", cast(r.Dg), Up[t])  # 3 tgradpcoru (M4 part)
+        qt += np.einsum("dsf,efv->edsv", cast(r.M6), C - Uf[t])  # 4 tgradcoru
+        q = np.einsum("edc,edsv->ecsv", cast(mesh.Jinv[t]), qt)  # 5 gradcoru (J^-T)
+        Q[t] = q
+        Qf[t] = np.einsum("fs,ecsv->efcv", cast(r.M0), q)  # 6 gradcoru_fpts
+    for t in mesh.types:
+        r = mesh.refs[t]
+        E = mesh.nelem[t]
+        rt = np.empty((E, r.nu, 5), dtype=dtype)
+        chunk = max(1, int(2.0e7 // (r.nq * 20)))
+        for e0 in range(0, E, chunk):
+            sl = slice(e0, min(E, e0 + chunk))
+            uq = np.einsum("qu,euv->vqe", cast(r.M7), Up[t][sl])  # 8 uqpts
+            qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), Q[t][sl])  # 7 gradcoru_qpts
+            f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9 tdisf
+            ft = np.einsum("e,edc,cvqe->edqv", cast(mesh.detJ[t][sl]), cast(mesh.Jinv[t][sl]), f)
+            fu = np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10 tdivtpcorf: M9 (I3 x M8)
+            div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)  # M1
+            nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)  # M2
+            rt[sl] = div - np.einsum("uf,efv->euv", cast(r.M3), nf)  # - M3 M2
+        Rt[t] = rt
+    qfa = _flat(Qf, mesh, (3, 5))
+    nL = cast(mesh.fnrm[mesh.iL])
+    F = physics.common_normal_flux(uL.T, uR.T, qfa[mesh.iL].transpose(1, 2, 0),
+                                   qfa[mesh.iR].transpose(1, 2, 0), nL.T, gas, beta, tau).T  # 11
+    mag = cast(mesh.fmag[mesh.iL])[:, None]
+    da = np.empty_like(ufa)
+    da[mesh.iL] = mag * F
+    da[mesh.iR] = -(mag * F)
+    out = {}
+    for t in mesh.types:
+        r = mesh.refs[t]
+        D = _unflat(da, mesh, t, (5,))
+        rt = Rt[t] + np.einsum("uf,efv->euv", cast(r.M3), D)  # 12 tdivtconf
+        du = -rt / cast(mesh.detJ[t])[:, None, None]  # 13 negdivconf
+        out[t] = du.transpose(0, 2, 1).copy()
+    return out
+
+
+def rk4_step(mesh, U, par, dt):
+    """Classical four-stage Runge-Kutta step (the time integrator named in
+    section 3); returns the new state."""
+    def axpy(a, X, Y):
+        return {t: Y[t] + a * X[t] for t in mesh.types}
+
+    k1 = rhs(mesh, U, par)
+    k2 = rhs(mesh, axpy(0.5 * dt, k1, U), par)
+    k3 = rhs(mesh, axpy(0.5 * dt, k2, U), par)
+    k4 = rhs(mesh, axpy(dt, k3, U), par)
+    return {t: U[t] + (dt / 6.0) * (k1[t] + 2.0 * k2[t] + 2.0 * k3[t] + k4[t]) for t in mesh.types}

@@ -1,0 +1,204 @@
+"""Benchmark: flux-reconstruction Navier-Stokes RHS with flux anti-aliasing.
+
+One step = one full right-hand-side evaluation (all kernel groups) of the
+Taylor-Green vortex state on a 48^3 periodic hexahedral mesh, p = 3, with
+6^3 Gauss-Legendre anti-aliasing points per element, fused kernels with
+FP32 bulk arithmetic and FP64 state.  value = whole-job GDoF-RHS/s, with
+DoF = 5 conserved variables x solution points (7.08M points, 35.4M DoF).
+The same run reports the FP64 fused path and p = 4 alongside, the volume
+kernel's HBM/ALU roofline position measured with HIP events, and the
+reference oracle timed on the host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDoF-RHS/s NS+AA FR (fused FP32 vs plain FP64), % HBM roofline; p99 step ms"
+HBM_PEAK_GBS = 8000.0
+# vector ALU peak from unit counts: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
+# FP64 FMA runs at full rate; FP32 reaches twice this only with packed math,
+# which this build does not emit.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def volume_model(p, bytes_real):
+    """Algorithmic HBM bytes and FLOPs of one element in the fused volume
+    kernel (hex).  Bytes: state read (5 N_u doubles), neighbour face states
+    (5 N_f reals), normal viscous flux written (4 N_f reals), volume residual
+    written (5 N_u reals), face records + per-element metrics (small).
+    FLOPs: the sum-factorised sweeps, gradient, the point-wise flux at the
+    m^3 quadrature points (about 130 flops each) and the face viscous fluxes."""
+    n, m = p + 1, p + 3
+    nu, nf = n ** 3, 6 * n * n
+    byts = 5 * nu * 8 + 5 * nf * bytes_real + 4 * nf * bytes_real + 5 * nu * bytes_real + 6 * 8 + 10 * bytes_real
+    fl = 0
+    fl += 2 * 5 * 3 * n * n * n * 2                      # own face values (lb, rb)
+    fl += 2 * 15 * nu * (n + 2)                           # corrected gradient
+    fl += 2 * 15 * nu * 3                                 # J^-T
+    fl += 2 * 20 * 3 * n * n * n * 2 + 3 * n * n * 2 * 60  # face interpolation + viscous normal flux
+    fl += 2 * 20 * m * n * n * n                          # x sweep
+    fl += 2 * 20 * m * m * n * n                          # y interpolation per column
+    fl += 2 * 20 * m * m * m * n                          # z interpolation on the fly
+    fl += m ** 3 * (130 + 2 * 45)                          # point flux + transformed flux
+    fl += 2 * 15 * m ** 3 * n                             # z projection
+    fl += 2 * 5 * m * n * (m * 3) * n                     # y projection
+    fl += 2 * 5 * n * n * (2 * m) * n                     # x projection
+    return byts, fl
+
+
+def rhs_bytes_model(p, bytes_real):
+    """Algorithmic bytes of one full fused RHS per element (hex): disu reads
+    U and writes U^f; the volume group reads U and the neighbour U^f and
+    writes V^f and the volume residual; the interface group reads the
+    residual, own and neighbour U^f and V^f, and writes du."""
+    n = p + 1
+    nu, nf = n ** 3, 6 * n * n
+    b = 5 * nu * 8 + 5 * nf * bytes_real
+    b += 5 * nu * 8 + 5 * nf * bytes_real + 4 * nf * bytes_real + 5 * nu * bytes_real
+    b += 5 * nu * bytes_real + 2 * 5 * nf * bytes_real + 2 * 4 * nf * bytes_real + 5 * nu * 8
+    return b
+
+
+def time_variant(frmi, torch, n, p, prec, steps, warmup):
+    from paper_2401_06132_amd import inputs
+    s = frmi.Solver(n, p, "hex", prec=prec, pref=inputs.P0)
+    coords = s.upts_coords()
+    U = inputs.element_state(coords, seed=0)
+    u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
+    del U, coords
+    du = torch.empty_like(u)
+    for _ in range(warmup):
+        s.rhs(u, du)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(steps):
+        s.rhs(u, du)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    # dominant kernel (volume group) alone, same launch configuration
+    for _ in range(max(1, warmup // 2)):
+        s.rhs_stages(u, du, 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        s.rhs_stages(u, du, 2)
+    e1.record()
+    torch.cuda.synchronize()
+    vol_ms = e0.elapsed_time(e1) / steps
+    ok = bool(torch.isfinite(du).all().item())
+    res = dict(n_dof=s.n_state, n_elem=s.n_hex, wall_s=wall, ms_per_step=wall * 1e3 / steps,
+               p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), vol_ms=vol_ms,
+               finite=ok)
+    del s, u, du
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(budget_s=20.0):
+    """The oracle (plain NumPy, dense operators) on the host: one RHS of the
+    same Taylor-Green hex p=3 workload on a smaller periodic box; the box is
+    chosen so that the run takes roughly budget_s seconds."""
+    from oracle.mesh import Mesh
+    from oracle.rhs import Params, rhs
+    from paper_2401_06132_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    N = 4
+    elapsed = 0.0
+    while True:
+        m = Mesh(N, N, N, 3, "hex")
+        U = {t: u for t, u in zip(m.types, inputs.element_state([m.upts_coords(t) for t in m.types]))}
+        t0 = time.perf_counter()
+        rhs(m, U, Params(pref=inputs.P0))
+        elapsed = time.perf_counter() - t0
+        dof = 5 * m.nelem["hex"] * m.refs["hex"].nu
+        if elapsed * 8 > budget_s or N >= 24:
+            break
+        N *= 2
+    return {"value": dof / elapsed / 1e9, "unit": "GDoF-RHS/s", "cores": int(threads), "kind": "oracle",
+            "sample": "one RHS of the TGV hex p=3 flux-AA case on a %d^3 periodic box (%d DoF), %.2f s" %
+                      (N, dof, elapsed)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline variant only")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2401_06132_amd as frmi
+    torch.cuda.set_device(0)
+    variants = {}
+    order = [("fp32", 3)] if args.quick else [("fp32", 3), ("fp64", 3), ("fp32", 4), ("fp64", 4)]
+    for prec, p in order:
+        r = time_variant(frmi, torch, args.n, p, prec, args.steps, args.warmup)
+        br = 4 if prec == "fp32" else 8
+        vb, vf = volume_model(p, br)
+        E = r["n_elem"]
+        r["gdof_s"] = r["n_dof"] * args.steps / r["wall_s"] / 1e9
+        r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
+        r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
+        r["rhs_GBs"] = rhs_bytes_model(p, br) * E * args.steps / r["wall_s"] / 1e9
+        variants["%s_p%d" % (prec, p)] = r
+        print("variant", prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
+              file=sys.stderr, flush=True)
+    head = variants["fp32_p3"]
+    vb, vf = volume_model(3, 4)
+    ai = vf / vb
+    ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if ai > ridge:
+        roof = {"bound": "alu", "achieved": round(head["vol_TFLOPs"], 3), "peak": round(VALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(head["vol_TFLOPs"] / VALU_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(head["vol_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4)}
+    roof.update({"kernel": "hex_volume<3,float>", "traffic": None, "hbm_GBs": round(head["vol_GBs"], 1),
+                 "hbm_frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4), "flop_per_byte": round(ai, 2),
+                 "avg_ms": round(head["vol_ms"], 4)})
+    out = {
+        "metric": METRIC, "value": round(head["gdof_s"], 3), "unit": "GDoF-RHS/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Taylor-Green vortex, %d^3 periodic hex, p=3, flux AA GL(6)^3, fused, FP32 bulk / "
+                               "FP64 state" % args.n, "elements": head["n_elem"], "dof": head["n_dof"]},
+        "p50_step_ms": round(head["p50_ms"], 4), "p99_step_ms": round(head["p99_ms"], 4),
+        "hbm_frac_rhs": round(head["rhs_GBs"] / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+        "variants": {k: {"gdof_s": round(v["gdof_s"], 3), "p99_step_ms": round(v["p99_ms"], 4),
+                         "vol_ms": round(v["vol_ms"], 4), "hbm_frac_rhs": round(v["rhs_GBs"] / HBM_PEAK_GBS, 4),
+                         "finite": v["finite"]} for k, v in variants.items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

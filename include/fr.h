@@ -1,0 +1,173 @@
+/*
+ * fr.h -- C ABI of the MI355X flux-reconstruction library (libfrmi.so).
+ *
+ * The library evaluates the semi-discrete right-hand side du/dt = R(u) of the
+ * compressible Navier-Stokes equations discretised with flux reconstruction
+ * (DG correction functions) and flux anti-aliasing, and advances it with
+ * classical RK4, following Akkurt, Witherden & Vincent, "Cache Blocking for
+ * Flux Reconstruction: Extension to Navier-Stokes Equations and
+ * Anti-aliasing":
+ *   - governing equations and fluxes: section 2.1, eqs. gov, ucons, fluxe,
+ *     fluxv; first-order system eq. govq; mapping eqs. transall, govqtrans;
+ *   - FR steps: eqs. FR-disu, FR-conu, FR-qfinal, FR-gradcoru,
+ *     FR-gradcoru_fpts, FR-comm_flux, FRfinal;
+ *   - flux anti-aliasing: eqs. FR-uqpts, FR-gradcoru_qpts, FR-tdisfq,
+ *     FR-tdivtpcorfq (section 2.1.1) and the operator matrices M0..M10 of
+ *     section 2.2;
+ *   - tensor-product factorisation of the anti-aliasing operators for
+ *     hexahedra and prisms: section 4 and 4.1;
+ *   - the kernel groups of section 6.1 (figure NSAAKG), realised as fused
+ *     GPU kernels.
+ *
+ * Conventions
+ *   - All functions return an fr_status (0 = FR_OK, negative = error) and never
+ *     throw or abort; fr_last_error() gives a human-readable message.
+ *   - A context is single-stream and not thread-safe.  Device work is enqueued
+ *     on the context stream (the stream passed to fr_create, or the null
+ *     stream) and is asynchronous unless stated otherwise.
+ *   - State layout ("library layout"): all hexahedra first, then all prisms;
+ *     within a type, elements in mesh order; per element the five conserved
+ *     variables [rho, rho vx, rho vy, rho vz, E] (eq. ucons), each as N_u
+ *     contiguous doubles in solution-point order.  I.e. per type an array
+ *     (E_t, 5, N_u) of float64, row-major.
+ *   - Solution points: hex GL(p+1)^3, index i + n(j + n k) (x fastest);
+ *     prism = triangle nodes x GL(p+1), index t + N_t k.  Triangle nodes:
+ *     Blyth-Pozrikidis construction on the Gauss-Legendre master grid.
+ *   - Anti-aliasing quadrature: hex GL(p+3)^3; prism conical triangle rule
+ *     with (p+1)^2 points (exact to degree 2p+1) x GL(p+3).
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_ctx fr_ctx;
+
+typedef enum {
+  FR_OK = 0,
+  FR_EINVAL = -1,        /* bad argument (null pointer, size, unsupported order, ...) */
+  FR_ENOMEM = -2,        /* host or device allocation failed */
+  FR_EDEVICE = -3,       /* a HIP call failed; see fr_last_error */
+  FR_ESTATE = -4,        /* call out of order (e.g. no mesh yet) */
+  FR_EUNSUPPORTED = -5   /* combination not built (e.g. order outside 1..4) */
+} fr_status;
+
+typedef enum { FR_HEX = 0, FR_PRISM = 1 } fr_etype;
+typedef enum { FR_MESH_HEX = 0, FR_MESH_PRISM = 1, FR_MESH_MIXED = 2 } fr_mesh_kind;
+typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
+typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
+
+/* Physics and scheme parameters.
+ *   gamma, prandtl, mu : perfect gas, constant viscosity (section 2.1)
+ *   ldg_beta, ldg_tau  : LDG common solution / viscous flux parameters
+ *                        (eq. FR-conu and the LDG flux of section 2.1);
+ *                        beta = 0, tau = 0 gives BR1-type central fluxes
+ *   pref               : constant reference pressure.  The energy is operated
+ *                        on as E - pref/(gamma-1) and the constant pref*I
+ *                        momentum flux is dropped (it has zero discrete
+ *                        divergence); mathematically identical, it removes
+ *                        the low-Mach cancellation.  0 = textbook form.
+ *   prec               : FR_PREC_FP64: every step in double precision.
+ *                        FR_PREC_FP32: state, reference subtraction, final
+ *                        RHS and RK accumulation in double; interpolation,
+ *                        fluxes, projections and interface exchange in float.
+ *   form               : FR_FORM_FUSED: three fused kernels per element type
+ *                        (disu | volume group | interface group).
+ *                        FR_FORM_PLAIN: the paper's unfused kernel sequence
+ *                        with dense operator matrices (comparison path). */
+typedef struct {
+  double gamma, prandtl, mu, ldg_beta, ldg_tau, pref;
+  int prec;   /* fr_precision */
+  int form;   /* fr_form */
+} fr_physics;
+
+/* Fill *ph with the Taylor-Green defaults: gamma 1.4, Pr 0.71, mu 1/1600,
+ * beta 0.5, tau 0.1, pref 0, FP64, fused. */
+void fr_physics_default(fr_physics* ph);
+
+/* Create a context.  hip_stream: a hipStream_t or NULL (null stream).  No
+ * device call is made here.  *out receives the context; free with
+ * fr_destroy.  Errors: FR_EINVAL (null out/ph, non-physical parameters). */
+fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
+
+/* Build a periodic box mesh [lo,hi]^3 of nx*ny*nz cells at order p (1..4).
+ * kind: FR_MESH_HEX (one hexahedron per cell), FR_MESH_PRISM (each cell split
+ * along the diagonal of its x-z face into two prisms extruded along y),
+ * FR_MESH_MIXED (hexahedra where the cell centre has z < 0, prisms
+ * elsewhere; the interfaces are conforming quadrilaterals).  Host-side only:
+ * device buffers are allocated and uploaded by the first call that needs
+ * them.  Element numbering: cells in index order i + nx(j + ny k); a prism
+ * cell yields two elements.  Errors: FR_EINVAL (n < 1, hi <= lo),
+ * FR_EUNSUPPORTED (p outside 1..4), FR_ESTATE (mesh already built). */
+fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind);
+
+/* Sizes of the library layout: number of hexahedra, of prisms, and the total
+ * number of doubles of a state vector.  Any pointer may be NULL. */
+fr_status fr_layout(const fr_ctx* c, int64_t* n_hex, int64_t* n_prism, int64_t* n_state);
+
+/* Physical coordinates of every solution point in library order:
+ * xyz_host receives n_state/5*3 doubles, (point, xyz) row-major. Host only. */
+fr_status fr_upts_coords(const fr_ctx* c, double* xyz_host);
+
+/* du = R(u).  u_dev, du_dev: caller-owned device buffers of n_state doubles
+ * in library layout (e.g. torch tensor data pointers); they must not alias.
+ * Asynchronous on the context stream.  Errors: FR_ESTATE (no mesh),
+ * FR_EINVAL (null), FR_EDEVICE. */
+fr_status fr_rhs(fr_ctx* c, const double* u_dev, double* du_dev);
+
+/* Profiling aid: enqueue only some kernel groups of fr_rhs on the context
+ * stream.  mask bit 0: disu (solution at flux points), bit 1: volume group
+ * (common solution, corrected gradients, anti-aliased flux, projection and
+ * divergence), bit 2: interface group (common flux, lifting, final scaling).
+ * A run without all three bits leaves du incomplete; it exists so that a
+ * benchmark can time one group in the launch configuration of fr_rhs.
+ * Errors as fr_rhs; FR_EINVAL if mask is 0 or > 7. */
+fr_status fr_rhs_stages(fr_ctx* c, const double* u_dev, double* du_dev, int mask);
+
+/* Copy a state into the context's internal state (used by fr_rk4_step):
+ * u points to n_state doubles on the host (on_device = 0) or the device. */
+fr_status fr_set_state(fr_ctx* c, const double* u, int on_device);
+
+/* Copy the internal state out (host or device destination); synchronises
+ * the stream. */
+fr_status fr_get_state(fr_ctx* c, double* u, int on_device);
+
+/* Advance the internal state by nsteps classical RK4 steps of size dt
+ * (the time integrator named in section 3).  Stage accumulation is in
+ * double precision for both precisions.  Asynchronous. */
+fr_status fr_rk4_step(fr_ctx* c, double dt, int nsteps);
+
+/* Integrals of the conserved variables of the internal state,
+ * sum_e det J_e sum_u w_u u_e (w_u = integrals of the nodal basis); out5
+ * receives 5 doubles.  Synchronises the stream. */
+fr_status fr_integrals(fr_ctx* c, double* out5);
+
+/* Host-side inspection (no device needed).
+ * fr_ref_operator: copy a reference-element quantity of type etype and order
+ * p into out (capacity cap doubles); *count receives its size.  Names:
+ *   "upts", "fpts", "qpts"  point coordinates (N x 3)
+ *   "qwts"                  quadrature weights (N_q)
+ *   "M0" (N_f x N_u), "M3" (N_u x N_f), "M7" (N_q x N_u), "M8" (N_u x N_q),
+ *   "Dxi", "Deta", "Dzeta" (N_u x N_u)   dense operators of section 2.2.
+ * Errors: FR_EINVAL (unknown name, cap too small). */
+fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count);
+
+/* fr_connectivity: for every flux point of every element (types in order,
+ * then element, then flux point): nbr[i] = flat index of the paired flux
+ * point, is_left[i] = 1 if this side is "L" of the pair (the element with
+ * the lower mesh-order index; for an element paired with itself, the face
+ * with the lexicographically smaller centroid).  Arrays of n_fpts entries;
+ * *n_fpts receives the count when nbr is NULL. */
+fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_t* n_fpts);
+
+const char* fr_last_error(const fr_ctx* c);
+void fr_destroy(fr_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FR_H */

@@ -1,0 +1,199 @@
+"""MI355X flux-reconstruction library: Python binding of libfrmi.so.
+
+Thin ctypes wrapper over the C ABI declared in include/fr.h: argument
+marshalling only.  Every step of the right-hand side and of RK4 runs in the
+HIP kernels of the shared library; there is no fallback.  Device buffers are
+torch tensors (float64, on the current HIP device); PyTorch is used for
+device memory and streams only.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import inputs  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrmi.so")
+
+FR_HEX, FR_PRISM = 0, 1
+MESH_KIND = {"hex": 0, "prism": 1, "mixed": 2}
+PREC = {"fp64": 0, "fp32": 1}
+FORM = {"fused": 0, "plain": 1}
+_STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE", -5: "FR_EUNSUPPORTED"}
+
+# every symbol the header declares
+SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_upts_coords", "fr_rhs", "fr_rhs_stages",
+           "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
+           "fr_last_error", "fr_destroy"]
+
+
+class FrPhysics(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
+                ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("pref", ctypes.c_double),
+                ("prec", ctypes.c_int), ("form", ctypes.c_int)]
+
+
+class FrError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libfrmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise FrError("libfrmi.so not built; run paper_2401_06132_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "fr_physics_default": (None, [ctypes.POINTER(FrPhysics)]),
+        "fr_create": (I, [ctypes.POINTER(FrPhysics), P, ctypes.POINTER(P)]),
+        "fr_mesh_box": (I, [P, I, I, I, D, D, I, I]),
+        "fr_layout": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "fr_upts_coords": (I, [P, P]),
+        "fr_rhs": (I, [P, P, P]),
+        "fr_rhs_stages": (I, [P, P, P, I]),
+        "fr_set_state": (I, [P, P, I]),
+        "fr_get_state": (I, [P, P, I]),
+        "fr_rk4_step": (I, [P, D, I]),
+        "fr_integrals": (I, [P, P]),
+        "fr_ref_operator": (I, [I, I, ctypes.c_char_p, P, I64, ctypes.POINTER(I64)]),
+        "fr_connectivity": (I, [P, P, P, ctypes.POINTER(I64)]),
+        "fr_last_error": (ctypes.c_char_p, [P]),
+        "fr_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def physics(gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0, prec="fp64", form="fused"):
+    return FrPhysics(gamma, prandtl, mu, beta, tau, pref, PREC[prec], FORM[form])
+
+
+def ref_operator(etype, p, name):
+    """Reference-element quantity computed by the library's host setup."""
+    lib = load_library()
+    cnt = ctypes.c_int64(0)
+    _check(None, lib.fr_ref_operator(etype, p, name.encode(), None, 0, ctypes.byref(cnt)))
+    out = np.empty(cnt.value, dtype=np.float64)
+    _check(None, lib.fr_ref_operator(etype, p, name.encode(), out.ctypes.data, cnt.value, ctypes.byref(cnt)))
+    return out
+
+
+def _check(ctx, st):
+    if st != 0:
+        msg = load_library().fr_last_error(ctx).decode() if ctx else ""
+        raise FrError("%s: %s" % (_STATUS.get(st, st), msg))
+
+
+class Solver:
+    """One flux-reconstruction context (mesh + operators + device buffers)."""
+
+    def __init__(self, n, p, kind="hex", prec="fp64", form="fused", lo=-np.pi, hi=np.pi, stream=None, **phys):
+        self.lib = load_library()
+        nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+        ph = physics(prec=prec, form=form, **phys)
+        c = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(stream)
+        _check(None, self.lib.fr_create(ctypes.byref(ph), st, ctypes.byref(c)))
+        self.ctx = c
+        self.p, self.kind, self.prec = p, kind, prec
+        _check(self.ctx, self.lib.fr_mesh_box(self.ctx, nx, ny, nz, lo, hi, p, MESH_KIND[kind]))
+        nh, npr, ns = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self.ctx, self.lib.fr_layout(self.ctx, ctypes.byref(nh), ctypes.byref(npr), ctypes.byref(ns)))
+        self.n_hex, self.n_prism, self.n_state = nh.value, npr.value, ns.value
+        n1 = p + 1
+        self.nu = {"hex": n1 ** 3, "prism": (n1 * (n1 + 1) // 2) * n1}
+
+    def __del__(self):
+        if getattr(self, "ctx", None):
+            self.lib.fr_destroy(self.ctx)
+            self.ctx = None
+
+    @property
+    def n_dof(self):
+        return self.n_state
+
+    def blocks(self):
+        """[(type name, element count, points per element)] in library order."""
+        out = []
+        if self.n_hex:
+            out.append(("hex", self.n_hex, self.nu["hex"]))
+        if self.n_prism:
+            out.append(("prism", self.n_prism, self.nu["prism"]))
+        return out
+
+    def upts_coords(self):
+        xyz = np.empty((self.n_state // 5, 3))
+        _check(self.ctx, self.lib.fr_upts_coords(self.ctx, xyz.ctypes.data))
+        out, k = [], 0
+        for _, E, nu in self.blocks():
+            out.append(xyz[k:k + E * nu].reshape(E, nu, 3))
+            k += E * nu
+        return out
+
+    def split(self, flat):
+        """Split a flat state (numpy or torch) into per-type (E, 5, N_u) views."""
+        out, k = [], 0
+        for _, E, nu in self.blocks():
+            out.append(flat[k:k + E * 5 * nu].reshape(E, 5, nu))
+            k += E * 5 * nu
+        return out
+
+    def connectivity(self):
+        cnt = ctypes.c_int64()
+        _check(self.ctx, self.lib.fr_connectivity(self.ctx, None, None, ctypes.byref(cnt)))
+        nbr = np.empty(cnt.value, dtype=np.int64)
+        isl = np.empty(cnt.value, dtype=np.int8)
+        _check(self.ctx, self.lib.fr_connectivity(self.ctx, nbr.ctypes.data, isl.ctypes.data, ctypes.byref(cnt)))
+        return nbr, isl
+
+    # ---- device calls (torch tensors, float64, contiguous, on the GPU) ----
+    @staticmethod
+    def _dev(t, n):
+        if t.dtype.itemsize != 8 or not t.is_contiguous() or t.numel() != n or t.device.type != "cuda":
+            raise FrError("expected a contiguous float64 device tensor of %d elements" % n)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def rhs(self, u, du):
+        _check(self.ctx, self.lib.fr_rhs(self.ctx, self._dev(u, self.n_state), self._dev(du, self.n_state)))
+
+    def rhs_stages(self, u, du, mask):
+        _check(self.ctx, self.lib.fr_rhs_stages(self.ctx, self._dev(u, self.n_state), self._dev(du, self.n_state),
+                                                int(mask)))
+
+    def set_state(self, u):
+        if isinstance(u, np.ndarray):
+            u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+            if u.size != self.n_state:
+                raise FrError("state size mismatch")
+            _check(self.ctx, self.lib.fr_set_state(self.ctx, u.ctypes.data, 0))
+        else:
+            _check(self.ctx, self.lib.fr_set_state(self.ctx, self._dev(u, self.n_state), 1))
+
+    def get_state(self, out=None):
+        if out is None:
+            out = np.empty(self.n_state)
+            _check(self.ctx, self.lib.fr_get_state(self.ctx, out.ctypes.data, 0))
+            return out
+        _check(self.ctx, self.lib.fr_get_state(self.ctx, self._dev(out, self.n_state), 1))
+        return out
+
+    def rk4(self, dt, nsteps=1):
+        _check(self.ctx, self.lib.fr_rk4_step(self.ctx, float(dt), int(nsteps)))
+
+    def integrals(self):
+        out = np.empty(5)
+        _check(self.ctx, self.lib.fr_integrals(self.ctx, out.ctypes.data))
+        return out

@@ -1,0 +1,423 @@
+// C ABI implementation (host): context, mesh, device buffers and the
+// right-hand-side / RK4 drivers.  See include/fr.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_host.h"
+#include "fr_kernels.h"
+
+struct fr_ctx {
+  fr_physics ph;
+  hipStream_t st = nullptr;
+  std::string err;
+  bool mesh_ok = false, dev_ok = false;
+  int p = 0;
+  fr::RefElem ref[2];
+  bool has[2] = {false, false};
+  fr::Mesh M;
+  int64_t off[2] = {0, 0}, n_state = 0;
+  fr::HostOps hops[2];
+  fr::GasHost gas;
+  // device buffers
+  double* d_state = nullptr;  // internal state
+  double* d_rk = nullptr;     // 3 x n_state: stage state, stage derivative, accumulator
+  void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
+  fr::FaceRec* d_faces = nullptr;
+  uint8_t* d_perms = nullptr;
+  void* d_met[2] = {nullptr, nullptr};
+  double* d_detj[2] = {nullptr, nullptr};
+  void* d_pops = nullptr;
+};
+
+namespace {
+
+fr_status fail(fr_ctx* c, fr_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(c, FR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t rsize(const fr_ctx* c) { return c->ph.prec == FR_PREC_FP64 ? 8 : 4; }
+
+template <typename T>
+void put(std::vector<unsigned char>& buf, const std::vector<double>& v, size_t n) {
+  buf.resize(n * sizeof(T));
+  T* p = reinterpret_cast<T*>(buf.data());
+  for (size_t i = 0; i < n; ++i) p[i] = T(v[i]);
+}
+
+void to_real(const fr_ctx* c, const std::vector<double>& v, std::vector<unsigned char>& buf) {
+  if (rsize(c) == 8)
+    put<double>(buf, v, v.size());
+  else
+    put<float>(buf, v, v.size());
+}
+
+fr_status ensure_device(fr_ctx* c) {
+  if (c->dev_ok) return FR_OK;
+  if (!c->mesh_ok) return fail(c, FR_ESTATE, "no mesh");
+  const fr::Mesh& M = c->M;
+  const int n = c->p + 1, nfp = n * n;
+  const size_t rs = rsize(c);
+  const int64_t S = M.nslots;
+  HIPCHK(hipMalloc(&c->d_state, sizeof(double) * c->n_state));
+  HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(double) * c->n_state, c->st));
+  HIPCHK(hipMalloc(&c->d_rk, sizeof(double) * c->n_state * 3));
+  HIPCHK(hipMalloc(&c->d_Uf, rs * S * 5 * nfp));
+  HIPCHK(hipMalloc(&c->d_Vf, rs * S * 4 * nfp));
+  HIPCHK(hipMalloc(&c->d_Rp, rs * c->n_state));
+  // faces
+  std::vector<fr::FaceRec> fr(S);
+  std::vector<double> geo(4 * S);
+  for (int64_t s = 0; s < S; ++s) {
+    fr[s].nbr = (int32_t)M.nbr_slot[s];
+    fr[s].info = (M.perm_id[s] << 1) | (M.is_left[s] ? 1 : 0);
+    for (int d = 0; d < 3; ++d) geo[4 * s + d] = M.nrm[3 * s + d];
+    geo[4 * s + 3] = M.mag[s];
+  }
+  HIPCHK(hipMalloc(&c->d_faces, sizeof(fr::FaceRec) * S));
+  HIPCHK(hipMemcpyAsync(c->d_faces, fr.data(), sizeof(fr::FaceRec) * S, hipMemcpyHostToDevice, c->st));
+  std::vector<unsigned char> buf;
+  to_real(c, geo, buf);
+  HIPCHK(hipMalloc(&c->d_fgeo, buf.size()));
+  HIPCHK(hipMemcpyAsync(c->d_fgeo, buf.data(), buf.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  std::vector<uint8_t> perms(M.perms.size() * nfp, 0);
+  for (size_t k = 0; k < M.perms.size(); ++k)
+    for (size_t r = 0; r < M.perms[k].size(); ++r) perms[k * nfp + r] = (uint8_t)M.perms[k][r];
+  HIPCHK(hipMalloc(&c->d_perms, perms.size()));
+  HIPCHK(hipMemcpy(c->d_perms, perms.data(), perms.size(), hipMemcpyHostToDevice));
+  for (int t = 0; t < 2; ++t) {
+    if (!c->has[t]) continue;
+    const int64_t E = M.nel[t];
+    std::vector<double> met(10 * E);
+    for (int64_t e = 0; e < E; ++e) {
+      for (int k = 0; k < 9; ++k) met[10 * e + k] = M.jinv[t][9 * e + k];
+      met[10 * e + 9] = M.detj[t][e];
+    }
+    to_real(c, met, buf);
+    HIPCHK(hipMalloc(&c->d_met[t], buf.size()));
+    HIPCHK(hipMemcpy(c->d_met[t], buf.data(), buf.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&c->d_detj[t], sizeof(double) * E));
+    HIPCHK(hipMemcpy(c->d_detj[t], M.detj[t].data(), sizeof(double) * E, hipMemcpyHostToDevice));
+  }
+  if (c->has[1]) {
+    size_t nb = fr::prism_ops_bytes(c->p, c->ph.prec);
+    std::vector<unsigned char> pb(nb);
+    fr::prism_ops_pack(c->ref[1], c->ph.prec, pb.data());
+    HIPCHK(hipMalloc(&c->d_pops, nb));
+    HIPCHK(hipMemcpy(c->d_pops, pb.data(), nb, hipMemcpyHostToDevice));
+  }
+  c->dev_ok = true;
+  return FR_OK;
+}
+
+fr::TypeArgs type_args(fr_ctx* c, int t, const double* u, double* du, int stage) {
+  fr::TypeArgs a;
+  a.p = c->p;
+  a.E = c->M.nel[t];
+  a.slot_base = c->M.slot_base[t];
+  a.stage = stage;
+  a.U = u + c->off[t];
+  a.du = du + c->off[t];
+  a.Uf = c->d_Uf;
+  a.Vf = c->d_Vf;
+  a.Rp = (char*)c->d_Rp + rsize(c) * c->off[t];
+  a.faces = c->d_faces;
+  a.fgeo = c->d_fgeo;
+  a.perms = c->d_perms;
+  a.met = c->d_met[t];
+  a.detj = c->d_detj[t];
+  a.dops = c->d_pops;
+  a.ops = &c->hops[t];
+  a.gas = &c->gas;
+  return a;
+}
+
+fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7) {
+  if (c->ph.form != FR_FORM_FUSED) return fail(c, FR_EUNSUPPORTED, "plain form not built");
+  for (int stage = 1; stage <= 4; stage <<= 1)
+    if (mask & stage)
+    for (int t = 0; t < 2; ++t) {
+      if (!c->has[t]) continue;
+      fr::TypeArgs a = type_args(c, t, u, du, stage);
+      hipError_t e = t == 0 ? fr::hex_rhs(a, c->ph.prec, c->st) : fr::prism_rhs(a, c->ph.prec, c->st);
+      if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+  return FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fr_physics_default(fr_physics* ph) {
+  if (!ph) return;
+  ph->gamma = 1.4;
+  ph->prandtl = 0.71;
+  ph->mu = 1.0 / 1600.0;
+  ph->ldg_beta = 0.5;
+  ph->ldg_tau = 0.1;
+  ph->pref = 0.0;
+  ph->prec = FR_PREC_FP64;
+  ph->form = FR_FORM_FUSED;
+}
+
+fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
+  if (!ph || !out) return FR_EINVAL;
+  *out = nullptr;
+  if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
+      !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
+      ph->form > 1)
+    return FR_EINVAL;
+  fr_ctx* c = new (std::nothrow) fr_ctx();
+  if (!c) return FR_ENOMEM;
+  c->ph = *ph;
+  c->st = (hipStream_t)stream;
+  c->gas = {ph->gamma, ph->prandtl, ph->mu, ph->pref, ph->ldg_beta, ph->ldg_tau};
+  *out = c;
+  return FR_OK;
+}
+
+fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind) {
+  if (!c) return FR_EINVAL;
+  if (c->mesh_ok) return fail(c, FR_ESTATE, "mesh already built");
+  if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind > 2) return fail(c, FR_EINVAL, "bad mesh size");
+  if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
+  try {
+    c->p = p;
+    fr::build_ref(0, p, c->ref[0]);
+    fr::build_ref(1, p, c->ref[1]);
+    const fr::RefElem* refs[2] = {&c->ref[0], &c->ref[1]};
+    std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
+    if (!e.empty()) return fail(c, FR_EINVAL, e);
+  } catch (const std::exception& ex) {
+    return fail(c, FR_EINVAL, ex.what());
+  }
+  for (int t = 0; t < 2; ++t) {
+    c->has[t] = c->M.nel[t] > 0;
+    const fr::RefElem& r = c->ref[t];
+    fr::HostOps& h = c->hops[t];
+    h.I = r.line.I.data();
+    h.D = r.line.D.data();
+    h.P = r.line.P.data();
+    h.AP = r.line.AP.data();
+    h.lb = r.line.lb.data();
+    h.rb = r.line.rb.data();
+    h.liftL = r.line.liftL.data();
+    h.liftR = r.line.liftR.data();
+    h.tri = &r.tri;
+    h.ref = &r;
+  }
+  c->off[0] = 0;
+  c->off[1] = c->M.nel[0] * 5 * c->ref[0].nu;
+  c->n_state = c->off[1] + c->M.nel[1] * 5 * c->ref[1].nu;
+  c->mesh_ok = true;
+  return FR_OK;
+}
+
+fr_status fr_layout(const fr_ctx* c, int64_t* nh, int64_t* np, int64_t* ns) {
+  if (!c) return FR_EINVAL;
+  if (!c->mesh_ok) return FR_ESTATE;
+  if (nh) *nh = c->M.nel[0];
+  if (np) *np = c->M.nel[1];
+  if (ns) *ns = c->n_state;
+  return FR_OK;
+}
+
+fr_status fr_upts_coords(const fr_ctx* c, double* xyz) {
+  if (!c || !xyz) return FR_EINVAL;
+  if (!c->mesh_ok) return FR_ESTATE;
+  int64_t k = 0;
+  for (int t = 0; t < 2; ++t) {
+    const fr::RefElem& r = c->ref[t];
+    for (int64_t e = 0; e < c->M.nel[t]; ++e) {
+      const double* A = &c->M.jac[t][9 * e];
+      const double* o = &c->M.org[t][3 * e];
+      for (int u = 0; u < r.nu; ++u) {
+        const double* xi = &r.upts[3 * u];
+        for (int d = 0; d < 3; ++d)
+          xyz[3 * (k + u) + d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
+      }
+      k += r.nu;
+    }
+  }
+  return FR_OK;
+}
+
+fr_status fr_rhs(fr_ctx* c, const double* u, double* du) {
+  if (!c) return FR_EINVAL;
+  if (!u || !du) return fail(c, FR_EINVAL, "null buffer");
+  if (u == du) return fail(c, FR_EINVAL, "u and du must not alias");
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  return launch_rhs(c, u, du);
+}
+
+fr_status fr_rhs_stages(fr_ctx* c, const double* u, double* du, int mask) {
+  if (!c) return FR_EINVAL;
+  if (!u || !du || mask < 1 || mask > 7) return fail(c, FR_EINVAL, "bad arguments");
+  if (u == du) return fail(c, FR_EINVAL, "u and du must not alias");
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  return launch_rhs(c, u, du, mask);
+}
+
+fr_status fr_set_state(fr_ctx* c, const double* u, int on_device) {
+  if (!c) return FR_EINVAL;
+  if (!u) return fail(c, FR_EINVAL, "null buffer");
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  HIPCHK(hipMemcpyAsync(c->d_state, u, sizeof(double) * c->n_state,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
+  if (!on_device) HIPCHK(hipStreamSynchronize(c->st));
+  return FR_OK;
+}
+
+fr_status fr_get_state(fr_ctx* c, double* u, int on_device) {
+  if (!c) return FR_EINVAL;
+  if (!u) return fail(c, FR_EINVAL, "null buffer");
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  HIPCHK(hipMemcpyAsync(u, c->d_state, sizeof(double) * c->n_state,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FR_OK;
+}
+
+fr_status fr_rk4_step(fr_ctx* c, double dt, int nsteps) {
+  if (!c) return FR_EINVAL;
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(c, FR_EINVAL, "bad step");
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  const int64_t N = c->n_state;
+  double* ust = c->d_rk;
+  double* k = c->d_rk + N;
+  double* acc = c->d_rk + 2 * N;
+  // classical RK4: k1 = R(u), k2 = R(u + dt/2 k1), k3 = R(u + dt/2 k2),
+  // k4 = R(u + dt k3), u += dt/6 (k1 + 2 k2 + 2 k3 + k4)
+  const double wa[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
+  const double wb[4] = {dt / 2, dt / 2, dt, 0.0};
+  for (int step = 0; step < nsteps; ++step) {
+    for (int st = 0; st < 4; ++st) {
+      s = launch_rhs(c, st == 0 ? c->d_state : ust, k);
+      if (s != FR_OK) return s;
+      double* outu = st == 3 ? c->d_state : ust;
+      HIPCHK(fr::rk_stage(N, c->d_state, k, acc, outu, wa[st], wb[st], st == 0 ? 1 : (st == 3 ? 2 : 0), c->st));
+    }
+  }
+  return FR_OK;
+}
+
+fr_status fr_integrals(fr_ctx* c, double* out5) {
+  if (!c || !out5) return FR_EINVAL;
+  fr_status s = ensure_device(c);
+  if (s != FR_OK) return s;
+  std::vector<double> u(c->n_state);
+  s = fr_get_state(c, u.data(), 0);
+  if (s != FR_OK) return s;
+  for (int v = 0; v < 5; ++v) out5[v] = 0.0;
+  for (int t = 0; t < 2; ++t) {
+    const fr::RefElem& r = c->ref[t];
+    for (int64_t e = 0; e < c->M.nel[t]; ++e) {
+      const double* ue = &u[c->off[t] + e * 5 * r.nu];
+      for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (int q = 0; q < r.nu; ++q) acc += r.wu[q] * ue[v * r.nu + q];
+        out5[v] += c->M.detj[t][e] * acc;
+      }
+    }
+  }
+  return FR_OK;
+}
+
+fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count) {
+  if (!name || (etype != 0 && etype != 1)) return FR_EINVAL;
+  if (p < 1 || p > 4) return FR_EUNSUPPORTED;
+  fr::RefElem r;
+  try {
+    fr::build_ref(etype, p, r);
+  } catch (...) {
+    return FR_EINVAL;
+  }
+  const std::vector<double>* v = nullptr;
+  std::vector<double> tmp;
+  std::string nm(name);
+  if (nm == "upts") v = &r.upts;
+  else if (nm == "fpts") v = &r.fpts;
+  else if (nm == "qpts") v = &r.qpts;
+  else if (nm == "qwts") v = &r.qwts;
+  else if (nm == "M0") v = &r.M0;
+  else if (nm == "M3") v = &r.M3;
+  else if (nm == "M7") v = &r.M7;
+  else if (nm == "M8") v = &r.M8;
+  else if (nm == "wu") v = &r.wu;
+  else if (nm == "Dxi" || nm == "Deta" || nm == "Dzeta") {
+    int d = nm == "Dxi" ? 0 : (nm == "Deta" ? 1 : 2);
+    tmp.assign(r.Dg.begin() + (size_t)d * r.nu * r.nu, r.Dg.begin() + (size_t)(d + 1) * r.nu * r.nu);
+    v = &tmp;
+  } else
+    return FR_EINVAL;
+  if (count) *count = (int64_t)v->size();
+  if (!out) return FR_OK;
+  if (cap < (int64_t)v->size()) return FR_EINVAL;
+  std::memcpy(out, v->data(), sizeof(double) * v->size());
+  return FR_OK;
+}
+
+fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_t* n_fpts) {
+  if (!c) return FR_EINVAL;
+  if (!c->mesh_ok) return FR_ESTATE;
+  const fr::Mesh& M = c->M;
+  // flat flux-point numbering: types in order, element, flux point
+  int64_t base[2] = {0, M.nel[0] * c->ref[0].nf};
+  int64_t total = base[1] + M.nel[1] * c->ref[1].nf;
+  if (n_fpts) *n_fpts = total;
+  if (!nbr) return FR_OK;
+  const int nfc[2] = {6, 5};
+  for (int64_t s = 0; s < M.nslots; ++s) {
+    int t = (M.nel[1] > 0 && s >= M.slot_base[1]) ? 1 : 0;
+    int64_t e = (s - M.slot_base[t]) / nfc[t];
+    int f = int((s - M.slot_base[t]) % nfc[t]);
+    int64_t o = M.nbr_slot[s];
+    int to = (M.nel[1] > 0 && o >= M.slot_base[1]) ? 1 : 0;
+    int64_t eo = (o - M.slot_base[to]) / nfc[to];
+    int fo = int((o - M.slot_base[to]) % nfc[to]);
+    const fr::RefElem& r = c->ref[t];
+    const fr::RefElem& ro = c->ref[to];
+    const std::vector<int>& pm = M.perms[M.perm_id[s]];
+    for (int q = 0; q < r.face_npts[f]; ++q) {
+      int64_t i = base[t] + e * r.nf + r.face_start[f] + q;
+      nbr[i] = base[to] + eo * ro.nf + ro.face_start[fo] + pm[q];
+      if (is_left) is_left[i] = (int8_t)M.is_left[s];
+    }
+  }
+  return FR_OK;
+}
+
+const char* fr_last_error(const fr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void fr_destroy(fr_ctx* c) {
+  if (!c) return;
+  if (c->dev_ok || c->d_state) {
+    (void)hipStreamSynchronize(c->st);
+    void* bufs[] = {c->d_state, c->d_rk, c->d_Uf, c->d_Vf, c->d_Rp, c->d_fgeo, c->d_faces, c->d_perms,
+                    c->d_met[0], c->d_met[1], c->d_detj[0], c->d_detj[1], c->d_pops};
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+  }
+  delete c;
+}
+
+}  // extern "C"

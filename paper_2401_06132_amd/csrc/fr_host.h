@@ -1,0 +1,91 @@
+// Host-side data structures of the flux-reconstruction library: reference
+// elements with their factorised operators, and the periodic box mesh with
+// its face connectivity.  No device code here.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fr {
+
+// 1-D operators on Gauss-Legendre solution points (n = p+1) and m GL
+// quadrature points.  These are the factors of the hex operators
+// (section 4: M7 and M9 factor into per-direction sparse sweeps).
+struct Line1D {
+  int n = 0, m = 0;
+  std::vector<double> x, w;    // GL(n) nodes and weights
+  std::vector<double> xq, wq;  // GL(m)
+  std::vector<double> D;       // n x n  D[i][j] = l_j'(x_i)
+  std::vector<double> I;       // m x n  I[a][i] = l_i(xq_a)
+  std::vector<double> Dq;      // m x n  l_i'(xq_a)
+  std::vector<double> P;       // n x m  L2 projection  I^T W_q / w_i
+  std::vector<double> AP;      // n x m  -(Dq^T W_q)/w_i : projection followed by the
+                               //        SBP form of (M1 - M3 M2) along the line
+  std::vector<double> lb, rb;  // l_i(-1), l_i(+1)
+  std::vector<double> liftL, liftR;  // l_i(-1)/w_i, l_i(+1)/w_i  (DG correction)
+};
+
+// Triangle factors of the prism operators (section 4.1: block structured
+// triangle-plane operator times a sparse line operator).
+struct Tri {
+  int p = 0, nt = 0, ntq = 0;
+  std::vector<double> nodes;        // nt x 2
+  std::vector<double> qp, qw;       // ntq x 2, ntq  (conical rule, degree 2p+1)
+  std::vector<double> Tq;           // ntq x nt  l_t(q)
+  std::vector<double> Dxi, Deta;    // nt x nt   derivatives of l_t at the nodes
+  std::vector<double> DxiQ, DetaQ;  // ntq x nt  derivatives of l_t at q
+  std::vector<double> mass, massInv;  // nt x nt
+  std::vector<double> PT;           // nt x ntq  M_T^-1 Tq^T W
+  std::vector<double> APxi, APeta;  // nt x ntq  -M_T^-1 DQ^T W
+  std::vector<double> Tedge;        // 3 x n x nt   l_t at the GL points of each edge
+  std::vector<double> LiftEdge;     // 3 x nt x n   M_T^-1 Tedge^T diag(w) |edge jac|
+  double edgeJac[3] = {1, 1, 1};
+  double edgeNormal[3][2] = {{0, -1}, {0, 0}, {-1, 0}};
+};
+
+// Geometry of a reference element (hex or prism) and its dense operators.
+struct RefElem {
+  int etype = 0, p = 0, n = 0, m = 0;
+  int nu = 0, nf = 0, nq = 0, nfaces = 0, nfp_max = 0;
+  Line1D line;
+  Tri tri;  // prisms only
+  std::vector<double> upts, fpts, qpts, qwts;  // N x 3 / N
+  std::vector<int> face_start, face_npts;      // per face
+  std::vector<double> face_normal;             // nfaces x 3, unit reference normals
+  std::vector<double> wu;                      // integrals of the nodal basis
+  // dense operators of section 2.2 (row-major), built from the factors
+  std::vector<double> M0, M3, M7, M8, Dg;  // Dg: 3 x nu x nu
+};
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x, std::vector<double>& w);
+void triangle_nodes(int p, std::vector<double>& xy);
+void build_ref(int etype, int p, RefElem& r);
+
+// Periodic box mesh with face connectivity.
+struct Mesh {
+  int nx = 0, ny = 0, nz = 0, p = 0, kind = 0;
+  double lo = 0, hi = 0;
+  int64_t nel[2] = {0, 0};
+  std::vector<double> org[2];    // element origin (x at reference 0)
+  std::vector<double> jac[2];    // J (3x3 row-major, rows x,y,z cols xi,eta,zeta)
+  std::vector<double> jinv[2];   // J^-1
+  std::vector<double> detj[2];
+  std::vector<int64_t> gid[2];   // mesh-order index
+  // face slots: hex e*6+f, prisms slot_base[1] + e*5+f
+  int64_t slot_base[2] = {0, 0};
+  int64_t nslots = 0;
+  std::vector<int64_t> nbr_slot;  // paired slot
+  std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]
+  std::vector<uint8_t> is_left;
+  std::vector<double> nrm;        // per slot: L-side physical unit normal (3)
+  std::vector<double> mag;        // per slot: L-side area factor |det J J^-T n|
+  std::vector<std::vector<int>> perms;
+};
+
+// Build the box mesh and its connectivity; returns an error string or "".
+std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
+                           const RefElem* refs[2], Mesh& m);
+
+}  // namespace fr

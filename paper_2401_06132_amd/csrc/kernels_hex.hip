@@ -1,0 +1,533 @@
+// Fused flux-reconstruction kernels for hexahedra (gfx950).
+//
+// The paper's kernel groups (section 6.1, figure NSAAKG) become three
+// kernels per right-hand side:
+//   hex_disu     group 1: disu (eq. FR-disu) -- solution at the flux points
+//   hex_volume   groups 2+3: con_u, tgradpcoru, tgradcoru, gradcoru,
+//                gradcoru_fpts, uqpts, gradcoru_qpts, tdisf, tdivtpcorf;
+//                every intermediate stays in LDS/registers; the outputs are
+//                the normal viscous flux at the element's own flux points and
+//                the volume part of the transformed divergence
+//   hex_surface  groups 4+5: comm_flux, tdivtconf, negdivconf
+// The anti-aliasing operators are applied by sum factorisation (section 4):
+// M7 = I (x) I (x) I and, combined with the DG divergence (M1 - M3 M2) M9,
+// the projection-divergence of component d is AP along d and P along the
+// other two directions, where P = W_u^-1 I^T W_q and AP = -W_u^-1 Dq^T W_q
+// (summation-by-parts form of the GL collocation operators).
+//
+// Threads work on "lines": a thread holds the n (or m) values of one 1-D line
+// of one field in registers and applies a 1-D operator whose entries are
+// wave-uniform (kernel-argument constants).  The column phase keeps one
+// (x,y) quadrature column per thread and runs the z direction on the fly:
+// interpolate the 20 fields (state + gradient), evaluate the flux, and
+// accumulate the z projection, so the quadrature-point data never exists as
+// a whole.  A workgroup owns EB elements; element data is contiguous in HBM
+// (element-major layout), so every global load/store is coalesced.
+#include "fr_device.h"
+#include "fr_kernels.h"
+
+namespace fr {
+
+template <int P, typename R>
+struct HexOps {
+  static constexpr int n = P + 1, m = P + 3;
+  R I[m][n];   // l_i at GL(m)
+  R D[n][n];   // l_j' at the solution points
+  R Pj[n][m];  // projection
+  R AP[n][m];  // projection + divergence
+  R lb[n], rb[n], liftL[n], liftR[n];
+};
+
+template <int P>
+struct HexCfg {
+  static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
+  static constexpr int SZ_X = 20 * NU;  // state (5) + gradients (15)
+  static constexpr int SZ_J = 30 * NFP; // jumps C - u^f, 6 faces x 5 vars
+  static constexpr int SZ_Z = 15 * m * m * n;
+  static constexpr int SZ_A = (SZ_X + SZ_J > SZ_Z) ? SZ_X + SZ_J : SZ_Z;
+  static constexpr int SZ_T1 = 20 * m * n * n;
+  static constexpr int PER_ELEM = SZ_A + SZ_T1;
+};
+
+// index of the point with coordinate index i along axis ax and tangential
+// indices (a, b) (tangential axes in increasing order)
+template <int n>
+__device__ __forceinline__ int hex_pt(int ax, int i, int a, int b) {
+  return ax == 0 ? i + n * (a + n * b) : (ax == 1 ? a + n * (i + n * b) : a + n * (b + n * i));
+}
+
+// select v[idx] for a lane-varying idx from a compile-time array (no
+// dynamic indexing into kernel arguments)
+template <int N, typename R>
+__device__ __forceinline__ R sel(const R (&v)[N], int idx) {
+  R r = v[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = idx == k ? v[k] : r;
+  return r;
+}
+
+// ----------------------------------------------------------------- disu
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) hex_disu(const double* __restrict__ U, R* __restrict__ Uf,
+                                               const HexOps<P, R> op, const double eref, const int E,
+                                               const int slot_base) {
+  using C = HexCfg<P>;
+  constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
+  __shared__ R sU[EB * 5 * NU];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
+    R val = R(0);
+    if (e < E) {
+      double x = U[(size_t)e * 5 * NU + r];
+      if (r >= 4 * NU) x -= eref;
+      val = R(x);
+    }
+    sU[it] = val;
+  }
+  __syncthreads();
+  for (int it = tid; it < EB * 15 * NFP; it += NT) {
+    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
+    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+    const int a = r % n, b = r / n, e = e0 + le;
+    if (e >= E) continue;
+    R xm = R(0), xp = R(0);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const R x = sU[le * 5 * NU + v * NU + hex_pt<n>(ax, i, a, b)];
+      xm += op.lb[i] * x;
+      xp += op.rb[i] * x;
+    }
+    const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
+    Uf[s0 * 5 * NFP + v * NFP + r] = xm;
+    Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = xp;
+  }
+}
+
+// --------------------------------------------------------------- volume
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT)
+    hex_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
+               const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
+               const R* __restrict__ met, const HexOps<P, R> op, const Gas<R> g, const double eref, const int E,
+               const int slot_base) {
+  using C = HexCfg<P>;
+  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  __shared__ R smem[EB * PE];
+  __shared__ R sMet[EB][10];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+#define XS(le) (smem + (le)*PE)                 /* [20][NU] state + gradients */
+#define JS(le) (smem + (le)*PE + C::SZ_X)       /* [6][5][NFP] jumps          */
+#define ZS(le) (smem + (le)*PE)                 /* [3][5][m][m][n]            */
+#define TS(le) (smem + (le)*PE + C::SZ_A)       /* [20][m][n][n]              */
+
+  // phase 0: state (reference form), metrics, neighbour states at own faces
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
+    R val = R(0);
+    if (e < E) {
+      double x = U[(size_t)e * 5 * NU + r];
+      if (r >= 4 * NU) x -= eref;
+      val = R(x);
+    }
+    XS(le)[r] = val;
+  }
+  for (int it = tid; it < EB * 10; it += NT) {
+    const int le = it / 10, k = it - le * 10, e = e0 + le;
+    sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
+  }
+  for (int it = tid; it < EB * 30 * NFP; it += NT) {
+    const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
+    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP, e = e0 + le;
+    R val = R(0);
+    if (e < E) {
+      const FaceRec fr = faces[slot_base + e * 6 + f];
+      const int rr = perms[(fr.info >> 1) * NFP + r];
+      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    }
+    JS(le)[r0] = val;
+  }
+  __syncthreads();
+
+  // phase 1: own face values and jumps C - u^f (eq. FR-conu):
+  //   L side: (1/2 + beta)(u_nbr - u_own), R side: (1/2 - beta)(u_nbr - u_own)
+  for (int it = tid; it < EB * 15 * NFP; it += NT) {
+    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
+    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+    const int a = r % n, b = r / n, e = e0 + le;
+    if (e >= E) continue;
+    R xm = R(0), xp = R(0);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const R x = XS(le)[v * NU + hex_pt<n>(ax, i, a, b)];
+      xm += op.lb[i] * x;
+      xp += op.rb[i] * x;
+    }
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      const int f = 2 * ax + sg;
+      const int info = faces[slot_base + e * 6 + f].info;
+      const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
+      R* jj = JS(le) + (f * 5 + v) * NFP + r;
+      *jj = coef * (*jj - (sg ? xp : xm));
+    }
+  }
+  __syncthreads();
+
+  // phase 2: corrected reference gradient along each axis (eq. FR-qfinal,
+  // M4 U + M6 (C - U^f)), one line per thread
+  for (int it = tid; it < EB * 15 * NFP; it += NT) {
+    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
+    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+    const int a = r % n, b = r / n;
+    R x[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) x[i] = XS(le)[v * NU + hex_pt<n>(ax, i, a, b)];
+    const R jm = JS(le)[((2 * ax) * 5 + v) * NFP + r], jp = JS(le)[((2 * ax + 1) * 5 + v) * NFP + r];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      R s = op.liftR[i] * jp - op.liftL[i] * jm;
+#pragma unroll
+      for (int c = 0; c < n; ++c) s += op.D[i][c] * x[c];
+      XS(le)[(5 + ax * 5 + v) * NU + hex_pt<n>(ax, i, a, b)] = s;
+    }
+  }
+  __syncthreads();
+
+  // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU;
+    R* X = XS(le);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+    }
+  }
+  __syncthreads();
+
+  // phase 4a: gradcoru_fpts + normal viscous flux at own flux points
+  // phase 4b: first anti-aliasing sweep (x) of the 20 fields
+  constexpr int NFACE_IT = 3 * NFP, NSWEEP_IT = 20 * NFP;
+  for (int it = tid; it < EB * (NFACE_IT + NSWEEP_IT); it += NT) {
+    if (it < EB * NFACE_IT) {
+      const int le = it / NFACE_IT, r0 = it - le * NFACE_IT;
+      const int ax = r0 / NFP, r = r0 - ax * NFP, a = r % n, b = r / n, e = e0 + le;
+      if (e >= E) continue;
+      const R* X = XS(le);
+      R fm[20], fp[20];
+#pragma unroll
+      for (int fld = 0; fld < 20; ++fld) {
+        R sm = R(0), sp = R(0);
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          const R x = X[fld * NU + hex_pt<n>(ax, i, a, b)];
+          sm += op.lb[i] * x;
+          sp += op.rb[i] * x;
+        }
+        fm[fld] = sm;
+        fp[fld] = sp;
+      }
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        const R* w = sg ? fp : fm;
+        const int slot = slot_base + e * 6 + 2 * ax + sg;
+        const int info = faces[slot].info;
+        const R sgn = (info & 1) ? R(1) : R(-1);
+        const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+        R u[5], q[3][5], V[4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          u[v] = w[v];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
+        }
+        normal_viscous(u, q, nn, g, V);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
+      }
+    } else {
+      const int i2 = it - EB * NFACE_IT;
+      const int le = i2 / NSWEEP_IT, r0 = i2 - le * NSWEEP_IT, fld = r0 / NFP, r = r0 - fld * NFP;
+      const int j = r % n, l = r / n;
+      R x[n];
+#pragma unroll
+      for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * (j + n * l)];
+#pragma unroll
+      for (int a = 0; a < m; ++a) {
+        R s = R(0);
+#pragma unroll
+        for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
+        TS(le)[((fld * m + a) * n + j) * n + l] = s;
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 5: quadrature columns.  y interpolation, then for each z level:
+  // z interpolation (uqpts, gradcoru_qpts), flux (tdisf, eq. FR-tdisfq) and
+  // the z part of the projection-divergence (tdivtpcorf)
+  for (int it = tid; it < EB * m * m; it += NT) {
+    const int le = it / (m * m), r = it - le * (m * m), a = r / m, b = r - a * m;
+    R Ib[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      R t = op.I[0][j];
+#pragma unroll
+      for (int bb = 1; bb < m; ++bb) t = b == bb ? op.I[bb][j] : t;
+      Ib[j] = t;
+    }
+    R t2[20][n];
+    const R* T = TS(le);
+#pragma unroll
+    for (int fld = 0; fld < 20; ++fld)
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < n; ++j) s += Ib[j] * T[((fld * m + a) * n + j) * n + l];
+        t2[fld][l] = s;
+      }
+    R S[3][3];
+    const R dj = sMet[le][9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[le][3 * d + c];
+    R acc[3][5][n];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int l = 0; l < n; ++l) acc[d][v][l] = R(0);
+#pragma unroll
+    for (int kq = 0; kq < m; ++kq) {
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int fld = 0; fld < 20; ++fld) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < n; ++l) s += op.I[kq][l] * t2[fld][l];
+        if (fld < 5)
+          u[fld] = s;
+        else
+          q[(fld - 5) / 5][(fld - 5) % 5] = s;
+      }
+      point_flux(u, q, g, f);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const R ft = S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
+#pragma unroll
+          for (int l = 0; l < n; ++l) acc[d][v][l] += (d == 2 ? op.AP[l][kq] : op.Pj[l][kq]) * ft;
+        }
+    }
+    // the column region aliases T1 of other columns only through ZS, which
+    // lives in the (dead) state/gradient region
+    R* Z = ZS(le);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int l = 0; l < n; ++l) Z[(((d * 5 + v) * m + a) * m + b) * n + l] = acc[d][v][l];
+  }
+  __syncthreads();
+
+  // phase 6: y projection: X' = P_y X, Y' = AP_y Y + P_y Z
+  for (int it = tid; it < EB * 5 * m * n; it += NT) {
+    const int le = it / (5 * m * n), r0 = it - le * (5 * m * n);
+    const int v = r0 / (m * n), r1 = r0 - v * (m * n), a = r1 / n, l = r1 - a * n;
+    const R* Z = ZS(le);
+    R zx[m], zy[m], zz[m];
+#pragma unroll
+    for (int b = 0; b < m; ++b) {
+      zx[b] = Z[(((0 * 5 + v) * m + a) * m + b) * n + l];
+      zy[b] = Z[(((1 * 5 + v) * m + a) * m + b) * n + l];
+      zz[b] = Z[(((2 * 5 + v) * m + a) * m + b) * n + l];
+    }
+    R* Y = TS(le);
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      R sx = R(0), sy = R(0);
+#pragma unroll
+      for (int b = 0; b < m; ++b) {
+        sx += op.Pj[j][b] * zx[b];
+        sy += op.AP[j][b] * zy[b] + op.Pj[j][b] * zz[b];
+      }
+      Y[(((0 * 5 + v) * m + a) * n + j) * n + l] = sx;
+      Y[(((1 * 5 + v) * m + a) * n + j) * n + l] = sy;
+    }
+  }
+  __syncthreads();
+
+  // phase 7: x projection: R_vol = AP_x X' + P_x Y'
+  for (int it = tid; it < EB * 5 * NFP; it += NT) {
+    const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), v = r0 / NFP, r = r0 - v * NFP;
+    const int j = r % n, l = r / n, e = e0 + le;
+    if (e >= E) continue;
+    const R* Y = TS(le);
+    R y0[m], y1[m];
+#pragma unroll
+    for (int a = 0; a < m; ++a) {
+      y0[a] = Y[(((0 * 5 + v) * m + a) * n + j) * n + l];
+      y1[a] = Y[(((1 * 5 + v) * m + a) * n + j) * n + l];
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int a = 0; a < m; ++a) s += op.AP[i][a] * y0[a] + op.Pj[i][a] * y1[a];
+      Rp[(size_t)e * 5 * NU + v * NU + i + n * (j + n * l)] = s;
+    }
+  }
+#undef XS
+#undef JS
+#undef ZS
+#undef TS
+}
+
+// -------------------------------------------------------------- surface
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT)
+    hex_surface(const R* __restrict__ Uf, const R* __restrict__ Vf, const R* __restrict__ Rp, double* __restrict__ du,
+                const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
+                const double* __restrict__ detj, const HexOps<P, R> op, const Gas<R> g, const int E,
+                const int slot_base) {
+  using C = HexCfg<P>;
+  constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
+  __shared__ R sD[EB * 30 * NFP];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  // comm_flux: common normal flux at every own flux point, times +-mag
+  for (int it = tid; it < EB * 6 * NFP; it += NT) {
+    const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
+    if (e >= E) continue;
+    const int slot = slot_base + e * 6 + f;
+    const FaceRec fr = faces[slot];
+    const int rr = perms[(fr.info >> 1) * NFP + r];
+    const bool left = fr.info & 1;
+    R uo[5], un[5], Vo[4], Vn[4], F[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      uo[v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
+      un[v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Vo[k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
+      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
+    }
+    const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
+    const R mag = fgeo[4 * slot + 3];
+    if (left)
+      common_flux(uo, un, Vo, Vn, nL, g, F);
+    else
+      common_flux(un, uo, Vn, Vo, nL, g, F);
+    const R sc = left ? mag : -mag;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sD[(le * 6 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
+  }
+  __syncthreads();
+  // tdivtconf (lift of the common flux, DG correction) + negdivconf
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
+    if (e >= E) continue;
+    const int i = s % n, j = (s / n) % n, k = s / (n * n);
+    const R* D = sD + le * 30 * NFP + v * NFP;
+    R acc = Rp[(size_t)e * 5 * NU + r0];
+    acc += sel(op.liftL, i) * D[0 * 5 * NFP + j + n * k] + sel(op.liftR, i) * D[1 * 5 * NFP + j + n * k];
+    acc += sel(op.liftL, j) * D[2 * 5 * NFP + i + n * k] + sel(op.liftR, j) * D[3 * 5 * NFP + i + n * k];
+    acc += sel(op.liftL, k) * D[4 * 5 * NFP + i + n * j] + sel(op.liftR, k) * D[5 * 5 * NFP + i + n * j];
+    du[(size_t)e * 5 * NU + r0] = -double(acc) / detj[e];
+  }
+}
+
+// ------------------------------------------------------------ launchers
+template <int P, typename R>
+static HexOps<P, R> make_hex_ops(const HostOps& h) {
+  HexOps<P, R> o;
+  constexpr int n = P + 1, m = P + 3;
+  for (int a = 0; a < m; ++a)
+    for (int i = 0; i < n; ++i) o.I[a][i] = R(h.I[a * n + i]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) o.D[i][j] = R(h.D[i * n + j]);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < m; ++a) {
+      o.Pj[i][a] = R(h.P[i * m + a]);
+      o.AP[i][a] = R(h.AP[i * m + a]);
+    }
+  for (int i = 0; i < n; ++i) {
+    o.lb[i] = R(h.lb[i]);
+    o.rb[i] = R(h.rb[i]);
+    o.liftL[i] = R(h.liftL[i]);
+    o.liftR[i] = R(h.liftR[i]);
+  }
+  return o;
+}
+
+template <typename R>
+static Gas<R> make_gas(const GasHost& g) {
+  Gas<R> o;
+  o.gamma = R(g.gamma);
+  o.gm1 = R(g.gamma - 1.0);
+  o.mu = R(g.mu);
+  o.muh = R(g.mu * g.gamma / g.prandtl);
+  o.pref = R(g.pref);
+  o.eref = R(g.pref / (g.gamma - 1.0));
+  o.href = R(g.gamma * g.pref / (g.gamma - 1.0));
+  o.beta = R(g.beta);
+  o.tau = R(g.tau);
+  return o;
+}
+
+template <int P>
+struct HexLaunch {
+  static constexpr int EB_D = 2, NT_D = 128;   // FP64 volume
+  static constexpr int EB_S = 4, NT_S = 256;   // FP32 volume
+};
+
+template <int P, typename R>
+static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
+  const HexOps<P, R> op = make_hex_ops<P, R>(*a.ops);
+  const Gas<R> g = make_gas<R>(*a.gas);
+  const int E = (int)a.E;
+  if (E == 0) return hipSuccess;
+  constexpr bool dbl = sizeof(R) == 8;
+  constexpr int EB = dbl ? HexLaunch<P>::EB_D : HexLaunch<P>::EB_S;
+  constexpr int NT = dbl ? HexLaunch<P>::NT_D : HexLaunch<P>::NT_S;
+  const double eref = a.gas->pref / (a.gas->gamma - 1.0);
+  const int sb = (int)a.slot_base;
+  if (a.stage & 1) {
+    constexpr int EBA = 8, NTA = 256;
+    hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA>), dim3((E + EBA - 1) / EBA), dim3(NTA), 0, st, a.U, (R*)a.Uf, op,
+                       eref, E, sb);
+  }
+  if (a.stage & 2) {
+    hipLaunchKernelGGL((hex_volume<P, R, EB, NT>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U, (const R*)a.Uf,
+                       (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op, g, eref, E, sb);
+  }
+  if (a.stage & 4) {
+    constexpr int EBC = 4, NTC = 256;
+    hipLaunchKernelGGL((hex_surface<P, R, EBC, NTC>), dim3((E + EBC - 1) / EBC), dim3(NTC), 0, st, (const R*)a.Uf,
+                       (const R*)a.Vf, (const R*)a.Rp, a.du, a.faces, (const R*)a.fgeo, a.perms, a.detj, op, g, E,
+                       sb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t hex_rhs(const TypeArgs& a, int prec, hipStream_t st) {
+  const bool d = prec == 0;
+  switch (a.p) {
+    case 1: return d ? hex_rhs_t<1, double>(a, st) : hex_rhs_t<1, float>(a, st);
+    case 2: return d ? hex_rhs_t<2, double>(a, st) : hex_rhs_t<2, float>(a, st);
+    case 3: return d ? hex_rhs_t<3, double>(a, st) : hex_rhs_t<3, float>(a, st);
+    case 4: return d ? hex_rhs_t<4, double>(a, st) : hex_rhs_t<4, float>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fr

@@ -1,0 +1,242 @@
+// Periodic box meshes and face connectivity (host).
+//
+// Cells c = i + nx (j + ny k).  Hexahedra are axis aligned.  A prism cell is
+// split by the diagonal of its x-z face from (x0+h, z0) to (x0, z0+h) and
+// extruded along y; the two prisms map the reference prism (triangle in
+// (xi, eta), line in zeta) with positive Jacobian:
+//   first : x = x0 + (eta+1) hx/2,      y = y0 + (zeta+1) hy/2, z = z0 + (xi+1) hz/2
+//   second: x = x0 + hx - (eta+1) hx/2, y = y0 + (zeta+1) hy/2, z = z0 + hz - (xi+1) hz/2
+// so every z = const cell face is a full prism quadrilateral and a mixed mesh
+// (hexahedra below z = 0) is conforming.
+//
+// Connectivity: faces are paired by their centroids modulo the period, then
+// the points of each face pair are matched by coordinates (section 2.1: paired
+// flux points coincide in physical space).  Of each pair, "L" is the element
+// with the lower mesh-order index; for an element paired with itself, the
+// face with the lexicographically smaller centroid.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+
+#include "fr_host.h"
+
+namespace fr {
+
+std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind, const RefElem* refs[2],
+                           Mesh& M) {
+  M = Mesh();
+  M.nx = nx;
+  M.ny = ny;
+  M.nz = nz;
+  M.p = p;
+  M.kind = kind;
+  M.lo = lo;
+  M.hi = hi;
+  const double Lx = hi - lo;
+  const double h[3] = {Lx / nx, Lx / ny, Lx / nz};
+  int64_t g = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double x0[3] = {lo + i * h[0], lo + j * h[1], lo + k * h[2]};
+        double zc = x0[2] + 0.5 * h[2];
+        int t = kind == 2 ? (zc < 0.0 ? 0 : 1) : kind;
+        double c[3] = {x0[0] + 0.5 * h[0], x0[1] + 0.5 * h[1], x0[2] + 0.5 * h[2]};
+        if (t == 0) {
+          for (int d = 0; d < 3; ++d) M.org[0].push_back(c[d]);
+          double J[9] = {0.5 * h[0], 0, 0, 0, 0.5 * h[1], 0, 0, 0, 0.5 * h[2]};
+          M.jac[0].insert(M.jac[0].end(), J, J + 9);
+          M.gid[0].push_back(g++);
+        } else {
+          for (int s = 0; s < 2; ++s) {
+            double sg = s ? -1.0 : 1.0;
+            for (int d = 0; d < 3; ++d) M.org[1].push_back(c[d]);
+            double J[9] = {0, sg * 0.5 * h[0], 0, 0, 0, 0.5 * h[1], sg * 0.5 * h[2], 0, 0};
+            M.jac[1].insert(M.jac[1].end(), J, J + 9);
+            M.gid[1].push_back(g++);
+          }
+        }
+      }
+  for (int t = 0; t < 2; ++t) {
+    M.nel[t] = (int64_t)M.gid[t].size();
+    M.jinv[t].resize(9 * M.nel[t]);
+    M.detj[t].resize(M.nel[t]);
+    for (int64_t e = 0; e < M.nel[t]; ++e) {
+      const double* A = &M.jac[t][9 * e];
+      double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                 A[2] * (A[3] * A[7] - A[4] * A[6]);
+      if (!(d > 0)) return "non-positive Jacobian";
+      M.detj[t][e] = d;
+      double* B = &M.jinv[t][9 * e];
+      B[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+      B[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+      B[2] = (A[1] * A[5] - A[2] * A[4]) / d;
+      B[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+      B[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+      B[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+      B[6] = (A[3] * A[7] - A[4] * A[6]) / d;
+      B[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+      B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+    }
+  }
+  const int nfc[2] = {6, 5};
+  M.slot_base[0] = 0;
+  M.slot_base[1] = M.nel[0] * 6;
+  M.nslots = M.slot_base[1] + M.nel[1] * 5;
+  const int64_t S = M.nslots;
+
+  // physical face points and centroids
+  auto phys = [&](int t, int64_t e, const double* xi, double* x) {
+    const double* A = &M.jac[t][9 * e];
+    const double* o = &M.org[t][3 * e];
+    for (int d = 0; d < 3; ++d) x[d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
+  };
+  std::vector<double> cent(3 * S);
+  std::vector<std::array<int64_t, 4>> keys(S);  // quantised centroid mod period, slot
+  const double Q = double(1 << 24);
+  auto slot_info = [&](int64_t s, int& t, int64_t& e, int& f) {
+    t = s >= M.slot_base[1] && M.nel[1] > 0 ? 1 : 0;
+    int64_t r = s - M.slot_base[t];
+    e = r / nfc[t];
+    f = int(r % nfc[t]);
+  };
+  for (int64_t s = 0; s < S; ++s) {
+    int t, f;
+    int64_t e;
+    slot_info(s, t, e, f);
+    const RefElem& R = *refs[t];
+    double c[3] = {0, 0, 0};
+    for (int q = 0; q < R.face_npts[f]; ++q) {
+      double x[3];
+      phys(t, e, &R.fpts[3 * (R.face_start[f] + q)], x);
+      for (int d = 0; d < 3; ++d) c[d] += x[d] / R.face_npts[f];
+    }
+    std::array<int64_t, 4> k;
+    for (int d = 0; d < 3; ++d) {
+      cent[3 * s + d] = c[d];
+      int64_t v = (int64_t)std::llround((c[d] - lo) / Lx * Q);
+      v %= (int64_t)Q;
+      if (v < 0) v += (int64_t)Q;
+      k[d] = v;
+    }
+    k[3] = s;
+    keys[s] = k;
+  }
+  std::sort(keys.begin(), keys.end());
+  if (S % 2) return "odd number of faces";
+  M.nbr_slot.assign(S, -1);
+  M.perm_id.assign(S, 0);
+  M.is_left.assign(S, 0);
+  M.nrm.assign(3 * S, 0);
+  M.mag.assign(S, 0);
+  std::map<std::vector<int>, int> permidx;
+  std::map<int, int> last_perm;
+  for (int64_t i = 0; i < S; i += 2) {
+    const auto& a = keys[i];
+    const auto& b = keys[i + 1];
+    if (a[0] != b[0] || a[1] != b[1] || a[2] != b[2]) return "faces do not pair up (non-conforming mesh)";
+    if (i + 2 < S && keys[i + 2][0] == a[0] && keys[i + 2][1] == a[1] && keys[i + 2][2] == a[2])
+      return "more than two faces share a centroid";
+    int64_t sa = a[3], sb = b[3];
+    M.nbr_slot[sa] = sb;
+    M.nbr_slot[sb] = sa;
+  }
+  // per pair: L/R, point permutation, L-side normal and area factor
+  for (int64_t s = 0; s < S; ++s) {
+    int64_t o = M.nbr_slot[s];
+    int t, f, to, fo;
+    int64_t e, eo;
+    slot_info(s, t, e, f);
+    slot_info(o, to, eo, fo);
+    const RefElem& R = *refs[t];
+    const RefElem& RO = *refs[to];
+    int np = R.face_npts[f];
+    if (RO.face_npts[fo] != np) return "paired faces have different point counts";
+    bool left;
+    if (M.gid[t][e] != M.gid[to][eo]) {
+      left = M.gid[t][e] < M.gid[to][eo];
+    } else {
+      const double* ca = &cent[3 * s];
+      const double* cb = &cent[3 * o];
+      left = std::lexicographical_compare(ca, ca + 3, cb, cb + 3);
+    }
+    M.is_left[s] = left ? 1 : 0;
+    // try the permutation found last for this (type, face, type, face) class
+    // first; search by brute force only when it does not match
+    auto dist = [&](int q, int r) {
+      double x[3], y[3];
+      phys(t, e, &R.fpts[3 * (R.face_start[f] + q)], x);
+      phys(to, eo, &RO.fpts[3 * (RO.face_start[fo] + r)], y);
+      double d2 = 0;
+      for (int d = 0; d < 3; ++d) {
+        double dd = x[d] - y[d];
+        dd -= Lx * std::nearbyint(dd / Lx);
+        d2 += dd * dd;
+      }
+      return std::sqrt(d2);
+    };
+    const double tol = 1e-9 * std::min(h[0], std::min(h[1], h[2]));
+    int cls = ((t * 8 + f) * 2 + to) * 8 + fo;
+    std::vector<int> perm;
+    auto cit = last_perm.find(cls);
+    if (cit != last_perm.end()) {
+      perm = M.perms[cit->second];
+      for (int q = 0; q < np; ++q)
+        if (dist(q, perm[q]) > tol) {
+          perm.clear();
+          break;
+        }
+    }
+    if (perm.empty()) {
+      perm.assign(np, -1);
+      for (int q = 0; q < np; ++q) {
+        double best = 1e300;
+        int bi = -1;
+        for (int r = 0; r < np; ++r) {
+          double d = dist(q, r);
+          if (d < best) {
+            best = d;
+            bi = r;
+          }
+        }
+        if (best > tol) return "paired flux points do not coincide";
+        perm[q] = bi;
+      }
+    }
+    {
+      std::vector<int> chk(perm);
+      std::sort(chk.begin(), chk.end());
+      for (int q = 0; q < np; ++q)
+        if (chk[q] != q) return "flux-point matching is not one-to-one";
+    }
+    auto it = permidx.find(perm);
+    int pid;
+    if (it == permidx.end()) {
+      pid = (int)M.perms.size();
+      permidx[perm] = pid;
+      M.perms.push_back(perm);
+    } else {
+      pid = it->second;
+    }
+    M.perm_id[s] = pid;
+    last_perm[cls] = pid;
+  }
+  // normals: n = det J J^-T nhat / mag (Nanson), taken from the L side
+  for (int64_t s = 0; s < S; ++s) {
+    int64_t l = M.is_left[s] ? s : M.nbr_slot[s];
+    int t, f;
+    int64_t e;
+    slot_info(l, t, e, f);
+    const double* B = &M.jinv[t][9 * e];
+    const double* nh = &refs[t]->face_normal[3 * f];
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = M.detj[t][e] * (B[0 * 3 + c] * nh[0] + B[1 * 3 + c] * nh[1] + B[2 * 3 + c] * nh[2]);
+    double mg = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int c = 0; c < 3; ++c) M.nrm[3 * s + c] = v[c] / mg;
+    M.mag[s] = mg;
+  }
+  return "";
+}
+
+}  // namespace fr

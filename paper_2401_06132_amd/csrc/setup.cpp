@@ -1,0 +1,506 @@
+// Reference elements and their operators (host).
+//
+// Points: Gauss-Legendre roots by bracketing + Newton on the three-term
+// recurrence; Gauss-Jacobi(1,0) likewise with the closed-form weights.
+// Lines: Lagrange polynomials evaluated by their product formula.
+// Triangles: the Proriol-Koornwinder-Dubiner basis (Jacobi polynomials in
+// collapsed coordinates) for the nodal Vandermonde.
+// Operators follow section 2.2 (M0, M3, M7, M8, gradients) with the DG
+// correction functions; the factored forms follow section 4 (hex: three 1-D
+// sweeps) and section 4.1 (prism: triangle-plane block times line).
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+#include "fr_host.h"
+
+namespace fr {
+
+namespace {
+
+// P_n^{(a,b)}(x) and its derivative by the standard recurrence.
+void jacobi(int n, double a, double b, double x, double& pn, double& dpn) {
+  auto val = [&](int k, double aa, double bb) {
+    if (k == 0) return 1.0;
+    double p0 = 1.0, p1 = 0.5 * ((aa + bb + 2.0) * x + (aa - bb));
+    for (int j = 2; j <= k; ++j) {
+      double c = 2.0 * j + aa + bb;
+      double a1 = 2.0 * j * (j + aa + bb) * (c - 2.0);
+      double a2 = (c - 1.0) * (aa * aa - bb * bb);
+      double a3 = (c - 2.0) * (c - 1.0) * c;
+      double a4 = 2.0 * (j + aa - 1.0) * (j + bb - 1.0) * c;
+      double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+      p0 = p1;
+      p1 = p2;
+    }
+    return p1;
+  };
+  pn = val(n, a, b);
+  dpn = n == 0 ? 0.0 : 0.5 * (n + a + b + 1.0) * val(n - 1, a + 1.0, b + 1.0);
+}
+
+void roots(int n, double a, double b, std::vector<double>& x) {
+  x.clear();
+  const int ns = 4000;
+  double pa, d;
+  jacobi(n, a, b, -1.0, pa, d);
+  double xa = -1.0;
+  for (int s = 1; s <= ns; ++s) {
+    double xb = -1.0 + 2.0 * s / ns, pb;
+    jacobi(n, a, b, xb, pb, d);
+    if (pb == 0.0) {
+      x.push_back(xb);  // exact root on a sample point (e.g. x = 0 for odd n)
+    } else if (pa != 0.0 && (pa < 0) != (pb < 0)) {
+      double lo = xa, hi = xb, flo = pa;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), fm;
+        jacobi(n, a, b, mid, fm, d);
+        if ((fm < 0) == (flo < 0)) {
+          lo = mid;
+          flo = fm;
+        } else {
+          hi = mid;
+        }
+      }
+      double r = 0.5 * (lo + hi);
+      for (int it = 0; it < 3; ++it) {
+        double f, df;
+        jacobi(n, a, b, r, f, df);
+        if (df != 0) r -= f / df;
+      }
+      x.push_back(r);
+    }
+    xa = xb;
+    pa = pb;
+  }
+  if ((int)x.size() != n) throw std::runtime_error("root finding failed");
+}
+
+double lagrange(const std::vector<double>& x, int j, double y) {
+  double v = 1.0;
+  for (size_t k = 0; k < x.size(); ++k)
+    if ((int)k != j) v *= (y - x[k]) / (x[j] - x[k]);
+  return v;
+}
+
+double dlagrange(const std::vector<double>& x, int j, double y) {
+  double s = 0.0;
+  for (size_t mm = 0; mm < x.size(); ++mm) {
+    if ((int)mm == j) continue;
+    double t = 1.0 / (x[j] - x[mm]);
+    for (size_t k = 0; k < x.size(); ++k)
+      if ((int)k != j && k != mm) t *= (y - x[k]) / (x[j] - x[k]);
+    s += t;
+  }
+  return s;
+}
+
+// Dense inverse by Gauss-Jordan with partial pivoting (small matrices).
+std::vector<double> inverse(std::vector<double> A, int n) {
+  std::vector<double> B(n * n, 0.0);
+  for (int i = 0; i < n; ++i) B[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) throw std::runtime_error("singular matrix");
+    for (int k = 0; k < n; ++k) {
+      std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(B[c * n + k], B[piv * n + k]);
+    }
+    double d = 1.0 / A[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[c * n + k] *= d;
+      B[c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        A[r * n + k] -= f * A[c * n + k];
+        B[r * n + k] -= f * B[c * n + k];
+      }
+    }
+  }
+  return B;
+}
+
+// PKD basis on the triangle {xi,eta >= -1, xi+eta <= 0}: mode (i,j), i+j <= p,
+// psi = P_i(a) P_j^{(2i+1,0)}(b) (1-b)^i with a = 2(1+xi)/(1-eta) - 1, b = eta.
+// Points with eta = 1 (the top vertex) are never evaluated.
+void pkd(int p, double xi, double eta, double* v, double* dxi, double* deta) {
+  double b = eta, omb = 1.0 - b;
+  double a = 2.0 * (1.0 + xi) / omb - 1.0;
+  int k = 0;
+  for (int j0 = 0; j0 <= p; ++j0) {
+    for (int i = 0; i + j0 <= p; ++i) {
+      int j = j0;
+      double pa, dpa, pb, dpb;
+      jacobi(i, 0.0, 0.0, a, pa, dpa);
+      jacobi(j, 2.0 * i + 1.0, 0.0, b, pb, dpb);
+      double w = std::pow(omb, i), wm1 = i > 0 ? std::pow(omb, i - 1) : 0.0;
+      v[k] = pa * pb * w;
+      dxi[k] = i > 0 ? 2.0 * dpa * pb * wm1 : 0.0;
+      deta[k] = (i > 0 ? dpa * (1.0 + a) * pb * wm1 : 0.0) + pa * (dpb * w - (i > 0 ? i * pb * wm1 : 0.0));
+      ++k;
+    }
+  }
+}
+
+}  // namespace
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) { gauss_jacobi(n, 0.0, 0.0, x, w); }
+
+void gauss_jacobi(int n, double a, double b, std::vector<double>& x, std::vector<double>& w) {
+  roots(n, a, b, x);
+  w.resize(n);
+  double c = std::pow(2.0, a + b + 1.0) * std::exp(std::lgamma(n + a + 1.0) + std::lgamma(n + b + 1.0) -
+                                                    std::lgamma(n + a + b + 1.0) - std::lgamma(n + 1.0));
+  for (int i = 0; i < n; ++i) {
+    double f, df;
+    jacobi(n, a, b, x[i], f, df);
+    w[i] = c / ((1.0 - x[i] * x[i]) * df * df);
+  }
+}
+
+void triangle_nodes(int p, std::vector<double>& xy) {
+  // Blyth-Pozrikidis points from the Gauss-Legendre master grid
+  std::vector<double> g, gw;
+  gauss_legendre(p + 1, g, gw);
+  std::vector<double> v(p + 1);
+  for (int i = 0; i <= p; ++i) v[i] = 0.5 * (1.0 + g[i]);
+  xy.clear();
+  for (int j = 0; j <= p; ++j)
+    for (int i = 0; i + j <= p; ++i) {
+      int k = p - i - j;
+      double X = (1.0 + 2.0 * v[i] - v[j] - v[k]) / 3.0;
+      double Y = (1.0 + 2.0 * v[j] - v[i] - v[k]) / 3.0;
+      xy.push_back(2.0 * X - 1.0);
+      xy.push_back(2.0 * Y - 1.0);
+    }
+}
+
+static void build_line(int p, int m, Line1D& L) {
+  int n = p + 1;
+  L.n = n;
+  L.m = m;
+  gauss_legendre(n, L.x, L.w);
+  gauss_legendre(m, L.xq, L.wq);
+  L.D.assign(n * n, 0);
+  L.I.assign(m * n, 0);
+  L.Dq.assign(m * n, 0);
+  L.P.assign(n * m, 0);
+  L.AP.assign(n * m, 0);
+  L.lb.resize(n);
+  L.rb.resize(n);
+  L.liftL.resize(n);
+  L.liftR.resize(n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) L.D[i * n + j] = dlagrange(L.x, j, L.x[i]);
+  for (int a = 0; a < m; ++a)
+    for (int i = 0; i < n; ++i) {
+      L.I[a * n + i] = lagrange(L.x, i, L.xq[a]);
+      L.Dq[a * n + i] = dlagrange(L.x, i, L.xq[a]);
+    }
+  for (int i = 0; i < n; ++i) {
+    for (int a = 0; a < m; ++a) {
+      L.P[i * m + a] = L.I[a * n + i] * L.wq[a] / L.w[i];
+      L.AP[i * m + a] = -L.Dq[a * n + i] * L.wq[a] / L.w[i];
+    }
+    L.lb[i] = lagrange(L.x, i, -1.0);
+    L.rb[i] = lagrange(L.x, i, 1.0);
+    L.liftL[i] = L.lb[i] / L.w[i];
+    L.liftR[i] = L.rb[i] / L.w[i];
+  }
+}
+
+static void build_tri(int p, const Line1D& L, Tri& T) {
+  T.p = p;
+  triangle_nodes(p, T.nodes);
+  int nt = (p + 1) * (p + 2) / 2, n = p + 1;
+  T.nt = nt;
+  // conical rule with (p+1)^2 points: GL in a, Gauss-Jacobi(1,0) in b
+  std::vector<double> ga, gwa, gb, gwb;
+  gauss_legendre(p + 1, ga, gwa);
+  gauss_jacobi(p + 1, 1.0, 0.0, gb, gwb);
+  T.ntq = (p + 1) * (p + 1);
+  for (int j = 0; j <= p; ++j)
+    for (int i = 0; i <= p; ++i) {
+      T.qp.push_back(0.5 * (1.0 + ga[i]) * (1.0 - gb[j]) - 1.0);
+      T.qp.push_back(gb[j]);
+      T.qw.push_back(0.5 * gwa[i] * gwb[j]);
+    }
+  int ntq = T.ntq;
+  std::vector<double> V(nt * nt), v(nt), dx(nt), dy(nt);
+  for (int t = 0; t < nt; ++t) {
+    pkd(p, T.nodes[2 * t], T.nodes[2 * t + 1], v.data(), dx.data(), dy.data());
+    for (int k = 0; k < nt; ++k) V[t * nt + k] = v[k];
+  }
+  std::vector<double> Vi = inverse(V, nt);
+  // nodal basis at a point: l_t(y) = sum_k psi_k(y) Vi[k][t]
+  auto nodal = [&](double xi, double eta, double* l, double* lx, double* ly) {
+    pkd(p, xi, eta, v.data(), dx.data(), dy.data());
+    for (int t = 0; t < nt; ++t) {
+      double s = 0, sx = 0, sy = 0;
+      for (int k = 0; k < nt; ++k) {
+        s += v[k] * Vi[k * nt + t];
+        sx += dx[k] * Vi[k * nt + t];
+        sy += dy[k] * Vi[k * nt + t];
+      }
+      l[t] = s;
+      if (lx) lx[t] = sx;
+      if (ly) ly[t] = sy;
+    }
+  };
+  T.Tq.assign(ntq * nt, 0);
+  T.DxiQ.assign(ntq * nt, 0);
+  T.DetaQ.assign(ntq * nt, 0);
+  for (int q = 0; q < ntq; ++q)
+    nodal(T.qp[2 * q], T.qp[2 * q + 1], &T.Tq[q * nt], &T.DxiQ[q * nt], &T.DetaQ[q * nt]);
+  T.Dxi.assign(nt * nt, 0);
+  T.Deta.assign(nt * nt, 0);
+  std::vector<double> tmp(nt);
+  for (int t = 0; t < nt; ++t) nodal(T.nodes[2 * t], T.nodes[2 * t + 1], tmp.data(), &T.Dxi[t * nt], &T.Deta[t * nt]);
+  T.mass.assign(nt * nt, 0);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      double s = 0;
+      for (int q = 0; q < ntq; ++q) s += T.Tq[q * nt + a] * T.qw[q] * T.Tq[q * nt + b];
+      T.mass[a * nt + b] = s;
+    }
+  T.massInv = inverse(T.mass, nt);
+  T.PT.assign(nt * ntq, 0);
+  T.APxi.assign(nt * ntq, 0);
+  T.APeta.assign(nt * ntq, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int q = 0; q < ntq; ++q) {
+      double s = 0, sx = 0, sy = 0;
+      for (int k = 0; k < nt; ++k) {
+        s += T.massInv[t * nt + k] * T.Tq[q * nt + k];
+        sx += T.massInv[t * nt + k] * T.DxiQ[q * nt + k];
+        sy += T.massInv[t * nt + k] * T.DetaQ[q * nt + k];
+      }
+      T.PT[t * ntq + q] = s * T.qw[q];
+      T.APxi[t * ntq + q] = -sx * T.qw[q];
+      T.APeta[t * ntq + q] = -sy * T.qw[q];
+    }
+  // edges (counter-clockwise): e0 eta=-1 (xi=s); e1 hypotenuse (-s, s); e2 xi=-1 (-1, -s)
+  T.edgeJac[0] = 1.0;
+  T.edgeJac[1] = std::sqrt(2.0);
+  T.edgeJac[2] = 1.0;
+  T.edgeNormal[0][0] = 0.0;
+  T.edgeNormal[0][1] = -1.0;
+  T.edgeNormal[1][0] = 1.0 / std::sqrt(2.0);
+  T.edgeNormal[1][1] = 1.0 / std::sqrt(2.0);
+  T.edgeNormal[2][0] = -1.0;
+  T.edgeNormal[2][1] = 0.0;
+  T.Tedge.assign(3 * n * nt, 0);
+  T.LiftEdge.assign(3 * nt * n, 0);
+  for (int e = 0; e < 3; ++e)
+    for (int i = 0; i < n; ++i) {
+      double s = L.x[i];
+      double xi = e == 0 ? s : (e == 1 ? -s : -1.0);
+      double eta = e == 0 ? -1.0 : (e == 1 ? s : -s);
+      nodal(xi, eta, &T.Tedge[(e * n + i) * nt], nullptr, nullptr);
+    }
+  for (int e = 0; e < 3; ++e)
+    for (int t = 0; t < nt; ++t)
+      for (int i = 0; i < n; ++i) {
+        double s = 0;
+        for (int k = 0; k < nt; ++k) s += T.massInv[t * nt + k] * T.Tedge[(e * n + i) * nt + k];
+        T.LiftEdge[(e * nt + t) * n + i] = s * L.w[i] * T.edgeJac[e];
+      }
+}
+
+void build_ref(int etype, int p, RefElem& r) {
+  int n = p + 1, m = p + 3;
+  r.etype = etype;
+  r.p = p;
+  r.n = n;
+  r.m = m;
+  build_line(p, m, r.line);
+  const Line1D& L = r.line;
+  auto push3 = [](std::vector<double>& v, double a, double b, double c) {
+    v.push_back(a);
+    v.push_back(b);
+    v.push_back(c);
+  };
+  r.upts.clear();
+  r.fpts.clear();
+  r.qpts.clear();
+  r.qwts.clear();
+  r.face_start.clear();
+  r.face_npts.clear();
+  r.face_normal.clear();
+  if (etype == 0) {
+    r.nu = n * n * n;
+    r.nfaces = 6;
+    r.nfp_max = n * n;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) push3(r.upts, L.x[i], L.x[j], L.x[k]);
+    for (int ax = 0; ax < 3; ++ax)
+      for (int sg = 0; sg < 2; ++sg) {
+        double s = sg ? 1.0 : -1.0;
+        r.face_start.push_back((int)r.fpts.size() / 3);
+        r.face_npts.push_back(n * n);
+        double nr[3] = {0, 0, 0};
+        nr[ax] = s;
+        push3(r.face_normal, nr[0], nr[1], nr[2]);
+        int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            double c[3];
+            c[ax] = s;
+            c[t0] = L.x[a];
+            c[t1] = L.x[b];
+            push3(r.fpts, c[0], c[1], c[2]);
+          }
+      }
+    for (int k = 0; k < m; ++k)
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          push3(r.qpts, L.xq[i], L.xq[j], L.xq[k]);
+          r.qwts.push_back(L.wq[i] * L.wq[j] * L.wq[k]);
+        }
+  } else {
+    build_tri(p, L, r.tri);
+    const Tri& T = r.tri;
+    int nt = T.nt;
+    r.nu = nt * n;
+    r.nfaces = 5;
+    r.nfp_max = n * n;
+    for (int k = 0; k < n; ++k)
+      for (int t = 0; t < nt; ++t) push3(r.upts, T.nodes[2 * t], T.nodes[2 * t + 1], L.x[k]);
+    for (int sg = 0; sg < 2; ++sg) {
+      r.face_start.push_back((int)r.fpts.size() / 3);
+      r.face_npts.push_back(nt);
+      push3(r.face_normal, 0, 0, sg ? 1.0 : -1.0);
+      for (int t = 0; t < nt; ++t) push3(r.fpts, T.nodes[2 * t], T.nodes[2 * t + 1], sg ? 1.0 : -1.0);
+    }
+    for (int e = 0; e < 3; ++e) {
+      r.face_start.push_back((int)r.fpts.size() / 3);
+      r.face_npts.push_back(n * n);
+      push3(r.face_normal, T.edgeNormal[e][0], T.edgeNormal[e][1], 0.0);
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          double s = L.x[a];
+          double xi = e == 0 ? s : (e == 1 ? -s : -1.0);
+          double eta = e == 0 ? -1.0 : (e == 1 ? s : -s);
+          push3(r.fpts, xi, eta, L.x[b]);
+        }
+    }
+    for (int k = 0; k < m; ++k)
+      for (int q = 0; q < T.ntq; ++q) {
+        push3(r.qpts, T.qp[2 * q], T.qp[2 * q + 1], L.xq[k]);
+        r.qwts.push_back(T.qw[q] * L.wq[k]);
+      }
+  }
+  r.nf = (int)r.fpts.size() / 3;
+  r.nq = (int)r.qwts.size();
+  int nu = r.nu, nf = r.nf, nq = r.nq;
+
+  // dense operators from the factors
+  r.M0.assign(nf * nu, 0);
+  r.M3.assign(nu * nf, 0);
+  r.M7.assign(nq * nu, 0);
+  r.M8.assign(nu * nq, 0);
+  r.Dg.assign(3 * nu * nu, 0);
+  r.wu.assign(nu, 0);
+  if (etype == 0) {
+    auto uidx = [n](int i, int j, int k) { return i + n * (j + n * k); };
+    for (int ax = 0; ax < 3; ++ax)
+      for (int sg = 0; sg < 2; ++sg) {
+        int f = 2 * ax + sg;
+        const std::vector<double>& bv = sg ? L.rb : L.lb;
+        const std::vector<double>& lv = sg ? L.liftR : L.liftL;
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            int fp = r.face_start[f] + a + n * b;
+            for (int i = 0; i < n; ++i) {
+              int c[3];
+              c[ax] = i;
+              c[ax == 0 ? 1 : 0] = a;
+              c[ax == 2 ? 1 : 2] = b;
+              int u = uidx(c[0], c[1], c[2]);
+              r.M0[fp * nu + u] = bv[i];
+              r.M3[u * nf + fp] = lv[i];
+            }
+          }
+      }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int s = uidx(i, j, k);
+          r.wu[s] = L.w[i] * L.w[j] * L.w[k];
+          for (int a = 0; a < n; ++a) {
+            r.Dg[(0 * nu + s) * nu + uidx(a, j, k)] = L.D[i * n + a];
+            r.Dg[(1 * nu + s) * nu + uidx(i, a, k)] = L.D[j * n + a];
+            r.Dg[(2 * nu + s) * nu + uidx(i, j, a)] = L.D[k * n + a];
+          }
+        }
+    for (int c = 0; c < m; ++c)
+      for (int b = 0; b < m; ++b)
+        for (int a = 0; a < m; ++a) {
+          int q = a + m * (b + m * c);
+          for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+              for (int i = 0; i < n; ++i) {
+                int u = uidx(i, j, k);
+                r.M7[q * nu + u] = L.I[a * n + i] * L.I[b * n + j] * L.I[c * n + k];
+                r.M8[u * nq + q] = L.P[i * m + a] * L.P[j * m + b] * L.P[k * m + c];
+              }
+        }
+  } else {
+    const Tri& T = r.tri;
+    int nt = T.nt, ntq = T.ntq;
+    for (int sg = 0; sg < 2; ++sg) {
+      const std::vector<double>& bv = sg ? L.rb : L.lb;
+      const std::vector<double>& lv = sg ? L.liftR : L.liftL;
+      for (int t = 0; t < nt; ++t) {
+        int fp = r.face_start[sg] + t;
+        for (int k = 0; k < n; ++k) {
+          r.M0[fp * nu + t + nt * k] = bv[k];
+          r.M3[(t + nt * k) * nf + fp] = lv[k];
+        }
+      }
+    }
+    for (int e = 0; e < 3; ++e)
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          int fp = r.face_start[2 + e] + a + n * b;
+          for (int t = 0; t < nt; ++t) {
+            r.M0[fp * nu + t + nt * b] = T.Tedge[(e * n + a) * nt + t];
+            r.M3[(t + nt * b) * nf + fp] = T.LiftEdge[(e * nt + t) * n + a];
+          }
+        }
+    for (int k = 0; k < n; ++k)
+      for (int t = 0; t < nt; ++t) {
+        int s = t + nt * k;
+        for (int t2 = 0; t2 < nt; ++t2) {
+          r.Dg[(0 * nu + s) * nu + t2 + nt * k] = T.Dxi[t * nt + t2];
+          r.Dg[(1 * nu + s) * nu + t2 + nt * k] = T.Deta[t * nt + t2];
+        }
+        for (int a = 0; a < n; ++a) r.Dg[(2 * nu + s) * nu + t + nt * a] = L.D[k * n + a];
+      }
+    for (int c = 0; c < m; ++c)
+      for (int q = 0; q < ntq; ++q) {
+        int qq = q + ntq * c;
+        for (int k = 0; k < n; ++k)
+          for (int t = 0; t < nt; ++t) {
+            int u = t + nt * k;
+            r.M7[qq * nu + u] = T.Tq[q * nt + t] * L.I[c * n + k];
+            r.M8[u * nq + qq] = T.PT[t * ntq + q] * L.P[k * m + c];
+          }
+      }
+    for (int k = 0; k < n; ++k)
+      for (int t = 0; t < nt; ++t) {
+        double s = 0;
+        for (int q = 0; q < ntq; ++q) s += T.Tq[q * nt + t] * T.qw[q];
+        r.wu[t + nt * k] = s * L.w[k];
+      }
+  }
+}
+
+}  // namespace fr

@@ -69,9 +69,9 @@ def rhs_bytes_model(p, bytes_real):
     return b
 
 
-def time_variant(frmi, torch, n, p, prec, steps, warmup):
+def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused"):
     from paper_2401_06132_amd import inputs
-    s = frmi.Solver(n, p, "hex", prec=prec, pref=inputs.P0)
+    s = frmi.Solver(n, p, "hex", prec=prec, pref=inputs.P0, form=form)
     coords = s.upts_coords()
     U = inputs.element_state(coords, seed=0)
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
@@ -90,16 +90,18 @@ def time_variant(frmi, torch, n, p, prec, steps, warmup):
     wall = time.perf_counter() - t0
     per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
     # dominant kernel (volume group) alone, same launch configuration
-    for _ in range(max(1, warmup // 2)):
-        s.rhs_stages(u, du, 2)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
-        s.rhs_stages(u, du, 2)
-    e1.record()
-    torch.cuda.synchronize()
-    vol_ms = e0.elapsed_time(e1) / steps
+    vol_ms = float("nan")
+    if form == "fused":
+        for _ in range(max(1, warmup // 2)):
+            s.rhs_stages(u, du, 2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            s.rhs_stages(u, du, 2)
+        e1.record()
+        torch.cuda.synchronize()
+        vol_ms = e0.elapsed_time(e1) / steps
     ok = bool(torch.isfinite(du).all().item())
     res = dict(n_dof=s.n_state, n_elem=s.n_hex, wall_s=wall, ms_per_step=wall * 1e3 / steps,
                p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), vol_ms=vol_ms,
@@ -155,9 +157,11 @@ def main():
     import paper_2401_06132_amd as frmi
     torch.cuda.set_device(0)
     variants = {}
-    order = [("fp32", 3)] if args.quick else [("fp32", 3), ("fp64", 3), ("fp32", 4), ("fp64", 4)]
-    for prec, p in order:
-        r = time_variant(frmi, torch, args.n, p, prec, args.steps, args.warmup)
+    order = [("fp32", 3, "fused")] if args.quick else [
+        ("fp32", 3, "fused"), ("fp64", 3, "fused"), ("fp64", 3, "plain"),
+        ("fp32", 4, "fused"), ("fp64", 4, "fused"), ("fp64", 4, "plain")]
+    for prec, p, form in order:
+        r = time_variant(frmi, torch, args.n, p, prec, args.steps, args.warmup, form)
         br = 4 if prec == "fp32" else 8
         vb, vf = volume_model(p, br)
         E = r["n_elem"]
@@ -165,10 +169,14 @@ def main():
         r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
         r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
         r["rhs_GBs"] = rhs_bytes_model(p, br) * E * args.steps / r["wall_s"] / 1e9
-        variants["%s_p%d" % (prec, p)] = r
-        print("variant", prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
+        variants["%s%s_p%d" % ("plain_" if form == "plain" else "", prec, p)] = r
+        print("variant", form, prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
               file=sys.stderr, flush=True)
     head = variants["fp32_p3"]
+    for p in (3, 4):
+        if "plain_fp64_p%d" % p in variants and "fp32_p%d" % p in variants:
+            variants["fp32_p%d" % p]["speedup_vs_plain_fp64"] = (variants["fp32_p%d" % p]["gdof_s"] /
+                                                                   variants["plain_fp64_p%d" % p]["gdof_s"])
     vb, vf = volume_model(3, 4)
     ai = vf / vb
     ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -181,6 +189,8 @@ def main():
     roof.update({"kernel": "hex_volume<3,float>", "traffic": None, "hbm_GBs": round(head["vol_GBs"], 1),
                  "hbm_frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4), "flop_per_byte": round(ai, 2),
                  "avg_ms": round(head["vol_ms"], 4)})
+    def _r(x):
+        return round(x, 4) if isinstance(x, float) and np.isfinite(x) else (x if not isinstance(x, float) else None)
     out = {
         "metric": METRIC, "value": round(head["gdof_s"], 3), "unit": "GDoF-RHS/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4),
@@ -191,9 +201,10 @@ def main():
         "p50_step_ms": round(head["p50_ms"], 4), "p99_step_ms": round(head["p99_ms"], 4),
         "hbm_frac_rhs": round(head["rhs_GBs"] / HBM_PEAK_GBS, 4),
         "roofline": roof,
-        "variants": {k: {"gdof_s": round(v["gdof_s"], 3), "p99_step_ms": round(v["p99_ms"], 4),
-                         "vol_ms": round(v["vol_ms"], 4), "hbm_frac_rhs": round(v["rhs_GBs"] / HBM_PEAK_GBS, 4),
-                         "finite": v["finite"]} for k, v in variants.items()},
+        "variants": {k: {"gdof_s": _r(v["gdof_s"]), "p99_step_ms": _r(v["p99_ms"]), "vol_ms": _r(v["vol_ms"]),
+                         "hbm_frac_rhs": _r(v["rhs_GBs"] / HBM_PEAK_GBS), "finite": v["finite"],
+                         "speedup_vs_plain_fp64": _r(v.get("speedup_vs_plain_fp64", float("nan")))}
+                     for k, v in variants.items()},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

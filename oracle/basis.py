@@ -13,12 +13,41 @@ basis-independent mass-matrix form in elements.py.
 import numpy as np
 from numpy.polynomial import legendre as npleg
 
+# Operators are built in extended precision and rounded once by the caller:
+# a Vandermonde inverse at p = 4 loses ~1e-14 (prism: ~3e-13) in float64,
+# which would otherwise dominate the oracle's own rounding.
+EXT = np.longdouble
+
+
+def inv(A):
+    """Inverse of a small dense matrix by Gauss-Jordan elimination with
+    partial pivoting, in the matrix's own precision (numpy.linalg has no
+    extended-precision path)."""
+    A = np.array(A, dtype=EXT, copy=True)
+    n = A.shape[0]
+    B = np.eye(n, dtype=EXT)
+    for c in range(n):
+        piv = c + int(np.argmax(np.abs(A[c:, c])))
+        if A[piv, c] == 0:
+            raise np.linalg.LinAlgError("singular matrix")
+        A[[c, piv]] = A[[piv, c]]
+        B[[c, piv]] = B[[piv, c]]
+        d = A[c, c]
+        A[c] /= d
+        B[c] /= d
+        f = A[:, c].copy()
+        f[c] = 0
+        A -= np.outer(f, A[c])
+        B -= np.outer(f, B[c])
+    return B
+
 
 def legendre_values(kmax, x):
-    """P_0..P_kmax at x and their first derivatives: arrays (kmax+1, len(x))."""
-    x = np.asarray(x, dtype=np.float64)
-    vals = np.empty((kmax + 1, x.size))
-    ders = np.empty((kmax + 1, x.size))
+    """P_0..P_kmax at x and their first derivatives: arrays (kmax+1, len(x)),
+    in extended precision."""
+    x = np.asarray(x, dtype=EXT)
+    vals = np.empty((kmax + 1, x.size), dtype=EXT)
+    ders = np.empty((kmax + 1, x.size), dtype=EXT)
     for k in range(kmax + 1):
         c = np.zeros(k + 1)
         c[k] = 1.0
@@ -37,13 +66,13 @@ def modes(etype, p):
 
 def eval_basis(etype, p, pts):
     """Basis values V[pt, mode] and gradients G[d, pt, mode] at pts (N, 3)."""
-    pts = np.asarray(pts, dtype=np.float64)
+    pts = np.asarray(pts, dtype=EXT)
     vx, dx = legendre_values(p, pts[:, 0])
     vy, dy = legendre_values(p, pts[:, 1])
     vz, dz = legendre_values(p, pts[:, 2])
     md = modes(etype, p)
-    V = np.empty((len(pts), len(md)))
-    G = np.empty((3, len(pts), len(md)))
+    V = np.empty((len(pts), len(md)), dtype=EXT)
+    G = np.empty((3, len(pts), len(md)), dtype=EXT)
     for k, (a, b, c) in enumerate(md):
         V[:, k] = vx[a] * vy[b] * vz[c]
         G[0, :, k] = dx[a] * vy[b] * vz[c]
@@ -57,7 +86,7 @@ def nodal(etype, p, nodes, pts):
     L[pt, zeta] and gradients DL[d, pt, zeta]."""
     Vn, _ = eval_basis(etype, p, nodes)
     V, G = eval_basis(etype, p, pts)
-    Vinv = np.linalg.inv(Vn)
+    Vinv = inv(Vn)
     return V @ Vinv, np.einsum("dpm,mz->dpz", G, Vinv)
 
 
@@ -70,7 +99,7 @@ def tri_nodal(p, nodes2, pts2):
         vy, _ = legendre_values(p, q[:, 1])
         return np.stack([vx[a] * vy[b] for a, b in md], axis=1)
 
-    return ev(np.asarray(pts2)) @ np.linalg.inv(ev(np.asarray(nodes2)))
+    return ev(np.asarray(pts2)) @ inv(ev(np.asarray(nodes2)))
 
 
 def line_nodal(nodes1, pts1):
@@ -78,4 +107,4 @@ def line_nodal(nodes1, pts1):
     n = len(nodes1)
     vn, _ = legendre_values(n - 1, nodes1)
     v, _ = legendre_values(n - 1, pts1)
-    return v.T @ np.linalg.inv(vn.T)
+    return v.T @ inv(vn.T)

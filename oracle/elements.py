@@ -12,6 +12,8 @@ Reference elements
         2,3,4 = the quadrilaterals eta = -1, xi + eta = 0, xi = -1 with GL(n)
         points along the edge (parameter s, edges run counter-clockwise) times
         GL(n) in zeta, index a + n b.
+All operators are computed in extended precision (numpy longdouble) and kept
+there; callers cast them to their working precision (rounding once).
 Anti-aliasing quadrature (section 2.1.1): hex GL(m)^3; prism conical triangle
 rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default.
 
@@ -143,11 +145,12 @@ class RefElement:
         W = np.diag(self.qwts)
         mass = Lq.T @ W @ Lq
         self.mass = mass
-        self.M8 = np.linalg.solve(mass, Lq.T @ W)
+        massinv = basis.inv(mass)
+        self.M8 = massinv @ (Lq.T @ W)
         self.wu = Lq.T @ self.qwts
 
         # DG lifting: E[u, f] = int_face(f) l_u l^face_f dS_ref
-        E = np.zeros((self.nu, self.nf))
+        E = np.zeros((self.nu, self.nf), dtype=basis.EXT)
         gl = self.gl
         for fidx, fc in enumerate(self.faces):
             cols = np.nonzero(self.fface == fidx)[0]
@@ -167,5 +170,5 @@ class RefElement:
                 lface = basis.tri_nodal(p, self.tri_nodes, tq)
             Lv, _ = basis.nodal(et, p, up, xs)
             E[:, cols] = Lv.T @ (w[:, None] * lface)
-        self.M3 = np.linalg.solve(mass, E)
+        self.M3 = massinv @ E
         self.M6 = self.fnorm.T[:, None, :] * self.M3[None, :, :]

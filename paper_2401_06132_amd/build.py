@@ -48,7 +48,8 @@ def build(verbose=False, jobs=None):
             if err.strip():
                 print(err, file=sys.stderr)
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in res]
+    cmd = [HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in res] + \
+        ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))

@@ -2,6 +2,7 @@
 // right-hand-side / RK4 drivers.  See include/fr.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -11,6 +12,7 @@
 #include "../../include/fr.h"
 #include "fr_host.h"
 #include "fr_kernels.h"
+#include "fr_plain.h"
 
 struct fr_ctx {
   fr_physics ph;
@@ -33,6 +35,7 @@ struct fr_ctx {
   void* d_met[2] = {nullptr, nullptr};
   double* d_detj[2] = {nullptr, nullptr};
   void* d_pops = nullptr;
+  fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
 
 namespace {
@@ -64,9 +67,113 @@ void to_real(const fr_ctx* c, const std::vector<double>& v, std::vector<unsigned
     put<float>(buf, v, v.size());
 }
 
+fr_status setup_plain(fr_ctx* c) {
+  const fr::Mesh& M = c->M;
+  fr::PlainCtx* P = new (std::nothrow) fr::PlainCtx();
+  if (!P) return fail(c, FR_ENOMEM, "host allocation");
+  c->plain = P;
+  if (!fr::plain_create_handle(&P->blas)) return fail(c, FR_EDEVICE, "rocblas_create_handle failed");
+  P->beta = c->ph.ldg_beta;
+  P->eref = c->ph.pref / (c->ph.gamma - 1.0);
+  P->gas.gamma = c->ph.gamma;
+  P->gas.gm1 = c->ph.gamma - 1.0;
+  P->gas.mu = c->ph.mu;
+  P->gas.muh = c->ph.mu * c->ph.gamma / c->ph.prandtl;
+  P->gas.pref = c->ph.pref;
+  P->gas.eref = P->eref;
+  P->gas.href = c->ph.gamma * c->ph.pref / (c->ph.gamma - 1.0);
+  P->gas.beta = c->ph.ldg_beta;
+  P->gas.tau = c->ph.ldg_tau;
+  int64_t nftot = 0, nqmax = 0;
+  for (int t = 0; t < 2; ++t) {
+    P->ty.E[t] = M.nel[t];
+    P->ty.nf[t] = c->ref[t].nf;
+    P->ty.off_f[t] = 5 * nftot;
+    nftot += M.nel[t] * c->ref[t].nf;
+    P->state_off[t] = c->off[t];
+    if (!c->has[t]) continue;
+    fr::build_plain_ops(c->ref[t], P->ops[t]);
+    const fr::PlainOps& o = P->ops[t];
+    nqmax = std::max<int64_t>(nqmax, M.nel[t] * o.nq);
+    struct {
+      double** d;
+      const std::vector<double>* h;
+    } up[] = {{&P->dM0[t], &o.M0}, {&P->dG1[t], &o.G1}, {&P->dM6[t], &o.M6},
+              {&P->dM7[t], &o.M7}, {&P->dK[t], &o.K},   {&P->dM3[t], &o.M3}};
+    for (auto& x : up) {
+      HIPCHK(hipMalloc(x.d, sizeof(double) * x.h->size()));
+      HIPCHK(hipMemcpy(*x.d, x.h->data(), sizeof(double) * x.h->size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMalloc(&P->jinv[t], sizeof(double) * 9 * M.nel[t]));
+    HIPCHK(hipMemcpy(P->jinv[t], M.jinv[t].data(), sizeof(double) * 9 * M.nel[t], hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&P->detj[t], sizeof(double) * M.nel[t]));
+    HIPCHK(hipMemcpy(P->detj[t], M.detj[t].data(), sizeof(double) * M.nel[t], hipMemcpyHostToDevice));
+  }
+  // per flux point neighbour records and L-side normals (the paper's n^(f))
+  std::vector<fr::PlainFace> pf(nftot);
+  std::vector<double> geo(4 * nftot);
+  const int nfc[2] = {6, 5};
+  int64_t base[2] = {0, M.nel[0] * c->ref[0].nf};
+  for (int64_t s = 0; s < M.nslots; ++s) {
+    int t = (M.nel[1] > 0 && s >= M.slot_base[1]) ? 1 : 0;
+    int64_t e = (s - M.slot_base[t]) / nfc[t];
+    int f = int((s - M.slot_base[t]) % nfc[t]);
+    int64_t o = M.nbr_slot[s];
+    int to = (M.nel[1] > 0 && o >= M.slot_base[1]) ? 1 : 0;
+    int64_t eo = (o - M.slot_base[to]) / nfc[to];
+    int fo = int((o - M.slot_base[to]) % nfc[to]);
+    const std::vector<int>& pm = M.perms[M.perm_id[s]];
+    for (int q = 0; q < c->ref[t].face_npts[f]; ++q) {
+      int64_t i = base[t] + e * c->ref[t].nf + c->ref[t].face_start[f] + q;
+      pf[i].nbr_elem = (int32_t)eo;
+      pf[i].nbr_fpt = (int16_t)(c->ref[to].face_start[fo] + pm[q]);
+      pf[i].nbr_type = (int8_t)to;
+      pf[i].is_left = (int8_t)M.is_left[s];
+      for (int d = 0; d < 3; ++d) geo[4 * i + d] = M.nrm[3 * s + d];
+      geo[4 * i + 3] = M.mag[s];
+    }
+  }
+  HIPCHK(hipMalloc(&P->faces, sizeof(fr::PlainFace) * nftot));
+  HIPCHK(hipMemcpy(P->faces, pf.data(), sizeof(fr::PlainFace) * nftot, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&P->fgeo, sizeof(double) * 4 * nftot));
+  HIPCHK(hipMemcpy(P->fgeo, geo.data(), sizeof(double) * 4 * nftot, hipMemcpyHostToDevice));
+  const size_t d8 = sizeof(double);
+  HIPCHK(hipMalloc(&P->W, d8 * c->n_state));
+  HIPCHK(hipMalloc(&P->Q, d8 * 3 * c->n_state));
+  HIPCHK(hipMalloc(&P->Uf, d8 * 5 * nftot));
+  HIPCHK(hipMalloc(&P->Cf, d8 * 5 * nftot));
+  HIPCHK(hipMalloc(&P->Df, d8 * 5 * nftot));
+  HIPCHK(hipMalloc(&P->Qf, d8 * 15 * nftot));
+  HIPCHK(hipMalloc(&P->Uq, d8 * 5 * nqmax));
+  HIPCHK(hipMalloc(&P->Qq, d8 * 15 * nqmax));
+  return FR_OK;
+}
+
+void free_plain(fr_ctx* c) {
+  fr::PlainCtx* P = c->plain;
+  if (!P) return;
+  void* bufs[] = {P->W, P->Uf, P->Cf, P->Q, P->Qf, P->Uq, P->Qq, P->Df, P->fgeo, P->faces,
+                  P->dM0[0], P->dG1[0], P->dM6[0], P->dM7[0], P->dK[0], P->dM3[0], P->jinv[0], P->detj[0],
+                  P->dM0[1], P->dG1[1], P->dM6[1], P->dM7[1], P->dK[1], P->dM3[1], P->jinv[1], P->detj[1]};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  fr::plain_destroy_handle(P->blas);
+  delete P;
+  c->plain = nullptr;
+}
+
 fr_status ensure_device(fr_ctx* c) {
   if (c->dev_ok) return FR_OK;
   if (!c->mesh_ok) return fail(c, FR_ESTATE, "no mesh");
+  if (c->ph.form == FR_FORM_PLAIN) {
+    HIPCHK(hipMalloc(&c->d_state, sizeof(double) * c->n_state));
+    HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(double) * c->n_state, c->st));
+    HIPCHK(hipMalloc(&c->d_rk, sizeof(double) * c->n_state * 3));
+    fr_status s = setup_plain(c);
+    if (s != FR_OK) return s;
+    c->dev_ok = true;
+    return FR_OK;
+  }
   const fr::Mesh& M = c->M;
   const int n = c->p + 1, nfp = n * n;
   const size_t rs = rsize(c);
@@ -146,7 +253,11 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const double* u, double* du, int stage)
 }
 
 fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7) {
-  if (c->ph.form != FR_FORM_FUSED) return fail(c, FR_EUNSUPPORTED, "plain form not built");
+  if (c->ph.form == FR_FORM_PLAIN) {
+    hipError_t e = fr::plain_rhs(*c->plain, u, du, c->st);
+    if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("plain path: ") + hipGetErrorString(e));
+    return FR_OK;
+  }
   for (int stage = 1; stage <= 4; stage <<= 1)
     if (mask & stage)
     for (int t = 0; t < 2; ++t) {
@@ -181,6 +292,7 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
       !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
       ph->form > 1)
     return FR_EINVAL;
+  if (ph->form == FR_FORM_PLAIN && ph->prec != FR_PREC_FP64) return FR_EUNSUPPORTED;
   fr_ctx* c = new (std::nothrow) fr_ctx();
   if (!c) return FR_ENOMEM;
   c->ph = *ph;
@@ -417,6 +529,7 @@ void fr_destroy(fr_ctx* c) {
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }
+  free_plain(c);
   delete c;
 }
 

@@ -1,10 +1,635 @@
-// Fused flux-reconstruction kernels for prisms (gfx950) -- see below.
+// Fused flux-reconstruction kernels for prisms (gfx950).
+//
+// Same kernel groups as the hexahedral kernels (section 6.1): disu | volume
+// group | interface group.  The prism operators factor into a dense
+// triangle-plane block times a sparse line operator (section 4.1, figure
+// priplanarint):  M7 = I_line (x) T_q,  and the projection-divergence
+//   (M1 - M3 M2) M9 F = (AP_xi (x) P_line) F_xi + (AP_eta (x) P_line) F_eta
+//                     + (P_T (x) AP_line) F_zeta
+// with P_T = M_T^-1 T_q^T W, AP_xi/eta = -M_T^-1 (d_xi/eta T_q)^T W (M_T the
+// triangle mass matrix), i.e. the weak form of the DG divergence with the
+// L2-projected flux.  Triangle blocks are applied by one thread per (field,
+// plane) with all rows unrolled, so the operator entries are wave-uniform
+// scalar loads; the line direction uses the same on-the-fly quadrature
+// columns as the hexahedral kernel.
+//
+// Reference prism: triangle {xi, eta >= -1, xi + eta <= 0} x zeta in [-1,1];
+// solution point t + NT k; faces 0/1 = zeta -1/+1 (triangle nodes), faces
+// 2/3/4 = edges eta=-1, xi+eta=0, xi=-1 (GL points along the edge x GL in zeta,
+// index i + n k).
+#include "fr_device.h"
 #include "fr_kernels.h"
 
 namespace fr {
 
-size_t prism_ops_bytes(int, int) { return 8; }
-void prism_ops_pack(const RefElem&, int, void* dst) { *(double*)dst = 0.0; }
-hipError_t prism_rhs(const TypeArgs&, int, hipStream_t) { return hipErrorNotSupported; }
+template <int P, typename R>
+struct PrismOps {
+  static constexpr int n = P + 1, m = P + 3, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
+  // line factors (kernel argument)
+  R I[m][n], D[n][n], Pj[n][m], AP[n][m];
+  R lb[n], rb[n], liftL[n], liftR[n];
+};
+
+template <int P, typename R>
+struct PrismTri {
+  static constexpr int n = P + 1, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
+  R Tq[NTQ][NT];              // triangle nodal basis at the conical quadrature points
+  R Dxi[NT][NT], Deta[NT][NT];  // triangle derivatives at the nodes
+  R PT[NT][NTQ], APxi[NT][NTQ], APeta[NT][NTQ];
+  R Tedge[3][n][NT];          // nodal basis at the GL points of each edge
+  R LiftEdge[3][NT][n];       // DG lifting of an edge point into the plane
+};
+
+template <int P>
+struct PrismCfg {
+  static constexpr int n = P + 1, m = P + 3, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
+  static constexpr int NU = NT * n, NFP = n * n;
+  static constexpr int SZ_X = 20 * NU;
+  static constexpr int SZ_J = 25 * NFP;  // 5 faces x 5 variables
+  static constexpr int SZ_Z = 15 * NTQ * n;
+  static constexpr int SZ_A = (SZ_X + SZ_J > SZ_Z) ? SZ_X + SZ_J : SZ_Z;
+  static constexpr int SZ_T1 = 20 * n * NTQ;
+  static constexpr int PER_ELEM = SZ_A + SZ_T1;
+};
+
+// reference unit normals of the three quadrilateral faces (xi, eta components)
+template <typename R>
+__device__ __forceinline__ void edge_normal(int e, R& nx, R& ny) {
+  const R h = R(0.70710678118654752440);
+  nx = e == 0 ? R(0) : (e == 1 ? h : R(-1));
+  ny = e == 0 ? R(-1) : (e == 1 ? h : R(0));
+}
+
+template <int N, typename R>
+__device__ __forceinline__ R psel(const R (&v)[N], int idx) {
+  R r = v[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = idx == k ? v[k] : r;
+  return r;
+}
+
+// ----------------------------------------------------------------- disu
+template <int P, typename R, int EB, int NT_>
+__global__ void __launch_bounds__(NT_) prism_disu(const double* __restrict__ U, R* __restrict__ Uf,
+                                                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri,
+                                                  const double eref, const int E, const int slot_base) {
+  using C = PrismCfg<P>;
+  constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
+  __shared__ R sU[EB * 5 * NU];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  for (int it = tid; it < EB * 5 * NU; it += NT_) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
+    R val = R(0);
+    if (e < E) {
+      double x = U[(size_t)e * 5 * NU + r];
+      if (r >= 4 * NU) x -= eref;
+      val = R(x);
+    }
+    sU[it] = val;
+  }
+  __syncthreads();
+  // triangle faces: line interpolation in zeta at every node
+  for (int it = tid; it < EB * 5 * NT; it += NT_) {
+    const int le = it / (5 * NT), r = it - le * (5 * NT), v = r / NT, t = r - v * NT, e = e0 + le;
+    if (e >= E) continue;
+    R xm = R(0), xp = R(0);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const R x = sU[le * 5 * NU + v * NU + t + NT * k];
+      xm += op.lb[k] * x;
+      xp += op.rb[k] * x;
+    }
+    const size_t s0 = (size_t)(slot_base + e * 5);
+    Uf[s0 * 5 * NFP + v * NFP + t] = xm;
+    Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = xp;
+  }
+  // quadrilateral faces: triangle-plane interpolation to the edge points
+  for (int it = tid; it < EB * 5 * n; it += NT_) {
+    const int le = it / (5 * n), r = it - le * (5 * n), v = r / n, k = r - v * n, e = e0 + le;
+    if (e >= E) continue;
+    R x[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) x[t] = sU[le * 5 * NU + v * NU + t + NT * k];
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * x[t];
+        Uf[(size_t)(slot_base + e * 5 + 2 + ed) * 5 * NFP + v * NFP + i + n * k] = s;
+      }
+  }
+}
+
+// --------------------------------------------------------------- volume
+template <int P, typename R, int EB, int NT_>
+__global__ void __launch_bounds__(NT_)
+    prism_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
+                 const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
+                 const R* __restrict__ met, const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri,
+                 const Gas<R> g, const double eref, const int E, const int slot_base) {
+  using C = PrismCfg<P>;
+  constexpr int n = C::n, m = C::m, NT = C::NT, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  __shared__ R smem[EB * PE];
+  __shared__ R sMet[EB][10];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+#define XS(le) (smem + (le)*PE)            /* [20][NU]              */
+#define JS(le) (smem + (le)*PE + C::SZ_X)  /* [5][5][NFP]           */
+#define ZS(le) (smem + (le)*PE)            /* [3][5][NTQ][n]        */
+#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][NTQ]          */
+  const int fnp[5] = {NT, NT, NFP, NFP, NFP};
+
+  // phase 0: state, metrics, neighbour face states
+  for (int it = tid; it < EB * 5 * NU; it += NT_) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
+    R val = R(0);
+    if (e < E) {
+      double x = U[(size_t)e * 5 * NU + r];
+      if (r >= 4 * NU) x -= eref;
+      val = R(x);
+    }
+    XS(le)[r] = val;
+  }
+  for (int it = tid; it < EB * 10; it += NT_) {
+    const int le = it / 10, k = it - le * 10, e = e0 + le;
+    sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
+  }
+  for (int it = tid; it < EB * 25 * NFP; it += NT_) {
+    const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
+    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP, e = e0 + le;
+    R val = R(0);
+    if (e < E && r < fnp[f]) {
+      const FaceRec fr = faces[slot_base + e * 5 + f];
+      const int rr = perms[(fr.info >> 1) * NFP + r];
+      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    }
+    JS(le)[r0] = val;
+  }
+  __syncthreads();
+
+  // phase 1: own face values and jumps (eq. FR-conu)
+  for (int it = tid; it < EB * 5 * (NT + n); it += NT_) {
+    const int le = it / (5 * (NT + n)), r0 = it - le * (5 * (NT + n)), e = e0 + le;
+    if (e >= E) continue;
+    const R* X = XS(le);
+    if (r0 < 5 * NT) {
+      const int v = r0 / NT, t = r0 - v * NT;
+      R xm = R(0), xp = R(0);
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const R x = X[v * NU + t + NT * k];
+        xm += op.lb[k] * x;
+        xp += op.rb[k] * x;
+      }
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        const int info = faces[slot_base + e * 5 + sg].info;
+        const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
+        R* jj = JS(le) + (sg * 5 + v) * NFP + t;
+        *jj = coef * (*jj - (sg ? xp : xm));
+      }
+    } else {
+      const int r1 = r0 - 5 * NT, v = r1 / n, k = r1 - v * n;
+      R x[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) x[t] = X[v * NU + t + NT * k];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed) {
+        const int info = faces[slot_base + e * 5 + 2 + ed].info;
+        const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * x[t];
+          R* jj = JS(le) + ((2 + ed) * 5 + v) * NFP + i + n * k;
+          *jj = coef * (*jj - s);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 2: corrected reference gradient (eq. FR-qfinal): zeta along lines,
+  // (xi, eta) per triangle plane with the edge lifting
+  for (int it = tid; it < EB * 5 * (NT + n); it += NT_) {
+    const int le = it / (5 * (NT + n)), r0 = it - le * (5 * (NT + n));
+    R* X = XS(le);
+    const R* J = JS(le);
+    if (r0 < 5 * NT) {
+      const int v = r0 / NT, t = r0 - v * NT;
+      R x[n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) x[k] = X[v * NU + t + NT * k];
+      const R jm = J[(0 * 5 + v) * NFP + t], jp = J[(1 * 5 + v) * NFP + t];
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        R s = op.liftR[k] * jp - op.liftL[k] * jm;
+#pragma unroll
+        for (int c = 0; c < n; ++c) s += op.D[k][c] * x[c];
+        X[(5 + 2 * 5 + v) * NU + t + NT * k] = s;
+      }
+    } else {
+      const int r1 = r0 - 5 * NT, v = r1 / n, k = r1 - v * n;
+      R x[NT], je[3][n];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) x[t] = X[v * NU + t + NT * k];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+        for (int i = 0; i < n; ++i) je[ed][i] = J[((2 + ed) * 5 + v) * NFP + i + n * k];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        R sx = R(0), sy = R(0);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          sx += tri->Dxi[t][c] * x[c];
+          sy += tri->Deta[t][c] * x[c];
+        }
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed) {
+          R nx, ny;
+          edge_normal<R>(ed, nx, ny);
+          R l = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) l += tri->LiftEdge[ed][t][i] * je[ed][i];
+          sx += nx * l;
+          sy += ny * l;
+        }
+        X[(5 + 0 * 5 + v) * NU + t + NT * k] = sx;
+        X[(5 + 1 * 5 + v) * NU + t + NT * k] = sy;
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru)
+  for (int it = tid; it < EB * NU; it += NT_) {
+    const int le = it / NU, s = it - le * NU;
+    R* X = XS(le);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+    }
+  }
+  __syncthreads();
+
+  // phase 4a: normal viscous flux at own flux points (gradcoru_fpts)
+  // phase 4b: triangle-plane interpolation of the 20 fields to the
+  //           triangle quadrature points (first factor of M7 / M10)
+  constexpr int NI_TRI = NT, NI_QUAD = 3 * n, NI_SW = 20 * n;
+  for (int it = tid; it < EB * (NI_TRI + NI_QUAD + NI_SW); it += NT_) {
+    if (it < EB * (NI_TRI + NI_QUAD)) {
+      const int le = it / (NI_TRI + NI_QUAD), r0 = it - le * (NI_TRI + NI_QUAD), e = e0 + le;
+      if (e >= E) continue;
+      const R* X = XS(le);
+      if (r0 < NI_TRI) {
+        const int t = r0;
+        R fm[20], fp[20];
+#pragma unroll
+        for (int fld = 0; fld < 20; ++fld) {
+          R sm = R(0), sp = R(0);
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            const R x = X[fld * NU + t + NT * k];
+            sm += op.lb[k] * x;
+            sp += op.rb[k] * x;
+          }
+          fm[fld] = sm;
+          fp[fld] = sp;
+        }
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+          const R* w = sg ? fp : fm;
+          const int slot = slot_base + e * 5 + sg;
+          const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
+          const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+          R u[5], q[3][5], V[4];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            u[v] = w[v];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
+          }
+          normal_viscous(u, q, nn, g, V);
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + t] = V[kk];
+        }
+      } else {
+        const int r1 = r0 - NI_TRI, ed = r1 / n, k = r1 - ed * n;
+        const int slot = slot_base + e * 5 + 2 + ed;
+        const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
+        const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+        // edge values of the 20 fields on plane k, one edge point at a time
+        for (int i = 0; i < n; ++i) {
+          R w[20];
+#pragma unroll
+          for (int fld = 0; fld < 20; ++fld) {
+            R s = R(0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * X[fld * NU + t + NT * k];
+            w[fld] = s;
+          }
+          R u[5], q[3][5], V[4];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            u[v] = w[v];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
+          }
+          normal_viscous(u, q, nn, g, V);
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
+        }
+      }
+    } else {
+      const int i2 = it - EB * (NI_TRI + NI_QUAD);
+      const int le = i2 / NI_SW, r0 = i2 - le * NI_SW, fld = r0 / n, k = r0 - fld * n;
+      R x[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) x[t] = XS(le)[fld * NU + t + NT * k];
+#pragma unroll
+      for (int tq = 0; tq < NTQ; ++tq) {
+        R s = R(0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) s += tri->Tq[tq][t] * x[t];
+        TS(le)[(fld * n + k) * NTQ + tq] = s;
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 5: line columns over the triangle quadrature points: zeta
+  // interpolation, flux (tdisf) and the line part of the projection-divergence
+  for (int it = tid; it < EB * NTQ; it += NT_) {
+    const int le = it / NTQ, tq = it - le * NTQ;
+    const R* T = TS(le);
+    R t1[20][n];
+#pragma unroll
+    for (int fld = 0; fld < 20; ++fld)
+#pragma unroll
+      for (int k = 0; k < n; ++k) t1[fld][k] = T[(fld * n + k) * NTQ + tq];
+    R S[3][3];
+    const R dj = sMet[le][9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[le][3 * d + c];
+    R acc[3][5][n];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int k = 0; k < n; ++k) acc[d][v][k] = R(0);
+#pragma unroll
+    for (int kq = 0; kq < m; ++kq) {
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int fld = 0; fld < 20; ++fld) {
+        R s = R(0);
+#pragma unroll
+        for (int k = 0; k < n; ++k) s += op.I[kq][k] * t1[fld][k];
+        if (fld < 5)
+          u[fld] = s;
+        else
+          q[(fld - 5) / 5][(fld - 5) % 5] = s;
+      }
+      point_flux(u, q, g, f);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const R ft = S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
+#pragma unroll
+          for (int k = 0; k < n; ++k) acc[d][v][k] += (d == 2 ? op.AP[k][kq] : op.Pj[k][kq]) * ft;
+        }
+    }
+    R* Z = ZS(le);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int k = 0; k < n; ++k) Z[((d * 5 + v) * NTQ + tq) * n + k] = acc[d][v][k];
+  }
+  __syncthreads();
+
+  // phase 6: triangle-plane projection-divergence, per solution level
+  for (int it = tid; it < EB * 5 * n; it += NT_) {
+    const int le = it / (5 * n), r0 = it - le * (5 * n), v = r0 / n, k = r0 - v * n, e = e0 + le;
+    if (e >= E) continue;
+    const R* Z = ZS(le);
+    R out[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) out[t] = R(0);
+#pragma unroll
+    for (int tq = 0; tq < NTQ; ++tq) {
+      const R zx = Z[((0 * 5 + v) * NTQ + tq) * n + k];
+      const R zy = Z[((1 * 5 + v) * NTQ + tq) * n + k];
+      const R zz = Z[((2 * 5 + v) * NTQ + tq) * n + k];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) out[t] += tri->APxi[t][tq] * zx + tri->APeta[t][tq] * zy + tri->PT[t][tq] * zz;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Rp[(size_t)e * 5 * NU + v * NU + t + NT * k] = out[t];
+  }
+#undef XS
+#undef JS
+#undef ZS
+#undef TS
+}
+
+// -------------------------------------------------------------- surface
+template <int P, typename R, int EB, int NT_>
+__global__ void __launch_bounds__(NT_)
+    prism_surface(const R* __restrict__ Uf, const R* __restrict__ Vf, const R* __restrict__ Rp,
+                  double* __restrict__ du, const FaceRec* __restrict__ faces, const R* __restrict__ fgeo,
+                  const uint8_t* __restrict__ perms, const double* __restrict__ detj, const PrismOps<P, R> op,
+                  const PrismTri<P, R>* __restrict__ tri, const Gas<R> g, const int E, const int slot_base) {
+  using C = PrismCfg<P>;
+  constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
+  __shared__ R sD[EB * 25 * NFP];
+  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  const int fnp[5] = {NT, NT, NFP, NFP, NFP};
+  for (int it = tid; it < EB * 5 * NFP; it += NT_) {
+    const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
+    if (e >= E || r >= fnp[f]) continue;
+    const int slot = slot_base + e * 5 + f;
+    const FaceRec fr = faces[slot];
+    const int rr = perms[(fr.info >> 1) * NFP + r];
+    const bool left = fr.info & 1;
+    R uo[5], un[5], Vo[4], Vn[4], F[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      uo[v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
+      un[v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Vo[k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
+      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
+    }
+    const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
+    const R mag = fgeo[4 * slot + 3];
+    if (left)
+      common_flux(uo, un, Vo, Vn, nL, g, F);
+    else
+      common_flux(un, uo, Vn, Vo, nL, g, F);
+    const R sc = left ? mag : -mag;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sD[(le * 5 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
+  }
+  __syncthreads();
+  // tdivtconf + negdivconf, one (variable, plane) per thread
+  for (int it = tid; it < EB * 5 * n; it += NT_) {
+    const int le = it / (5 * n), r0 = it - le * (5 * n), v = r0 / n, k = r0 - v * n, e = e0 + le;
+    if (e >= E) continue;
+    const R* D = sD + le * 25 * NFP + v * NFP;
+    const R lL = psel(op.liftL, k), lR = psel(op.liftR, k);
+    R de[3][n];
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+      for (int i = 0; i < n; ++i) de[ed][i] = D[(2 + ed) * 5 * NFP + i + n * k];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      R acc = Rp[(size_t)e * 5 * NU + v * NU + t + NT * k] + lL * D[0 * 5 * NFP + t] + lR * D[1 * 5 * NFP + t];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+        for (int i = 0; i < n; ++i) acc += tri->LiftEdge[ed][t][i] * de[ed][i];
+      du[(size_t)e * 5 * NU + v * NU + t + NT * k] = -double(acc) / detj[e];
+    }
+  }
+}
+
+// ------------------------------------------------------------ host side
+template <int P, typename R>
+static PrismOps<P, R> make_prism_ops(const HostOps& h) {
+  PrismOps<P, R> o;
+  constexpr int n = P + 1, m = P + 3;
+  for (int a = 0; a < m; ++a)
+    for (int i = 0; i < n; ++i) o.I[a][i] = R(h.I[a * n + i]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) o.D[i][j] = R(h.D[i * n + j]);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < m; ++a) {
+      o.Pj[i][a] = R(h.P[i * m + a]);
+      o.AP[i][a] = R(h.AP[i * m + a]);
+    }
+  for (int i = 0; i < n; ++i) {
+    o.lb[i] = R(h.lb[i]);
+    o.rb[i] = R(h.rb[i]);
+    o.liftL[i] = R(h.liftL[i]);
+    o.liftR[i] = R(h.liftR[i]);
+  }
+  return o;
+}
+
+template <int P, typename R>
+static void pack_tri(const Tri& T, PrismTri<P, R>* o) {
+  constexpr int n = P + 1, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
+  for (int q = 0; q < NTQ; ++q)
+    for (int t = 0; t < NT; ++t) o->Tq[q][t] = R(T.Tq[q * NT + t]);
+  for (int a = 0; a < NT; ++a)
+    for (int b = 0; b < NT; ++b) {
+      o->Dxi[a][b] = R(T.Dxi[a * NT + b]);
+      o->Deta[a][b] = R(T.Deta[a * NT + b]);
+    }
+  for (int t = 0; t < NT; ++t)
+    for (int q = 0; q < NTQ; ++q) {
+      o->PT[t][q] = R(T.PT[t * NTQ + q]);
+      o->APxi[t][q] = R(T.APxi[t * NTQ + q]);
+      o->APeta[t][q] = R(T.APeta[t * NTQ + q]);
+    }
+  for (int e = 0; e < 3; ++e) {
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < NT; ++t) o->Tedge[e][i][t] = R(T.Tedge[(e * n + i) * NT + t]);
+    for (int t = 0; t < NT; ++t)
+      for (int i = 0; i < n; ++i) o->LiftEdge[e][t][i] = R(T.LiftEdge[(e * NT + t) * n + i]);
+  }
+}
+
+size_t prism_ops_bytes(int p, int prec) {
+  const bool d = prec == 0;
+  switch (p) {
+    case 1: return d ? sizeof(PrismTri<1, double>) : sizeof(PrismTri<1, float>);
+    case 2: return d ? sizeof(PrismTri<2, double>) : sizeof(PrismTri<2, float>);
+    case 3: return d ? sizeof(PrismTri<3, double>) : sizeof(PrismTri<3, float>);
+    case 4: return d ? sizeof(PrismTri<4, double>) : sizeof(PrismTri<4, float>);
+  }
+  return 0;
+}
+
+void prism_ops_pack(const RefElem& r, int prec, void* dst) {
+  const bool d = prec == 0;
+  switch (r.p) {
+    case 1: d ? pack_tri<1, double>(r.tri, (PrismTri<1, double>*)dst) : pack_tri<1, float>(r.tri, (PrismTri<1, float>*)dst); break;
+    case 2: d ? pack_tri<2, double>(r.tri, (PrismTri<2, double>*)dst) : pack_tri<2, float>(r.tri, (PrismTri<2, float>*)dst); break;
+    case 3: d ? pack_tri<3, double>(r.tri, (PrismTri<3, double>*)dst) : pack_tri<3, float>(r.tri, (PrismTri<3, float>*)dst); break;
+    case 4: d ? pack_tri<4, double>(r.tri, (PrismTri<4, double>*)dst) : pack_tri<4, float>(r.tri, (PrismTri<4, float>*)dst); break;
+  }
+}
+
+template <typename R>
+static Gas<R> make_gas_p(const GasHost& g) {
+  Gas<R> o;
+  o.gamma = R(g.gamma);
+  o.gm1 = R(g.gamma - 1.0);
+  o.mu = R(g.mu);
+  o.muh = R(g.mu * g.gamma / g.prandtl);
+  o.pref = R(g.pref);
+  o.eref = R(g.pref / (g.gamma - 1.0));
+  o.href = R(g.gamma * g.pref / (g.gamma - 1.0));
+  o.beta = R(g.beta);
+  o.tau = R(g.tau);
+  return o;
+}
+
+template <int P, typename R>
+static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
+  const PrismOps<P, R> op = make_prism_ops<P, R>(*a.ops);
+  const Gas<R> g = make_gas_p<R>(*a.gas);
+  const PrismTri<P, R>* tri = (const PrismTri<P, R>*)a.dops;
+  const int E = (int)a.E;
+  if (E == 0) return hipSuccess;
+  constexpr bool dbl = sizeof(R) == 8;
+  constexpr int EB = dbl ? 2 : 4, NT = EB * 64;
+  const double eref = a.gas->pref / (a.gas->gamma - 1.0);
+  const int sb = (int)a.slot_base;
+  if (a.stage & 1) {
+    constexpr int EBA = 8, NTA = 256;
+    hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA>), dim3((E + EBA - 1) / EBA), dim3(NTA), 0, st, a.U, (R*)a.Uf, op,
+                       tri, eref, E, sb);
+  }
+  if (a.stage & 2) {
+    hipLaunchKernelGGL((prism_volume<P, R, EB, NT>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U, (const R*)a.Uf,
+                       (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op, tri, g, eref, E,
+                       sb);
+  }
+  if (a.stage & 4) {
+    constexpr int EBC = 4, NTC = 256;
+    hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC>), dim3((E + EBC - 1) / EBC), dim3(NTC), 0, st, (const R*)a.Uf,
+                       (const R*)a.Vf, (const R*)a.Rp, a.du, a.faces, (const R*)a.fgeo, a.perms, a.detj, op, tri, g,
+                       E, sb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t prism_rhs(const TypeArgs& a, int prec, hipStream_t st) {
+  const bool d = prec == 0;
+  switch (a.p) {
+    case 1: return d ? prism_rhs_t<1, double>(a, st) : prism_rhs_t<1, float>(a, st);
+    case 2: return d ? prism_rhs_t<2, double>(a, st) : prism_rhs_t<2, float>(a, st);
+    case 3: return d ? prism_rhs_t<3, double>(a, st) : prism_rhs_t<3, float>(a, st);
+    case 4: return d ? prism_rhs_t<4, double>(a, st) : prism_rhs_t<4, float>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
 
 }  // namespace fr

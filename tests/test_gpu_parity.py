@@ -48,8 +48,8 @@ def _rel_err(got, ref):
     return np.max(out, axis=0)
 
 
-def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0):
-    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref)
+def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0, form="fused"):
+    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref, form=form)
     flat = np.concatenate([u.reshape(-1) for u in U])
     u = torch.from_numpy(flat).cuda()
     du = torch.empty_like(u)
@@ -59,7 +59,9 @@ def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0):
 
 
 CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((2, 3, 3), 4, "hex"),
-         ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex")]
+         ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"),
+         ((2, 2, 2), 3, "prism"), ((3, 2, 2), 1, "prism"), ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"),
+         ((1, 1, 1), 3, "prism"), ((2, 2, 4), 3, "mixed"), ((3, 2, 2), 4, "mixed"), ((2, 1, 2), 2, "mixed")]
 
 
 def _references(m, U):
@@ -85,6 +87,42 @@ def test_rhs_parity(dims, p, kind, prec):
         tol = np.maximum(tol, 4 * own)
     print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
     assert np.all(err < tol), (err, tol)
+
+
+@pytest.mark.parametrize("dims,p,kind", [((4, 4, 4), 3, "hex"), ((2, 2, 2), 3, "prism"), ((2, 2, 4), 2, "mixed"),
+                                         ((2, 3, 3), 4, "hex")])
+def test_plain_path_parity(dims, p, kind):
+    """The unfused FP64 comparison path (dense operators, library GEMMs)."""
+    _need_gpu()
+    print("plain case", dims, p, kind, flush=True)
+    m, U = _case(dims, p, kind)
+    r64, rld = _references(m, U)
+    got, _ = _gpu_rhs(dims, p, kind, "fp64", U, form="plain")
+    err = _rel_err(got, rld).astype(np.float64)
+    own = _rel_err(r64, rld).astype(np.float64)
+    tol = np.maximum(1e-12, 4 * own)
+    print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
+    assert np.all(err < tol), (err, tol)
+
+
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed"])
+def test_fused_matches_plain_on_gpu(kind):
+    """Fused and plain GPU paths on a medium mesh (several workgroups and a
+    ragged last block), FP64."""
+    _need_gpu()
+    dims = (5, 3, 4)
+    s = frmi.Solver(dims, 3, kind, pref=inputs.P0)
+    U = inputs.element_state(s.upts_coords(), seed=3)
+    flat = torch.from_numpy(np.concatenate([u.reshape(-1) for u in U])).cuda()
+    a, b = torch.empty_like(flat), torch.empty_like(flat)
+    s.rhs(flat, a)
+    sp = frmi.Solver(dims, 3, kind, pref=inputs.P0, form="plain")
+    sp.rhs(flat, b)
+    torch.cuda.synchronize()
+    for x, y in zip(s.split(a.cpu().numpy()), s.split(b.cpu().numpy())):
+        err = np.abs(x - y).max(axis=(0, 2)) / np.abs(y).max(axis=(0, 2))
+        print(kind, "fused vs plain", err)
+        assert np.all(err < 5e-12)
 
 
 def test_free_stream_and_conservation_gpu():

@@ -180,7 +180,7 @@ def test_divergence_operator_is_weak_form(refs, case):
     for d in range(3):
         fu = r.M8  # M9 block for component d
         lhs = r.Dg[d] @ fu - r.M3 @ (r.fnorm[:, d][:, None] * (r.M0 @ fu))
-        rhs = -np.linalg.solve(r.mass, Dq[d].T * r.qwts[None, :])
+        rhs = -np.linalg.solve(r.mass.astype(np.float64), (Dq[d].T * r.qwts[None, :]).astype(np.float64))
         np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.abs(rhs).max())
 
 
@@ -253,5 +253,5 @@ def test_prism_operators_factor_into_triangle_times_line(refs, p):
     np.testing.assert_allclose(r.M7, np.kron(L, T), atol=1e-13)
     PL = (L.T * gqw[None, :]) / glw[:, None]
     Mt = T.T @ (tqw[:, None] * T)
-    PT = np.linalg.solve(Mt, T.T * tqw[None, :])
+    PT = np.linalg.solve(Mt.astype(np.float64), (T.T * tqw[None, :]).astype(np.float64))
     np.testing.assert_allclose(r.M8, np.kron(PL, PT), atol=1e-12)

@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--n", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline variant only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -156,6 +158,14 @@ def main():
     import torch
     import paper_2401_06132_amd as frmi
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
     variants = {}
     order = [("fp32", 3, "fused")] if args.quick else [
         ("fp32", 3, "fused"), ("fp64", 3, "fused"), ("fp64", 3, "plain"),

@@ -24,6 +24,7 @@ struct fr_ctx {
   bool has[2] = {false, false};
   fr::Mesh M;
   int64_t off[2] = {0, 0}, n_state = 0;
+  bool diag[2] = {false, false};  // all Jacobians of the type are diagonal
   fr::HostOps hops[2];
   fr::GasHost gas;
   // device buffers
@@ -236,6 +237,7 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const double* u, double* du, int stage)
   a.E = c->M.nel[t];
   a.slot_base = c->M.slot_base[t];
   a.stage = stage;
+  a.diag = c->diag[t];
   a.U = u + c->off[t];
   a.du = du + c->off[t];
   a.Uf = c->d_Uf;
@@ -331,6 +333,14 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     h.liftR = r.line.liftR.data();
     h.tri = &r.tri;
     h.ref = &r;
+  }
+  for (int t = 0; t < 2; ++t) {
+    bool d = c->has[t];
+    for (int64_t e = 0; e < c->M.nel[t] && d; ++e) {
+      const double* A = &c->M.jac[t][9 * e];
+      d = A[1] == 0 && A[2] == 0 && A[3] == 0 && A[5] == 0 && A[6] == 0 && A[7] == 0;
+    }
+    c->diag[t] = d;
   }
   c->off[0] = 0;
   c->off[1] = c->M.nel[0] * 5 * c->ref[0].nu;

@@ -23,6 +23,12 @@ template <typename R>
 __device__ __forceinline__ R rcp(R x) {
   return R(1) / x;
 }
+// single precision: the hardware reciprocal (1 ulp), well inside the FP32
+// path's rounding budget; double precision keeps the correctly rounded division
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
 
 // Physical flux f = f^e - f^v at one point.  u: 5 conserved (reference
 // form), q[d][v]: physical gradients d/dx_d of the conserved variables.

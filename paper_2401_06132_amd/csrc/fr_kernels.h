@@ -28,6 +28,7 @@ struct TypeArgs {
   int64_t E = 0;          // elements of this type
   int64_t slot_base = 0;  // first face slot of this type
   int stage = 7;          // bit 0: disu, bit 1: volume group, bit 2: interface group
+  bool diag = false;      // every element of this type has a diagonal Jacobian
   const double* U = nullptr;  // state of this type (E x 5 x N_u)
   double* du = nullptr;
   void* Uf = nullptr;  // face states   [slot][5][n^2]   (precision R)

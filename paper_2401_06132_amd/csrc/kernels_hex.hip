@@ -105,21 +105,38 @@ __global__ void __launch_bounds__(NT) hex_disu(const double* __restrict__ U, R* 
 }
 
 // --------------------------------------------------------------- volume
-template <int P, typename R, int EB, int NT>
+// LDS per element: region A holds the state + gradients (20 fields at the
+// solution points), later the y-projected residual; region B holds the
+// neighbour face states, then the x-interpolated fields T1, then the
+// z-projected flux Z (written only after every column has read T1).
+template <int P>
+struct HexVol {
+  static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
+  static constexpr int SZ_X = 20 * NU, SZ_Y = 10 * m * n * n;
+  static constexpr int SZ_A = SZ_X > SZ_Y ? SZ_X : SZ_Y;
+  static constexpr int SZ_T1 = 20 * m * n * n, SZ_Z = 15 * m * m * n, SZ_J = 30 * NFP;
+  static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
+  static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
+  static constexpr int PER_ELEM = SZ_A + SZ_B;
+};
+
+template <int P, typename R, int EB, int NT, bool DIAG>
 __global__ void __launch_bounds__(NT)
     hex_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
                const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
                const R* __restrict__ met, const HexOps<P, R> op, const Gas<R> g, const double eref, const int E,
                const int slot_base) {
-  using C = HexCfg<P>;
+  using C = HexVol<P>;
   constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   const int tid = threadIdx.x, e0 = blockIdx.x * EB;
-#define XS(le) (smem + (le)*PE)                 /* [20][NU] state + gradients */
-#define JS(le) (smem + (le)*PE + C::SZ_X)       /* [6][5][NFP] jumps          */
-#define ZS(le) (smem + (le)*PE)                 /* [3][5][m][m][n]            */
-#define TS(le) (smem + (le)*PE + C::SZ_A)       /* [20][m][n][n]              */
+#define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
+#define YS(le) (smem + (le)*PE)            /* [2][5][m][n][n]              */
+#define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
+#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][m][n][n]                */
+#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][m][m][n]              */
 
   // phase 0: state (reference form), metrics, neighbour states at own faces
   for (int it = tid; it < EB * 5 * NU; it += NT) {
@@ -142,161 +159,160 @@ __global__ void __launch_bounds__(NT)
     R val = R(0);
     if (e < E) {
       const FaceRec fr = faces[slot_base + e * 6 + f];
-      const int rr = perms[(fr.info >> 1) * NFP + r];
-      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + perms[(fr.info >> 1) * NFP + r]];
     }
     JS(le)[r0] = val;
   }
   __syncthreads();
 
-  // phase 1: own face values and jumps C - u^f (eq. FR-conu):
-  //   L side: (1/2 + beta)(u_nbr - u_own), R side: (1/2 - beta)(u_nbr - u_own)
-  for (int it = tid; it < EB * 15 * NFP; it += NT) {
-    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
-    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+  // phase 1: per axis and line: own face values, jumps C - u^f (eq. FR-conu:
+  // L side (1/2 + beta)(u_nbr - u_own), R side (1/2 - beta)(u_nbr - u_own)),
+  // and the corrected gradient D u + lift (eq. FR-qfinal).  With a diagonal
+  // metric the J^-T scaling of eq. FR-gradcoru is applied here as well.
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    constexpr int dummy = 0;
+    (void)dummy;
+    const int si = ax == 0 ? 1 : (ax == 1 ? n : n * n);
+    const int sa = ax == 0 ? n : 1, sb = ax == 2 ? n : n * n;
+    for (int it = tid; it < EB * 5 * NFP; it += NT) {
+      const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), v = r0 / NFP, r = r0 - v * NFP;
+      const int a = r % n, b = r / n, e = e0 + le;
+      R* X = XS(le);
+      const int base = a * sa + b * sb;
+      R x[n];
+#pragma unroll
+      for (int i = 0; i < n; ++i) x[i] = X[v * NU + base + i * si];
+      R xm = R(0), xp = R(0);
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        xm += op.lb[i] * x[i];
+        xp += op.rb[i] * x[i];
+      }
+      int im = 0, ip = 0;
+      if (e < E) {
+        im = faces[slot_base + e * 6 + 2 * ax].info;
+        ip = faces[slot_base + e * 6 + 2 * ax + 1].info;
+      }
+      const R jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax) * 5 + v) * NFP + r] - xm);
+      const R jp = ((ip & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax + 1) * 5 + v) * NFP + r] - xp);
+      const R sc = DIAG ? sMet[le][4 * ax] : R(1);
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        R s = op.liftR[i] * jp - op.liftL[i] * jm;
+#pragma unroll
+        for (int c = 0; c < n; ++c) s += op.D[i][c] * x[c];
+        X[(5 + ax * 5 + v) * NU + base + i * si] = sc * s;
+      }
+    }
+  }
+  __syncthreads();
+
+  if (!DIAG) {
+    // phase 2: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s = it - le * NU;
+      R* X = XS(le);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+      }
+    }
+    __syncthreads();
+  }
+
+  // phase 3a: gradcoru_fpts + normal viscous flux at the own flux points
+  for (int it = tid; it < EB * 3 * NFP; it += NT) {
+    const int le = it / (3 * NFP), r0 = it - le * (3 * NFP), ax = r0 / NFP, r = r0 - ax * NFP;
     const int a = r % n, b = r / n, e = e0 + le;
     if (e >= E) continue;
-    R xm = R(0), xp = R(0);
+    const int si = ax == 0 ? 1 : (ax == 1 ? n : n * n);
+    const int base = ax == 0 ? n * a + n * n * b : (ax == 1 ? a + n * n * b : a + n * b);
+    const R* X = XS(le);
+    R fm[20], fp[20];
 #pragma unroll
-    for (int i = 0; i < n; ++i) {
-      const R x = XS(le)[v * NU + hex_pt<n>(ax, i, a, b)];
-      xm += op.lb[i] * x;
-      xp += op.rb[i] * x;
+    for (int fld = 0; fld < 20; ++fld) {
+      R sm = R(0), sp = R(0);
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const R x = X[fld * NU + base + i * si];
+        sm += op.lb[i] * x;
+        sp += op.rb[i] * x;
+      }
+      fm[fld] = sm;
+      fp[fld] = sp;
     }
 #pragma unroll
     for (int sg = 0; sg < 2; ++sg) {
-      const int f = 2 * ax + sg;
-      const int info = faces[slot_base + e * 6 + f].info;
-      const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
-      R* jj = JS(le) + (f * 5 + v) * NFP + r;
-      *jj = coef * (*jj - (sg ? xp : xm));
+      const R* w = sg ? fp : fm;
+      const int slot = slot_base + e * 6 + 2 * ax + sg;
+      const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+      R u[5], q[3][5], V[4];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = w[v];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
+      }
+      normal_viscous(u, q, nn, g, V);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
     }
   }
-  __syncthreads();
-
-  // phase 2: corrected reference gradient along each axis (eq. FR-qfinal,
-  // M4 U + M6 (C - U^f)), one line per thread
-  for (int it = tid; it < EB * 15 * NFP; it += NT) {
-    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
-    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-    const int a = r % n, b = r / n;
+  // phase 3b: x interpolation of the 20 fields (first factor of M7 / M10)
+  for (int it = tid; it < EB * 20 * NFP; it += NT) {
+    const int le = it / (20 * NFP), r0 = it - le * (20 * NFP), fld = r0 / NFP, r = r0 - fld * NFP;
+    const int j = r % n, l = r / n;
     R x[n];
 #pragma unroll
-    for (int i = 0; i < n; ++i) x[i] = XS(le)[v * NU + hex_pt<n>(ax, i, a, b)];
-    const R jm = JS(le)[((2 * ax) * 5 + v) * NFP + r], jp = JS(le)[((2 * ax + 1) * 5 + v) * NFP + r];
+    for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * r];
+    R* T = TS(le) + (fld * m) * NFP + j * n + l;
 #pragma unroll
-    for (int i = 0; i < n; ++i) {
-      R s = op.liftR[i] * jp - op.liftL[i] * jm;
+    for (int a = 0; a < m; ++a) {
+      R s = R(0);
 #pragma unroll
-      for (int c = 0; c < n; ++c) s += op.D[i][c] * x[c];
-      XS(le)[(5 + ax * 5 + v) * NU + hex_pt<n>(ax, i, a, b)] = s;
+      for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
+      T[a * NFP] = s;
     }
   }
   __syncthreads();
 
-  // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
-  for (int it = tid; it < EB * NU; it += NT) {
-    const int le = it / NU, s = it - le * NU;
-    R* X = XS(le);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
-    }
-  }
-  __syncthreads();
-
-  // phase 4a: gradcoru_fpts + normal viscous flux at own flux points
-  // phase 4b: first anti-aliasing sweep (x) of the 20 fields
-  constexpr int NFACE_IT = 3 * NFP, NSWEEP_IT = 20 * NFP;
-  for (int it = tid; it < EB * (NFACE_IT + NSWEEP_IT); it += NT) {
-    if (it < EB * NFACE_IT) {
-      const int le = it / NFACE_IT, r0 = it - le * NFACE_IT;
-      const int ax = r0 / NFP, r = r0 - ax * NFP, a = r % n, b = r / n, e = e0 + le;
-      if (e >= E) continue;
-      const R* X = XS(le);
-      R fm[20], fp[20];
-#pragma unroll
-      for (int fld = 0; fld < 20; ++fld) {
-        R sm = R(0), sp = R(0);
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-          const R x = X[fld * NU + hex_pt<n>(ax, i, a, b)];
-          sm += op.lb[i] * x;
-          sp += op.rb[i] * x;
-        }
-        fm[fld] = sm;
-        fp[fld] = sp;
-      }
-#pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        const R* w = sg ? fp : fm;
-        const int slot = slot_base + e * 6 + 2 * ax + sg;
-        const int info = faces[slot].info;
-        const R sgn = (info & 1) ? R(1) : R(-1);
-        const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
-        R u[5], q[3][5], V[4];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          u[v] = w[v];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
-        }
-        normal_viscous(u, q, nn, g, V);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
-      }
-    } else {
-      const int i2 = it - EB * NFACE_IT;
-      const int le = i2 / NSWEEP_IT, r0 = i2 - le * NSWEEP_IT, fld = r0 / NFP, r = r0 - fld * NFP;
-      const int j = r % n, l = r / n;
-      R x[n];
-#pragma unroll
-      for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * (j + n * l)];
-#pragma unroll
-      for (int a = 0; a < m; ++a) {
-        R s = R(0);
-#pragma unroll
-        for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
-        TS(le)[((fld * m + a) * n + j) * n + l] = s;
-      }
-    }
-  }
-  __syncthreads();
-
-  // phase 5: quadrature columns.  y interpolation, then for each z level:
-  // z interpolation (uqpts, gradcoru_qpts), flux (tdisf, eq. FR-tdisfq) and
-  // the z part of the projection-divergence (tdivtpcorf)
-  for (int it = tid; it < EB * m * m; it += NT) {
-    const int le = it / (m * m), r = it - le * (m * m), a = r / m, b = r - a * m;
+  // phase 4: one quadrature column (a, b) per thread: y interpolation, then
+  // for each z level: z interpolation (uqpts, gradcoru_qpts), the flux
+  // (tdisf, eq. FR-tdisfq) and the z factor of the projection-divergence
+  const bool col = tid < EB * m * m;
+  const int cle = tid / (m * m), cr = tid - cle * (m * m), ca = cr / m, cb = cr - ca * m;
+  R acc[3][5][n];
+  if (col) {
     R Ib[n];
 #pragma unroll
     for (int j = 0; j < n; ++j) {
       R t = op.I[0][j];
 #pragma unroll
-      for (int bb = 1; bb < m; ++bb) t = b == bb ? op.I[bb][j] : t;
+      for (int bb = 1; bb < m; ++bb) t = cb == bb ? op.I[bb][j] : t;
       Ib[j] = t;
     }
     R t2[20][n];
-    const R* T = TS(le);
+    const R* T = TS(cle) + ca * NFP;
 #pragma unroll
-    for (int fld = 0; fld < 20; ++fld)
+    for (int fld = 0; fld < 20; ++fld) {
 #pragma unroll
-      for (int l = 0; l < n; ++l) {
-        R s = R(0);
+      for (int l = 0; l < n; ++l) t2[fld][l] = R(0);
 #pragma unroll
-        for (int j = 0; j < n; ++j) s += Ib[j] * T[((fld * m + a) * n + j) * n + l];
-        t2[fld][l] = s;
-      }
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int l = 0; l < n; ++l) t2[fld][l] += Ib[j] * T[fld * m * NFP + j * n + l];
+    }
     R S[3][3];
-    const R dj = sMet[le][9];
+    const R dj = sMet[cle][9];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[le][3 * d + c];
-    R acc[3][5][n];
+      for (int c = 0; c < 3; ++c) S[d][c] = DIAG ? (d == c ? dj * sMet[cle][4 * d] : R(0)) : dj * sMet[cle][3 * d + c];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -321,24 +337,25 @@ __global__ void __launch_bounds__(NT)
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          const R ft = S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
+          const R ft = DIAG ? S[d][d] * f[d][v] : S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
 #pragma unroll
           for (int l = 0; l < n; ++l) acc[d][v][l] += (d == 2 ? op.AP[l][kq] : op.Pj[l][kq]) * ft;
         }
     }
-    // the column region aliases T1 of other columns only through ZS, which
-    // lives in the (dead) state/gradient region
-    R* Z = ZS(le);
+  }
+  __syncthreads();  // every column has read T1; Z may now overwrite it
+  if (col) {
+    R* Z = ZS(cle);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int l = 0; l < n; ++l) Z[(((d * 5 + v) * m + a) * m + b) * n + l] = acc[d][v][l];
+        for (int l = 0; l < n; ++l) Z[(((d * 5 + v) * m + ca) * m + cb) * n + l] = acc[d][v][l];
   }
   __syncthreads();
 
-  // phase 6: y projection: X' = P_y X, Y' = AP_y Y + P_y Z
+  // phase 5: y projection: X' = P_y X, Y' = AP_y Y + P_y Z
   for (int it = tid; it < EB * 5 * m * n; it += NT) {
     const int le = it / (5 * m * n), r0 = it - le * (5 * m * n);
     const int v = r0 / (m * n), r1 = r0 - v * (m * n), a = r1 / n, l = r1 - a * n;
@@ -350,7 +367,7 @@ __global__ void __launch_bounds__(NT)
       zy[b] = Z[(((1 * 5 + v) * m + a) * m + b) * n + l];
       zz[b] = Z[(((2 * 5 + v) * m + a) * m + b) * n + l];
     }
-    R* Y = TS(le);
+    R* Y = YS(le);
 #pragma unroll
     for (int j = 0; j < n; ++j) {
       R sx = R(0), sy = R(0);
@@ -365,12 +382,12 @@ __global__ void __launch_bounds__(NT)
   }
   __syncthreads();
 
-  // phase 7: x projection: R_vol = AP_x X' + P_x Y'
+  // phase 6: x projection: R_vol = AP_x X' + P_x Y'
   for (int it = tid; it < EB * 5 * NFP; it += NT) {
     const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), v = r0 / NFP, r = r0 - v * NFP;
     const int j = r % n, l = r / n, e = e0 + le;
     if (e >= E) continue;
-    const R* Y = TS(le);
+    const R* Y = YS(le);
     R y0[m], y1[m];
 #pragma unroll
     for (int a = 0; a < m; ++a) {
@@ -386,9 +403,10 @@ __global__ void __launch_bounds__(NT)
     }
   }
 #undef XS
+#undef YS
 #undef JS
-#undef ZS
 #undef TS
+#undef ZS
 }
 
 // -------------------------------------------------------------- surface
@@ -484,11 +502,18 @@ static Gas<R> make_gas(const GasHost& g) {
   return o;
 }
 
-template <int P>
-struct HexLaunch {
-  static constexpr int EB_D = 2, NT_D = 128;   // FP64 volume
-  static constexpr int EB_S = 4, NT_S = 256;   // FP32 volume
-};
+// launch shapes of the volume kernel: EB elements per workgroup, NT threads,
+// with EB * m^2 <= NT (one quadrature column per thread) chosen to fill waves
+template <int P, bool DBL>
+struct HexLaunch;
+template <> struct HexLaunch<1, false> { static constexpr int EB = 4, NT = 64; };   // 64 columns
+template <> struct HexLaunch<2, false> { static constexpr int EB = 5, NT = 128; };  // 125
+template <> struct HexLaunch<3, false> { static constexpr int EB = 5, NT = 192; };  // 180
+template <> struct HexLaunch<4, false> { static constexpr int EB = 2, NT = 128; };  // 98
+template <> struct HexLaunch<1, true> { static constexpr int EB = 4, NT = 64; };
+template <> struct HexLaunch<2, true> { static constexpr int EB = 2, NT = 64; };    // 50
+template <> struct HexLaunch<3, true> { static constexpr int EB = 1, NT = 64; };    // 36
+template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 49
 
 template <int P, typename R>
 static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
@@ -497,8 +522,7 @@ static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   const int E = (int)a.E;
   if (E == 0) return hipSuccess;
   constexpr bool dbl = sizeof(R) == 8;
-  constexpr int EB = dbl ? HexLaunch<P>::EB_D : HexLaunch<P>::EB_S;
-  constexpr int NT = dbl ? HexLaunch<P>::NT_D : HexLaunch<P>::NT_S;
+  constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   const int sb = (int)a.slot_base;
   if (a.stage & 1) {
@@ -507,8 +531,14 @@ static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
                        eref, E, sb);
   }
   if (a.stage & 2) {
-    hipLaunchKernelGGL((hex_volume<P, R, EB, NT>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U, (const R*)a.Uf,
-                       (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op, g, eref, E, sb);
+    if (a.diag)
+      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U,
+                         (const R*)a.Uf, (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op,
+                         g, eref, E, sb);
+    else
+      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U,
+                         (const R*)a.Uf, (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op,
+                         g, eref, E, sb);
   }
   if (a.stage & 4) {
     constexpr int EBC = 4, NTC = 256;

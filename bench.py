@@ -69,9 +69,9 @@ def rhs_bytes_model(p, bytes_real):
     return b
 
 
-def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused"):
+def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex"):
     from paper_2401_06132_amd import inputs
-    s = frmi.Solver(n, p, "hex", prec=prec, pref=inputs.P0, form=form)
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form)
     coords = s.upts_coords()
     U = inputs.element_state(coords, seed=0)
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
@@ -103,12 +103,51 @@ def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused"):
         torch.cuda.synchronize()
         vol_ms = e0.elapsed_time(e1) / steps
     ok = bool(torch.isfinite(du).all().item())
-    res = dict(n_dof=s.n_state, n_elem=s.n_hex, wall_s=wall, ms_per_step=wall * 1e3 / steps,
+    res = dict(n_dof=s.n_state, n_elem=s.n_hex + s.n_prism, wall_s=wall, ms_per_step=wall * 1e3 / steps,
                p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), vol_ms=vol_ms,
                finite=ok)
     del s, u, du
     torch.cuda.empty_cache()
     return res
+
+
+def run_rk(frmi, torch, kind, n, p, prec, nsteps, dt):
+    """nsteps RK4 steps on the internal state; per-step HIP-event times and
+    the drift of the conserved integrals."""
+    from paper_2401_06132_amd import inputs
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0)
+    U = inputs.element_state(s.upts_coords(), seed=0)
+    s.set_state(np.concatenate([x.reshape(-1) for x in U]))
+    del U
+    c0 = s.integrals()
+    s.rk4(dt, 1)  # warm-up step (not timed), part of the trajectory
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nsteps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(nsteps):
+        s.rk4(dt, 1)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(nsteps)])
+    c1 = s.integrals()
+    st = s.get_state()
+    finite = bool(np.isfinite(st).all())
+    vol = (2 * np.pi) ** 3
+    # drift relative to the integral itself (mass, energy) or to the mass
+    # integral (momentum, whose integral is ~0 for the vortex)
+    scale = np.array([abs(c0[0]), abs(c0[0]), abs(c0[0]), abs(c0[0]), abs(c0[4])])
+    out = dict(workload="Taylor-Green vortex, %d^3-cell periodic box, %s, p=%d, %s, %d RK4 steps of dt=%g"
+               % (n, kind, p, prec, nsteps + 1, dt),
+               elements=s.n_hex + s.n_prism, n_hex=s.n_hex, n_prism=s.n_prism, dof=s.n_state,
+               ms_per_step=wall * 1e3 / nsteps, p50_step_ms=float(np.percentile(per, 50)),
+               p99_step_ms=float(np.percentile(per, 99)),
+               gdof_rhs_s=s.n_state * 4 * nsteps / wall / 1e9, finite=finite,
+               conservation_drift=[float(x) for x in (c1 - c0) / scale], domain_volume=vol)
+    del s, st
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(budget_s=20.0):
@@ -167,26 +206,34 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}))
         return
     variants = {}
-    order = [("fp32", 3, "fused")] if args.quick else [
-        ("fp32", 3, "fused"), ("fp64", 3, "fused"), ("fp64", 3, "plain"),
-        ("fp32", 4, "fused"), ("fp64", 4, "fused"), ("fp64", 4, "plain")]
-    for prec, p, form in order:
-        r = time_variant(frmi, torch, args.n, p, prec, args.steps, args.warmup, form)
+    order = [("fp32", 3, "fused", "hex")] if args.quick else [
+        ("fp32", 3, "fused", "hex"), ("fp64", 3, "fused", "hex"), ("fp64", 3, "plain", "hex"),
+        ("fp32", 4, "fused", "hex"), ("fp64", 4, "fused", "hex"), ("fp64", 4, "plain", "hex"),
+        ("fp32", 3, "fused", "prism"), ("fp64", 3, "fused", "prism"), ("fp64", 3, "plain", "prism"),
+        ("fp32", 4, "fused", "prism")]
+    for prec, p, form, kind in order:
+        ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
+        r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)
         br = 4 if prec == "fp32" else 8
         vb, vf = volume_model(p, br)
         E = r["n_elem"]
-        r["gdof_s"] = r["n_dof"] * args.steps / r["wall_s"] / 1e9
-        r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
-        r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
-        r["rhs_GBs"] = rhs_bytes_model(p, br) * E * args.steps / r["wall_s"] / 1e9
-        variants["%s%s_p%d" % ("plain_" if form == "plain" else "", prec, p)] = r
+        r["gdof_s"] = r["n_dof"] * ksteps / r["wall_s"] / 1e9
+        if kind == "hex":
+            r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
+            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
+            r["rhs_GBs"] = rhs_bytes_model(p, br) * E * ksteps / r["wall_s"] / 1e9
+        else:
+            r["vol_GBs"] = r["vol_TFLOPs"] = r["rhs_GBs"] = float("nan")
+        variants["%s%s%s_p%d" % ("prism_" if kind == "prism" else "", "plain_" if form == "plain" else "", prec,
+                                  p)] = r
         print("variant", form, prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
               file=sys.stderr, flush=True)
     head = variants["fp32_p3"]
-    for p in (3, 4):
-        if "plain_fp64_p%d" % p in variants and "fp32_p%d" % p in variants:
-            variants["fp32_p%d" % p]["speedup_vs_plain_fp64"] = (variants["fp32_p%d" % p]["gdof_s"] /
-                                                                   variants["plain_fp64_p%d" % p]["gdof_s"])
+    for pre in ("", "prism_"):
+        for p in (3, 4):
+            a, b = "%sfp32_p%d" % (pre, p), "%splain_fp64_p%d" % (pre, p)
+            if a in variants and b in variants:
+                variants[a]["speedup_vs_plain_fp64"] = variants[a]["gdof_s"] / variants[b]["gdof_s"]
     vb, vf = volume_model(3, 4)
     ai = vf / vb
     ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -216,6 +263,10 @@ def main():
                          "speedup_vs_plain_fp64": _r(v.get("speedup_vs_plain_fp64", float("nan")))}
                      for k, v in variants.items()},
     }
+    if not args.quick:
+        rk = run_rk(frmi, torch, "mixed", 64, 4, "fp32", 99, 2e-4)
+        out["mixed_rk4"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rk.items()}
+        print("mixed rk4", json.dumps(out["mixed_rk4"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -92,6 +92,9 @@ class Mesh:
             self.foff[t] = off
             off += self.nelem[t] * self.refs[t].nf
         self.nfpts = off
+        # per flat flux point: element type index and element
+        self.ftype = np.concatenate([np.full(self.nelem[t] * self.refs[t].nf, i) for i, t in enumerate(self.types)])
+        self.felem = np.concatenate([np.repeat(np.arange(self.nelem[t]), self.refs[t].nf) for t in self.types])
         # faces: match by centroid modulo the period, then points within a face pair
         fkeys, finfo, fcent = [], [], []
         Qk = 1 << 24
@@ -123,24 +126,36 @@ class Mesh:
         ucls, inv = np.unique(cls, axis=0, return_inverse=True)
         inv = inv.reshape(-1)
         for ci, (tl, ffl, tr, ffr) in enumerate(ucls):
-            sel = np.nonzero(inv == ci)[0]
+            allsel = np.nonzero(inv == ci)[0]
             tL, tR = self.types[tl], self.types[tr]
             rL, rR = self.refs[tL], self.refs[tR]
             pl = np.nonzero(rL.fface == ffl)[0]
             pr = np.nonzero(rR.fface == ffr)[0]
-            eL, eR = info[fL[sel], 1], info[fR[sel], 1]
-            XL = self.org[tL][eL][:, None, :] + np.einsum("eij,pj->epi", self.J[tL][eL], rL.fpts[pl])
-            XR = self.org[tR][eR][:, None, :] + np.einsum("eij,pj->epi", self.J[tR][eR], rR.fpts[pr])
-            d = XL[:, :, None, :] - XR[:, None, :, :]
-            d -= self.period * np.rint(d / self.period)
-            dist = np.linalg.norm(d, axis=3)
-            j = np.argmin(dist, axis=2)
-            if len(pl) != len(pr) or np.max(np.take_along_axis(dist, j[:, :, None], 2)) > 1e-9 * self.h.min():
-                raise ValueError("flux points of paired faces do not coincide")
-            if np.any(np.sort(j, axis=1) != np.arange(len(pr))[None, :]):
-                raise ValueError("flux-point matching is not one-to-one")
-            iL.append((self.foff[tL] + eL[:, None] * rL.nf + pl[None, :]).reshape(-1))
-            iR.append((self.foff[tR] + eR[:, None] * rR.nf + pr[j]).reshape(-1))
+            for c0 in range(0, len(allsel), 65536):
+                sel = allsel[c0:c0 + 65536]
+                eL, eR = info[fL[sel], 1], info[fR[sel], 1]
+                XL = self.org[tL][eL][:, None, :] + np.einsum("eij,pj->epi", self.J[tL][eL], rL.fpts[pl])
+                XR = self.org[tR][eR][:, None, :] + np.einsum("eij,pj->epi", self.J[tR][eR], rR.fpts[pr])
+                if len(pl) != len(pr):
+                    raise ValueError("paired faces have different point counts")
+                # coordinates relative to each face's centroid coincide for the
+                # two sides (the centroids differ by a period at most): match the
+                # points by the rank of their quantised relative coordinates
+                G, npt = XL.shape[0], XL.shape[1]
+                q = 1e-7 * self.h.min()
+                kL = np.rint((XL - XL.mean(axis=1, keepdims=True)) / q).astype(np.int64).reshape(-1, 3)
+                kR = np.rint((XR - XR.mean(axis=1, keepdims=True)) / q).astype(np.int64).reshape(-1, 3)
+                rows = np.repeat(np.arange(G), npt)
+                oL = np.lexsort((kL[:, 2], kL[:, 1], kL[:, 0], rows)).reshape(G, npt) - (np.arange(G) * npt)[:, None]
+                oR = np.lexsort((kR[:, 2], kR[:, 1], kR[:, 0], rows)).reshape(G, npt) - (np.arange(G) * npt)[:, None]
+                j = np.empty_like(oL)
+                np.put_along_axis(j, oL, oR, axis=1)
+                d = XL - np.take_along_axis(XR, j[:, :, None], axis=1)
+                d -= self.period * np.rint(d / self.period)
+                if np.abs(d).max() > 1e-9 * self.h.min():
+                    raise ValueError("flux points of paired faces do not coincide")
+                iL.append((self.foff[tL] + eL[:, None] * rL.nf + pl[None, :]).reshape(-1))
+                iR.append((self.foff[tR] + eR[:, None] * rR.nf + pr[j]).reshape(-1))
         self.iL, self.iR = np.concatenate(iL), np.concatenate(iR)
         if len(self.iL) * 2 != self.nfpts:
             raise ValueError("flux points left unpaired")

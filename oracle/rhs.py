@@ -119,3 +119,121 @@ def rk4_step(mesh, U, par, dt):
     k3 = rhs(mesh, axpy(0.5 * dt, k2, U), par)
     k4 = rhs(mesh, axpy(dt, k3, U), par)
     return {t: U[t] + (dt / 6.0) * (k1[t] + 2.0 * k2[t] + 2.0 * k3[t] + k4[t]) for t in mesh.types}
+
+
+def rhs_subset(mesh, U, par, sel, dtype=None):
+    """du = R(u) for selected elements only, with the same steps as rhs().
+
+    sel: dict type -> array of element indices.  The RHS of an element needs
+    the face states of its neighbours (for C and the common flux) and the
+    gradients of its neighbours (for the common flux), which in turn need the
+    face states of the neighbours' neighbours; so the disu step runs on the
+    two-hop neighbourhood, con_u/gradients on the one-hop neighbourhood and
+    the anti-aliased volume term only on the selected elements.  Returns
+    dict type -> (len(sel[t]), 5, N_u)."""
+    gas, beta, tau = par.gas, par.beta, par.tau
+    if dtype is None:
+        dtype = U[mesh.types[0]].dtype
+    cast = lambda a: np.asarray(a, dtype=dtype)  # noqa: E731
+    nt = len(mesh.types)
+    ti = {t: i for i, t in enumerate(mesh.types)}
+
+    def fpts_of(t, elems):
+        r = mesh.refs[t]
+        return (mesh.foff[t] + elems[:, None] * r.nf + np.arange(r.nf)[None, :]).reshape(-1)
+
+    def neighbours(sets):
+        out = [set(s) for s in sets]
+        for t in mesh.types:
+            idx = np.array(sorted(sets[ti[t]]), dtype=np.int64)
+            if len(idx) == 0:
+                continue
+            pp = mesh.partner[fpts_of(t, idx)]
+            for tt, ee in zip(mesh.ftype[pp], mesh.felem[pp]):
+                out[tt].add(int(ee))
+        return out
+
+    S0 = [set(int(e) for e in sel.get(t, [])) for t in mesh.types]
+    S1 = neighbours(S0)
+    S2 = neighbours(S1)
+    L0 = [np.array(sorted(s), dtype=np.int64) for s in S0]
+    L1 = [np.array(sorted(s), dtype=np.int64) for s in S1]
+    L2 = [np.array(sorted(s), dtype=np.int64) for s in S2]
+    # flat flux point -> row in the compact S2 face arrays
+    row = np.full(mesh.nfpts, -1, dtype=np.int64)
+    blocks, off = [], 0
+    Up = {}
+    for t in mesh.types:
+        r = mesh.refs[t]
+        e2 = L2[ti[t]]
+        fp = fpts_of(t, e2)
+        row[fp] = off + np.arange(len(fp))
+        off += len(fp)
+        u = cast(U[t][e2]).transpose(0, 2, 1).copy()
+        u[:, :, 4] -= cast(gas.eref)
+        Up[t] = (e2, u)
+        blocks.append(np.einsum("fu,euv->efv", cast(r.M0), u).reshape(-1, 5))  # 1 disu
+    ufa = np.concatenate(blocks) if blocks else np.zeros((0, 5), dtype)
+    Q, Qrow = {}, np.full(mesh.nfpts, -1, dtype=np.int64)
+    qblocks, qoff = [], 0
+    for t in mesh.types:
+        r = mesh.refs[t]
+        e1 = L1[ti[t]]
+        if len(e1) == 0:
+            continue
+        e2, u2 = Up[t]
+        pos = np.searchsorted(e2, e1)
+        u = u2[pos]
+        fp = fpts_of(t, e1)
+        own = ufa[row[fp]].reshape(len(e1), r.nf, 5)
+        nb = ufa[row[mesh.partner[fp]]].reshape(len(e1), r.nf, 5)
+        left = np.zeros(mesh.nfpts, dtype=bool)
+        left[mesh.iL] = True
+        lf = left[fp].reshape(len(e1), r.nf, 1)
+        C = np.where(lf, physics.common_solution(own, nb, beta), physics.common_solution(nb, own, beta))  # 2
+        qt = np.einsum("dsu,euv->edsv", cast(r.Dg), u)  # 3
+        qt += np.einsum("dsf,efv->edsv", cast(r.M6), C - own)  # 4
+        jinv = cast(mesh.Jinv[t][e1])
+        q = np.einsum("edc,edsv->ecsv", jinv, qt)  # 5
+        Q[t] = (e1, q)
+        qblocks.append(np.einsum("fs,ecsv->efcv", cast(r.M0), q).reshape(-1, 3, 5))  # 6
+        Qrow[fp] = qoff + np.arange(len(fp))
+        qoff += len(fp)
+    qfa = np.concatenate(qblocks)
+    out = {}
+    for t in mesh.types:
+        r = mesh.refs[t]
+        e0 = L0[ti[t]]
+        if len(e0) == 0:
+            continue
+        e2, u2 = Up[t]
+        u = u2[np.searchsorted(e2, e0)]
+        e1, q1 = Q[t]
+        q = q1[np.searchsorted(e1, e0)]
+        uq = np.einsum("qu,euv->vqe", cast(r.M7), u)  # 8
+        qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), q)  # 7
+        f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9
+        ft = np.einsum("e,edc,cvqe->edqv", cast(mesh.detJ[t][e0]), cast(mesh.Jinv[t][e0]), f)
+        fu = np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10
+        div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)
+        nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)
+        rt = div - np.einsum("uf,efv->euv", cast(r.M3), nf)
+        fp = fpts_of(t, e0)
+        left = np.zeros(mesh.nfpts, dtype=bool)
+        left[mesh.iL] = True
+        lf = left[fp]
+        pp = mesh.partner[fp]
+        uo, un = ufa[row[fp]], ufa[row[pp]]
+        qo, qn = qfa[Qrow[fp]], qfa[Qrow[pp]]
+        iL = np.where(lf, fp, pp)
+        nL = cast(mesh.fnrm[iL])
+        uL, uR = np.where(lf[:, None], uo, un), np.where(lf[:, None], un, uo)
+        qL, qR = np.where(lf[:, None, None], qo, qn), np.where(lf[:, None, None], qn, qo)
+        F = physics.common_normal_flux(uL.T, uR.T, qL.transpose(1, 2, 0), qR.transpose(1, 2, 0), nL.T, gas, beta,
+                                       tau).T  # 11
+        mag = cast(mesh.fmag[iL])[:, None]
+        D = np.where(lf[:, None], mag * F, -(mag * F)).reshape(len(e0), r.nf, 5)
+        rt = rt + np.einsum("uf,efv->euv", cast(r.M3), D)  # 12
+        du = -rt / cast(mesh.detJ[t][e0])[:, None, None]  # 13
+        out[t] = du.transpose(0, 2, 1).copy()
+    return out

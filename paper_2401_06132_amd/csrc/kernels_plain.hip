@@ -147,12 +147,23 @@ dim3 grid_for(int64_t n) {
   return dim3((unsigned)b);
 }
 
+// host matrix product with extended-precision accumulation (composite
+// operators are rounded to double once)
 void mat_mul(const double* A, int M, int K, const double* B, int64_t N, double* C, double beta, double* out) {
   for (int i = 0; i < M; ++i)
     for (int j = 0; j < N; ++j) {
-      double s = 0;
-      for (int k = 0; k < K; ++k) s += A[i * K + k] * B[k * N + j];
-      out[i * N + j] = (beta != 0 ? beta * C[i * N + j] : 0.0) + s;
+      long double s = 0;
+      for (int k = 0; k < K; ++k) s += (long double)A[i * K + k] * (long double)B[k * N + j];
+      out[i * N + j] = (double)((beta != 0 ? (long double)beta * C[i * N + j] : 0.0L) + s);
+    }
+}
+
+void mat_mul_ld(const long double* A, int M, int K, const double* B, int64_t N, long double* out) {
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < N; ++j) {
+      long double s = 0;
+      for (int k = 0; k < K; ++k) s += A[i * K + k] * (long double)B[k * N + j];
+      out[i * N + j] = s;
     }
 }
 
@@ -176,24 +187,25 @@ void build_plain_ops(const RefElem& r, PlainOps& o) {
         while (face + 1 < r.nfaces && f >= r.face_start[face + 1]) ++face;
         o.M6[(d * nu + s) * nf + f] = r.face_normal[3 * face + d] * r.M3[s * nf + f];
       }
-  std::vector<double> M6M0(3 * nu * nu);
-  mat_mul(o.M6.data(), 3 * nu, nf, r.M0.data(), nu, nullptr, 0.0, M6M0.data());
+  std::vector<long double> M6ld(o.M6.begin(), o.M6.end()), M6M0(3 * nu * nu);
+  mat_mul_ld(M6ld.data(), 3 * nu, nf, r.M0.data(), nu, M6M0.data());
   o.G1.assign(3 * nu * nu, 0.0);
-  for (int k = 0; k < 3 * nu * nu; ++k) o.G1[k] = r.Dg[k] - M6M0[k];
+  for (int k = 0; k < 3 * nu * nu; ++k) o.G1[k] = (double)((long double)r.Dg[k] - M6M0[k]);
   // K = (M1 - M3 M2) M9: for component d, (Dg_d - M3 N_d M0) M8, columns (d, q)
   o.K.assign((size_t)nu * 3 * nq, 0.0);
-  std::vector<double> Ad(nu * nu), NM0(nf * nu), M3NM0(nu * nu), Kd(nu * nq);
+  std::vector<long double> Ad(nu * nu), M3NM0(nu * nu), Kd(nu * nq), M3ld(r.M3.begin(), r.M3.end());
+  std::vector<double> NM0(nf * nu);
   for (int d = 0; d < 3; ++d) {
     for (int f = 0; f < nf; ++f) {
       int face = 0;
       while (face + 1 < r.nfaces && f >= r.face_start[face + 1]) ++face;
       for (int u = 0; u < nu; ++u) NM0[f * nu + u] = r.face_normal[3 * face + d] * r.M0[f * nu + u];
     }
-    mat_mul(r.M3.data(), nu, nf, NM0.data(), nu, nullptr, 0.0, M3NM0.data());
-    for (int k = 0; k < nu * nu; ++k) Ad[k] = r.Dg[(size_t)d * nu * nu + k] - M3NM0[k];
-    mat_mul(Ad.data(), nu, nu, r.M8.data(), nq, nullptr, 0.0, Kd.data());
+    mat_mul_ld(M3ld.data(), nu, nf, NM0.data(), nu, M3NM0.data());
+    for (int k = 0; k < nu * nu; ++k) Ad[k] = (long double)r.Dg[(size_t)d * nu * nu + k] - M3NM0[k];
+    mat_mul_ld(Ad.data(), nu, nu, r.M8.data(), nq, Kd.data());
     for (int s = 0; s < nu; ++s)
-      for (int q = 0; q < nq; ++q) o.K[(size_t)s * 3 * nq + d * nq + q] = Kd[s * nq + q];
+      for (int q = 0; q < nq; ++q) o.K[(size_t)s * 3 * nq + d * nq + q] = (double)Kd[s * nq + q];
   }
 }
 

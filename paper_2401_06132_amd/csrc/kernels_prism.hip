@@ -123,24 +123,60 @@ __global__ void __launch_bounds__(NT_) prism_disu(const double* __restrict__ U, 
 }
 
 // --------------------------------------------------------------- volume
+// LDS per element: region A = state + gradients at the solution points;
+// region B = neighbour face states / jumps, then the triangle-interpolated
+// fields T1, then the line-projected flux Z (after a barrier).  The triangle
+// operator tables are staged in LDS once per workgroup so that every
+// triangle-plane product can run one output point per thread.
+template <int P>
+struct PrismVol {
+  static constexpr int n = P + 1, m = P + 3, NTN = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
+  static constexpr int NU = NTN * n, NFP = n * n;
+  static constexpr int SZ_A = 20 * NU;
+  static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * NTQ, SZ_Z = 15 * NTQ * n;
+  static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
+  static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
+  static constexpr int PER_ELEM = SZ_A + SZ_B;
+};
+
+// sum of a value over an adjacent lane pair (lanes 2i, 2i+1), both lanes get
+// the same bits (addition is commutative)
+__device__ __forceinline__ float pair_sum(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false);
+  return x + __int_as_float(y);
+}
+__device__ __forceinline__ double pair_sum(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return x + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int P, typename R, int EB, int NT_>
 __global__ void __launch_bounds__(NT_)
     prism_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
                  const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
-                 const R* __restrict__ met, const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri,
+                 const R* __restrict__ met, const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g,
                  const Gas<R> g, const double eref, const int E, const int slot_base) {
-  using C = PrismCfg<P>;
-  constexpr int n = C::n, m = C::m, NT = C::NT, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  using C = PrismVol<P>;
+  constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
+  __shared__ PrismTri<P, R> tri;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   const int tid = threadIdx.x, e0 = blockIdx.x * EB;
-#define XS(le) (smem + (le)*PE)            /* [20][NU]              */
-#define JS(le) (smem + (le)*PE + C::SZ_X)  /* [5][5][NFP]           */
-#define ZS(le) (smem + (le)*PE)            /* [3][5][NTQ][n]        */
-#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][NTQ]          */
-  const int fnp[5] = {NT, NT, NFP, NFP, NFP};
+#define XS(le) (smem + (le)*PE)            /* [20][NU]                 */
+#define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
+#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][NTQ]             */
+#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][NTQ][n]           */
 
-  // phase 0: state, metrics, neighbour face states
+  // phase 0: operator tables, state (reference form), metrics, neighbour states
+  {
+    constexpr int NW = sizeof(PrismTri<P, R>) / sizeof(R);
+    const R* src = reinterpret_cast<const R*>(tri_g);
+    R* dst = reinterpret_cast<R*>(&tri);
+    for (int it = tid; it < NW; it += NT_) dst[it] = src[it];
+  }
   for (int it = tid; it < EB * 5 * NU; it += NT_) {
     const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
     R val = R(0);
@@ -159,107 +195,94 @@ __global__ void __launch_bounds__(NT_)
     const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
     const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP, e = e0 + le;
     R val = R(0);
-    if (e < E && r < fnp[f]) {
+    if (e < E && (f >= 2 || r < NTN)) {
       const FaceRec fr = faces[slot_base + e * 5 + f];
-      const int rr = perms[(fr.info >> 1) * NFP + r];
-      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + perms[(fr.info >> 1) * NFP + r]];
     }
     JS(le)[r0] = val;
   }
   __syncthreads();
 
-  // phase 1: own face values and jumps (eq. FR-conu)
-  for (int it = tid; it < EB * 5 * (NT + n); it += NT_) {
-    const int le = it / (5 * (NT + n)), r0 = it - le * (5 * (NT + n)), e = e0 + le;
-    if (e >= E) continue;
+  // phase 1: jumps C - u^f (eq. FR-conu) at every own flux point, in place
+  // over the neighbour values: triangle faces (line interpolation in zeta),
+  // quadrilateral faces (triangle-plane interpolation to the edge point)
+  constexpr int NJ_TRI = 5 * NTN, NJ_QUAD = 5 * 3 * n * n;
+  for (int it = tid; it < EB * (NJ_TRI + NJ_QUAD); it += NT_) {
+    const int le = it / (NJ_TRI + NJ_QUAD), r0 = it - le * (NJ_TRI + NJ_QUAD), e = e0 + le;
     const R* X = XS(le);
-    if (r0 < 5 * NT) {
-      const int v = r0 / NT, t = r0 - v * NT;
+    if (r0 < NJ_TRI) {
+      const int v = r0 / NTN, t = r0 - v * NTN;
       R xm = R(0), xp = R(0);
 #pragma unroll
       for (int k = 0; k < n; ++k) {
-        const R x = X[v * NU + t + NT * k];
+        const R x = X[v * NU + t + NTN * k];
         xm += op.lb[k] * x;
         xp += op.rb[k] * x;
       }
-#pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        const int info = faces[slot_base + e * 5 + sg].info;
-        const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
-        R* jj = JS(le) + (sg * 5 + v) * NFP + t;
-        *jj = coef * (*jj - (sg ? xp : xm));
+      int im = 0, ip = 0;
+      if (e < E) {
+        im = faces[slot_base + e * 5].info;
+        ip = faces[slot_base + e * 5 + 1].info;
       }
+      R* jm = JS(le) + (0 * 5 + v) * NFP + t;
+      R* jp = JS(le) + (1 * 5 + v) * NFP + t;
+      *jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jm - xm);
+      *jp = ((ip & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jp - xp);
     } else {
-      const int r1 = r0 - 5 * NT, v = r1 / n, k = r1 - v * n;
-      R x[NT];
+      const int r1 = r0 - NJ_TRI, v = r1 / (3 * n * n), r2 = r1 - v * (3 * n * n), ed = r2 / (n * n);
+      const int r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
+      R s = R(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) x[t] = X[v * NU + t + NT * k];
-#pragma unroll
-      for (int ed = 0; ed < 3; ++ed) {
-        const int info = faces[slot_base + e * 5 + 2 + ed].info;
-        const R coef = (info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-          R s = R(0);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * x[t];
-          R* jj = JS(le) + ((2 + ed) * 5 + v) * NFP + i + n * k;
-          *jj = coef * (*jj - s);
-        }
-      }
+      for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * X[v * NU + t + NTN * k];
+      const int info = e < E ? faces[slot_base + e * 5 + 2 + ed].info : 0;
+      R* jj = JS(le) + ((2 + ed) * 5 + v) * NFP + i + n * k;
+      *jj = ((info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jj - s);
     }
   }
   __syncthreads();
 
-  // phase 2: corrected reference gradient (eq. FR-qfinal): zeta along lines,
-  // (xi, eta) per triangle plane with the edge lifting
-  for (int it = tid; it < EB * 5 * (NT + n); it += NT_) {
-    const int le = it / (5 * (NT + n)), r0 = it - le * (5 * (NT + n));
+  // phase 2: corrected reference gradient (eq. FR-qfinal): zeta along the
+  // lines with the triangle-face lifting; (xi, eta) per output point with the
+  // triangle derivative blocks and the quadrilateral-face lifting
+  constexpr int NG_Z = 5 * NTN, NG_T = 5 * n * NTN;
+  for (int it = tid; it < EB * (NG_Z + NG_T); it += NT_) {
+    const int le = it / (NG_Z + NG_T), r0 = it - le * (NG_Z + NG_T);
     R* X = XS(le);
     const R* J = JS(le);
-    if (r0 < 5 * NT) {
-      const int v = r0 / NT, t = r0 - v * NT;
+    if (r0 < NG_Z) {
+      const int v = r0 / NTN, t = r0 - v * NTN;
       R x[n];
 #pragma unroll
-      for (int k = 0; k < n; ++k) x[k] = X[v * NU + t + NT * k];
+      for (int k = 0; k < n; ++k) x[k] = X[v * NU + t + NTN * k];
       const R jm = J[(0 * 5 + v) * NFP + t], jp = J[(1 * 5 + v) * NFP + t];
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         R s = op.liftR[k] * jp - op.liftL[k] * jm;
 #pragma unroll
         for (int c = 0; c < n; ++c) s += op.D[k][c] * x[c];
-        X[(5 + 2 * 5 + v) * NU + t + NT * k] = s;
+        X[(15 + v) * NU + t + NTN * k] = s;
       }
     } else {
-      const int r1 = r0 - 5 * NT, v = r1 / n, k = r1 - v * n;
-      R x[NT], je[3][n];
+      const int r1 = r0 - NG_Z, v = r1 / (n * NTN), r2 = r1 - v * (n * NTN), k = r2 / NTN, t = r2 - k * NTN;
+      R sx = R(0), sy = R(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) x[t] = X[v * NU + t + NT * k];
-#pragma unroll
-      for (int ed = 0; ed < 3; ++ed)
-#pragma unroll
-        for (int i = 0; i < n; ++i) je[ed][i] = J[((2 + ed) * 5 + v) * NFP + i + n * k];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        R sx = R(0), sy = R(0);
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-          sx += tri->Dxi[t][c] * x[c];
-          sy += tri->Deta[t][c] * x[c];
-        }
-#pragma unroll
-        for (int ed = 0; ed < 3; ++ed) {
-          R nx, ny;
-          edge_normal<R>(ed, nx, ny);
-          R l = R(0);
-#pragma unroll
-          for (int i = 0; i < n; ++i) l += tri->LiftEdge[ed][t][i] * je[ed][i];
-          sx += nx * l;
-          sy += ny * l;
-        }
-        X[(5 + 0 * 5 + v) * NU + t + NT * k] = sx;
-        X[(5 + 1 * 5 + v) * NU + t + NT * k] = sy;
+      for (int c = 0; c < NTN; ++c) {
+        const R x = X[v * NU + c + NTN * k];
+        sx += tri.Dxi[t][c] * x;
+        sy += tri.Deta[t][c] * x;
       }
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed) {
+        R nx, ny;
+        edge_normal<R>(ed, nx, ny);
+        R l = R(0);
+#pragma unroll
+        for (int i = 0; i < n; ++i) l += tri.LiftEdge[ed][t][i] * J[((2 + ed) * 5 + v) * NFP + i + n * k];
+        sx += nx * l;
+        sy += ny * l;
+      }
+      X[(5 + v) * NU + t + NTN * k] = sx;
+      X[(10 + v) * NU + t + NTN * k] = sy;
     }
   }
   __syncthreads();
@@ -279,121 +302,122 @@ __global__ void __launch_bounds__(NT_)
   __syncthreads();
 
   // phase 4a: normal viscous flux at own flux points (gradcoru_fpts)
-  // phase 4b: triangle-plane interpolation of the 20 fields to the
-  //           triangle quadrature points (first factor of M7 / M10)
-  constexpr int NI_TRI = NT, NI_QUAD = 3 * n, NI_SW = 20 * n;
-  for (int it = tid; it < EB * (NI_TRI + NI_QUAD + NI_SW); it += NT_) {
-    if (it < EB * (NI_TRI + NI_QUAD)) {
-      const int le = it / (NI_TRI + NI_QUAD), r0 = it - le * (NI_TRI + NI_QUAD), e = e0 + le;
-      if (e >= E) continue;
-      const R* X = XS(le);
-      if (r0 < NI_TRI) {
-        const int t = r0;
-        R fm[20], fp[20];
+  constexpr int NV_TRI = NTN, NV_QUAD = 3 * n * n;
+  for (int it = tid; it < EB * (NV_TRI + NV_QUAD); it += NT_) {
+    const int le = it / (NV_TRI + NV_QUAD), r0 = it - le * (NV_TRI + NV_QUAD), e = e0 + le;
+    if (e >= E) continue;
+    const R* X = XS(le);
+    if (r0 < NV_TRI) {
+      const int t = r0;
+      R fm[20], fp[20];
 #pragma unroll
-        for (int fld = 0; fld < 20; ++fld) {
-          R sm = R(0), sp = R(0);
+      for (int fld = 0; fld < 20; ++fld) {
+        R sm = R(0), sp = R(0);
 #pragma unroll
-          for (int k = 0; k < n; ++k) {
-            const R x = X[fld * NU + t + NT * k];
-            sm += op.lb[k] * x;
-            sp += op.rb[k] * x;
-          }
-          fm[fld] = sm;
-          fp[fld] = sp;
+        for (int k = 0; k < n; ++k) {
+          const R x = X[fld * NU + t + NTN * k];
+          sm += op.lb[k] * x;
+          sp += op.rb[k] * x;
         }
+        fm[fld] = sm;
+        fp[fld] = sp;
+      }
 #pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-          const R* w = sg ? fp : fm;
-          const int slot = slot_base + e * 5 + sg;
-          const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
-          const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
-          R u[5], q[3][5], V[4];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            u[v] = w[v];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
-          }
-          normal_viscous(u, q, nn, g, V);
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + t] = V[kk];
-        }
-      } else {
-        const int r1 = r0 - NI_TRI, ed = r1 / n, k = r1 - ed * n;
-        const int slot = slot_base + e * 5 + 2 + ed;
+      for (int sg = 0; sg < 2; ++sg) {
+        const R* w = sg ? fp : fm;
+        const int slot = slot_base + e * 5 + sg;
         const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
         const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
-        // edge values of the 20 fields on plane k, one edge point at a time
-        for (int i = 0; i < n; ++i) {
-          R w[20];
+        R u[5], q[3][5], V[4];
 #pragma unroll
-          for (int fld = 0; fld < 20; ++fld) {
-            R s = R(0);
+        for (int v = 0; v < 5; ++v) {
+          u[v] = w[v];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * X[fld * NU + t + NT * k];
-            w[fld] = s;
-          }
-          R u[5], q[3][5], V[4];
-#pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            u[v] = w[v];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
-          }
-          normal_viscous(u, q, nn, g, V);
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
+          for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
         }
+        normal_viscous(u, q, nn, g, V);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + t] = V[kk];
       }
     } else {
-      const int i2 = it - EB * (NI_TRI + NI_QUAD);
-      const int le = i2 / NI_SW, r0 = i2 - le * NI_SW, fld = r0 / n, k = r0 - fld * n;
-      R x[NT];
+      const int r1 = r0 - NV_TRI, ed = r1 / (n * n), r2 = r1 - ed * (n * n), k = r2 / n, i = r2 - k * n;
+      const int slot = slot_base + e * 5 + 2 + ed;
+      const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+      R u[5], q[3][5], V[4];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) x[t] = XS(le)[fld * NU + t + NT * k];
-#pragma unroll
-      for (int tq = 0; tq < NTQ; ++tq) {
+      for (int fld = 0; fld < 20; ++fld) {
         R s = R(0);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) s += tri->Tq[tq][t] * x[t];
-        TS(le)[(fld * n + k) * NTQ + tq] = s;
+        for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * X[fld * NU + t + NTN * k];
+        if (fld < 5)
+          u[fld] = s;
+        else
+          q[(fld - 5) / 5][(fld - 5) % 5] = s;
       }
+      normal_viscous(u, q, nn, g, V);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
     }
+  }
+  // phase 4b: triangle-plane interpolation of the 20 fields to the triangle
+  // quadrature points (first factor of M7 / M10), one output per thread
+  for (int it = tid; it < EB * 20 * n * NTQ; it += NT_) {
+    const int le = it / (20 * n * NTQ), r0 = it - le * (20 * n * NTQ);
+    const int fk = r0 / NTQ, tq = r0 - fk * NTQ, fld = fk / n, k = fk - fld * n;
+    const R* x = XS(le) + fld * NU + NTN * k;
+    R s = R(0);
+#pragma unroll
+    for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * x[t];
+    TS(le)[r0] = s;  // [fld][k][tq]
   }
   __syncthreads();
 
-  // phase 5: line columns over the triangle quadrature points: zeta
-  // interpolation, flux (tdisf) and the line part of the projection-divergence
-  for (int it = tid; it < EB * NTQ; it += NT_) {
-    const int le = it / NTQ, tq = it - le * NTQ;
-    const R* T = TS(le);
+  // phase 5: line columns over the triangle quadrature points, two threads
+  // per column (alternate zeta levels): zeta interpolation, flux (tdisf) and
+  // the line part of the projection-divergence; the pair sum completes it
+  const bool col = tid < 2 * EB * NTQ;
+  const int cc = tid >> 1, half = tid & 1, cle = cc / NTQ, ctq = cc - cle * NTQ;
+  R acc[3][5][n];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc[d][v][k] = R(0);
+  if (col) {
+    const R* T = TS(cle);
     R t1[20][n];
 #pragma unroll
     for (int fld = 0; fld < 20; ++fld)
 #pragma unroll
-      for (int k = 0; k < n; ++k) t1[fld][k] = T[(fld * n + k) * NTQ + tq];
+      for (int k = 0; k < n; ++k) t1[fld][k] = T[(fld * n + k) * NTQ + ctq];
     R S[3][3];
-    const R dj = sMet[le][9];
+    const R dj = sMet[cle][9];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[le][3 * d + c];
-    R acc[3][5][n];
+      for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[cle][3 * d + c];
+    // thread `half` takes zeta level kq = 2j + half; the operator entries are
+    // selected per lane (no divergent branch); for odd m the surplus level of
+    // the odd thread repeats level 2j with zero projection weights
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int j = 0; j < (m + 1) / 2; ++j) {
+      const int k0 = 2 * j, k1 = 2 * j + 1 < m ? 2 * j + 1 : 2 * j;
+      const bool has1 = 2 * j + 1 < m;
+      R wI[n], wP[n], wA[n];
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-#pragma unroll
-        for (int k = 0; k < n; ++k) acc[d][v][k] = R(0);
-#pragma unroll
-    for (int kq = 0; kq < m; ++kq) {
+      for (int k = 0; k < n; ++k) {
+        wI[k] = half ? op.I[k1][k] : op.I[k0][k];
+        wP[k] = half ? (has1 ? op.Pj[k][k1] : R(0)) : op.Pj[k][k0];
+        wA[k] = half ? (has1 ? op.AP[k][k1] : R(0)) : op.AP[k][k0];
+      }
       R u[5], q[3][5], f[3][5];
 #pragma unroll
       for (int fld = 0; fld < 20; ++fld) {
         R s = R(0);
 #pragma unroll
-        for (int k = 0; k < n; ++k) s += op.I[kq][k] * t1[fld][k];
+        for (int k = 0; k < n; ++k) s += wI[k] * t1[fld][k];
         if (fld < 5)
           u[fld] = s;
         else
@@ -406,42 +430,47 @@ __global__ void __launch_bounds__(NT_)
         for (int v = 0; v < 5; ++v) {
           const R ft = S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
 #pragma unroll
-          for (int k = 0; k < n; ++k) acc[d][v][k] += (d == 2 ? op.AP[k][kq] : op.Pj[k][kq]) * ft;
+          for (int k = 0; k < n; ++k) acc[d][v][k] += (d == 2 ? wA[k] : wP[k]) * ft;
         }
     }
-    R* Z = ZS(le);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int k = 0; k < n; ++k) acc[d][v][k] = pair_sum(acc[d][v][k]);
+  __syncthreads();  // every column has read T1; Z may now overwrite it
+  if (col) {
+    R* Z = ZS(cle);
+    // both threads of a pair hold the same sums; each writes half the values
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int k = 0; k < n; ++k) Z[((d * 5 + v) * NTQ + tq) * n + k] = acc[d][v][k];
+        for (int k = 0; k < n; ++k)
+          if (((d * 5 + v) * n + k) % 2 == half) Z[((d * 5 + v) * NTQ + ctq) * n + k] = acc[d][v][k];
   }
   __syncthreads();
 
-  // phase 6: triangle-plane projection-divergence, per solution level
-  for (int it = tid; it < EB * 5 * n; it += NT_) {
-    const int le = it / (5 * n), r0 = it - le * (5 * n), v = r0 / n, k = r0 - v * n, e = e0 + le;
+  // phase 6: triangle-plane projection-divergence, one output point per thread
+  for (int it = tid; it < EB * 5 * n * NTN; it += NT_) {
+    const int le = it / (5 * n * NTN), r0 = it - le * (5 * n * NTN);
+    const int v = r0 / (n * NTN), r1 = r0 - v * (n * NTN), k = r1 / NTN, t = r1 - k * NTN, e = e0 + le;
     if (e >= E) continue;
     const R* Z = ZS(le);
-    R out[NT];
+    R s = R(0);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) out[t] = R(0);
-#pragma unroll
-    for (int tq = 0; tq < NTQ; ++tq) {
-      const R zx = Z[((0 * 5 + v) * NTQ + tq) * n + k];
-      const R zy = Z[((1 * 5 + v) * NTQ + tq) * n + k];
-      const R zz = Z[((2 * 5 + v) * NTQ + tq) * n + k];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) out[t] += tri->APxi[t][tq] * zx + tri->APeta[t][tq] * zy + tri->PT[t][tq] * zz;
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) Rp[(size_t)e * 5 * NU + v * NU + t + NT * k] = out[t];
+    for (int tq = 0; tq < NTQ; ++tq)
+      s += tri.APxi[t][tq] * Z[((0 * 5 + v) * NTQ + tq) * n + k] + tri.APeta[t][tq] * Z[((1 * 5 + v) * NTQ + tq) * n + k] +
+           tri.PT[t][tq] * Z[((2 * 5 + v) * NTQ + tq) * n + k];
+    Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = s;
   }
 #undef XS
 #undef JS
-#undef ZS
 #undef TS
+#undef ZS
 }
 
 // -------------------------------------------------------------- surface
@@ -591,6 +620,18 @@ static Gas<R> make_gas_p(const GasHost& g) {
   return o;
 }
 
+// launch shapes of the volume kernel: two threads per quadrature column
+template <int P, bool DBL>
+struct PrismLaunch;
+template <> struct PrismLaunch<1, false> { static constexpr int EB = 8, NT = 64; };   // 64 column threads
+template <> struct PrismLaunch<2, false> { static constexpr int EB = 7, NT = 128; };  // 126
+template <> struct PrismLaunch<3, false> { static constexpr int EB = 4, NT = 128; };  // 128
+template <> struct PrismLaunch<4, false> { static constexpr int EB = 2, NT = 128; };  // 100
+template <> struct PrismLaunch<1, true> { static constexpr int EB = 8, NT = 64; };
+template <> struct PrismLaunch<2, true> { static constexpr int EB = 3, NT = 64; };    // 54
+template <> struct PrismLaunch<3, true> { static constexpr int EB = 2, NT = 64; };    // 64
+template <> struct PrismLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 50
+
 template <int P, typename R>
 static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   const PrismOps<P, R> op = make_prism_ops<P, R>(*a.ops);
@@ -599,7 +640,7 @@ static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   const int E = (int)a.E;
   if (E == 0) return hipSuccess;
   constexpr bool dbl = sizeof(R) == 8;
-  constexpr int EB = dbl ? 2 : 4, NT = EB * 64;
+  constexpr int EB = PrismLaunch<P, dbl>::EB, NT = PrismLaunch<P, dbl>::NT;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   const int sb = (int)a.slot_base;
   if (a.stage & 1) {

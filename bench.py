@@ -150,6 +150,83 @@ def run_rk(frmi, torch, kind, n, p, prec, nsteps, dt):
     return out
 
 
+def serving_dt(n, p, kind, u0=1.0, c0=10.0):
+    """RK4 step of a serving request: 0.25 h / ((2p+1)(U0 + c0)), h the cell
+    size, c0 = 1/Ma (the same bound for hexahedra and prisms; twice this
+    step is unstable on hexahedra)."""
+    h = 2 * np.pi / n
+    return 0.25 * h / ((2 * p + 1) * (u0 + c0))
+
+
+def run_serving(frmi, torch, budget_gib=64.0, max_active=64, nreq=512, seed=0, check_every=64):
+    """The serving stream: requests arrive by their Poisson schedule (wall
+    clock), are queued, admitted by device footprint and slot limit, and
+    advanced together one RK4 step per pool round until done.  Step latency
+    = wall time of one pool round that advanced at least one request."""
+    from paper_2401_06132_amd import inputs
+    reqs = inputs.serving_requests(n=nreq, seed=seed)
+    budget = int(budget_gib * (1 << 30))
+    pool = frmi.Pool(budget, max_active=max_active, prec="fp32", pref=inputs.P0)
+    outs, t_arr, t_adm, t_fin, dof_req = {}, {}, {}, {}, {}
+    step_ms, step_dof, active, launches = [], [], [], []
+    peak_bytes, nxt, done, work = 0, 0, 0, 0
+    t0 = time.perf_counter()
+    last_print = t0
+    while done < nreq:
+        now = time.perf_counter() - t0
+        while nxt < nreq and reqs[nxt]["arrival"] <= now:
+            r = reqs[nxt]
+            kw = dict(n=r["n"], p=r["p"], kind=r["etype"], nsteps=r["steps"],
+                      dt=serving_dt(r["n"], r["p"], r["etype"]), tgv_p0=inputs.P0)
+            if r["id"] % check_every == 0:
+                kw["u_out"] = np.empty(pool.footprint(**kw)[1])
+            rid = pool.submit(**kw)
+            if "u_out" in kw:
+                outs[rid] = kw["u_out"]
+            t_arr[rid] = r["arrival"]
+            dof_req[rid] = pool.footprint(**kw)[1]
+            nxt += 1
+        ts = time.perf_counter()
+        st, adm, fin = pool.step()
+        te = time.perf_counter()
+        for i in adm:
+            t_adm[i] = te - t0
+        for i in fin:
+            t_fin[i] = te - t0
+        done += len(fin)
+        peak_bytes = max(peak_bytes, st["bytes_in_use"])
+        if st["n_active"] > 0:
+            step_ms.append((te - ts) * 1e3)
+            step_dof.append(st["dof"])
+            active.append(st["n_active"])
+            launches.append(st["n_launches"])
+            work += 4 * st["dof"]
+        elif st["n_queued"] == 0 and not adm and nxt < nreq:
+            time.sleep(max(0.0, reqs[nxt]["arrival"] - (time.perf_counter() - t0)))
+        if te - last_print > 10:
+            last_print = te
+            print("serving: t=%.1fs done=%d submitted=%d active=%d queued=%d" %
+                  (te - t0, done, nxt, st["n_active"], st["n_queued"]), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    lat = np.array([t_fin[i] - t_arr[i] for i in t_fin])
+    wait = np.array([t_adm[i] - t_arr[i] for i in t_adm])
+    finite = all(bool(np.isfinite(o).all()) for o in outs.values())
+    sm = np.array(step_ms)
+    return {
+        "workload": "%d Taylor-Green requests, Poisson arrivals (mean %.0f/s), n^3 boxes n in 6..32, hex|prism, "
+                    "p in {2,3,4}, 20-200 RK4 steps, fp32 fused" % (nreq, 200.0),
+        "budget_GiB": budget_gib, "max_active": max_active, "requests": nreq, "wall_s": wall,
+        "rounds": len(step_ms), "p50_step_ms": float(np.percentile(sm, 50)),
+        "p99_step_ms": float(np.percentile(sm, 99)), "max_step_ms": float(sm.max()),
+        "gdof_rhs_s": work / wall / 1e9, "gdof_rhs_s_busy": work / (sm.sum() * 1e-3) / 1e9,
+        "mean_active": float(np.mean(active)), "max_active_seen": int(max(active)),
+        "mean_launches_per_step": float(np.mean(launches)), "peak_GiB": peak_bytes / (1 << 30),
+        "p50_request_latency_s": float(np.percentile(lat, 50)), "p99_request_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_wait_s": float(np.percentile(wait, 50)), "p99_queue_wait_s": float(np.percentile(wait, 99)),
+        "checked_finite": len(outs), "finite": finite,
+    }
+
+
 def cpu_baseline(budget_s=20.0):
     """The oracle (plain NumPy, dense operators) on the host: one RHS of the
     same Taylor-Green hex p=3 workload on a smaller periodic box; the box is
@@ -187,6 +264,11 @@ def main():
     ap.add_argument("--n", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline variant only")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving stream")
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +286,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
+    if args.serving_only:
+        sv = run_serving(frmi, torch, args.serving_budget_gib, args.serving_slots, args.serving_requests)
+        print(json.dumps({"serving": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sv.items()}}),
+              flush=True)
         return
     variants = {}
     order = [("fp32", 3, "fused", "hex")] if args.quick else [
@@ -267,6 +354,10 @@ def main():
         rk = run_rk(frmi, torch, "mixed", 64, 4, "fp32", 99, 2e-4)
         out["mixed_rk4"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rk.items()}
         print("mixed rk4", json.dumps(out["mixed_rk4"]), file=sys.stderr, flush=True)
+    if not args.quick and not args.no_serving:
+        sv = run_serving(frmi, torch, args.serving_budget_gib, args.serving_slots, args.serving_requests)
+        out["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sv.items()}
+        print("serving", json.dumps(out["serving"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -167,6 +167,92 @@ fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_
 const char* fr_last_error(const fr_ctx* c);
 void fr_destroy(fr_ctx* c);
 
+/* ------------------------------------------------------------------------
+ * Serving pool: continuous batching of independent solves.
+ *
+ * A pool holds many periodic-box solves (requests) on one GPU.  Requests are
+ * queued in submission order and admitted, strictly in that order, while
+ * their device footprint fits the pool's byte budget and fewer than
+ * max_active requests are admitted.  Each fr_pool_step advances every
+ * admitted request by one classical RK4 step of its own dt, with one kernel
+ * launch per (element type, order, kernel, RK stage) covering the elements of
+ * all of them; the arithmetic applied to each element is the one of
+ * fr_rk4_step, so a request's result does not depend on what else shares the
+ * pool.  A request leaves the pool after its last step; its final state is
+ * copied to u_out (if given) and its memory is reused by later admissions.
+ * The RHS is the fused form of section 6.1 at the pool's precision; the
+ * Taylor-Green initial condition is the test case of section 7.2.
+ * ---------------------------------------------------------------------- */
+typedef struct fr_pool fr_pool;
+
+typedef struct {
+  int nx, ny, nz;        /* cells of the periodic box [lo,hi]^3 */
+  double lo, hi;
+  int p;                 /* order 1..4 */
+  int kind;              /* fr_mesh_kind */
+  double dt;             /* RK4 step size */
+  int nsteps;            /* RK4 steps to run (>= 0) */
+  const double* u_init;  /* host, n_state doubles in library layout, or NULL:
+                            Taylor-Green vortex with rho0 = U0 = 1 and mean
+                            pressure tgv_p0.  Read when the request is
+                            admitted: keep it valid until fr_pool_query
+                            reports the request active or done. */
+  double tgv_p0;
+  double* u_out;         /* host, n_state doubles receiving the final state,
+                            or NULL.  Written inside the fr_pool_step that
+                            completes the request. */
+} fr_request;
+
+typedef struct {
+  int n_active;          /* requests advanced by this step */
+  int n_admitted;        /* requests admitted by this call (first step next call) */
+  int n_finished;        /* requests completed by this call */
+  int n_queued;          /* requests waiting after this call */
+  int n_launches;        /* kernel launches enqueued for the step */
+  int64_t dof;           /* degrees of freedom advanced: sum of n_state */
+  int64_t bytes_in_use;  /* device bytes held by admitted requests */
+} fr_pool_stats;
+
+/* Create a pool.  ph: physics and precision shared by all requests (form
+ * must be FR_FORM_FUSED).  hip_stream: stream for all pool work, or NULL.
+ * budget_bytes: device memory for request data, allocated as one block by
+ * the first fr_pool_step (no device call is made before).  max_active:
+ * slot limit.  Errors: FR_EINVAL, FR_EUNSUPPORTED (plain form). */
+fr_status fr_pool_create(const fr_physics* ph, void* hip_stream, int64_t budget_bytes, int max_active,
+                         fr_pool** out);
+
+/* Device bytes a request occupies while admitted, and its state size in
+ * doubles.  Host only.  Errors: FR_EINVAL / FR_EUNSUPPORTED for a bad
+ * request (as fr_pool_submit). */
+fr_status fr_pool_footprint(const fr_pool* pool, const fr_request* r, int64_t* bytes, int64_t* n_state);
+
+/* Queue a request; *id receives its handle (0, 1, 2, ... in submission
+ * order).  The request is copied.  Host only.  Errors: FR_EINVAL (bad
+ * sizes, nsteps < 0, neither u_init nor tgv_p0 > 0), FR_EUNSUPPORTED (p
+ * outside 1..4), FR_ENOMEM (footprint above the whole budget: it could
+ * never be admitted). */
+fr_status fr_pool_submit(fr_pool* pool, const fr_request* r, int64_t* id);
+
+/* One scheduling round: enqueue one RK4 step of every admitted request, then
+ * admit queued requests (host mesh set-up overlaps the GPU work), wait for
+ * the stream, and retire requests that completed their steps.  Synchronous.
+ * stats may be NULL.  After FR_EDEVICE the pool is unusable: destroy it. */
+fr_status fr_pool_step(fr_pool* pool, fr_pool_stats* stats);
+
+/* Ids admitted and finished by the last fr_pool_step (arrays of cap
+ * entries, either may be NULL; counts always written).  FR_EINVAL if a list
+ * does not fit. */
+fr_status fr_pool_events(const fr_pool* pool, int64_t* admitted, int* n_admitted, int64_t* finished,
+                         int* n_finished, int cap);
+
+/* Status of a request: 0 queued, 1 admitted, 2 done; steps completed.
+ * FR_EINVAL for an unknown id. */
+fr_status fr_pool_query(const fr_pool* pool, int64_t id, int* status, int* steps_done);
+
+const char* fr_pool_last_error(const fr_pool* pool);
+/* Synchronises the pool stream and frees all device memory of the pool. */
+void fr_pool_destroy(fr_pool* pool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,13 +26,27 @@ _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "
 # every symbol the header declares
 SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_upts_coords", "fr_rhs", "fr_rhs_stages",
            "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
-           "fr_last_error", "fr_destroy"]
+           "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
+           "fr_pool_events", "fr_pool_query", "fr_pool_last_error", "fr_pool_destroy"]
 
 
 class FrPhysics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
                 ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("pref", ctypes.c_double),
                 ("prec", ctypes.c_int), ("form", ctypes.c_int)]
+
+
+class FrRequest(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("p", ctypes.c_int), ("kind", ctypes.c_int), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int), ("u_init", ctypes.c_void_p), ("tgv_p0", ctypes.c_double),
+                ("u_out", ctypes.c_void_p)]
+
+
+class FrPoolStats(ctypes.Structure):
+    _fields_ = [("n_active", ctypes.c_int), ("n_admitted", ctypes.c_int), ("n_finished", ctypes.c_int),
+                ("n_queued", ctypes.c_int), ("n_launches", ctypes.c_int), ("dof", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64)]
 
 
 class FrError(RuntimeError):
@@ -68,6 +82,14 @@ def load_library(path=None):
         "fr_connectivity": (I, [P, P, P, ctypes.POINTER(I64)]),
         "fr_last_error": (ctypes.c_char_p, [P]),
         "fr_destroy": (None, [P]),
+        "fr_pool_create": (I, [ctypes.POINTER(FrPhysics), P, I64, I, ctypes.POINTER(P)]),
+        "fr_pool_footprint": (I, [P, ctypes.POINTER(FrRequest), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "fr_pool_submit": (I, [P, ctypes.POINTER(FrRequest), ctypes.POINTER(I64)]),
+        "fr_pool_step": (I, [P, ctypes.POINTER(FrPoolStats)]),
+        "fr_pool_events": (I, [P, P, ctypes.POINTER(I), P, ctypes.POINTER(I), I]),
+        "fr_pool_query": (I, [P, I64, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "fr_pool_last_error": (ctypes.c_char_p, [P]),
+        "fr_pool_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -91,9 +113,10 @@ def ref_operator(etype, p, name):
     return out
 
 
-def _check(ctx, st):
+def _check(ctx, st, pool=False):
     if st != 0:
-        msg = load_library().fr_last_error(ctx).decode() if ctx else ""
+        lib = load_library()
+        msg = (lib.fr_pool_last_error(ctx) if pool else lib.fr_last_error(ctx)).decode() if ctx else ""
         raise FrError("%s: %s" % (_STATUS.get(st, st), msg))
 
 
@@ -197,3 +220,83 @@ class Solver:
         out = np.empty(5)
         _check(self.ctx, self.lib.fr_integrals(self.ctx, out.ctypes.data))
         return out
+
+
+class Pool:
+    """Serving pool (fr_pool_*): continuous batching of independent solves.
+
+    submit() queues a periodic-box request; step() runs one scheduling round
+    (one RK4 step of every admitted request in shared launches, admissions by
+    device footprint, retirement).  Host buffers given as u_init / u_out are
+    kept referenced here until the request is done.
+    """
+
+    QUEUED, ACTIVE, DONE = 0, 1, 2
+
+    def __init__(self, budget_bytes, max_active=64, prec="fp32", stream=None, **phys):
+        self.lib = load_library()
+        ph = physics(prec=prec, form="fused", **phys)
+        c = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(stream)
+        _check(None, self.lib.fr_pool_create(ctypes.byref(ph), st, int(budget_bytes), int(max_active),
+                                             ctypes.byref(c)))
+        self.pool = c
+        self._keep = {}
+
+    def __del__(self):
+        if getattr(self, "pool", None):
+            self.lib.fr_pool_destroy(self.pool)
+            self.pool = None
+
+    @staticmethod
+    def request(n, p, kind="hex", nsteps=1, dt=1e-4, lo=-np.pi, hi=np.pi, u_init=None, tgv_p0=0.0, u_out=None):
+        nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+        return FrRequest(nx, ny, nz, lo, hi, p, MESH_KIND[kind], dt, nsteps,
+                         None if u_init is None else u_init.ctypes.data, tgv_p0,
+                         None if u_out is None else u_out.ctypes.data)
+
+    def footprint(self, **req):
+        r = self.request(**req)
+        b, ns = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.pool, self.lib.fr_pool_footprint(self.pool, ctypes.byref(r), ctypes.byref(b), ctypes.byref(ns)),
+               pool=True)
+        return b.value, ns.value
+
+    def submit(self, **req):
+        """Queue a request; returns its id.  u_init / u_out: float64 numpy
+        arrays of n_state entries (library layout) or None."""
+        for k in ("u_init", "u_out"):
+            a = req.get(k)
+            if a is not None and (not isinstance(a, np.ndarray) or a.dtype != np.float64 or
+                                  not a.flags.c_contiguous):
+                raise FrError(k + " must be a contiguous float64 numpy array")
+        if req.get("u_init") is not None or req.get("u_out") is not None:
+            _, ns = self.footprint(**req)
+            for k in ("u_init", "u_out"):
+                if req.get(k) is not None and req[k].size != ns:
+                    raise FrError("%s must hold %d doubles" % (k, ns))
+        r = self.request(**req)
+        i = ctypes.c_int64()
+        _check(self.pool, self.lib.fr_pool_submit(self.pool, ctypes.byref(r), ctypes.byref(i)), pool=True)
+        self._keep[i.value] = (req.get("u_init"), req.get("u_out"))
+        return i.value
+
+    def step(self):
+        """One scheduling round; returns (stats dict, admitted ids, finished ids)."""
+        s = FrPoolStats()
+        _check(self.pool, self.lib.fr_pool_step(self.pool, ctypes.byref(s)), pool=True)
+        na, nf = ctypes.c_int(), ctypes.c_int()
+        cap = max(s.n_admitted, s.n_finished, 1)
+        adm = np.empty(cap, dtype=np.int64)
+        fin = np.empty(cap, dtype=np.int64)
+        _check(self.pool, self.lib.fr_pool_events(self.pool, adm.ctypes.data, ctypes.byref(na), fin.ctypes.data,
+                                                  ctypes.byref(nf), cap), pool=True)
+        for i in fin[:nf.value]:
+            self._keep.pop(int(i), None)
+        stats = {k: getattr(s, k) for k, _ in FrPoolStats._fields_}
+        return stats, adm[:na.value].tolist(), fin[:nf.value].tolist()
+
+    def query(self, rid):
+        st, sd = ctypes.c_int(), ctypes.c_int()
+        _check(self.pool, self.lib.fr_pool_query(self.pool, int(rid), ctypes.byref(st), ctypes.byref(sd)), pool=True)
+        return st.value, sd.value

@@ -29,7 +29,7 @@ struct fr_ctx {
   fr::GasHost gas;
   // device buffers
   double* d_state = nullptr;  // internal state
-  double* d_rk = nullptr;     // 3 x n_state: stage state, stage derivative, accumulator
+  double* d_rk = nullptr;     // RK buffers: stage state, accumulator (+ stage derivative, plain form)
   void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
   fr::FaceRec* d_faces = nullptr;
   uint8_t* d_perms = nullptr;
@@ -181,7 +181,7 @@ fr_status ensure_device(fr_ctx* c) {
   const int64_t S = M.nslots;
   HIPCHK(hipMalloc(&c->d_state, sizeof(double) * c->n_state));
   HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(double) * c->n_state, c->st));
-  HIPCHK(hipMalloc(&c->d_rk, sizeof(double) * c->n_state * 3));
+  HIPCHK(hipMalloc(&c->d_rk, sizeof(double) * c->n_state * 2));  // stage state, accumulator
   HIPCHK(hipMalloc(&c->d_Uf, rs * S * 5 * nfp));
   HIPCHK(hipMalloc(&c->d_Vf, rs * S * 4 * nfp));
   HIPCHK(hipMalloc(&c->d_Rp, rs * c->n_state));
@@ -231,30 +231,43 @@ fr_status ensure_device(fr_ctx* c) {
   return FR_OK;
 }
 
-fr::TypeArgs type_args(fr_ctx* c, int t, const double* u, double* du, int stage) {
+// the segment of element type t: caller's u/du for a plain evaluation, the
+// internal state and RK buffers otherwise
+fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
+  fr::Seg s;
+  const int64_t o = c->off[t];
+  s.U = const_cast<double*>(u ? u : c->d_state) + o;
+  s.du = du ? du + o : nullptr;
+  s.ust = c->d_rk + o;
+  s.acc = c->d_rk + c->n_state + o;
+  s.Uf = c->d_Uf;
+  s.Vf = c->d_Vf;
+  s.Rp = (char*)c->d_Rp + rsize(c) * o;
+  s.faces = c->d_faces;
+  s.fgeo = c->d_fgeo;
+  s.perms = c->d_perms;
+  s.met = c->d_met[t];
+  s.detj = c->d_detj[t];
+  s.E = (int32_t)c->M.nel[t];
+  s.slot_base = (int32_t)c->M.slot_base[t];
+  return s;
+}
+
+fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
   fr::TypeArgs a;
   a.p = c->p;
-  a.E = c->M.nel[t];
-  a.slot_base = c->M.slot_base[t];
   a.stage = stage;
   a.diag = c->diag[t];
-  a.U = u + c->off[t];
-  a.du = du + c->off[t];
-  a.Uf = c->d_Uf;
-  a.Vf = c->d_Vf;
-  a.Rp = (char*)c->d_Rp + rsize(c) * c->off[t];
-  a.faces = c->d_faces;
-  a.fgeo = c->d_fgeo;
-  a.perms = c->d_perms;
-  a.met = c->d_met[t];
-  a.detj = c->d_detj[t];
+  a.one = s;
   a.dops = c->d_pops;
   a.ops = &c->hops[t];
   a.gas = &c->gas;
   return a;
 }
 
-fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7) {
+// one right-hand side (rk < 0: du = R(u)) or one fused RK4 stage rk on the
+// internal state (u, du unused)
+fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int rk = -1, double dt = 0.0) {
   if (c->ph.form == FR_FORM_PLAIN) {
     hipError_t e = fr::plain_rhs(*c->plain, u, du, c->st);
     if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("plain path: ") + hipGetErrorString(e));
@@ -264,7 +277,10 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7) {
     if (mask & stage)
     for (int t = 0; t < 2; ++t) {
       if (!c->has[t]) continue;
-      fr::TypeArgs a = type_args(c, t, u, du, stage);
+      fr::TypeArgs a = type_args(c, t, seg_of_type(c, t, rk < 0 ? u : nullptr, rk < 0 ? du : nullptr), stage);
+      a.one.dt = dt;
+      a.rk = rk;
+      a.from_ust = rk > 0;
       hipError_t e = t == 0 ? fr::hex_rhs(a, c->ph.prec, c->st) : fr::prism_rhs(a, c->ph.prec, c->st);
       if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
@@ -424,11 +440,20 @@ fr_status fr_rk4_step(fr_ctx* c, double dt, int nsteps) {
   fr_status s = ensure_device(c);
   if (s != FR_OK) return s;
   const int64_t N = c->n_state;
+  // classical RK4: k1 = R(u), k2 = R(u + dt/2 k1), k3 = R(u + dt/2 k2),
+  // k4 = R(u + dt k3), u += dt/6 (k1 + 2 k2 + 2 k3 + k4)
+  if (c->ph.form == FR_FORM_FUSED) {
+    // the stage update is fused into the interface kernel (no k buffer)
+    for (int step = 0; step < nsteps; ++step)
+      for (int st = 0; st < 4; ++st) {
+        s = launch_rhs(c, nullptr, nullptr, 7, st, dt);
+        if (s != FR_OK) return s;
+      }
+    return FR_OK;
+  }
   double* ust = c->d_rk;
   double* k = c->d_rk + N;
   double* acc = c->d_rk + 2 * N;
-  // classical RK4: k1 = R(u), k2 = R(u + dt/2 k1), k3 = R(u + dt/2 k2),
-  // k4 = R(u + dt k3), u += dt/6 (k1 + 2 k2 + 2 k3 + k4)
   const double wa[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
   const double wb[4] = {dt / 2, dt / 2, dt, 0.0};
   for (int step = 0; step < nsteps; ++step) {

@@ -84,6 +84,9 @@ struct Mesh {
   std::vector<std::vector<int>> perms;
 };
 
+// element counts per type of a box mesh (same cell typing as build_box_mesh)
+void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[2]);
+
 // Build the box mesh and its connectivity; returns an error string or "".
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
                            const RefElem* refs[2], Mesh& m);

@@ -22,30 +22,57 @@ struct GasHost {
   double gamma, prandtl, mu, pref, beta, tau;
 };
 
+// One segment: the elements of one type of one mesh, with every per-mesh
+// array the kernels touch.  A launch covers either a single segment (passed
+// by value) or a list of segments in device memory addressed through a
+// per-workgroup table, so that one launch advances many independent meshes.
+struct Seg {
+  double* U = nullptr;    // state at the solution points [E][5][N_u] (RK: u_n)
+  double* ust = nullptr;  // RK stage state (input of stages 2-4)
+  double* acc = nullptr;  // RK accumulator
+  double* du = nullptr;   // right-hand side output (plain evaluation)
+  void* Uf = nullptr;     // face states [slot][5][n^2] (precision R), per mesh
+  void* Vf = nullptr;     // normal viscous fluxes [slot][4][n^2], per mesh
+  void* Rp = nullptr;     // volume divergence [E][5][N_u] (precision R)
+  const FaceRec* faces = nullptr;
+  const void* fgeo = nullptr;      // [slot][4]: L-side unit normal, area factor (R)
+  const uint8_t* perms = nullptr;  // [perm][n^2]
+  const void* met = nullptr;       // [E][10]: J^-1 (row-major), det J   (R)
+  const double* detj = nullptr;    // [E]
+  double dt = 0.0;                 // RK time step of this mesh
+  int32_t E = 0;                   // elements in the segment
+  int32_t slot_base = 0;           // first face slot of this type in the mesh
+};
+
+// workgroup -> (segment, first element of the segment)
+struct BlkRef {
+  int32_t seg, e0;
+};
+
+// kernels of one right-hand side, in launch order
+enum { K_DISU = 0, K_VOLUME = 1, K_SURFACE = 2 };
+
 // everything one element type needs for a right-hand-side evaluation
 struct TypeArgs {
   int p = 0;
-  int64_t E = 0;          // elements of this type
-  int64_t slot_base = 0;  // first face slot of this type
-  int stage = 7;          // bit 0: disu, bit 1: volume group, bit 2: interface group
-  bool diag = false;      // every element of this type has a diagonal Jacobian
-  const double* U = nullptr;  // state of this type (E x 5 x N_u)
-  double* du = nullptr;
-  void* Uf = nullptr;  // face states   [slot][5][n^2]   (precision R)
-  void* Vf = nullptr;  // normal viscous fluxes [slot][4][n^2]
-  void* Rp = nullptr;  // volume divergence of this type (E x 5 x N_u, precision R)
-  const FaceRec* faces = nullptr;
-  const void* fgeo = nullptr;     // [slot][4]: L-side unit normal, area factor (R)
-  const uint8_t* perms = nullptr; // [perm][n^2]
-  const void* met = nullptr;      // [E][10]: J^-1 (row-major), det J   (R)
-  const double* detj = nullptr;   // [E]
-  const void* dops = nullptr;     // device copy of the prism operator tables (R)
+  int stage = 7;        // bit 0: disu, bit 1: volume group, bit 2: interface group
+  bool diag = false;    // every element has a diagonal Jacobian
+  bool from_ust = false;  // disu/volume read Seg::ust instead of Seg::U
+  int rk = -1;          // -1: surface writes du; 0..3: fused classical RK4 stage
+  Seg one;              // the segment when bt is null
+  const BlkRef* bt[3] = {nullptr, nullptr, nullptr};  // per-kernel workgroup tables
+  int nblk[3] = {0, 0, 0};                            // workgroups per kernel
+  const Seg* segs = nullptr;                          // device segment list
+  const void* dops = nullptr;  // device copy of the prism operator tables (R)
   const HostOps* ops = nullptr;
   const GasHost* gas = nullptr;
 };
 
 hipError_t hex_rhs(const TypeArgs& a, int prec, hipStream_t st);
 hipError_t prism_rhs(const TypeArgs& a, int prec, hipStream_t st);
+// elements per workgroup of kernel k (K_DISU, K_VOLUME, K_SURFACE)
+int hex_block_elems(int p, int prec, int k);
+int prism_block_elems(int p, int prec, int k);
 // size in bytes of the prism operator table for order p and precision prec,
 // and its packing into host memory (uploaded once per context)
 size_t prism_ops_bytes(int p, int prec);
@@ -55,5 +82,44 @@ void prism_ops_pack(const RefElem& r, int prec, void* dst);
 // acc = u0 + a k)
 hipError_t rk_stage(int64_t n, const double* u0, const double* k, double* acc, double* ust, double a, double b,
                     int first, hipStream_t st);
+
+// Taylor-Green initial state at the solution points of E affine elements:
+// x = org_e + J_e xi_u (geo: [E][12] = org, J row-major; ref: [N_u][3])
+hipError_t tgv_init(int64_t E, int nu, const double* geo, const double* ref, double gamma, double p0, double* U,
+                    hipStream_t st);
+
+// locate this workgroup's segment and first element: BT (batched launch)
+// reads the workgroup table, otherwise the single segment passed by value
+template <bool BT>
+__device__ __forceinline__ Seg seg_of(const Seg& one, const BlkRef* bt, const Seg* segs, int EB, int& e0) {
+  if constexpr (BT) {
+    const BlkRef b = bt[blockIdx.x];
+    e0 = b.e0;
+    return segs[b.seg];
+  } else {
+    e0 = blockIdx.x * EB;
+    return one;
+  }
+}
+
+// write the right-hand side value k of state entry i, or apply the classical
+// RK4 stage rk to it:  k1..k4 at u_n, u_n + dt/2 k1, u_n + dt/2 k2, u_n + dt k3;
+// u_{n+1} = u_n + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+__device__ __forceinline__ void rk_store(const Seg& s, int rk, size_t i, double k) {
+  if (rk < 0) {
+    s.du[i] = k;
+    return;
+  }
+  const double dt = s.dt;
+  if (rk == 3) {
+    s.U[i] = s.acc[i] + (dt / 6) * k;
+    return;
+  }
+  const double u = s.U[i];
+  const double a = rk == 0 ? dt / 6 : dt / 3;
+  const double b = rk == 2 ? dt : dt / 2;
+  s.acc[i] = (rk == 0 ? u : s.acc[i]) + a * k;
+  s.ust[i] = u + b * k;
+}
 
 }  // namespace fr

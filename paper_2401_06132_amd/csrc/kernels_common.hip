@@ -30,4 +30,40 @@ hipError_t rk_stage(int64_t n, const double* u0, const double* k, double* acc, d
   return hipGetLastError();
 }
 
+// Taylor-Green vortex (the paper's test case, section 7.2) at the solution
+// points: v = (sin x cos y cos z, -cos x sin y cos z, 0),
+// p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16, rho = p/p0 (rho0 = U0 = 1),
+// E = p/(gamma-1) + rho |v|^2/2.  One thread per solution point.
+__global__ void tgv_init_kernel(int64_t E, int nu, const double* __restrict__ geo, const double* __restrict__ ref,
+                                double gamma, double p0, double* __restrict__ U) {
+  const int64_t n = E * nu;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / nu;
+    const int u = int(i - e * nu);
+    const double* G = geo + 12 * e;
+    const double* xi = ref + 3 * u;
+    double x[3];
+    for (int d = 0; d < 3; ++d) x[d] = G[d] + G[3 + 3 * d] * xi[0] + G[4 + 3 * d] * xi[1] + G[5 + 3 * d] * xi[2];
+    const double sx = sin(x[0]), cx = cos(x[0]), sy = sin(x[1]), cy = cos(x[1]), cz = cos(x[2]);
+    const double vx = sx * cy * cz, vy = -cx * sy * cz;
+    const double p = p0 + (cos(2 * x[0]) + cos(2 * x[1])) * (cos(2 * x[2]) + 2.0) / 16.0;
+    const double rho = p / p0;
+    double* ue = U + e * 5 * nu + u;
+    ue[0] = rho;
+    ue[nu] = rho * vx;
+    ue[2 * nu] = rho * vy;
+    ue[3 * nu] = 0.0;
+    ue[4 * nu] = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy);
+  }
+}
+
+hipError_t tgv_init(int64_t E, int nu, const double* geo, const double* ref, double gamma, double p0, double* U,
+                    hipStream_t st) {
+  int64_t blocks = (E * nu + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(tgv_init_kernel, dim3((unsigned)blocks), dim3(256), 0, st, E, nu, geo, ref, gamma, p0, U);
+  return hipGetLastError();
+}
+
 }  // namespace fr

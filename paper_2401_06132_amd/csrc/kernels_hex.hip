@@ -67,14 +67,18 @@ __device__ __forceinline__ R sel(const R (&v)[N], int idx) {
 }
 
 // ----------------------------------------------------------------- disu
-template <int P, typename R, int EB, int NT>
-__global__ void __launch_bounds__(NT) hex_disu(const double* __restrict__ U, R* __restrict__ Uf,
-                                               const HexOps<P, R> op, const double eref, const int E,
-                                               const int slot_base) {
+template <int P, typename R, int EB, int NT, bool BT>
+__global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __restrict__ bt,
+                                               const Seg* __restrict__ segs, const bool from_ust,
+                                               const HexOps<P, R> op, const double eref) {
   using C = HexCfg<P>;
   constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
   __shared__ R sU[EB * 5 * NU];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  R* __restrict__ Uf = (R*)sg.Uf;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
   for (int it = tid; it < EB * 5 * NU; it += NT) {
     const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
     R val = R(0);
@@ -120,18 +124,26 @@ struct HexVol {
   static constexpr int PER_ELEM = SZ_A + SZ_B;
 };
 
-template <int P, typename R, int EB, int NT, bool DIAG>
+template <int P, typename R, int EB, int NT, bool DIAG, bool BT>
 __global__ void __launch_bounds__(NT)
-    hex_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
-               const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
-               const R* __restrict__ met, const HexOps<P, R> op, const Gas<R> g, const double eref, const int E,
-               const int slot_base) {
+    hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
+               const HexOps<P, R> op, const Gas<R> g, const double eref) {
   using C = HexVol<P>;
   constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
   static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  R* __restrict__ Vf = (R*)sg.Vf;
+  R* __restrict__ Rp = (R*)sg.Rp;
+  const FaceRec* __restrict__ faces = sg.faces;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+  const uint8_t* __restrict__ perms = sg.perms;
+  const R* __restrict__ met = (const R*)sg.met;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
 #define YS(le) (smem + (le)*PE)            /* [2][5][m][n][n]              */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
@@ -410,16 +422,23 @@ __global__ void __launch_bounds__(NT)
 }
 
 // -------------------------------------------------------------- surface
-template <int P, typename R, int EB, int NT>
+template <int P, typename R, int EB, int NT, bool BT>
 __global__ void __launch_bounds__(NT)
-    hex_surface(const R* __restrict__ Uf, const R* __restrict__ Vf, const R* __restrict__ Rp, double* __restrict__ du,
-                const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
-                const double* __restrict__ detj, const HexOps<P, R> op, const Gas<R> g, const int E,
-                const int slot_base) {
+    hex_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
+                const HexOps<P, R> op, const Gas<R> g) {
   using C = HexCfg<P>;
   constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
   __shared__ R sD[EB * 30 * NFP];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  const R* __restrict__ Vf = (const R*)sg.Vf;
+  const R* __restrict__ Rp = (const R*)sg.Rp;
+  const FaceRec* __restrict__ faces = sg.faces;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+  const uint8_t* __restrict__ perms = sg.perms;
+  const double* __restrict__ detj = sg.detj;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
   // comm_flux: common normal flux at every own flux point, times +-mag
   for (int it = tid; it < EB * 6 * NFP; it += NT) {
     const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
@@ -460,7 +479,7 @@ __global__ void __launch_bounds__(NT)
     acc += sel(op.liftL, i) * D[0 * 5 * NFP + j + n * k] + sel(op.liftR, i) * D[1 * 5 * NFP + j + n * k];
     acc += sel(op.liftL, j) * D[2 * 5 * NFP + i + n * k] + sel(op.liftR, j) * D[3 * 5 * NFP + i + n * k];
     acc += sel(op.liftL, k) * D[4 * 5 * NFP + i + n * j] + sel(op.liftR, k) * D[5 * 5 * NFP + i + n * j];
-    du[(size_t)e * 5 * NU + r0] = -double(acc) / detj[e];
+    rk_store(sg, rk, (size_t)e * 5 * NU + r0, -double(acc) / detj[e]);
   }
 }
 
@@ -515,38 +534,58 @@ template <> struct HexLaunch<2, true> { static constexpr int EB = 2, NT = 64; };
 template <> struct HexLaunch<3, true> { static constexpr int EB = 1, NT = 64; };    // 36
 template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 49
 
-template <int P, typename R>
-static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
+// elements per workgroup of the disu and surface kernels (256 threads)
+constexpr int HEX_DISU_EB = 8, HEX_SURF_EB = 4;
+
+template <int P, typename R, bool BT>
+static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const HexOps<P, R> op = make_hex_ops<P, R>(*a.ops);
   const Gas<R> g = make_gas<R>(*a.gas);
-  const int E = (int)a.E;
-  if (E == 0) return hipSuccess;
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
+  constexpr int EBA = HEX_DISU_EB, NTA = 256, EBC = HEX_SURF_EB, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
-  const int sb = (int)a.slot_base;
-  if (a.stage & 1) {
-    constexpr int EBA = 8, NTA = 256;
-    hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA>), dim3((E + EBA - 1) / EBA), dim3(NTA), 0, st, a.U, (R*)a.Uf, op,
-                       eref, E, sb);
-  }
-  if (a.stage & 2) {
+  if ((a.stage & 1) && grid[K_DISU] > 0)
+    hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
+                       a.segs, a.from_ust, op, eref);
+  if ((a.stage & 2) && grid[K_VOLUME] > 0) {
     if (a.diag)
-      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U,
-                         (const R*)a.Uf, (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op,
-                         g, eref, E, sb);
+      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
     else
-      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U,
-                         (const R*)a.Uf, (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op,
-                         g, eref, E, sb);
+      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
   }
-  if (a.stage & 4) {
-    constexpr int EBC = 4, NTC = 256;
-    hipLaunchKernelGGL((hex_surface<P, R, EBC, NTC>), dim3((E + EBC - 1) / EBC), dim3(NTC), 0, st, (const R*)a.Uf,
-                       (const R*)a.Vf, (const R*)a.Rp, a.du, a.faces, (const R*)a.fgeo, a.perms, a.detj, op, g, E,
-                       sb);
-  }
+  if ((a.stage & 4) && grid[K_SURFACE] > 0)
+    hipLaunchKernelGGL((hex_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
+                       a.bt[K_SURFACE], a.segs, a.rk, op, g);
+}
+
+template <int P, typename R>
+static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
+  constexpr bool dbl = sizeof(R) == 8;
+  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB, HEX_SURF_EB};
+  const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
+  int grid[3];
+  for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
+  if (bt)
+    hex_launch<P, R, true>(a, grid, st);
+  else
+    hex_launch<P, R, false>(a, grid, st);
   return hipGetLastError();
+}
+
+int hex_block_elems(int p, int prec, int k) {
+  if (k == K_DISU) return HEX_DISU_EB;
+  if (k == K_SURFACE) return HEX_SURF_EB;
+  const bool d = prec == 0;
+  switch (p) {
+    case 1: return d ? HexLaunch<1, true>::EB : HexLaunch<1, false>::EB;
+    case 2: return d ? HexLaunch<2, true>::EB : HexLaunch<2, false>::EB;
+    case 3: return d ? HexLaunch<3, true>::EB : HexLaunch<3, false>::EB;
+    case 4: return d ? HexLaunch<4, true>::EB : HexLaunch<4, false>::EB;
+  }
+  return 0;
 }
 
 hipError_t hex_rhs(const TypeArgs& a, int prec, hipStream_t st) {

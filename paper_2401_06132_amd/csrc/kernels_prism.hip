@@ -69,14 +69,19 @@ __device__ __forceinline__ R psel(const R (&v)[N], int idx) {
 }
 
 // ----------------------------------------------------------------- disu
-template <int P, typename R, int EB, int NT_>
-__global__ void __launch_bounds__(NT_) prism_disu(const double* __restrict__ U, R* __restrict__ Uf,
+template <int P, typename R, int EB, int NT_, bool BT>
+__global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* __restrict__ bt,
+                                                  const Seg* __restrict__ segs, const bool from_ust,
                                                   const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri,
-                                                  const double eref, const int E, const int slot_base) {
+                                                  const double eref) {
   using C = PrismCfg<P>;
   constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
   __shared__ R sU[EB * 5 * NU];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  R* __restrict__ Uf = (R*)sg.Uf;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
   for (int it = tid; it < EB * 5 * NU; it += NT_) {
     const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
     R val = R(0);
@@ -152,19 +157,28 @@ __device__ __forceinline__ double pair_sum(double x) {
   return x + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int P, typename R, int EB, int NT_>
+template <int P, typename R, int EB, int NT_, bool BT>
 __global__ void __launch_bounds__(NT_)
-    prism_volume(const double* __restrict__ U, const R* __restrict__ Uf, R* __restrict__ Vf, R* __restrict__ Rp,
-                 const FaceRec* __restrict__ faces, const R* __restrict__ fgeo, const uint8_t* __restrict__ perms,
-                 const R* __restrict__ met, const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g,
-                 const Gas<R> g, const double eref, const int E, const int slot_base) {
+    prism_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
+                 const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g, const Gas<R> g,
+                 const double eref) {
   using C = PrismVol<P>;
   constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
   static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
   __shared__ PrismTri<P, R> tri;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  R* __restrict__ Vf = (R*)sg.Vf;
+  R* __restrict__ Rp = (R*)sg.Rp;
+  const FaceRec* __restrict__ faces = sg.faces;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+  const uint8_t* __restrict__ perms = sg.perms;
+  const R* __restrict__ met = (const R*)sg.met;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                 */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
 #define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][NTQ]             */
@@ -474,17 +488,28 @@ __global__ void __launch_bounds__(NT_)
 }
 
 // -------------------------------------------------------------- surface
-template <int P, typename R, int EB, int NT_>
+template <int P, typename R, int EB, int NT_, bool BT>
 __global__ void __launch_bounds__(NT_)
-    prism_surface(const R* __restrict__ Uf, const R* __restrict__ Vf, const R* __restrict__ Rp,
-                  double* __restrict__ du, const FaceRec* __restrict__ faces, const R* __restrict__ fgeo,
-                  const uint8_t* __restrict__ perms, const double* __restrict__ detj, const PrismOps<P, R> op,
-                  const PrismTri<P, R>* __restrict__ tri, const Gas<R> g, const int E, const int slot_base) {
+    prism_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
+                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri, const Gas<R> g) {
   using C = PrismCfg<P>;
   constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
   __shared__ R sD[EB * 25 * NFP];
-  const int tid = threadIdx.x, e0 = blockIdx.x * EB;
+  __shared__ R sLift[3][NT][n];
+  int e0;
+  const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  const R* __restrict__ Vf = (const R*)sg.Vf;
+  const R* __restrict__ Rp = (const R*)sg.Rp;
+  const FaceRec* __restrict__ faces = sg.faces;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+  const uint8_t* __restrict__ perms = sg.perms;
+  const double* __restrict__ detj = sg.detj;
+  const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
   const int fnp[5] = {NT, NT, NFP, NFP, NFP};
+  // edge lifting table, staged in LDS for the per-point lift below
+  for (int it = tid; it < 3 * NT * n; it += NT_) (&sLift[0][0][0])[it] = (&tri->LiftEdge[0][0][0])[it];
+  // comm_flux: common normal flux at every own flux point, times +-mag
   for (int it = tid; it < EB * 5 * NFP; it += NT_) {
     const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
     if (e >= E || r >= fnp[f]) continue;
@@ -514,26 +539,19 @@ __global__ void __launch_bounds__(NT_)
     for (int v = 0; v < 5; ++v) sD[(le * 5 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
   }
   __syncthreads();
-  // tdivtconf + negdivconf, one (variable, plane) per thread
-  for (int it = tid; it < EB * 5 * n; it += NT_) {
-    const int le = it / (5 * n), r0 = it - le * (5 * n), v = r0 / n, k = r0 - v * n, e = e0 + le;
+  // tdivtconf + negdivconf, one output point per thread (coalesced state
+  // and residual access)
+  for (int it = tid; it < EB * 5 * NU; it += NT_) {
+    const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
     if (e >= E) continue;
+    const int k = s / NT, t = s - k * NT;
     const R* D = sD + le * 25 * NFP + v * NFP;
-    const R lL = psel(op.liftL, k), lR = psel(op.liftR, k);
-    R de[3][n];
+    R acc = Rp[(size_t)e * 5 * NU + r0] + psel(op.liftL, k) * D[0 * 5 * NFP + t] + psel(op.liftR, k) * D[1 * 5 * NFP + t];
 #pragma unroll
     for (int ed = 0; ed < 3; ++ed)
 #pragma unroll
-      for (int i = 0; i < n; ++i) de[ed][i] = D[(2 + ed) * 5 * NFP + i + n * k];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      R acc = Rp[(size_t)e * 5 * NU + v * NU + t + NT * k] + lL * D[0 * 5 * NFP + t] + lR * D[1 * 5 * NFP + t];
-#pragma unroll
-      for (int ed = 0; ed < 3; ++ed)
-#pragma unroll
-        for (int i = 0; i < n; ++i) acc += tri->LiftEdge[ed][t][i] * de[ed][i];
-      du[(size_t)e * 5 * NU + v * NU + t + NT * k] = -double(acc) / detj[e];
-    }
+      for (int i = 0; i < n; ++i) acc += sLift[ed][t][i] * D[(2 + ed) * 5 * NFP + i + n * k];
+    rk_store(sg, rk, (size_t)e * 5 * NU + r0, -double(acc) / detj[e]);
   }
 }
 
@@ -632,34 +650,54 @@ template <> struct PrismLaunch<2, true> { static constexpr int EB = 3, NT = 64; 
 template <> struct PrismLaunch<3, true> { static constexpr int EB = 2, NT = 64; };    // 64
 template <> struct PrismLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 50
 
-template <int P, typename R>
-static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
+// elements per workgroup of the disu and surface kernels (256 threads)
+constexpr int PRISM_DISU_EB = 8, PRISM_SURF_EB = 4;
+
+template <int P, typename R, bool BT>
+static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const PrismOps<P, R> op = make_prism_ops<P, R>(*a.ops);
   const Gas<R> g = make_gas_p<R>(*a.gas);
   const PrismTri<P, R>* tri = (const PrismTri<P, R>*)a.dops;
-  const int E = (int)a.E;
-  if (E == 0) return hipSuccess;
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = PrismLaunch<P, dbl>::EB, NT = PrismLaunch<P, dbl>::NT;
+  constexpr int EBA = PRISM_DISU_EB, NTA = 256, EBC = PRISM_SURF_EB, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
-  const int sb = (int)a.slot_base;
-  if (a.stage & 1) {
-    constexpr int EBA = 8, NTA = 256;
-    hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA>), dim3((E + EBA - 1) / EBA), dim3(NTA), 0, st, a.U, (R*)a.Uf, op,
-                       tri, eref, E, sb);
-  }
-  if (a.stage & 2) {
-    hipLaunchKernelGGL((prism_volume<P, R, EB, NT>), dim3((E + EB - 1) / EB), dim3(NT), 0, st, a.U, (const R*)a.Uf,
-                       (R*)a.Vf, (R*)a.Rp, a.faces, (const R*)a.fgeo, a.perms, (const R*)a.met, op, tri, g, eref, E,
-                       sb);
-  }
-  if (a.stage & 4) {
-    constexpr int EBC = 4, NTC = 256;
-    hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC>), dim3((E + EBC - 1) / EBC), dim3(NTC), 0, st, (const R*)a.Uf,
-                       (const R*)a.Vf, (const R*)a.Rp, a.du, a.faces, (const R*)a.fgeo, a.perms, a.detj, op, tri, g,
-                       E, sb);
-  }
+  if ((a.stage & 1) && grid[K_DISU] > 0)
+    hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
+                       a.segs, a.from_ust, op, tri, eref);
+  if ((a.stage & 2) && grid[K_VOLUME] > 0)
+    hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                       a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+  if ((a.stage & 4) && grid[K_SURFACE] > 0)
+    hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
+                       a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
+}
+
+template <int P, typename R>
+static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
+  constexpr bool dbl = sizeof(R) == 8;
+  const int ebs[3] = {PRISM_DISU_EB, PrismLaunch<P, dbl>::EB, PRISM_SURF_EB};
+  const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
+  int grid[3];
+  for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
+  if (bt)
+    prism_launch<P, R, true>(a, grid, st);
+  else
+    prism_launch<P, R, false>(a, grid, st);
   return hipGetLastError();
+}
+
+int prism_block_elems(int p, int prec, int k) {
+  if (k == K_DISU) return PRISM_DISU_EB;
+  if (k == K_SURFACE) return PRISM_SURF_EB;
+  const bool d = prec == 0;
+  switch (p) {
+    case 1: return d ? PrismLaunch<1, true>::EB : PrismLaunch<1, false>::EB;
+    case 2: return d ? PrismLaunch<2, true>::EB : PrismLaunch<2, false>::EB;
+    case 3: return d ? PrismLaunch<3, true>::EB : PrismLaunch<3, false>::EB;
+    case 4: return d ? PrismLaunch<4, true>::EB : PrismLaunch<4, false>::EB;
+  }
+  return 0;
 }
 
 hipError_t prism_rhs(const TypeArgs& a, int prec, hipStream_t st) {

@@ -18,10 +18,53 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <thread>
 
 #include "fr_host.h"
 
 namespace fr {
+
+// run body(lo, hi, chunk) over [0, n) in contiguous chunks on up to 16 host
+// threads (one chunk when n is small); returns the number of chunks
+static int64_t chunk_len(int64_t n) {
+  int nth = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 40000) nth = 1;
+  return std::max<int64_t>(1, (n + nth - 1) / nth);
+}
+
+template <typename F>
+static int parallel_chunks(int64_t n, F body) {
+  const int64_t per = chunk_len(n);
+  const bool serial = per >= n;
+  std::vector<std::thread> th;
+  int c = 0;
+  for (int64_t lo = 0; lo < n; lo += per, ++c) {
+    const int64_t hi = std::min(n, lo + per);
+    if (serial) {
+      body(lo, hi, c);
+    } else {
+      th.emplace_back(body, lo, hi, c);
+    }
+  }
+  for (auto& t : th) t.join();
+  return c;
+}
+
+// mixed meshes: hexahedra where the cell centre has z < 0, prisms elsewhere
+static int cell_type(int k, int nz, double lo, double hi, int kind) {
+  if (kind != 2) return kind;
+  const double hz = (hi - lo) / nz;
+  const double zc = (lo + k * hz) + 0.5 * hz;
+  return zc < 0.0 ? 0 : 1;
+}
+
+void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[2]) {
+  nel[0] = nel[1] = 0;
+  for (int k = 0; k < nz; ++k) {
+    const int t = cell_type(k, nz, lo, hi, kind);
+    nel[t] += (int64_t)nx * ny * (t == 0 ? 1 : 2);
+  }
+}
 
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind, const RefElem* refs[2],
                            Mesh& M) {
@@ -40,8 +83,7 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         double x0[3] = {lo + i * h[0], lo + j * h[1], lo + k * h[2]};
-        double zc = x0[2] + 0.5 * h[2];
-        int t = kind == 2 ? (zc < 0.0 ? 0 : 1) : kind;
+        int t = cell_type(k, nz, lo, hi, kind);
         double c[3] = {x0[0] + 0.5 * h[0], x0[1] + 0.5 * h[1], x0[2] + 0.5 * h[2]};
         if (t == 0) {
           for (int d = 0; d < 3; ++d) M.org[0].push_back(c[d]);
@@ -101,7 +143,8 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     e = r / nfc[t];
     f = int(r % nfc[t]);
   };
-  for (int64_t s = 0; s < S; ++s) {
+  parallel_chunks(S, [&](int64_t s0, int64_t s1, int) {
+  for (int64_t s = s0; s < s1; ++s) {
     int t, f;
     int64_t e;
     slot_info(s, t, e, f);
@@ -123,15 +166,27 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     k[3] = s;
     keys[s] = k;
   }
-  std::sort(keys.begin(), keys.end());
+  });
+  {
+    // chunks sorted on host threads, then merged pairwise
+    parallel_chunks(S, [&](int64_t s0, int64_t s1, int) { std::sort(keys.begin() + s0, keys.begin() + s1); });
+    for (int64_t w = chunk_len(S); w < S; w *= 2) {
+      std::vector<std::thread> th;
+      for (int64_t lo = 0; lo + w < S; lo += 2 * w) {
+        const int64_t mid = lo + w, hi = std::min(S, lo + 2 * w);
+        th.emplace_back([&keys, lo, mid, hi] {
+          std::inplace_merge(keys.begin() + lo, keys.begin() + mid, keys.begin() + hi);
+        });
+      }
+      for (auto& t : th) t.join();
+    }
+  }
   if (S % 2) return "odd number of faces";
   M.nbr_slot.assign(S, -1);
   M.perm_id.assign(S, 0);
   M.is_left.assign(S, 0);
   M.nrm.assign(3 * S, 0);
   M.mag.assign(S, 0);
-  std::map<std::vector<int>, int> permidx;
-  std::map<int, int> last_perm;
   for (int64_t i = 0; i < S; i += 2) {
     const auto& a = keys[i];
     const auto& b = keys[i + 1];
@@ -142,88 +197,119 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     M.nbr_slot[sa] = sb;
     M.nbr_slot[sb] = sa;
   }
-  // per pair: L/R, point permutation, L-side normal and area factor
-  for (int64_t s = 0; s < S; ++s) {
-    int64_t o = M.nbr_slot[s];
-    int t, f, to, fo;
-    int64_t e, eo;
-    slot_info(s, t, e, f);
-    slot_info(o, to, eo, fo);
-    const RefElem& R = *refs[t];
-    const RefElem& RO = *refs[to];
-    int np = R.face_npts[f];
-    if (RO.face_npts[fo] != np) return "paired faces have different point counts";
-    bool left;
-    if (M.gid[t][e] != M.gid[to][eo]) {
-      left = M.gid[t][e] < M.gid[to][eo];
-    } else {
-      const double* ca = &cent[3 * s];
-      const double* cb = &cent[3 * o];
-      left = std::lexicographical_compare(ca, ca + 3, cb, cb + 3);
-    }
-    M.is_left[s] = left ? 1 : 0;
-    // try the permutation found last for this (type, face, type, face) class
-    // first; search by brute force only when it does not match
-    auto dist = [&](int q, int r) {
-      double x[3], y[3];
-      phys(t, e, &R.fpts[3 * (R.face_start[f] + q)], x);
-      phys(to, eo, &RO.fpts[3 * (RO.face_start[fo] + r)], y);
-      double d2 = 0;
-      for (int d = 0; d < 3; ++d) {
-        double dd = x[d] - y[d];
-        dd -= Lx * std::nearbyint(dd / Lx);
-        d2 += dd * dd;
+  // per pair: L/R and point permutation.  Chunks of slots run on host
+  // threads, each with its own permutation table; the tables are merged in
+  // slot order, so permutation ids are numbered by first appearance.
+  struct Local {
+    std::vector<std::vector<int>> perms;
+    std::vector<int> pid;  // per slot of the chunk: index into perms
+    std::string err;
+  };
+  std::vector<Local> loc(16);
+  const int nchunk = parallel_chunks(S, [&](int64_t s0, int64_t s1, int chunk) {
+    Local& L = loc[chunk];
+    L.pid.assign(s1 - s0, -1);
+    std::vector<int> last;  // face class -> local permutation id
+    for (int64_t s = s0; s < s1; ++s) {
+      int64_t o = M.nbr_slot[s];
+      int t, f, to, fo;
+      int64_t e, eo;
+      slot_info(s, t, e, f);
+      slot_info(o, to, eo, fo);
+      const RefElem& R = *refs[t];
+      const RefElem& RO = *refs[to];
+      const int np = R.face_npts[f];
+      if (RO.face_npts[fo] != np) {
+        L.err = "paired faces have different point counts";
+        return;
       }
-      return std::sqrt(d2);
-    };
-    const double tol = 1e-9 * std::min(h[0], std::min(h[1], h[2]));
-    int cls = ((t * 8 + f) * 2 + to) * 8 + fo;
-    std::vector<int> perm;
-    auto cit = last_perm.find(cls);
-    if (cit != last_perm.end()) {
-      perm = M.perms[cit->second];
-      for (int q = 0; q < np; ++q)
-        if (dist(q, perm[q]) > tol) {
-          perm.clear();
-          break;
+      bool left;
+      if (M.gid[t][e] != M.gid[to][eo]) {
+        left = M.gid[t][e] < M.gid[to][eo];
+      } else {
+        const double* ca = &cent[3 * s];
+        const double* cb = &cent[3 * o];
+        left = std::lexicographical_compare(ca, ca + 3, cb, cb + 3);
+      }
+      M.is_left[s] = left ? 1 : 0;
+      // try the permutation found last for this (type, face, type, face)
+      // class first; search by brute force only when it does not match
+      auto dist2 = [&](int q, int r) {
+        double x[3], y[3];
+        phys(t, e, &R.fpts[3 * (R.face_start[f] + q)], x);
+        phys(to, eo, &RO.fpts[3 * (RO.face_start[fo] + r)], y);
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) {
+          double dd = x[d] - y[d];
+          dd -= Lx * std::nearbyint(dd / Lx);
+          d2 += dd * dd;
         }
-    }
-    if (perm.empty()) {
-      perm.assign(np, -1);
-      for (int q = 0; q < np; ++q) {
-        double best = 1e300;
-        int bi = -1;
-        for (int r = 0; r < np; ++r) {
-          double d = dist(q, r);
-          if (d < best) {
-            best = d;
-            bi = r;
+        return d2;
+      };
+      const double tol = 1e-9 * std::min(h[0], std::min(h[1], h[2])), tol2 = tol * tol;
+      const int cls = ((t * 8 + f) * 2 + to) * 8 + fo;
+      int pid = cls < (int)last.size() ? last[cls] : -1;
+      if (pid >= 0) {
+        const std::vector<int>& pm = L.perms[pid];
+        for (int q = 0; q < np && pid >= 0; ++q)
+          if (dist2(q, pm[q]) > tol2) pid = -1;
+      }
+      if (pid < 0) {
+        std::vector<int> perm(np, -1);
+        for (int q = 0; q < np; ++q) {
+          double best = 1e300;
+          int bi = -1;
+          for (int r = 0; r < np; ++r) {
+            const double d = dist2(q, r);
+            if (d < best) {
+              best = d;
+              bi = r;
+            }
           }
+          if (best > tol2) {
+            L.err = "paired flux points do not coincide";
+            return;
+          }
+          perm[q] = bi;
         }
-        if (best > tol) return "paired flux points do not coincide";
-        perm[q] = bi;
+        std::vector<int> chk(perm);
+        std::sort(chk.begin(), chk.end());
+        for (int q = 0; q < np; ++q)
+          if (chk[q] != q) {
+            L.err = "flux-point matching is not one-to-one";
+            return;
+          }
+        pid = (int)(std::find(L.perms.begin(), L.perms.end(), perm) - L.perms.begin());
+        if (pid == (int)L.perms.size()) L.perms.push_back(perm);
+        if (cls >= (int)last.size()) last.resize(cls + 1, -1);
+        last[cls] = pid;
+      }
+      L.pid[s - s0] = pid;
+    }
+  });
+  {
+    std::map<std::vector<int>, int> permidx;
+    int64_t s = 0;
+    for (int c = 0; c < nchunk; ++c) {
+      const Local& L = loc[c];
+      if (!L.err.empty()) return L.err;
+      std::vector<int> l2g(L.perms.size(), -1);
+      for (int lid : L.pid) {
+        if (l2g[lid] < 0) {
+          auto it = permidx.find(L.perms[lid]);
+          if (it == permidx.end()) {
+            it = permidx.emplace(L.perms[lid], (int)M.perms.size()).first;
+            M.perms.push_back(L.perms[lid]);
+          }
+          l2g[lid] = it->second;
+        }
+        M.perm_id[s++] = l2g[lid];
       }
     }
-    {
-      std::vector<int> chk(perm);
-      std::sort(chk.begin(), chk.end());
-      for (int q = 0; q < np; ++q)
-        if (chk[q] != q) return "flux-point matching is not one-to-one";
-    }
-    auto it = permidx.find(perm);
-    int pid;
-    if (it == permidx.end()) {
-      pid = (int)M.perms.size();
-      permidx[perm] = pid;
-      M.perms.push_back(perm);
-    } else {
-      pid = it->second;
-    }
-    M.perm_id[s] = pid;
-    last_perm[cls] = pid;
   }
   // normals: n = det J J^-T nhat / mag (Nanson), taken from the L side
-  for (int64_t s = 0; s < S; ++s) {
+  parallel_chunks(S, [&](int64_t s0, int64_t s1, int) {
+  for (int64_t s = s0; s < s1; ++s) {
     int64_t l = M.is_left[s] ? s : M.nbr_slot[s];
     int t, f;
     int64_t e;
@@ -236,6 +322,7 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     for (int c = 0; c < 3; ++c) M.nrm[3 * s + c] = v[c] / mg;
     M.mag[s] = mg;
   }
+  });
   return "";
 }
 

@@ -136,9 +136,12 @@ def test_free_stream_and_conservation_gpu():
     assert du.abs().max().item() < 1e-12 * 72 * 10
 
 
-def test_rk4_parity_tgv_c1():
-    """Plain FP64 RHS + 10 RK4 steps, dt = 1e-3, 4^3 hex p=3 (the small TGV
-    case); compared on the state change u(t) - u(0)."""
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_rk4_parity_tgv_c1(form):
+    """FP64 RHS + 10 RK4 steps, dt = 1e-3, 4^3 hex p=3 (the small TGV case),
+    for the plain path (separate stage-update kernel) and the fused path
+    (stage update inside the interface kernel); compared on the state change
+    u(t) - u(0)."""
     _need_gpu()
     dims, p = (4, 4, 4), 3
     m, U = _case(dims, p, "hex")
@@ -146,7 +149,7 @@ def test_rk4_parity_tgv_c1():
     Uo = {"hex": U[0]}
     for _ in range(10):
         Uo = oracle_rk4(m, Uo, par, 1e-3)
-    s = frmi.Solver(dims, p, "hex", pref=inputs.P0)
+    s = frmi.Solver(dims, p, "hex", pref=inputs.P0, form=form)
     s.set_state(U[0])
     c0 = s.integrals()
     s.rk4(1e-3, 10)

@@ -250,6 +250,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.detj = c->d_detj[t];
   s.E = (int32_t)c->M.nel[t];
   s.slot_base = (int32_t)c->M.slot_base[t];
+  s.nperm = (int32_t)c->M.perms.size();
   return s;
 }
 
@@ -332,6 +333,7 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     const fr::RefElem* refs[2] = {&c->ref[0], &c->ref[1]};
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
+    if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }

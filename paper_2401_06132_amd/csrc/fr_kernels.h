@@ -42,7 +42,12 @@ struct Seg {
   double dt = 0.0;                 // RK time step of this mesh
   int32_t E = 0;                   // elements in the segment
   int32_t slot_base = 0;           // first face slot of this type in the mesh
+  int32_t nperm = 0;               // face-point permutations in perms (<= MAX_PERMS)
 };
+
+// largest number of distinct face-point permutations a mesh may use (the
+// fused kernels stage the table in LDS; box meshes use at most 3)
+constexpr int MAX_PERMS = 16;
 
 // workgroup -> (segment, first element of the segment)
 struct BlkRef {

@@ -150,30 +150,73 @@ __global__ void __launch_bounds__(NT)
 #define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][m][n][n]                */
 #define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][m][m][n]              */
 
-  // phase 0: state (reference form), metrics, neighbour states at own faces
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
-    R val = R(0);
+  // phase 0: state (reference form), metrics, neighbour states at own
+  // faces.  Face records, face geometry and the permutation table go to LDS
+  // first, so the neighbour gather is one global load per value, and every
+  // thread issues all of its loads before the first use.
+  __shared__ FaceRec sFR[EB * 6];
+  __shared__ R sFG[EB * 6][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFP];
+  for (int it = tid; it < EB * 6; it += NT) {
+    const int e = e0 + it / 6;
+    FaceRec fr{0, 0};
+    R g4[4] = {R(0), R(0), R(0), R(0)};
     if (e < E) {
-      double x = U[(size_t)e * 5 * NU + r];
-      if (r >= 4 * NU) x -= eref;
-      val = R(x);
+      const int slot = slot_base + e0 * 6 + it;
+      fr = faces[slot];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g4[k] = fgeo[4 * slot + k];
     }
-    XS(le)[r] = val;
+    sFR[it] = fr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sFG[it][k] = g4[k];
   }
+  for (int it = tid; it < sg.nperm * NFP; it += NT) sPerm[it] = perms[it];
   for (int it = tid; it < EB * 10; it += NT) {
     const int le = it / 10, k = it - le * 10, e = e0 + le;
     sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
   }
-  for (int it = tid; it < EB * 30 * NFP; it += NT) {
-    const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
-    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP, e = e0 + le;
-    R val = R(0);
-    if (e < E) {
-      const FaceRec fr = faces[slot_base + e * 6 + f];
-      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + perms[(fr.info >> 1) * NFP + r]];
+  constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
+  double xs[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT;
+    xs[k] = 0.0;
+    if (it < EB * 5 * NU && e0 + it / (5 * NU) < E) xs[k] = U[(size_t)e0 * 5 * NU + it];
+  }
+  __syncthreads();
+  constexpr int NG = (EB * 30 * NFP + NT - 1) / NT;
+  R gv[NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int it = tid + k * NT;
+    gv[k] = R(0);
+    if (it < EB * 30 * NFP) {
+      const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
+      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+      if (e0 + le < E) {
+        const FaceRec fr = sFR[le * 6 + f];
+        gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + r]];
+      }
     }
-    JS(le)[r0] = val;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 5 * NU) {
+      const int le = it / (5 * NU), r = it - le * (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      XS(le)[r] = R(x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 30 * NFP) {
+      const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
+      JS(le)[r0] = gv[k];
+    }
   }
   __syncthreads();
 
@@ -201,11 +244,7 @@ __global__ void __launch_bounds__(NT)
         xm += op.lb[i] * x[i];
         xp += op.rb[i] * x[i];
       }
-      int im = 0, ip = 0;
-      if (e < E) {
-        im = faces[slot_base + e * 6 + 2 * ax].info;
-        ip = faces[slot_base + e * 6 + 2 * ax + 1].info;
-      }
+      const int im = sFR[le * 6 + 2 * ax].info, ip = sFR[le * 6 + 2 * ax + 1].info;
       const R jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax) * 5 + v) * NFP + r] - xm);
       const R jp = ((ip & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax + 1) * 5 + v) * NFP + r] - xp);
       const R sc = DIAG ? sMet[le][4 * ax] : R(1);
@@ -258,11 +297,11 @@ __global__ void __launch_bounds__(NT)
       fp[fld] = sp;
     }
 #pragma unroll
-    for (int sg = 0; sg < 2; ++sg) {
-      const R* w = sg ? fp : fm;
-      const int slot = slot_base + e * 6 + 2 * ax + sg;
-      const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
-      const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+    for (int side = 0; side < 2; ++side) {
+      const R* w = side ? fp : fm;
+      const int lf = le * 6 + 2 * ax + side, slot = slot_base + e * 6 + 2 * ax + side;
+      const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
       R u[5], q[3][5], V[4];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {

@@ -191,29 +191,72 @@ __global__ void __launch_bounds__(NT_)
     R* dst = reinterpret_cast<R*>(&tri);
     for (int it = tid; it < NW; it += NT_) dst[it] = src[it];
   }
-  for (int it = tid; it < EB * 5 * NU; it += NT_) {
-    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
-    R val = R(0);
+  // face records, face geometry and the permutation table go to LDS first,
+  // so the neighbour gather is one global load per value; every thread
+  // issues all of its state and gather loads before the first use
+  __shared__ FaceRec sFR[EB * 5];
+  __shared__ R sFG[EB * 5][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFP];
+  for (int it = tid; it < EB * 5; it += NT_) {
+    const int e = e0 + it / 5;
+    FaceRec fr{0, 0};
+    R g4[4] = {R(0), R(0), R(0), R(0)};
     if (e < E) {
-      double x = U[(size_t)e * 5 * NU + r];
-      if (r >= 4 * NU) x -= eref;
-      val = R(x);
+      const int slot = slot_base + e0 * 5 + it;
+      fr = faces[slot];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g4[k] = fgeo[4 * slot + k];
     }
-    XS(le)[r] = val;
+    sFR[it] = fr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sFG[it][k] = g4[k];
   }
+  for (int it = tid; it < sg.nperm * NFP; it += NT_) sPerm[it] = perms[it];
   for (int it = tid; it < EB * 10; it += NT_) {
     const int le = it / 10, k = it - le * 10, e = e0 + le;
     sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
   }
-  for (int it = tid; it < EB * 25 * NFP; it += NT_) {
-    const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
-    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP, e = e0 + le;
-    R val = R(0);
-    if (e < E && (f >= 2 || r < NTN)) {
-      const FaceRec fr = faces[slot_base + e * 5 + f];
-      val = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + perms[(fr.info >> 1) * NFP + r]];
+  constexpr int NS = (EB * 5 * NU + NT_ - 1) / NT_;
+  double xs[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT_;
+    xs[k] = 0.0;
+    if (it < EB * 5 * NU && e0 + it / (5 * NU) < E) xs[k] = U[(size_t)e0 * 5 * NU + it];
+  }
+  __syncthreads();
+  constexpr int NG = (EB * 25 * NFP + NT_ - 1) / NT_;
+  R gv[NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int it = tid + k * NT_;
+    gv[k] = R(0);
+    if (it < EB * 25 * NFP) {
+      const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
+      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+      if (e0 + le < E && (f >= 2 || r < NTN)) {
+        const FaceRec fr = sFR[le * 5 + f];
+        gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + r]];
+      }
     }
-    JS(le)[r0] = val;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT_;
+    if (it < EB * 5 * NU) {
+      const int le = it / (5 * NU), r = it - le * (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      XS(le)[r] = R(x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int it = tid + k * NT_;
+    if (it < EB * 25 * NFP) {
+      const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
+      JS(le)[r0] = gv[k];
+    }
   }
   __syncthreads();
 
@@ -233,11 +276,7 @@ __global__ void __launch_bounds__(NT_)
         xm += op.lb[k] * x;
         xp += op.rb[k] * x;
       }
-      int im = 0, ip = 0;
-      if (e < E) {
-        im = faces[slot_base + e * 5].info;
-        ip = faces[slot_base + e * 5 + 1].info;
-      }
+      const int im = sFR[le * 5].info, ip = sFR[le * 5 + 1].info;
       R* jm = JS(le) + (0 * 5 + v) * NFP + t;
       R* jp = JS(le) + (1 * 5 + v) * NFP + t;
       *jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jm - xm);
@@ -248,7 +287,7 @@ __global__ void __launch_bounds__(NT_)
       R s = R(0);
 #pragma unroll
       for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * X[v * NU + t + NTN * k];
-      const int info = e < E ? faces[slot_base + e * 5 + 2 + ed].info : 0;
+      const int info = sFR[le * 5 + 2 + ed].info;
       R* jj = JS(le) + ((2 + ed) * 5 + v) * NFP + i + n * k;
       *jj = ((info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jj - s);
     }
@@ -337,11 +376,11 @@ __global__ void __launch_bounds__(NT_)
         fp[fld] = sp;
       }
 #pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        const R* w = sg ? fp : fm;
-        const int slot = slot_base + e * 5 + sg;
-        const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
-        const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+      for (int side = 0; side < 2; ++side) {
+        const R* w = side ? fp : fm;
+        const int lf = le * 5 + side, slot = slot_base + e * 5 + side;
+        const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+        const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
         R u[5], q[3][5], V[4];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -355,9 +394,9 @@ __global__ void __launch_bounds__(NT_)
       }
     } else {
       const int r1 = r0 - NV_TRI, ed = r1 / (n * n), r2 = r1 - ed * (n * n), k = r2 / n, i = r2 - k * n;
-      const int slot = slot_base + e * 5 + 2 + ed;
-      const R sgn = (faces[slot].info & 1) ? R(1) : R(-1);
-      const R nn[3] = {sgn * fgeo[4 * slot], sgn * fgeo[4 * slot + 1], sgn * fgeo[4 * slot + 2]};
+      const int lf = le * 5 + 2 + ed, slot = slot_base + e * 5 + 2 + ed;
+      const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
       R u[5], q[3][5], V[4];
 #pragma unroll
       for (int fld = 0; fld < 20; ++fld) {

@@ -28,7 +28,6 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxPerms = 64;  // distinct face-point permutations reserved per mesh
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // First-fit allocator over byte offsets [0, cap), coalescing on release.
@@ -104,7 +103,7 @@ Layout make_layout(const fr_request& q, int rs) {
   L.Vf = take((size_t)rs * L.nslots * 4 * L.nfp);
   L.faces = take(sizeof(fr::FaceRec) * L.nslots);
   L.fgeo = take((size_t)rs * 4 * L.nslots);
-  L.perms = take((size_t)kMaxPerms * L.nfp);
+  L.perms = take((size_t)fr::MAX_PERMS * L.nfp);
   for (int t = 0; t < 2; ++t) {
     L.met[t] = take((size_t)rs * 10 * L.nel[t]);
     L.detj[t] = take(8 * L.nel[t]);
@@ -119,6 +118,7 @@ Layout make_layout(const fr_request& q, int rs) {
 struct Prepared {
   std::string err;  // non-empty: the mesh could not be built
   int64_t nel[2] = {0, 0}, slot_base[2] = {0, 0}, nslots = 0;
+  int nperm = 0;
   bool diag[2] = {false, false};
   std::vector<fr::FaceRec> faces;
   std::vector<unsigned char> fgeo, met[2];  // precision of the pool
@@ -144,7 +144,7 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[2
   }
   if (!R.err.empty()) return out;
   const int64_t nfp = (int64_t)(q.p + 1) * (q.p + 1);
-  if ((int64_t)M.perms.size() > kMaxPerms) {
+  if ((int64_t)M.perms.size() > fr::MAX_PERMS) {
     R.err = "too many face permutations";
     return out;
   }
@@ -162,6 +162,7 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[2
     to_prec<float>(R.fgeo, geo.data(), geo.size());
   else
     to_prec<double>(R.fgeo, geo.data(), geo.size());
+  R.nperm = (int)M.perms.size();
   R.perms.assign(M.perms.size() * nfp, 0);
   for (size_t k = 0; k < M.perms.size(); ++k)
     for (size_t r = 0; r < M.perms[k].size(); ++r) R.perms[k * nfp + r] = (uint8_t)M.perms[k][r];
@@ -420,6 +421,7 @@ fr_status admit(fr_pool* P, Req& R) {
     g.dt = q.dt;
     g.E = (int32_t)E;
     g.slot_base = (int32_t)M.slot_base[t];
+    g.nperm = M.nperm;
     if (!q.u_init) {
       // Taylor-Green state from element origins, Jacobians and reference points
       const fr::RefElem& r = P->ref[t][q.p];

@@ -18,7 +18,7 @@ def _expected_bytes(n, p, kind, rs):
     ns = 5 * (ne[0] * nu[0] + ne[1] * nu[1])
     slots = 6 * ne[0] + 5 * ne[1]
     parts = [8 * ns, 8 * ns, 8 * ns, rs * ns, rs * slots * 5 * k * k, rs * slots * 4 * k * k, 8 * slots,
-             rs * 4 * slots, 64 * k * k]
+             rs * 4 * slots, 16 * k * k]
     for t in range(2):
         parts += [rs * 10 * ne[t], 8 * ne[t]]
     return sum(al(x) for x in parts), ns

@@ -30,6 +30,17 @@ __device__ __forceinline__ float rcp<float>(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// orders global memory, which makes every barrier wait for all outstanding
+// global loads and stores of the wave; kernels whose global data is never
+// exchanged between the waves of a workgroup use this one so that prefetched
+// loads stay in flight across barriers.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Physical flux f = f^e - f^v at one point.  u: 5 conserved (reference
 // form), q[d][v]: physical gradients d/dx_d of the conserved variables.
 // f[d][v]: component d of the flux of variable v.

@@ -124,6 +124,105 @@ struct HexVol {
   static constexpr int PER_ELEM = SZ_A + SZ_B;
 };
 
+// Loads of one batch of EB elements, held in registers: the state, face
+// records, face geometry and metrics first (independent loads), then the
+// neighbour face states (gathered through face records in LDS).  Every
+// thread issues all of its loads before the first use.
+template <int P, typename R, int EB, int NT>
+struct HexVolLoads {
+  using C = HexVol<P>;
+  static constexpr int NU = C::NU, NFP = C::NFP;
+  static constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
+  static constexpr int NG = (EB * 30 * NFP + NT - 1) / NT;
+  static constexpr int NF = (EB * 6 + NT - 1) / NT;
+  static constexpr int NM = (EB * 10 + NT - 1) / NT;
+  double xs[NS];
+  R gv[NG];
+  FaceRec fr[NF];
+  R fg[NF][4];
+  R mt[NM];
+
+  // branch-free: an out-of-range item loads from a valid address (the
+  // segment's first element) and its value is never used for an output (every
+  // store of the kernel is guarded by the element count), so no select
+  // follows the load and the compiler can keep all loads in flight
+  __device__ __forceinline__ void load(const double* __restrict__ U, const FaceRec* __restrict__ faces,
+                                       const R* __restrict__ fgeo, const R* __restrict__ met, int e0, int E,
+                                       int slot_base, int tid) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int it = tid + k * NT;
+      const bool ok = it < EB * 6 && e0 + it / 6 < E;
+      const int slot = slot_base + (ok ? e0 * 6 + it : 0);
+      fr[k] = faces[slot];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fg[k][c] = fgeo[4 * slot + c];
+    }
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      const int it = tid + k * NT;
+      const bool ok = it < EB * 10 && e0 + it / 10 < E;
+      mt[k] = met[ok ? (size_t)e0 * 10 + it : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int it = tid + k * NT;
+      const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
+      xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
+    }
+  }
+  __device__ __forceinline__ void put_faces(FaceRec* sFR, R (*sFG)[4], int tid) const {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 6) {
+        sFR[it] = fr[k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sFG[it][c] = fg[k][c];
+      }
+    }
+  }
+  // face records of out-of-range elements are those of a valid slot, so
+  // every gathered address is valid; only in-range values are ever used
+  __device__ __forceinline__ void gather(const R* __restrict__ Uf, const FaceRec* sFR, const uint8_t* sPerm, int tid) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int it = tid + k * NT;
+      const int itc = it < EB * 30 * NFP ? it : 0;
+      const int le = itc / (30 * NFP), r0 = itc - le * (30 * NFP);
+      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+      const FaceRec q = sFR[le * 6 + f];
+      gv[k] = Uf[(size_t)q.nbr * 5 * NFP + v * NFP + sPerm[(q.info >> 1) * NFP + r]];
+    }
+  }
+  // state in reference form, metrics and neighbour states to LDS
+  __device__ __forceinline__ void put_elems(R* smem, R (*sMet)[10], double eref, int tid) const {
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 10) sMet[it / 10][it % 10] = mt[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 5 * NU) {
+        const int le = it / (5 * NU), r = it - le * (5 * NU);
+        double x = xs[k];
+        if (r >= 4 * NU) x -= eref;
+        smem[le * C::PER_ELEM + r] = R(x);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 30 * NFP) {
+        const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
+        smem[le * C::PER_ELEM + C::SZ_A + r0] = gv[k];
+      }
+    }
+  }
+};
+
 template <int P, typename R, int EB, int NT, bool DIAG, bool BT>
 __global__ void __launch_bounds__(NT)
     hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
@@ -133,6 +232,10 @@ __global__ void __launch_bounds__(NT)
   static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
+  __shared__ FaceRec sFR[EB * 6];
+  __shared__ R sFG[EB * 6][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFP];
+  __shared__ R sI[m][n];  // interpolation rows, read with a per-thread row index
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -141,7 +244,6 @@ __global__ void __launch_bounds__(NT)
   R* __restrict__ Rp = (R*)sg.Rp;
   const FaceRec* __restrict__ faces = sg.faces;
   const R* __restrict__ fgeo = (const R*)sg.fgeo;
-  const uint8_t* __restrict__ perms = sg.perms;
   const R* __restrict__ met = (const R*)sg.met;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
@@ -152,73 +254,18 @@ __global__ void __launch_bounds__(NT)
 
   // phase 0: state (reference form), metrics, neighbour states at own
   // faces.  Face records, face geometry and the permutation table go to LDS
-  // first, so the neighbour gather is one global load per value, and every
-  // thread issues all of its loads before the first use.
-  __shared__ FaceRec sFR[EB * 6];
-  __shared__ R sFG[EB * 6][4];
-  __shared__ uint8_t sPerm[MAX_PERMS * NFP];
-  for (int it = tid; it < EB * 6; it += NT) {
-    const int e = e0 + it / 6;
-    FaceRec fr{0, 0};
-    R g4[4] = {R(0), R(0), R(0), R(0)};
-    if (e < E) {
-      const int slot = slot_base + e0 * 6 + it;
-      fr = faces[slot];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) g4[k] = fgeo[4 * slot + k];
-    }
-    sFR[it] = fr;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sFG[it][k] = g4[k];
-  }
-  for (int it = tid; it < sg.nperm * NFP; it += NT) sPerm[it] = perms[it];
-  for (int it = tid; it < EB * 10; it += NT) {
-    const int le = it / 10, k = it - le * 10, e = e0 + le;
-    sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
-  }
-  constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
-  double xs[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int it = tid + k * NT;
-    xs[k] = 0.0;
-    if (it < EB * 5 * NU && e0 + it / (5 * NU) < E) xs[k] = U[(size_t)e0 * 5 * NU + it];
-  }
-  __syncthreads();
-  constexpr int NG = (EB * 30 * NFP + NT - 1) / NT;
-  R gv[NG];
-#pragma unroll
-  for (int k = 0; k < NG; ++k) {
-    const int it = tid + k * NT;
-    gv[k] = R(0);
-    if (it < EB * 30 * NFP) {
-      const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
-      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-      if (e0 + le < E) {
-        const FaceRec fr = sFR[le * 6 + f];
-        gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + r]];
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int it = tid + k * NT;
-    if (it < EB * 5 * NU) {
-      const int le = it / (5 * NU), r = it - le * (5 * NU);
-      double x = xs[k];
-      if (r >= 4 * NU) x -= eref;
-      XS(le)[r] = R(x);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NG; ++k) {
-    const int it = tid + k * NT;
-    if (it < EB * 30 * NFP) {
-      const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
-      JS(le)[r0] = gv[k];
-    }
-  }
-  __syncthreads();
+  // first, so the neighbour gather is one global load per value.
+  for (int it = tid; it < sg.nperm * NFP; it += NT) sPerm[it] = sg.perms[it];
+  if (tid < m * n) sI[tid / n][tid % n] = op.I[tid / n][tid % n];
+  HexVolLoads<P, R, EB, NT> ld;
+  ld.load(U, faces, fgeo, met, e0, E, slot_base, tid);
+  ld.put_faces(sFR, sFG, tid);
+  lds_barrier();
+  ld.gather(Uf, sFR, sPerm, tid);
+  ld.put_elems(smem, sMet, eref, tid);
+  lds_barrier();
+  const FaceRec* cFR = sFR;
+  const R (*cFG)[4] = sFG;
 
   // phase 1: per axis and line: own face values, jumps C - u^f (eq. FR-conu:
   // L side (1/2 + beta)(u_nbr - u_own), R side (1/2 - beta)(u_nbr - u_own)),
@@ -226,8 +273,6 @@ __global__ void __launch_bounds__(NT)
   // metric the J^-T scaling of eq. FR-gradcoru is applied here as well.
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    constexpr int dummy = 0;
-    (void)dummy;
     const int si = ax == 0 ? 1 : (ax == 1 ? n : n * n);
     const int sa = ax == 0 ? n : 1, sb = ax == 2 ? n : n * n;
     for (int it = tid; it < EB * 5 * NFP; it += NT) {
@@ -244,7 +289,7 @@ __global__ void __launch_bounds__(NT)
         xm += op.lb[i] * x[i];
         xp += op.rb[i] * x[i];
       }
-      const int im = sFR[le * 6 + 2 * ax].info, ip = sFR[le * 6 + 2 * ax + 1].info;
+      const int im = cFR[le * 6 + 2 * ax].info, ip = cFR[le * 6 + 2 * ax + 1].info;
       const R jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax) * 5 + v) * NFP + r] - xm);
       const R jp = ((ip & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (JS(le)[((2 * ax + 1) * 5 + v) * NFP + r] - xp);
       const R sc = DIAG ? sMet[le][4 * ax] : R(1);
@@ -257,7 +302,7 @@ __global__ void __launch_bounds__(NT)
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   if (!DIAG) {
     // phase 2: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
@@ -272,7 +317,7 @@ __global__ void __launch_bounds__(NT)
           X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // phase 3a: gradcoru_fpts + normal viscous flux at the own flux points
@@ -300,8 +345,8 @@ __global__ void __launch_bounds__(NT)
     for (int side = 0; side < 2; ++side) {
       const R* w = side ? fp : fm;
       const int lf = le * 6 + 2 * ax + side, slot = slot_base + e * 6 + 2 * ax + side;
-      const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
-      const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+      const R sgn = (cFR[lf].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * cFG[lf][0], sgn * cFG[lf][1], sgn * cFG[lf][2]};
       R u[5], q[3][5], V[4];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -330,7 +375,7 @@ __global__ void __launch_bounds__(NT)
       T[a * NFP] = s;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 4: one quadrature column (a, b) per thread: y interpolation, then
   // for each z level: z interpolation (uqpts, gradcoru_qpts), the flux
@@ -341,12 +386,7 @@ __global__ void __launch_bounds__(NT)
   if (col) {
     R Ib[n];
 #pragma unroll
-    for (int j = 0; j < n; ++j) {
-      R t = op.I[0][j];
-#pragma unroll
-      for (int bb = 1; bb < m; ++bb) t = cb == bb ? op.I[bb][j] : t;
-      Ib[j] = t;
-    }
+    for (int j = 0; j < n; ++j) Ib[j] = sI[cb][j];
     R t2[20][n];
     const R* T = TS(cle) + ca * NFP;
 #pragma unroll
@@ -394,7 +434,7 @@ __global__ void __launch_bounds__(NT)
         }
     }
   }
-  __syncthreads();  // every column has read T1; Z may now overwrite it
+  lds_barrier();  // every column has read T1; Z may now overwrite it
   if (col) {
     R* Z = ZS(cle);
 #pragma unroll
@@ -404,7 +444,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
         for (int l = 0; l < n; ++l) Z[(((d * 5 + v) * m + ca) * m + cb) * n + l] = acc[d][v][l];
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 5: y projection: X' = P_y X, Y' = AP_y Y + P_y Z
   for (int it = tid; it < EB * 5 * m * n; it += NT) {
@@ -431,7 +471,7 @@ __global__ void __launch_bounds__(NT)
       Y[(((1 * 5 + v) * m + a) * n + j) * n + l] = sy;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 6: x projection: R_vol = AP_x X' + P_x Y'
   for (int it = tid; it < EB * 5 * NFP; it += NT) {

@@ -197,48 +197,41 @@ __global__ void __launch_bounds__(NT_)
   __shared__ FaceRec sFR[EB * 5];
   __shared__ R sFG[EB * 5][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFP];
+  // out-of-range items load from a valid address (the segment's first
+  // element) without a select afterwards, so every load stays in flight;
+  // their values never reach an output (all stores are guarded)
   for (int it = tid; it < EB * 5; it += NT_) {
-    const int e = e0 + it / 5;
-    FaceRec fr{0, 0};
-    R g4[4] = {R(0), R(0), R(0), R(0)};
-    if (e < E) {
-      const int slot = slot_base + e0 * 5 + it;
-      fr = faces[slot];
+    const int slot = slot_base + (e0 + it / 5 < E ? e0 * 5 + it : 0);
+    sFR[it] = faces[slot];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) g4[k] = fgeo[4 * slot + k];
-    }
-    sFR[it] = fr;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sFG[it][k] = g4[k];
+    for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
   }
   for (int it = tid; it < sg.nperm * NFP; it += NT_) sPerm[it] = perms[it];
   for (int it = tid; it < EB * 10; it += NT_) {
     const int le = it / 10, k = it - le * 10, e = e0 + le;
-    sMet[le][k] = e < E ? met[(size_t)e * 10 + k] : R(0);
+    sMet[le][k] = met[e < E ? (size_t)e * 10 + k : 0];
   }
   constexpr int NS = (EB * 5 * NU + NT_ - 1) / NT_;
   double xs[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int it = tid + k * NT_;
-    xs[k] = 0.0;
-    if (it < EB * 5 * NU && e0 + it / (5 * NU) < E) xs[k] = U[(size_t)e0 * 5 * NU + it];
+    const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
+    xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
-  __syncthreads();
+  lds_barrier();
   constexpr int NG = (EB * 25 * NFP + NT_ - 1) / NT_;
   R gv[NG];
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
     const int it = tid + k * NT_;
-    gv[k] = R(0);
-    if (it < EB * 25 * NFP) {
-      const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
-      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-      if (e0 + le < E && (f >= 2 || r < NTN)) {
-        const FaceRec fr = sFR[le * 5 + f];
-        gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + r]];
-      }
-    }
+    const int itc = it < EB * 25 * NFP ? it : 0;
+    const int le = itc / (25 * NFP), r0 = itc - le * (25 * NFP);
+    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
+    // triangle faces have NTN < NFP points: the unused tail reads point 0
+    const int rr = (f >= 2 || r < NTN) ? r : 0;
+    const FaceRec fr = sFR[le * 5 + f];
+    gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + rr]];
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -258,7 +251,7 @@ __global__ void __launch_bounds__(NT_)
       JS(le)[r0] = gv[k];
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 1: jumps C - u^f (eq. FR-conu) at every own flux point, in place
   // over the neighbour values: triangle faces (line interpolation in zeta),
@@ -292,7 +285,7 @@ __global__ void __launch_bounds__(NT_)
       *jj = ((info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jj - s);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 2: corrected reference gradient (eq. FR-qfinal): zeta along the
   // lines with the triangle-face lifting; (xi, eta) per output point with the
@@ -338,7 +331,7 @@ __global__ void __launch_bounds__(NT_)
       X[(10 + v) * NU + t + NTN * k] = sy;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru)
   for (int it = tid; it < EB * NU; it += NT_) {
@@ -352,7 +345,7 @@ __global__ void __launch_bounds__(NT_)
         X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 4a: normal viscous flux at own flux points (gradcoru_fpts)
   constexpr int NV_TRI = NTN, NV_QUAD = 3 * n * n;
@@ -424,7 +417,7 @@ __global__ void __launch_bounds__(NT_)
     for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * x[t];
     TS(le)[r0] = s;  // [fld][k][tq]
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 5: line columns over the triangle quadrature points, two threads
   // per column (alternate zeta levels): zeta interpolation, flux (tdisf) and
@@ -493,7 +486,7 @@ __global__ void __launch_bounds__(NT_)
     for (int v = 0; v < 5; ++v)
 #pragma unroll
       for (int k = 0; k < n; ++k) acc[d][v][k] = pair_sum(acc[d][v][k]);
-  __syncthreads();  // every column has read T1; Z may now overwrite it
+  lds_barrier();  // every column has read T1; Z may now overwrite it
   if (col) {
     R* Z = ZS(cle);
     // both threads of a pair hold the same sums; each writes half the values
@@ -505,7 +498,7 @@ __global__ void __launch_bounds__(NT_)
         for (int k = 0; k < n; ++k)
           if (((d * 5 + v) * n + k) % 2 == half) Z[((d * 5 + v) * NTQ + ctq) * n + k] = acc[d][v][k];
   }
-  __syncthreads();
+  lds_barrier();
 
   // phase 6: triangle-plane projection-divergence, one output point per thread
   for (int it = tid; it < EB * 5 * n * NTN; it += NT_) {

@@ -239,18 +239,17 @@ def cpu_baseline(budget_s=20.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    N = 4
-    elapsed = 0.0
-    while True:
+    def run(N):
         m = Mesh(N, N, N, 3, "hex")
         U = {t: u for t, u in zip(m.types, inputs.element_state([m.upts_coords(t) for t in m.types]))}
         t0 = time.perf_counter()
         rhs(m, U, Params(pref=inputs.P0))
-        elapsed = time.perf_counter() - t0
-        dof = 5 * m.nelem["hex"] * m.refs["hex"].nu
-        if elapsed * 8 > budget_s or N >= 24:
-            break
-        N *= 2
+        return time.perf_counter() - t0, 5 * m.nelem["hex"] * m.refs["hex"].nu
+
+    # an 8^3 probe sizes the sample box for about budget_s of work
+    t8, _ = run(8)
+    N = int(max(8, min(32, round(8 * (budget_s / max(t8, 1e-3)) ** (1.0 / 3.0)))))
+    elapsed, dof = run(N)
     return {"value": dof / elapsed / 1e9, "unit": "GDoF-RHS/s", "cores": int(threads), "kind": "oracle",
             "sample": "one RHS of the TGV hex p=3 flux-AA case on a %d^3 periodic box (%d DoF), %.2f s" %
                       (N, dof, elapsed)}

@@ -127,4 +127,51 @@ __device__ __forceinline__ void rk_store(const Seg& s, int rk, size_t i, double 
   s.ust[i] = u + b * k;
 }
 
+// rk_store for the NL values a thread holds: item it = tid + k NT of a
+// workgroup covering elements [e0, e0 + elems) with per elements values,
+// valid while it < total and its element < E.  In an RK stage every state
+// load is issued before the first store.
+template <int NL, int NT>
+__device__ __forceinline__ void rk_store_block(const Seg& s, int rk, int e0, int E, int per, int total, int tid,
+                                               const double (&val)[NL]) {
+  size_t idx[NL];
+  bool ok[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int it = tid + k * NT;
+    ok[k] = it < total && e0 + it / per < E;
+    idx[k] = ok[k] ? (size_t)e0 * per + it : 0;
+  }
+  if (rk < 0) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (ok[k]) s.du[idx[k]] = val[k];
+    return;
+  }
+  const double dt = s.dt;
+  if (rk == 3) {
+    double a[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) a[k] = s.acc[idx[k]];
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (ok[k]) s.U[idx[k]] = a[k] + (dt / 6) * val[k];
+    return;
+  }
+  const double ca = rk == 0 ? dt / 6 : dt / 3;
+  const double cb = rk == 2 ? dt : dt / 2;
+  double u[NL], a[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    u[k] = s.U[idx[k]];
+    a[k] = rk == 0 ? u[k] : s.acc[idx[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k)
+    if (ok[k]) {
+      s.acc[idx[k]] = a[k] + ca * val[k];
+      s.ust[idx[k]] = u[k] + cb * val[k];
+    }
+}
+
 }  // namespace fr

@@ -79,17 +79,25 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   R* __restrict__ Uf = (R*)sg.Uf;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
-    R val = R(0);
-    if (e < E) {
-      double x = U[(size_t)e * 5 * NU + r];
-      if (r >= 4 * NU) x -= eref;
-      val = R(x);
-    }
-    sU[it] = val;
+  constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
+  double xs[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT;
+    const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
+    xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 5 * NU) {
+      const int r = it % (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      sU[it] = R(x);
+    }
+  }
+  lds_barrier();
   for (int it = tid; it < EB * 15 * NFP; it += NT) {
     const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
     const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
@@ -501,13 +509,24 @@ __global__ void __launch_bounds__(NT)
 }
 
 // -------------------------------------------------------------- surface
+// Face records, face geometry, the permutation table, the lifting weights
+// and det J are staged in LDS; the volume residual is prefetched before the
+// first barrier; every flux point's own and neighbour loads are issued
+// branch-free (out-of-range items read a valid address and are dropped).
 template <int P, typename R, int EB, int NT, bool BT>
 __global__ void __launch_bounds__(NT)
     hex_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
                 const HexOps<P, R> op, const Gas<R> g) {
   using C = HexCfg<P>;
   constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
+  constexpr int NI = (EB * 6 * NFP + NT - 1) / NT;  // flux points per thread
+  constexpr int NL = (EB * 5 * NU + NT - 1) / NT;   // solution values per thread
   __shared__ R sD[EB * 30 * NFP];
+  __shared__ FaceRec sFR[EB * 6];
+  __shared__ R sFG[EB * 6][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFP];
+  __shared__ R sLift[2][n];
+  __shared__ double sDet[EB];
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -515,51 +534,85 @@ __global__ void __launch_bounds__(NT)
   const R* __restrict__ Rp = (const R*)sg.Rp;
   const FaceRec* __restrict__ faces = sg.faces;
   const R* __restrict__ fgeo = (const R*)sg.fgeo;
-  const uint8_t* __restrict__ perms = sg.perms;
-  const double* __restrict__ detj = sg.detj;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
+  for (int it = tid; it < EB * 6; it += NT) {
+    const int slot = slot_base + (e0 + it / 6 < E ? e0 * 6 + it : 0);
+    sFR[it] = faces[slot];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sFG[it][c] = fgeo[4 * slot + c];
+  }
+  for (int it = tid; it < sg.nperm * NFP; it += NT) sPerm[it] = sg.perms[it];
+  if (tid < n) {
+    sLift[0][tid] = op.liftL[tid];
+    sLift[1][tid] = op.liftR[tid];
+  }
+  if (tid < EB) sDet[tid] = sg.detj[e0 + tid < E ? e0 + tid : 0];
+  R rp[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int it = tid + k * NT;
+    const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
+    rp[k] = Rp[ok ? (size_t)e0 * 5 * NU + it : 0];
+  }
+  lds_barrier();
   // comm_flux: common normal flux at every own flux point, times +-mag
-  for (int it = tid; it < EB * 6 * NFP; it += NT) {
-    const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
-    if (e >= E) continue;
-    const int slot = slot_base + e * 6 + f;
-    const FaceRec fr = faces[slot];
-    const int rr = perms[(fr.info >> 1) * NFP + r];
-    const bool left = fr.info & 1;
-    R uo[5], un[5], Vo[4], Vn[4], F[5];
+  {
+    R uo[NI][5], un[NI][5], Vo[NI][4], Vn[NI][4];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      uo[v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
-      un[v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    for (int q = 0; q < NI; ++q) {
+      const int it = tid + q * NT;
+      const int itc = it < EB * 6 * NFP ? it : 0;
+      const int le = itc / (6 * NFP), r0 = itc - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP;
+      const int slot = slot_base + (e0 + le < E ? (e0 + le) * 6 + f : 0);
+      const FaceRec fr = sFR[le * 6 + f];
+      const int rr = sPerm[(fr.info >> 1) * NFP + r];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        uo[q][v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
+        un[q][v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Vo[q][k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
+        Vn[q][k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Vo[k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
-      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
-    }
-    const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
-    const R mag = fgeo[4 * slot + 3];
-    if (left)
-      common_flux(uo, un, Vo, Vn, nL, g, F);
-    else
-      common_flux(un, uo, Vn, Vo, nL, g, F);
-    const R sc = left ? mag : -mag;
+    for (int q = 0; q < NI; ++q) {
+      const int it = tid + q * NT;
+      if (it >= EB * 6 * NFP) continue;
+      const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP;
+      const int lf = le * 6 + f;
+      const bool left = sFR[lf].info & 1;
+      const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
+      const R mag = sFG[lf][3];
+      R F[5];
+      if (left)
+        common_flux(uo[q], un[q], Vo[q], Vn[q], nL, g, F);
+      else
+        common_flux(un[q], uo[q], Vn[q], Vo[q], nL, g, F);
+      const R sc = left ? mag : -mag;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sD[(le * 6 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
+      for (int v = 0; v < 5; ++v) sD[lf * 5 * NFP + v * NFP + r] = sc * F[v];
+    }
   }
-  __syncthreads();
+  lds_barrier();
   // tdivtconf (lift of the common flux, DG correction) + negdivconf
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
-    if (e >= E) continue;
-    const int i = s % n, j = (s / n) % n, k = s / (n * n);
+  double val[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int it = tid + k * NT;
+    const int itc = it < EB * 5 * NU ? it : 0;
+    const int le = itc / (5 * NU), r0 = itc - le * (5 * NU), v = r0 / NU, s = r0 - v * NU;
+    const int i = s % n, j = (s / n) % n, kk = s / (n * n);
     const R* D = sD + le * 30 * NFP + v * NFP;
-    R acc = Rp[(size_t)e * 5 * NU + r0];
-    acc += sel(op.liftL, i) * D[0 * 5 * NFP + j + n * k] + sel(op.liftR, i) * D[1 * 5 * NFP + j + n * k];
-    acc += sel(op.liftL, j) * D[2 * 5 * NFP + i + n * k] + sel(op.liftR, j) * D[3 * 5 * NFP + i + n * k];
-    acc += sel(op.liftL, k) * D[4 * 5 * NFP + i + n * j] + sel(op.liftR, k) * D[5 * 5 * NFP + i + n * j];
-    rk_store(sg, rk, (size_t)e * 5 * NU + r0, -double(acc) / detj[e]);
+    R acc = rp[k];
+    acc += sLift[0][i] * D[0 * 5 * NFP + j + n * kk] + sLift[1][i] * D[1 * 5 * NFP + j + n * kk];
+    acc += sLift[0][j] * D[2 * 5 * NFP + i + n * kk] + sLift[1][j] * D[3 * 5 * NFP + i + n * kk];
+    acc += sLift[0][kk] * D[4 * 5 * NFP + i + n * j] + sLift[1][kk] * D[5 * 5 * NFP + i + n * j];
+    val[k] = -double(acc) / sDet[le];
   }
+  rk_store_block<NL, NT>(sg, rk, e0, E, 5 * NU, EB * 5 * NU, tid, val);
 }
 
 // ------------------------------------------------------------ launchers
@@ -613,8 +666,14 @@ template <> struct HexLaunch<2, true> { static constexpr int EB = 2, NT = 64; };
 template <> struct HexLaunch<3, true> { static constexpr int EB = 1, NT = 64; };    // 36
 template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 49
 
-// elements per workgroup of the disu and surface kernels (256 threads)
-constexpr int HEX_DISU_EB = 8, HEX_SURF_EB = 4;
+// elements per workgroup of the disu kernel (256 threads)
+constexpr int HEX_DISU_EB = 8;
+// elements per workgroup of the interface kernel (256 threads): at most two
+// flux points and about five solution values per thread
+template <int P, bool DBL>
+struct HexSurf {
+  static constexpr int EB = (DBL ? 8 : 16) >> (P - 1);
+};
 
 template <int P, typename R, bool BT>
 static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
@@ -622,7 +681,7 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const Gas<R> g = make_gas<R>(*a.gas);
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
-  constexpr int EBA = HEX_DISU_EB, NTA = 256, EBC = HEX_SURF_EB, NTC = 256;
+  constexpr int EBA = HEX_DISU_EB, NTA = 256, EBC = HexSurf<P, dbl>::EB, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
@@ -643,7 +702,7 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
 template <int P, typename R>
 static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB, HEX_SURF_EB};
+  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB, HexSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
   for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
@@ -656,8 +715,16 @@ static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
 
 int hex_block_elems(int p, int prec, int k) {
   if (k == K_DISU) return HEX_DISU_EB;
-  if (k == K_SURFACE) return HEX_SURF_EB;
   const bool d = prec == 0;
+  if (k == K_SURFACE) {
+    switch (p) {
+      case 1: return d ? HexSurf<1, true>::EB : HexSurf<1, false>::EB;
+      case 2: return d ? HexSurf<2, true>::EB : HexSurf<2, false>::EB;
+      case 3: return d ? HexSurf<3, true>::EB : HexSurf<3, false>::EB;
+      case 4: return d ? HexSurf<4, true>::EB : HexSurf<4, false>::EB;
+    }
+    return 0;
+  }
   switch (p) {
     case 1: return d ? HexLaunch<1, true>::EB : HexLaunch<1, false>::EB;
     case 2: return d ? HexLaunch<2, true>::EB : HexLaunch<2, false>::EB;

@@ -82,17 +82,25 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   R* __restrict__ Uf = (R*)sg.Uf;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
-  for (int it = tid; it < EB * 5 * NU; it += NT_) {
-    const int le = it / (5 * NU), r = it - le * (5 * NU), e = e0 + le;
-    R val = R(0);
-    if (e < E) {
-      double x = U[(size_t)e * 5 * NU + r];
-      if (r >= 4 * NU) x -= eref;
-      val = R(x);
-    }
-    sU[it] = val;
+  constexpr int NS = (EB * 5 * NU + NT_ - 1) / NT_;
+  double xs[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT_;
+    const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
+    xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int it = tid + k * NT_;
+    if (it < EB * 5 * NU) {
+      const int r = it % (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      sU[it] = R(x);
+    }
+  }
+  lds_barrier();
   // triangle faces: line interpolation in zeta at every node
   for (int it = tid; it < EB * 5 * NT; it += NT_) {
     const int le = it / (5 * NT), r = it - le * (5 * NT), v = r / NT, t = r - v * NT, e = e0 + le;
@@ -682,8 +690,13 @@ template <> struct PrismLaunch<2, true> { static constexpr int EB = 3, NT = 64; 
 template <> struct PrismLaunch<3, true> { static constexpr int EB = 2, NT = 64; };    // 64
 template <> struct PrismLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 50
 
-// elements per workgroup of the disu and surface kernels (256 threads)
-constexpr int PRISM_DISU_EB = 8, PRISM_SURF_EB = 4;
+// elements per workgroup of the disu kernel (256 threads)
+constexpr int PRISM_DISU_EB = 8;
+// elements per workgroup of the interface kernel (256 threads)
+template <int P, bool DBL>
+struct PrismSurf {
+  static constexpr int EB = 4;
+};
 
 template <int P, typename R, bool BT>
 static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
@@ -692,7 +705,7 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const PrismTri<P, R>* tri = (const PrismTri<P, R>*)a.dops;
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = PrismLaunch<P, dbl>::EB, NT = PrismLaunch<P, dbl>::NT;
-  constexpr int EBA = PRISM_DISU_EB, NTA = 256, EBC = PRISM_SURF_EB, NTC = 256;
+  constexpr int EBA = PRISM_DISU_EB, NTA = 256, EBC = PrismSurf<P, dbl>::EB, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
@@ -708,7 +721,7 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
 template <int P, typename R>
 static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {PRISM_DISU_EB, PrismLaunch<P, dbl>::EB, PRISM_SURF_EB};
+  const int ebs[3] = {PRISM_DISU_EB, PrismLaunch<P, dbl>::EB, PrismSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
   for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
@@ -721,8 +734,16 @@ static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
 
 int prism_block_elems(int p, int prec, int k) {
   if (k == K_DISU) return PRISM_DISU_EB;
-  if (k == K_SURFACE) return PRISM_SURF_EB;
   const bool d = prec == 0;
+  if (k == K_SURFACE) {
+    switch (p) {
+      case 1: return d ? PrismSurf<1, true>::EB : PrismSurf<1, false>::EB;
+      case 2: return d ? PrismSurf<2, true>::EB : PrismSurf<2, false>::EB;
+      case 3: return d ? PrismSurf<3, true>::EB : PrismSurf<3, false>::EB;
+      case 4: return d ? PrismSurf<4, true>::EB : PrismSurf<4, false>::EB;
+    }
+    return 0;
+  }
   switch (p) {
     case 1: return d ? PrismLaunch<1, true>::EB : PrismLaunch<1, false>::EB;
     case 2: return d ? PrismLaunch<2, true>::EB : PrismLaunch<2, false>::EB;

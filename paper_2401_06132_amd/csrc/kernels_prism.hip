@@ -146,7 +146,10 @@ struct PrismVol {
   static constexpr int n = P + 1, m = P + 3, NTN = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
   static constexpr int NU = NTN * n, NFP = n * n;
   static constexpr int SZ_A = 20 * NU;
-  static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * NTQ, SZ_Z = 15 * NTQ * n;
+  // padded strides keep the LDS accesses of both writer and reader free of
+  // bank conflicts: T1 rows of NTQ + 1, Z variables NTQ n + 4 apart
+  static constexpr int TQS = NTQ + 1, ZVS = NTQ * n + 4;
+  static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * TQS, SZ_Z = 15 * ZVS;
   static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
   static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
@@ -189,8 +192,8 @@ __global__ void __launch_bounds__(NT_)
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                 */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
-#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][NTQ]             */
-#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][NTQ][n]           */
+#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][TQS]             */
+#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][ZVS: NTQ][n]      */
 
   // phase 0: operator tables, state (reference form), metrics, neighbour states
   {
@@ -415,15 +418,30 @@ __global__ void __launch_bounds__(NT_)
     }
   }
   // phase 4b: triangle-plane interpolation of the 20 fields to the triangle
-  // quadrature points (first factor of M7 / M10), one output per thread
-  for (int it = tid; it < EB * 20 * n * NTQ; it += NT_) {
-    const int le = it / (20 * n * NTQ), r0 = it - le * (20 * n * NTQ);
-    const int fk = r0 / NTQ, tq = r0 - fk * NTQ, fld = fk / n, k = fk - fld * n;
+  // quadrature points (first factor of M7 / M10): one (field, plane) per
+  // thread, its N_t values in registers, operator entries read from the LDS
+  // copy at wave-uniform addresses (broadcast reads)
+  // (at high order SPL threads share a plane, taking alternate outputs, so
+  // that more lanes are busy)
+  constexpr int SPL = P >= 4 ? 2 : 1;
+  for (int it = tid; it < EB * 20 * n * SPL; it += NT_) {
+    const int le = it / (20 * n * SPL), r0 = it - le * (20 * n * SPL), fk = r0 / SPL, h = r0 - fk * SPL;
+    const int fld = fk / n, k = fk - fld * n;
     const R* x = XS(le) + fld * NU + NTN * k;
-    R s = R(0);
+    R xv[NTN];
 #pragma unroll
-    for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * x[t];
-    TS(le)[r0] = s;  // [fld][k][tq]
+    for (int t = 0; t < NTN; ++t) xv[t] = x[t];
+    R* T = TS(le) + fk * C::TQS;  // [fld][k][tq]
+#pragma unroll
+    for (int j = 0; j < (NTQ + SPL - 1) / SPL; ++j) {
+      const int tq = SPL * j + h;
+      if (tq < NTQ) {
+        R s = R(0);
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * xv[t];
+        T[tq] = s;
+      }
+    }
   }
   lds_barrier();
 
@@ -445,7 +463,7 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
     for (int fld = 0; fld < 20; ++fld)
 #pragma unroll
-      for (int k = 0; k < n; ++k) t1[fld][k] = T[(fld * n + k) * NTQ + ctq];
+      for (int k = 0; k < n; ++k) t1[fld][k] = T[(fld * n + k) * C::TQS + ctq];
     R S[3][3];
     const R dj = sMet[cle][9];
 #pragma unroll
@@ -504,22 +522,36 @@ __global__ void __launch_bounds__(NT_)
       for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int k = 0; k < n; ++k)
-          if (((d * 5 + v) * n + k) % 2 == half) Z[((d * 5 + v) * NTQ + ctq) * n + k] = acc[d][v][k];
+          if (((d * 5 + v) * n + k) % 2 == half) Z[(d * 5 + v) * C::ZVS + ctq * n + k] = acc[d][v][k];
   }
   lds_barrier();
 
-  // phase 6: triangle-plane projection-divergence, one output point per thread
-  for (int it = tid; it < EB * 5 * n * NTN; it += NT_) {
-    const int le = it / (5 * n * NTN), r0 = it - le * (5 * n * NTN);
-    const int v = r0 / (n * NTN), r1 = r0 - v * (n * NTN), k = r1 / NTN, t = r1 - k * NTN, e = e0 + le;
+  // phase 6: triangle-plane projection-divergence: one (variable, plane) per
+  // thread, its 3 N_tq line-projected flux values in registers, operator
+  // entries read from the LDS copy at wave-uniform addresses
+  for (int it = tid; it < EB * 5 * n * SPL; it += NT_) {
+    const int le = it / (5 * n * SPL), r0 = it - le * (5 * n * SPL), vk = r0 / SPL, h = r0 - vk * SPL;
+    const int v = vk / n, k = vk - v * n, e = e0 + le;
     if (e >= E) continue;
     const R* Z = ZS(le);
-    R s = R(0);
+    R z0[NTQ], z1[NTQ], z2[NTQ];
 #pragma unroll
-    for (int tq = 0; tq < NTQ; ++tq)
-      s += tri.APxi[t][tq] * Z[((0 * 5 + v) * NTQ + tq) * n + k] + tri.APeta[t][tq] * Z[((1 * 5 + v) * NTQ + tq) * n + k] +
-           tri.PT[t][tq] * Z[((2 * 5 + v) * NTQ + tq) * n + k];
-    Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = s;
+    for (int tq = 0; tq < NTQ; ++tq) {
+      z0[tq] = Z[(0 * 5 + v) * C::ZVS + tq * n + k];
+      z1[tq] = Z[(1 * 5 + v) * C::ZVS + tq * n + k];
+      z2[tq] = Z[(2 * 5 + v) * C::ZVS + tq * n + k];
+    }
+#pragma unroll
+    for (int j = 0; j < (NTN + SPL - 1) / SPL; ++j) {
+      const int t = SPL * j + h;
+      if (t < NTN) {
+        R s = R(0);
+#pragma unroll
+        for (int tq = 0; tq < NTQ; ++tq)
+          s += tri.APxi[t][tq] * z0[tq] + tri.APeta[t][tq] * z1[tq] + tri.PT[t][tq] * z2[tq];
+        Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = s;
+      }
+    }
   }
 #undef XS
 #undef JS

@@ -265,9 +265,13 @@ __global__ void __launch_bounds__(NT_)
   lds_barrier();
 
   // phase 1: jumps C - u^f (eq. FR-conu) at every own flux point, in place
-  // over the neighbour values: triangle faces (line interpolation in zeta),
-  // quadrilateral faces (triangle-plane interpolation to the edge point)
-  constexpr int NJ_TRI = 5 * NTN, NJ_QUAD = 5 * 3 * n * n;
+  // over the neighbour values: triangle faces (line interpolation in zeta,
+  // one line per thread), quadrilateral faces (triangle-plane interpolation
+  // to the edge points).  PL: one (variable, plane) per thread with broadcast
+  // operator reads, which pays where enough planes fill the workgroup (single
+  // precision up to p = 3); otherwise one edge point per thread.
+  constexpr bool PL = sizeof(R) == 4 && P <= 3;
+  constexpr int NJ_TRI = 5 * NTN, NJ_QUAD = PL ? 5 * n : 5 * 3 * n * n;
   for (int it = tid; it < EB * (NJ_TRI + NJ_QUAD); it += NT_) {
     const int le = it / (NJ_TRI + NJ_QUAD), r0 = it - le * (NJ_TRI + NJ_QUAD), e = e0 + le;
     const R* X = XS(le);
@@ -285,6 +289,23 @@ __global__ void __launch_bounds__(NT_)
       R* jp = JS(le) + (1 * 5 + v) * NFP + t;
       *jm = ((im & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jm - xm);
       *jp = ((ip & 1) ? R(0.5) + g.beta : R(0.5) - g.beta) * (*jp - xp);
+    } else if constexpr (PL) {
+      const int r1 = r0 - NJ_TRI, v = r1 / n, k = r1 - v * n;
+      R x[NTN];
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) x[t] = X[v * NU + t + NTN * k];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed) {
+        const R w = (sFR[le * 5 + 2 + ed].info & 1) ? R(0.5) + g.beta : R(0.5) - g.beta;
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * x[t];
+          R* jj = JS(le) + ((2 + ed) * 5 + v) * NFP + i + n * k;
+          *jj = w * (*jj - s);
+        }
+      }
     } else {
       const int r1 = r0 - NJ_TRI, v = r1 / (3 * n * n), r2 = r1 - v * (3 * n * n), ed = r2 / (n * n);
       const int r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
@@ -299,9 +320,10 @@ __global__ void __launch_bounds__(NT_)
   lds_barrier();
 
   // phase 2: corrected reference gradient (eq. FR-qfinal): zeta along the
-  // lines with the triangle-face lifting; (xi, eta) per output point with the
-  // triangle derivative blocks and the quadrilateral-face lifting
-  constexpr int NG_Z = 5 * NTN, NG_T = 5 * n * NTN;
+  // lines with the triangle-face lifting; (xi, eta) with the triangle
+  // derivative blocks and the quadrilateral-face lifting (per plane or per
+  // point, as in phase 1)
+  constexpr int NG_Z = 5 * NTN, NG_T = PL ? 5 * n : 5 * n * NTN;
   for (int it = tid; it < EB * (NG_Z + NG_T); it += NT_) {
     const int le = it / (NG_Z + NG_T), r0 = it - le * (NG_Z + NG_T);
     R* X = XS(le);
@@ -318,6 +340,36 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
         for (int c = 0; c < n; ++c) s += op.D[k][c] * x[c];
         X[(15 + v) * NU + t + NTN * k] = s;
+      }
+    } else if constexpr (PL) {
+      const int r1 = r0 - NG_Z, v = r1 / n, k = r1 - v * n;
+      R x[NTN], jq[3][n];
+#pragma unroll
+      for (int c = 0; c < NTN; ++c) x[c] = X[v * NU + c + NTN * k];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+        for (int i = 0; i < n; ++i) jq[ed][i] = J[((2 + ed) * 5 + v) * NFP + i + n * k];
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) {
+        R sx = R(0), sy = R(0);
+#pragma unroll
+        for (int c = 0; c < NTN; ++c) {
+          sx += tri.Dxi[t][c] * x[c];
+          sy += tri.Deta[t][c] * x[c];
+        }
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed) {
+          R nx, ny;
+          edge_normal<R>(ed, nx, ny);
+          R l = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) l += tri.LiftEdge[ed][t][i] * jq[ed][i];
+          sx += nx * l;
+          sy += ny * l;
+        }
+        X[(5 + v) * NU + t + NTN * k] = sx;
+        X[(10 + v) * NU + t + NTN * k] = sy;
       }
     } else {
       const int r1 = r0 - NG_Z, v = r1 / (n * NTN), r2 = r1 - v * (n * NTN), k = r2 / NTN, t = r2 - k * NTN;

@@ -263,6 +263,7 @@ def main():
     ap.add_argument("--n", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline variant only")
+    ap.add_argument("--only", default=None, help="one variant kind:prec:p:form, e.g. prism:fp32:3:fused (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serving-only", action="store_true", help="only the serving stream")
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
@@ -292,6 +293,13 @@ def main():
               flush=True)
         return
     variants = {}
+    if args.only:
+        kind, prec, p, form = args.only.split(":")
+        r = time_variant(frmi, torch, args.n, int(p), prec, args.steps, args.warmup, form, kind)
+        r["gdof_s"] = r["n_dof"] * args.steps / r["wall_s"] / 1e9
+        print(json.dumps({"variant": args.only, **{k: (round(v, 4) if isinstance(v, float) else v)
+                                                   for k, v in r.items()}}), flush=True)
+        return
     order = [("fp32", 3, "fused", "hex")] if args.quick else [
         ("fp32", 3, "fused", "hex"), ("fp64", 3, "fused", "hex"), ("fp64", 3, "plain", "hex"),
         ("fp32", 4, "fused", "hex"), ("fp64", 4, "fused", "hex"), ("fp64", 4, "plain", "hex"),

@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # FP64 FMA runs at full rate; FP32 reaches twice this only with packed math,
 # which this build does not emit.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# HBM bytes per launch of hex_volume<3, float> on the 48^3 workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from
+# a 1 GiB copy), profiles/hex_fused_fp32_p3_tgv48.md.  Valid for the kernel as
+# profiled; None once the kernel changes.
+HEX_VOL_P3_FP32_TRAFFIC = (272356.8 * 2.0 + 304128.0) * 1024
 
 
 def volume_model(p, bytes_real):
@@ -337,7 +342,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(head["vol_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": "hex_volume<3,float>", "traffic": None, "hbm_GBs": round(head["vol_GBs"], 1),
+    traffic = HEX_VOL_P3_FP32_TRAFFIC if args.n == 48 else None
+    roof.update({"kernel": "hex_volume<3,float>", "traffic": traffic, "traffic_unit": "bytes per launch",
+                 "algorithmic_bytes": vb * head["n_elem"], "hbm_GBs": round(head["vol_GBs"], 1),
                  "hbm_frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4), "flop_per_byte": round(ai, 2),
                  "avg_ms": round(head["vol_ms"], 4)})
     def _r(x):

@@ -74,9 +74,9 @@ def rhs_bytes_model(p, bytes_real):
     return b
 
 
-def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex"):
+def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex", aa=True):
     from paper_2401_06132_amd import inputs
-    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form)
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form, aa=aa)
     coords = s.upts_coords()
     U = inputs.element_state(coords, seed=0)
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
@@ -309,21 +309,24 @@ def main():
         ("fp32", 3, "fused", "hex"), ("fp64", 3, "fused", "hex"), ("fp64", 3, "plain", "hex"),
         ("fp32", 4, "fused", "hex"), ("fp64", 4, "fused", "hex"), ("fp64", 4, "plain", "hex"),
         ("fp32", 3, "fused", "prism"), ("fp64", 3, "fused", "prism"), ("fp64", 3, "plain", "prism"),
-        ("fp32", 4, "fused", "prism")]
+        ("fp32", 4, "fused", "prism"),
+        ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex")]
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
-        r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)
+        # "noaa": the fused path without flux anti-aliasing (the paper's AA-off column)
+        r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, "fused" if form == "noaa" else form,
+                         kind, aa=form != "noaa")
         br = 4 if prec == "fp32" else 8
         vb, vf = volume_model(p, br)
         E = r["n_elem"]
         r["gdof_s"] = r["n_dof"] * ksteps / r["wall_s"] / 1e9
         if kind == "hex":
             r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
-            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
+            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12 if form != "noaa" else float("nan")
             r["rhs_GBs"] = rhs_bytes_model(p, br) * E * ksteps / r["wall_s"] / 1e9
         else:
             r["vol_GBs"] = r["vol_TFLOPs"] = r["rhs_GBs"] = float("nan")
-        variants["%s%s%s_p%d" % ("prism_" if kind == "prism" else "", "plain_" if form == "plain" else "", prec,
+        variants["%s%s%s_p%d" % ("prism_" if kind == "prism" else "", "" if form == "fused" else form + "_", prec,
                                   p)] = r
         print("variant", form, prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
               file=sys.stderr, flush=True)

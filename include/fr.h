@@ -78,15 +78,23 @@ typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
  *   form               : FR_FORM_FUSED: three fused kernels per element type
  *                        (disu | volume group | interface group).
  *                        FR_FORM_PLAIN: the paper's unfused kernel sequence
- *                        with dense operator matrices (comparison path). */
+ *                        with dense operator matrices (comparison path).
+ *   flux_aa            : 1: flux anti-aliasing (the flux is evaluated at the
+ *                        quadrature points and projected, section 2.1.1);
+ *                        0: no anti-aliasing, the flux is evaluated at the
+ *                        solution points (the paper's "AA off"
+ *                        configuration).  0 is built for hexahedra in the
+ *                        fused form; other combinations report
+ *                        FR_EUNSUPPORTED when the mesh is built. */
 typedef struct {
   double gamma, prandtl, mu, ldg_beta, ldg_tau, pref;
-  int prec;   /* fr_precision */
-  int form;   /* fr_form */
+  int prec;     /* fr_precision */
+  int form;     /* fr_form */
+  int flux_aa;  /* 1 (default) or 0 */
 } fr_physics;
 
 /* Fill *ph with the Taylor-Green defaults: gamma 1.4, Pr 0.71, mu 1/1600,
- * beta 0.5, tau 0.1, pref 0, FP64, fused. */
+ * beta 0.5, tau 0.1, pref 0, FP64, fused, flux anti-aliasing on. */
 void fr_physics_default(fr_physics* ph);
 
 /* Create a context.  hip_stream: a hipStream_t or NULL (null stream).  No

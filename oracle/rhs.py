@@ -18,6 +18,10 @@ v1.11.0), with dense operators and no fusion:
   13 negdivconf    R   = -R~ / det J
 Affine elements: J, det J and J^-1 are constant per element.
 
+Without flux anti-aliasing (the paper's "AA off" configuration) steps 7, 8
+and the projection M8 are absent: tdisf evaluates the flux at the solution
+points from U and Q, and that F~^u enters step 10 directly.
+
 Arrays: the state of element type t is U[t] with shape (E_t, 5, N_u)
 (element, variable, solution point).
 """
@@ -32,9 +36,10 @@ class Params:
     gamma 1.4, Pr 0.71, Re 1600 (mu = 1/1600 with rho0 = U0 = L = 1), LDG
     beta = 1/2, tau = 0.1, reference pressure 0 (textbook form)."""
 
-    def __init__(self, gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0):
+    def __init__(self, gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0, aa=True):
         self.gas = physics.Gas(gamma, prandtl, mu, pref)
         self.beta, self.tau = beta, tau
+        self.aa = aa  # flux anti-aliasing on (default) or off
 
 
 def _flat(arrs, mesh, tail):
@@ -45,6 +50,25 @@ def _unflat(flat, mesh, t, tail):
     r = mesh.refs[t]
     o = mesh.foff[t]
     return flat[o:o + mesh.nelem[t] * r.nf].reshape((mesh.nelem[t], r.nf) + tail)
+
+
+def _volume_flux(r, u, q, detj, jinv, gas, aa, cast):
+    """Transformed flux F~ at the solution points, (E, 3, N_u, 5).
+    u: (E, N_u, 5) state (reference form), q: (E, 3, N_u, 5) gradients.
+    With flux anti-aliasing: U^q = M7 U, Q^q = M10 Q (steps 7, 8), the flux
+    at the quadrature points (step 9) and its projection M9 = I3 x M8 (first
+    factor of step 10).  Without: the flux at the solution points."""
+    if aa:
+        uq = np.einsum("qu,euv->vqe", cast(r.M7), u)  # 8 uqpts
+        qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), q)  # 7 gradcoru_qpts
+    else:
+        uq = np.ascontiguousarray(u.transpose(2, 1, 0))  # (5, N_u, E)
+        qq = np.ascontiguousarray(q.transpose(1, 3, 2, 0))  # (3, 5, N_u, E)
+    f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9 tdisf
+    ft = np.einsum("e,edc,cvqe->edqv", cast(detj), cast(jinv), f)
+    if aa:
+        return np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10 tdivtpcorf: M9 (I3 x M8)
+    return ft
 
 
 def rhs(mesh, U, par, dtype=None):
@@ -81,11 +105,7 @@ def rhs(mesh, U, par, dtype=None):
         chunk = max(1, int(2.0e7 // (r.nq * 20)))
         for e0 in range(0, E, chunk):
             sl = slice(e0, min(E, e0 + chunk))
-            uq = np.einsum("qu,euv->vqe", cast(r.M7), Up[t][sl])  # 8 uqpts
-            qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), Q[t][sl])  # 7 gradcoru_qpts
-            f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9 tdisf
-            ft = np.einsum("e,edc,cvqe->edqv", cast(mesh.detJ[t][sl]), cast(mesh.Jinv[t][sl]), f)
-            fu = np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10 tdivtpcorf: M9 (I3 x M8)
+            fu = _volume_flux(r, Up[t][sl], Q[t][sl], mesh.detJ[t][sl], mesh.Jinv[t][sl], gas, par.aa, cast)
             div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)  # M1
             nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)  # M2
             rt[sl] = div - np.einsum("uf,efv->euv", cast(r.M3), nf)  # - M3 M2
@@ -210,11 +230,7 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         u = u2[np.searchsorted(e2, e0)]
         e1, q1 = Q[t]
         q = q1[np.searchsorted(e1, e0)]
-        uq = np.einsum("qu,euv->vqe", cast(r.M7), u)  # 8
-        qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), q)  # 7
-        f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9
-        ft = np.einsum("e,edc,cvqe->edqv", cast(mesh.detJ[t][e0]), cast(mesh.Jinv[t][e0]), f)
-        fu = np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10
+        fu = _volume_flux(r, u, q, mesh.detJ[t][e0], mesh.Jinv[t][e0], gas, par.aa, cast)  # 7-10
         div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)
         nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)
         rt = div - np.einsum("uf,efv->euv", cast(r.M3), nf)

@@ -282,6 +282,7 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
       a.one.dt = dt;
       a.rk = rk;
       a.from_ust = rk > 0;
+      a.aa = c->ph.flux_aa != 0;
       hipError_t e = t == 0 ? fr::hex_rhs(a, c->ph.prec, c->st) : fr::prism_rhs(a, c->ph.prec, c->st);
       if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
@@ -302,6 +303,7 @@ void fr_physics_default(fr_physics* ph) {
   ph->pref = 0.0;
   ph->prec = FR_PREC_FP64;
   ph->form = FR_FORM_FUSED;
+  ph->flux_aa = 1;
 }
 
 fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
@@ -309,9 +311,10 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
   *out = nullptr;
   if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
       !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
-      ph->form > 1)
+      ph->form > 1 || ph->flux_aa < 0 || ph->flux_aa > 1)
     return FR_EINVAL;
   if (ph->form == FR_FORM_PLAIN && ph->prec != FR_PREC_FP64) return FR_EUNSUPPORTED;
+  if (ph->form == FR_FORM_PLAIN && !ph->flux_aa) return FR_EUNSUPPORTED;
   fr_ctx* c = new (std::nothrow) fr_ctx();
   if (!c) return FR_ENOMEM;
   c->ph = *ph;
@@ -334,6 +337,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
     if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
+    if (!c->ph.flux_aa && c->M.nel[1] > 0)
+      return fail(c, FR_EUNSUPPORTED, "the path without anti-aliasing is built for hexahedra only");
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }
@@ -345,6 +350,7 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     h.D = r.line.D.data();
     h.P = r.line.P.data();
     h.AP = r.line.AP.data();
+    h.APu = r.line.APu.data();
     h.lb = r.line.lb.data();
     h.rb = r.line.rb.data();
     h.liftL = r.line.liftL.data();

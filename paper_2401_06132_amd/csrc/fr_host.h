@@ -22,6 +22,8 @@ struct Line1D {
   std::vector<double> P;       // n x m  L2 projection  I^T W_q / w_i
   std::vector<double> AP;      // n x m  -(Dq^T W_q)/w_i : projection followed by the
                                //        SBP form of (M1 - M3 M2) along the line
+  std::vector<double> APu;     // n x n  -(D^T W)/w_i : the same at the solution points
+                               //        (no anti-aliasing: flux collocated at GL(n))
   std::vector<double> lb, rb;  // l_i(-1), l_i(+1)
   std::vector<double> liftL, liftR;  // l_i(-1)/w_i, l_i(+1)/w_i  (DG correction)
 };

@@ -12,7 +12,7 @@ namespace fr {
 
 // host copies of the 1-D (and triangle) operator factors of one element type
 struct HostOps {
-  const double *I = nullptr, *D = nullptr, *P = nullptr, *AP = nullptr;
+  const double *I = nullptr, *D = nullptr, *P = nullptr, *AP = nullptr, *APu = nullptr;
   const double *lb = nullptr, *rb = nullptr, *liftL = nullptr, *liftR = nullptr;
   const Tri* tri = nullptr;
   const RefElem* ref = nullptr;
@@ -63,6 +63,7 @@ struct TypeArgs {
   int stage = 7;        // bit 0: disu, bit 1: volume group, bit 2: interface group
   bool diag = false;    // every element has a diagonal Jacobian
   bool from_ust = false;  // disu/volume read Seg::ust instead of Seg::U
+  bool aa = true;       // flux anti-aliasing (false: flux at the solution points)
   int rk = -1;          // -1: surface writes du; 0..3: fused classical RK4 stage
   Seg one;              // the segment when bt is null
   const BlkRef* bt[3] = {nullptr, nullptr, nullptr};  // per-kernel workgroup tables

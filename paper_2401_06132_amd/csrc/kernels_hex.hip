@@ -35,6 +35,7 @@ struct HexOps {
   R D[n][n];   // l_j' at the solution points
   R Pj[n][m];  // projection
   R AP[n][m];  // projection + divergence
+  R APu[n][n]; // divergence at the solution points (no anti-aliasing)
   R lb[n], rb[n], liftL[n], liftR[n];
 };
 
@@ -203,8 +204,9 @@ struct HexVolLoads {
       gv[k] = Uf[(size_t)q.nbr * 5 * NFP + v * NFP + sPerm[(q.info >> 1) * NFP + r]];
     }
   }
-  // state in reference form, metrics and neighbour states to LDS
-  __device__ __forceinline__ void put_elems(R* smem, R (*sMet)[10], double eref, int tid) const {
+  // state in reference form, metrics and neighbour states to LDS (pe: LDS
+  // values per element)
+  __device__ __forceinline__ void put_elems(R* smem, R (*sMet)[10], double eref, int pe, int tid) const {
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
       const int it = tid + k * NT;
@@ -217,7 +219,7 @@ struct HexVolLoads {
         const int le = it / (5 * NU), r = it - le * (5 * NU);
         double x = xs[k];
         if (r >= 4 * NU) x -= eref;
-        smem[le * C::PER_ELEM + r] = R(x);
+        smem[le * pe + r] = R(x);
       }
     }
 #pragma unroll
@@ -225,18 +227,22 @@ struct HexVolLoads {
       const int it = tid + k * NT;
       if (it < EB * 30 * NFP) {
         const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
-        smem[le * C::PER_ELEM + C::SZ_A + r0] = gv[k];
+        smem[le * pe + C::SZ_A + r0] = gv[k];
       }
     }
   }
 };
 
-template <int P, typename R, int EB, int NT, bool DIAG, bool BT>
+// AA: flux anti-aliasing (quadrature GL(p+3)^3); without it the flux is
+// evaluated at the solution points and its divergence uses -W^-1 D^T W
+// along each direction (exact for the GL solution points)
+template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA>
 __global__ void __launch_bounds__(NT)
     hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                const HexOps<P, R> op, const Gas<R> g, const double eref) {
   using C = HexVol<P>;
-  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
+  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + C::SZ_J;
   static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
@@ -270,7 +276,7 @@ __global__ void __launch_bounds__(NT)
   ld.put_faces(sFR, sFG, tid);
   lds_barrier();
   ld.gather(Uf, sFR, sPerm, tid);
-  ld.put_elems(smem, sMet, eref, tid);
+  ld.put_elems(smem, sMet, eref, PE, tid);
   lds_barrier();
   const FaceRec* cFR = sFR;
   const R (*cFG)[4] = sFG;
@@ -366,6 +372,51 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
     }
+  }
+  if constexpr (!AA) {
+    // no anti-aliasing: transformed flux at each solution point, in place
+    // over the gradients (tdisf), then its divergence (M1 - M3 M2) as
+    // -W^-1 D^T W along each direction
+    __shared__ R sAPu[n][n];  // read with a per-thread row index
+    if (tid < n * n) sAPu[tid / n][tid % n] = op.APu[tid / n][tid % n];
+    lds_barrier();  // the face viscous fluxes have read the gradients
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s = it - le * NU;
+      R* X = XS(le);
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = X[v * NU + s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) q[d][v] = X[(5 + d * 5 + v) * NU + s];
+      }
+      point_flux(u, q, g, f);
+      const R dj = sMet[le][9];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const R ft = DIAG ? sMet[le][4 * d] * f[d][v]
+                            : sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v];
+          X[(5 + d * 5 + v) * NU + s] = dj * ft;
+        }
+    }
+    lds_barrier();
+    for (int it = tid; it < EB * 5 * NU; it += NT) {
+      const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
+      if (e >= E) continue;
+      const int i = s % n, j = (s / n) % n, k = s / (n * n);
+      const R* F = XS(le) + 5 * NU + v * NU;  // component d at F + d * 5 NU
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < n; ++c) {
+        acc += sAPu[i][c] * F[0 * 5 * NU + c + n * (j + n * k)];
+        acc += sAPu[j][c] * F[1 * 5 * NU + i + n * (c + n * k)];
+        acc += sAPu[k][c] * F[2 * 5 * NU + i + n * (j + n * c)];
+      }
+      Rp[(size_t)e * 5 * NU + r0] = acc;
+    }
+    return;
   }
   // phase 3b: x interpolation of the 20 fields (first factor of M7 / M10)
   for (int it = tid; it < EB * 20 * NFP; it += NT) {
@@ -634,6 +685,7 @@ static HexOps<P, R> make_hex_ops(const HostOps& h) {
     o.rb[i] = R(h.rb[i]);
     o.liftL[i] = R(h.liftL[i]);
     o.liftR[i] = R(h.liftR[i]);
+    for (int j = 0; j < n; ++j) o.APu[i][j] = R(h.APu[i * n + j]);
   }
   return o;
 }
@@ -687,12 +739,22 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
     hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, eref);
   if ((a.stage & 2) && grid[K_VOLUME] > 0) {
-    if (a.diag)
-      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                         a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
-    else
-      hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                         a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
+    const dim3 gv(grid[K_VOLUME]), bv(NT);
+    if (a.aa) {
+      if (a.diag)
+        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT, true>), gv, bv, 0, st, a.one, a.bt[K_VOLUME], a.segs,
+                           a.from_ust, op, g, eref);
+      else
+        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT, true>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
+                           a.segs, a.from_ust, op, g, eref);
+    } else {
+      if (a.diag)
+        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT, false>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
+                           a.segs, a.from_ust, op, g, eref);
+      else
+        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT, false>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
+                           a.segs, a.from_ust, op, g, eref);
+    }
   }
   if ((a.stage & 4) && grid[K_SURFACE] > 0)
     hipLaunchKernelGGL((hex_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,

@@ -279,6 +279,8 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind > 2)
     return pfail(P, FR_EINVAL, "bad mesh size");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
+  if (!P->ph.flux_aa && q->kind != FR_MESH_HEX)
+    return pfail(P, FR_EUNSUPPORTED, "the path without anti-aliasing is built for hexahedra only");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
   if (!q->u_init && !(q->tgv_p0 > 0.0)) return pfail(P, FR_EINVAL, "no initial state and tgv_p0 <= 0");
   const int64_t cells = (int64_t)q->nx * q->ny * q->nz;
@@ -303,6 +305,7 @@ fr_status ensure_refs(fr_pool* P, int p) {
     h.D = r.line.D.data();
     h.P = r.line.P.data();
     h.AP = r.line.AP.data();
+    h.APu = r.line.APu.data();
     h.lb = r.line.lb.data();
     h.rb = r.line.rb.data();
     h.liftL = r.line.liftL.data();
@@ -512,6 +515,7 @@ fr_status enqueue_step(fr_pool* P, int* launches) {
         a.diag = V.diag;
         a.from_ust = st > 0;
         a.rk = st;
+        a.aa = P->ph.flux_aa != 0;
         a.segs = (const fr::Seg*)(P->d_tab + V.off_segs);
         for (int j = 0; j < 3; ++j) {
           a.bt[j] = (const fr::BlkRef*)(P->d_tab + V.off_bt[j]);
@@ -550,7 +554,8 @@ fr_status fr_pool_create(const fr_physics* ph, void* stream, int64_t budget_byte
   if (!ph || !out) return FR_EINVAL;
   *out = nullptr;
   if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
-      !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1)
+      !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 ||
+      ph->flux_aa < 0 || ph->flux_aa > 1)
     return FR_EINVAL;
   if (ph->form != FR_FORM_FUSED) return FR_EUNSUPPORTED;
   if (budget_bytes <= 0 || max_active < 1) return FR_EINVAL;

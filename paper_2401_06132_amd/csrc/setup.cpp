@@ -192,6 +192,7 @@ static void build_line(int p, int m, Line1D& L) {
   L.Dq.assign(m * n, 0);
   L.P.assign(n * m, 0);
   L.AP.assign(n * m, 0);
+  L.APu.assign(n * n, 0);
   L.lb.resize(n);
   L.rb.resize(n);
   L.liftL.resize(n);
@@ -210,6 +211,7 @@ static void build_line(int p, int m, Line1D& L) {
     }
     L.lb[i] = lagrange(L.x, i, -1.0);
     L.rb[i] = lagrange(L.x, i, 1.0);
+    for (int j = 0; j < n; ++j) L.APu[i * n + j] = -L.D[j * n + i] * L.w[j] / L.w[i];
     L.liftL[i] = L.lb[i] / L.w[i];
     L.liftR[i] = L.rb[i] / L.w[i];
   }

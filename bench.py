@@ -310,7 +310,8 @@ def main():
         ("fp32", 4, "fused", "hex"), ("fp64", 4, "fused", "hex"), ("fp64", 4, "plain", "hex"),
         ("fp32", 3, "fused", "prism"), ("fp64", 3, "fused", "prism"), ("fp64", 3, "plain", "prism"),
         ("fp32", 4, "fused", "prism"),
-        ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex")]
+        ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex"),
+        ("fp32", 3, "noaa", "prism"), ("fp32", 4, "noaa", "prism")]
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
         # "noaa": the fused path without flux anti-aliasing (the paper's AA-off column)

@@ -83,9 +83,8 @@ typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
  *                        quadrature points and projected, section 2.1.1);
  *                        0: no anti-aliasing, the flux is evaluated at the
  *                        solution points (the paper's "AA off"
- *                        configuration).  0 is built for hexahedra in the
- *                        fused form; other combinations report
- *                        FR_EUNSUPPORTED when the mesh is built. */
+ *                        configuration), in the fused form (the plain form
+ *                        reports FR_EUNSUPPORTED). */
 typedef struct {
   double gamma, prandtl, mu, ldg_beta, ldg_tau, pref;
   int prec;     /* fr_precision */

@@ -337,8 +337,6 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
     if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
-    if (!c->ph.flux_aa && c->M.nel[1] > 0)
-      return fail(c, FR_EUNSUPPORTED, "the path without anti-aliasing is built for hexahedra only");
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }

@@ -168,13 +168,17 @@ __device__ __forceinline__ double pair_sum(double x) {
   return x + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int P, typename R, int EB, int NT_, bool BT>
+// AA: flux anti-aliasing; without it the flux is evaluated at the solution
+// points and its divergence is taken in strong form, (M1 - M3 M2) F~: the
+// derivative blocks minus the lifted normal flux interpolated to the faces
+template <int P, typename R, int EB, int NT_, bool BT, bool AA>
 __global__ void __launch_bounds__(NT_)
     prism_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g, const Gas<R> g,
                  const double eref) {
   using C = PrismVol<P>;
-  constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP, PE = C::PER_ELEM;
+  constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
+  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + C::SZ_J;
   static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
   __shared__ PrismTri<P, R> tri;
   __shared__ R smem[EB * PE];
@@ -468,6 +472,91 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
     }
+  }
+  if constexpr (!AA) {
+    // line derivative and lifting weights, read with a per-thread index
+    __shared__ R sDz[n][n], sLz[2][n];
+    if (tid < n * n) sDz[tid / n][tid % n] = op.D[tid / n][tid % n];
+    if (tid < n) {
+      sLz[0][tid] = op.liftL[tid];
+      sLz[1][tid] = op.liftR[tid];
+    }
+    lds_barrier();  // the face viscous fluxes have read the gradients
+    // tdisf at the solution points, in place over the gradients
+    for (int it = tid; it < EB * NU; it += NT_) {
+      const int le = it / NU, s = it - le * NU;
+      R* X = XS(le);
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = X[v * NU + s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) q[d][v] = X[(5 + d * 5 + v) * NU + s];
+      }
+      point_flux(u, q, g, f);
+      const R dj = sMet[le][9];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          X[(5 + d * 5 + v) * NU + s] =
+              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+    }
+    lds_barrier();
+    // M2 F~: reference normal flux at the own flux points (JS region, free
+    // since the gradient phase): triangle faces from the zeta lines,
+    // quadrilateral faces from the triangle planes
+    for (int it = tid; it < EB * 5 * (NTN + 3 * n * n); it += NT_) {
+      const int le = it / (5 * (NTN + 3 * n * n)), r0 = it - le * (5 * (NTN + 3 * n * n));
+      const R* F = XS(le) + 5 * NU;  // component d of variable v at F[(d * 5 + v) * NU]
+      R* NF = JS(le);
+      if (r0 < 5 * NTN) {
+        const int v = r0 / NTN, t = r0 - v * NTN;
+        R fm = R(0), fp = R(0);
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const R x = F[(2 * 5 + v) * NU + t + NTN * k];
+          fm += op.lb[k] * x;
+          fp += op.rb[k] * x;
+        }
+        NF[(0 * 5 + v) * NFP + t] = -fm;  // zeta = -1: outward normal -e_zeta
+        NF[(1 * 5 + v) * NFP + t] = fp;
+      } else {
+        const int r1 = r0 - 5 * NTN, v = r1 / (3 * n * n), r2 = r1 - v * (3 * n * n), ed = r2 / (n * n);
+        const int r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
+        R sx = R(0), sy = R(0);
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) {
+          sx += tri.Tedge[ed][i][t] * F[(0 * 5 + v) * NU + t + NTN * k];
+          sy += tri.Tedge[ed][i][t] * F[(1 * 5 + v) * NU + t + NTN * k];
+        }
+        R nx, ny;
+        edge_normal<R>(ed, nx, ny);
+        NF[((2 + ed) * 5 + v) * NFP + i + n * k] = nx * sx + ny * sy;
+      }
+    }
+    lds_barrier();
+    // (M1 - M3 M2) F~ at every solution point
+    for (int it = tid; it < EB * 5 * NU; it += NT_) {
+      const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
+      if (e >= E) continue;
+      const int k = s / NTN, t = s - k * NTN;
+      const R* F = XS(le) + 5 * NU;
+      const R* NF = JS(le);
+      R acc = R(0);
+#pragma unroll
+      for (int c = 0; c < NTN; ++c)
+        acc += tri.Dxi[t][c] * F[(0 * 5 + v) * NU + c + NTN * k] + tri.Deta[t][c] * F[(1 * 5 + v) * NU + c + NTN * k];
+#pragma unroll
+      for (int c = 0; c < n; ++c) acc += sDz[k][c] * F[(2 * 5 + v) * NU + t + NTN * c];
+      acc -= sLz[0][k] * NF[(0 * 5 + v) * NFP + t] + sLz[1][k] * NF[(1 * 5 + v) * NFP + t];
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+        for (int i = 0; i < n; ++i) acc -= tri.LiftEdge[ed][t][i] * NF[((2 + ed) * 5 + v) * NFP + i + n * k];
+      Rp[(size_t)e * 5 * NU + r0] = acc;
+    }
+    return;
   }
   // phase 4b: triangle-plane interpolation of the 20 fields to the triangle
   // quadrature points (first factor of M7 / M10): one (field, plane) per
@@ -794,9 +883,14 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, tri, eref);
-  if ((a.stage & 2) && grid[K_VOLUME] > 0)
-    hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                       a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+  if ((a.stage & 2) && grid[K_VOLUME] > 0) {
+    if (a.aa)
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+    else
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+  }
   if ((a.stage & 4) && grid[K_SURFACE] > 0)
     hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
                        a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);

@@ -279,8 +279,6 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind > 2)
     return pfail(P, FR_EINVAL, "bad mesh size");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
-  if (!P->ph.flux_aa && q->kind != FR_MESH_HEX)
-    return pfail(P, FR_EUNSUPPORTED, "the path without anti-aliasing is built for hexahedra only");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
   if (!q->u_init && !(q->tgv_p0 > 0.0)) return pfail(P, FR_EINVAL, "no initial state and tgv_p0 <= 0");
   const int64_t cells = (int64_t)q->nx * q->ny * q->nz;

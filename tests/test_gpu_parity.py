@@ -171,19 +171,21 @@ def test_rhs_is_deterministic():
         assert np.array_equal(x, y)
 
 
-NOAA_CASES = [((4, 4, 4), 3), ((3, 3, 3), 1), ((3, 2, 4), 2), ((2, 3, 3), 4), ((1, 1, 1), 3), ((5, 1, 2), 2)]
+NOAA_CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((2, 3, 3), 4, "hex"),
+              ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"), ((2, 2, 2), 3, "prism"), ((3, 2, 2), 1, "prism"),
+              ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"), ((2, 2, 4), 3, "mixed"), ((2, 1, 2), 2, "mixed")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("dims,p", NOAA_CASES)
-def test_rhs_parity_without_anti_aliasing(dims, p, prec):
+@pytest.mark.parametrize("dims,p,kind", NOAA_CASES)
+def test_rhs_parity_without_anti_aliasing(dims, p, kind, prec):
     """The configuration without flux anti-aliasing (flux at the solution
-    points), hexahedra, against the oracle's AA-off path; same tolerances."""
+    points) against the oracle's AA-off path; same tolerances."""
     _need_gpu()
-    print("noaa case", dims, p, prec, flush=True)
-    m, U = _case(dims, p, "hex")
+    print("noaa case", dims, p, kind, prec, flush=True)
+    m, U = _case(dims, p, kind)
     r64, rld = _references(m, U, aa=False)
-    got, _ = _gpu_rhs(dims, p, "hex", prec, U, aa=False)
+    got, _ = _gpu_rhs(dims, p, kind, prec, U, aa=False)
     err = _rel_err(got, rld).astype(np.float64)
     own = _rel_err(r64, rld).astype(np.float64)
     tol = TOL[prec]

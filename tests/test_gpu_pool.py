@@ -153,20 +153,19 @@ def test_pool_matches_oracle():
         assert np.all(err < 1e-11)
 
 
-def test_pool_without_anti_aliasing_equals_rk4_step():
-    """A pool in the configuration without flux anti-aliasing (hexahedra)
-    ends bit-identical to fr_rk4_step in the same configuration."""
+@pytest.mark.parametrize("kind", ["hex", "mixed"])
+def test_pool_without_anti_aliasing_equals_rk4_step(kind):
+    """A pool in the configuration without flux anti-aliasing ends
+    bit-identical to fr_rk4_step in the same configuration."""
     _need_gpu()
     n, p, steps, dt = (3, 2, 4), 3, 4, 2e-4
-    u0 = _init(n, p, "hex", seed=4)
-    s = frmi.Solver(n, p, "hex", prec="fp32", pref=inputs.P0, aa=False)
+    u0 = _init(n, p, kind, seed=4)
+    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, aa=False)
     s.set_state(u0)
     s.rk4(dt, steps)
     ref = s.get_state()
     pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, aa=False)
     out = np.empty_like(u0)
-    pool.submit(n=n, p=p, kind="hex", nsteps=steps, dt=dt, u_init=u0, u_out=out)
+    pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
     _drain(pool)
     assert np.array_equal(out, ref)
-    with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
-        pool.submit(n=3, p=3, kind="prism", nsteps=1, tgv_p0=1.0)

@@ -474,13 +474,6 @@ __global__ void __launch_bounds__(NT_)
     }
   }
   if constexpr (!AA) {
-    // line derivative and lifting weights, read with a per-thread index
-    __shared__ R sDz[n][n], sLz[2][n];
-    if (tid < n * n) sDz[tid / n][tid % n] = op.D[tid / n][tid % n];
-    if (tid < n) {
-      sLz[0][tid] = op.liftL[tid];
-      sLz[1][tid] = op.liftR[tid];
-    }
     lds_barrier();  // the face viscous fluxes have read the gradients
     // tdisf at the solution points, in place over the gradients
     for (int it = tid; it < EB * NU; it += NT_) {
@@ -505,9 +498,10 @@ __global__ void __launch_bounds__(NT_)
     lds_barrier();
     // M2 F~: reference normal flux at the own flux points (JS region, free
     // since the gradient phase): triangle faces from the zeta lines,
-    // quadrilateral faces from the triangle planes
-    for (int it = tid; it < EB * 5 * (NTN + 3 * n * n); it += NT_) {
-      const int le = it / (5 * (NTN + 3 * n * n)), r0 = it - le * (5 * (NTN + 3 * n * n));
+    // quadrilateral faces from the triangle planes (per plane where PL)
+    constexpr int NQF = PL ? 5 * n : 5 * 3 * n * n;
+    for (int it = tid; it < EB * (5 * NTN + NQF); it += NT_) {
+      const int le = it / (5 * NTN + NQF), r0 = it - le * (5 * NTN + NQF);
       const R* F = XS(le) + 5 * NU;  // component d of variable v at F[(d * 5 + v) * NU]
       R* NF = JS(le);
       if (r0 < 5 * NTN) {
@@ -521,6 +515,29 @@ __global__ void __launch_bounds__(NT_)
         }
         NF[(0 * 5 + v) * NFP + t] = -fm;  // zeta = -1: outward normal -e_zeta
         NF[(1 * 5 + v) * NFP + t] = fp;
+      } else if constexpr (PL) {
+        const int r1 = r0 - 5 * NTN, v = r1 / n, k = r1 - v * n;
+        R fx[NTN], fy[NTN];
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) {
+          fx[t] = F[(0 * 5 + v) * NU + t + NTN * k];
+          fy[t] = F[(1 * 5 + v) * NU + t + NTN * k];
+        }
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed) {
+          R nx, ny;
+          edge_normal<R>(ed, nx, ny);
+#pragma unroll
+          for (int i = 0; i < n; ++i) {
+            R sx = R(0), sy = R(0);
+#pragma unroll
+            for (int t = 0; t < NTN; ++t) {
+              sx += tri.Tedge[ed][i][t] * fx[t];
+              sy += tri.Tedge[ed][i][t] * fy[t];
+            }
+            NF[((2 + ed) * 5 + v) * NFP + i + n * k] = nx * sx + ny * sy;
+          }
+        }
       } else {
         const int r1 = r0 - 5 * NTN, v = r1 / (3 * n * n), r2 = r1 - v * (3 * n * n), ed = r2 / (n * n);
         const int r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
@@ -536,25 +553,67 @@ __global__ void __launch_bounds__(NT_)
       }
     }
     lds_barrier();
-    // (M1 - M3 M2) F~ at every solution point
-    for (int it = tid; it < EB * 5 * NU; it += NT_) {
-      const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
-      if (e >= E) continue;
-      const int k = s / NTN, t = s - k * NTN;
+    // (M1 - M3 M2) F~: the zeta derivative and triangle-face lifting per
+    // line, accumulated over the state slots (dead since the flux phase) ...
+    for (int it = tid; it < EB * 5 * NTN; it += NT_) {
+      const int le = it / (5 * NTN), r0 = it - le * (5 * NTN), v = r0 / NTN, t = r0 - v * NTN;
       const R* F = XS(le) + 5 * NU;
       const R* NF = JS(le);
-      R acc = R(0);
+      R z[n];
 #pragma unroll
-      for (int c = 0; c < NTN; ++c)
-        acc += tri.Dxi[t][c] * F[(0 * 5 + v) * NU + c + NTN * k] + tri.Deta[t][c] * F[(1 * 5 + v) * NU + c + NTN * k];
+      for (int c = 0; c < n; ++c) z[c] = F[(2 * 5 + v) * NU + t + NTN * c];
+      const R nm = NF[(0 * 5 + v) * NFP + t], np = NF[(1 * 5 + v) * NFP + t];
 #pragma unroll
-      for (int c = 0; c < n; ++c) acc += sDz[k][c] * F[(2 * 5 + v) * NU + t + NTN * c];
-      acc -= sLz[0][k] * NF[(0 * 5 + v) * NFP + t] + sLz[1][k] * NF[(1 * 5 + v) * NFP + t];
+      for (int k = 0; k < n; ++k) {
+        R acc = -(op.liftL[k] * nm + op.liftR[k] * np);
 #pragma unroll
-      for (int ed = 0; ed < 3; ++ed)
+        for (int c = 0; c < n; ++c) acc += op.D[k][c] * z[c];
+        XS(le)[v * NU + t + NTN * k] = acc;
+      }
+    }
+    lds_barrier();
+    // ... then the (xi, eta) derivative blocks and quadrilateral-face lifting
+    constexpr int NDV = PL ? 5 * n : 5 * NU;
+    for (int it = tid; it < EB * NDV; it += NT_) {
+      const int le = it / NDV, r0 = it - le * NDV, e = e0 + le;
+      if (e >= E) continue;
+      const R* F = XS(le) + 5 * NU;
+      const R* NF = JS(le);
+      if constexpr (PL) {
+        const int v = r0 / n, k = r0 - v * n;
+        R fx[NTN], fy[NTN], nq[3][n];
 #pragma unroll
-        for (int i = 0; i < n; ++i) acc -= tri.LiftEdge[ed][t][i] * NF[((2 + ed) * 5 + v) * NFP + i + n * k];
-      Rp[(size_t)e * 5 * NU + r0] = acc;
+        for (int c = 0; c < NTN; ++c) {
+          fx[c] = F[(0 * 5 + v) * NU + c + NTN * k];
+          fy[c] = F[(1 * 5 + v) * NU + c + NTN * k];
+        }
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+          for (int i = 0; i < n; ++i) nq[ed][i] = NF[((2 + ed) * 5 + v) * NFP + i + n * k];
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) {
+          R acc = XS(le)[v * NU + t + NTN * k];
+#pragma unroll
+          for (int c = 0; c < NTN; ++c) acc += tri.Dxi[t][c] * fx[c] + tri.Deta[t][c] * fy[c];
+#pragma unroll
+          for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+            for (int i = 0; i < n; ++i) acc -= tri.LiftEdge[ed][t][i] * nq[ed][i];
+          Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = acc;
+        }
+      } else {
+        const int v = r0 / NU, s = r0 - v * NU, k = s / NTN, t = s - k * NTN;
+        R acc = XS(le)[r0];
+#pragma unroll
+        for (int c = 0; c < NTN; ++c)
+          acc += tri.Dxi[t][c] * F[(0 * 5 + v) * NU + c + NTN * k] + tri.Deta[t][c] * F[(1 * 5 + v) * NU + c + NTN * k];
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+          for (int i = 0; i < n; ++i) acc -= tri.LiftEdge[ed][t][i] * NF[((2 + ed) * 5 + v) * NFP + i + n * k];
+        Rp[(size_t)e * 5 * NU + r0] = acc;
+      }
     }
     return;
   }

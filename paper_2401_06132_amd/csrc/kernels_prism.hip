@@ -150,8 +150,12 @@ struct PrismVol {
   // bank conflicts: T1 rows of NTQ + 1, Z variables NTQ n + 4 apart
   static constexpr int TQS = NTQ + 1, ZVS = NTQ * n + 4;
   static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * TQS, SZ_Z = 15 * ZVS;
+  static constexpr int EFS = 3 * NFP + 1;  // the 20 fields at the quadrilateral-face points,
+  static constexpr int SZ_EF = 20 * EFS;   // odd stride per field (no bank conflicts)
+  static constexpr int SZ_JE = SZ_J > SZ_EF ? SZ_J : SZ_EF;
   static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
-  static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
+  static constexpr int SZ_B1 = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
+  static constexpr int SZ_B = SZ_B1 > SZ_EF ? SZ_B1 : SZ_EF;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
 };
 
@@ -178,7 +182,11 @@ __global__ void __launch_bounds__(NT_)
                  const double eref) {
   using C = PrismVol<P>;
   constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
-  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + C::SZ_J;
+  // single precision up to p = 3: triangle-plane work one (field, plane) per
+  // thread with broadcast operator reads (enough planes fill the workgroup);
+  // otherwise one output point per thread
+  constexpr bool PL = sizeof(R) == 4 && P <= 3;
+  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + (PL ? C::SZ_JE : C::SZ_J);
   static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
   __shared__ PrismTri<P, R> tri;
   __shared__ R smem[EB * PE];
@@ -271,10 +279,7 @@ __global__ void __launch_bounds__(NT_)
   // phase 1: jumps C - u^f (eq. FR-conu) at every own flux point, in place
   // over the neighbour values: triangle faces (line interpolation in zeta,
   // one line per thread), quadrilateral faces (triangle-plane interpolation
-  // to the edge points).  PL: one (variable, plane) per thread with broadcast
-  // operator reads, which pays where enough planes fill the workgroup (single
-  // precision up to p = 3); otherwise one edge point per thread.
-  constexpr bool PL = sizeof(R) == 4 && P <= 3;
+  // to the edge points): per plane (PL) or per edge point.
   constexpr int NJ_TRI = 5 * NTN, NJ_QUAD = PL ? 5 * n : 5 * 3 * n * n;
   for (int it = tid; it < EB * (NJ_TRI + NJ_QUAD); it += NT_) {
     const int le = it / (NJ_TRI + NJ_QUAD), r0 = it - le * (NJ_TRI + NJ_QUAD), e = e0 + le;
@@ -414,7 +419,30 @@ __global__ void __launch_bounds__(NT_)
   }
   lds_barrier();
 
-  // phase 4a: normal viscous flux at own flux points (gradcoru_fpts)
+  // phase 4a: normal viscous flux at own flux points (gradcoru_fpts).  With
+  // PL the 20 fields are first interpolated to the quadrilateral-face points
+  // one (field, plane) per thread into LDS (the jump region, free since the
+  // gradient phase)
+  if constexpr (PL) {
+    for (int it = tid; it < EB * 20 * n; it += NT_) {
+      const int le = it / (20 * n), fk = it - le * (20 * n), fld = fk / n, k = fk - fld * n;
+      const R* x = XS(le) + fld * NU + NTN * k;
+      R xv[NTN];
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) xv[t] = x[t];
+      R* EF = JS(le) + fld * C::EFS;
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * xv[t];
+          EF[ed * NFP + i + n * k] = s;
+        }
+    }
+    lds_barrier();
+  }
   constexpr int NV_TRI = NTN, NV_QUAD = 3 * n * n;
   for (int it = tid; it < EB * (NV_TRI + NV_QUAD); it += NT_) {
     const int le = it / (NV_TRI + NV_QUAD), r0 = it - le * (NV_TRI + NV_QUAD), e = e0 + le;
@@ -461,8 +489,12 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int fld = 0; fld < 20; ++fld) {
         R s = R(0);
+        if constexpr (PL) {
+          s = JS(le)[fld * C::EFS + ed * NFP + i + n * k];
+        } else {
 #pragma unroll
-        for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * X[fld * NU + t + NTN * k];
+          for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * X[fld * NU + t + NTN * k];
+        }
         if (fld < 5)
           u[fld] = s;
         else
@@ -617,6 +649,7 @@ __global__ void __launch_bounds__(NT_)
     }
     return;
   }
+  if constexpr (PL) lds_barrier();  // every edge point has read its fields
   // phase 4b: triangle-plane interpolation of the 20 fields to the triangle
   // quadrature points (first factor of M7 / M10): one (field, plane) per
   // thread, its N_t values in registers, operator entries read from the LDS

@@ -36,6 +36,11 @@ Parity status (pins live in tests/test_oracle_*.py):
     symmetry, one-dimensional reduction, design-order convergence to exact
     time derivatives (entropy wave, heat conduction) and the closed-form
     initial kinetic-energy decay rate of the Taylor-Green vortex.
+  * surface-flux anti-aliasing (Mesh(..., surf_aa=True)): the rebuilt lifting
+    is pinned against explicit Lagrange polynomials and high-order face
+    integration; the right-hand side by free stream, conservation, equality
+    with the flux-point form when every interface flux is a face polynomial
+    of degree <= p, and design-order convergence (test_oracle_surface_aa.py).
   * The full right-hand side at a perturbed state has no closed form; it is
     pinned only through the properties above.
 """

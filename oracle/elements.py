@@ -17,6 +17,17 @@ there; callers cast them to their working precision (rounding once).
 Anti-aliasing quadrature (section 2.1.1): hex GL(m)^3; prism conical triangle
 rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default.
 
+Surface-flux anti-aliasing (surf_aa=True, section 2.1.1 and table
+"operatorms"): the flux points are replaced by quadrature points on the
+faces -- GL(m)^2 on every quadrilateral face (index a + m b), the conical
+triangle rule with (p+1)^2 points on the prism triangles -- and every
+operator acting on flux points (M0, M3, M6) is rebuilt for that point set.
+The lifting integral is then taken with the face rule itself,
+E[u, f] = l_u(x^f) w_f; on quadrilaterals this is the exact DG lifting of
+the GL(m) Lagrange basis (the rule integrates degree p + m - 1 exactly); on
+triangles a (p+1)^2-point set defines no nodal basis, so the quadrature form
+is the definition used there (a reading).
+
 Operators (section 2.2; shapes as implied by the products):
   M0[f, u]     = l_u(x^f)                               disu
   Dg[d, s, u]  = d l_u / d xi_d (x^u_s)                 M4 (gradient) and M1
@@ -36,10 +47,12 @@ from . import basis, quadrature
 
 
 class RefElement:
-    def __init__(self, etype, p, m=None, tri_nodes=None):
+    def __init__(self, etype, p, m=None, tri_nodes=None, surf_aa=False):
         if m is None:
             m = p + 3
         self.etype, self.p, self.n, self.m = etype, p, p + 1, m
+        self.surf_aa = surf_aa
+        self.fwts = None  # face quadrature weights per flux point (surf_aa)
         n = self.n
         gl, glw = quadrature.gauss_legendre(n)
         self.gl, self.glw = gl, glw
@@ -73,8 +86,11 @@ class RefElement:
                 nrm[axis] = sgn
                 faces.append(dict(kind="quad", map=fmap, normal=nrm, jac=1.0))
         self.faces = faces
-        self._quad_face_points(gl)
         qx, qw = quadrature.gauss_legendre(m)
+        if self.surf_aa:
+            self._quad_face_points(qx, qw)
+        else:
+            self._quad_face_points(gl)
         self.qpts = np.array([(qx[i], qx[j], qx[k]) for k in range(m) for j in range(m) for i in range(m)])
         self.qwts = np.array([qw[i] * qw[j] * qw[k] for k in range(m) for j in range(m) for i in range(m)])
 
@@ -103,35 +119,54 @@ class RefElement:
                 return np.stack([xi, eta, t], axis=1)
             faces.append(dict(kind="quad", map=qmap, normal=nrm, jac=jac))
         self.faces = faces
-        fp, fid = [], []
+        tq, tw = quadrature.triangle_conical(p + 1)
+        fp, fid, fw = [], [], []
         for f, fc in enumerate(faces):
             if fc["kind"] == "tri":
-                x = fc["map"](tn[:, 0], tn[:, 1])
+                if self.surf_aa:
+                    x = fc["map"](tq[:, 0], tq[:, 1])
+                    fw.append(tw * fc["jac"])
+                else:
+                    x = fc["map"](tn[:, 0], tn[:, 1])
             else:
-                s = np.array([gl[a] for b in range(n) for a in range(n)])
-                t = np.array([gl[b] for b in range(n) for a in range(n)])
+                if self.surf_aa:
+                    g1, w1 = quadrature.gauss_legendre(m)
+                else:
+                    g1, w1 = gl, None
+                k = len(g1)
+                s = np.array([g1[a] for b in range(k) for a in range(k)])
+                t = np.array([g1[b] for b in range(k) for a in range(k)])
                 x = fc["map"](s, t)
+                if self.surf_aa:
+                    fw.append(np.array([w1[a] * w1[b] for b in range(k) for a in range(k)]) * fc["jac"])
             fp.append(x)
             fid += [f] * len(x)
         self.fpts = np.concatenate(fp)
         self.fface = np.array(fid)
         self.fnorm = np.array([faces[f]["normal"] for f in self.fface])
-        tq, tw = quadrature.triangle_conical(p + 1)
+        if self.surf_aa:
+            self.fwts = np.concatenate(fw)
         lq, lw = quadrature.gauss_legendre(m)
         self.qpts = np.array([(tq[t, 0], tq[t, 1], lq[k]) for k in range(m) for t in range(len(tq))])
         self.qwts = np.array([tw[t] * lw[k] for k in range(m) for t in range(len(tq))])
 
-    def _quad_face_points(self, gl):
-        n = self.n
-        s = np.array([gl[a] for b in range(n) for a in range(n)])
-        t = np.array([gl[b] for b in range(n) for a in range(n)])
-        fp, fid = [], []
+    def _quad_face_points(self, g1, w1=None):
+        """Tensor points g1 x g1 on every (quadrilateral) face; with weights
+        w1 the points are a face quadrature rule (surface-flux AA)."""
+        k = len(g1)
+        s = np.array([g1[a] for b in range(k) for a in range(k)])
+        t = np.array([g1[b] for b in range(k) for a in range(k)])
+        fp, fid, fw = [], [], []
         for f, fc in enumerate(self.faces):
             fp.append(fc["map"](s, t))
-            fid += [f] * (n * n)
+            fid += [f] * (k * k)
+            if w1 is not None:
+                fw.append(np.array([w1[a] * w1[b] for b in range(k) for a in range(k)]) * fc["jac"])
         self.fpts = np.concatenate(fp)
         self.fface = np.array(fid)
         self.fnorm = np.array([self.faces[f]["normal"] for f in self.fface])
+        if w1 is not None:
+            self.fwts = np.concatenate(fw)
 
     # ------------------------------------------------------------ operators
     def _build_operators(self):
@@ -149,6 +184,13 @@ class RefElement:
         self.M8 = massinv @ (Lq.T @ W)
         self.wu = Lq.T @ self.qwts
 
+        if self.surf_aa:
+            # flux points are face quadrature points: the lifting integral
+            # taken with the face rule, E[u, f] = l_u(x^f) w_f
+            E = self.M0.T * np.asarray(self.fwts, dtype=basis.EXT)[None, :]
+            self.M3 = massinv @ E
+            self.M6 = self.fnorm.T[:, None, :] * self.M3[None, :, :]
+            return
         # DG lifting: E[u, f] = int_face(f) l_u l^face_f dS_ref
         E = np.zeros((self.nu, self.nf), dtype=basis.EXT)
         gl = self.gl

@@ -12,6 +12,8 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                    A: x = x0 + (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + (xi+1) h/2
                    B: x = x0 + h - (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + h - (xi+1) h/2
   kind "mixed" : hexahedra in cells whose centre has z < 0, prisms elsewhere.
+surf_aa=True builds the reference elements with surface-flux
+anti-aliasing (flux points at the face quadrature points).
 Element numbering: cells in index order; a prism cell yields A then B.  The
 position in that sequence is the global element id; each element type keeps
 its own elements in order of appearance.
@@ -30,7 +32,7 @@ from .elements import RefElement
 
 
 class Mesh:
-    def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None):
+    def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None, surf_aa=False):
         self.nx, self.ny, self.nz, self.p, self.kind = nx, ny, nz, p, kind
         self.lo, self.hi = lo, hi
         L = hi - lo
@@ -40,7 +42,7 @@ class Mesh:
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"]}[kind]
         self.refs = {}
         for t in types:
-            self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes)
+            self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
         org = {t: [] for t in types}
         A = {t: [] for t in types}
         gid = {t: [] for t in types}

@@ -22,6 +22,10 @@ Without flux anti-aliasing (the paper's "AA off" configuration) steps 7, 8
 and the projection M8 are absent: tdisf evaluates the flux at the solution
 points from U and Q, and that F~^u enters step 10 directly.
 
+Surface-flux anti-aliasing needs no change here: it is a property of the
+mesh's reference elements (flux points at the face quadrature points, with
+M0, M3 and M6 rebuilt), and every step above applies unchanged.
+
 Arrays: the state of element type t is U[t] with shape (E_t, 5, N_u)
 (element, variable, solution point).
 """

@@ -74,9 +74,13 @@ def rhs_bytes_model(p, bytes_real):
     return b
 
 
-def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex", aa=True):
+def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex", aa=True, surface_aa=False):
     from paper_2401_06132_amd import inputs
-    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form, aa=aa)
+    if form in ("noaa", "fullaa"):
+        # the fused path without flux anti-aliasing (the paper's "AA off"), or
+        # with flux and surface-flux anti-aliasing (its "full AA")
+        aa, surface_aa, form = form == "fullaa", form == "fullaa", "fused"
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form, aa=aa, surface_aa=surface_aa)
     coords = s.upts_coords()
     U = inputs.element_state(coords, seed=0)
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
@@ -311,19 +315,19 @@ def main():
         ("fp32", 3, "fused", "prism"), ("fp64", 3, "fused", "prism"), ("fp64", 3, "plain", "prism"),
         ("fp32", 4, "fused", "prism"),
         ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex"),
-        ("fp32", 3, "noaa", "prism"), ("fp32", 4, "noaa", "prism")]
+        ("fp32", 3, "noaa", "prism"), ("fp32", 4, "noaa", "prism"),
+        ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
+        ("fp64", 4, "fullaa", "hex")]
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
-        # "noaa": the fused path without flux anti-aliasing (the paper's AA-off column)
-        r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, "fused" if form == "noaa" else form,
-                         kind, aa=form != "noaa")
+        r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)
         br = 4 if prec == "fp32" else 8
         vb, vf = volume_model(p, br)
         E = r["n_elem"]
         r["gdof_s"] = r["n_dof"] * ksteps / r["wall_s"] / 1e9
         if kind == "hex":
             r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
-            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12 if form != "noaa" else float("nan")
+            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12 if form == "fused" else float("nan")
             r["rhs_GBs"] = rhs_bytes_model(p, br) * E * ksteps / r["wall_s"] / 1e9
         else:
             r["vol_GBs"] = r["vol_TFLOPs"] = r["rhs_GBs"] = float("nan")

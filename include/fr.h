@@ -84,16 +84,29 @@ typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
  *                        0: no anti-aliasing, the flux is evaluated at the
  *                        solution points (the paper's "AA off"
  *                        configuration), in the fused form (the plain form
- *                        reports FR_EUNSUPPORTED). */
+ *                        reports FR_EUNSUPPORTED).
+ *   surface_aa         : 1: surface-flux anti-aliasing as well (section
+ *                        2.1.1, table "operatorms": the interface flux
+ *                        points are replaced by the face quadrature points,
+ *                        GL(p+3)^2 on quadrilateral faces), i.e. the paper's
+ *                        "full AA" together with flux_aa = 1.  Requires
+ *                        flux_aa = 1 and the fused form (else
+ *                        FR_EUNSUPPORTED).  The state layout and the
+ *                        flux-point arrays do not change: the common flux is
+ *                        evaluated at the face quadrature points and lifted
+ *                        through its projection onto the flux points.
+ *                        0 (default): interface fluxes at the flux points. */
 typedef struct {
   double gamma, prandtl, mu, ldg_beta, ldg_tau, pref;
-  int prec;     /* fr_precision */
-  int form;     /* fr_form */
-  int flux_aa;  /* 1 (default) or 0 */
+  int prec;        /* fr_precision */
+  int form;        /* fr_form */
+  int flux_aa;     /* 1 (default) or 0 */
+  int surface_aa;  /* 0 (default) or 1 */
 } fr_physics;
 
 /* Fill *ph with the Taylor-Green defaults: gamma 1.4, Pr 0.71, mu 1/1600,
- * beta 0.5, tau 0.1, pref 0, FP64, fused, flux anti-aliasing on. */
+ * beta 0.5, tau 0.1, pref 0, FP64, fused, flux anti-aliasing on, surface-flux
+ * anti-aliasing off. */
 void fr_physics_default(fr_physics* ph);
 
 /* Create a context.  hip_stream: a hipStream_t or NULL (null stream).  No

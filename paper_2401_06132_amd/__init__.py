@@ -33,7 +33,8 @@ SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_up
 class FrPhysics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
                 ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("pref", ctypes.c_double),
-                ("prec", ctypes.c_int), ("form", ctypes.c_int), ("flux_aa", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("form", ctypes.c_int), ("flux_aa", ctypes.c_int),
+                ("surface_aa", ctypes.c_int)]
 
 
 class FrRequest(ctypes.Structure):
@@ -100,8 +101,11 @@ def load_library(path=None):
 
 
 def physics(gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0, prec="fp64", form="fused",
-            aa=True):
-    return FrPhysics(gamma, prandtl, mu, beta, tau, pref, PREC[prec], FORM[form], 1 if aa else 0)
+            aa=True, surface_aa=False):
+    """aa: flux anti-aliasing; surface_aa: surface-flux anti-aliasing as well
+    (the paper's "full AA" with aa=True)."""
+    return FrPhysics(gamma, prandtl, mu, beta, tau, pref, PREC[prec], FORM[form], 1 if aa else 0,
+                     1 if surface_aa else 0)
 
 
 def ref_operator(etype, p, name):

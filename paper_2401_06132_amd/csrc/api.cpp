@@ -283,6 +283,7 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
       a.rk = rk;
       a.from_ust = rk > 0;
       a.aa = c->ph.flux_aa != 0;
+      a.saa = c->ph.surface_aa != 0;
       hipError_t e = t == 0 ? fr::hex_rhs(a, c->ph.prec, c->st) : fr::prism_rhs(a, c->ph.prec, c->st);
       if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
@@ -304,6 +305,7 @@ void fr_physics_default(fr_physics* ph) {
   ph->prec = FR_PREC_FP64;
   ph->form = FR_FORM_FUSED;
   ph->flux_aa = 1;
+  ph->surface_aa = 0;
 }
 
 fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
@@ -311,10 +313,11 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
   *out = nullptr;
   if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
       !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
-      ph->form > 1 || ph->flux_aa < 0 || ph->flux_aa > 1)
+      ph->form > 1 || ph->flux_aa < 0 || ph->flux_aa > 1 || ph->surface_aa < 0 || ph->surface_aa > 1)
     return FR_EINVAL;
   if (ph->form == FR_FORM_PLAIN && ph->prec != FR_PREC_FP64) return FR_EUNSUPPORTED;
-  if (ph->form == FR_FORM_PLAIN && !ph->flux_aa) return FR_EUNSUPPORTED;
+  if (ph->form == FR_FORM_PLAIN && (!ph->flux_aa || ph->surface_aa)) return FR_EUNSUPPORTED;
+  if (ph->surface_aa && !ph->flux_aa) return FR_EUNSUPPORTED;
   fr_ctx* c = new (std::nothrow) fr_ctx();
   if (!c) return FR_ENOMEM;
   c->ph = *ph;
@@ -329,6 +332,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   if (c->mesh_ok) return fail(c, FR_ESTATE, "mesh already built");
   if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind > 2) return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
+  if (c->ph.surface_aa && kind != FR_MESH_HEX)
+    return fail(c, FR_EUNSUPPORTED, "surface-flux anti-aliasing is built for hexahedra only");
   try {
     c->p = p;
     fr::build_ref(0, p, c->ref[0]);

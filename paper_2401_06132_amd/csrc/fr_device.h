@@ -149,6 +149,43 @@ __device__ __forceinline__ void common_flux(const R uL[5], const R uR[5], const 
     F[1 + k] = R(0.5) * (fl[1 + k] + fr[1 + k]) + a * (uL[1 + k] - uR[1 + k]) - (bl * VL[k] - br * VR[k]);
 }
 
+// The two parts of common_flux, for surface-flux anti-aliasing, where the
+// nonlinear Rusanov part is evaluated at the face quadrature points and the
+// part that is linear in the two sides' values at the flux points:
+//   rusanov_flux : 1/2 (f^e_L + f^e_R).n + 1/2 s (uL - uR)
+//   linear_flux  : tau (uL - uR) - [(1/2 + beta) VL - (1/2 - beta) VR]
+template <typename R>
+__device__ __forceinline__ void euler_normal(const R u[5], const R n[3], const Gas<R>& g, R f[5], R& s) {
+  const R ir = rcp(u[0]);
+  const R vn = (u[1] * n[0] + u[2] * n[1] + u[3] * n[2]) * ir;
+  const R pp = g.gm1 * (u[4] - R(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir);
+  f[0] = u[0] * vn;
+  f[1] = u[1] * vn + pp * n[0];
+  f[2] = u[2] * vn + pp * n[1];
+  f[3] = u[3] * vn + pp * n[2];
+  f[4] = vn * (u[4] + pp + g.href);
+  s = fabs(vn) + sqrt(g.gamma * (pp + g.pref) * ir);
+}
+
+template <typename R>
+__device__ __forceinline__ void rusanov_flux(const R uL[5], const R uR[5], const R n[3], const Gas<R>& g, R F[5]) {
+  R fl[5], fr[5], sl, sr;
+  euler_normal(uL, n, g, fl, sl);
+  euler_normal(uR, n, g, fr, sr);
+  const R a = R(0.5) * (sl > sr ? sl : sr);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = R(0.5) * (fl[v] + fr[v]) + a * (uL[v] - uR[v]);
+}
+
+template <typename R>
+__device__ __forceinline__ void linear_flux(const R uL[5], const R uR[5], const R VL[4], const R VR[4],
+                                            const Gas<R>& g, R F[5]) {
+  const R bl = R(0.5) + g.beta, br = R(0.5) - g.beta;
+  F[0] = g.tau * (uL[0] - uR[0]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) F[1 + k] = g.tau * (uL[1 + k] - uR[1 + k]) - (bl * VL[k] - br * VR[k]);
+}
+
 // Per-slot face record shared by the fused kernels.
 struct FaceRec {
   int32_t nbr;   // paired slot

@@ -64,6 +64,7 @@ struct TypeArgs {
   bool diag = false;    // every element has a diagonal Jacobian
   bool from_ust = false;  // disu/volume read Seg::ust instead of Seg::U
   bool aa = true;       // flux anti-aliasing (false: flux at the solution points)
+  bool saa = false;     // surface-flux anti-aliasing (only together with aa)
   int rk = -1;          // -1: surface writes du; 0..3: fused classical RK4 stage
   Seg one;              // the segment when bt is null
   const BlkRef* bt[3] = {nullptr, nullptr, nullptr};  // per-kernel workgroup tables
@@ -77,8 +78,8 @@ struct TypeArgs {
 hipError_t hex_rhs(const TypeArgs& a, int prec, hipStream_t st);
 hipError_t prism_rhs(const TypeArgs& a, int prec, hipStream_t st);
 // elements per workgroup of kernel k (K_DISU, K_VOLUME, K_SURFACE)
-int hex_block_elems(int p, int prec, int k);
-int prism_block_elems(int p, int prec, int k);
+int hex_block_elems(int p, int prec, int k, bool saa);
+int prism_block_elems(int p, int prec, int k, bool saa);
 // size in bytes of the prism operator table for order p and precision prec,
 // and its packing into host memory (uploaded once per context)
 size_t prism_ops_bytes(int p, int prec);

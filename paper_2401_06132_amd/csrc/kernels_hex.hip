@@ -131,6 +131,11 @@ struct HexVol {
   static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
   static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
+  // surface-flux anti-aliasing, per axis: face values interpolated along the
+  // first tangential axis [2][20][m][n], viscous flux at the face
+  // quadrature points [2][4][m][m]
+  static constexpr int SZ_ST = 2 * 20 * m * n, SZ_S = SZ_ST + 2 * 4 * m * m;
+  static_assert(SZ_S <= SZ_B, "face quadrature staging fits region B");
 };
 
 // Loads of one batch of EB elements, held in registers: the state, face
@@ -235,14 +240,26 @@ struct HexVolLoads {
 
 // AA: flux anti-aliasing (quadrature GL(p+3)^3); without it the flux is
 // evaluated at the solution points and its divergence uses -W^-1 D^T W
-// along each direction (exact for the GL solution points)
-template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA>
+// along each direction (exact for the GL solution points).
+// SAA: surface-flux anti-aliasing (face quadrature GL(p+3)^2).  With the
+// flux points moved to the face quadrature points, the lifting of face data
+// factorises into the projection P x P onto the GL(n)^2 flux points followed
+// by the lifting of those (the GL(m) rule integrates l_u L_f exactly).  The
+// common solution is linear in the two sides' states and the LDG viscous
+// flux is linear in the two sides' normal viscous fluxes, so the projected
+// common solution is the common solution of the flux-point states, and each
+// side may project its own viscous flux: this kernel evaluates n . f^v at
+// the face quadrature points (from the solution and corrected gradient
+// interpolated there) and stores its projection at the flux points.  Only
+// the Rusanov flux, nonlinear in the pair, is left to the interface kernel.
+template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA, bool SAA>
 __global__ void __launch_bounds__(NT)
     hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                const HexOps<P, R> op, const Gas<R> g, const double eref) {
   using C = HexVol<P>;
   constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
-  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + C::SZ_J;
+  constexpr int SZ_BN = SAA && C::SZ_S > C::SZ_J ? C::SZ_S : C::SZ_J;  // region B without AA
+  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + SZ_BN;
   static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
@@ -265,6 +282,7 @@ __global__ void __launch_bounds__(NT)
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
 #define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][m][n][n]                */
 #define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][m][m][n]              */
+#define SS(le) (smem + (le)*PE + C::SZ_A)  /* [2][20][m][n], [2][4][m][m]  */
 
   // phase 0: state (reference form), metrics, neighbour states at own
   // faces.  Face records, face geometry and the permutation table go to LDS
@@ -334,6 +352,99 @@ __global__ void __launch_bounds__(NT)
     lds_barrier();
   }
 
+  if constexpr (SAA) {
+    // phase 3a with surface-flux anti-aliasing, one axis (two faces) at a
+    // time: S1 interpolates the 20 fields to the face (normal direction) and
+    // along the first tangential axis to GL(m); S2 along the second and
+    // evaluates n . f^v at each face quadrature point; S3 projects it back to
+    // the flux points (P along the second axis, then the first)
+    __shared__ R sPj[n][m];  // read with a per-thread row index
+    if (tid < n * m) sPj[tid / m][tid % m] = op.Pj[tid / m][tid % m];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      for (int it = tid; it < EB * 40 * n; it += NT) {
+        const int le = it / (40 * n), r0 = it - le * (40 * n), side = r0 / (20 * n), r1 = r0 - side * (20 * n);
+        const int fld = r1 / n, b = r1 - fld * n;
+        const R* X = XS(le) + fld * NU;
+        R y[n];
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
+          R s = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) s += (side ? op.rb[i] : op.lb[i]) * X[hex_pt<n>(ax, i, a, b)];
+          y[a] = s;
+        }
+        R* T = SS(le) + (side * 20 + fld) * m * n + b;
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) {
+          R s = R(0);
+#pragma unroll
+          for (int a = 0; a < n; ++a) s += op.I[a2][a] * y[a];
+          T[a2 * n] = s;
+        }
+      }
+      lds_barrier();
+      for (int it = tid; it < EB * 2 * m * m; it += NT) {
+        const int le = it / (2 * m * m), r0 = it - le * (2 * m * m), side = r0 / (m * m), r1 = r0 - side * (m * m);
+        const int a2 = r1 / m, b2 = r1 - a2 * m;
+        R Ib[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
+        const R* T = SS(le) + (side * 20 * m + a2) * n;
+        R w[20];
+#pragma unroll
+        for (int fld = 0; fld < 20; ++fld) {
+          R s = R(0);
+#pragma unroll
+          for (int b = 0; b < n; ++b) s += Ib[b] * T[fld * m * n + b];
+          w[fld] = s;
+        }
+        const int lf = le * 6 + 2 * ax + side;
+        const R sgn = (cFR[lf].info & 1) ? R(1) : R(-1);
+        const R nn[3] = {sgn * cFG[lf][0], sgn * cFG[lf][1], sgn * cFG[lf][2]};
+        R u[5], q[3][5], V[4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          u[v] = w[v];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) q[d][v] = w[5 + d * 5 + v];
+        }
+        normal_viscous(u, q, nn, g, V);
+        R* VQ = SS(le) + C::SZ_ST + side * 4 * m * m + a2 * m + b2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) VQ[k * m * m] = V[k];
+      }
+      lds_barrier();
+      // the next axis's S1 writes T (read above, before the barrier) and its
+      // S2 writes VQ only after the next barrier
+      for (int it = tid; it < EB * 8 * n; it += NT) {
+        const int le = it / (8 * n), r0 = it - le * (8 * n), side = r0 / (4 * n), r1 = r0 - side * (4 * n);
+        const int k = r1 / n, b = r1 - k * n, e = e0 + le;
+        if (e >= E) continue;
+        R pb[m];
+#pragma unroll
+        for (int b2 = 0; b2 < m; ++b2) pb[b2] = sPj[b][b2];
+        const R* VQ = SS(le) + C::SZ_ST + (side * 4 + k) * m * m;
+        R z[m];
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) {
+          R s = R(0);
+#pragma unroll
+          for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * VQ[a2 * m + b2];
+          z[a2] = s;
+        }
+        const size_t slot = (size_t)(slot_base + e * 6 + 2 * ax + side);
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
+          R s = R(0);
+#pragma unroll
+          for (int a2 = 0; a2 < m; ++a2) s += op.Pj[a][a2] * z[a2];
+          Vf[slot * 4 * NFP + k * NFP + a + n * b] = s;
+        }
+      }
+    }
+    lds_barrier();  // region B is reused below
+  } else {
   // phase 3a: gradcoru_fpts + normal viscous flux at the own flux points
   for (int it = tid; it < EB * 3 * NFP; it += NT) {
     const int le = it / (3 * NFP), r0 = it - le * (3 * NFP), ax = r0 / NFP, r = r0 - ax * NFP;
@@ -372,6 +483,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
     }
+  }
   }
   if constexpr (!AA) {
     // no anti-aliasing: transformed flux at each solution point, in place
@@ -557,6 +669,7 @@ __global__ void __launch_bounds__(NT)
 #undef JS
 #undef TS
 #undef ZS
+#undef SS
 }
 
 // -------------------------------------------------------------- surface
@@ -564,15 +677,32 @@ __global__ void __launch_bounds__(NT)
 // and det J are staged in LDS; the volume residual is prefetched before the
 // first barrier; every flux point's own and neighbour loads are issued
 // branch-free (out-of-range items read a valid address and are dropped).
-template <int P, typename R, int EB, int NT, bool BT>
+//
+// With surface-flux anti-aliasing (SAA) the common flux is wanted at the
+// GL(m)^2 face quadrature points and lifted from there, which equals lifting
+// its projection P x P onto the flux points.  The part of the common flux
+// that is linear in the two sides' values (LDG viscous flux, penalty) is
+// projected already (the viscous fluxes arrive projected from the volume
+// kernel; the states are face polynomials of degree p) and is evaluated at
+// the flux points; the Rusanov flux is evaluated at the quadrature points
+// from the interpolated pair of states and projected back.
+template <int P, typename R, int EB, int NT, bool BT, bool SAA>
 __global__ void __launch_bounds__(NT)
     hex_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
                 const HexOps<P, R> op, const Gas<R> g) {
   using C = HexCfg<P>;
-  constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
+  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
   constexpr int NI = (EB * 6 * NFP + NT - 1) / NT;  // flux points per thread
   constexpr int NL = (EB * 5 * NU + NT - 1) / NT;   // solution values per thread
+  // SAA staging per face: the pair of states at the flux points [10][NFP],
+  // later the Rusanov flux at the quadrature points [5][m][m] (sW); the
+  // states interpolated along the first tangential axis [10][m][n] (sT)
+  constexpr int SW = 10 * NFP > 5 * m * m ? 10 * NFP : 5 * m * m, ST = 10 * m * n;
   __shared__ R sD[EB * 30 * NFP];
+  __shared__ R sW[SAA ? EB * 6 * SW : 1];
+  __shared__ R sT[SAA ? EB * 6 * ST : 1];
+  __shared__ R sI[SAA ? m : 1][n];  // rows read with a per-thread index
+  __shared__ R sPj[SAA ? n : 1][m];
   __shared__ FaceRec sFR[EB * 6];
   __shared__ R sFG[EB * 6][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFP];
@@ -598,6 +728,12 @@ __global__ void __launch_bounds__(NT)
     sLift[1][tid] = op.liftR[tid];
   }
   if (tid < EB) sDet[tid] = sg.detj[e0 + tid < E ? e0 + tid : 0];
+  if constexpr (SAA) {
+    if (tid < m * n) {
+      sI[tid / n][tid % n] = op.I[tid / n][tid % n];
+      sPj[tid / m][tid % m] = op.Pj[tid / m][tid % m];
+    }
+  }
   R rp[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
@@ -638,16 +774,105 @@ __global__ void __launch_bounds__(NT)
       const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
       const R mag = sFG[lf][3];
       R F[5];
-      if (left)
-        common_flux(uo[q], un[q], Vo[q], Vn[q], nL, g, F);
-      else
-        common_flux(un[q], uo[q], Vn[q], Vo[q], nL, g, F);
       const R sc = left ? mag : -mag;
+      if constexpr (SAA) {
+        if (left)
+          linear_flux(uo[q], un[q], Vo[q], Vn[q], g, F);
+        else
+          linear_flux(un[q], uo[q], Vn[q], Vo[q], g, F);
+        R* W = sW + lf * SW + r;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          W[v * NFP] = left ? uo[q][v] : un[q][v];
+          W[(5 + v) * NFP] = left ? un[q][v] : uo[q][v];
+        }
+      } else {
+        if (left)
+          common_flux(uo[q], un[q], Vo[q], Vn[q], nL, g, F);
+        else
+          common_flux(un[q], uo[q], Vn[q], Vo[q], nL, g, F);
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) sD[lf * 5 * NFP + v * NFP + r] = sc * F[v];
     }
   }
   lds_barrier();
+  if constexpr (SAA) {
+    // the pair of states along the first tangential axis to GL(m)
+    for (int it = tid; it < EB * 60 * n; it += NT) {
+      const int lf = it / (10 * n), r0 = it - lf * (10 * n), fld = r0 / n, b = r0 - fld * n;
+      if (e0 + lf / 6 >= E) continue;
+      const R* W = sW + lf * SW + fld * NFP + n * b;
+      R y[n];
+#pragma unroll
+      for (int a = 0; a < n; ++a) y[a] = W[a];
+      R* T = sT + lf * ST + fld * m * n + b;
+#pragma unroll
+      for (int a2 = 0; a2 < m; ++a2) {
+        R s = R(0);
+#pragma unroll
+        for (int a = 0; a < n; ++a) s += op.I[a2][a] * y[a];
+        T[a2 * n] = s;
+      }
+    }
+    lds_barrier();
+    // along the second axis, then the Rusanov flux at each quadrature point
+    // (over the states: sW is free once the pass above has read it)
+    for (int it = tid; it < EB * 6 * m * m; it += NT) {
+      const int lf = it / (m * m), r0 = it - lf * (m * m), a2 = r0 / m, b2 = r0 - a2 * m;
+      if (e0 + lf / 6 >= E) continue;
+      R Ib[n];
+#pragma unroll
+      for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
+      const R* T = sT + lf * ST + a2 * n;
+      R uL[5], uR[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        R sl = R(0), sr = R(0);
+#pragma unroll
+        for (int b = 0; b < n; ++b) {
+          sl += Ib[b] * T[v * m * n + b];
+          sr += Ib[b] * T[(5 + v) * m * n + b];
+        }
+        uL[v] = sl;
+        uR[v] = sr;
+      }
+      const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
+      R F[5];
+      rusanov_flux(uL, uR, nL, g, F);
+      R* FQ = sW + lf * SW + a2 * m + b2;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) FQ[v * m * m] = F[v];
+    }
+    lds_barrier();
+    // projection to the flux points, added to the linear part
+    for (int it = tid; it < EB * 30 * n; it += NT) {
+      const int lf = it / (5 * n), r0 = it - lf * (5 * n), v = r0 / n, b = r0 - v * n;
+      if (e0 + lf / 6 >= E) continue;
+      R pb[m];
+#pragma unroll
+      for (int b2 = 0; b2 < m; ++b2) pb[b2] = sPj[b][b2];
+      const R* FQ = sW + lf * SW + v * m * m;
+      R z[m];
+#pragma unroll
+      for (int a2 = 0; a2 < m; ++a2) {
+        R s = R(0);
+#pragma unroll
+        for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * FQ[a2 * m + b2];
+        z[a2] = s;
+      }
+      const R sc = (sFR[lf].info & 1) ? sFG[lf][3] : -sFG[lf][3];
+      R* D = sD + lf * 5 * NFP + v * NFP + n * b;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        R s = R(0);
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) s += op.Pj[a][a2] * z[a2];
+        D[a] += sc * s;
+      }
+    }
+    lds_barrier();
+  }
   // tdivtconf (lift of the common flux, DG correction) + negdivconf
   double val[NL];
 #pragma unroll
@@ -722,49 +947,67 @@ template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };
 constexpr int HEX_DISU_EB = 8;
 // elements per workgroup of the interface kernel (256 threads): at most two
 // flux points and about five solution values per thread
-template <int P, bool DBL>
+template <int P, bool DBL, bool SAA = false>
 struct HexSurf {
-  static constexpr int EB = (DBL ? 8 : 16) >> (P - 1);
+  // surface-flux anti-aliasing stages the face quadrature data in LDS: half
+  // the elements per workgroup
+  static constexpr int EB0 = (DBL ? 8 : 16) >> (P - 1);
+  static constexpr int EB = SAA ? (EB0 > 1 ? EB0 / 2 : 1) : EB0;
 };
+
+template <int P, typename R, bool BT, bool DIAG, bool AA, bool SAA>
+static void hex_volume_launch(const TypeArgs& a, int nb, const HexOps<P, R>& op, const Gas<R>& g, double eref,
+                              hipStream_t st) {
+  constexpr bool dbl = sizeof(R) == 8;
+  constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
+  hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA>), dim3(nb), dim3(NT), 0, st, a.one,
+                     a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
+}
+
+// surface-flux anti-aliasing is built together with flux anti-aliasing only
+// (the paper's "full AA"); the library rejects it without
+template <int P, typename R, bool BT, bool DIAG>
+static void hex_volume_dispatch(const TypeArgs& a, int nb, const HexOps<P, R>& op, const Gas<R>& g, double eref,
+                                hipStream_t st) {
+  if (a.saa)
+    hex_volume_launch<P, R, BT, DIAG, true, true>(a, nb, op, g, eref, st);
+  else if (a.aa)
+    hex_volume_launch<P, R, BT, DIAG, true, false>(a, nb, op, g, eref, st);
+  else
+    hex_volume_launch<P, R, BT, DIAG, false, false>(a, nb, op, g, eref, st);
+}
 
 template <int P, typename R, bool BT>
 static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const HexOps<P, R> op = make_hex_ops<P, R>(*a.ops);
   const Gas<R> g = make_gas<R>(*a.gas);
   constexpr bool dbl = sizeof(R) == 8;
-  constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
-  constexpr int EBA = HEX_DISU_EB, NTA = 256, EBC = HexSurf<P, dbl>::EB, NTC = 256;
+  constexpr int EBA = HEX_DISU_EB, NTA = 256, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, eref);
   if ((a.stage & 2) && grid[K_VOLUME] > 0) {
-    const dim3 gv(grid[K_VOLUME]), bv(NT);
-    if (a.aa) {
-      if (a.diag)
-        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT, true>), gv, bv, 0, st, a.one, a.bt[K_VOLUME], a.segs,
-                           a.from_ust, op, g, eref);
-      else
-        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT, true>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
-                           a.segs, a.from_ust, op, g, eref);
-    } else {
-      if (a.diag)
-        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, true, BT, false>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
-                           a.segs, a.from_ust, op, g, eref);
-      else
-        hipLaunchKernelGGL((hex_volume<P, R, EB, NT, false, BT, false>), gv, bv, 0, st, a.one, a.bt[K_VOLUME],
-                           a.segs, a.from_ust, op, g, eref);
-    }
+    if (a.diag)
+      hex_volume_dispatch<P, R, BT, true>(a, grid[K_VOLUME], op, g, eref, st);
+    else
+      hex_volume_dispatch<P, R, BT, false>(a, grid[K_VOLUME], op, g, eref, st);
   }
-  if ((a.stage & 4) && grid[K_SURFACE] > 0)
-    hipLaunchKernelGGL((hex_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
-                       a.bt[K_SURFACE], a.segs, a.rk, op, g);
+  if ((a.stage & 4) && grid[K_SURFACE] > 0) {
+    if (a.saa)
+      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl, true>::EB, NTC, BT, true>), dim3(grid[K_SURFACE]),
+                         dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
+    else
+      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl>::EB, NTC, BT, false>), dim3(grid[K_SURFACE]), dim3(NTC),
+                         0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
+  }
 }
 
 template <int P, typename R>
 static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB, HexSurf<P, dbl>::EB};
+  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB,
+                      a.saa ? HexSurf<P, dbl, true>::EB : HexSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
   for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
@@ -775,15 +1018,21 @@ static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int hex_block_elems(int p, int prec, int k) {
+template <int P>
+static int hex_surf_elems(bool d, bool saa) {
+  return d ? (saa ? HexSurf<P, true, true>::EB : HexSurf<P, true>::EB)
+           : (saa ? HexSurf<P, false, true>::EB : HexSurf<P, false>::EB);
+}
+
+int hex_block_elems(int p, int prec, int k, bool saa) {
   if (k == K_DISU) return HEX_DISU_EB;
   const bool d = prec == 0;
   if (k == K_SURFACE) {
     switch (p) {
-      case 1: return d ? HexSurf<1, true>::EB : HexSurf<1, false>::EB;
-      case 2: return d ? HexSurf<2, true>::EB : HexSurf<2, false>::EB;
-      case 3: return d ? HexSurf<3, true>::EB : HexSurf<3, false>::EB;
-      case 4: return d ? HexSurf<4, true>::EB : HexSurf<4, false>::EB;
+      case 1: return hex_surf_elems<1>(d, saa);
+      case 2: return hex_surf_elems<2>(d, saa);
+      case 3: return hex_surf_elems<3>(d, saa);
+      case 4: return hex_surf_elems<4>(d, saa);
     }
     return 0;
   }

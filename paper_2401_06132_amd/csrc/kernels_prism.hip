@@ -1002,7 +1002,8 @@ static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int prism_block_elems(int p, int prec, int k) {
+int prism_block_elems(int p, int prec, int k, bool saa) {
+  (void)saa;
   if (k == K_DISU) return PRISM_DISU_EB;
   const bool d = prec == 0;
   if (k == K_SURFACE) {

@@ -279,6 +279,8 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind > 2)
     return pfail(P, FR_EINVAL, "bad mesh size");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
+  if (P->ph.surface_aa && q->kind != FR_MESH_HEX)
+    return pfail(P, FR_EUNSUPPORTED, "surface-flux anti-aliasing is built for hexahedra only");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
   if (!q->u_init && !(q->tgv_p0 > 0.0)) return pfail(P, FR_EINVAL, "no initial state and tgv_p0 <= 0");
   const int64_t cells = (int64_t)q->nx * q->ny * q->nz;
@@ -467,7 +469,9 @@ fr_status rebuild_tables(fr_pool* P) {
       const int32_t si = (int32_t)V.segs.size();
       V.segs.push_back(R.seg[t]);
       for (int k = 0; k < 3; ++k) {
-        const int eb = t == 0 ? fr::hex_block_elems(R.q.p, P->ph.prec, k) : fr::prism_block_elems(R.q.p, P->ph.prec, k);
+        const bool saa = P->ph.surface_aa != 0;
+        const int eb = t == 0 ? fr::hex_block_elems(R.q.p, P->ph.prec, k, saa)
+                              : fr::prism_block_elems(R.q.p, P->ph.prec, k, saa);
         for (int32_t e0 = 0; e0 < R.seg[t].E; e0 += eb) V.bt[k].push_back({si, e0});
       }
     }
@@ -514,6 +518,7 @@ fr_status enqueue_step(fr_pool* P, int* launches) {
         a.from_ust = st > 0;
         a.rk = st;
         a.aa = P->ph.flux_aa != 0;
+        a.saa = P->ph.surface_aa != 0;
         a.segs = (const fr::Seg*)(P->d_tab + V.off_segs);
         for (int j = 0; j < 3; ++j) {
           a.bt[j] = (const fr::BlkRef*)(P->d_tab + V.off_bt[j]);
@@ -553,9 +558,10 @@ fr_status fr_pool_create(const fr_physics* ph, void* stream, int64_t budget_byte
   *out = nullptr;
   if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
       !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 ||
-      ph->flux_aa < 0 || ph->flux_aa > 1)
+      ph->flux_aa < 0 || ph->flux_aa > 1 || ph->surface_aa < 0 || ph->surface_aa > 1)
     return FR_EINVAL;
   if (ph->form != FR_FORM_FUSED) return FR_EUNSUPPORTED;
+  if (ph->surface_aa && !ph->flux_aa) return FR_EUNSUPPORTED;
   if (budget_bytes <= 0 || max_active < 1) return FR_EINVAL;
   fr_pool* P = new (std::nothrow) fr_pool();
   if (!P) return FR_ENOMEM;

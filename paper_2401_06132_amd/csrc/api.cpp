@@ -332,8 +332,6 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   if (c->mesh_ok) return fail(c, FR_ESTATE, "mesh already built");
   if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind > 2) return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
-  if (c->ph.surface_aa && kind != FR_MESH_HEX)
-    return fail(c, FR_EUNSUPPORTED, "surface-flux anti-aliasing is built for hexahedra only");
   try {
     c->p = p;
     fr::build_ref(0, p, c->ref[0]);
@@ -342,6 +340,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
     if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
+    if (c->ph.surface_aa && !fr::prism_tri_faces_aligned(c->M))
+      return fail(c, FR_EUNSUPPORTED, "surface-flux anti-aliasing needs aligned prism triangle faces");
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }

@@ -89,6 +89,11 @@ struct Mesh {
 // element counts per type of a box mesh (same cell typing as build_box_mesh)
 void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[2]);
 
+// True if every prism triangle face sees its neighbour's triangle nodes in
+// the same order (identity point permutation), as surface-flux
+// anti-aliasing on the (unsymmetric) triangle quadrature rule requires.
+bool prism_tri_faces_aligned(const Mesh& m);
+
 // Build the box mesh and its connectivity; returns an error string or "".
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
                            const RefElem* refs[2], Mesh& m);

@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(NT)
     const int sa = ax == 0 ? n : 1, sb = ax == 2 ? n : n * n;
     for (int it = tid; it < EB * 5 * NFP; it += NT) {
       const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), v = r0 / NFP, r = r0 - v * NFP;
-      const int a = r % n, b = r / n, e = e0 + le;
+      const int a = r % n, b = r / n;
       R* X = XS(le);
       const int base = a * sa + b * sb;
       R x[n];

@@ -157,6 +157,13 @@ struct PrismVol {
   static constexpr int SZ_B1 = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
   static constexpr int SZ_B = SZ_B1 > SZ_EF ? SZ_B1 : SZ_EF;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
+  // surface-flux anti-aliasing, one round per face kind: the 20 fields at
+  // the two triangles' nodes [2][20][NTN] or along one quadrilateral's first
+  // axis at GL(m) [20][m][n] (offset 0); the viscous flux at the face
+  // quadrature points [2][4][NTQ] or [4][m][m] (offset SZ_S0)
+  static constexpr int SZ_S0 = 40 * NTN > 20 * m * n ? 40 * NTN : 20 * m * n;
+  static constexpr int SZ_S = SZ_S0 + (8 * NTQ > 4 * m * m ? 8 * NTQ : 4 * m * m);
+  static_assert(SZ_S <= SZ_B, "face quadrature staging fits region B");
 };
 
 // sum of a value over an adjacent lane pair (lanes 2i, 2i+1), both lanes get
@@ -174,8 +181,16 @@ __device__ __forceinline__ double pair_sum(double x) {
 
 // AA: flux anti-aliasing; without it the flux is evaluated at the solution
 // points and its divergence is taken in strong form, (M1 - M3 M2) F~: the
-// derivative blocks minus the lifted normal flux interpolated to the faces
-template <int P, typename R, int EB, int NT_, bool BT, bool AA>
+// derivative blocks minus the lifted normal flux interpolated to the faces.
+// SAA: surface-flux anti-aliasing (built with AA only).  The face quadrature
+// rules are the volume rule's factors: the conical triangle rule on the two
+// triangles and GL(m)^2 on the quadrilaterals.  As for hexahedra, each side
+// evaluates its normal viscous flux at the face quadrature points and stores
+// its projection onto the flux points: P_T = M_T^-1 T_q^T W on a triangle
+// (M_T the triangle mass matrix; lifting the projection reproduces the
+// quadrature-point lifting because the rule integrates M_T exactly) and
+// P x P on a quadrilateral.
+template <int P, typename R, int EB, int NT_, bool BT, bool AA, bool SAA>
 __global__ void __launch_bounds__(NT_)
     prism_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g, const Gas<R> g,
@@ -206,6 +221,7 @@ __global__ void __launch_bounds__(NT_)
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
 #define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][TQS]             */
 #define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][ZVS: NTQ][n]      */
+#define SS(le) (smem + (le)*PE + C::SZ_A)  /* face quadrature staging   */
 
   // phase 0: operator tables, state (reference form), metrics, neighbour states
   {
@@ -282,7 +298,7 @@ __global__ void __launch_bounds__(NT_)
   // to the edge points): per plane (PL) or per edge point.
   constexpr int NJ_TRI = 5 * NTN, NJ_QUAD = PL ? 5 * n : 5 * 3 * n * n;
   for (int it = tid; it < EB * (NJ_TRI + NJ_QUAD); it += NT_) {
-    const int le = it / (NJ_TRI + NJ_QUAD), r0 = it - le * (NJ_TRI + NJ_QUAD), e = e0 + le;
+    const int le = it / (NJ_TRI + NJ_QUAD), r0 = it - le * (NJ_TRI + NJ_QUAD);
     const R* X = XS(le);
     if (r0 < NJ_TRI) {
       const int v = r0 / NTN, t = r0 - v * NTN;
@@ -419,6 +435,156 @@ __global__ void __launch_bounds__(NT_)
   }
   lds_barrier();
 
+  if constexpr (SAA) {
+    // phase 4a with surface-flux anti-aliasing.  Triangle round: S1 the 20
+    // fields at both triangles' nodes (zeta lines), S2 T_q to the
+    // triangle quadrature points and n . f^v there, S3 P_T back to the nodes.
+    // Quadrilateral rounds (one per face): S1 the fields at the face's GL
+    // points (edge interpolation per plane) and I along the edge, S2 I along
+    // zeta and n . f^v at each GL(m)^2 point, S3 P x P back
+    __shared__ R sI[m][n];   // rows read with a per-thread index
+    __shared__ R sPj[n][m];
+    if (tid < m * n) {
+      sI[tid / n][tid % n] = op.I[tid / n][tid % n];
+      sPj[tid / m][tid % m] = op.Pj[tid / m][tid % m];
+    }
+    for (int it = tid; it < EB * 20 * NTN; it += NT_) {
+      const int le = it / (20 * NTN), r0 = it - le * (20 * NTN), fld = r0 / NTN, t = r0 - fld * NTN;
+      const R* X = XS(le) + fld * NU + t;
+      R sm = R(0), sp = R(0);
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const R x = X[NTN * k];
+        sm += op.lb[k] * x;
+        sp += op.rb[k] * x;
+      }
+      SS(le)[fld * NTN + t] = sm;
+      SS(le)[(20 + fld) * NTN + t] = sp;
+    }
+    lds_barrier();
+    for (int it = tid; it < EB * 2 * NTQ; it += NT_) {
+      const int le = it / (2 * NTQ), r0 = it - le * (2 * NTQ), side = r0 / NTQ, q = r0 - side * NTQ;
+      const R* FT = SS(le) + side * 20 * NTN;
+      R w[20];
+#pragma unroll
+      for (int fld = 0; fld < 20; ++fld) {
+        R s = R(0);
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) s += tri.Tq[q][t] * FT[fld * NTN + t];
+        w[fld] = s;
+      }
+      const int lf = le * 5 + side;
+      const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+      const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+      R u[5], q3[3][5], V[4];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = w[v];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) q3[d][v] = w[5 + d * 5 + v];
+      }
+      normal_viscous(u, q3, nn, g, V);
+      R* VT = SS(le) + C::SZ_S0 + side * 4 * NTQ + q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) VT[k * NTQ] = V[k];
+    }
+    lds_barrier();
+    for (int it = tid; it < EB * 8 * NTN; it += NT_) {
+      const int le = it / (8 * NTN), r0 = it - le * (8 * NTN), side = r0 / (4 * NTN), r1 = r0 - side * (4 * NTN);
+      const int k = r1 / NTN, t = r1 - k * NTN, e = e0 + le;
+      if (e >= E) continue;
+      const R* VT = SS(le) + C::SZ_S0 + (side * 4 + k) * NTQ;
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < NTQ; ++q) s += tri.PT[t][q] * VT[q];
+      Vf[(size_t)(slot_base + e * 5 + side) * 4 * NFP + k * NFP + t] = s;
+    }
+    // quadrilateral rounds: their S1 overwrites the triangle-node fields (read
+    // before the last barrier) and their S2 the triangle viscous fluxes (read
+    // above) only after the next barrier
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed) {
+      for (int it = tid; it < EB * 20 * n; it += NT_) {
+        const int le = it / (20 * n), r0 = it - le * (20 * n), fld = r0 / n, k = r0 - fld * n;
+        const R* X = XS(le) + fld * NU + NTN * k;
+        R xv[NTN];
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) xv[t] = X[t];
+        R y[n];
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int t = 0; t < NTN; ++t) s += tri.Tedge[ed][i][t] * xv[t];
+          y[i] = s;
+        }
+        R* T = SS(le) + fld * m * n + k;
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) {
+          R s = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) s += op.I[a2][i] * y[i];
+          T[a2 * n] = s;
+        }
+      }
+      lds_barrier();
+      for (int it = tid; it < EB * m * m; it += NT_) {
+        const int le = it / (m * m), r0 = it - le * (m * m), a2 = r0 / m, b2 = r0 - a2 * m;
+        R Ib[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
+        const R* T = SS(le) + a2 * n;
+        R w[20];
+#pragma unroll
+        for (int fld = 0; fld < 20; ++fld) {
+          R s = R(0);
+#pragma unroll
+          for (int k = 0; k < n; ++k) s += Ib[k] * T[fld * m * n + k];
+          w[fld] = s;
+        }
+        const int lf = le * 5 + 2 + ed;
+        const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+        const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+        R u[5], q3[3][5], V[4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          u[v] = w[v];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) q3[d][v] = w[5 + d * 5 + v];
+        }
+        normal_viscous(u, q3, nn, g, V);
+        R* VQ = SS(le) + C::SZ_S0 + a2 * m + b2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) VQ[k * m * m] = V[k];
+      }
+      lds_barrier();
+      for (int it = tid; it < EB * 4 * n; it += NT_) {
+        const int le = it / (4 * n), r0 = it - le * (4 * n), k = r0 / n, b = r0 - k * n, e = e0 + le;
+        if (e >= E) continue;
+        R pb[m];
+#pragma unroll
+        for (int b2 = 0; b2 < m; ++b2) pb[b2] = sPj[b][b2];
+        const R* VQ = SS(le) + C::SZ_S0 + k * m * m;
+        R z[m];
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) {
+          R s = R(0);
+#pragma unroll
+          for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * VQ[a2 * m + b2];
+          z[a2] = s;
+        }
+        const size_t slot = (size_t)(slot_base + e * 5 + 2 + ed);
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int a2 = 0; a2 < m; ++a2) s += op.Pj[i][a2] * z[a2];
+          Vf[slot * 4 * NFP + k * NFP + i + n * b] = s;
+        }
+      }
+    }
+    lds_barrier();  // region B is reused below
+  } else {
   // phase 4a: normal viscous flux at own flux points (gradcoru_fpts).  With
   // PL the 20 fields are first interpolated to the quadrilateral-face points
   // one (field, plane) per thread into LDS (the jump region, free since the
@@ -504,6 +670,7 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
     }
+  }
   }
   if constexpr (!AA) {
     lds_barrier();  // the face viscous fluxes have read the gradients
@@ -649,7 +816,7 @@ __global__ void __launch_bounds__(NT_)
     }
     return;
   }
-  if constexpr (PL) lds_barrier();  // every edge point has read its fields
+  if constexpr (PL && !SAA) lds_barrier();  // every edge point has read its fields
   // phase 4b: triangle-plane interpolation of the 20 fields to the triangle
   // quadrature points (first factor of M7 / M10): one (field, plane) per
   // thread, its N_t values in registers, operator entries read from the LDS
@@ -790,17 +957,40 @@ __global__ void __launch_bounds__(NT_)
 #undef JS
 #undef TS
 #undef ZS
+#undef SS
 }
 
 // -------------------------------------------------------------- surface
-template <int P, typename R, int EB, int NT_, bool BT>
+// With surface-flux anti-aliasing (SAA) the common flux is lifted through
+// its projection onto the flux points (P_T on the triangles, P x P on the
+// quadrilaterals): the part linear in the two sides' values at the flux
+// points, the Rusanov flux at the face quadrature points from the
+// interpolated pair of states (T_q on the triangles, I x I on the
+// quadrilaterals).  The triangle rule is not symmetric, so both sides of a
+// triangle face must see the same nodes: the library requires the identity
+// point permutation there.
+template <int P, typename R, int EB, int NT_, bool BT, bool SAA>
 __global__ void __launch_bounds__(NT_)
     prism_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
                   const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri, const Gas<R> g) {
   using C = PrismCfg<P>;
-  constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
+  constexpr int n = C::n, m = C::m, NT = C::NT, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
+  // SAA staging per face: the pair of states [10][NFP], later the Rusanov
+  // flux at a quadrilateral's quadrature points [5][m][m] (sW); a
+  // quadrilateral's states along its first axis at GL(m) [10][m][n] (sT);
+  // the Rusanov flux at a triangle's quadrature points [5][NTQ] (sFt)
+  constexpr int SW = 10 * NFP > 5 * m * m ? 10 * NFP : 5 * m * m, ST = 10 * m * n, SF = 5 * NTQ;
   __shared__ R sD[EB * 25 * NFP];
   __shared__ R sLift[3][NT][n];
+  __shared__ R sW[SAA ? EB * 5 * SW : 1];
+  __shared__ R sT[SAA ? EB * 3 * ST : 1];
+  __shared__ R sFt[SAA ? EB * 2 * SF : 1];
+  __shared__ R sTq[SAA ? NTQ : 1][NT];
+  __shared__ R sPT[SAA ? NT : 1][NTQ];
+  __shared__ R sI[SAA ? m : 1][n];
+  __shared__ R sPj[SAA ? n : 1][m];
+  __shared__ R sFG[SAA ? EB * 5 : 1][4];
+  __shared__ int sInfo[SAA ? EB * 5 : 1];
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -814,7 +1004,18 @@ __global__ void __launch_bounds__(NT_)
   const int fnp[5] = {NT, NT, NFP, NFP, NFP};
   // edge lifting table, staged in LDS for the per-point lift below
   for (int it = tid; it < 3 * NT * n; it += NT_) (&sLift[0][0][0])[it] = (&tri->LiftEdge[0][0][0])[it];
+  if constexpr (SAA) {
+    for (int it = tid; it < NTQ * NT; it += NT_) {
+      (&sTq[0][0])[it] = (&tri->Tq[0][0])[it];
+      (&sPT[0][0])[it] = (&tri->PT[0][0])[it];
+    }
+    if (tid < m * n) {
+      sI[tid / n][tid % n] = op.I[tid / n][tid % n];
+      sPj[tid / m][tid % m] = op.Pj[tid / m][tid % m];
+    }
+  }
   // comm_flux: common normal flux at every own flux point, times +-mag
+  // (with SAA: its linear part, and the pair of states to LDS)
   for (int it = tid; it < EB * 5 * NFP; it += NT_) {
     const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
     if (e >= E || r >= fnp[f]) continue;
@@ -835,13 +1036,148 @@ __global__ void __launch_bounds__(NT_)
     }
     const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
     const R mag = fgeo[4 * slot + 3];
-    if (left)
-      common_flux(uo, un, Vo, Vn, nL, g, F);
-    else
-      common_flux(un, uo, Vn, Vo, nL, g, F);
+    if constexpr (SAA) {
+      if (left)
+        linear_flux(uo, un, Vo, Vn, g, F);
+      else
+        linear_flux(un, uo, Vn, Vo, g, F);
+      R* W = sW + (le * 5 + f) * SW + r;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        W[v * NFP] = left ? uo[v] : un[v];
+        W[(5 + v) * NFP] = left ? un[v] : uo[v];
+      }
+      if (r == 0) {
+        sInfo[le * 5 + f] = fr.info;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sFG[le * 5 + f][k] = nL[k];
+        sFG[le * 5 + f][3] = mag;
+      }
+    } else {
+      if (left)
+        common_flux(uo, un, Vo, Vn, nL, g, F);
+      else
+        common_flux(un, uo, Vn, Vo, nL, g, F);
+    }
     const R sc = left ? mag : -mag;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sD[(le * 5 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
+  }
+  if constexpr (SAA) {
+    __syncthreads();
+    // triangles: Rusanov at the quadrature points (T_q of the pair);
+    // quadrilaterals: the pair along the first axis to GL(m)
+    constexpr int NA = 2 * NTQ + 3 * 10 * n;
+    for (int it = tid; it < EB * NA; it += NT_) {
+      const int le = it / NA, r0 = it - le * NA;
+      if (e0 + le >= E) continue;
+      if (r0 < 2 * NTQ) {
+        const int f = r0 / NTQ, q = r0 - f * NTQ, lf = le * 5 + f;
+        const R* W = sW + lf * SW;
+        R uL[5], uR[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          R sl = R(0), sr = R(0);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            sl += sTq[q][t] * W[v * NFP + t];
+            sr += sTq[q][t] * W[(5 + v) * NFP + t];
+          }
+          uL[v] = sl;
+          uR[v] = sr;
+        }
+        const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
+        R F[5];
+        rusanov_flux(uL, uR, nL, g, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sFt[(le * 2 + f) * SF + v * NTQ + q] = F[v];
+      } else {
+        const int r1 = r0 - 2 * NTQ, ed = r1 / (10 * n), r2 = r1 - ed * (10 * n), fld = r2 / n, k = r2 - fld * n;
+        const R* W = sW + (le * 5 + 2 + ed) * SW + fld * NFP + n * k;
+        R y[n];
+#pragma unroll
+        for (int i = 0; i < n; ++i) y[i] = W[i];
+        R* T = sT + (le * 3 + ed) * ST + fld * m * n + k;
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) {
+          R s = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) s += op.I[a2][i] * y[i];
+          T[a2 * n] = s;
+        }
+      }
+    }
+    __syncthreads();
+    // triangles: P_T of the Rusanov flux, added; quadrilaterals: the pair
+    // along zeta to GL(m) and Rusanov at each quadrature point (over the
+    // quadrilateral states, read in the previous pass)
+    constexpr int NB = 2 * 5 * NT + 3 * m * m;
+    for (int it = tid; it < EB * NB; it += NT_) {
+      const int le = it / NB, r0 = it - le * NB;
+      if (e0 + le >= E) continue;
+      if (r0 < 10 * NT) {
+        const int f = r0 / (5 * NT), r1 = r0 - f * (5 * NT), v = r1 / NT, t = r1 - v * NT, lf = le * 5 + f;
+        const R* Ft = sFt + (le * 2 + f) * SF + v * NTQ;
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < NTQ; ++q) s += sPT[t][q] * Ft[q];
+        const R sc = (sInfo[lf] & 1) ? sFG[lf][3] : -sFG[lf][3];
+        sD[lf * 5 * NFP + v * NFP + t] += sc * s;
+      } else {
+        const int r1 = r0 - 10 * NT, ed = r1 / (m * m), r2 = r1 - ed * (m * m), a2 = r2 / m, b2 = r2 - a2 * m;
+        const int lf = le * 5 + 2 + ed;
+        R Ib[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
+        const R* T = sT + (le * 3 + ed) * ST + a2 * n;
+        R uL[5], uR[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          R sl = R(0), sr = R(0);
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            sl += Ib[k] * T[v * m * n + k];
+            sr += Ib[k] * T[(5 + v) * m * n + k];
+          }
+          uL[v] = sl;
+          uR[v] = sr;
+        }
+        const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
+        R F[5];
+        rusanov_flux(uL, uR, nL, g, F);
+        R* FQ = sW + lf * SW + a2 * m + b2;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) FQ[v * m * m] = F[v];
+      }
+    }
+    __syncthreads();
+    // quadrilaterals: P x P of the Rusanov flux, added
+    for (int it = tid; it < EB * 3 * 5 * n; it += NT_) {
+      const int le = it / (15 * n), r0 = it - le * (15 * n), ed = r0 / (5 * n), r1 = r0 - ed * (5 * n);
+      const int v = r1 / n, b = r1 - v * n, lf = le * 5 + 2 + ed;
+      if (e0 + le >= E) continue;
+      R pb[m];
+#pragma unroll
+      for (int b2 = 0; b2 < m; ++b2) pb[b2] = sPj[b][b2];
+      const R* FQ = sW + lf * SW + v * m * m;
+      R z[m];
+#pragma unroll
+      for (int a2 = 0; a2 < m; ++a2) {
+        R s = R(0);
+#pragma unroll
+        for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * FQ[a2 * m + b2];
+        z[a2] = s;
+      }
+      const R sc = (sInfo[lf] & 1) ? sFG[lf][3] : -sFG[lf][3];
+      R* D = sD + lf * 5 * NFP + v * NFP + n * b;
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int a2 = 0; a2 < m; ++a2) s += op.Pj[i][a2] * z[a2];
+        D[i] += sc * s;
+      }
+    }
   }
   __syncthreads();
   // tdivtconf + negdivconf, one output point per thread (coalesced state
@@ -958,9 +1294,11 @@ template <> struct PrismLaunch<4, true> { static constexpr int EB = 1, NT = 64; 
 // elements per workgroup of the disu kernel (256 threads)
 constexpr int PRISM_DISU_EB = 8;
 // elements per workgroup of the interface kernel (256 threads)
-template <int P, bool DBL>
+template <int P, bool DBL, bool SAA = false>
 struct PrismSurf {
-  static constexpr int EB = 4;
+  // surface-flux anti-aliasing stages the face quadrature data in LDS: half
+  // the elements per workgroup
+  static constexpr int EB = SAA ? 2 : 4;
 };
 
 template <int P, typename R, bool BT>
@@ -976,22 +1314,33 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
     hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, tri, eref);
   if ((a.stage & 2) && grid[K_VOLUME] > 0) {
-    if (a.aa)
-      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+    // surface-flux anti-aliasing is built together with flux anti-aliasing
+    // only (the paper's "full AA"); the library rejects it without
+    if (a.saa)
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, true>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+    else if (a.aa)
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
                          a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
     else
-      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st,
+                         a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
   }
-  if ((a.stage & 4) && grid[K_SURFACE] > 0)
-    hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
-                       a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
+  if ((a.stage & 4) && grid[K_SURFACE] > 0) {
+    if (a.saa)
+      hipLaunchKernelGGL((prism_surface<P, R, PrismSurf<P, dbl, true>::EB, NTC, BT, true>), dim3(grid[K_SURFACE]),
+                         dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
+    else
+      hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT, false>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
+                         a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
+  }
 }
 
 template <int P, typename R>
 static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {PRISM_DISU_EB, PrismLaunch<P, dbl>::EB, PrismSurf<P, dbl>::EB};
+  const int ebs[3] = {PRISM_DISU_EB, PrismLaunch<P, dbl>::EB,
+                      a.saa ? PrismSurf<P, dbl, true>::EB : PrismSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
   for (int k = 0; k < 3; ++k) grid[k] = bt ? a.nblk[k] : (a.one.E + ebs[k] - 1) / ebs[k];
@@ -1002,16 +1351,21 @@ static hipError_t prism_rhs_t(const TypeArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int P>
+static int prism_surf_elems(bool d, bool saa) {
+  return d ? (saa ? PrismSurf<P, true, true>::EB : PrismSurf<P, true>::EB)
+           : (saa ? PrismSurf<P, false, true>::EB : PrismSurf<P, false>::EB);
+}
+
 int prism_block_elems(int p, int prec, int k, bool saa) {
-  (void)saa;
   if (k == K_DISU) return PRISM_DISU_EB;
   const bool d = prec == 0;
   if (k == K_SURFACE) {
     switch (p) {
-      case 1: return d ? PrismSurf<1, true>::EB : PrismSurf<1, false>::EB;
-      case 2: return d ? PrismSurf<2, true>::EB : PrismSurf<2, false>::EB;
-      case 3: return d ? PrismSurf<3, true>::EB : PrismSurf<3, false>::EB;
-      case 4: return d ? PrismSurf<4, true>::EB : PrismSurf<4, false>::EB;
+      case 1: return prism_surf_elems<1>(d, saa);
+      case 2: return prism_surf_elems<2>(d, saa);
+      case 3: return prism_surf_elems<3>(d, saa);
+      case 4: return prism_surf_elems<4>(d, saa);
     }
     return 0;
   }

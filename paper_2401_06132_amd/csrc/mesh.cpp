@@ -326,4 +326,20 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
   return "";
 }
 
+bool prism_tri_faces_aligned(const Mesh& m) {
+  std::vector<char> checked(m.perms.size(), 0), ok(m.perms.size(), 1);
+  for (int64_t e = 0; e < m.nel[1]; ++e)
+    for (int f = 0; f < 2; ++f) {
+      const int id = m.perm_id[m.slot_base[1] + e * 5 + f];
+      if (!checked[id]) {
+        checked[id] = 1;
+        const std::vector<int>& pm = m.perms[id];
+        for (size_t r = 0; r < pm.size(); ++r)
+          if (pm[r] != (int)r) ok[id] = 0;
+      }
+      if (!ok[id]) return false;
+    }
+  return true;
+}
+
 }  // namespace fr

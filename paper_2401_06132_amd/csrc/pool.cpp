@@ -133,7 +133,7 @@ void to_prec(std::vector<unsigned char>& buf, const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i) d[i] = T(v[i]);
 }
 
-std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[2], int rs) {
+std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[2], int rs, bool saa) {
   auto out = std::make_shared<Prepared>();
   Prepared& R = *out;
   fr::Mesh M;
@@ -146,6 +146,10 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[2
   const int64_t nfp = (int64_t)(q.p + 1) * (q.p + 1);
   if ((int64_t)M.perms.size() > fr::MAX_PERMS) {
     R.err = "too many face permutations";
+    return out;
+  }
+  if (saa && !fr::prism_tri_faces_aligned(M)) {
+    R.err = "surface-flux anti-aliasing needs aligned prism triangle faces";
     return out;
   }
   const int64_t S = M.nslots;
@@ -279,8 +283,6 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind > 2)
     return pfail(P, FR_EINVAL, "bad mesh size");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
-  if (P->ph.surface_aa && q->kind != FR_MESH_HEX)
-    return pfail(P, FR_EUNSUPPORTED, "surface-flux anti-aliasing is built for hexahedra only");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
   if (!q->u_init && !(q->tgv_p0 > 0.0)) return pfail(P, FR_EINVAL, "no initial state and tgv_p0 <= 0");
   const int64_t cells = (int64_t)q->nx * q->ny * q->nz;
@@ -340,7 +342,7 @@ void worker_main(fr_pool* P) {
     const fr::RefElem* refs[2] = {&P->ref[0][q.p], &P->ref[1][q.p]};
     const int rs = P->rs;
     lk.unlock();
-    std::shared_ptr<Prepared> r = prepare(q, refs, rs);
+    std::shared_ptr<Prepared> r = prepare(q, refs, rs, P->ph.surface_aa != 0);
     lk.lock();
     P->ready[id] = std::move(r);
     P->in_flight = -1;
@@ -370,7 +372,7 @@ std::shared_ptr<Prepared> take_prepared(fr_pool* P, int64_t id) {
     const fr::RefElem* refs[2] = {&P->ref[0][q.p], &P->ref[1][q.p]};
     const int rs = P->rs;
     lk.unlock();
-    return prepare(q, refs, rs);
+    return prepare(q, refs, rs, P->ph.surface_aa != 0);
   }
 }
 

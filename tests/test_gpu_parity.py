@@ -207,7 +207,10 @@ def test_anti_aliasing_changes_the_rhs():
 
 
 FULL_AA_CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((2, 3, 3), 4, "hex"),
-                 ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"), ((7, 3, 2), 3, "hex")]
+                 ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"), ((7, 3, 2), 3, "hex"),
+                 ((2, 2, 2), 3, "prism"), ((3, 2, 2), 1, "prism"), ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"),
+                 ((1, 1, 1), 3, "prism"), ((5, 2, 1), 3, "prism"), ((2, 2, 4), 3, "mixed"), ((3, 2, 2), 4, "mixed"),
+                 ((2, 1, 2), 2, "mixed")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -241,30 +244,31 @@ def test_surface_anti_aliasing_changes_the_rhs():
     assert np.abs(a[0] - b[0]).max() > 1e-6 * np.abs(a[0]).max()
 
 
-def test_full_aa_free_stream_conservation_and_rk4():
+@pytest.mark.parametrize("kind", ["hex", "mixed"])
+def test_full_aa_free_stream_conservation_and_rk4(kind):
     """Uniform flow stays uniform; 5 fused RK4 steps match the oracle's state
     change and conserve the integrals (each side of a face projects the
     common flux in its own frame, so conservation holds to rounding)."""
     _need_gpu()
     dims, p = (3, 2, 2), 3
-    s = frmi.Solver(dims, p, "hex", pref=inputs.P0, surface_aa=True)
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0, surface_aa=True)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
     du = torch.empty_like(u)
     s.rhs(u, du)
     assert du.abs().max().item() < 1e-12 * 72 * 10
-    m, U = _case(dims, p, "hex", surf_aa=True)
-    Uo = {"hex": U[0]}
+    m, U = _case(dims, p, kind, surf_aa=True)
+    Uo = {t: u for t, u in zip(m.types, U)}
     for _ in range(5):
         Uo = oracle_rk4(m, Uo, Params(pref=inputs.P0), 1e-3)
-    s.set_state(U[0])
+    s.set_state(np.concatenate([u.reshape(-1) for u in U]))
     c0 = s.integrals()
     s.rk4(1e-3, 5)
-    got = s.split(s.get_state())[0]
-    d_ref = Uo["hex"] - U[0]
-    err = np.abs((got - U[0]) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
-    print("full-aa rk4 rel err of the state change", err)
-    assert np.all(err < 1e-11)
+    for got, t, u in zip(s.split(s.get_state()), m.types, U):
+        d_ref = Uo[t] - u
+        err = np.abs((got - u) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
+        print("full-aa rk4 rel err of the state change", t, err)
+        assert np.all(err < 1e-11)
     c1 = s.integrals()
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())
 

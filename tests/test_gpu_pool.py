@@ -169,3 +169,24 @@ def test_pool_without_anti_aliasing_equals_rk4_step(kind):
     pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
     _drain(pool)
     assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed"])
+def test_pool_full_anti_aliasing_equals_rk4_step(kind):
+    """A pool with flux and surface-flux anti-aliasing (the surface kernels
+    then run half the elements per workgroup) ends bit-identical to
+    fr_rk4_step in the same configuration, also batched with a second
+    request of another order."""
+    _need_gpu()
+    n, p, steps, dt = (3, 2, 4), 3, 4, 2e-4
+    u0 = _init(n, p, kind, seed=5)
+    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, surface_aa=True)
+    s.set_state(u0)
+    s.rk4(dt, steps)
+    ref = s.get_state()
+    pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, surface_aa=True)
+    out = np.empty_like(u0)
+    pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
+    pool.submit(n=(2, 3, 2), p=2, kind="prism", nsteps=3, dt=dt, tgv_p0=inputs.P0)
+    _drain(pool)
+    assert np.array_equal(out, ref)

@@ -13,7 +13,8 @@ v1.11.0), with dense operators and no fusion:
   10 tdivtpcorf    R~   = (M1 - M3 M2) M9 F~^q, applied literally:
                    F~^u = M8 F~^q (per component), then
                    R~ = sum_d D_d F~^u_d - M3 (sum_d nhat_d M0 F~^u_d)
-  11 comm_flux     D~ = mag F(uL, uR, qL, qR, nL) on L, -mag F on R
+  11 comm_flux     D~ = mag_L F(uL, uR, qL, qR, nL) on L, -mag_R F on R
+                   (mag: each side's own area factor |det J J^-T nhat|)
   12 tdivtconf     R~  += M3 D~
   13 negdivconf    R   = -R~ / det J
 Affine elements: J, det J and J^-1 are constant per element.
@@ -118,10 +119,11 @@ def rhs(mesh, U, par, dtype=None):
     nL = cast(mesh.fnrm[mesh.iL])
     F = physics.common_normal_flux(uL.T, uR.T, qfa[mesh.iL].transpose(1, 2, 0),
                                    qfa[mesh.iR].transpose(1, 2, 0), nL.T, gas, beta, tau).T  # 11
-    mag = cast(mesh.fmag[mesh.iL])[:, None]
+    # the common normal flux is physical, equal and opposite on the two sides
+    # (eq. FR-comm_flux); each side transforms it with its own area factor
     da = np.empty_like(ufa)
-    da[mesh.iL] = mag * F
-    da[mesh.iR] = -(mag * F)
+    da[mesh.iL] = cast(mesh.fmag[mesh.iL])[:, None] * F
+    da[mesh.iR] = -(cast(mesh.fmag[mesh.iR])[:, None] * F)
     out = {}
     for t in mesh.types:
         r = mesh.refs[t]
@@ -251,7 +253,7 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         qL, qR = np.where(lf[:, None, None], qo, qn), np.where(lf[:, None, None], qn, qo)
         F = physics.common_normal_flux(uL.T, uR.T, qL.transpose(1, 2, 0), qR.transpose(1, 2, 0), nL.T, gas, beta,
                                        tau).T  # 11
-        mag = cast(mesh.fmag[iL])[:, None]
+        mag = cast(mesh.fmag[fp])[:, None]  # own area factor (eq. FR-comm_flux)
         D = np.where(lf[:, None], mag * F, -(mag * F)).reshape(len(e0), r.nf, 5)
         rt = rt + np.einsum("uf,efv->euv", cast(r.M3), D)  # 12
         du = -rt / cast(mesh.detJ[t][e0])[:, None, None]  # 13

@@ -6,6 +6,7 @@ The oracle uses Legendre products, which are well conditioned and have no
 singularity on the triangle:
   hex    Q_p : P_a(xi) P_b(eta) P_c(zeta), a, b, c <= p
   prism      : P_a(xi) P_b(eta) P_c(zeta), a + b <= p, c <= p
+  tet    P_p : P_a(xi) P_b(eta) P_c(zeta), a + b + c <= p
 The paper's L2 projection (eq. FR-tdivtpcorfq) is evaluated with the
 basis-independent mass-matrix form in elements.py.
 """
@@ -61,6 +62,8 @@ def modes(etype, p):
         return [(a, b, c) for c in range(p + 1) for b in range(p + 1) for a in range(p + 1)]
     if etype == "prism":
         return [(a, b, c) for c in range(p + 1) for b in range(p + 1) for a in range(p + 1 - b)]
+    if etype == "tet":
+        return [(a, b, c) for c in range(p + 1) for b in range(p + 1 - c) for a in range(p + 1 - b - c)]
     raise ValueError(etype)
 
 

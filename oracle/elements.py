@@ -12,10 +12,18 @@ Reference elements
         2,3,4 = the quadrilaterals eta = -1, xi + eta = 0, xi = -1 with GL(n)
         points along the edge (parameter s, edges run counter-clockwise) times
         GL(n) in zeta, index a + n b.
+  tet   {xi, eta, zeta >= -1, xi + eta + zeta <= -1}, vertices V0..V3 =
+        (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1).  Solution points: the
+        tetrahedron node set of quadrature.tetrahedron_nodes (a reading).
+        Faces 0..3 = zeta = -1, eta = -1, xi = -1 and the slanted face
+        opposite V0; each a triangle carrying the triangle nodes (mapped from
+        the reference triangle with vertices (-1,-1), (1,-1), (-1,1) to the
+        face's vertices in the order listed in _build_tet).
 All operators are computed in extended precision (numpy longdouble) and kept
 there; callers cast them to their working precision (rounding once).
 Anti-aliasing quadrature (section 2.1.1): hex GL(m)^3; prism conical triangle
-rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default.
+rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default;
+tet conical-product rule with (p+1)^3 points (degree 2p+1).
 
 Surface-flux anti-aliasing (surf_aa=True, section 2.1.1 and table
 "operatorms"): the flux points are replaced by quadrature points on the
@@ -60,6 +68,8 @@ class RefElement:
             self._build_hex(gl)
         elif etype == "prism":
             self._build_prism(gl, tri_nodes)
+        elif etype == "tet":
+            self._build_tet(tri_nodes)
         else:
             raise ValueError(etype)
         self.nu, self.nf, self.nq = len(self.upts), len(self.fpts), len(self.qpts)
@@ -149,6 +159,45 @@ class RefElement:
         lq, lw = quadrature.gauss_legendre(m)
         self.qpts = np.array([(tq[t, 0], tq[t, 1], lq[k]) for k in range(m) for t in range(len(tq))])
         self.qwts = np.array([tw[t] * lw[k] for k in range(m) for t in range(len(tq))])
+
+    # ------------------------------------------------------------------ tet
+    def _build_tet(self, tri_nodes):
+        p = self.p
+        tn = quadrature.triangle_nodes(p) if tri_nodes is None else np.asarray(tri_nodes, float)
+        self.tri_nodes = tn
+        self.nt = len(tn)
+        self.upts = quadrature.tetrahedron_nodes(p)
+        V = quadrature.TET_VERTS
+        self.nfaces = 4
+        # (vertices the reference triangle's (-1,-1), (1,-1), (-1,1) map to, normal)
+        spec = [((0, 1, 2), (0.0, 0.0, -1.0)), ((0, 1, 3), (0.0, -1.0, 0.0)), ((0, 2, 3), (-1.0, 0.0, 0.0)),
+                ((1, 2, 3), tuple(np.ones(3) / np.sqrt(3.0)))]
+        faces = []
+        for (a, b, c), nrm in spec:
+            A, B, C = V[a], V[b], V[c]
+
+            def tmap(s, t, A=A, B=B, C=C):
+                s, t = np.asarray(s, float), np.asarray(t, float)
+                la, lb, lc = -(s + t) / 2.0, (1.0 + s) / 2.0, (1.0 + t) / 2.0
+                return la[:, None] * A + lb[:, None] * B + lc[:, None] * C
+            jac = np.linalg.norm(np.cross(B - A, C - A)) / 2.0 / 2.0  # face area / reference triangle area
+            faces.append(dict(kind="tri", map=tmap, normal=np.array(nrm), jac=jac))
+        self.faces = faces
+        tq, tw = quadrature.triangle_conical(p + 1)
+        fp, fid, fw = [], [], []
+        for f, fc in enumerate(faces):
+            if self.surf_aa:
+                fp.append(fc["map"](tq[:, 0], tq[:, 1]))
+                fw.append(tw * fc["jac"])
+            else:
+                fp.append(fc["map"](tn[:, 0], tn[:, 1]))
+            fid += [f] * len(fp[-1])
+        self.fpts = np.concatenate(fp)
+        self.fface = np.array(fid)
+        self.fnorm = np.array([faces[f]["normal"] for f in self.fface])
+        if self.surf_aa:
+            self.fwts = np.concatenate(fw)
+        self.qpts, self.qwts = quadrature.tetrahedron_conical(p + 1)
 
     def _quad_face_points(self, g1, w1=None):
         """Tensor points g1 x g1 on every (quadrilateral) face; with weights

@@ -12,6 +12,17 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                    A: x = x0 + (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + (xi+1) h/2
                    B: x = x0 + h - (eta+1) h/2, y = y0 + (zeta+1) h/2, z = z0 + h - (xi+1) h/2
   kind "mixed" : hexahedra in cells whose centre has z < 0, prisms elsewhere.
+  kind "tet"   : six tetrahedra per cell (Kuhn subdivision of the cube
+                 mirrored in x: in unit coordinates u = ((x0+h-x)/h, (y-y0)/h,
+                 (z-z0)/h) the tetrahedra are u_a >= u_b >= u_c for the six
+                 orders (a, b, c) of the axes, vertices 0, e_a, e_a + e_b,
+                 (1,1,1) in that order mapped to V0..V3 (V1 and V2 swapped
+                 where that gives a negative Jacobian)).  Every cell face is
+                 cut along the same diagonal as its opposite face, so the
+                 tetrahedra are conforming across cells and the period; the
+                 y faces are cut along the prisms' diagonal.
+  kind "prism_tet" : prisms in cells whose centre has y < 0, tetrahedra
+                 elsewhere (prism triangles meet tetrahedron faces).
 surf_aa=True builds the reference elements with surface-flux
 anti-aliasing (flux points at the face quadrature points).
 Element numbering: cells in index order; a prism cell yields A then B.  The
@@ -31,6 +42,24 @@ import numpy as np
 from .elements import RefElement
 
 
+def _kuhn_tets(x0, h):
+    """Vertices (4, 3) of the six tetrahedra of the cell at x0 (see the
+    module header), each with a positive orientation."""
+    from itertools import permutations
+    out = []
+    for order in permutations(range(3)):
+        u = [np.zeros(3)]
+        for ax in order:
+            nxt = u[-1].copy()
+            nxt[ax] = 1.0
+            u.append(nxt)
+        P = [x0 + h * np.array([1.0 - q[0], q[1], q[2]]) for q in u]
+        if np.linalg.det(np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1)) < 0:
+            P[1], P[2] = P[2], P[1]
+        out.append(P)
+    return out
+
+
 class Mesh:
     def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None, surf_aa=False):
         self.nx, self.ny, self.nz, self.p, self.kind = nx, ny, nz, p, kind
@@ -39,7 +68,8 @@ class Mesh:
         self.period = np.array([L, L, L])
         h = np.array([L / nx, L / ny, L / nz])
         self.h = h
-        types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"]}[kind]
+        types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
+                 "prism_tet": ["prism", "tet"]}[kind]
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -52,8 +82,21 @@ class Mesh:
                 for i in range(nx):
                     x0 = lo + np.array([i, j, k]) * h
                     zc = x0[2] + 0.5 * h[2]
-                    ctype = kind if kind != "mixed" else ("hex" if zc < 0.0 else "prism")
-                    if ctype == "hex":
+                    yc = x0[1] + 0.5 * h[1]
+                    if kind == "mixed":
+                        ctype = "hex" if zc < 0.0 else "prism"
+                    elif kind == "prism_tet":
+                        ctype = "prism" if yc < 0.0 else "tet"
+                    else:
+                        ctype = kind
+                    if ctype == "tet":
+                        for P in _kuhn_tets(x0, h):
+                            Jt = np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1) / 2.0
+                            org["tet"].append(P[0] + Jt @ np.ones(3))
+                            A["tet"].append(Jt)
+                            gid["tet"].append(g)
+                            g += 1
+                    elif ctype == "hex":
                         org["hex"].append(x0 + 0.5 * h)
                         A["hex"].append(np.diag(0.5 * h))
                         gid["hex"].append(g)

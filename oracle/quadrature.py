@@ -73,3 +73,52 @@ def triangle_nodes(p):
             y = (1.0 + 2.0 * v[j] - v[i] - v[k]) / 3.0
             pts.append((2.0 * x - 1.0, 2.0 * y - 1.0))
     return np.array(pts)
+
+
+def tetrahedron_conical(k):
+    """Conical-product (collapsed-coordinate) rule on the reference
+    tetrahedron {xi, eta, zeta >= -1, xi + eta + zeta <= -1} with k^3 points,
+    exact for total degree 2k-1: Gauss-Legendre in a, Gauss-Jacobi(1,0) in b,
+    Gauss-Jacobi(2,0) in c, with
+        zeta = c,  eta = (1+b)(1-c)/2 - 1,  xi = (1+a)(1-b)(1-c)/4 - 1,
+        dxi deta dzeta = (1-b)(1-c)^2/8 da db dc.
+    Ordering: c outer, b, a inner."""
+    a, wa = gauss_legendre(k)
+    b, wb = gauss_jacobi(k, 1.0, 0.0)
+    c, wc = gauss_jacobi(k, 2.0, 0.0)
+    pts = np.empty((k ** 3, 3))
+    wts = np.empty(k ** 3)
+    for l in range(k):
+        for j in range(k):
+            for i in range(k):
+                q = (l * k + j) * k + i
+                pts[q] = (0.25 * (1 + a[i]) * (1 - b[j]) * (1 - c[l]) - 1.0, 0.5 * (1 + b[j]) * (1 - c[l]) - 1.0, c[l])
+                wts[q] = wa[i] * wb[j] * wc[l] / 8.0
+    return pts, wts
+
+
+# vertices of the reference tetrahedron
+TET_VERTS = np.array([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
+
+
+def tetrahedron_nodes(p):
+    """(p+1)(p+2)(p+3)/6 nodes in the reference tetrahedron (the paper prints
+    none; a reading): the three-dimensional form of the Blyth-Pozrikidis
+    construction on the Gauss-Legendre master grid v_m = (1 + t_m)/2,
+    t_m = GL(p+1) nodes.  For i + j + k + l = p the barycentric coordinates
+        lambda_1 = (1 + 3 v_i - v_j - v_k - v_l)/4   (vertex 1, and likewise
+        lambda_2 from j, lambda_3 from k, lambda_0 from l)
+    sum to one; the node is sum_a lambda_a V_a.  Ordering: k outer, j, i inner."""
+    if p == 0:
+        return TET_VERTS.mean(axis=0)[None, :]
+    v = 0.5 * (1.0 + gauss_legendre(p + 1)[0])
+    pts = []
+    for k in range(p + 1):
+        for j in range(p + 1 - k):
+            for i in range(p + 1 - k - j):
+                l = p - i - j - k
+                idx = (l, i, j, k)
+                s = sum(v[t] for t in idx)
+                lam = [(1.0 + 4.0 * v[t] - s) / 4.0 for t in idx]
+                pts.append(sum(lam[a] * TET_VERTS[a] for a in range(4)))
+    return np.array(pts)

@@ -114,6 +114,8 @@ def _random_poly(etype, p, rng):
     """A random polynomial of the element's solution space, as monomials."""
     if etype == "hex":
         terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1) for c in range(p + 1)]
+    elif etype == "tet":
+        terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1 - a - b)]
     else:
         terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1)]
     coef = rng.standard_normal(len(terms))
@@ -135,7 +137,7 @@ def _random_poly(etype, p, rng):
     return f, grad
 
 
-CASES = [("hex", p) for p in (1, 2, 3, 4)] + [("prism", p) for p in (1, 2, 3, 4)]
+CASES = [("hex", p) for p in (1, 2, 3, 4)] + [("prism", p) for p in (1, 2, 3, 4)] + [("tet", p) for p in (1, 2, 3, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -165,7 +167,7 @@ def test_projection_is_left_inverse_of_interpolation(refs, case):
 @pytest.mark.parametrize("case", CASES)
 def test_quadrature_weights_and_volume(refs, case):
     r = refs[case]
-    vol = 8.0 if r.etype == "hex" else 4.0
+    vol = {"hex": 8.0, "prism": 4.0, "tet": 4.0 / 3.0}[r.etype]
     assert abs(r.qwts.sum() - vol) < 1e-13
     assert abs(r.wu.sum() - vol) < 1e-13
 

@@ -56,7 +56,7 @@ typedef enum {
   FR_EUNSUPPORTED = -5   /* combination not built (e.g. order outside 1..4) */
 } fr_status;
 
-typedef enum { FR_HEX = 0, FR_PRISM = 1 } fr_etype;
+typedef enum { FR_HEX = 0, FR_PRISM = 1, FR_TET = 2 } fr_etype;
 typedef enum { FR_MESH_HEX = 0, FR_MESH_PRISM = 1, FR_MESH_MIXED = 2 } fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;

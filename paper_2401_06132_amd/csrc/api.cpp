@@ -501,7 +501,7 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
 }
 
 fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count) {
-  if (!name || (etype != 0 && etype != 1)) return FR_EINVAL;
+  if (!name || etype < 0 || etype > 2) return FR_EINVAL;
   if (p < 1 || p > 4) return FR_EUNSUPPORTED;
   fr::RefElem r;
   try {

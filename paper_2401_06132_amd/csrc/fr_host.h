@@ -46,7 +46,8 @@ struct Tri {
   double edgeNormal[3][2] = {{0, -1}, {0, 0}, {-1, 0}};
 };
 
-// Geometry of a reference element (hex or prism) and its dense operators.
+// Geometry of a reference element (hex, prism or tet) and its dense operators.
+// etype: 0 hex, 1 prism, 2 tet.
 struct RefElem {
   int etype = 0, p = 0, n = 0, m = 0;
   int nu = 0, nf = 0, nq = 0, nfaces = 0, nfp_max = 0;
@@ -55,9 +56,13 @@ struct RefElem {
   std::vector<double> upts, fpts, qpts, qwts;  // N x 3 / N
   std::vector<int> face_start, face_npts;      // per face
   std::vector<double> face_normal;             // nfaces x 3, unit reference normals
+  std::vector<double> face_jac;                // tets: face area / reference triangle area
   std::vector<double> wu;                      // integrals of the nodal basis
   // dense operators of section 2.2 (row-major), built from the factors
   std::vector<double> M0, M3, M7, M8, Dg;  // Dg: 3 x nu x nu
+  // tetrahedra (no factorisation): projection-divergence per reference
+  // direction, AP_d = -Mass^-1 Dq_d^T W_q (3 x nu x nq), and the mass matrix
+  std::vector<double> APd, mass;
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);

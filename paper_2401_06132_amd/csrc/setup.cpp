@@ -315,6 +315,259 @@ static void build_tri(int p, const Line1D& L, Tri& T) {
       }
 }
 
+// Tetrahedron {xi, eta, zeta >= -1, xi + eta + zeta <= -1} with vertices
+// V0..V3 = (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1).
+static const double kTetV[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+// faces: the vertices the reference triangle's (-1,-1), (1,-1), (-1,1) map to
+static const int kTetFace[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+
+// solution points: barycentric Blyth-Pozrikidis-type construction on the GL
+// master grid v = (1 + GL(p+1))/2: for i + j + k + l = p,
+// lambda_a = (1 + 4 v_a - (v_i + v_j + v_k + v_l))/4 (l for V0, i, j, k for V1..V3)
+static void tet_nodes(int p, std::vector<double>& x) {
+  x.clear();
+  if (p == 0) {
+    x = {-0.5, -0.5, -0.5};
+    return;
+  }
+  std::vector<double> g, gw;
+  gauss_legendre(p + 1, g, gw);
+  std::vector<double> v(p + 1);
+  for (int i = 0; i <= p; ++i) v[i] = 0.5 * (1.0 + g[i]);
+  for (int k = 0; k <= p; ++k)
+    for (int j = 0; j + k <= p; ++j)
+      for (int i = 0; i + j + k <= p; ++i) {
+        const int idx[4] = {p - i - j - k, i, j, k};
+        const double sum = v[idx[0]] + v[idx[1]] + v[idx[2]] + v[idx[3]];
+        double c[3] = {0, 0, 0};
+        for (int a = 0; a < 4; ++a) {
+          const double lam = (1.0 + 4.0 * v[idx[a]] - sum) / 4.0;
+          for (int d = 0; d < 3; ++d) c[d] += lam * kTetV[a][d];
+        }
+        x.insert(x.end(), c, c + 3);
+      }
+}
+
+// The tetrahedron has no tensor structure, so its operators come from a
+// Vandermonde inverse of the full P_p basis; that and the mass-matrix inverse
+// run in long double (the Vandermonde's condition number reaches ~5e3 at
+// p = 4) and the results are rounded once.
+typedef long double xreal;
+
+static std::vector<xreal> inverse_x(std::vector<xreal> A, int n) {
+  std::vector<xreal> B(n * n, 0.0L);
+  for (int i = 0; i < n; ++i) B[i * n + i] = 1.0L;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0L) throw std::runtime_error("singular matrix");
+    for (int k = 0; k < n; ++k) {
+      std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(B[c * n + k], B[piv * n + k]);
+    }
+    const xreal d = 1.0L / A[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[c * n + k] *= d;
+      B[c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const xreal f = A[r * n + c];
+      if (f == 0.0L) continue;
+      for (int k = 0; k < n; ++k) {
+        A[r * n + k] -= f * A[c * n + k];
+        B[r * n + k] -= f * B[c * n + k];
+      }
+    }
+  }
+  return B;
+}
+
+// Legendre P_0..P_p and derivatives at x (three-term recurrence)
+static void legendre_x(int p, xreal x, xreal* P, xreal* dP) {
+  P[0] = 1.0L;
+  dP[0] = 0.0L;
+  if (p >= 1) {
+    P[1] = x;
+    dP[1] = 1.0L;
+  }
+  for (int k = 1; k < p; ++k) {
+    P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+    dP[k + 1] = dP[k - 1] + (2 * k + 1) * P[k];
+  }
+}
+
+// basis of P_p on the tetrahedron: Legendre products P_a(xi) P_b(eta) P_c(zeta),
+// a + b + c <= p, with gradients
+static void tet_basis(int p, const xreal* y, xreal* v, xreal* g0, xreal* g1, xreal* g2) {
+  xreal P[3][8], dP[3][8];
+  for (int d = 0; d < 3; ++d) legendre_x(p, y[d], P[d], dP[d]);
+  int k = 0;
+  for (int c = 0; c <= p; ++c)
+    for (int b = 0; b + c <= p; ++b)
+      for (int a = 0; a + b + c <= p; ++a) {
+        v[k] = P[0][a] * P[1][b] * P[2][c];
+        g0[k] = dP[0][a] * P[1][b] * P[2][c];
+        g1[k] = P[0][a] * dP[1][b] * P[2][c];
+        g2[k] = P[0][a] * P[1][b] * dP[2][c];
+        ++k;
+      }
+}
+
+static void build_tet(int p, RefElem& r) {
+  build_tri(p, r.line, r.tri);
+  const Tri& T = r.tri;
+  const int nt = T.nt, nu = (p + 1) * (p + 2) * (p + 3) / 6;
+  r.nu = nu;
+  r.nfaces = 4;
+  r.nfp_max = nt;
+  tet_nodes(p, r.upts);
+  for (int f = 0; f < 4; ++f) {
+    const double* A = kTetV[kTetFace[f][0]];
+    const double* B = kTetV[kTetFace[f][1]];
+    const double* C = kTetV[kTetFace[f][2]];
+    r.face_start.push_back((int)r.fpts.size() / 3);
+    r.face_npts.push_back(nt);
+    // outward unit normal: (B - A) x (C - A), oriented away from the opposite vertex
+    double e1[3], e2[3], nr[3];
+    for (int d = 0; d < 3; ++d) {
+      e1[d] = B[d] - A[d];
+      e2[d] = C[d] - A[d];
+    }
+    nr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    nr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    nr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double len = std::sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    const int opp = 6 - kTetFace[f][0] - kTetFace[f][1] - kTetFace[f][2];
+    double side = 0;
+    for (int d = 0; d < 3; ++d) side += nr[d] * (kTetV[opp][d] - A[d]);
+    const double sgn = side > 0 ? -1.0 : 1.0;
+    for (int d = 0; d < 3; ++d) r.face_normal.push_back(sgn * nr[d] / len);
+    r.face_jac.push_back(0.25 * len);  // face area / reference triangle area (2)
+    for (int t = 0; t < nt; ++t) {
+      const double s = T.nodes[2 * t], u = T.nodes[2 * t + 1];
+      const double la = -(s + u) / 2.0, lb = (1.0 + s) / 2.0, lc = (1.0 + u) / 2.0;
+      for (int d = 0; d < 3; ++d) r.fpts.push_back(la * A[d] + lb * B[d] + lc * C[d]);
+    }
+  }
+  // conical-product rule with (p+1)^3 points (degree 2p+1)
+  {
+    const int k = p + 1;
+    std::vector<double> a, wa, b, wb, c, wc;
+    gauss_legendre(k, a, wa);
+    gauss_jacobi(k, 1.0, 0.0, b, wb);
+    gauss_jacobi(k, 2.0, 0.0, c, wc);
+    for (int l = 0; l < k; ++l)
+      for (int j = 0; j < k; ++j)
+        for (int i = 0; i < k; ++i) {
+          r.qpts.push_back(0.25 * (1 + a[i]) * (1 - b[j]) * (1 - c[l]) - 1.0);
+          r.qpts.push_back(0.5 * (1 + b[j]) * (1 - c[l]) - 1.0);
+          r.qpts.push_back(c[l]);
+          r.qwts.push_back(wa[i] * wb[j] * wc[l] / 8.0);
+        }
+  }
+  r.nf = (int)r.fpts.size() / 3;
+  r.nq = (int)r.qwts.size();
+  const int nf = r.nf, nq = r.nq;
+  // nodal basis l_u(y) = sum_k psi_k(y) Vi[k][u]
+  std::vector<xreal> V(nu * nu), v(nu), g0(nu), g1(nu), g2(nu);
+  for (int u = 0; u < nu; ++u) {
+    const xreal y[3] = {r.upts[3 * u], r.upts[3 * u + 1], r.upts[3 * u + 2]};
+    tet_basis(p, y, v.data(), g0.data(), g1.data(), g2.data());
+    for (int k = 0; k < nu; ++k) V[u * nu + k] = v[k];
+  }
+  const std::vector<xreal> Vi = inverse_x(V, nu);
+  auto nodal = [&](const double* yd, xreal* l, xreal* d0, xreal* d1, xreal* d2) {
+    const xreal y[3] = {yd[0], yd[1], yd[2]};
+    tet_basis(p, y, v.data(), g0.data(), g1.data(), g2.data());
+    for (int u = 0; u < nu; ++u) {
+      xreal s = 0, s0 = 0, s1 = 0, s2 = 0;
+      for (int k = 0; k < nu; ++k) {
+        const xreal w = Vi[k * nu + u];
+        s += v[k] * w;
+        s0 += g0[k] * w;
+        s1 += g1[k] * w;
+        s2 += g2[k] * w;
+      }
+      if (l) l[u] = s;
+      if (d0) {
+        d0[u] = s0;
+        d1[u] = s1;
+        d2[u] = s2;
+      }
+    }
+  };
+  auto rounded = [](const std::vector<xreal>& a) { return std::vector<double>(a.begin(), a.end()); };
+  std::vector<xreal> M0(nf * nu), Dg(3 * nu * nu), M7(nq * nu), Dq(3 * nq * nu);
+  for (int f = 0; f < nf; ++f) nodal(&r.fpts[3 * f], &M0[f * nu], nullptr, nullptr, nullptr);
+  for (int s = 0; s < nu; ++s)
+    nodal(&r.upts[3 * s], nullptr, &Dg[(0 * nu + s) * nu], &Dg[(1 * nu + s) * nu], &Dg[(2 * nu + s) * nu]);
+  for (int q = 0; q < nq; ++q)
+    nodal(&r.qpts[3 * q], &M7[q * nu], &Dq[(0 * nq + q) * nu], &Dq[(1 * nq + q) * nu], &Dq[(2 * nq + q) * nu]);
+  r.M0 = rounded(M0);
+  r.Dg = rounded(Dg);
+  r.M7 = rounded(M7);
+  std::vector<xreal> mass(nu * nu);
+  for (int a = 0; a < nu; ++a)
+    for (int b = 0; b < nu; ++b) {
+      xreal s = 0;
+      for (int q = 0; q < nq; ++q) s += M7[q * nu + a] * (xreal)r.qwts[q] * M7[q * nu + b];
+      mass[a * nu + b] = s;
+    }
+  r.mass = rounded(mass);
+  const std::vector<xreal> Mi = inverse_x(mass, nu);
+  r.M8.assign(nu * nq, 0);
+  r.APd.assign(3 * nu * nq, 0);
+  std::vector<xreal> wu(nu, 0.0L);
+  for (int u = 0; u < nu; ++u) {
+    for (int q = 0; q < nq; ++q) {
+      xreal s = 0, s0 = 0, s1 = 0, s2 = 0;
+      for (int k = 0; k < nu; ++k) {
+        const xreal w = Mi[u * nu + k];
+        s += w * M7[q * nu + k];
+        s0 += w * Dq[(0 * nq + q) * nu + k];
+        s1 += w * Dq[(1 * nq + q) * nu + k];
+        s2 += w * Dq[(2 * nq + q) * nu + k];
+      }
+      const xreal wq = r.qwts[q];
+      r.M8[u * nq + q] = (double)(s * wq);
+      r.APd[(0 * nu + u) * nq + q] = (double)(-s0 * wq);
+      r.APd[(1 * nu + u) * nq + q] = (double)(-s1 * wq);
+      r.APd[(2 * nu + u) * nq + q] = (double)(-s2 * wq);
+      wu[u] += M7[q * nu + u] * wq;
+    }
+  }
+  r.wu = rounded(wu);
+  // DG lifting: E[u, f] = int_face l_u l^face_f dS_ref, with the triangle
+  // rule mapped onto each face; M3 = Mass^-1 E
+  std::vector<xreal> Ef(nu * nf, 0.0L), lf(nu);
+  for (int f = 0; f < 4; ++f) {
+    const double* A = kTetV[kTetFace[f][0]];
+    const double* B = kTetV[kTetFace[f][1]];
+    const double* C = kTetV[kTetFace[f][2]];
+    for (int q = 0; q < T.ntq; ++q) {
+      const double s = T.qp[2 * q], u = T.qp[2 * q + 1];
+      const double la = -(s + u) / 2.0, lb = (1.0 + s) / 2.0, lc = (1.0 + u) / 2.0;
+      double y[3];
+      for (int d = 0; d < 3; ++d) y[d] = la * A[d] + lb * B[d] + lc * C[d];
+      nodal(y, lf.data(), nullptr, nullptr, nullptr);
+      const xreal w = (xreal)T.qw[q] * (xreal)r.face_jac[f];
+      for (int t = 0; t < nt; ++t) {
+        const xreal wt = w * (xreal)T.Tq[q * nt + t];
+        for (int uu = 0; uu < nu; ++uu) Ef[uu * nf + r.face_start[f] + t] += lf[uu] * wt;
+      }
+    }
+  }
+  r.M3.assign(nu * nf, 0);
+  for (int u = 0; u < nu; ++u)
+    for (int f = 0; f < nf; ++f) {
+      xreal s = 0;
+      for (int k = 0; k < nu; ++k) s += Mi[u * nu + k] * Ef[k * nf + f];
+      r.M3[u * nf + f] = (double)s;
+    }
+}
+
 void build_ref(int etype, int p, RefElem& r) {
   int n = p + 1, m = p + 3;
   r.etype = etype;
@@ -335,6 +588,11 @@ void build_ref(int etype, int p, RefElem& r) {
   r.face_start.clear();
   r.face_npts.clear();
   r.face_normal.clear();
+  r.face_jac.clear();
+  if (etype == 2) {
+    build_tet(p, r);
+    return;
+  }
   if (etype == 0) {
     r.nu = n * n * n;
     r.nfaces = 6;

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(frmi.SYMBOLS)
 
 
-@pytest.mark.parametrize("etype,name", [(0, "hex"), (1, "prism")])
+@pytest.mark.parametrize("etype,name", [(0, "hex"), (1, "prism"), (2, "tet")])
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_reference_operators_match_oracle(etype, name, p):
     _lib_or_skip()

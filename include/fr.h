@@ -57,7 +57,13 @@ typedef enum {
 } fr_status;
 
 typedef enum { FR_HEX = 0, FR_PRISM = 1, FR_TET = 2 } fr_etype;
-typedef enum { FR_MESH_HEX = 0, FR_MESH_PRISM = 1, FR_MESH_MIXED = 2 } fr_mesh_kind;
+typedef enum {
+  FR_MESH_HEX = 0,
+  FR_MESH_PRISM = 1,
+  FR_MESH_MIXED = 2,      /* hexahedra where z < 0, prisms elsewhere */
+  FR_MESH_TET = 3,        /* six tetrahedra per cell */
+  FR_MESH_PRISM_TET = 4   /* prisms where y < 0, tetrahedra elsewhere */
+} fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
 
@@ -118,16 +124,29 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * kind: FR_MESH_HEX (one hexahedron per cell), FR_MESH_PRISM (each cell split
  * along the diagonal of its x-z face into two prisms extruded along y),
  * FR_MESH_MIXED (hexahedra where the cell centre has z < 0, prisms
- * elsewhere; the interfaces are conforming quadrilaterals).  Host-side only:
- * device buffers are allocated and uploaded by the first call that needs
- * them.  Element numbering: cells in index order i + nx(j + ny k); a prism
- * cell yields two elements.  Errors: FR_EINVAL (n < 1, hi <= lo),
- * FR_EUNSUPPORTED (p outside 1..4), FR_ESTATE (mesh already built). */
+ * elsewhere; the interfaces are conforming quadrilaterals), FR_MESH_TET (six
+ * tetrahedra per cell: the cube's Kuhn subdivision mirrored in x, so every
+ * cell face is cut along the same diagonal as the prisms' y faces) and
+ * FR_MESH_PRISM_TET (prisms where the cell centre has y < 0, tetrahedra
+ * elsewhere; prism triangles meet tetrahedron faces).  Tetrahedra have no
+ * tensor-product structure (the paper's factorisation does not apply) and
+ * run on dense-operator kernels; they are built for the fused form with flux
+ * anti-aliasing (otherwise FR_EUNSUPPORTED).  Host-side only: device buffers
+ * are allocated and uploaded by the first call that needs them.  Element
+ * numbering: cells in index order i + nx(j + ny k); a prism cell yields two
+ * elements, a tetrahedron cell six.  Errors: FR_EINVAL (n < 1, hi <= lo,
+ * unknown kind), FR_EUNSUPPORTED (p outside 1..4), FR_ESTATE (mesh already
+ * built). */
 fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind);
 
 /* Sizes of the library layout: number of hexahedra, of prisms, and the total
  * number of doubles of a state vector.  Any pointer may be NULL. */
 fr_status fr_layout(const fr_ctx* c, int64_t* n_hex, int64_t* n_prism, int64_t* n_state);
+
+/* Number of elements of type etype (fr_etype: hex, prism, tet) in the mesh.
+ * Library order of the state: all hexahedra, then prisms, then tetrahedra.
+ * Errors: FR_EINVAL (null, bad etype), FR_ESTATE (no mesh). */
+fr_status fr_type_count(const fr_ctx* c, int etype, int64_t* n_elem);
 
 /* Physical coordinates of every solution point in library order:
  * xyz_host receives n_state/5*3 doubles, (point, xyz) row-major. Host only. */

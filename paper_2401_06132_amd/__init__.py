@@ -18,14 +18,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfrmi.so")
 
 FR_HEX, FR_PRISM = 0, 1
-MESH_KIND = {"hex": 0, "prism": 1, "mixed": 2}
+MESH_KIND = {"hex": 0, "prism": 1, "mixed": 2, "tet": 3, "prism_tet": 4}
 PREC = {"fp64": 0, "fp32": 1}
 FORM = {"fused": 0, "plain": 1}
 _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE", -5: "FR_EUNSUPPORTED"}
 
 # every symbol the header declares
-SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_upts_coords", "fr_rhs", "fr_rhs_stages",
-           "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
+SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
+           "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
            "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
            "fr_pool_events", "fr_pool_query", "fr_pool_last_error", "fr_pool_destroy"]
 
@@ -72,6 +72,7 @@ def load_library(path=None):
         "fr_create": (I, [ctypes.POINTER(FrPhysics), P, ctypes.POINTER(P)]),
         "fr_mesh_box": (I, [P, I, I, I, D, D, I, I]),
         "fr_layout": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+        "fr_type_count": (I, [P, I, ctypes.POINTER(I64)]),
         "fr_upts_coords": (I, [P, P]),
         "fr_rhs": (I, [P, P, P]),
         "fr_rhs_stages": (I, [P, P, P, I]),
@@ -141,8 +142,11 @@ class Solver:
         nh, npr, ns = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self.ctx, self.lib.fr_layout(self.ctx, ctypes.byref(nh), ctypes.byref(npr), ctypes.byref(ns)))
         self.n_hex, self.n_prism, self.n_state = nh.value, npr.value, ns.value
+        nt = ctypes.c_int64()
+        _check(self.ctx, self.lib.fr_type_count(self.ctx, 2, ctypes.byref(nt)))
+        self.n_tet = nt.value
         n1 = p + 1
-        self.nu = {"hex": n1 ** 3, "prism": (n1 * (n1 + 1) // 2) * n1}
+        self.nu = {"hex": n1 ** 3, "prism": (n1 * (n1 + 1) // 2) * n1, "tet": n1 * (n1 + 1) * (n1 + 2) // 6}
 
     def __del__(self):
         if getattr(self, "ctx", None):
@@ -160,6 +164,8 @@ class Solver:
             out.append(("hex", self.n_hex, self.nu["hex"]))
         if self.n_prism:
             out.append(("prism", self.n_prism, self.nu["prism"]))
+        if self.n_tet:
+            out.append(("tet", self.n_tet, self.nu["tet"]))
         return out
 
     def upts_coords(self):

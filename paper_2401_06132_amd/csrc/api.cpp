@@ -20,12 +20,12 @@ struct fr_ctx {
   std::string err;
   bool mesh_ok = false, dev_ok = false;
   int p = 0;
-  fr::RefElem ref[2];
-  bool has[2] = {false, false};
+  fr::RefElem ref[fr::NTYPES];
+  bool has[fr::NTYPES] = {false, false, false};
   fr::Mesh M;
-  int64_t off[2] = {0, 0}, n_state = 0;
-  bool diag[2] = {false, false};  // all Jacobians of the type are diagonal
-  fr::HostOps hops[2];
+  int64_t off[fr::NTYPES] = {0, 0, 0}, n_state = 0;
+  bool diag[fr::NTYPES] = {false, false, false};  // all Jacobians of the type are diagonal
+  fr::HostOps hops[fr::NTYPES];
   fr::GasHost gas;
   // device buffers
   double* d_state = nullptr;  // internal state
@@ -33,9 +33,10 @@ struct fr_ctx {
   void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
   fr::FaceRec* d_faces = nullptr;
   uint8_t* d_perms = nullptr;
-  void* d_met[2] = {nullptr, nullptr};
-  double* d_detj[2] = {nullptr, nullptr};
-  void* d_pops = nullptr;
+  void* d_met[fr::NTYPES] = {nullptr, nullptr, nullptr};
+  double* d_detj[fr::NTYPES] = {nullptr, nullptr, nullptr};
+  void* d_pops = nullptr;  // prism triangle tables
+  void* d_tops = nullptr;  // tetrahedron operator tables
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
 
@@ -206,7 +207,7 @@ fr_status ensure_device(fr_ctx* c) {
     for (size_t r = 0; r < M.perms[k].size(); ++r) perms[k * nfp + r] = (uint8_t)M.perms[k][r];
   HIPCHK(hipMalloc(&c->d_perms, perms.size()));
   HIPCHK(hipMemcpy(c->d_perms, perms.data(), perms.size(), hipMemcpyHostToDevice));
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     if (!c->has[t]) continue;
     const int64_t E = M.nel[t];
     std::vector<double> met(10 * E);
@@ -226,6 +227,13 @@ fr_status ensure_device(fr_ctx* c) {
     fr::prism_ops_pack(c->ref[1], c->ph.prec, pb.data());
     HIPCHK(hipMalloc(&c->d_pops, nb));
     HIPCHK(hipMemcpy(c->d_pops, pb.data(), nb, hipMemcpyHostToDevice));
+  }
+  if (c->has[2]) {
+    size_t nb = fr::tet_ops_bytes(c->p, c->ph.prec);
+    std::vector<unsigned char> pb(nb);
+    fr::tet_ops_pack(c->ref[2], c->ph.prec, pb.data());
+    HIPCHK(hipMalloc(&c->d_tops, nb));
+    HIPCHK(hipMemcpy(c->d_tops, pb.data(), nb, hipMemcpyHostToDevice));
   }
   c->dev_ok = true;
   return FR_OK;
@@ -260,7 +268,7 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
   a.stage = stage;
   a.diag = c->diag[t];
   a.one = s;
-  a.dops = c->d_pops;
+  a.dops = t == 2 ? c->d_tops : c->d_pops;
   a.ops = &c->hops[t];
   a.gas = &c->gas;
   return a;
@@ -276,7 +284,7 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
   }
   for (int stage = 1; stage <= 4; stage <<= 1)
     if (mask & stage)
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < fr::NTYPES; ++t) {
       if (!c->has[t]) continue;
       fr::TypeArgs a = type_args(c, t, seg_of_type(c, t, rk < 0 ? u : nullptr, rk < 0 ? du : nullptr), stage);
       a.one.dt = dt;
@@ -284,7 +292,9 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
       a.from_ust = rk > 0;
       a.aa = c->ph.flux_aa != 0;
       a.saa = c->ph.surface_aa != 0;
-      hipError_t e = t == 0 ? fr::hex_rhs(a, c->ph.prec, c->st) : fr::prism_rhs(a, c->ph.prec, c->st);
+      hipError_t e = t == 0   ? fr::hex_rhs(a, c->ph.prec, c->st)
+                     : t == 1 ? fr::prism_rhs(a, c->ph.prec, c->st)
+                              : fr::tet_rhs(a, c->ph.prec, c->st);
       if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
   return FR_OK;
@@ -330,13 +340,16 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
 fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind) {
   if (!c) return FR_EINVAL;
   if (c->mesh_ok) return fail(c, FR_ESTATE, "mesh already built");
-  if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind > 2) return fail(c, FR_EINVAL, "bad mesh size");
+  if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind >= fr::kNumKinds)
+    return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
+  const bool tets = kind == FR_MESH_TET || kind == FR_MESH_PRISM_TET;
+  if (tets && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
+    return fail(c, FR_EUNSUPPORTED, "tetrahedra: fused form with flux anti-aliasing only");
   try {
     c->p = p;
-    fr::build_ref(0, p, c->ref[0]);
-    fr::build_ref(1, p, c->ref[1]);
-    const fr::RefElem* refs[2] = {&c->ref[0], &c->ref[1]};
+    for (int t = 0; t < fr::NTYPES; ++t) fr::build_ref(t, p, c->ref[t]);
+    const fr::RefElem* refs[fr::NTYPES] = {&c->ref[0], &c->ref[1], &c->ref[2]};
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
     if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
@@ -345,7 +358,7 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     c->has[t] = c->M.nel[t] > 0;
     const fr::RefElem& r = c->ref[t];
     fr::HostOps& h = c->hops[t];
@@ -361,7 +374,7 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     h.tri = &r.tri;
     h.ref = &r;
   }
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     bool d = c->has[t];
     for (int64_t e = 0; e < c->M.nel[t] && d; ++e) {
       const double* A = &c->M.jac[t][9 * e];
@@ -370,8 +383,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     c->diag[t] = d;
   }
   c->off[0] = 0;
-  c->off[1] = c->M.nel[0] * 5 * c->ref[0].nu;
-  c->n_state = c->off[1] + c->M.nel[1] * 5 * c->ref[1].nu;
+  for (int t = 1; t < fr::NTYPES; ++t) c->off[t] = c->off[t - 1] + c->M.nel[t - 1] * 5 * c->ref[t - 1].nu;
+  c->n_state = c->off[fr::NTYPES - 1] + c->M.nel[fr::NTYPES - 1] * 5 * c->ref[fr::NTYPES - 1].nu;
   c->mesh_ok = true;
   return FR_OK;
 }
@@ -385,11 +398,18 @@ fr_status fr_layout(const fr_ctx* c, int64_t* nh, int64_t* np, int64_t* ns) {
   return FR_OK;
 }
 
+fr_status fr_type_count(const fr_ctx* c, int etype, int64_t* n_elem) {
+  if (!c || !n_elem || etype < 0 || etype >= fr::NTYPES) return FR_EINVAL;
+  if (!c->mesh_ok) return FR_ESTATE;
+  *n_elem = c->M.nel[etype];
+  return FR_OK;
+}
+
 fr_status fr_upts_coords(const fr_ctx* c, double* xyz) {
   if (!c || !xyz) return FR_EINVAL;
   if (!c->mesh_ok) return FR_ESTATE;
   int64_t k = 0;
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     const fr::RefElem& r = c->ref[t];
     for (int64_t e = 0; e < c->M.nel[t]; ++e) {
       const double* A = &c->M.jac[t][9 * e];
@@ -486,7 +506,7 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
   s = fr_get_state(c, u.data(), 0);
   if (s != FR_OK) return s;
   for (int v = 0; v < 5; ++v) out5[v] = 0.0;
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     const fr::RefElem& r = c->ref[t];
     for (int64_t e = 0; e < c->M.nel[t]; ++e) {
       const double* ue = &u[c->off[t] + e * 5 * r.nu];
@@ -539,19 +559,25 @@ fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_
   if (!c->mesh_ok) return FR_ESTATE;
   const fr::Mesh& M = c->M;
   // flat flux-point numbering: types in order, element, flux point
-  int64_t base[2] = {0, M.nel[0] * c->ref[0].nf};
-  int64_t total = base[1] + M.nel[1] * c->ref[1].nf;
+  int64_t base[fr::NTYPES] = {0, 0, 0};
+  for (int t = 1; t < fr::NTYPES; ++t) base[t] = base[t - 1] + M.nel[t - 1] * c->ref[t - 1].nf;
+  int64_t total = base[fr::NTYPES - 1] + M.nel[fr::NTYPES - 1] * c->ref[fr::NTYPES - 1].nf;
   if (n_fpts) *n_fpts = total;
   if (!nbr) return FR_OK;
-  const int nfc[2] = {6, 5};
+  auto type_of = [&](int64_t s) {
+    int t = 0;
+    for (int u = 1; u < fr::NTYPES; ++u)
+      if (M.nel[u] > 0 && s >= M.slot_base[u]) t = u;
+    return t;
+  };
   for (int64_t s = 0; s < M.nslots; ++s) {
-    int t = (M.nel[1] > 0 && s >= M.slot_base[1]) ? 1 : 0;
-    int64_t e = (s - M.slot_base[t]) / nfc[t];
-    int f = int((s - M.slot_base[t]) % nfc[t]);
+    int t = type_of(s);
+    int64_t e = (s - M.slot_base[t]) / fr::kFacesOf[t];
+    int f = int((s - M.slot_base[t]) % fr::kFacesOf[t]);
     int64_t o = M.nbr_slot[s];
-    int to = (M.nel[1] > 0 && o >= M.slot_base[1]) ? 1 : 0;
-    int64_t eo = (o - M.slot_base[to]) / nfc[to];
-    int fo = int((o - M.slot_base[to]) % nfc[to]);
+    int to = type_of(o);
+    int64_t eo = (o - M.slot_base[to]) / fr::kFacesOf[to];
+    int fo = int((o - M.slot_base[to]) % fr::kFacesOf[to]);
     const fr::RefElem& r = c->ref[t];
     const fr::RefElem& ro = c->ref[to];
     const std::vector<int>& pm = M.perms[M.perm_id[s]];
@@ -571,7 +597,8 @@ void fr_destroy(fr_ctx* c) {
   if (c->dev_ok || c->d_state) {
     (void)hipStreamSynchronize(c->st);
     void* bufs[] = {c->d_state, c->d_rk, c->d_Uf, c->d_Vf, c->d_Rp, c->d_fgeo, c->d_faces, c->d_perms,
-                    c->d_met[0], c->d_met[1], c->d_detj[0], c->d_detj[1], c->d_pops};
+                    c->d_met[0], c->d_met[1], c->d_met[2], c->d_detj[0], c->d_detj[1], c->d_detj[2],
+                    c->d_pops, c->d_tops};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }

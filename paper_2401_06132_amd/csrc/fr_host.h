@@ -70,29 +70,36 @@ void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x, std:
 void triangle_nodes(int p, std::vector<double>& xy);
 void build_ref(int etype, int p, RefElem& r);
 
+// element types of a mesh: 0 hexahedra, 1 prisms, 2 tetrahedra
+constexpr int NTYPES = 3;
+constexpr int kFacesOf[NTYPES] = {6, 5, 4};
+// box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
+// 4 prism (y < 0) + tet
+constexpr int kNumKinds = 5;
+
 // Periodic box mesh with face connectivity.
 struct Mesh {
   int nx = 0, ny = 0, nz = 0, p = 0, kind = 0;
   double lo = 0, hi = 0;
-  int64_t nel[2] = {0, 0};
-  std::vector<double> org[2];    // element origin (x at reference 0)
-  std::vector<double> jac[2];    // J (3x3 row-major, rows x,y,z cols xi,eta,zeta)
-  std::vector<double> jinv[2];   // J^-1
-  std::vector<double> detj[2];
-  std::vector<int64_t> gid[2];   // mesh-order index
-  // face slots: hex e*6+f, prisms slot_base[1] + e*5+f
-  int64_t slot_base[2] = {0, 0};
+  int64_t nel[NTYPES] = {0, 0, 0};
+  std::vector<double> org[NTYPES];    // element origin (x at reference 0)
+  std::vector<double> jac[NTYPES];    // J (3x3 row-major, rows x,y,z cols xi,eta,zeta)
+  std::vector<double> jinv[NTYPES];   // J^-1
+  std::vector<double> detj[NTYPES];
+  std::vector<int64_t> gid[NTYPES];   // mesh-order index
+  // face slots: type t, element e, face f at slot_base[t] + e * kFacesOf[t] + f
+  int64_t slot_base[NTYPES] = {0, 0, 0};
   int64_t nslots = 0;
   std::vector<int64_t> nbr_slot;  // paired slot
   std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]
   std::vector<uint8_t> is_left;
   std::vector<double> nrm;        // per slot: L-side physical unit normal (3)
-  std::vector<double> mag;        // per slot: L-side area factor |det J J^-T n|
+  std::vector<double> mag;        // per slot: the slot's own area factor |det J J^-T n|
   std::vector<std::vector<int>> perms;
 };
 
 // element counts per type of a box mesh (same cell typing as build_box_mesh)
-void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[2]);
+void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[NTYPES]);
 
 // True if every prism triangle face sees its neighbour's triangle nodes in
 // the same order (identity point permutation), as surface-flux
@@ -101,6 +108,6 @@ bool prism_tri_faces_aligned(const Mesh& m);
 
 // Build the box mesh and its connectivity; returns an error string or "".
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
-                           const RefElem* refs[2], Mesh& m);
+                           const RefElem* refs[NTYPES], Mesh& m);
 
 }  // namespace fr

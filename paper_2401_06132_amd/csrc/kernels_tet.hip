@@ -1,0 +1,418 @@
+// Fused flux-reconstruction kernels for tetrahedra (gfx950).
+//
+// Tetrahedra have no tensor-product structure: the paper's sum factorisation
+// does not apply to them (sections 1 and 4.1), so every operator is a dense
+// per-element matrix: M0 (N_f x N_u), the corrected-gradient operator
+// [D_d | n_d M3] (N_u x (N_u + N_f)), M7 (N_q x N_u), the projection-
+// divergence AP_d = -Mass^-1 Dq_d^T W_q (N_u x N_q; the weak form of
+// (M1 - M3 M2) M9, as for the other types) and the lifting M3 (N_u x N_f).
+// The kernel groups are those of the hexahedral and prism kernels: disu |
+// volume group | interface group.
+//
+// Dense products C = A B run one operator row per thread: the row is read
+// from the device table into registers (in chunks of KC entries, so long
+// rows at p = 4 stay within the register budget) and applied to the
+// columns of one element held in LDS.  The lanes of a wave work on rows of
+// the same element, so every LDS read is a broadcast.
+//
+// Reference tetrahedron {xi, eta, zeta >= -1, xi + eta + zeta <= -1};
+// faces 0..3 = zeta = -1, eta = -1, xi = -1, the slanted face; each face
+// slot holds the N_t triangle-node values of its face (slot stride (p+1)^2).
+#include "fr_device.h"
+#include "fr_kernels.h"
+
+namespace fr {
+
+template <int P>
+struct TetCfg {
+  static constexpr int n = P + 1;
+  static constexpr int NU = (P + 1) * (P + 2) * (P + 3) / 6;  // solution points
+  static constexpr int NTN = (P + 1) * (P + 2) / 2;           // points per face
+  static constexpr int NF = 4 * NTN;                          // flux points
+  static constexpr int NQ = (P + 1) * (P + 1) * (P + 1);      // quadrature points
+  static constexpr int NFPS = n * n;                          // face slot stride
+  static constexpr int KG = NU + NF;                          // gradient operator row
+  // device table (working precision), row-major blocks
+  static constexpr int O_M0 = 0;                 // [NF][NU]
+  static constexpr int O_G = O_M0 + NF * NU;     // [3][NU][KG]
+  static constexpr int O_M7 = O_G + 3 * NU * KG; // [NQ][NU]
+  static constexpr int O_AP = O_M7 + NQ * NU;    // [3][NU][NQ]
+  static constexpr int O_M3 = O_AP + 3 * NU * NQ;  // [NU][NF]
+  static constexpr int SIZE = O_M3 + NU * NF;
+  // LDS per element of the volume kernel: state + gradients [20][NU]
+  // (later the partial divergences [3][5][NU]), neighbour values then jumps
+  // [5][NF], the transformed flux at the quadrature points [3][5][FQS]
+  static constexpr int FQS = NQ + 1;  // odd stride: the three components' rows hit different banks
+  static constexpr int SZ_X = 20 * NU, SZ_J = 5 * NF, SZ_F = 15 * FQS;
+  static constexpr int PER_ELEM = SZ_X + SZ_J + SZ_F;
+};
+
+// acc[c] += sum_k A[k] B[c * ldb + k] (k < K, c < NC): a row A of a dense
+// operator (device memory, read KC entries at a time) against NC columns of
+// one element in LDS
+template <int K, int NC, typename R>
+__device__ __forceinline__ void row_cols(const R* __restrict__ A, const R* B, int ldb, R (&acc)[NC]) {
+  constexpr int KC = 32;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    R a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (k0 + k < K) a[k] = A[k0 + k];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k0 + k < K) acc[c] += a[k] * B[c * ldb + k0 + k];
+  }
+}
+
+// ----------------------------------------------------------------- disu
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) tet_disu(const Seg sg, const bool from_ust, const R* __restrict__ ops,
+                                               const double eref) {
+  using C = TetCfg<P>;
+  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NFPS = C::NFPS;
+  __shared__ R sU[EB * 5 * NU];
+  const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  R* __restrict__ Uf = (R*)sg.Uf;
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const bool ok = e0 + it / (5 * NU) < E;
+    double x = U[ok ? (size_t)e0 * 5 * NU + it : 0];
+    if (it % (5 * NU) >= 4 * NU) x -= eref;
+    sU[it] = R(x);
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * NF; it += NT) {
+    const int le = it / NF, fp = it - le * NF, e = e0 + le;
+    if (e >= E) continue;
+    R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
+    row_cols<NU, 5>(ops + C::O_M0 + fp * NU, sU + le * 5 * NU, NU, acc);
+    const int f = fp / NTN, t = fp - f * NTN;
+    const size_t slot = (size_t)(sg.slot_base + e * 4 + f);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Uf[slot * 5 * NFPS + v * NFPS + t] = acc[v];
+  }
+}
+
+// --------------------------------------------------------------- volume
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_ust, const R* __restrict__ ops,
+                                                 const Gas<R> g, const double eref) {
+  using C = TetCfg<P>;
+  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, FQS = C::FQS;
+  constexpr int PE = C::PER_ELEM;
+  __shared__ R smem[EB * PE];
+  __shared__ R sMet[EB][10];
+  __shared__ FaceRec sFR[EB * 4];
+  __shared__ R sFG[EB * 4][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
+  const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  R* __restrict__ Vf = (R*)sg.Vf;
+  R* __restrict__ Rp = (R*)sg.Rp;
+  const R* __restrict__ met = (const R*)sg.met;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+#define XS(le) (smem + (le)*PE)                        /* [20][NU]    */
+#define JS(le) (smem + (le)*PE + C::SZ_X)              /* [5][NF]     */
+#define FQ(le) (smem + (le)*PE + C::SZ_X + C::SZ_J)    /* [3][5][FQS] */
+
+  // phase 0: face records, geometry, permutations and metrics to LDS, the
+  // state (reference form), then the neighbour face values
+  for (int it = tid; it < EB * 4; it += NT) {
+    const int slot = sg.slot_base + (e0 + it / 4 < E ? e0 * 4 + it : 0);
+    sFR[it] = sg.faces[slot];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
+  }
+  for (int it = tid; it < sg.nperm * NFPS; it += NT) sPerm[it] = sg.perms[it];
+  for (int it = tid; it < EB * 10; it += NT) {
+    const int le = it / 10, k = it - le * 10;
+    sMet[le][k] = met[e0 + le < E ? (size_t)(e0 + le) * 10 + k : 0];
+  }
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU);
+    double x = U[e0 + le < E ? (size_t)e0 * 5 * NU + it : 0];
+    if (r >= 4 * NU) x -= eref;
+    XS(le)[r] = R(x);
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * 5 * NF; it += NT) {
+    const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
+    const int f = fp / NTN, t = fp - f * NTN;
+    const FaceRec fr = sFR[le * 4 + f];
+    JS(le)[r0] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+  }
+  lds_barrier();
+
+  // phase 1: own face values (disu, M0) and the jumps C - u^f (eq. FR-conu:
+  // L side (1/2 + beta)(u_nbr - u_own), R side (1/2 - beta)(u_nbr - u_own)),
+  // in place over the neighbour values
+  for (int it = tid; it < EB * NF; it += NT) {
+    const int le = it / NF, fp = it - le * NF;
+    R uf[5] = {R(0), R(0), R(0), R(0), R(0)};
+    row_cols<NU, 5>(ops + C::O_M0 + fp * NU, XS(le), NU, uf);
+    const bool left = sFR[le * 4 + fp / NTN].info & 1;
+    const R w = left ? R(0.5) + g.beta : R(0.5) - g.beta;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) JS(le)[v * NF + fp] = w * (JS(le)[v * NF + fp] - uf[v]);
+  }
+  lds_barrier();
+
+  // phase 2: corrected reference gradient (eq. FR-qfinal), one (point,
+  // direction) row of [D_d | n_d M3] per thread
+  for (int it = tid; it < EB * 3 * NU; it += NT) {
+    const int le = it / (3 * NU), r0 = it - le * (3 * NU), d = r0 / NU, s = r0 - d * NU;
+    const R* row = ops + C::O_G + (d * NU + s) * C::KG;
+    R q[5] = {R(0), R(0), R(0), R(0), R(0)};
+    row_cols<NU, 5>(row, XS(le), NU, q);
+    row_cols<NF, 5>(row + NU, JS(le), NF, q);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) XS(le)[(5 + d * 5 + v) * NU + s] = q[v];
+  }
+  lds_barrier();
+
+  // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU;
+    R* X = XS(le);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+    }
+  }
+  lds_barrier();
+
+  // phase 3a: gradcoru_fpts and the own normal viscous flux at every flux
+  // point (exchanged instead of the gradient)
+  for (int it = tid; it < EB * NF; it += NT) {
+    const int le = it / NF, fp = it - le * NF, e = e0 + le;
+    if (e >= E) continue;
+    R w[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) w[k] = R(0);
+    row_cols<NU, 20>(ops + C::O_M0 + fp * NU, XS(le), NU, w);
+    const int f = fp / NTN, t = fp - f * NTN, lf = le * 4 + f;
+    const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+    const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+    R u[5], q[3][5], V[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = w[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
+    }
+    normal_viscous(u, q, nn, g, V);
+    const size_t slot = (size_t)(sg.slot_base + e * 4 + f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
+  }
+
+  // phase 4: uqpts / gradcoru_qpts (M7) and tdisf at each quadrature point
+  // (eq. FR-tdisfq): F~_d = det J sum_c (J^-1)_{dc} f_c
+  for (int it = tid; it < EB * NQ; it += NT) {
+    const int le = it / NQ, q0 = it - le * NQ;
+    R w[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) w[k] = R(0);
+    row_cols<NU, 20>(ops + C::O_M7 + q0 * NU, XS(le), NU, w);
+    R u[5], q[3][5], f[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = w[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
+    }
+    point_flux(u, q, g, f);
+    const R dj = sMet[le][9];
+    R* F = FQ(le);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        F[(d * 5 + v) * FQS + q0] =
+            dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+  }
+  lds_barrier();  // every face and quadrature point has read the state and gradients
+
+  // phase 5: projection-divergence (M1 - M3 M2) M9 in weak form, one (point,
+  // direction) row of AP_d per thread; the three partial sums go over the
+  // state slots
+  for (int it = tid; it < EB * 3 * NU; it += NT) {
+    const int le = it / (3 * NU), r0 = it - le * (3 * NU), d = r0 / NU, s = r0 - d * NU;
+    R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
+    row_cols<NQ, 5>(ops + C::O_AP + (d * NU + s) * NQ, FQ(le) + d * 5 * FQS, FQS, acc);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) XS(le)[(d * 5 + v) * NU + s] = acc[v];
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r0 = it - le * (5 * NU), e = e0 + le;
+    if (e >= E) continue;
+    const R* X = XS(le);
+    Rp[(size_t)e * 5 * NU + r0] = X[r0] + X[5 * NU + r0] + X[10 * NU + r0];
+  }
+#undef XS
+#undef JS
+#undef FQ
+}
+
+// -------------------------------------------------------------- surface
+// comm_flux at every own flux point (both sides of a pair evaluate the same
+// expression on the same inputs and normal; each side scales by its own area
+// factor), then tdivtconf (M3) + negdivconf and the RK4 stage store
+template <int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) tet_surface(const Seg sg, const int rk, const R* __restrict__ ops,
+                                                  const Gas<R> g) {
+  using C = TetCfg<P>;
+  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NFPS = C::NFPS;
+  __shared__ R sD[EB * 5 * NF];
+  const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  const R* __restrict__ Vf = (const R*)sg.Vf;
+  const R* __restrict__ Rp = (const R*)sg.Rp;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+  for (int it = tid; it < EB * NF; it += NT) {
+    const int le = it / NF, fp = it - le * NF, e = e0 + le;
+    if (e >= E) continue;
+    const int f = fp / NTN, t = fp - f * NTN;
+    const int slot = sg.slot_base + e * 4 + f;
+    const FaceRec fr = sg.faces[slot];
+    const int rr = sg.perms[(fr.info >> 1) * NFPS + t];
+    const bool left = fr.info & 1;
+    R uo[5], un[5], Vo[4], Vn[4], F[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      uo[v] = Uf[(size_t)slot * 5 * NFPS + v * NFPS + t];
+      un[v] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + rr];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Vo[k] = Vf[(size_t)slot * 4 * NFPS + k * NFPS + t];
+      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFPS + k * NFPS + rr];
+    }
+    const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
+    const R mag = fgeo[4 * slot + 3];
+    if (left)
+      common_flux(uo, un, Vo, Vn, nL, g, F);
+    else
+      common_flux(un, uo, Vn, Vo, nL, g, F);
+    const R sc = left ? mag : -mag;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sD[(le * 5 + v) * NF + fp] = sc * F[v];
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU, e = e0 + le;
+    if (e >= E) continue;
+    R acc[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[v] = Rp[(size_t)e * 5 * NU + v * NU + s];
+    row_cols<NF, 5>(ops + C::O_M3 + s * NF, sD + le * 5 * NF, NF, acc);
+    const double dj = sg.detj[e];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rk_store(sg, rk, (size_t)e * 5 * NU + v * NU + s, -double(acc[v]) / dj);
+  }
+}
+
+// ------------------------------------------------------------ host side
+template <int P, typename R>
+static void pack_tet(const RefElem& r, R* o) {
+  using C = TetCfg<P>;
+  constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NTN = C::NTN, KG = C::KG;
+  for (int f = 0; f < NF; ++f)
+    for (int u = 0; u < NU; ++u) o[C::O_M0 + f * NU + u] = R(r.M0[f * NU + u]);
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < NU; ++s) {
+      R* row = o + C::O_G + (d * NU + s) * KG;
+      for (int u = 0; u < NU; ++u) row[u] = R(r.Dg[(d * NU + s) * NU + u]);
+      for (int f = 0; f < NF; ++f) row[NU + f] = R(r.face_normal[3 * (f / NTN) + d] * r.M3[s * NF + f]);
+    }
+  for (int q = 0; q < NQ; ++q)
+    for (int u = 0; u < NU; ++u) o[C::O_M7 + q * NU + u] = R(r.M7[q * NU + u]);
+  for (int i = 0; i < 3 * NU * NQ; ++i) o[C::O_AP + i] = R(r.APd[i]);
+  for (int i = 0; i < NU * NF; ++i) o[C::O_M3 + i] = R(r.M3[i]);
+}
+
+size_t tet_ops_bytes(int p, int prec) {
+  const size_t rs = prec == 0 ? 8 : 4;
+  switch (p) {
+    case 1: return rs * TetCfg<1>::SIZE;
+    case 2: return rs * TetCfg<2>::SIZE;
+    case 3: return rs * TetCfg<3>::SIZE;
+    case 4: return rs * TetCfg<4>::SIZE;
+  }
+  return 0;
+}
+
+void tet_ops_pack(const RefElem& r, int prec, void* dst) {
+  const bool d = prec == 0;
+  switch (r.p) {
+    case 1: d ? pack_tet<1>(r, (double*)dst) : pack_tet<1>(r, (float*)dst); break;
+    case 2: d ? pack_tet<2>(r, (double*)dst) : pack_tet<2>(r, (float*)dst); break;
+    case 3: d ? pack_tet<3>(r, (double*)dst) : pack_tet<3>(r, (float*)dst); break;
+    case 4: d ? pack_tet<4>(r, (double*)dst) : pack_tet<4>(r, (float*)dst); break;
+  }
+}
+
+template <typename R>
+static Gas<R> make_gas_t(const GasHost& gh) {
+  Gas<R> o;
+  o.gamma = R(gh.gamma);
+  o.gm1 = R(gh.gamma - 1.0);
+  o.mu = R(gh.mu);
+  o.muh = R(gh.mu * gh.gamma / gh.prandtl);
+  o.pref = R(gh.pref);
+  o.eref = R(gh.pref / (gh.gamma - 1.0));
+  o.href = R(gh.gamma * gh.pref / (gh.gamma - 1.0));
+  o.beta = R(gh.beta);
+  o.tau = R(gh.tau);
+  return o;
+}
+
+// elements per workgroup of the volume kernel: about one quadrature point per
+// thread (256 threads)
+template <int P>
+struct TetLaunch {
+  static constexpr int NQ = TetCfg<P>::NQ;
+  static constexpr int EB = NQ >= 256 ? 1 : (256 / NQ > 16 ? 16 : 256 / NQ);
+};
+constexpr int TET_DISU_EB = 8, TET_SURF_EB = 8;
+
+template <int P, typename R>
+static hipError_t tet_rhs_t(const TypeArgs& a, hipStream_t st) {
+  const R* ops = (const R*)a.dops;
+  const Gas<R> g = make_gas_t<R>(*a.gas);
+  const double eref = a.gas->pref / (a.gas->gamma - 1.0);
+  const int E = a.one.E;
+  constexpr int EB = TetLaunch<P>::EB;
+  if ((a.stage & 1) && E > 0)
+    hipLaunchKernelGGL((tet_disu<P, R, TET_DISU_EB, 256>), dim3((E + TET_DISU_EB - 1) / TET_DISU_EB), dim3(256), 0,
+                       st, a.one, a.from_ust, ops, eref);
+  if ((a.stage & 2) && E > 0)
+    hipLaunchKernelGGL((tet_volume<P, R, EB, 256>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one, a.from_ust,
+                       ops, g, eref);
+  if ((a.stage & 4) && E > 0)
+    hipLaunchKernelGGL((tet_surface<P, R, TET_SURF_EB, 256>), dim3((E + TET_SURF_EB - 1) / TET_SURF_EB), dim3(256),
+                       0, st, a.one, a.rk, ops, g);
+  return hipGetLastError();
+}
+
+hipError_t tet_rhs(const TypeArgs& a, int prec, hipStream_t st) {
+  if (!a.dops) return hipErrorInvalidValue;
+  const bool d = prec == 0;
+  switch (a.p) {
+    case 1: return d ? tet_rhs_t<1, double>(a, st) : tet_rhs_t<1, float>(a, st);
+    case 2: return d ? tet_rhs_t<2, double>(a, st) : tet_rhs_t<2, float>(a, st);
+    case 3: return d ? tet_rhs_t<3, double>(a, st) : tet_rhs_t<3, float>(a, st);
+    case 4: return d ? tet_rhs_t<4, double>(a, st) : tet_rhs_t<4, float>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fr

@@ -7,7 +7,15 @@
 //   first : x = x0 + (eta+1) hx/2,      y = y0 + (zeta+1) hy/2, z = z0 + (xi+1) hz/2
 //   second: x = x0 + hx - (eta+1) hx/2, y = y0 + (zeta+1) hy/2, z = z0 + hz - (xi+1) hz/2
 // so every z = const cell face is a full prism quadrilateral and a mixed mesh
-// (hexahedra below z = 0) is conforming.
+// (hexahedra below z = 0) is conforming.  A tetrahedron cell holds six
+// tetrahedra: the Kuhn subdivision of the cube mirrored in x (unit
+// coordinates u = ((x0+h-x)/h, (y-y0)/h, (z-z0)/h); for each order (a, b, c)
+// of the axes the tetrahedron u_a >= u_b >= u_c with vertices 0, e_a,
+// e_a + e_b, (1,1,1) mapped to the reference vertices V0..V3, V1 and V2
+// swapped where that gives a negative Jacobian).  Opposite cell faces are cut
+// along parallel diagonals (conforming across cells and the period), and the
+// y faces along the prisms' diagonal (prism triangles meet tetrahedra in the
+// prism/tet mesh, prisms below y = 0).
 //
 // Connectivity: faces are paired by their centroids modulo the period, then
 // the points of each face pair are matched by coordinates (section 2.1: paired
@@ -50,24 +58,60 @@ static int parallel_chunks(int64_t n, F body) {
   return c;
 }
 
-// mixed meshes: hexahedra where the cell centre has z < 0, prisms elsewhere
-static int cell_type(int k, int nz, double lo, double hi, int kind) {
-  if (kind != 2) return kind;
-  const double hz = (hi - lo) / nz;
-  const double zc = (lo + k * hz) + 0.5 * hz;
-  return zc < 0.0 ? 0 : 1;
+// element type of cell (j, k): kind 2 has hexahedra where the cell centre
+// has z < 0 and prisms elsewhere; kind 4 prisms where y < 0, tetrahedra
+// elsewhere
+static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kind) {
+  if (kind == 2) {
+    const double hz = (hi - lo) / nz;
+    return (lo + k * hz) + 0.5 * hz < 0.0 ? 0 : 1;
+  }
+  if (kind == 4) {
+    const double hy = (hi - lo) / ny;
+    return (lo + j * hy) + 0.5 * hy < 0.0 ? 1 : 2;
+  }
+  return kind == 3 ? 2 : kind;
 }
 
-void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[2]) {
-  nel[0] = nel[1] = 0;
-  for (int k = 0; k < nz; ++k) {
-    const int t = cell_type(k, nz, lo, hi, kind);
-    nel[t] += (int64_t)nx * ny * (t == 0 ? 1 : 2);
+static constexpr int kPerCell[NTYPES] = {1, 2, 6};
+
+void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[NTYPES]) {
+  for (int t = 0; t < NTYPES; ++t) nel[t] = 0;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j) {
+      const int t = cell_type(j, k, ny, nz, lo, hi, kind);
+      nel[t] += (int64_t)nx * kPerCell[t];
+    }
+}
+
+// vertices of the six tetrahedra of the cell at x0 (module header)
+static void kuhn_tets(const double x0[3], const double h[3], double P[6][4][3]) {
+  static const int order[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int o = 0; o < 6; ++o) {
+    double u[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+    u[1][order[o][0]] = 1;
+    u[2][order[o][0]] = 1;
+    u[2][order[o][1]] = 1;
+    for (int v = 0; v < 4; ++v) {
+      P[o][v][0] = x0[0] + h[0] * (1.0 - u[v][0]);
+      P[o][v][1] = x0[1] + h[1] * u[v][1];
+      P[o][v][2] = x0[2] + h[2] * u[v][2];
+    }
+    double a[3], b[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+      a[d] = P[o][1][d] - P[o][0][d];
+      b[d] = P[o][2][d] - P[o][0][d];
+      c[d] = P[o][3][d] - P[o][0][d];
+    }
+    const double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                       a[2] * (b[0] * c[1] - b[1] * c[0]);
+    if (det < 0)
+      for (int d = 0; d < 3; ++d) std::swap(P[o][1][d], P[o][2][d]);
   }
 }
 
-std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind, const RefElem* refs[2],
-                           Mesh& M) {
+std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
+                           const RefElem* refs[NTYPES], Mesh& M) {
   M = Mesh();
   M.nx = nx;
   M.ny = ny;
@@ -83,9 +127,21 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         double x0[3] = {lo + i * h[0], lo + j * h[1], lo + k * h[2]};
-        int t = cell_type(k, nz, lo, hi, kind);
+        int t = cell_type(j, k, ny, nz, lo, hi, kind);
         double c[3] = {x0[0] + 0.5 * h[0], x0[1] + 0.5 * h[1], x0[2] + 0.5 * h[2]};
-        if (t == 0) {
+        if (t == 2) {
+          double P[6][4][3];
+          kuhn_tets(x0, h, P);
+          for (int o = 0; o < 6; ++o) {
+            // x = P0 + J (xi + 1): columns (P_v - P0)/2; origin at xi = 0
+            double J[9];
+            for (int d = 0; d < 3; ++d)
+              for (int v = 0; v < 3; ++v) J[3 * d + v] = 0.5 * (P[o][v + 1][d] - P[o][0][d]);
+            for (int d = 0; d < 3; ++d) M.org[2].push_back(P[o][0][d] + J[3 * d] + J[3 * d + 1] + J[3 * d + 2]);
+            M.jac[2].insert(M.jac[2].end(), J, J + 9);
+            M.gid[2].push_back(g++);
+          }
+        } else if (t == 0) {
           for (int d = 0; d < 3; ++d) M.org[0].push_back(c[d]);
           double J[9] = {0.5 * h[0], 0, 0, 0, 0.5 * h[1], 0, 0, 0, 0.5 * h[2]};
           M.jac[0].insert(M.jac[0].end(), J, J + 9);
@@ -100,7 +156,7 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
           }
         }
       }
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NTYPES; ++t) {
     M.nel[t] = (int64_t)M.gid[t].size();
     M.jinv[t].resize(9 * M.nel[t]);
     M.detj[t].resize(M.nel[t]);
@@ -122,10 +178,9 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
       B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
     }
   }
-  const int nfc[2] = {6, 5};
   M.slot_base[0] = 0;
-  M.slot_base[1] = M.nel[0] * 6;
-  M.nslots = M.slot_base[1] + M.nel[1] * 5;
+  for (int t = 1; t < NTYPES; ++t) M.slot_base[t] = M.slot_base[t - 1] + M.nel[t - 1] * kFacesOf[t - 1];
+  M.nslots = M.slot_base[NTYPES - 1] + M.nel[NTYPES - 1] * kFacesOf[NTYPES - 1];
   const int64_t S = M.nslots;
 
   // physical face points and centroids
@@ -138,10 +193,12 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
   std::vector<std::array<int64_t, 4>> keys(S);  // quantised centroid mod period, slot
   const double Q = double(1 << 24);
   auto slot_info = [&](int64_t s, int& t, int64_t& e, int& f) {
-    t = s >= M.slot_base[1] && M.nel[1] > 0 ? 1 : 0;
+    t = 0;
+    for (int u = 1; u < NTYPES; ++u)
+      if (M.nel[u] > 0 && s >= M.slot_base[u]) t = u;
     int64_t r = s - M.slot_base[t];
-    e = r / nfc[t];
-    f = int(r % nfc[t]);
+    e = r / kFacesOf[t];
+    f = int(r % kFacesOf[t]);
   };
   parallel_chunks(S, [&](int64_t s0, int64_t s1, int) {
   for (int64_t s = s0; s < s1; ++s) {
@@ -247,7 +304,7 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
         return d2;
       };
       const double tol = 1e-9 * std::min(h[0], std::min(h[1], h[2])), tol2 = tol * tol;
-      const int cls = ((t * 8 + f) * 2 + to) * 8 + fo;
+      const int cls = ((t * 8 + f) * NTYPES + to) * 8 + fo;
       int pid = cls < (int)last.size() ? last[cls] : -1;
       if (pid >= 0) {
         const std::vector<int>& pm = L.perms[pid];
@@ -307,20 +364,27 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
       }
     }
   }
-  // normals: n = det J J^-T nhat / mag (Nanson), taken from the L side
-  parallel_chunks(S, [&](int64_t s0, int64_t s1, int) {
-  for (int64_t s = s0; s < s1; ++s) {
-    int64_t l = M.is_left[s] ? s : M.nbr_slot[s];
+  // normals: n = det J J^-T nhat / mag (Nanson).  The unit normal is the L
+  // side's for both slots of a pair (both evaluate the common flux with the
+  // same inputs); the area factor is each slot's own (the two differ where
+  // the reference faces differ in size, e.g. a tetrahedron's slanted face
+  // against an axis-aligned one)
+  auto nanson = [&](int64_t s, double v[3]) {
     int t, f;
     int64_t e;
-    slot_info(l, t, e, f);
+    slot_info(s, t, e, f);
     const double* B = &M.jinv[t][9 * e];
     const double* nh = &refs[t]->face_normal[3 * f];
-    double v[3];
     for (int c = 0; c < 3; ++c) v[c] = M.detj[t][e] * (B[0 * 3 + c] * nh[0] + B[1 * 3 + c] * nh[1] + B[2 * 3 + c] * nh[2]);
-    double mg = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  };
+  parallel_chunks(S, [&](int64_t s0, int64_t s1, int) {
+  for (int64_t s = s0; s < s1; ++s) {
+    double v[3];
+    M.mag[s] = nanson(s, v);
+    if (!M.is_left[s]) nanson(M.nbr_slot[s], v);
+    const double mg = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     for (int c = 0; c < 3; ++c) M.nrm[3 * s + c] = v[c] / mg;
-    M.mag[s] = mg;
   }
   });
   return "";

@@ -272,3 +272,53 @@ def test_full_aa_free_stream_conservation_and_rk4(kind):
     c1 = s.integrals()
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())
 
+
+
+TET_CASES = [((2, 2, 2), 1, "tet"), ((2, 2, 2), 2, "tet"), ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"),
+             ((3, 2, 1), 3, "tet"), ((1, 1, 1), 2, "tet"), ((2, 2, 2), 3, "prism_tet"), ((2, 3, 2), 2, "prism_tet"),
+             ((1, 2, 1), 4, "prism_tet")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,p,kind", TET_CASES)
+def test_rhs_parity_tetrahedra(dims, p, kind, prec):
+    """Tetrahedral and prism/tetrahedron meshes (dense-operator kernels)
+    against the oracle; same tolerances."""
+    _need_gpu()
+    print("tet case", dims, p, kind, prec, flush=True)
+    m, U = _case(dims, p, kind)
+    r64, rld = _references(m, U)
+    got, _ = _gpu_rhs(dims, p, kind, prec, U)
+    err = _rel_err(got, rld).astype(np.float64)
+    own = _rel_err(r64, rld).astype(np.float64)
+    tol = TOL[prec]
+    if prec == "fp64":
+        tol = np.maximum(tol, 4 * own)
+    print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
+    assert np.all(err < tol), (err, tol)
+
+
+@pytest.mark.parametrize("kind", ["tet", "prism_tet"])
+def test_tet_free_stream_conservation_and_rk4(kind):
+    _need_gpu()
+    dims, p = (2, 2, 2), 3
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0)
+    U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
+    u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
+    du = torch.empty_like(u)
+    s.rhs(u, du)
+    assert du.abs().max().item() < 1e-12 * 72 * 10
+    m, U = _case(dims, p, kind)
+    Uo = {t: x for t, x in zip(m.types, U)}
+    for _ in range(3):
+        Uo = oracle_rk4(m, Uo, Params(pref=inputs.P0), 1e-3)
+    s.set_state(np.concatenate([x.reshape(-1) for x in U]))
+    c0 = s.integrals()
+    s.rk4(1e-3, 3)
+    for got, t, x in zip(s.split(s.get_state()), m.types, U):
+        d_ref = Uo[t] - x
+        err = np.abs((got - x) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
+        print("tet rk4 rel err of the state change", t, err)
+        assert np.all(err < 1e-11)
+    c1 = s.integrals()
+    assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())

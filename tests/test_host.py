@@ -48,7 +48,7 @@ def test_reference_operators_match_oracle(etype, name, p):
         np.testing.assert_allclose(got, ref, atol=5e-14 * scale, err_msg=key)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet"])
 def test_mesh_coordinates_and_connectivity_match_oracle(kind):
     _lib_or_skip()
     dims = (3, 2, 4)
@@ -87,3 +87,18 @@ def test_surface_aa_rejected_where_not_built():
         frmi.Solver((2, 2, 2), 3, "hex", form="plain", surface_aa=True)
     for kind in ("hex", "prism", "mixed"):
         frmi.Solver((2, 2, 2), 3, kind, surface_aa=True)
+
+
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet"])
+def test_element_counts_match_oracle(kind):
+    """The library's element counts per type (hexahedra, prisms, tetrahedra)
+    and its pairing match the oracle's."""
+    _lib_or_skip()
+    dims = (2, 3, 2)
+    s = frmi.Solver(dims, 2, kind)
+    m = Mesh(*dims, 2, kind)
+    counts = {"hex": s.n_hex, "prism": s.n_prism, "tet": s.n_tet}
+    for t in ("hex", "prism", "tet"):
+        assert counts[t] == m.nelem.get(t, 0)
+    nbr, isl = s.connectivity()
+    np.testing.assert_array_equal(nbr, m.partner)

@@ -317,7 +317,8 @@ def main():
         ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex"),
         ("fp32", 3, "noaa", "prism"), ("fp32", 4, "noaa", "prism"),
         ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
-        ("fp64", 4, "fullaa", "hex"), ("fp32", 3, "fullaa", "prism"), ("fp32", 4, "fullaa", "prism")]
+        ("fp64", 4, "fullaa", "hex"), ("fp32", 3, "fullaa", "prism"), ("fp32", 4, "fullaa", "prism"),
+        ("fp32", 3, "fused", "tet"), ("fp64", 3, "fused", "tet"), ("fp32", 4, "fused", "tet")]
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
         r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)
@@ -331,7 +332,7 @@ def main():
             r["rhs_GBs"] = rhs_bytes_model(p, br) * E * ksteps / r["wall_s"] / 1e9
         else:
             r["vol_GBs"] = r["vol_TFLOPs"] = r["rhs_GBs"] = float("nan")
-        variants["%s%s%s_p%d" % ("prism_" if kind == "prism" else "", "" if form == "fused" else form + "_", prec,
+        variants["%s%s%s_p%d" % ("" if kind == "hex" else kind + "_", "" if form == "fused" else form + "_", prec,
                                   p)] = r
         print("variant", form, prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
               file=sys.stderr, flush=True)

@@ -13,11 +13,13 @@ from the product.
 Modules
 -------
 quadrature  Gauss-Legendre / Gauss-Lobatto / Gauss-Jacobi rules, the
-            conical-product triangle rule and the triangle node set.
-basis       Polynomial bases of the hex, triangle and prism solution spaces.
+            conical-product triangle and tetrahedron rules and the triangle
+            and tetrahedron node sets.
+basis       Polynomial bases of the hex, triangle, prism and tet solution spaces.
 elements    Reference elements (solution, flux and quadrature points, unit
             reference normals) and the dense operator matrices M0..M10.
-mesh        Periodic box meshes of hexahedra, split prisms or both, affine
+mesh        Periodic box meshes of hexahedra, split prisms, tetrahedra and
+            mixtures (hex/prism, prism/tet), affine
             metric terms and flux-point pairing by physical coordinates.
 physics     Inviscid / viscous fluxes, Rusanov and LDG interface fluxes.
 rhs         The semi-discrete right-hand side (the paper's thirteen kernels,
@@ -41,6 +43,10 @@ Parity status (pins live in tests/test_oracle_*.py):
     integration; the right-hand side by free stream, conservation, equality
     with the flux-point form when every interface flux is a face polynomial
     of degree <= p, and design-order convergence (test_oracle_surface_aa.py).
+  * tetrahedra (RefElement("tet"), Mesh kinds "tet" and "prism_tet"): the
+    conical-product rule against closed-form simplex moments, the node set's
+    symmetry and unisolvence, the operator identities above, free stream,
+    conservation and entropy-wave convergence (test_oracle_tet.py).
   * The full right-hand side at a perturbed state has no closed form; it is
     pinned only through the properties above.
 """

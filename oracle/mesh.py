@@ -23,6 +23,20 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                  y faces are cut along the prisms' diagonal.
   kind "prism_tet" : prisms in cells whose centre has y < 0, tetrahedra
                  elsewhere (prism triangles meet tetrahedron faces).
+  kind "hex_warp" : curved (non-affine) hexahedra: every grid vertex x is
+                 moved to x + warp h (sin y cos z, sin z cos x, sin x cos y)
+                 (h the cell size per axis, warp = 0.2 by default; the field
+                 is periodic, so the mesh stays periodic and conforming) and
+                 each element is the trilinear map of its eight moved
+                 vertices, so its faces are bilinear (curved) surfaces and its
+                 metrics vary from point to point.  The cofactor metric terms
+                 det J J^-1 of a trilinear map are exact (no discrete metric
+                 is formed); their normal components are bilinear on every
+                 face, so the GL(n)^2 flux points interpolate them exactly,
+                 and the volume integrand is integrated exactly by GL(m)^3:
+                 free-stream preservation is exact at every order.
+Metrics: affine meshes keep one J per element (Jinv, detJ of shape (E, 3, 3)
+and (E,)); curved meshes give them per point through metrics(t, ref_pts).
 surf_aa=True builds the reference elements with surface-flux
 anti-aliasing (flux points at the face quadrature points).
 Element numbering: cells in index order; a prism cell yields A then B.  The
@@ -61,7 +75,8 @@ def _kuhn_tets(x0, h):
 
 
 class Mesh:
-    def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None, surf_aa=False):
+    def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None, surf_aa=False,
+                 warp=0.2):
         self.nx, self.ny, self.nz, self.p, self.kind = nx, ny, nz, p, kind
         self.lo, self.hi = lo, hi
         L = hi - lo
@@ -69,7 +84,9 @@ class Mesh:
         h = np.array([L / nx, L / ny, L / nz])
         self.h = h
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
-                 "prism_tet": ["prism", "tet"]}[kind]
+                 "prism_tet": ["prism", "tet"], "hex_warp": ["hex"]}[kind]
+        self.curved = kind == "hex_warp"
+        verts = []
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -96,11 +113,22 @@ class Mesh:
                             A["tet"].append(Jt)
                             gid["tet"].append(g)
                             g += 1
-                    elif ctype == "hex":
+                    elif ctype in ("hex", "hex_warp"):
                         org["hex"].append(x0 + 0.5 * h)
                         A["hex"].append(np.diag(0.5 * h))
                         gid["hex"].append(g)
                         g += 1
+                        if self.curved:
+                            # vertex a + 2 b + 4 c at x0 + h (a, b, c), moved
+                            X = []
+                            for c in range(2):
+                                for b in range(2):
+                                    for a in range(2):
+                                        x = x0 + h * np.array([a, b, c], dtype=float)
+                                        X.append(x + warp * h * np.array([np.sin(x[1]) * np.cos(x[2]),
+                                                                          np.sin(x[2]) * np.cos(x[0]),
+                                                                          np.sin(x[0]) * np.cos(x[1])]))
+                            verts.append(np.array(X))
                     else:
                         hx, hy, hz = 0.5 * h
                         # columns: d x / d(xi, eta, zeta)
@@ -117,15 +145,54 @@ class Mesh:
         self.J = {t: np.array(A[t]) for t in self.types}
         self.gid = {t: np.array(gid[t]) for t in self.types}
         self.nelem = {t: len(self.org[t]) for t in self.types}
-        self.detJ = {t: np.linalg.det(self.J[t]) for t in self.types}
-        self.Jinv = {t: np.linalg.inv(self.J[t]) for t in self.types}
+        if self.curved:
+            self.verts = {"hex": np.array(verts)}
+            r = self.refs["hex"]
+            self.detJ, self.Jinv = {}, {}
+            self.detJ["hex"], self.Jinv["hex"] = self.metrics("hex", r.upts)  # at the solution points
+            self.detJq, self.Jinvq = {}, {}
+            self.detJq["hex"], self.Jinvq["hex"] = self.metrics("hex", r.qpts)  # at the quadrature points
+            if np.any(self.metrics("hex", r.fpts)[0] <= 0) or np.any(self.detJq["hex"] <= 0):
+                raise ValueError("non-positive Jacobian")
+        else:
+            self.detJ = {t: np.linalg.det(self.J[t]) for t in self.types}
+            self.Jinv = {t: np.linalg.inv(self.J[t]) for t in self.types}
         if any(np.any(self.detJ[t] <= 0) for t in self.types):
             raise ValueError("non-positive Jacobian")
         self._pair()
 
+    @staticmethod
+    def _trilinear(ref_pts):
+        """Shape functions N_v (npts, 8) and their gradients (npts, 8, 3) of
+        the trilinear map, vertex v = a + 2 b + 4 c at reference corner
+        (2a-1, 2b-1, 2c-1)."""
+        x = np.asarray(ref_pts, float)
+        s = np.array([[2 * a - 1, 2 * b - 1, 2 * c - 1] for c in range(2) for b in range(2) for a in range(2)], float)
+        f = 0.5 * (1.0 + x[:, None, :] * s[None, :, :])  # (npts, 8, 3)
+        N = f.prod(axis=2)
+        dN = np.empty(f.shape)
+        for d in range(3):
+            o = [k for k in range(3) if k != d]
+            dN[:, :, d] = 0.5 * s[None, :, d] * f[:, :, o[0]] * f[:, :, o[1]]
+        return N, dN
+
+    def metrics(self, t, ref_pts, elems=None):
+        """det J (E, npts) and J^-1 (E, npts, 3, 3) at reference points
+        (curved meshes; J[i][j] = d x_i / d xi_j)."""
+        X = self.verts[t] if elems is None else self.verts[t][elems]
+        _, dN = self._trilinear(ref_pts)
+        J = np.einsum("evi,pvj->epij", X, dN)
+        return np.linalg.det(J), np.linalg.inv(J)
+
     # physical coordinates of reference points for every element of type t
-    def phys(self, t, ref_pts):
-        return self.org[t][:, None, :] + np.einsum("eij,pj->epi", self.J[t], ref_pts)
+    def phys(self, t, ref_pts, elems=None):
+        if self.curved:
+            X = self.verts[t] if elems is None else self.verts[t][elems]
+            N, _ = self._trilinear(ref_pts)
+            return np.einsum("pv,evi->epi", N, X)
+        org = self.org[t] if elems is None else self.org[t][elems]
+        J = self.J[t] if elems is None else self.J[t][elems]
+        return org[:, None, :] + np.einsum("eij,pj->epi", J, ref_pts)
 
     def upts_coords(self, t):
         return self.phys(t, self.refs[t].upts)
@@ -146,8 +213,8 @@ class Mesh:
         for ti, t in enumerate(self.types):
             r = self.refs[t]
             E = self.nelem[t]
-            fc = np.stack([r.fpts[r.fface == f].mean(axis=0) for f in range(r.nfaces)])
-            c = self.phys(t, fc).reshape(-1, 3)
+            c = np.stack([self.phys(t, r.fpts[r.fface == f]).mean(axis=1) for f in range(r.nfaces)],
+                         axis=1).reshape(-1, 3)
             fcent.append(c)
             fkeys.append(np.mod(np.rint((c - self.lo) / self.period * Qk).astype(np.int64), Qk))
             finfo.append(np.stack([np.full(E * r.nfaces, ti), np.repeat(np.arange(E), r.nfaces),
@@ -179,8 +246,8 @@ class Mesh:
             for c0 in range(0, len(allsel), 65536):
                 sel = allsel[c0:c0 + 65536]
                 eL, eR = info[fL[sel], 1], info[fR[sel], 1]
-                XL = self.org[tL][eL][:, None, :] + np.einsum("eij,pj->epi", self.J[tL][eL], rL.fpts[pl])
-                XR = self.org[tR][eR][:, None, :] + np.einsum("eij,pj->epi", self.J[tR][eR], rR.fpts[pr])
+                XL = self.phys(tL, rL.fpts[pl], eL)
+                XR = self.phys(tR, rR.fpts[pr], eR)
                 if len(pl) != len(pr):
                     raise ValueError("paired faces have different point counts")
                 # coordinates relative to each face's centroid coincide for the
@@ -213,7 +280,11 @@ class Mesh:
         nrm, mag = [], []
         for t in self.types:
             r = self.refs[t]
-            v = self.detJ[t][:, None, None] * np.einsum("edc,fd->efc", self.Jinv[t], r.fnorm)
+            if self.curved:
+                dj, ji = self.metrics(t, r.fpts)  # at every flux point
+                v = dj[:, :, None] * np.einsum("efdc,fd->efc", ji, r.fnorm)
+            else:
+                v = self.detJ[t][:, None, None] * np.einsum("edc,fd->efc", self.Jinv[t], r.fnorm)
             mg = np.linalg.norm(v, axis=2)
             nrm.append((v / mg[:, :, None]).reshape(-1, 3))
             mag.append(mg.reshape(-1))

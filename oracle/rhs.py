@@ -17,7 +17,11 @@ v1.11.0), with dense operators and no fusion:
                    (mag: each side's own area factor |det J J^-T nhat|)
   12 tdivtconf     R~  += M3 D~
   13 negdivconf    R   = -R~ / det J
-Affine elements: J, det J and J^-1 are constant per element.
+Affine elements: J, det J and J^-1 are constant per element.  Curved
+elements (trilinear maps): J^-T at the solution points (step 5), det J J^-1
+at the quadrature points (step 9; at the solution points without AA), det J
+at the solution points (step 13), and the normals and area factors of every
+flux point from J there.
 
 Without flux anti-aliasing (the paper's "AA off" configuration) steps 7, 8
 and the projection M8 are absent: tdisf evaluates the flux at the solution
@@ -62,7 +66,9 @@ def _volume_flux(r, u, q, detj, jinv, gas, aa, cast):
     u: (E, N_u, 5) state (reference form), q: (E, 3, N_u, 5) gradients.
     With flux anti-aliasing: U^q = M7 U, Q^q = M10 Q (steps 7, 8), the flux
     at the quadrature points (step 9) and its projection M9 = I3 x M8 (first
-    factor of step 10).  Without: the flux at the solution points."""
+    factor of step 10).  Without: the flux at the solution points.
+    detj, jinv: per element ((E,), (E, 3, 3)) on affine meshes, or at the
+    points where the flux is evaluated ((E, N), (E, N, 3, 3)) on curved ones."""
     if aa:
         uq = np.einsum("qu,euv->vqe", cast(r.M7), u)  # 8 uqpts
         qq = np.einsum("qs,ecsv->cvqe", cast(r.M7), q)  # 7 gradcoru_qpts
@@ -70,10 +76,38 @@ def _volume_flux(r, u, q, detj, jinv, gas, aa, cast):
         uq = np.ascontiguousarray(u.transpose(2, 1, 0))  # (5, N_u, E)
         qq = np.ascontiguousarray(q.transpose(1, 3, 2, 0))  # (3, 5, N_u, E)
     f = physics.inviscid_flux(uq, gas) - physics.viscous_flux(uq, qq, gas)  # 9 tdisf
-    ft = np.einsum("e,edc,cvqe->edqv", cast(detj), cast(jinv), f)
+    if np.ndim(detj) == 2:
+        ft = np.einsum("eq,eqdc,cvqe->edqv", cast(detj), cast(jinv), f)
+    else:
+        ft = np.einsum("e,edc,cvqe->edqv", cast(detj), cast(jinv), f)
     if aa:
         return np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10 tdivtpcorf: M9 (I3 x M8)
     return ft
+
+
+def _sel(a, sel):
+    return a if sel is None else a[sel]
+
+
+def _to_physical(mesh, t, qt, sel, cast):
+    """q = J^-T q~ at the solution points (eq. FR-gradcoru); qt (E, 3, N_u, 5)."""
+    if mesh.curved:
+        return np.einsum("esdc,edsv->ecsv", cast(_sel(mesh.Jinv[t], sel)), qt)
+    return np.einsum("edc,edsv->ecsv", cast(_sel(mesh.Jinv[t], sel)), qt)
+
+
+def _flux_metrics(mesh, t, aa, sel):
+    """det J and J^-1 where the flux is evaluated: per element on affine
+    meshes; at the quadrature points (AA) or solution points on curved ones."""
+    if mesh.curved and aa:
+        return _sel(mesh.detJq[t], sel), _sel(mesh.Jinvq[t], sel)
+    return _sel(mesh.detJ[t], sel), _sel(mesh.Jinv[t], sel)
+
+
+def _detj_u(mesh, t, sel, cast):
+    """det J broadcast against (E, N_u, 5): per element, or per solution point."""
+    d = cast(_sel(mesh.detJ[t], sel))
+    return d[:, :, None] if mesh.curved else d[:, None, None]
 
 
 def rhs(mesh, U, par, dtype=None):
@@ -100,7 +134,7 @@ def rhs(mesh, U, par, dtype=None):
         C = _unflat(ca, mesh, t, (5,))
         qt = np.einsum("dsu,euv->edsv", cast(r.Dg), Up[t])  # 3 tgradpcoru (M4 part)
         qt += np.einsum("dsf,efv->edsv", cast(r.M6), C - Uf[t])  # 4 tgradcoru
-        q = np.einsum("edc,edsv->ecsv", cast(mesh.Jinv[t]), qt)  # 5 gradcoru (J^-T)
+        q = _to_physical(mesh, t, qt, None, cast)  # 5 gradcoru (J^-T)
         Q[t] = q
         Qf[t] = np.einsum("fs,ecsv->efcv", cast(r.M0), q)  # 6 gradcoru_fpts
     for t in mesh.types:
@@ -110,7 +144,8 @@ def rhs(mesh, U, par, dtype=None):
         chunk = max(1, int(2.0e7 // (r.nq * 20)))
         for e0 in range(0, E, chunk):
             sl = slice(e0, min(E, e0 + chunk))
-            fu = _volume_flux(r, Up[t][sl], Q[t][sl], mesh.detJ[t][sl], mesh.Jinv[t][sl], gas, par.aa, cast)
+            dj, ji = _flux_metrics(mesh, t, par.aa, sl)
+            fu = _volume_flux(r, Up[t][sl], Q[t][sl], dj, ji, gas, par.aa, cast)
             div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)  # M1
             nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)  # M2
             rt[sl] = div - np.einsum("uf,efv->euv", cast(r.M3), nf)  # - M3 M2
@@ -129,7 +164,7 @@ def rhs(mesh, U, par, dtype=None):
         r = mesh.refs[t]
         D = _unflat(da, mesh, t, (5,))
         rt = Rt[t] + np.einsum("uf,efv->euv", cast(r.M3), D)  # 12 tdivtconf
-        du = -rt / cast(mesh.detJ[t])[:, None, None]  # 13 negdivconf
+        du = -rt / _detj_u(mesh, t, None, cast)  # 13 negdivconf
         out[t] = du.transpose(0, 2, 1).copy()
     return out
 
@@ -219,8 +254,7 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         C = np.where(lf, physics.common_solution(own, nb, beta), physics.common_solution(nb, own, beta))  # 2
         qt = np.einsum("dsu,euv->edsv", cast(r.Dg), u)  # 3
         qt += np.einsum("dsf,efv->edsv", cast(r.M6), C - own)  # 4
-        jinv = cast(mesh.Jinv[t][e1])
-        q = np.einsum("edc,edsv->ecsv", jinv, qt)  # 5
+        q = _to_physical(mesh, t, qt, e1, cast)  # 5
         Q[t] = (e1, q)
         qblocks.append(np.einsum("fs,ecsv->efcv", cast(r.M0), q).reshape(-1, 3, 5))  # 6
         Qrow[fp] = qoff + np.arange(len(fp))
@@ -236,7 +270,8 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         u = u2[np.searchsorted(e2, e0)]
         e1, q1 = Q[t]
         q = q1[np.searchsorted(e1, e0)]
-        fu = _volume_flux(r, u, q, mesh.detJ[t][e0], mesh.Jinv[t][e0], gas, par.aa, cast)  # 7-10
+        dj, ji = _flux_metrics(mesh, t, par.aa, e0)
+        fu = _volume_flux(r, u, q, dj, ji, gas, par.aa, cast)  # 7-10
         div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)
         nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)
         rt = div - np.einsum("uf,efv->euv", cast(r.M3), nf)
@@ -256,6 +291,6 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         mag = cast(mesh.fmag[fp])[:, None]  # own area factor (eq. FR-comm_flux)
         D = np.where(lf[:, None], mag * F, -(mag * F)).reshape(len(e0), r.nf, 5)
         rt = rt + np.einsum("uf,efv->euv", cast(r.M3), D)  # 12
-        du = -rt / cast(mesh.detJ[t][e0])[:, None, None]  # 13
+        du = -rt / _detj_u(mesh, t, e0, cast)  # 13
         out[t] = du.transpose(0, 2, 1).copy()
     return out

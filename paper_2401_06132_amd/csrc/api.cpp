@@ -37,6 +37,7 @@ struct fr_ctx {
   double* d_detj[fr::NTYPES] = {nullptr, nullptr, nullptr};
   void* d_pops = nullptr;  // prism triangle tables
   void* d_tops = nullptr;  // tetrahedron operator tables
+  void* d_verts = nullptr; // curved hexahedra: element vertices [E][8][3]
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
 
@@ -228,6 +229,11 @@ fr_status ensure_device(fr_ctx* c) {
     HIPCHK(hipMalloc(&c->d_pops, nb));
     HIPCHK(hipMemcpy(c->d_pops, pb.data(), nb, hipMemcpyHostToDevice));
   }
+  if (M.curved) {
+    to_real(c, M.verts, buf);
+    HIPCHK(hipMalloc(&c->d_verts, buf.size()));
+    HIPCHK(hipMemcpy(c->d_verts, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  }
   if (c->has[2]) {
     size_t nb = fr::tet_ops_bytes(c->p, c->ph.prec);
     std::vector<unsigned char> pb(nb);
@@ -259,6 +265,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.E = (int32_t)c->M.nel[t];
   s.slot_base = (int32_t)c->M.slot_base[t];
   s.nperm = (int32_t)c->M.perms.size();
+  s.verts = t == 0 ? c->d_verts : nullptr;
   return s;
 }
 
@@ -269,6 +276,7 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
   a.diag = c->diag[t];
   a.one = s;
   a.dops = t == 2 ? c->d_tops : c->d_pops;
+  a.warp = c->M.curved && t == 0;
   a.ops = &c->hops[t];
   a.gas = &c->gas;
   return a;
@@ -346,6 +354,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   const bool tets = kind == FR_MESH_TET || kind == FR_MESH_PRISM_TET;
   if (tets && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
     return fail(c, FR_EUNSUPPORTED, "tetrahedra: fused form with flux anti-aliasing only");
+  if (kind == FR_MESH_HEX_WARP && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
+    return fail(c, FR_EUNSUPPORTED, "curved hexahedra: fused form with flux anti-aliasing only");
   try {
     c->p = p;
     for (int t = 0; t < fr::NTYPES; ++t) fr::build_ref(t, p, c->ref[t]);
@@ -373,9 +383,11 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     h.liftR = r.line.liftR.data();
     h.tri = &r.tri;
     h.ref = &r;
+    h.x = r.line.x.data();
+    h.xq = r.line.xq.data();
   }
   for (int t = 0; t < fr::NTYPES; ++t) {
-    bool d = c->has[t];
+    bool d = c->has[t] && !c->M.curved;
     for (int64_t e = 0; e < c->M.nel[t] && d; ++e) {
       const double* A = &c->M.jac[t][9 * e];
       d = A[1] == 0 && A[2] == 0 && A[3] == 0 && A[5] == 0 && A[6] == 0 && A[7] == 0;
@@ -412,13 +424,7 @@ fr_status fr_upts_coords(const fr_ctx* c, double* xyz) {
   for (int t = 0; t < fr::NTYPES; ++t) {
     const fr::RefElem& r = c->ref[t];
     for (int64_t e = 0; e < c->M.nel[t]; ++e) {
-      const double* A = &c->M.jac[t][9 * e];
-      const double* o = &c->M.org[t][3 * e];
-      for (int u = 0; u < r.nu; ++u) {
-        const double* xi = &r.upts[3 * u];
-        for (int d = 0; d < 3; ++d)
-          xyz[3 * (k + u) + d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
-      }
+      for (int u = 0; u < r.nu; ++u) fr::map_point(c->M, t, e, &r.upts[3 * u], &xyz[3 * (k + u)]);
       k += r.nu;
     }
   }
@@ -510,10 +516,19 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
     const fr::RefElem& r = c->ref[t];
     for (int64_t e = 0; e < c->M.nel[t]; ++e) {
       const double* ue = &u[c->off[t] + e * 5 * r.nu];
+      // det J at every solution point (constant for affine elements)
+      std::vector<double> dj(r.nu, c->M.detj[t][e]);
+      if (c->M.curved && t == 0)
+        for (int q = 0; q < r.nu; ++q) {
+          double J[9];
+          fr::jac_point(c->M, t, e, &r.upts[3 * q], J);
+          dj[q] = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                  J[2] * (J[3] * J[7] - J[4] * J[6]);
+        }
       for (int v = 0; v < 5; ++v) {
         double acc = 0.0;
-        for (int q = 0; q < r.nu; ++q) acc += r.wu[q] * ue[v * r.nu + q];
-        out5[v] += c->M.detj[t][e] * acc;
+        for (int q = 0; q < r.nu; ++q) acc += r.wu[q] * dj[q] * ue[v * r.nu + q];
+        out5[v] += acc;
       }
     }
   }
@@ -598,7 +613,7 @@ void fr_destroy(fr_ctx* c) {
     (void)hipStreamSynchronize(c->st);
     void* bufs[] = {c->d_state, c->d_rk, c->d_Uf, c->d_Vf, c->d_Rp, c->d_fgeo, c->d_faces, c->d_perms,
                     c->d_met[0], c->d_met[1], c->d_met[2], c->d_detj[0], c->d_detj[1], c->d_detj[2],
-                    c->d_pops, c->d_tops};
+                    c->d_pops, c->d_tops, c->d_verts};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }

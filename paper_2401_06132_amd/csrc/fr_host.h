@@ -74,8 +74,10 @@ void build_ref(int etype, int p, RefElem& r);
 constexpr int NTYPES = 3;
 constexpr int kFacesOf[NTYPES] = {6, 5, 4};
 // box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
-// 4 prism (y < 0) + tet
-constexpr int kNumKinds = 5;
+// 4 prism (y < 0) + tet, 5 curved hexahedra (warped grid)
+constexpr int kNumKinds = 6;
+// vertex displacement of the warped grid, in cell sizes
+constexpr double kWarp = 0.2;
 
 // Periodic box mesh with face connectivity.
 struct Mesh {
@@ -93,10 +95,20 @@ struct Mesh {
   std::vector<int64_t> nbr_slot;  // paired slot
   std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]
   std::vector<uint8_t> is_left;
+  // curved hexahedra: the eight vertices of every element ([E][8][3], vertex
+  // a + 2b + 4c at reference corner (2a-1, 2b-1, 2c-1)); the element is
+  // their trilinear map (jac/jinv/detj then hold the undeformed cell's)
+  bool curved = false;
+  std::vector<double> verts;
   std::vector<double> nrm;        // per slot: L-side physical unit normal (3)
   std::vector<double> mag;        // per slot: the slot's own area factor |det J J^-T n|
   std::vector<std::vector<int>> perms;
 };
+
+// physical point and Jacobian J[i][j] = d x_i / d xi_j of element e of type t
+// at reference point xi (affine, or the trilinear map of a curved mesh)
+void map_point(const Mesh& m, int t, int64_t e, const double* xi, double* x);
+void jac_point(const Mesh& m, int t, int64_t e, const double* xi, double J[9]);
 
 // element counts per type of a box mesh (same cell typing as build_box_mesh)
 void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[NTYPES]);

@@ -16,6 +16,7 @@ struct HostOps {
   const double *lb = nullptr, *rb = nullptr, *liftL = nullptr, *liftR = nullptr;
   const Tri* tri = nullptr;
   const RefElem* ref = nullptr;
+  const double *x = nullptr, *xq = nullptr;  // GL(n) and GL(m) nodes
 };
 
 struct GasHost {
@@ -35,7 +36,7 @@ struct Seg {
   void* Vf = nullptr;     // normal viscous fluxes [slot][4][n^2], per mesh
   void* Rp = nullptr;     // volume divergence [E][5][N_u] (precision R)
   const FaceRec* faces = nullptr;
-  const void* fgeo = nullptr;      // [slot][4]: L-side unit normal, area factor (R)
+  const void* fgeo = nullptr;      // [slot][4]: L-side unit normal, own area factor (R)
   const uint8_t* perms = nullptr;  // [perm][n^2]
   const void* met = nullptr;       // [E][10]: J^-1 (row-major), det J   (R)
   const double* detj = nullptr;    // [E]
@@ -43,6 +44,7 @@ struct Seg {
   int32_t E = 0;                   // elements in the segment
   int32_t slot_base = 0;           // first face slot of this type in the mesh
   int32_t nperm = 0;               // face-point permutations in perms (<= MAX_PERMS)
+  const void* verts = nullptr;     // curved hexahedra: [E][8][3] element vertices (R)
 };
 
 // largest number of distinct face-point permutations a mesh may use (the
@@ -65,6 +67,7 @@ struct TypeArgs {
   bool from_ust = false;  // disu/volume read Seg::ust instead of Seg::U
   bool aa = true;       // flux anti-aliasing (false: flux at the solution points)
   bool saa = false;     // surface-flux anti-aliasing (only together with aa)
+  bool warp = false;    // curved hexahedra: per-point metrics from Seg::verts
   int rk = -1;          // -1: surface writes du; 0..3: fused classical RK4 stage
   Seg one;              // the segment when bt is null
   const BlkRef* bt[3] = {nullptr, nullptr, nullptr};  // per-kernel workgroup tables

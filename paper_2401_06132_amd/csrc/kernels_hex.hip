@@ -37,7 +37,47 @@ struct HexOps {
   R AP[n][m];  // projection + divergence
   R APu[n][n]; // divergence at the solution points (no anti-aliasing)
   R lb[n], rb[n], liftL[n], liftR[n];
+  R x[n], xq[m];  // GL(n) solution and GL(m) quadrature nodes
 };
+
+// Curved hexahedra: the trilinear map of the eight vertices X (vertex
+// a + 2b + 4c at reference corner (2a-1, 2b-1, 2c-1)).  At reference point
+// (xi, eta, zeta): the columns J_c = dx/dxi_c (bilinear interpolations of the
+// four edge vectors along c), the cofactor rows S_d = J_{d+1} x J_{d+2}
+// (S = det J J^-1, the metric terms of the transformed flux and of the
+// normals) and det J = J_0 . S_0.
+template <typename R>
+__device__ __forceinline__ void trilinear_metric(const R* X, R xi, R eta, R zeta, R S[3][3], R& det) {
+  const R xm = R(1) - xi, xp = R(1) + xi, ym = R(1) - eta, yp = R(1) + eta, zm = R(1) - zeta, zp = R(1) + zeta;
+  R J[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    J[0][i] = R(0.125) * (ym * zm * (X[3 + i] - X[i]) + yp * zm * (X[9 + i] - X[6 + i]) +
+                          ym * zp * (X[15 + i] - X[12 + i]) + yp * zp * (X[21 + i] - X[18 + i]));
+    J[1][i] = R(0.125) * (xm * zm * (X[6 + i] - X[i]) + xp * zm * (X[9 + i] - X[3 + i]) +
+                          xm * zp * (X[18 + i] - X[12 + i]) + xp * zp * (X[21 + i] - X[15 + i]));
+    J[2][i] = R(0.125) * (xm * ym * (X[12 + i] - X[i]) + xp * ym * (X[15 + i] - X[3 + i]) +
+                          xm * yp * (X[18 + i] - X[6 + i]) + xp * yp * (X[21 + i] - X[9 + i]));
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const R* a = J[(d + 1) % 3];
+    const R* b = J[(d + 2) % 3];
+    S[d][0] = a[1] * b[2] - a[2] * b[1];
+    S[d][1] = a[2] * b[0] - a[0] * b[2];
+    S[d][2] = a[0] * b[1] - a[1] * b[0];
+  }
+  det = J[0][0] * S[0][0] + J[0][1] * S[0][1] + J[0][2] * S[0][2];
+}
+
+// reference coordinates of the point with index i along axis ax and
+// tangential indices (a, b) on the grid g (tangential axes in increasing order)
+template <typename R>
+__device__ __forceinline__ void grid_point(int ax, R xi_ax, R ta, R tb, R& x, R& y, R& z) {
+  x = ax == 0 ? xi_ax : ta;
+  y = ax == 1 ? xi_ax : (ax == 0 ? ta : tb);
+  z = ax == 2 ? xi_ax : tb;
+}
 
 template <int P>
 struct HexCfg {
@@ -252,7 +292,7 @@ struct HexVolLoads {
 // the face quadrature points (from the solution and corrected gradient
 // interpolated there) and stores its projection at the flux points.  Only
 // the Rusanov flux, nonlinear in the pair, is left to the interface kernel.
-template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA, bool SAA>
+template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA, bool SAA, bool WARP>
 __global__ void __launch_bounds__(NT)
     hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                const HexOps<P, R> op, const Gas<R> g, const double eref) {
@@ -267,6 +307,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ R sFG[EB * 6][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFP];
   __shared__ R sI[m][n];  // interpolation rows, read with a per-thread row index
+  __shared__ R sV[WARP ? EB : 1][24];  // curved: element vertices
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -292,6 +333,13 @@ __global__ void __launch_bounds__(NT)
   HexVolLoads<P, R, EB, NT> ld;
   ld.load(U, faces, fgeo, met, e0, E, slot_base, tid);
   ld.put_faces(sFR, sFG, tid);
+  if constexpr (WARP) {
+    const R* __restrict__ vx = (const R*)sg.verts;
+    for (int it = tid; it < EB * 24; it += NT) {
+      const int le = it / 24;
+      sV[le][it - le * 24] = vx[e0 + le < E ? (size_t)e0 * 24 + it : 0];
+    }
+  }
   lds_barrier();
   ld.gather(Uf, sFR, sPerm, tid);
   ld.put_elems(smem, sMet, eref, PE, tid);
@@ -341,12 +389,26 @@ __global__ void __launch_bounds__(NT)
     for (int it = tid; it < EB * NU; it += NT) {
       const int le = it / NU, s = it - le * NU;
       R* X = XS(le);
+      R M[3][3];  // M[d][c] = (J^-1)_{dc}
+      if constexpr (WARP) {
+        R S[3][3], det;
+        trilinear_metric(&sV[le][0], sel(op.x, s % n), sel(op.x, (s / n) % n), sel(op.x, s / (n * n)), S, det);
+        const R id = R(1) / det;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) M[d][c] = S[d][c] * id;
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) M[d][c] = sMet[le][3 * d + c];
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+        for (int c = 0; c < 3; ++c) X[(5 + c * 5 + v) * NU + s] = M[0][c] * g0 + M[1][c] * g1 + M[2][c] * g2;
       }
     }
     lds_barrier();
@@ -470,8 +532,20 @@ __global__ void __launch_bounds__(NT)
     for (int side = 0; side < 2; ++side) {
       const R* w = side ? fp : fm;
       const int lf = le * 6 + 2 * ax + side, slot = slot_base + e * 6 + 2 * ax + side;
-      const R sgn = (cFR[lf].info & 1) ? R(1) : R(-1);
-      const R nn[3] = {sgn * cFG[lf][0], sgn * cFG[lf][1], sgn * cFG[lf][2]};
+      R nn[3];
+      if constexpr (WARP) {
+        // own outward unit normal at this flux point: +-S_ax / |S_ax|
+        R px, py, pz, S[3][3], det;
+        grid_point(ax, side ? R(1) : R(-1), sel(op.x, a), sel(op.x, b), px, py, pz);
+        trilinear_metric(&sV[le][0], px, py, pz, S, det);
+        const R im = rcp(sqrt(S[ax][0] * S[ax][0] + S[ax][1] * S[ax][1] + S[ax][2] * S[ax][2]));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nn[c] = (side ? im : -im) * S[ax][c];
+      } else {
+        const R sgn = (cFR[lf].info & 1) ? R(1) : R(-1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nn[c] = sgn * cFG[lf][c];
+      }
       R u[5], q[3][5], V[4];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -575,6 +649,7 @@ __global__ void __launch_bounds__(NT)
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int c = 0; c < 3; ++c) S[d][c] = DIAG ? (d == c ? dj * sMet[cle][4 * d] : R(0)) : dj * sMet[cle][3 * d + c];
+    const R qx = WARP ? sel(op.xq, ca) : R(0), qy = WARP ? sel(op.xq, cb) : R(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -595,6 +670,10 @@ __global__ void __launch_bounds__(NT)
           q[(fld - 5) / 5][(fld - 5) % 5] = s;
       }
       point_flux(u, q, g, f);
+      if constexpr (WARP) {
+        R det;
+        trilinear_metric(&sV[cle][0], qx, qy, op.xq[kq], S, det);  // det J J^-1 at this point
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -686,7 +765,7 @@ __global__ void __launch_bounds__(NT)
 // kernel; the states are face polynomials of degree p) and is evaluated at
 // the flux points; the Rusanov flux is evaluated at the quadrature points
 // from the interpolated pair of states and projected back.
-template <int P, typename R, int EB, int NT, bool BT, bool SAA>
+template <int P, typename R, int EB, int NT, bool BT, bool SAA, bool WARP>
 __global__ void __launch_bounds__(NT)
     hex_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
                 const HexOps<P, R> op, const Gas<R> g) {
@@ -708,6 +787,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ uint8_t sPerm[MAX_PERMS * NFP];
   __shared__ R sLift[2][n];
   __shared__ double sDet[EB];
+  __shared__ R sV[WARP ? EB : 1][24];  // curved: element vertices
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -728,6 +808,13 @@ __global__ void __launch_bounds__(NT)
     sLift[1][tid] = op.liftR[tid];
   }
   if (tid < EB) sDet[tid] = sg.detj[e0 + tid < E ? e0 + tid : 0];
+  if constexpr (WARP) {
+    const R* __restrict__ vx = (const R*)sg.verts;
+    for (int it = tid; it < EB * 24; it += NT) {
+      const int le = it / 24;
+      sV[le][it - le * 24] = vx[e0 + le < E ? (size_t)e0 * 24 + it : 0];
+    }
+  }
   if constexpr (SAA) {
     if (tid < m * n) {
       sI[tid / n][tid % n] = op.I[tid / n][tid % n];
@@ -771,8 +858,20 @@ __global__ void __launch_bounds__(NT)
       const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP;
       const int lf = le * 6 + f;
       const bool left = sFR[lf].info & 1;
-      const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
-      const R mag = sFG[lf][3];
+      R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
+      R mag = sFG[lf][3];
+      if constexpr (WARP) {
+        // own area factor and outward normal at this flux point; the L side's
+        // normal is the opposite of the R side's own
+        const int ax = f >> 1, side = f & 1;
+        R px, py, pz, S[3][3], det;
+        grid_point(ax, side ? R(1) : R(-1), sel(op.x, r % n), sel(op.x, r / n), px, py, pz);
+        trilinear_metric(&sV[le][0], px, py, pz, S, det);
+        mag = sqrt(S[ax][0] * S[ax][0] + S[ax][1] * S[ax][1] + S[ax][2] * S[ax][2]);
+        const R im = (side == (left ? 1 : 0)) ? rcp(mag) : -rcp(mag);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nL[c] = im * S[ax][c];
+      }
       R F[5];
       const R sc = left ? mag : -mag;
       if constexpr (SAA) {
@@ -886,7 +985,13 @@ __global__ void __launch_bounds__(NT)
     acc += sLift[0][i] * D[0 * 5 * NFP + j + n * kk] + sLift[1][i] * D[1 * 5 * NFP + j + n * kk];
     acc += sLift[0][j] * D[2 * 5 * NFP + i + n * kk] + sLift[1][j] * D[3 * 5 * NFP + i + n * kk];
     acc += sLift[0][kk] * D[4 * 5 * NFP + i + n * j] + sLift[1][kk] * D[5 * 5 * NFP + i + n * j];
-    val[k] = -double(acc) / sDet[le];
+    double dj = sDet[le];
+    if constexpr (WARP) {
+      R S[3][3], det;
+      trilinear_metric(&sV[le][0], sel(op.x, i), sel(op.x, j), sel(op.x, kk), S, det);
+      dj = double(det);
+    }
+    val[k] = -double(acc) / dj;
   }
   rk_store_block<NL, NT>(sg, rk, e0, E, 5 * NU, EB * 5 * NU, tid, val);
 }
@@ -911,7 +1016,9 @@ static HexOps<P, R> make_hex_ops(const HostOps& h) {
     o.liftL[i] = R(h.liftL[i]);
     o.liftR[i] = R(h.liftR[i]);
     for (int j = 0; j < n; ++j) o.APu[i][j] = R(h.APu[i * n + j]);
+    o.x[i] = R(h.x[i]);
   }
+  for (int a = 0; a < m; ++a) o.xq[a] = R(h.xq[a]);
   return o;
 }
 
@@ -955,12 +1062,12 @@ struct HexSurf {
   static constexpr int EB = SAA ? (EB0 > 1 ? EB0 / 2 : 1) : EB0;
 };
 
-template <int P, typename R, bool BT, bool DIAG, bool AA, bool SAA>
+template <int P, typename R, bool BT, bool DIAG, bool AA, bool SAA, bool WARP = false>
 static void hex_volume_launch(const TypeArgs& a, int nb, const HexOps<P, R>& op, const Gas<R>& g, double eref,
                               hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
-  hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA>), dim3(nb), dim3(NT), 0, st, a.one,
+  hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA, WARP>), dim3(nb), dim3(NT), 0, st, a.one,
                      a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
 }
 
@@ -987,6 +1094,17 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, eref);
+  // curved hexahedra (single meshes only; flux anti-aliasing, general metric)
+  if constexpr (!BT) {
+    if (a.warp) {
+      if ((a.stage & 2) && grid[K_VOLUME] > 0)
+        hex_volume_launch<P, R, false, false, true, false, true>(a, grid[K_VOLUME], op, g, eref, st);
+      if ((a.stage & 4) && grid[K_SURFACE] > 0)
+        hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl>::EB, NTC, false, false, true>), dim3(grid[K_SURFACE]),
+                           dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
+      return;
+    }
+  }
   if ((a.stage & 2) && grid[K_VOLUME] > 0) {
     if (a.diag)
       hex_volume_dispatch<P, R, BT, true>(a, grid[K_VOLUME], op, g, eref, st);
@@ -995,11 +1113,11 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   }
   if ((a.stage & 4) && grid[K_SURFACE] > 0) {
     if (a.saa)
-      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl, true>::EB, NTC, BT, true>), dim3(grid[K_SURFACE]),
-                         dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
+      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl, true>::EB, NTC, BT, true, false>),
+                         dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
     else
-      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl>::EB, NTC, BT, false>), dim3(grid[K_SURFACE]), dim3(NTC),
-                         0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
+      hipLaunchKernelGGL((hex_surface<P, R, HexSurf<P, dbl>::EB, NTC, BT, false, false>), dim3(grid[K_SURFACE]),
+                         dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, g);
   }
 }
 

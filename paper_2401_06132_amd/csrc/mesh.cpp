@@ -70,7 +70,7 @@ static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kin
     const double hy = (hi - lo) / ny;
     return (lo + j * hy) + 0.5 * hy < 0.0 ? 1 : 2;
   }
-  return kind == 3 ? 2 : kind;
+  return kind == 3 ? 2 : (kind == 5 ? 0 : kind);
 }
 
 static constexpr int kPerCell[NTYPES] = {1, 2, 6};
@@ -110,6 +110,38 @@ static void kuhn_tets(const double x0[3], const double h[3], double P[6][4][3]) 
   }
 }
 
+void map_point(const Mesh& m, int t, int64_t e, const double* xi, double* x) {
+  if (m.curved && t == 0) {
+    const double* X = &m.verts[24 * e];
+    for (int d = 0; d < 3; ++d) x[d] = 0;
+    for (int v = 0; v < 8; ++v) {
+      const double w = 0.125 * (1 + (v & 1 ? xi[0] : -xi[0])) * (1 + (v & 2 ? xi[1] : -xi[1])) *
+                       (1 + (v & 4 ? xi[2] : -xi[2]));
+      for (int d = 0; d < 3; ++d) x[d] += w * X[3 * v + d];
+    }
+    return;
+  }
+  const double* A = &m.jac[t][9 * e];
+  const double* o = &m.org[t][3 * e];
+  for (int d = 0; d < 3; ++d) x[d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
+}
+
+void jac_point(const Mesh& m, int t, int64_t e, const double* xi, double J[9]) {
+  if (m.curved && t == 0) {
+    const double* X = &m.verts[24 * e];
+    for (int k = 0; k < 9; ++k) J[k] = 0;
+    for (int v = 0; v < 8; ++v) {
+      const double s[3] = {v & 1 ? 1.0 : -1.0, v & 2 ? 1.0 : -1.0, v & 4 ? 1.0 : -1.0};
+      const double f[3] = {1 + s[0] * xi[0], 1 + s[1] * xi[1], 1 + s[2] * xi[2]};
+      const double dN[3] = {0.125 * s[0] * f[1] * f[2], 0.125 * f[0] * s[1] * f[2], 0.125 * f[0] * f[1] * s[2]};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[3 * i + j] += dN[j] * X[3 * v + i];
+    }
+    return;
+  }
+  for (int k = 0; k < 9; ++k) J[k] = m.jac[t][9 * e + k];
+}
+
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
                            const RefElem* refs[NTYPES], Mesh& M) {
   M = Mesh();
@@ -146,6 +178,15 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
           double J[9] = {0.5 * h[0], 0, 0, 0, 0.5 * h[1], 0, 0, 0, 0.5 * h[2]};
           M.jac[0].insert(M.jac[0].end(), J, J + 9);
           M.gid[0].push_back(g++);
+          if (kind == 5) {
+            // warped grid: x + w h (sin y cos z, sin z cos x, sin x cos y)
+            for (int v = 0; v < 8; ++v) {
+              const double x[3] = {x0[0] + h[0] * (v & 1), x0[1] + h[1] * ((v >> 1) & 1), x0[2] + h[2] * (v >> 2)};
+              M.verts.push_back(x[0] + kWarp * h[0] * std::sin(x[1]) * std::cos(x[2]));
+              M.verts.push_back(x[1] + kWarp * h[1] * std::sin(x[2]) * std::cos(x[0]));
+              M.verts.push_back(x[2] + kWarp * h[2] * std::sin(x[0]) * std::cos(x[1]));
+            }
+          }
         } else {
           for (int s = 0; s < 2; ++s) {
             double sg = s ? -1.0 : 1.0;
@@ -156,6 +197,20 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
           }
         }
       }
+  M.curved = kind == 5;
+  if (M.curved) {
+    // the trilinear maps must keep a positive Jacobian at the corners and centre
+    for (int64_t e = 0; e < (int64_t)M.gid[0].size(); ++e)
+      for (int k = 0; k < 9; ++k) {
+        const double xi[3] = {k < 8 ? (k & 1 ? 1.0 : -1.0) : 0.0, k < 8 ? (k & 2 ? 1.0 : -1.0) : 0.0,
+                              k < 8 ? (k & 4 ? 1.0 : -1.0) : 0.0};
+        double J[9];
+        jac_point(M, 0, e, xi, J);
+        const double d = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                         J[2] * (J[3] * J[7] - J[4] * J[6]);
+        if (!(d > 0)) return "non-positive Jacobian";
+      }
+  }
   for (int t = 0; t < NTYPES; ++t) {
     M.nel[t] = (int64_t)M.gid[t].size();
     M.jinv[t].resize(9 * M.nel[t]);
@@ -184,11 +239,7 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
   const int64_t S = M.nslots;
 
   // physical face points and centroids
-  auto phys = [&](int t, int64_t e, const double* xi, double* x) {
-    const double* A = &M.jac[t][9 * e];
-    const double* o = &M.org[t][3 * e];
-    for (int d = 0; d < 3; ++d) x[d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
-  };
+  auto phys = [&](int t, int64_t e, const double* xi, double* x) { map_point(M, t, e, xi, x); };
   std::vector<double> cent(3 * S);
   std::vector<std::array<int64_t, 4>> keys(S);  // quantised centroid mod period, slot
   const double Q = double(1 << 24);

@@ -282,8 +282,8 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (!q) return pfail(P, FR_EINVAL, "null request");
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind >= fr::kNumKinds)
     return pfail(P, FR_EINVAL, "bad mesh size");
-  if (q->kind == FR_MESH_TET || q->kind == FR_MESH_PRISM_TET)
-    return pfail(P, FR_EUNSUPPORTED, "the pool serves hexahedra and prisms");
+  if (q->kind == FR_MESH_TET || q->kind == FR_MESH_PRISM_TET || q->kind == FR_MESH_HEX_WARP)
+    return pfail(P, FR_EUNSUPPORTED, "the pool serves affine hexahedra and prisms");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
   if (!q->u_init && !(q->tgv_p0 > 0.0)) return pfail(P, FR_EINVAL, "no initial state and tgv_p0 <= 0");
@@ -316,6 +316,8 @@ fr_status ensure_refs(fr_pool* P, int p) {
     h.liftR = r.line.liftR.data();
     h.tri = &r.tri;
     h.ref = &r;
+    h.x = r.line.x.data();
+    h.xq = r.line.xq.data();
   }
   P->ref_ok[p] = true;
   return FR_OK;

@@ -322,3 +322,53 @@ def test_tet_free_stream_conservation_and_rk4(kind):
         assert np.all(err < 1e-11)
     c1 = s.integrals()
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())
+
+
+WARP_CASES = [((3, 3, 3), 3), ((2, 3, 2), 1), ((3, 2, 4), 2), ((2, 3, 3), 4), ((5, 1, 2), 3), ((4, 4, 4), 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,p", WARP_CASES)
+def test_rhs_parity_curved_hexahedra(dims, p, prec):
+    """Curved hexahedra (trilinear maps of a warped grid; the kernels form the
+    metrics at every point from the vertices) against the oracle's per-point
+    metrics; same tolerances."""
+    _need_gpu()
+    print("warp case", dims, p, prec, flush=True)
+    m, U = _case(dims, p, "hex_warp")
+    r64, rld = _references(m, U)
+    got, _ = _gpu_rhs(dims, p, "hex_warp", prec, U)
+    err = _rel_err(got, rld).astype(np.float64)
+    own = _rel_err(r64, rld).astype(np.float64)
+    tol = TOL[prec]
+    if prec == "fp64":
+        tol = np.maximum(tol, 4 * own)
+    print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
+    assert np.all(err < tol), (err, tol)
+
+
+def test_curved_free_stream_conservation_and_rk4():
+    _need_gpu()
+    dims, p = (3, 2, 3), 3
+    s = frmi.Solver(dims, p, "hex_warp", pref=inputs.P0)
+    U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
+    u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
+    du = torch.empty_like(u)
+    s.rhs(u, du)
+    assert du.abs().max().item() < 1e-12 * 72 * 10
+    m, U = _case(dims, p, "hex_warp")
+    Uo = {"hex": U[0]}
+    for _ in range(3):
+        Uo = oracle_rk4(m, Uo, Params(pref=inputs.P0), 1e-3)
+    s.set_state(U[0])
+    c0 = s.integrals()
+    want0 = np.einsum("eu,u,evu->v", m.detJ["hex"], m.refs["hex"].wu, U[0])
+    assert np.allclose(c0, want0, rtol=1e-13, atol=1e-13 * np.abs(want0).max())
+    s.rk4(1e-3, 3)
+    got = s.split(s.get_state())[0]
+    d_ref = Uo["hex"] - U[0]
+    err = np.abs((got - U[0]) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
+    print("curved rk4 rel err of the state change", err)
+    assert np.all(err < 1e-11)
+    c1 = s.integrals()
+    assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())

@@ -48,7 +48,7 @@ def test_reference_operators_match_oracle(etype, name, p):
         np.testing.assert_allclose(got, ref, atol=5e-14 * scale, err_msg=key)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp"])
 def test_mesh_coordinates_and_connectivity_match_oracle(kind):
     _lib_or_skip()
     dims = (3, 2, 4)
@@ -83,6 +83,11 @@ def test_surface_aa_rejected_where_not_built():
     _lib_or_skip()
     with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
         frmi.Solver((2, 2, 2), 3, "hex", aa=False, surface_aa=True)
+    for kind in ("tet", "hex_warp"):
+        with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
+            frmi.Solver((2, 2, 2), 3, kind, aa=False)
+        with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
+            frmi.Solver((2, 2, 2), 3, kind, form="plain")
     with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
         frmi.Solver((2, 2, 2), 3, "hex", form="plain", surface_aa=True)
     for kind in ("hex", "prism", "mixed"):

@@ -787,7 +787,8 @@ __global__ void __launch_bounds__(NT)
   __shared__ uint8_t sPerm[MAX_PERMS * NFP];
   __shared__ R sLift[2][n];
   __shared__ double sDet[EB];
-  __shared__ R sV[WARP ? EB : 1][24];  // curved: element vertices
+  __shared__ R sV[WARP ? EB : 1][24];              // curved: element vertices
+  __shared__ R sDetU[WARP ? EB : 1][WARP ? NU : 1];  // curved: det J at the solution points
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -895,6 +896,14 @@ __global__ void __launch_bounds__(NT)
       for (int v = 0; v < 5; ++v) sD[lf * 5 * NFP + v * NFP + r] = sc * F[v];
     }
   }
+  if constexpr (WARP) {
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s = it - le * NU;
+      R S[3][3], det;
+      trilinear_metric(&sV[le][0], sel(op.x, s % n), sel(op.x, (s / n) % n), sel(op.x, s / (n * n)), S, det);
+      sDetU[le][s] = det;
+    }
+  }
   lds_barrier();
   if constexpr (SAA) {
     // the pair of states along the first tangential axis to GL(m)
@@ -985,12 +994,7 @@ __global__ void __launch_bounds__(NT)
     acc += sLift[0][i] * D[0 * 5 * NFP + j + n * kk] + sLift[1][i] * D[1 * 5 * NFP + j + n * kk];
     acc += sLift[0][j] * D[2 * 5 * NFP + i + n * kk] + sLift[1][j] * D[3 * 5 * NFP + i + n * kk];
     acc += sLift[0][kk] * D[4 * 5 * NFP + i + n * j] + sLift[1][kk] * D[5 * 5 * NFP + i + n * j];
-    double dj = sDet[le];
-    if constexpr (WARP) {
-      R S[3][3], det;
-      trilinear_metric(&sV[le][0], sel(op.x, i), sel(op.x, j), sel(op.x, kk), S, det);
-      dj = double(det);
-    }
+    const double dj = WARP ? double(sDetU[le][s]) : sDet[le];
     val[k] = -double(acc) / dj;
   }
   rk_store_block<NL, NT>(sg, rk, e0, E, 5 * NU, EB * 5 * NU, tid, val);

@@ -47,10 +47,11 @@ Parity status (pins live in tests/test_oracle_*.py):
     conical-product rule against closed-form simplex moments, the node set's
     symmetry and unisolvence, the operator identities above, free stream,
     conservation and entropy-wave convergence (test_oracle_tet.py).
-  * curved hexahedra (Mesh kind "hex_warp": trilinear maps of a warped grid,
-    per-point metrics): free stream, conservation, the discrete metric
-    identity, equality with the affine mesh at zero warp and entropy-wave
-    convergence (test_oracle_curved.py).
+  * curved hexahedra and prisms (Mesh kinds "hex_warp", "prism_warp",
+    "mixed_warp": vertex maps of a warped grid, per-point metrics): free
+    stream, conservation, the discrete metric identity, equality with the
+    affine mesh at zero warp and entropy-wave convergence
+    (test_oracle_curved.py).
   * The full right-hand side at a perturbed state has no closed form; it is
     pinned only through the properties above.
 """

@@ -23,13 +23,17 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                  y faces are cut along the prisms' diagonal.
   kind "prism_tet" : prisms in cells whose centre has y < 0, tetrahedra
                  elsewhere (prism triangles meet tetrahedron faces).
-  kind "hex_warp" : curved (non-affine) hexahedra: every grid vertex x is
+  kinds "hex_warp", "prism_warp", "mixed_warp" : the curved (non-affine)
+                 forms of "hex", "prism" and "mixed": every grid vertex x is
                  moved to x + warp h (sin y cos z, sin z cos x, sin x cos y)
                  (h the cell size per axis, warp = 0.2 by default; the field
                  is periodic, so the mesh stays periodic and conforming) and
-                 each element is the trilinear map of its eight moved
-                 vertices, so its faces are bilinear (curved) surfaces and its
-                 metrics vary from point to point.  The cofactor metric terms
+                 each element is the map of its moved vertices with the
+                 element's vertex shape functions -- trilinear for a
+                 hexahedron (8 vertices), a triangle's barycentric functions
+                 times the line's for a prism (6 vertices) -- so quadrilateral
+                 faces are bilinear (curved) surfaces and the metrics vary
+                 from point to point.  The cofactor metric terms
                  det J J^-1 of a trilinear map are exact (no discrete metric
                  is formed); their normal components are bilinear on every
                  face, so the GL(n)^2 flux points interpolate them exactly,
@@ -54,6 +58,13 @@ face whose centroid is lexicographically smaller in (x, y, z).
 import numpy as np
 
 from .elements import RefElement
+
+
+# reference vertices of the curved element types, in shape-function order
+_REF_VERTS = {
+    "hex": np.array([[2 * a - 1, 2 * b - 1, 2 * c - 1] for c in range(2) for b in range(2) for a in range(2)], float),
+    "prism": np.array([[x, y, z] for z in (-1.0, 1.0) for (x, y) in ((-1.0, -1.0), (1.0, -1.0), (-1.0, 1.0))]),
+}
 
 
 def _kuhn_tets(x0, h):
@@ -83,10 +94,13 @@ class Mesh:
         self.period = np.array([L, L, L])
         h = np.array([L / nx, L / ny, L / nz])
         self.h = h
+        self.curved = kind.endswith("_warp")
+        if self.curved:
+            kind = kind[:-len("_warp")]
+            if kind not in ("hex", "prism", "mixed"):
+                raise ValueError("warped meshes: hex, prism or mixed")
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
-                 "prism_tet": ["prism", "tet"], "hex_warp": ["hex"]}[kind]
-        self.curved = kind == "hex_warp"
-        verts = []
+                 "prism_tet": ["prism", "tet"]}[kind]
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -113,22 +127,11 @@ class Mesh:
                             A["tet"].append(Jt)
                             gid["tet"].append(g)
                             g += 1
-                    elif ctype in ("hex", "hex_warp"):
+                    elif ctype == "hex":
                         org["hex"].append(x0 + 0.5 * h)
                         A["hex"].append(np.diag(0.5 * h))
                         gid["hex"].append(g)
                         g += 1
-                        if self.curved:
-                            # vertex a + 2 b + 4 c at x0 + h (a, b, c), moved
-                            X = []
-                            for c in range(2):
-                                for b in range(2):
-                                    for a in range(2):
-                                        x = x0 + h * np.array([a, b, c], dtype=float)
-                                        X.append(x + warp * h * np.array([np.sin(x[1]) * np.cos(x[2]),
-                                                                          np.sin(x[2]) * np.cos(x[0]),
-                                                                          np.sin(x[0]) * np.cos(x[1])]))
-                            verts.append(np.array(X))
                     else:
                         hx, hy, hz = 0.5 * h
                         # columns: d x / d(xi, eta, zeta)
@@ -146,14 +149,21 @@ class Mesh:
         self.gid = {t: np.array(gid[t]) for t in self.types}
         self.nelem = {t: len(self.org[t]) for t in self.types}
         if self.curved:
-            self.verts = {"hex": np.array(verts)}
-            r = self.refs["hex"]
-            self.detJ, self.Jinv = {}, {}
-            self.detJ["hex"], self.Jinv["hex"] = self.metrics("hex", r.upts)  # at the solution points
-            self.detJq, self.Jinvq = {}, {}
-            self.detJq["hex"], self.Jinvq["hex"] = self.metrics("hex", r.qpts)  # at the quadrature points
-            if np.any(self.metrics("hex", r.fpts)[0] <= 0) or np.any(self.detJq["hex"] <= 0):
-                raise ValueError("non-positive Jacobian")
+            # vertices: the affine images of the reference vertices (cell
+            # corners), moved by the warp field
+            self.verts = {}
+            for t in self.types:
+                V = self.org[t][:, None, :] + np.einsum("eij,vj->evi", self.J[t], _REF_VERTS[t])
+                self.verts[t] = V + warp * h * np.stack([np.sin(V[..., 1]) * np.cos(V[..., 2]),
+                                                         np.sin(V[..., 2]) * np.cos(V[..., 0]),
+                                                         np.sin(V[..., 0]) * np.cos(V[..., 1])], axis=-1)
+            self.detJ, self.Jinv, self.detJq, self.Jinvq = {}, {}, {}, {}
+            for t in self.types:
+                r = self.refs[t]
+                self.detJ[t], self.Jinv[t] = self.metrics(t, r.upts)  # at the solution points
+                self.detJq[t], self.Jinvq[t] = self.metrics(t, r.qpts)  # at the quadrature points
+                if np.any(self.metrics(t, r.fpts)[0] <= 0) or np.any(self.detJq[t] <= 0):
+                    raise ValueError("non-positive Jacobian")
         else:
             self.detJ = {t: np.linalg.det(self.J[t]) for t in self.types}
             self.Jinv = {t: np.linalg.inv(self.J[t]) for t in self.types}
@@ -162,25 +172,44 @@ class Mesh:
         self._pair()
 
     @staticmethod
-    def _trilinear(ref_pts):
-        """Shape functions N_v (npts, 8) and their gradients (npts, 8, 3) of
-        the trilinear map, vertex v = a + 2 b + 4 c at reference corner
-        (2a-1, 2b-1, 2c-1)."""
+    def _shape(t, ref_pts):
+        """Vertex shape functions N_v (npts, nv) and their gradients
+        (npts, nv, 3).  hex: trilinear, vertex v = a + 2b + 4c at reference
+        corner (2a-1, 2b-1, 2c-1).  prism: lambda_t(xi, eta) (1 -+ zeta)/2,
+        vertex v = t + 3c with lambda_0 = -(xi+eta)/2, lambda_1 = (1+xi)/2,
+        lambda_2 = (1+eta)/2 (triangle vertices (-1,-1), (1,-1), (-1,1)),
+        c = 0 at zeta = -1."""
         x = np.asarray(ref_pts, float)
-        s = np.array([[2 * a - 1, 2 * b - 1, 2 * c - 1] for c in range(2) for b in range(2) for a in range(2)], float)
-        f = 0.5 * (1.0 + x[:, None, :] * s[None, :, :])  # (npts, 8, 3)
-        N = f.prod(axis=2)
-        dN = np.empty(f.shape)
-        for d in range(3):
-            o = [k for k in range(3) if k != d]
-            dN[:, :, d] = 0.5 * s[None, :, d] * f[:, :, o[0]] * f[:, :, o[1]]
+        if t == "hex":
+            s = np.array([[2 * a - 1, 2 * b - 1, 2 * c - 1] for c in range(2) for b in range(2) for a in range(2)],
+                         float)
+            f = 0.5 * (1.0 + x[:, None, :] * s[None, :, :])  # (npts, 8, 3)
+            N = f.prod(axis=2)
+            dN = np.empty(f.shape)
+            for d in range(3):
+                o = [k for k in range(3) if k != d]
+                dN[:, :, d] = 0.5 * s[None, :, d] * f[:, :, o[0]] * f[:, :, o[1]]
+            return N, dN
+        lam = np.stack([-(x[:, 0] + x[:, 1]) / 2, (1 + x[:, 0]) / 2, (1 + x[:, 1]) / 2], axis=1)
+        dlam = np.array([[-0.5, -0.5], [0.5, 0.0], [0.0, 0.5]])
+        zf = np.stack([(1 - x[:, 2]) / 2, (1 + x[:, 2]) / 2], axis=1)
+        zs = np.array([-0.5, 0.5])
+        N = np.empty((len(x), 6))
+        dN = np.empty((len(x), 6, 3))
+        for c in range(2):
+            for tv in range(3):
+                v = tv + 3 * c
+                N[:, v] = lam[:, tv] * zf[:, c]
+                dN[:, v, 0] = dlam[tv, 0] * zf[:, c]
+                dN[:, v, 1] = dlam[tv, 1] * zf[:, c]
+                dN[:, v, 2] = lam[:, tv] * zs[c]
         return N, dN
 
     def metrics(self, t, ref_pts, elems=None):
         """det J (E, npts) and J^-1 (E, npts, 3, 3) at reference points
         (curved meshes; J[i][j] = d x_i / d xi_j)."""
         X = self.verts[t] if elems is None else self.verts[t][elems]
-        _, dN = self._trilinear(ref_pts)
+        _, dN = self._shape(t, ref_pts)
         J = np.einsum("evi,pvj->epij", X, dN)
         return np.linalg.det(J), np.linalg.inv(J)
 
@@ -188,7 +217,7 @@ class Mesh:
     def phys(self, t, ref_pts, elems=None):
         if self.curved:
             X = self.verts[t] if elems is None else self.verts[t][elems]
-            N, _ = self._trilinear(ref_pts)
+            N, _ = self._shape(t, ref_pts)
             return np.einsum("pv,evi->epi", N, X)
         org = self.org[t] if elems is None else self.org[t][elems]
         J = self.J[t] if elems is None else self.J[t][elems]

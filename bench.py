@@ -319,7 +319,8 @@ def main():
         ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
         ("fp64", 4, "fullaa", "hex"), ("fp32", 3, "fullaa", "prism"), ("fp32", 4, "fullaa", "prism"),
         ("fp32", 3, "fused", "tet"), ("fp64", 3, "fused", "tet"), ("fp32", 4, "fused", "tet"),
-        ("fp32", 3, "fused", "hex_warp"), ("fp64", 3, "fused", "hex_warp"), ("fp32", 4, "fused", "hex_warp")]
+        ("fp32", 3, "fused", "hex_warp"), ("fp64", 3, "fused", "hex_warp"), ("fp32", 4, "fused", "hex_warp"),
+        ("fp32", 3, "fused", "prism_warp"), ("fp32", 4, "fused", "prism_warp")]
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
         r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)

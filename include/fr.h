@@ -63,7 +63,9 @@ typedef enum {
   FR_MESH_MIXED = 2,      /* hexahedra where z < 0, prisms elsewhere */
   FR_MESH_TET = 3,        /* six tetrahedra per cell */
   FR_MESH_PRISM_TET = 4,  /* prisms where y < 0, tetrahedra elsewhere */
-  FR_MESH_HEX_WARP = 5    /* curved hexahedra on a warped grid */
+  FR_MESH_HEX_WARP = 5,   /* kinds 0, 1, 2 on a warped grid: curved elements */
+  FR_MESH_PRISM_WARP = 6,
+  FR_MESH_MIXED_WARP = 7
 } fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
@@ -135,13 +137,15 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * anti-aliasing (otherwise FR_EUNSUPPORTED).  Host-side only: device buffers
  * are allocated and uploaded by the first call that needs them.  Element
  * numbering: cells in index order i + nx(j + ny k); a prism cell yields two
- * elements, a tetrahedron cell six.  FR_MESH_HEX_WARP: curved (non-affine)
- * hexahedra; every grid vertex x moves to
+ * elements, a tetrahedron cell six.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,
+ * FR_MESH_MIXED_WARP: the hex, prism and mixed meshes with curved
+ * (non-affine) elements; every grid vertex x moves to
  * x + 0.2 h (sin y cos z, sin z cos x, sin x cos y) (h the cell size per
  * axis; periodic, so the mesh stays periodic and conforming) and each
- * element is the trilinear map of its moved vertices (bilinear, curved
- * faces).  The kernels evaluate its metrics at every point from the vertices
- * (fused form with flux anti-aliasing only).  Errors: FR_EINVAL (n < 1, hi <= lo,
+ * element is the map of its moved vertices by its vertex shape functions
+ * (trilinear for a hexahedron, triangle x line for a prism; bilinear, curved
+ * quadrilateral faces).  The kernels evaluate the metrics at every point
+ * from the vertices (fused form with flux anti-aliasing only).  Errors: FR_EINVAL (n < 1, hi <= lo,
  * unknown kind), FR_EUNSUPPORTED (p outside 1..4), FR_ESTATE (mesh already
  * built). */
 fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind);

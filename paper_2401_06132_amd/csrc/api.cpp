@@ -37,7 +37,7 @@ struct fr_ctx {
   double* d_detj[fr::NTYPES] = {nullptr, nullptr, nullptr};
   void* d_pops = nullptr;  // prism triangle tables
   void* d_tops = nullptr;  // tetrahedron operator tables
-  void* d_verts = nullptr; // curved hexahedra: element vertices [E][8][3]
+  void* d_verts[2] = {nullptr, nullptr};  // curved meshes: element vertices [E][nv][3]
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
 
@@ -229,11 +229,13 @@ fr_status ensure_device(fr_ctx* c) {
     HIPCHK(hipMalloc(&c->d_pops, nb));
     HIPCHK(hipMemcpy(c->d_pops, pb.data(), nb, hipMemcpyHostToDevice));
   }
-  if (M.curved) {
-    to_real(c, M.verts, buf);
-    HIPCHK(hipMalloc(&c->d_verts, buf.size()));
-    HIPCHK(hipMemcpy(c->d_verts, buf.data(), buf.size(), hipMemcpyHostToDevice));
-  }
+  if (M.curved)
+    for (int t = 0; t < 2; ++t) {
+      if (!c->has[t]) continue;
+      to_real(c, M.verts[t], buf);
+      HIPCHK(hipMalloc(&c->d_verts[t], buf.size()));
+      HIPCHK(hipMemcpy(c->d_verts[t], buf.data(), buf.size(), hipMemcpyHostToDevice));
+    }
   if (c->has[2]) {
     size_t nb = fr::tet_ops_bytes(c->p, c->ph.prec);
     std::vector<unsigned char> pb(nb);
@@ -265,7 +267,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.E = (int32_t)c->M.nel[t];
   s.slot_base = (int32_t)c->M.slot_base[t];
   s.nperm = (int32_t)c->M.perms.size();
-  s.verts = t == 0 ? c->d_verts : nullptr;
+  s.verts = t < 2 ? c->d_verts[t] : nullptr;
   return s;
 }
 
@@ -276,7 +278,7 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
   a.diag = c->diag[t];
   a.one = s;
   a.dops = t == 2 ? c->d_tops : c->d_pops;
-  a.warp = c->M.curved && t == 0;
+  a.warp = c->M.curved && t < 2;
   a.ops = &c->hops[t];
   a.gas = &c->gas;
   return a;
@@ -354,8 +356,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   const bool tets = kind == FR_MESH_TET || kind == FR_MESH_PRISM_TET;
   if (tets && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
     return fail(c, FR_EUNSUPPORTED, "tetrahedra: fused form with flux anti-aliasing only");
-  if (kind == FR_MESH_HEX_WARP && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
-    return fail(c, FR_EUNSUPPORTED, "curved hexahedra: fused form with flux anti-aliasing only");
+  if (fr::kind_curved(kind) && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
+    return fail(c, FR_EUNSUPPORTED, "curved elements: fused form with flux anti-aliasing only");
   try {
     c->p = p;
     for (int t = 0; t < fr::NTYPES; ++t) fr::build_ref(t, p, c->ref[t]);
@@ -518,7 +520,7 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
       const double* ue = &u[c->off[t] + e * 5 * r.nu];
       // det J at every solution point (constant for affine elements)
       std::vector<double> dj(r.nu, c->M.detj[t][e]);
-      if (c->M.curved && t == 0)
+      if (c->M.curved && t < 2)
         for (int q = 0; q < r.nu; ++q) {
           double J[9];
           fr::jac_point(c->M, t, e, &r.upts[3 * q], J);
@@ -613,7 +615,7 @@ void fr_destroy(fr_ctx* c) {
     (void)hipStreamSynchronize(c->st);
     void* bufs[] = {c->d_state, c->d_rk, c->d_Uf, c->d_Vf, c->d_Rp, c->d_fgeo, c->d_faces, c->d_perms,
                     c->d_met[0], c->d_met[1], c->d_met[2], c->d_detj[0], c->d_detj[1], c->d_detj[2],
-                    c->d_pops, c->d_tops, c->d_verts};
+                    c->d_pops, c->d_tops, c->d_verts[0], c->d_verts[1]};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }

@@ -74,8 +74,9 @@ void build_ref(int etype, int p, RefElem& r);
 constexpr int NTYPES = 3;
 constexpr int kFacesOf[NTYPES] = {6, 5, 4};
 // box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
-// 4 prism (y < 0) + tet, 5 curved hexahedra (warped grid)
-constexpr int kNumKinds = 6;
+// 4 prism (y < 0) + tet; 5, 6, 7: kinds 0, 1, 2 on the warped grid (curved)
+constexpr int kNumKinds = 8;
+inline bool kind_curved(int kind) { return kind >= 5 && kind <= 7; }
 // vertex displacement of the warped grid, in cell sizes
 constexpr double kWarp = 0.2;
 
@@ -95,11 +96,13 @@ struct Mesh {
   std::vector<int64_t> nbr_slot;  // paired slot
   std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]
   std::vector<uint8_t> is_left;
-  // curved hexahedra: the eight vertices of every element ([E][8][3], vertex
-  // a + 2b + 4c at reference corner (2a-1, 2b-1, 2c-1)); the element is
-  // their trilinear map (jac/jinv/detj then hold the undeformed cell's)
+  // curved meshes: the vertices of every element, [E][nv][3] per type
+  // (hexahedra: 8, vertex a + 2b + 4c at reference corner (2a-1, 2b-1, 2c-1),
+  // trilinear map; prisms: 6, vertex t + 3c at triangle vertex t of
+  // (-1,-1), (1,-1), (-1,1) and zeta = 2c-1, map lambda_t(xi, eta)(1 -+ zeta)/2);
+  // jac/jinv/detj then hold the undeformed element's
   bool curved = false;
-  std::vector<double> verts;
+  std::vector<double> verts[NTYPES];
   std::vector<double> nrm;        // per slot: L-side physical unit normal (3)
   std::vector<double> mag;        // per slot: the slot's own area factor |det J J^-T n|
   std::vector<std::vector<int>> perms;

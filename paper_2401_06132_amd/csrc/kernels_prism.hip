@@ -28,6 +28,7 @@ struct PrismOps {
   // line factors (kernel argument)
   R I[m][n], D[n][n], Pj[n][m], AP[n][m];
   R lb[n], rb[n], liftL[n], liftR[n];
+  R x[n], xq[m];  // GL(n) solution and GL(m) quadrature nodes
 };
 
 template <int P, typename R>
@@ -38,7 +39,42 @@ struct PrismTri {
   R PT[NT][NTQ], APxi[NT][NTQ], APeta[NT][NTQ];
   R Tedge[3][n][NT];          // nodal basis at the GL points of each edge
   R LiftEdge[3][NT][n];       // DG lifting of an edge point into the plane
+  R nodes[NT][2], qp[NTQ][2];  // triangle nodes and conical quadrature points
 };
+
+// Curved prisms: the map of the six vertices X (vertex t + 3c at triangle
+// vertex t of (-1,-1), (1,-1), (-1,1) and zeta = 2c - 1) by
+// lambda_t(xi, eta) (1 -+ zeta)/2.  At reference point (xi, eta, zeta): the
+// columns J_c = dx/dxi_c, the cofactor rows S_d = J_{d+1} x J_{d+2}
+// (S = det J J^-1) and det J = J_0 . S_0.
+template <typename R>
+__device__ __forceinline__ void wedge_metric(const R* X, R xi, R eta, R zeta, R S[3][3], R& det) {
+  const R zm = R(0.5) * (R(1) - zeta), zp = R(0.5) * (R(1) + zeta);
+  const R l0 = -R(0.5) * (xi + eta), l1 = R(0.5) * (R(1) + xi), l2 = R(0.5) * (R(1) + eta);
+  R J[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    J[0][i] = R(0.5) * (zm * (X[3 + i] - X[i]) + zp * (X[12 + i] - X[9 + i]));
+    J[1][i] = R(0.5) * (zm * (X[6 + i] - X[i]) + zp * (X[15 + i] - X[9 + i]));
+    J[2][i] = R(0.5) * (l0 * (X[9 + i] - X[i]) + l1 * (X[12 + i] - X[3 + i]) + l2 * (X[15 + i] - X[6 + i]));
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const R* a = J[(d + 1) % 3];
+    const R* b = J[(d + 2) % 3];
+    S[d][0] = a[1] * b[2] - a[2] * b[1];
+    S[d][1] = a[2] * b[0] - a[0] * b[2];
+    S[d][2] = a[0] * b[1] - a[1] * b[0];
+  }
+  det = J[0][0] * S[0][0] + J[0][1] * S[0][1] + J[0][2] * S[0][2];
+}
+
+// reference coordinates (xi, eta) of GL point s along edge e (counter-clockwise)
+template <typename R>
+__device__ __forceinline__ void edge_point(int e, R s, R& xi, R& eta) {
+  xi = e == 0 ? s : (e == 1 ? -s : R(-1));
+  eta = e == 0 ? R(-1) : (e == 1 ? s : -s);
+}
 
 template <int P>
 struct PrismCfg {
@@ -190,7 +226,7 @@ __device__ __forceinline__ double pair_sum(double x) {
 // (M_T the triangle mass matrix; lifting the projection reproduces the
 // quadrature-point lifting because the rule integrates M_T exactly) and
 // P x P on a quadrilateral.
-template <int P, typename R, int EB, int NT_, bool BT, bool AA, bool SAA>
+template <int P, typename R, int EB, int NT_, bool BT, bool AA, bool SAA, bool WARP>
 __global__ void __launch_bounds__(NT_)
     prism_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g, const Gas<R> g,
@@ -246,6 +282,14 @@ __global__ void __launch_bounds__(NT_)
     for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
   }
   for (int it = tid; it < sg.nperm * NFP; it += NT_) sPerm[it] = perms[it];
+  __shared__ R sV[WARP ? EB : 1][18];  // curved: element vertices
+  if constexpr (WARP) {
+    const R* __restrict__ vx = (const R*)sg.verts;
+    for (int it = tid; it < EB * 18; it += NT_) {
+      const int le = it / 18;
+      sV[le][it - le * 18] = vx[e0 + le < E ? (size_t)e0 * 18 + it : 0];
+    }
+  }
   for (int it = tid; it < EB * 10; it += NT_) {
     const int le = it / 10, k = it - le * 10, e = e0 + le;
     sMet[le][k] = met[e < E ? (size_t)e * 10 + k : 0];
@@ -425,12 +469,27 @@ __global__ void __launch_bounds__(NT_)
   for (int it = tid; it < EB * NU; it += NT_) {
     const int le = it / NU, s = it - le * NU;
     R* X = XS(le);
+    R M[3][3];  // M[d][c] = (J^-1)_{dc}
+    if constexpr (WARP) {
+      const int t = s % NTN, k = s / NTN;
+      R S[3][3], det;
+      wedge_metric(&sV[le][0], tri.nodes[t][0], tri.nodes[t][1], psel(op.x, k), S, det);
+      const R id = R(1) / det;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[d][c] = S[d][c] * id;
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[d][c] = sMet[le][3 * d + c];
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+      for (int c = 0; c < 3; ++c) X[(5 + c * 5 + v) * NU + s] = M[0][c] * g0 + M[1][c] * g1 + M[2][c] * g2;
     }
   }
   lds_barrier();
@@ -633,8 +692,19 @@ __global__ void __launch_bounds__(NT_)
       for (int side = 0; side < 2; ++side) {
         const R* w = side ? fp : fm;
         const int lf = le * 5 + side, slot = slot_base + e * 5 + side;
-        const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
-        const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+        R nn[3];
+        if constexpr (WARP) {
+          // own outward unit normal: +-S_zeta / |S_zeta| at the triangle node
+          R S[3][3], det;
+          wedge_metric(&sV[le][0], tri.nodes[t][0], tri.nodes[t][1], side ? R(1) : R(-1), S, det);
+          const R im = rcp(sqrt(S[2][0] * S[2][0] + S[2][1] * S[2][1] + S[2][2] * S[2][2]));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) nn[c] = (side ? im : -im) * S[2][c];
+        } else {
+          const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) nn[c] = sgn * sFG[lf][c];
+        }
         R u[5], q[3][5], V[4];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -649,8 +719,24 @@ __global__ void __launch_bounds__(NT_)
     } else {
       const int r1 = r0 - NV_TRI, ed = r1 / (n * n), r2 = r1 - ed * (n * n), k = r2 / n, i = r2 - k * n;
       const int lf = le * 5 + 2 + ed, slot = slot_base + e * 5 + 2 + ed;
-      const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
-      const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+      R nn[3];
+      if constexpr (WARP) {
+        // own outward unit normal: (nx S_xi + ny S_eta) normalised at the edge point
+        R xi, eta, nx, ny, S[3][3], det;
+        edge_point(ed, psel(op.x, i), xi, eta);
+        edge_normal<R>(ed, nx, ny);
+        wedge_metric(&sV[le][0], xi, eta, psel(op.x, k), S, det);
+        R vv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vv[c] = nx * S[0][c] + ny * S[1][c];
+        const R im = rcp(sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nn[c] = im * vv[c];
+      } else {
+        const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nn[c] = sgn * sFG[lf][c];
+      }
       R u[5], q[3][5], V[4];
 #pragma unroll
       for (int fld = 0; fld < 20; ++fld) {
@@ -870,6 +956,7 @@ __global__ void __launch_bounds__(NT_)
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[cle][3 * d + c];
+    const R cqx = WARP ? tri.qp[ctq][0] : R(0), cqy = WARP ? tri.qp[ctq][1] : R(0);
     // thread `half` takes zeta level kq = 2j + half; the operator entries are
     // selected per lane (no divergent branch); for odd m the surplus level of
     // the odd thread repeats level 2j with zero projection weights
@@ -896,6 +983,10 @@ __global__ void __launch_bounds__(NT_)
           q[(fld - 5) / 5][(fld - 5) % 5] = s;
       }
       point_flux(u, q, g, f);
+      if constexpr (WARP) {
+        R det;
+        wedge_metric(&sV[cle][0], cqx, cqy, half ? op.xq[k1] : op.xq[k0], S, det);  // det J J^-1 here
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -969,7 +1060,7 @@ __global__ void __launch_bounds__(NT_)
 // quadrilaterals).  The triangle rule is not symmetric, so both sides of a
 // triangle face must see the same nodes: the library requires the identity
 // point permutation there.
-template <int P, typename R, int EB, int NT_, bool BT, bool SAA>
+template <int P, typename R, int EB, int NT_, bool BT, bool SAA, bool WARP>
 __global__ void __launch_bounds__(NT_)
     prism_surface(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const int rk,
                   const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri, const Gas<R> g) {
@@ -991,6 +1082,8 @@ __global__ void __launch_bounds__(NT_)
   __shared__ R sPj[SAA ? n : 1][m];
   __shared__ R sFG[SAA ? EB * 5 : 1][4];
   __shared__ int sInfo[SAA ? EB * 5 : 1];
+  __shared__ R sV[WARP ? EB : 1][18];              // curved: element vertices
+  __shared__ R sDetU[WARP ? EB : 1][WARP ? NU : 1];  // curved: det J at the solution points
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -1004,6 +1097,14 @@ __global__ void __launch_bounds__(NT_)
   const int fnp[5] = {NT, NT, NFP, NFP, NFP};
   // edge lifting table, staged in LDS for the per-point lift below
   for (int it = tid; it < 3 * NT * n; it += NT_) (&sLift[0][0][0])[it] = (&tri->LiftEdge[0][0][0])[it];
+  if constexpr (WARP) {
+    const R* __restrict__ vx = (const R*)sg.verts;
+    for (int it = tid; it < EB * 18; it += NT_) {
+      const int le = it / 18;
+      sV[le][it - le * 18] = vx[e0 + le < E ? (size_t)e0 * 18 + it : 0];
+    }
+    __syncthreads();
+  }
   if constexpr (SAA) {
     for (int it = tid; it < NTQ * NT; it += NT_) {
       (&sTq[0][0])[it] = (&tri->Tq[0][0])[it];
@@ -1034,8 +1135,29 @@ __global__ void __launch_bounds__(NT_)
       Vo[k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
       Vn[k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
     }
-    const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
-    const R mag = fgeo[4 * slot + 3];
+    R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
+    R mag = fgeo[4 * slot + 3];
+    if constexpr (WARP) {
+      // own area factor and outward normal at this flux point; the L side's
+      // normal is the opposite of the R side's own
+      R S[3][3], det, vv[3];
+      if (f < 2) {
+        wedge_metric(&sV[le][0], tri->nodes[r][0], tri->nodes[r][1], f ? R(1) : R(-1), S, det);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vv[c] = f ? S[2][c] : -S[2][c];
+      } else {
+        R xi, eta, nx, ny;
+        edge_point(f - 2, psel(op.x, r % n), xi, eta);
+        edge_normal<R>(f - 2, nx, ny);
+        wedge_metric(&sV[le][0], xi, eta, psel(op.x, r / n), S, det);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vv[c] = nx * S[0][c] + ny * S[1][c];
+      }
+      mag = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+      const R im = left ? rcp(mag) : -rcp(mag);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nL[c] = im * vv[c];
+    }
     if constexpr (SAA) {
       if (left)
         linear_flux(uo, un, Vo, Vn, g, F);
@@ -1179,6 +1301,14 @@ __global__ void __launch_bounds__(NT_)
       }
     }
   }
+  if constexpr (WARP) {
+    for (int it = tid; it < EB * NU; it += NT_) {
+      const int le = it / NU, s = it - le * NU;
+      R S[3][3], det;
+      wedge_metric(&sV[le][0], tri->nodes[s % NT][0], tri->nodes[s % NT][1], psel(op.x, s / NT), S, det);
+      sDetU[le][s] = det;
+    }
+  }
   __syncthreads();
   // tdivtconf + negdivconf, one output point per thread (coalesced state
   // and residual access)
@@ -1192,7 +1322,7 @@ __global__ void __launch_bounds__(NT_)
     for (int ed = 0; ed < 3; ++ed)
 #pragma unroll
       for (int i = 0; i < n; ++i) acc += sLift[ed][t][i] * D[(2 + ed) * 5 * NFP + i + n * k];
-    rk_store(sg, rk, (size_t)e * 5 * NU + r0, -double(acc) / detj[e]);
+    rk_store(sg, rk, (size_t)e * 5 * NU + r0, -double(acc) / (WARP ? double(sDetU[le][s]) : detj[e]));
   }
 }
 
@@ -1215,7 +1345,9 @@ static PrismOps<P, R> make_prism_ops(const HostOps& h) {
     o.rb[i] = R(h.rb[i]);
     o.liftL[i] = R(h.liftL[i]);
     o.liftR[i] = R(h.liftR[i]);
+    o.x[i] = R(h.x[i]);
   }
+  for (int a = 0; a < m; ++a) o.xq[a] = R(h.xq[a]);
   return o;
 }
 
@@ -1241,6 +1373,10 @@ static void pack_tri(const Tri& T, PrismTri<P, R>* o) {
     for (int t = 0; t < NT; ++t)
       for (int i = 0; i < n; ++i) o->LiftEdge[e][t][i] = R(T.LiftEdge[(e * NT + t) * n + i]);
   }
+  for (int t = 0; t < NT; ++t)
+    for (int d = 0; d < 2; ++d) o->nodes[t][d] = R(T.nodes[2 * t + d]);
+  for (int q = 0; q < NTQ; ++q)
+    for (int d = 0; d < 2; ++d) o->qp[q][d] = R(T.qp[2 * q + d]);
 }
 
 size_t prism_ops_bytes(int p, int prec) {
@@ -1314,25 +1450,37 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
                        a.segs, a.from_ust, op, tri, eref);
+  // curved prisms (single meshes only; flux anti-aliasing, general metric)
+  if constexpr (!BT) {
+    if (a.warp) {
+      if ((a.stage & 2) && grid[K_VOLUME] > 0)
+        hipLaunchKernelGGL((prism_volume<P, R, EB, NT, false, true, false, true>), dim3(grid[K_VOLUME]), dim3(NT), 0,
+                           st, a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+      if ((a.stage & 4) && grid[K_SURFACE] > 0)
+        hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, false, false, true>), dim3(grid[K_SURFACE]), dim3(NTC), 0,
+                           st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
+      return;
+    }
+  }
   if ((a.stage & 2) && grid[K_VOLUME] > 0) {
     // surface-flux anti-aliasing is built together with flux anti-aliasing
     // only (the paper's "full AA"); the library rejects it without
     if (a.saa)
-      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, true>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, true, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
                          a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
     else if (a.aa)
-      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
                          a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
     else
-      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st,
+      hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st,
                          a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
   }
   if ((a.stage & 4) && grid[K_SURFACE] > 0) {
     if (a.saa)
-      hipLaunchKernelGGL((prism_surface<P, R, PrismSurf<P, dbl, true>::EB, NTC, BT, true>), dim3(grid[K_SURFACE]),
+      hipLaunchKernelGGL((prism_surface<P, R, PrismSurf<P, dbl, true>::EB, NTC, BT, true, false>), dim3(grid[K_SURFACE]),
                          dim3(NTC), 0, st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
     else
-      hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT, false>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
+      hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, BT, false, false>), dim3(grid[K_SURFACE]), dim3(NTC), 0, st, a.one,
                          a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
   }
 }

@@ -70,7 +70,8 @@ static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kin
     const double hy = (hi - lo) / ny;
     return (lo + j * hy) + 0.5 * hy < 0.0 ? 1 : 2;
   }
-  return kind == 3 ? 2 : (kind == 5 ? 0 : kind);
+  if (kind == 7) return cell_type(j, k, ny, nz, lo, hi, 2);
+  return kind == 3 ? 2 : (kind >= 5 ? kind - 5 : kind);
 }
 
 static constexpr int kPerCell[NTYPES] = {1, 2, 6};
@@ -110,15 +111,41 @@ static void kuhn_tets(const double x0[3], const double h[3], double P[6][4][3]) 
   }
 }
 
-void map_point(const Mesh& m, int t, int64_t e, const double* xi, double* x) {
-  if (m.curved && t == 0) {
-    const double* X = &m.verts[24 * e];
-    for (int d = 0; d < 3; ++d) x[d] = 0;
+// vertex shape functions and their gradients (see Mesh::verts)
+static int vertex_shape(int t, const double* xi, double* N, double (*dN)[3]) {
+  if (t == 0) {
     for (int v = 0; v < 8; ++v) {
-      const double w = 0.125 * (1 + (v & 1 ? xi[0] : -xi[0])) * (1 + (v & 2 ? xi[1] : -xi[1])) *
-                       (1 + (v & 4 ? xi[2] : -xi[2]));
-      for (int d = 0; d < 3; ++d) x[d] += w * X[3 * v + d];
+      const double s[3] = {v & 1 ? 1.0 : -1.0, v & 2 ? 1.0 : -1.0, v & 4 ? 1.0 : -1.0};
+      const double f[3] = {0.5 * (1 + s[0] * xi[0]), 0.5 * (1 + s[1] * xi[1]), 0.5 * (1 + s[2] * xi[2])};
+      N[v] = f[0] * f[1] * f[2];
+      dN[v][0] = 0.5 * s[0] * f[1] * f[2];
+      dN[v][1] = 0.5 * f[0] * s[1] * f[2];
+      dN[v][2] = 0.5 * f[0] * f[1] * s[2];
     }
+    return 8;
+  }
+  const double lam[3] = {-(xi[0] + xi[1]) / 2, (1 + xi[0]) / 2, (1 + xi[1]) / 2};
+  const double dl[3][2] = {{-0.5, -0.5}, {0.5, 0.0}, {0.0, 0.5}};
+  for (int c = 0; c < 2; ++c)
+    for (int tv = 0; tv < 3; ++tv) {
+      const int v = tv + 3 * c;
+      const double zf = c ? 0.5 * (1 + xi[2]) : 0.5 * (1 - xi[2]);
+      N[v] = lam[tv] * zf;
+      dN[v][0] = dl[tv][0] * zf;
+      dN[v][1] = dl[tv][1] * zf;
+      dN[v][2] = lam[tv] * (c ? 0.5 : -0.5);
+    }
+  return 6;
+}
+
+void map_point(const Mesh& m, int t, int64_t e, const double* xi, double* x) {
+  if (m.curved && t < 2) {
+    double N[8], dN[8][3];
+    const int nv = vertex_shape(t, xi, N, dN);
+    const double* X = &m.verts[t][3 * nv * e];
+    for (int d = 0; d < 3; ++d) x[d] = 0;
+    for (int v = 0; v < nv; ++v)
+      for (int d = 0; d < 3; ++d) x[d] += N[v] * X[3 * v + d];
     return;
   }
   const double* A = &m.jac[t][9 * e];
@@ -127,16 +154,14 @@ void map_point(const Mesh& m, int t, int64_t e, const double* xi, double* x) {
 }
 
 void jac_point(const Mesh& m, int t, int64_t e, const double* xi, double J[9]) {
-  if (m.curved && t == 0) {
-    const double* X = &m.verts[24 * e];
+  if (m.curved && t < 2) {
+    double N[8], dN[8][3];
+    const int nv = vertex_shape(t, xi, N, dN);
+    const double* X = &m.verts[t][3 * nv * e];
     for (int k = 0; k < 9; ++k) J[k] = 0;
-    for (int v = 0; v < 8; ++v) {
-      const double s[3] = {v & 1 ? 1.0 : -1.0, v & 2 ? 1.0 : -1.0, v & 4 ? 1.0 : -1.0};
-      const double f[3] = {1 + s[0] * xi[0], 1 + s[1] * xi[1], 1 + s[2] * xi[2]};
-      const double dN[3] = {0.125 * s[0] * f[1] * f[2], 0.125 * f[0] * s[1] * f[2], 0.125 * f[0] * f[1] * s[2]};
+    for (int v = 0; v < nv; ++v)
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) J[3 * i + j] += dN[j] * X[3 * v + i];
-    }
+        for (int j = 0; j < 3; ++j) J[3 * i + j] += dN[v][j] * X[3 * v + i];
     return;
   }
   for (int k = 0; k < 9; ++k) J[k] = m.jac[t][9 * e + k];
@@ -178,15 +203,6 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
           double J[9] = {0.5 * h[0], 0, 0, 0, 0.5 * h[1], 0, 0, 0, 0.5 * h[2]};
           M.jac[0].insert(M.jac[0].end(), J, J + 9);
           M.gid[0].push_back(g++);
-          if (kind == 5) {
-            // warped grid: x + w h (sin y cos z, sin z cos x, sin x cos y)
-            for (int v = 0; v < 8; ++v) {
-              const double x[3] = {x0[0] + h[0] * (v & 1), x0[1] + h[1] * ((v >> 1) & 1), x0[2] + h[2] * (v >> 2)};
-              M.verts.push_back(x[0] + kWarp * h[0] * std::sin(x[1]) * std::cos(x[2]));
-              M.verts.push_back(x[1] + kWarp * h[1] * std::sin(x[2]) * std::cos(x[0]));
-              M.verts.push_back(x[2] + kWarp * h[2] * std::sin(x[0]) * std::cos(x[1]));
-            }
-          }
         } else {
           for (int s = 0; s < 2; ++s) {
             double sg = s ? -1.0 : 1.0;
@@ -197,19 +213,41 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
           }
         }
       }
-  M.curved = kind == 5;
+  M.curved = kind_curved(kind);
   if (M.curved) {
-    // the trilinear maps must keep a positive Jacobian at the corners and centre
-    for (int64_t e = 0; e < (int64_t)M.gid[0].size(); ++e)
-      for (int k = 0; k < 9; ++k) {
-        const double xi[3] = {k < 8 ? (k & 1 ? 1.0 : -1.0) : 0.0, k < 8 ? (k & 2 ? 1.0 : -1.0) : 0.0,
-                              k < 8 ? (k & 4 ? 1.0 : -1.0) : 0.0};
-        double J[9];
-        jac_point(M, 0, e, xi, J);
-        const double d = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
-                         J[2] * (J[3] * J[7] - J[4] * J[6]);
-        if (!(d > 0)) return "non-positive Jacobian";
-      }
+    // vertices: the affine images of the reference vertices (cell corners),
+    // moved by the warp field x + w h (sin y cos z, sin z cos x, sin x cos y)
+    static const double kRefV[2][8][3] = {
+        {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}, {1, 1, 1}},
+        {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}, {0, 0, 0}, {0, 0, 0}}};
+    for (int t = 0; t < 2; ++t) {
+      const int nv = t == 0 ? 8 : 6;
+      const int64_t E = (int64_t)M.gid[t].size();
+      M.verts[t].resize(3 * nv * E);
+      for (int64_t e = 0; e < E; ++e)
+        for (int v = 0; v < nv; ++v) {
+          const double* A = &M.jac[t][9 * e];
+          const double* o = &M.org[t][3 * e];
+          const double* xi = kRefV[t][v];
+          double x[3];
+          for (int d = 0; d < 3; ++d) x[d] = o[d] + A[3 * d] * xi[0] + A[3 * d + 1] * xi[1] + A[3 * d + 2] * xi[2];
+          double* X = &M.verts[t][3 * (nv * e + v)];
+          X[0] = x[0] + kWarp * h[0] * std::sin(x[1]) * std::cos(x[2]);
+          X[1] = x[1] + kWarp * h[1] * std::sin(x[2]) * std::cos(x[0]);
+          X[2] = x[2] + kWarp * h[2] * std::sin(x[0]) * std::cos(x[1]);
+        }
+      // the maps must keep a positive Jacobian at the vertices and centre
+      for (int64_t e = 0; e < E; ++e)
+        for (int k = 0; k <= nv; ++k) {
+          const double c0[3] = {0, 0, 0}, cp[3] = {-1.0 / 3.0, -1.0 / 3.0, 0};
+          const double* xi = k < nv ? kRefV[t][k] : (t == 0 ? c0 : cp);
+          double J[9];
+          jac_point(M, t, e, xi, J);
+          const double d = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                           J[2] * (J[3] * J[7] - J[4] * J[6]);
+          if (!(d > 0)) return "non-positive Jacobian";
+        }
+    }
   }
   for (int t = 0; t < NTYPES; ++t) {
     M.nel[t] = (int64_t)M.gid[t].size();

@@ -282,7 +282,7 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (!q) return pfail(P, FR_EINVAL, "null request");
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind >= fr::kNumKinds)
     return pfail(P, FR_EINVAL, "bad mesh size");
-  if (q->kind == FR_MESH_TET || q->kind == FR_MESH_PRISM_TET || q->kind == FR_MESH_HEX_WARP)
+  if (q->kind == FR_MESH_TET || q->kind == FR_MESH_PRISM_TET || fr::kind_curved(q->kind))
     return pfail(P, FR_EUNSUPPORTED, "the pool serves affine hexahedra and prisms");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");

@@ -324,20 +324,24 @@ def test_tet_free_stream_conservation_and_rk4(kind):
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())
 
 
-WARP_CASES = [((3, 3, 3), 3), ((2, 3, 2), 1), ((3, 2, 4), 2), ((2, 3, 3), 4), ((5, 1, 2), 3), ((4, 4, 4), 3)]
+WARP_CASES = [((3, 3, 3), 3, "hex_warp"), ((2, 3, 2), 1, "hex_warp"), ((3, 2, 4), 2, "hex_warp"),
+              ((2, 3, 3), 4, "hex_warp"), ((5, 1, 2), 3, "hex_warp"), ((4, 4, 4), 3, "hex_warp"),
+              ((2, 2, 2), 3, "prism_warp"), ((3, 2, 2), 1, "prism_warp"), ((2, 3, 1), 2, "prism_warp"),
+              ((2, 2, 2), 4, "prism_warp"), ((2, 2, 4), 3, "mixed_warp"), ((3, 2, 2), 4, "mixed_warp"),
+              ((2, 1, 2), 2, "mixed_warp")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("dims,p", WARP_CASES)
-def test_rhs_parity_curved_hexahedra(dims, p, prec):
-    """Curved hexahedra (trilinear maps of a warped grid; the kernels form the
-    metrics at every point from the vertices) against the oracle's per-point
-    metrics; same tolerances."""
+@pytest.mark.parametrize("dims,p,kind", WARP_CASES)
+def test_rhs_parity_curved_elements(dims, p, kind, prec):
+    """Curved hexahedra and prisms (vertex maps of a warped grid; the kernels
+    form the metrics at every point from the vertices) against the oracle's
+    per-point metrics; same tolerances."""
     _need_gpu()
-    print("warp case", dims, p, prec, flush=True)
-    m, U = _case(dims, p, "hex_warp")
+    print("warp case", dims, p, kind, prec, flush=True)
+    m, U = _case(dims, p, kind)
     r64, rld = _references(m, U)
-    got, _ = _gpu_rhs(dims, p, "hex_warp", prec, U)
+    got, _ = _gpu_rhs(dims, p, kind, prec, U)
     err = _rel_err(got, rld).astype(np.float64)
     own = _rel_err(r64, rld).astype(np.float64)
     tol = TOL[prec]
@@ -347,28 +351,29 @@ def test_rhs_parity_curved_hexahedra(dims, p, prec):
     assert np.all(err < tol), (err, tol)
 
 
-def test_curved_free_stream_conservation_and_rk4():
+@pytest.mark.parametrize("kind", ["hex_warp", "mixed_warp"])
+def test_curved_free_stream_conservation_and_rk4(kind):
     _need_gpu()
     dims, p = (3, 2, 3), 3
-    s = frmi.Solver(dims, p, "hex_warp", pref=inputs.P0)
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
     du = torch.empty_like(u)
     s.rhs(u, du)
     assert du.abs().max().item() < 1e-12 * 72 * 10
-    m, U = _case(dims, p, "hex_warp")
-    Uo = {"hex": U[0]}
+    m, U = _case(dims, p, kind)
+    Uo = {t: x for t, x in zip(m.types, U)}
     for _ in range(3):
         Uo = oracle_rk4(m, Uo, Params(pref=inputs.P0), 1e-3)
-    s.set_state(U[0])
+    s.set_state(np.concatenate([x.reshape(-1) for x in U]))
     c0 = s.integrals()
-    want0 = np.einsum("eu,u,evu->v", m.detJ["hex"], m.refs["hex"].wu, U[0])
+    want0 = sum(np.einsum("eu,u,evu->v", m.detJ[t], m.refs[t].wu, x) for t, x in zip(m.types, U))
     assert np.allclose(c0, want0, rtol=1e-13, atol=1e-13 * np.abs(want0).max())
     s.rk4(1e-3, 3)
-    got = s.split(s.get_state())[0]
-    d_ref = Uo["hex"] - U[0]
-    err = np.abs((got - U[0]) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
-    print("curved rk4 rel err of the state change", err)
-    assert np.all(err < 1e-11)
+    for got, t, x in zip(s.split(s.get_state()), m.types, U):
+        d_ref = Uo[t] - x
+        err = np.abs((got - x) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
+        print("curved rk4 rel err of the state change", t, err)
+        assert np.all(err < 1e-11)
     c1 = s.integrals()
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())

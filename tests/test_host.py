@@ -48,7 +48,7 @@ def test_reference_operators_match_oracle(etype, name, p):
         np.testing.assert_allclose(got, ref, atol=5e-14 * scale, err_msg=key)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp", "prism_warp", "mixed_warp"])
 def test_mesh_coordinates_and_connectivity_match_oracle(kind):
     _lib_or_skip()
     dims = (3, 2, 4)

@@ -133,8 +133,9 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * FR_MESH_PRISM_TET (prisms where the cell centre has y < 0, tetrahedra
  * elsewhere; prism triangles meet tetrahedron faces).  Tetrahedra have no
  * tensor-product structure (the paper's factorisation does not apply) and
- * run on dense-operator kernels; they are built for the fused form with flux
- * anti-aliasing (otherwise FR_EUNSUPPORTED).  Host-side only: device buffers
+ * run on dense-operator kernels; they support the fused form with or without
+ * flux anti-aliasing and the plain form, but not surface-flux anti-aliasing
+ * (FR_EUNSUPPORTED).  Host-side only: device buffers
  * are allocated and uploaded by the first call that needs them.  Element
  * numbering: cells in index order i + nx(j + ny k); a prism cell yields two
  * elements, a tetrahedron cell six.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,

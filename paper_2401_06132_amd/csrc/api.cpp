@@ -88,10 +88,11 @@ fr_status setup_plain(fr_ctx* c) {
   P->gas.beta = c->ph.ldg_beta;
   P->gas.tau = c->ph.ldg_tau;
   int64_t nftot = 0, nqmax = 0;
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
     P->ty.E[t] = M.nel[t];
     P->ty.nf[t] = c->ref[t].nf;
     P->ty.off_f[t] = 5 * nftot;
+    P->ty.f0[t] = nftot;
     nftot += M.nel[t] * c->ref[t].nf;
     P->state_off[t] = c->off[t];
     if (!c->has[t]) continue;
@@ -115,16 +116,22 @@ fr_status setup_plain(fr_ctx* c) {
   // per flux point neighbour records and L-side normals (the paper's n^(f))
   std::vector<fr::PlainFace> pf(nftot);
   std::vector<double> geo(4 * nftot);
-  const int nfc[2] = {6, 5};
-  int64_t base[2] = {0, M.nel[0] * c->ref[0].nf};
+  int64_t base[fr::NTYPES];
+  for (int t = 0; t < fr::NTYPES; ++t) base[t] = P->ty.f0[t];
+  auto type_of = [&](int64_t s) {
+    int t = 0;
+    for (int u = 1; u < fr::NTYPES; ++u)
+      if (M.nel[u] > 0 && s >= M.slot_base[u]) t = u;
+    return t;
+  };
   for (int64_t s = 0; s < M.nslots; ++s) {
-    int t = (M.nel[1] > 0 && s >= M.slot_base[1]) ? 1 : 0;
-    int64_t e = (s - M.slot_base[t]) / nfc[t];
-    int f = int((s - M.slot_base[t]) % nfc[t]);
+    int t = type_of(s);
+    int64_t e = (s - M.slot_base[t]) / fr::kFacesOf[t];
+    int f = int((s - M.slot_base[t]) % fr::kFacesOf[t]);
     int64_t o = M.nbr_slot[s];
-    int to = (M.nel[1] > 0 && o >= M.slot_base[1]) ? 1 : 0;
-    int64_t eo = (o - M.slot_base[to]) / nfc[to];
-    int fo = int((o - M.slot_base[to]) % nfc[to]);
+    int to = type_of(o);
+    int64_t eo = (o - M.slot_base[to]) / fr::kFacesOf[to];
+    int fo = int((o - M.slot_base[to]) % fr::kFacesOf[to]);
     const std::vector<int>& pm = M.perms[M.perm_id[s]];
     for (int q = 0; q < c->ref[t].face_npts[f]; ++q) {
       int64_t i = base[t] + e * c->ref[t].nf + c->ref[t].face_start[f] + q;
@@ -155,11 +162,14 @@ fr_status setup_plain(fr_ctx* c) {
 void free_plain(fr_ctx* c) {
   fr::PlainCtx* P = c->plain;
   if (!P) return;
-  void* bufs[] = {P->W, P->Uf, P->Cf, P->Q, P->Qf, P->Uq, P->Qq, P->Df, P->fgeo, P->faces,
-                  P->dM0[0], P->dG1[0], P->dM6[0], P->dM7[0], P->dK[0], P->dM3[0], P->jinv[0], P->detj[0],
-                  P->dM0[1], P->dG1[1], P->dM6[1], P->dM7[1], P->dK[1], P->dM3[1], P->jinv[1], P->detj[1]};
+  void* bufs[] = {P->W, P->Uf, P->Cf, P->Q, P->Qf, P->Uq, P->Qq, P->Df, P->fgeo, P->faces};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  for (int t = 0; t < fr::NTYPES; ++t) {
+    void* tb[] = {P->dM0[t], P->dG1[t], P->dM6[t], P->dM7[t], P->dK[t], P->dM3[t], P->jinv[t], P->detj[t]};
+    for (void* b : tb)
+      if (b) (void)hipFree(b);
+  }
   fr::plain_destroy_handle(P->blas);
   delete P;
   c->plain = nullptr;
@@ -354,8 +364,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
     return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
   const bool tets = kind == FR_MESH_TET || kind == FR_MESH_PRISM_TET;
-  if (tets && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
-    return fail(c, FR_EUNSUPPORTED, "tetrahedra: fused form with flux anti-aliasing only");
+  if (tets && c->ph.surface_aa)
+    return fail(c, FR_EUNSUPPORTED, "tetrahedra: no surface-flux anti-aliasing");
   if (fr::kind_curved(kind) && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
     return fail(c, FR_EUNSUPPORTED, "curved elements: fused form with flux anti-aliasing only");
   try {

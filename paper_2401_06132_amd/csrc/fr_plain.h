@@ -31,24 +31,33 @@ struct PlainFace {
 };
 
 struct PlainTypes {
-  int64_t E[2];      // elements per type
-  int64_t off_f[2];  // offset of each type block in the flux-point arrays (5 values per point)
-  int64_t nf[2];     // flux points per element
+  int64_t E[NTYPES];      // elements per type
+  int64_t off_f[NTYPES];  // offset of each type block in the flux-point arrays (5 values per point)
+  int64_t nf[NTYPES];     // flux points per element
+  int64_t f0[NTYPES];     // first flat flux point of each type (types in order)
 };
 
+// element type of flat flux point i
+__host__ __device__ inline int plain_type_of(const PlainTypes& ty, int64_t i) {
+  int t = 0;
+  for (int u = 1; u < NTYPES; ++u)
+    if (i >= ty.f0[u]) t = u;
+  return t;
+}
+
 struct PlainCtx {
-  PlainOps ops[2];
+  PlainOps ops[NTYPES];
   PlainTypes ty;
   Gas<double> gas;
   double beta = 0.5, eref = 0.0;
-  int64_t state_off[2] = {0, 0};
+  int64_t state_off[NTYPES] = {0, 0, 0};
   void* blas = nullptr;
   // device
-  double *dM0[2] = {nullptr, nullptr}, *dG1[2] = {nullptr, nullptr}, *dM6[2] = {nullptr, nullptr};
-  double *dM7[2] = {nullptr, nullptr}, *dK[2] = {nullptr, nullptr}, *dM3[2] = {nullptr, nullptr};
+  double *dM0[NTYPES] = {}, *dG1[NTYPES] = {}, *dM6[NTYPES] = {};
+  double *dM7[NTYPES] = {}, *dK[NTYPES] = {}, *dM3[NTYPES] = {};
   double *W = nullptr, *Uf = nullptr, *Cf = nullptr, *Q = nullptr, *Qf = nullptr, *Uq = nullptr, *Qq = nullptr;
   double *Df = nullptr, *fgeo = nullptr;
-  double *jinv[2] = {nullptr, nullptr}, *detj[2] = {nullptr, nullptr};
+  double *jinv[NTYPES] = {}, *detj[NTYPES] = {};
   PlainFace* faces = nullptr;
 };
 

@@ -33,11 +33,11 @@ namespace fr {
 
 namespace {
 
-__global__ void con_u_kernel(int64_t nf0, int64_t nftot, const double* __restrict__ Uf, double* __restrict__ Cf,
+__global__ void con_u_kernel(int64_t nftot, const double* __restrict__ Uf, double* __restrict__ Cf,
                              const PlainFace* __restrict__ fc, PlainTypes ty, double beta) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nftot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int t = i < nf0 ? 0 : 1;
-    const int64_t li = i - (t ? nf0 : 0);
+    const int t = plain_type_of(ty, i);
+    const int64_t li = i - ty.f0[t];
     const int64_t e = li / ty.nf[t], f = li - e * ty.nf[t];
     const PlainFace F = fc[i];
     const int tn = F.nbr_type;
@@ -87,13 +87,13 @@ __global__ void tdisf_kernel(int64_t E, int nq, const double* __restrict__ Uq, d
   }
 }
 
-__global__ void comm_flux_kernel(int64_t nf0, int64_t nftot, const double* __restrict__ Uf,
+__global__ void comm_flux_kernel(int64_t nftot, const double* __restrict__ Uf,
                                  const double* __restrict__ Qf, double* __restrict__ Df,
                                  const PlainFace* __restrict__ fc, const double* __restrict__ fgeo, PlainTypes ty,
                                  Gas<double> g) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nftot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int t = i < nf0 ? 0 : 1;
-    const int64_t li = i - (t ? nf0 : 0);
+    const int t = plain_type_of(ty, i);
+    const int64_t li = i - ty.f0[t];
     const int64_t e = li / ty.nf[t], f = li - e * ty.nf[t];
     const PlainFace F = fc[i];
     const int tn = F.nbr_type;
@@ -229,7 +229,7 @@ hipError_t plain_rhs(PlainCtx& P, const double* U, double* du, hipStream_t st) {
   const PlainTypes& ty = P.ty;
   const Gas<double>& g = P.gas;
   // reference-state copy of the state, then disu per type
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NTYPES; ++t) {
     if (!ty.E[t]) continue;
     const PlainOps& o = P.ops[t];
     const double* Ut = U + P.state_off[t];
@@ -238,10 +238,11 @@ hipError_t plain_rhs(PlainCtx& P, const double* U, double* du, hipStream_t st) {
     if (gemm(h, P.dM0[t], o.nf, o.nu, W, 5 * ty.E[t], P.Uf + ty.off_f[t], 0.0) != rocblas_status_success)
       return hipErrorUnknown;  // 1 disu
   }
-  const int64_t nf0 = ty.E[0] * ty.nf[0], nftot = nf0 + ty.E[1] * ty.nf[1];
-  hipLaunchKernelGGL(con_u_kernel, grid_for(nftot), dim3(256), 0, st, nf0, nftot, P.Uf, P.Cf, P.faces, ty,
+  int64_t nftot = 0;
+  for (int t = 0; t < NTYPES; ++t) nftot += ty.E[t] * ty.nf[t];
+  hipLaunchKernelGGL(con_u_kernel, grid_for(nftot), dim3(256), 0, st, nftot, P.Uf, P.Cf, P.faces, ty,
                      P.beta);  // 2 con_u
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NTYPES; ++t) {
     if (!ty.E[t]) continue;
     const PlainOps& o = P.ops[t];
     const int64_t E = ty.E[t];
@@ -260,9 +261,9 @@ hipError_t plain_rhs(PlainCtx& P, const double* U, double* du, hipStream_t st) {
     if (gemm(h, P.dK[t], o.nu, 3 * o.nq, P.Qq, 5 * E, du + P.state_off[t], 0.0) != rocblas_status_success)
       return hipErrorUnknown;  // 10 tdivpcorf
   }
-  hipLaunchKernelGGL(comm_flux_kernel, grid_for(nftot), dim3(256), 0, st, nf0, nftot, P.Uf, P.Qf, P.Df, P.faces,
+  hipLaunchKernelGGL(comm_flux_kernel, grid_for(nftot), dim3(256), 0, st, nftot, P.Uf, P.Qf, P.Df, P.faces,
                      P.fgeo, ty, g);  // 11 comm_flux
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NTYPES; ++t) {
     if (!ty.E[t]) continue;
     const PlainOps& o = P.ops[t];
     double* R = du + P.state_off[t];

@@ -38,7 +38,8 @@ struct TetCfg {
   static constexpr int O_M7 = O_G + 3 * NU * KG; // [NQ][NU]
   static constexpr int O_AP = O_M7 + NQ * NU;    // [3][NU][NQ]
   static constexpr int O_M3 = O_AP + 3 * NU * NQ;  // [NU][NF]
-  static constexpr int SIZE = O_M3 + NU * NF;
+  static constexpr int O_N = O_M3 + NU * NF;       // [4][3] reference unit normals
+  static constexpr int SIZE = O_N + 12;
   // LDS per element of the volume kernel: state + gradients [20][NU]
   // (later the partial divergences [3][5][NU]), neighbour values then jumps
   // [5][NF], the transformed flux at the quadrature points [3][5][FQS]
@@ -97,7 +98,10 @@ __global__ void __launch_bounds__(NT) tet_disu(const Seg sg, const bool from_ust
 }
 
 // --------------------------------------------------------------- volume
-template <int P, typename R, int EB, int NT>
+// AA: flux anti-aliasing; without it the flux is evaluated at the solution
+// points and the divergence takes the strong form (M1 - M3 M2) F~:
+// sum_d D_d F~_d - M3 (nhat . M0 F~)
+template <int P, typename R, int EB, int NT, bool AA>
 __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_ust, const R* __restrict__ ops,
                                                  const Gas<R> g, const double eref) {
   using C = TetCfg<P>;
@@ -213,6 +217,59 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
     for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
   }
 
+  if constexpr (!AA) {
+    // tdisf at the solution points, F~ into the flux region (NU <= FQS)
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s = it - le * NU;
+      const R* X = XS(le);
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = X[v * NU + s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[c][v] = X[(5 + c * 5 + v) * NU + s];
+      }
+      point_flux(u, q, g, f);
+      const R dj = sMet[le][9];
+      R* F = FQ(le);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          F[(d * 5 + v) * FQS + s] =
+              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+    }
+    lds_barrier();
+    // M2 F~: reference normal flux at the own flux points, into the jump
+    // region (free since the gradient phase)
+    for (int it = tid; it < EB * NF; it += NT) {
+      const int le = it / NF, fp = it - le * NF;
+      const R* nh = ops + C::O_N + 3 * (fp / NTN);
+      R nf[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        R a[5] = {R(0), R(0), R(0), R(0), R(0)};
+        row_cols<NU, 5>(ops + C::O_M0 + fp * NU, FQ(le) + d * 5 * FQS, FQS, a);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) nf[v] += nh[d] * a[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) JS(le)[v * NF + fp] = nf[v];
+    }
+    lds_barrier();
+    // (M1 - M3 M2) F~ = sum_d D_d F~_d - M3 (M2 F~)
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s = it - le * NU, e = e0 + le;
+      if (e >= E) continue;
+      R acc[5] = {R(0), R(0), R(0), R(0), R(0)}, lift[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) row_cols<NU, 5>(ops + C::O_G + (d * NU + s) * C::KG, FQ(le) + d * 5 * FQS, FQS, acc);
+      row_cols<NF, 5>(ops + C::O_M3 + s * NF, JS(le), NF, lift);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[v] - lift[v];
+    }
+    return;
+  }
   // phase 4: uqpts / gradcoru_qpts (M7) and tdisf at each quadrature point
   // (eq. FR-tdisfq): F~_d = det J sum_c (J^-1)_{dc} f_c
   for (int it = tid; it < EB * NQ; it += NT) {
@@ -337,6 +394,7 @@ static void pack_tet(const RefElem& r, R* o) {
     for (int u = 0; u < NU; ++u) o[C::O_M7 + q * NU + u] = R(r.M7[q * NU + u]);
   for (int i = 0; i < 3 * NU * NQ; ++i) o[C::O_AP + i] = R(r.APd[i]);
   for (int i = 0; i < NU * NF; ++i) o[C::O_M3 + i] = R(r.M3[i]);
+  for (int i = 0; i < 12; ++i) o[C::O_N + i] = R(r.face_normal[i]);
 }
 
 size_t tet_ops_bytes(int p, int prec) {
@@ -394,9 +452,14 @@ static hipError_t tet_rhs_t(const TypeArgs& a, hipStream_t st) {
   if ((a.stage & 1) && E > 0)
     hipLaunchKernelGGL((tet_disu<P, R, TET_DISU_EB, 256>), dim3((E + TET_DISU_EB - 1) / TET_DISU_EB), dim3(256), 0,
                        st, a.one, a.from_ust, ops, eref);
-  if ((a.stage & 2) && E > 0)
-    hipLaunchKernelGGL((tet_volume<P, R, EB, 256>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one, a.from_ust,
-                       ops, g, eref);
+  if ((a.stage & 2) && E > 0) {
+    if (a.aa)
+      hipLaunchKernelGGL((tet_volume<P, R, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+                         a.from_ust, ops, g, eref);
+    else
+      hipLaunchKernelGGL((tet_volume<P, R, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+                         a.from_ust, ops, g, eref);
+  }
   if ((a.stage & 4) && E > 0)
     hipLaunchKernelGGL((tet_surface<P, R, TET_SURF_EB, 256>), dim3((E + TET_SURF_EB - 1) / TET_SURF_EB), dim3(256),
                        0, st, a.one, a.rk, ops, g);

@@ -90,7 +90,7 @@ def test_rhs_parity(dims, p, kind, prec):
 
 
 @pytest.mark.parametrize("dims,p,kind", [((4, 4, 4), 3, "hex"), ((2, 2, 2), 3, "prism"), ((2, 2, 4), 2, "mixed"),
-                                         ((2, 3, 3), 4, "hex")])
+                                         ((2, 3, 3), 4, "hex"), ((2, 2, 2), 3, "tet"), ((2, 3, 2), 2, "prism_tet")])
 def test_plain_path_parity(dims, p, kind):
     """The unfused FP64 comparison path (dense operators, library GEMMs)."""
     _need_gpu()
@@ -105,7 +105,7 @@ def test_plain_path_parity(dims, p, kind):
     assert np.all(err < tol), (err, tol)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet"])
 def test_fused_matches_plain_on_gpu(kind):
     """Fused and plain GPU paths on a medium mesh (several workgroups and a
     ragged last block), FP64."""
@@ -173,7 +173,8 @@ def test_rhs_is_deterministic():
 
 NOAA_CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((2, 3, 3), 4, "hex"),
               ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"), ((2, 2, 2), 3, "prism"), ((3, 2, 2), 1, "prism"),
-              ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"), ((2, 2, 4), 3, "mixed"), ((2, 1, 2), 2, "mixed")]
+              ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"), ((2, 2, 4), 3, "mixed"), ((2, 1, 2), 2, "mixed"),
+              ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"), ((2, 2, 2), 1, "tet"), ((2, 3, 2), 2, "prism_tet")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -83,11 +83,15 @@ def test_surface_aa_rejected_where_not_built():
     _lib_or_skip()
     with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
         frmi.Solver((2, 2, 2), 3, "hex", aa=False, surface_aa=True)
-    for kind in ("tet", "hex_warp"):
+    for kind in ("hex_warp", "prism_warp", "mixed_warp"):
         with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
             frmi.Solver((2, 2, 2), 3, kind, aa=False)
         with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
             frmi.Solver((2, 2, 2), 3, kind, form="plain")
+    with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
+        frmi.Solver((2, 2, 2), 3, "tet", surface_aa=True)
+    frmi.Solver((2, 2, 2), 3, "tet", aa=False)
+    frmi.Solver((2, 2, 2), 3, "prism_tet", form="plain")
     with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
         frmi.Solver((2, 2, 2), 3, "hex", form="plain", surface_aa=True)
     for kind in ("hex", "prism", "mixed"):

@@ -13,13 +13,13 @@ from the product.
 Modules
 -------
 quadrature  Gauss-Legendre / Gauss-Lobatto / Gauss-Jacobi rules, the
-            conical-product triangle and tetrahedron rules and the triangle
-            and tetrahedron node sets.
-basis       Polynomial bases of the hex, triangle, prism and tet solution spaces.
+            conical-product triangle, tetrahedron and pyramid rules and the
+            triangle, tetrahedron and pyramid node sets.
+basis       Bases of the hex, triangle, prism, tet and pyramid solution spaces.
 elements    Reference elements (solution, flux and quadrature points, unit
             reference normals) and the dense operator matrices M0..M10.
-mesh        Periodic box meshes of hexahedra, split prisms, tetrahedra and
-            mixtures (hex/prism, prism/tet), affine
+mesh        Periodic box meshes of hexahedra, split prisms, tetrahedra,
+            pyramids and mixtures (hex/prism, prism/tet, hex/pyramid), affine
             metric terms and flux-point pairing by physical coordinates.
 physics     Inviscid / viscous fluxes, Rusanov and LDG interface fluxes.
 rhs         The semi-discrete right-hand side (the paper's thirteen kernels,
@@ -47,6 +47,12 @@ Parity status (pins live in tests/test_oracle_*.py):
     conical-product rule against closed-form simplex moments, the node set's
     symmetry and unisolvence, the operator identities above, free stream,
     conservation and entropy-wave convergence (test_oracle_tet.py).
+  * pyramids (RefElement("pyr"), Mesh kinds "pyr" and "hex_pyr"): the
+    conical-product rule against closed-form pyramid moments, the node set's
+    symmetry and unisolvence, the space (gradients, its rational members,
+    polynomial face traces), the weak-form divergence taken for pyramids
+    (exact for P_p fluxes, conservative), free stream, conservation and
+    entropy-wave convergence (test_oracle_pyr.py).
   * curved hexahedra and prisms (Mesh kinds "hex_warp", "prism_warp",
     "mixed_warp": vertex maps of a warped grid, per-point metrics): free
     stream, conservation, the discrete metric identity, equality with the

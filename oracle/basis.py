@@ -7,6 +7,13 @@ singularity on the triangle:
   hex    Q_p : P_a(xi) P_b(eta) P_c(zeta), a, b, c <= p
   prism      : P_a(xi) P_b(eta) P_c(zeta), a + b <= p, c <= p
   tet    P_p : P_a(xi) P_b(eta) P_c(zeta), a + b + c <= p
+  pyr        : the rational pyramid space (Bergot, Cohen & Durufle 2010),
+               spanned in the collapsed coordinates a = 2 xi/(1-zeta),
+               b = 2 eta/(1-zeta), c = zeta by
+               P_i(a) P_j(b) (1-c)^max(i,j) P_k(c),  i, j <= p, k <= p - max(i,j).
+               It contains P_p; its trace on the base is Q_p and on each
+               triangular face P_p, so it conforms with hexahedron,
+               prism and tetrahedron faces.
 The paper's L2 projection (eq. FR-tdivtpcorfq) is evaluated with the
 basis-independent mass-matrix form in elements.py.
 """
@@ -64,12 +71,41 @@ def modes(etype, p):
         return [(a, b, c) for c in range(p + 1) for b in range(p + 1) for a in range(p + 1 - b)]
     if etype == "tet":
         return [(a, b, c) for c in range(p + 1) for b in range(p + 1 - c) for a in range(p + 1 - b - c)]
+    if etype == "pyr":
+        return [(a, b, c) for b in range(p + 1) for a in range(p + 1) for c in range(p + 1 - max(a, b))]
     raise ValueError(etype)
+
+
+def _pyr_basis(p, pts):
+    """Pyramid space basis values and gradients (see the module header).
+    The points must avoid the apex zeta = 1."""
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    om = 1 - z
+    a, b = 2 * x / om, 2 * y / om
+    va, da = legendre_values(p, a)
+    vb, db = legendre_values(p, b)
+    vc, dc = legendre_values(p, z)
+    md = modes("pyr", p)
+    V = np.empty((len(pts), len(md)), dtype=EXT)
+    G = np.empty((3, len(pts), len(md)), dtype=EXT)
+    for k, (i, j, l) in enumerate(md):
+        mu = max(i, j)
+        C = om ** mu * vc[l]
+        # dC/dc; (1-c)^mu differentiates to -mu (1-c)^(mu-1)
+        dC = om ** mu * dc[l] - (mu * om ** (mu - 1) * vc[l] if mu > 0 else 0)
+        V[:, k] = va[i] * vb[j] * C
+        # d a/d xi = 2/(1-c), d a/d zeta = a/(1-c); likewise b
+        G[0, :, k] = da[i] * vb[j] * C * 2 / om
+        G[1, :, k] = va[i] * db[j] * C * 2 / om
+        G[2, :, k] = (da[i] * a * vb[j] + va[i] * db[j] * b) * C / om + va[i] * vb[j] * dC
+    return V, G
 
 
 def eval_basis(etype, p, pts):
     """Basis values V[pt, mode] and gradients G[d, pt, mode] at pts (N, 3)."""
     pts = np.asarray(pts, dtype=EXT)
+    if etype == "pyr":
+        return _pyr_basis(p, pts)
     vx, dx = legendre_values(p, pts[:, 0])
     vy, dy = legendre_values(p, pts[:, 1])
     vz, dz = legendre_values(p, pts[:, 2])

@@ -19,11 +19,18 @@ Reference elements
         opposite V0; each a triangle carrying the triangle nodes (mapped from
         the reference triangle with vertices (-1,-1), (1,-1), (-1,1) to the
         face's vertices in the order listed in _build_tet).
+  pyr   square base [-1,1]^2 at zeta = -1, apex (0, 0, 1); vertices V0..V4 =
+        (-1,-1,-1), (1,-1,-1), (1,1,-1), (-1,1,-1), (0,0,1).  Solution points:
+        quadrature.pyramid_nodes (a reading).  Face 0 = the base (GL(n)^2
+        flux points, index a + n b over (xi, eta)); faces 1..4 = the
+        triangles (V0,V1,V4), (V1,V2,V4), (V2,V3,V4), (V3,V0,V4) (outward
+        normals (0,-2,1), (2,0,1), (0,2,1), (-2,0,1) over sqrt 5), carrying
+        the triangle nodes mapped like the tetrahedron's faces.
 All operators are computed in extended precision (numpy longdouble) and kept
 there; callers cast them to their working precision (rounding once).
 Anti-aliasing quadrature (section 2.1.1): hex GL(m)^3; prism conical triangle
 rule with (p+1)^2 points (degree 2p+1) x GL(m); m = p + 3 by default;
-tet conical-product rule with (p+1)^3 points (degree 2p+1).
+tet and pyr conical-product rules with (p+1)^3 points (degree 2p+1).
 
 Surface-flux anti-aliasing (surf_aa=True, section 2.1.1 and table
 "operatorms"): the flux points are replaced by quadrature points on the
@@ -70,6 +77,8 @@ class RefElement:
             self._build_prism(gl, tri_nodes)
         elif etype == "tet":
             self._build_tet(tri_nodes)
+        elif etype == "pyr":
+            self._build_pyr(tri_nodes)
         else:
             raise ValueError(etype)
         self.nu, self.nf, self.nq = len(self.upts), len(self.fpts), len(self.qpts)
@@ -199,6 +208,42 @@ class RefElement:
             self.fwts = np.concatenate(fw)
         self.qpts, self.qwts = quadrature.tetrahedron_conical(p + 1)
 
+    # -------------------------------------------------------------- pyramid
+    def _build_pyr(self, tri_nodes):
+        p, n = self.p, self.n
+        if self.surf_aa:
+            raise ValueError("pyramids: no surface-flux anti-aliasing")
+        tn = quadrature.triangle_nodes(p) if tri_nodes is None else np.asarray(tri_nodes, float)
+        self.tri_nodes = tn
+        self.nt = len(tn)
+        self.upts = quadrature.pyramid_nodes(p)
+        V = quadrature.PYR_VERTS
+        self.nfaces = 5
+
+        def bmap(s, t):
+            s, t = np.asarray(s, float), np.asarray(t, float)
+            return np.stack([s, t, -np.ones_like(s)], axis=1)
+        faces = [dict(kind="quad", map=bmap, normal=np.array([0.0, 0.0, -1.0]), jac=1.0)]
+        for (a, b, c), nrm in [((0, 1, 4), (0.0, -2.0, 1.0)), ((1, 2, 4), (2.0, 0.0, 1.0)),
+                               ((2, 3, 4), (0.0, 2.0, 1.0)), ((3, 0, 4), (-2.0, 0.0, 1.0))]:
+            A, B, C = V[a], V[b], V[c]
+
+            def tmap(s, t, A=A, B=B, C=C):
+                s, t = np.asarray(s, float), np.asarray(t, float)
+                la, lb, lc = -(s + t) / 2.0, (1.0 + s) / 2.0, (1.0 + t) / 2.0
+                return la[:, None] * A + lb[:, None] * B + lc[:, None] * C
+            jac = np.linalg.norm(np.cross(B - A, C - A)) / 2.0 / 2.0
+            faces.append(dict(kind="tri", map=tmap, normal=np.array(nrm) / np.sqrt(5.0), jac=jac))
+        self.faces = faces
+        gl = self.gl
+        s = np.array([gl[a] for b in range(n) for a in range(n)])
+        t = np.array([gl[b] for b in range(n) for a in range(n)])
+        fp = [bmap(s, t)] + [fc["map"](tn[:, 0], tn[:, 1]) for fc in faces[1:]]
+        self.fpts = np.concatenate(fp)
+        self.fface = np.concatenate([np.full(len(x), f) for f, x in enumerate(fp)])
+        self.fnorm = np.array([faces[f]["normal"] for f in self.fface])
+        self.qpts, self.qwts = quadrature.pyramid_conical(p + 1)
+
     def _quad_face_points(self, g1, w1=None):
         """Tensor points g1 x g1 on every (quadrilateral) face; with weights
         w1 the points are a face quadrature rule (surface-flux AA)."""
@@ -233,6 +278,15 @@ class RefElement:
         self.M8 = massinv @ (Lq.T @ W)
         self.wu = Lq.T @ self.qwts
 
+        if et == "pyr":
+            # the pyramid space is not closed under differentiation, so the
+            # strong form (M1 - M3 M2) M9 differs from its weak form there;
+            # the weak form is kept (see rhs.py, step 10):
+            #   Kq[d] = -Mass^-1 Dq_d^T W_q (nu x nq), Ku[d] = Kq[d] M7
+            _, Dq = basis.nodal(et, p, up, self.qpts)
+            self.Kq = np.stack([-massinv @ (Dq[d].T * np.asarray(self.qwts, dtype=basis.EXT)[None, :])
+                                for d in range(3)])
+            self.Ku = np.einsum("dsq,qu->dsu", self.Kq, Lq)
         if self.surf_aa:
             # flux points are face quadrature points: the lifting integral
             # taken with the face rule, E[u, f] = l_u(x^f) w_f

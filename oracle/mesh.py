@@ -23,6 +23,18 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                  y faces are cut along the prisms' diagonal.
   kind "prism_tet" : prisms in cells whose centre has y < 0, tetrahedra
                  elsewhere (prism triangles meet tetrahedron faces).
+  kind "pyr"   : six pyramids per cell, one on each cell face (its base)
+                 with the apex at the cell centre; the pyramid on face f
+                 (x-, x+, y-, y+, z-, z+ in that order) maps reference
+                 (xi, eta, zeta) to B + xi e1 + eta e2 + (1+zeta)/2 (C - B),
+                 B the face centre, C the cell centre and e1, e2 the face's
+                 half edges, ordered so that e1 x e2 points into the cell
+                 (x-: (y, z); x+: (z, y); y-: (z, x); y+: (x, z); z-: (x, y);
+                 z+: (y, x)).  Bases meet hexahedron faces or other bases
+                 (GL(n)^2 points on the same square); triangles meet the
+                 neighbouring pyramids of the same cell.
+  kind "hex_pyr" : hexahedra in cells whose centre has z < 0, pyramids
+                 elsewhere.
   kinds "hex_warp", "prism_warp", "mixed_warp" : the curved (non-affine)
                  forms of "hex", "prism" and "mixed": every grid vertex x is
                  moved to x + warp h (sin y cos z, sin z cos x, sin x cos y)
@@ -43,7 +55,8 @@ Metrics: affine meshes keep one J per element (Jinv, detJ of shape (E, 3, 3)
 and (E,)); curved meshes give them per point through metrics(t, ref_pts).
 surf_aa=True builds the reference elements with surface-flux
 anti-aliasing (flux points at the face quadrature points).
-Element numbering: cells in index order; a prism cell yields A then B.  The
+Element numbering: cells in index order; a prism cell yields A then B, a
+pyramid cell its six pyramids in face order.  The
 position in that sequence is the global element id; each element type keeps
 its own elements in order of appearance.
 
@@ -100,7 +113,7 @@ class Mesh:
             if kind not in ("hex", "prism", "mixed"):
                 raise ValueError("warped meshes: hex, prism or mixed")
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
-                 "prism_tet": ["prism", "tet"]}[kind]
+                 "prism_tet": ["prism", "tet"], "pyr": ["pyr"], "hex_pyr": ["hex", "pyr"]}[kind]
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -118,9 +131,28 @@ class Mesh:
                         ctype = "hex" if zc < 0.0 else "prism"
                     elif kind == "prism_tet":
                         ctype = "prism" if yc < 0.0 else "tet"
+                    elif kind == "hex_pyr":
+                        ctype = "hex" if zc < 0.0 else "pyr"
                     else:
                         ctype = kind
-                    if ctype == "tet":
+                    if ctype == "pyr":
+                        C = x0 + 0.5 * h
+                        for ax in range(3):
+                            for sg in (-1.0, 1.0):
+                                t1, t2 = [a for a in range(3) if a != ax]
+                                # e1 x e2 must point into the cell, along -sg
+                                if (sg < 0) != (ax != 1):
+                                    t1, t2 = t2, t1
+                                e1, e2 = np.zeros(3), np.zeros(3)
+                                e1[t1], e2[t2] = 0.5 * h[t1], 0.5 * h[t2]
+                                B = C.copy()
+                                B[ax] += sg * 0.5 * h[ax]
+                                Jp = np.stack([e1, e2, 0.5 * (C - B)], axis=1)
+                                org["pyr"].append(B + 0.5 * (C - B))
+                                A["pyr"].append(Jp)
+                                gid["pyr"].append(g)
+                                g += 1
+                    elif ctype == "tet":
                         for P in _kuhn_tets(x0, h):
                             Jt = np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1) / 2.0
                             org["tet"].append(P[0] + Jt @ np.ones(3))

@@ -1,13 +1,14 @@
-"""One-dimensional rules, the conical-product triangle rule and the triangle
-node set used by the oracle.  Test infrastructure only (see package header).
+"""One-dimensional rules, the conical-product triangle, tetrahedron and
+pyramid rules and the node sets used by the oracle.  Test infrastructure
+only (see package header).
 
 Paper: section 2.1 allows any solution/flux point set; hexahedra use
 Gauss-Legendre points (the printed coordinates are the 3- and 4-point
 Gauss-Legendre nodes, figures "ufn" and "prism2toprims3").  Prisms are a
 triangle times a Gauss-Legendre line (section 4.1).  The paper prints
 triangle points only for p = 2 and p = 3, so the triangle node set is a
-reading: the Blyth-Pozrikidis construction on Gauss-Lobatto-Legendre master
-points, used for every order.
+reading: the Blyth-Pozrikidis construction on Gauss-Legendre master points,
+used for every order; the tetrahedron and pyramid sets are readings too.
 """
 
 import numpy as np
@@ -121,4 +122,53 @@ def tetrahedron_nodes(p):
                 s = sum(v[t] for t in idx)
                 lam = [(1.0 + 4.0 * v[t] - s) / 4.0 for t in idx]
                 pts.append(sum(lam[a] * TET_VERTS[a] for a in range(4)))
+    return np.array(pts)
+
+
+def pyramid_conical(k):
+    """Conical-product (collapsed-coordinate) rule on the reference pyramid
+    (square base [-1,1]^2 at zeta = -1, apex (0, 0, 1)) with k^3 points:
+    Gauss-Legendre in a and b, Gauss-Jacobi(2,0) in c, with
+        xi = a (1-c)/2,  eta = b (1-c)/2,  zeta = c,
+        dxi deta dzeta = (1-c)^2/4 da db dc.
+    A monomial xi^i eta^j zeta^l becomes a^i b^j times a polynomial of degree
+    i + j + l in c, so the rule is exact for total degree 2k-1 (and for
+    products of two functions of the pyramid space of order k-1, which are
+    polynomials of degree <= 2k-2 in each collapsed coordinate).
+    Ordering: c outer, b, a inner."""
+    a, wa = gauss_legendre(k)
+    c, wc = gauss_jacobi(k, 2.0, 0.0)
+    pts = np.empty((k ** 3, 3))
+    wts = np.empty(k ** 3)
+    for l in range(k):
+        for j in range(k):
+            for i in range(k):
+                q = (l * k + j) * k + i
+                s = 0.5 * (1.0 - c[l])
+                pts[q] = (a[i] * s, a[j] * s, c[l])
+                wts[q] = wa[i] * wa[j] * wc[l] / 4.0
+    return pts, wts
+
+
+# vertices of the reference pyramid: the base square counter-clockwise, then the apex
+PYR_VERTS = np.array([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [1.0, 1.0, -1.0], [-1.0, 1.0, -1.0], [0.0, 0.0, 1.0]])
+
+
+def pyramid_nodes(p):
+    """(p+1)(p+2)(2p+3)/6 solution points in the reference pyramid (the paper
+    prints none; a reading): p+1 layers at the heights zeta_l = t_l, the
+    Gauss-Legendre(p+1) nodes in increasing order; layer l holds the tensor
+    Gauss-Legendre(p+1-l) grid of the collapsed coordinates (a, b), i.e. the
+    points (a_i (1-zeta_l)/2, b_j (1-zeta_l)/2, zeta_l).  Every layer is
+    unisolvent for Q_{p-l} in (a, b) and the heights are distinct, which
+    makes the set unisolvent for the pyramid space.  Ordering: l outer, j,
+    i inner."""
+    t = gauss_legendre(p + 1)[0]
+    pts = []
+    for l in range(p + 1):
+        g = gauss_legendre(p + 1 - l)[0]
+        s = 0.5 * (1.0 - t[l])
+        for j in range(p + 1 - l):
+            for i in range(p + 1 - l):
+                pts.append((g[i] * s, g[j] * s, t[l]))
     return np.array(pts)

@@ -13,6 +13,13 @@ v1.11.0), with dense operators and no fusion:
   10 tdivtpcorf    R~   = (M1 - M3 M2) M9 F~^q, applied literally:
                    F~^u = M8 F~^q (per component), then
                    R~ = sum_d D_d F~^u_d - M3 (sum_d nhat_d M0 F~^u_d)
+                   Pyramids: the pyramid space (rational, see basis.py) is
+                   not closed under differentiation, so this strong form is
+                   not conservative there and differs from the weak form it
+                   equals for the other element types.  Pyramids take the
+                   weak form, R~ = sum_d -Mass^-1 Dq_d^T W_q F~^q_d (the
+                   DG-equivalent reading of FR with DG correction
+                   functions); without anti-aliasing F~^q = M7 F~^u.
   11 comm_flux     D~ = mag_L F(uL, uR, qL, qR, nL) on L, -mag_R F on R
                    (mag: each side's own area factor |det J J^-T nhat|)
   12 tdivtconf     R~  += M3 D~
@@ -61,7 +68,18 @@ def _unflat(flat, mesh, t, tail):
     return flat[o:o + mesh.nelem[t] * r.nf].reshape((mesh.nelem[t], r.nf) + tail)
 
 
-def _volume_flux(r, u, q, detj, jinv, gas, aa, cast):
+def _divergence(r, u, q, detj, jinv, gas, aa, cast):
+    """Steps 7-10: the volume part of R~, (E, N_u, 5)."""
+    if r.etype == "pyr":
+        f = _volume_flux(r, u, q, detj, jinv, gas, aa, cast, project=False)
+        return np.einsum("dsq,edqv->esv", cast(r.Kq if aa else r.Ku), f)
+    fu = _volume_flux(r, u, q, detj, jinv, gas, aa, cast)
+    div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)  # M1
+    nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)  # M2
+    return div - np.einsum("uf,efv->euv", cast(r.M3), nf)  # - M3 M2
+
+
+def _volume_flux(r, u, q, detj, jinv, gas, aa, cast, project=True):
     """Transformed flux F~ at the solution points, (E, 3, N_u, 5).
     u: (E, N_u, 5) state (reference form), q: (E, 3, N_u, 5) gradients.
     With flux anti-aliasing: U^q = M7 U, Q^q = M10 Q (steps 7, 8), the flux
@@ -80,7 +98,7 @@ def _volume_flux(r, u, q, detj, jinv, gas, aa, cast):
         ft = np.einsum("eq,eqdc,cvqe->edqv", cast(detj), cast(jinv), f)
     else:
         ft = np.einsum("e,edc,cvqe->edqv", cast(detj), cast(jinv), f)
-    if aa:
+    if aa and project:
         return np.einsum("uq,edqv->eduv", cast(r.M8), ft)  # 10 tdivtpcorf: M9 (I3 x M8)
     return ft
 
@@ -145,10 +163,7 @@ def rhs(mesh, U, par, dtype=None):
         for e0 in range(0, E, chunk):
             sl = slice(e0, min(E, e0 + chunk))
             dj, ji = _flux_metrics(mesh, t, par.aa, sl)
-            fu = _volume_flux(r, Up[t][sl], Q[t][sl], dj, ji, gas, par.aa, cast)
-            div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)  # M1
-            nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)  # M2
-            rt[sl] = div - np.einsum("uf,efv->euv", cast(r.M3), nf)  # - M3 M2
+            rt[sl] = _divergence(r, Up[t][sl], Q[t][sl], dj, ji, gas, par.aa, cast)
         Rt[t] = rt
     qfa = _flat(Qf, mesh, (3, 5))
     nL = cast(mesh.fnrm[mesh.iL])
@@ -271,10 +286,7 @@ def rhs_subset(mesh, U, par, sel, dtype=None):
         e1, q1 = Q[t]
         q = q1[np.searchsorted(e1, e0)]
         dj, ji = _flux_metrics(mesh, t, par.aa, e0)
-        fu = _volume_flux(r, u, q, dj, ji, gas, par.aa, cast)  # 7-10
-        div = np.einsum("dsu,eduv->esv", cast(r.Dg), fu)
-        nf = np.einsum("fd,fu,eduv->efv", cast(r.fnorm), cast(r.M0), fu)
-        rt = div - np.einsum("uf,efv->euv", cast(r.M3), nf)
+        rt = _divergence(r, u, q, dj, ji, gas, par.aa, cast)  # 7-10
         fp = fpts_of(t, e0)
         left = np.zeros(mesh.nfpts, dtype=bool)
         left[mesh.iL] = True

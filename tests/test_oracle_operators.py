@@ -114,7 +114,7 @@ def _random_poly(etype, p, rng):
     """A random polynomial of the element's solution space, as monomials."""
     if etype == "hex":
         terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1) for c in range(p + 1)]
-    elif etype == "tet":
+    elif etype in ("tet", "pyr"):  # P_p (inside the pyramid space)
         terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1 - a - b)]
     else:
         terms = [(a, b, c) for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1)]
@@ -137,7 +137,7 @@ def _random_poly(etype, p, rng):
     return f, grad
 
 
-CASES = [("hex", p) for p in (1, 2, 3, 4)] + [("prism", p) for p in (1, 2, 3, 4)] + [("tet", p) for p in (1, 2, 3, 4)]
+CASES = [(t, p) for t in ("hex", "prism", "tet", "pyr") for p in (1, 2, 3, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -167,16 +167,18 @@ def test_projection_is_left_inverse_of_interpolation(refs, case):
 @pytest.mark.parametrize("case", CASES)
 def test_quadrature_weights_and_volume(refs, case):
     r = refs[case]
-    vol = {"hex": 8.0, "prism": 4.0, "tet": 4.0 / 3.0}[r.etype]
+    vol = {"hex": 8.0, "prism": 4.0, "tet": 4.0 / 3.0, "pyr": 8.0 / 3.0}[r.etype]
     assert abs(r.qwts.sum() - vol) < 1e-13
     assert abs(r.wu.sum() - vol) < 1e-13
 
 
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", [c for c in CASES if c[0] != "pyr"])
 def test_divergence_operator_is_weak_form(refs, case):
     """(M1 - M3 M2) M9 = -Mass^-1 sum_d D_{q,d}^T W_q: the FR-DG divergence with
     the projected flux equals integration by parts against the test functions,
-    with the face terms removed exactly by the lifting."""
+    with the face terms removed exactly by the lifting.  Pyramids: the
+    identity needs a space closed under differentiation, which theirs is not;
+    their weak form is pinned in test_oracle_pyr.py."""
     r = refs[case]
     _, Dq = basis.nodal(r.etype, r.p, r.upts, r.qpts)
     for d in range(3):

@@ -56,7 +56,7 @@ typedef enum {
   FR_EUNSUPPORTED = -5   /* combination not built (e.g. order outside 1..4) */
 } fr_status;
 
-typedef enum { FR_HEX = 0, FR_PRISM = 1, FR_TET = 2 } fr_etype;
+typedef enum { FR_HEX = 0, FR_PRISM = 1, FR_TET = 2, FR_PYR = 3 } fr_etype;
 typedef enum {
   FR_MESH_HEX = 0,
   FR_MESH_PRISM = 1,
@@ -65,7 +65,9 @@ typedef enum {
   FR_MESH_PRISM_TET = 4,  /* prisms where y < 0, tetrahedra elsewhere */
   FR_MESH_HEX_WARP = 5,   /* kinds 0, 1, 2 on a warped grid: curved elements */
   FR_MESH_PRISM_WARP = 6,
-  FR_MESH_MIXED_WARP = 7
+  FR_MESH_MIXED_WARP = 7,
+  FR_MESH_PYR = 8,        /* six pyramids per cell */
+  FR_MESH_HEX_PYR = 9     /* hexahedra where z < 0, pyramids elsewhere */
 } fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
@@ -131,14 +133,20 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * tetrahedra per cell: the cube's Kuhn subdivision mirrored in x, so every
  * cell face is cut along the same diagonal as the prisms' y faces) and
  * FR_MESH_PRISM_TET (prisms where the cell centre has y < 0, tetrahedra
- * elsewhere; prism triangles meet tetrahedron faces).  Tetrahedra have no
- * tensor-product structure (the paper's factorisation does not apply) and
- * run on dense-operator kernels; they support the fused form with or without
- * flux anti-aliasing and the plain form, but not surface-flux anti-aliasing
- * (FR_EUNSUPPORTED).  Host-side only: device buffers
+ * elsewhere; prism triangles meet tetrahedron faces), FR_MESH_PYR (six
+ * pyramids per cell, one on each cell face with the apex at the cell centre)
+ * and FR_MESH_HEX_PYR (hexahedra where the cell centre has z < 0, pyramids
+ * elsewhere; pyramid bases meet hexahedron faces).  Tetrahedra and pyramids
+ * have no tensor-product structure (the paper's factorisation does not
+ * apply) and run on dense-operator kernels; they support the fused form with
+ * or without flux anti-aliasing and the plain form, but not surface-flux
+ * anti-aliasing (FR_EUNSUPPORTED).  Pyramids use the rational pyramid space
+ * (trace Q_p on the base, P_p on the triangles) and, since that space is not
+ * closed under differentiation, the weak form -Mass^-1 Dq^T W of the
+ * divergence (equal to (M1 - M3 M2) M9 for the other types).  Host-side only: device buffers
  * are allocated and uploaded by the first call that needs them.  Element
  * numbering: cells in index order i + nx(j + ny k); a prism cell yields two
- * elements, a tetrahedron cell six.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,
+ * elements, a tetrahedron or pyramid cell six.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,
  * FR_MESH_MIXED_WARP: the hex, prism and mixed meshes with curved
  * (non-affine) elements; every grid vertex x moves to
  * x + 0.2 h (sin y cos z, sin z cos x, sin x cos y) (h the cell size per
@@ -155,8 +163,9 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
  * number of doubles of a state vector.  Any pointer may be NULL. */
 fr_status fr_layout(const fr_ctx* c, int64_t* n_hex, int64_t* n_prism, int64_t* n_state);
 
-/* Number of elements of type etype (fr_etype: hex, prism, tet) in the mesh.
- * Library order of the state: all hexahedra, then prisms, then tetrahedra.
+/* Number of elements of type etype (fr_etype: hex, prism, tet, pyramid) in
+ * the mesh.  Library order of the state: all hexahedra, then prisms, then
+ * tetrahedra, then pyramids.
  * Errors: FR_EINVAL (null, bad etype), FR_ESTATE (no mesh). */
 fr_status fr_type_count(const fr_ctx* c, int etype, int64_t* n_elem);
 
@@ -203,8 +212,11 @@ fr_status fr_integrals(fr_ctx* c, double* out5);
  *   "upts", "fpts", "qpts"  point coordinates (N x 3)
  *   "qwts"                  quadrature weights (N_q)
  *   "M0" (N_f x N_u), "M3" (N_u x N_f), "M7" (N_q x N_u), "M8" (N_u x N_q),
- *   "Dxi", "Deta", "Dzeta" (N_u x N_u)   dense operators of section 2.2.
- * Errors: FR_EINVAL (unknown name, cap too small). */
+ *   "Dxi", "Deta", "Dzeta" (N_u x N_u)   dense operators of section 2.2;
+ *   "APd" (3 x N_u x N_q)   tetrahedra, pyramids: -Mass^-1 Dq_d^T W_q
+ *   "Ku" (3 x N_u x N_u)    pyramids: APd_d M7 (empty otherwise).
+ * etype: fr_etype.  Errors: FR_EINVAL (unknown name or etype, cap too
+ * small). */
 fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count);
 
 /* fr_connectivity: for every flux point of every element (types in order,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfrmi.so")
 
 FR_HEX, FR_PRISM = 0, 1
 MESH_KIND = {"hex": 0, "prism": 1, "mixed": 2, "tet": 3, "prism_tet": 4, "hex_warp": 5, "prism_warp": 6,
-             "mixed_warp": 7}
+             "mixed_warp": 7, "pyr": 8, "hex_pyr": 9}
 PREC = {"fp64": 0, "fp32": 1}
 FORM = {"fused": 0, "plain": 1}
 _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE", -5: "FR_EUNSUPPORTED"}
@@ -143,11 +143,13 @@ class Solver:
         nh, npr, ns = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self.ctx, self.lib.fr_layout(self.ctx, ctypes.byref(nh), ctypes.byref(npr), ctypes.byref(ns)))
         self.n_hex, self.n_prism, self.n_state = nh.value, npr.value, ns.value
-        nt = ctypes.c_int64()
+        nt, npy = ctypes.c_int64(), ctypes.c_int64()
         _check(self.ctx, self.lib.fr_type_count(self.ctx, 2, ctypes.byref(nt)))
-        self.n_tet = nt.value
+        _check(self.ctx, self.lib.fr_type_count(self.ctx, 3, ctypes.byref(npy)))
+        self.n_tet, self.n_pyr = nt.value, npy.value
         n1 = p + 1
-        self.nu = {"hex": n1 ** 3, "prism": (n1 * (n1 + 1) // 2) * n1, "tet": n1 * (n1 + 1) * (n1 + 2) // 6}
+        self.nu = {"hex": n1 ** 3, "prism": (n1 * (n1 + 1) // 2) * n1, "tet": n1 * (n1 + 1) * (n1 + 2) // 6,
+                   "pyr": n1 * (n1 + 1) * (2 * n1 + 1) // 6}
 
     def __del__(self):
         if getattr(self, "ctx", None):
@@ -167,6 +169,8 @@ class Solver:
             out.append(("prism", self.n_prism, self.nu["prism"]))
         if self.n_tet:
             out.append(("tet", self.n_tet, self.nu["tet"]))
+        if self.n_pyr:
+            out.append(("pyr", self.n_pyr, self.nu["pyr"]))
         return out
 
     def upts_coords(self):

@@ -21,10 +21,10 @@ struct fr_ctx {
   bool mesh_ok = false, dev_ok = false;
   int p = 0;
   fr::RefElem ref[fr::NTYPES];
-  bool has[fr::NTYPES] = {false, false, false};
+  bool has[fr::NTYPES] = {};
   fr::Mesh M;
-  int64_t off[fr::NTYPES] = {0, 0, 0}, n_state = 0;
-  bool diag[fr::NTYPES] = {false, false, false};  // all Jacobians of the type are diagonal
+  int64_t off[fr::NTYPES] = {}, n_state = 0;
+  bool diag[fr::NTYPES] = {};  // all Jacobians of the type are diagonal
   fr::HostOps hops[fr::NTYPES];
   fr::GasHost gas;
   // device buffers
@@ -33,10 +33,10 @@ struct fr_ctx {
   void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
   fr::FaceRec* d_faces = nullptr;
   uint8_t* d_perms = nullptr;
-  void* d_met[fr::NTYPES] = {nullptr, nullptr, nullptr};
-  double* d_detj[fr::NTYPES] = {nullptr, nullptr, nullptr};
+  void* d_met[fr::NTYPES] = {};
+  double* d_detj[fr::NTYPES] = {};
   void* d_pops = nullptr;  // prism triangle tables
-  void* d_tops = nullptr;  // tetrahedron operator tables
+  void* d_dops[fr::NTYPES] = {};  // dense operator tables (tetrahedra, pyramids)
   void* d_verts[2] = {nullptr, nullptr};  // curved meshes: element vertices [E][nv][3]
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
@@ -246,12 +246,13 @@ fr_status ensure_device(fr_ctx* c) {
       HIPCHK(hipMalloc(&c->d_verts[t], buf.size()));
       HIPCHK(hipMemcpy(c->d_verts[t], buf.data(), buf.size(), hipMemcpyHostToDevice));
     }
-  if (c->has[2]) {
-    size_t nb = fr::tet_ops_bytes(c->p, c->ph.prec);
+  for (int t = 2; t < fr::NTYPES; ++t) {
+    if (!c->has[t]) continue;
+    size_t nb = fr::dense_ops_bytes(t, c->p, c->ph.prec);
     std::vector<unsigned char> pb(nb);
-    fr::tet_ops_pack(c->ref[2], c->ph.prec, pb.data());
-    HIPCHK(hipMalloc(&c->d_tops, nb));
-    HIPCHK(hipMemcpy(c->d_tops, pb.data(), nb, hipMemcpyHostToDevice));
+    fr::dense_ops_pack(c->ref[t], c->ph.prec, pb.data());
+    HIPCHK(hipMalloc(&c->d_dops[t], nb));
+    HIPCHK(hipMemcpy(c->d_dops[t], pb.data(), nb, hipMemcpyHostToDevice));
   }
   c->dev_ok = true;
   return FR_OK;
@@ -287,7 +288,7 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
   a.stage = stage;
   a.diag = c->diag[t];
   a.one = s;
-  a.dops = t == 2 ? c->d_tops : c->d_pops;
+  a.dops = t >= 2 ? c->d_dops[t] : c->d_pops;
   a.warp = c->M.curved && t < 2;
   a.ops = &c->hops[t];
   a.gas = &c->gas;
@@ -314,7 +315,7 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
       a.saa = c->ph.surface_aa != 0;
       hipError_t e = t == 0   ? fr::hex_rhs(a, c->ph.prec, c->st)
                      : t == 1 ? fr::prism_rhs(a, c->ph.prec, c->st)
-                              : fr::tet_rhs(a, c->ph.prec, c->st);
+                              : fr::dense_rhs(t, a, c->ph.prec, c->st);
       if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
   return FR_OK;
@@ -363,15 +364,14 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind >= fr::kNumKinds)
     return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
-  const bool tets = kind == FR_MESH_TET || kind == FR_MESH_PRISM_TET;
-  if (tets && c->ph.surface_aa)
-    return fail(c, FR_EUNSUPPORTED, "tetrahedra: no surface-flux anti-aliasing");
+  if (fr::kind_dense(kind) && c->ph.surface_aa)
+    return fail(c, FR_EUNSUPPORTED, "tetrahedra and pyramids: no surface-flux anti-aliasing");
   if (fr::kind_curved(kind) && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))
     return fail(c, FR_EUNSUPPORTED, "curved elements: fused form with flux anti-aliasing only");
   try {
     c->p = p;
     for (int t = 0; t < fr::NTYPES; ++t) fr::build_ref(t, p, c->ref[t]);
-    const fr::RefElem* refs[fr::NTYPES] = {&c->ref[0], &c->ref[1], &c->ref[2]};
+    const fr::RefElem* refs[fr::NTYPES] = {&c->ref[0], &c->ref[1], &c->ref[2], &c->ref[3]};
     std::string e = fr::build_box_mesh(nx, ny, nz, lo, hi, p, kind, refs, c->M);
     if (!e.empty()) return fail(c, FR_EINVAL, e);
     if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
@@ -548,7 +548,7 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
 }
 
 fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count) {
-  if (!name || etype < 0 || etype > 2) return FR_EINVAL;
+  if (!name || etype < 0 || etype >= fr::NTYPES) return FR_EINVAL;
   if (p < 1 || p > 4) return FR_EUNSUPPORTED;
   fr::RefElem r;
   try {
@@ -568,6 +568,8 @@ fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64
   else if (nm == "M7") v = &r.M7;
   else if (nm == "M8") v = &r.M8;
   else if (nm == "wu") v = &r.wu;
+  else if (nm == "APd") v = &r.APd;
+  else if (nm == "Ku") v = &r.Ku;
   else if (nm == "Dxi" || nm == "Deta" || nm == "Dzeta") {
     int d = nm == "Dxi" ? 0 : (nm == "Deta" ? 1 : 2);
     tmp.assign(r.Dg.begin() + (size_t)d * r.nu * r.nu, r.Dg.begin() + (size_t)(d + 1) * r.nu * r.nu);
@@ -586,7 +588,7 @@ fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_
   if (!c->mesh_ok) return FR_ESTATE;
   const fr::Mesh& M = c->M;
   // flat flux-point numbering: types in order, element, flux point
-  int64_t base[fr::NTYPES] = {0, 0, 0};
+  int64_t base[fr::NTYPES] = {};
   for (int t = 1; t < fr::NTYPES; ++t) base[t] = base[t - 1] + M.nel[t - 1] * c->ref[t - 1].nf;
   int64_t total = base[fr::NTYPES - 1] + M.nel[fr::NTYPES - 1] * c->ref[fr::NTYPES - 1].nf;
   if (n_fpts) *n_fpts = total;
@@ -623,11 +625,15 @@ void fr_destroy(fr_ctx* c) {
   if (!c) return;
   if (c->dev_ok || c->d_state) {
     (void)hipStreamSynchronize(c->st);
-    void* bufs[] = {c->d_state, c->d_rk, c->d_Uf, c->d_Vf, c->d_Rp, c->d_fgeo, c->d_faces, c->d_perms,
-                    c->d_met[0], c->d_met[1], c->d_met[2], c->d_detj[0], c->d_detj[1], c->d_detj[2],
-                    c->d_pops, c->d_tops, c->d_verts[0], c->d_verts[1]};
+    void* bufs[] = {c->d_state, c->d_rk,    c->d_Uf,       c->d_Vf,      c->d_Rp, c->d_fgeo,
+                    c->d_faces, c->d_perms, c->d_pops, c->d_verts[0], c->d_verts[1]};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
+    for (int t = 0; t < fr::NTYPES; ++t) {
+      void* tb[] = {c->d_met[t], c->d_detj[t], c->d_dops[t]};
+      for (void* b : tb)
+        if (b) (void)hipFree(b);
+    }
   }
   free_plain(c);
   delete c;

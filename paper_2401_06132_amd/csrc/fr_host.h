@@ -46,8 +46,8 @@ struct Tri {
   double edgeNormal[3][2] = {{0, -1}, {0, 0}, {-1, 0}};
 };
 
-// Geometry of a reference element (hex, prism or tet) and its dense operators.
-// etype: 0 hex, 1 prism, 2 tet.
+// Geometry of a reference element (hex, prism, tet or pyramid) and its dense
+// operators.  etype: 0 hex, 1 prism, 2 tet, 3 pyramid.
 struct RefElem {
   int etype = 0, p = 0, n = 0, m = 0;
   int nu = 0, nf = 0, nq = 0, nfaces = 0, nfp_max = 0;
@@ -56,13 +56,15 @@ struct RefElem {
   std::vector<double> upts, fpts, qpts, qwts;  // N x 3 / N
   std::vector<int> face_start, face_npts;      // per face
   std::vector<double> face_normal;             // nfaces x 3, unit reference normals
-  std::vector<double> face_jac;                // tets: face area / reference triangle area
+  std::vector<double> face_jac;                // tets, pyramids: face area / reference face area
   std::vector<double> wu;                      // integrals of the nodal basis
   // dense operators of section 2.2 (row-major), built from the factors
   std::vector<double> M0, M3, M7, M8, Dg;  // Dg: 3 x nu x nu
-  // tetrahedra (no factorisation): projection-divergence per reference
-  // direction, AP_d = -Mass^-1 Dq_d^T W_q (3 x nu x nq), and the mass matrix
-  std::vector<double> APd, mass;
+  // tetrahedra and pyramids (no factorisation): projection-divergence per
+  // reference direction, AP_d = -Mass^-1 Dq_d^T W_q (3 x nu x nq), and the
+  // mass matrix; pyramids also Ku_d = AP_d M7 (3 x nu x nu), the divergence
+  // of a flux held at the solution points (no anti-aliasing)
+  std::vector<double> APd, mass, Ku;
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -70,13 +72,16 @@ void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x, std:
 void triangle_nodes(int p, std::vector<double>& xy);
 void build_ref(int etype, int p, RefElem& r);
 
-// element types of a mesh: 0 hexahedra, 1 prisms, 2 tetrahedra
-constexpr int NTYPES = 3;
-constexpr int kFacesOf[NTYPES] = {6, 5, 4};
+// element types of a mesh: 0 hexahedra, 1 prisms, 2 tetrahedra, 3 pyramids
+constexpr int NTYPES = 4;
+constexpr int kFacesOf[NTYPES] = {6, 5, 4, 5};
 // box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
-// 4 prism (y < 0) + tet; 5, 6, 7: kinds 0, 1, 2 on the warped grid (curved)
-constexpr int kNumKinds = 8;
+// 4 prism (y < 0) + tet; 5, 6, 7: kinds 0, 1, 2 on the warped grid (curved);
+// 8 pyramid (six per cell), 9 hex (z < 0) + pyramid
+constexpr int kNumKinds = 10;
 inline bool kind_curved(int kind) { return kind >= 5 && kind <= 7; }
+// kinds with tetrahedra or pyramids (dense-operator element types)
+inline bool kind_dense(int kind) { return kind == 3 || kind == 4 || kind == 8 || kind == 9; }
 // vertex displacement of the warped grid, in cell sizes
 constexpr double kWarp = 0.2;
 
@@ -84,14 +89,14 @@ constexpr double kWarp = 0.2;
 struct Mesh {
   int nx = 0, ny = 0, nz = 0, p = 0, kind = 0;
   double lo = 0, hi = 0;
-  int64_t nel[NTYPES] = {0, 0, 0};
+  int64_t nel[NTYPES] = {};
   std::vector<double> org[NTYPES];    // element origin (x at reference 0)
   std::vector<double> jac[NTYPES];    // J (3x3 row-major, rows x,y,z cols xi,eta,zeta)
   std::vector<double> jinv[NTYPES];   // J^-1
   std::vector<double> detj[NTYPES];
   std::vector<int64_t> gid[NTYPES];   // mesh-order index
   // face slots: type t, element e, face f at slot_base[t] + e * kFacesOf[t] + f
-  int64_t slot_base[NTYPES] = {0, 0, 0};
+  int64_t slot_base[NTYPES] = {};
   int64_t nslots = 0;
   std::vector<int64_t> nbr_slot;  // paired slot
   std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]

@@ -87,10 +87,11 @@ int prism_block_elems(int p, int prec, int k, bool saa);
 // and its packing into host memory (uploaded once per context)
 size_t prism_ops_bytes(int p, int prec);
 void prism_ops_pack(const RefElem& r, int prec, void* dst);
-// tetrahedra: dense operator tables (device copy) and the kernels
-size_t tet_ops_bytes(int p, int prec);
-void tet_ops_pack(const RefElem& r, int prec, void* dst);
-hipError_t tet_rhs(const TypeArgs& a, int prec, hipStream_t st);
+// tetrahedra and pyramids (etype 2, 3): dense operator tables (device copy)
+// and the kernels
+size_t dense_ops_bytes(int etype, int p, int prec);
+void dense_ops_pack(const RefElem& r, int prec, void* dst);
+hipError_t dense_rhs(int etype, const TypeArgs& a, int prec, hipStream_t st);
 
 // element-wise RK4 stage update: acc += a k; ust = u0 + b k  (first stage:
 // acc = u0 + a k)

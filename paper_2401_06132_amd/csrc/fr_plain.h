@@ -50,7 +50,7 @@ struct PlainCtx {
   PlainTypes ty;
   Gas<double> gas;
   double beta = 0.5, eref = 0.0;
-  int64_t state_off[NTYPES] = {0, 0, 0};
+  int64_t state_off[NTYPES] = {};
   void* blas = nullptr;
   // device
   double *dM0[NTYPES] = {}, *dG1[NTYPES] = {}, *dM6[NTYPES] = {};

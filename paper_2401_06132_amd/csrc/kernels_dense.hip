@@ -1,13 +1,17 @@
-// Fused flux-reconstruction kernels for tetrahedra (gfx950).
+// Fused flux-reconstruction kernels for tetrahedra and pyramids (gfx950).
 //
-// Tetrahedra have no tensor-product structure: the paper's sum factorisation
-// does not apply to them (sections 1 and 4.1), so every operator is a dense
-// per-element matrix: M0 (N_f x N_u), the corrected-gradient operator
-// [D_d | n_d M3] (N_u x (N_u + N_f)), M7 (N_q x N_u), the projection-
-// divergence AP_d = -Mass^-1 Dq_d^T W_q (N_u x N_q; the weak form of
-// (M1 - M3 M2) M9, as for the other types) and the lifting M3 (N_u x N_f).
-// The kernel groups are those of the hexahedral and prism kernels: disu |
-// volume group | interface group.
+// Tetrahedra and pyramids have no tensor-product structure: the paper's sum
+// factorisation does not apply to them (sections 1 and 4.1), so every
+// operator is a dense per-element matrix: M0 (N_f x N_u), the corrected-
+// gradient operator [D_d | n_d M3] (N_u x (N_u + N_f)), M7 (N_q x N_u), the
+// projection-divergence AP_d = -Mass^-1 Dq_d^T W_q (N_u x N_q; the weak form
+// of (M1 - M3 M2) M9 for tetrahedra, as for the other types; for pyramids,
+// whose rational space is not closed under differentiation, the divergence
+// by definition) and the lifting M3 (N_u x N_f).  Without anti-aliasing
+// tetrahedra take the strong form sum_d D_d F~_d - M3 (M2 F~) at the solution
+// points, pyramids the weak form Ku_d = AP_d M7 (N_u x N_u).  The kernel
+// groups are those of the hexahedral and prism kernels: disu | volume group
+// | interface group.
 //
 // Dense products C = A B run one operator row per thread: the row is read
 // from the device table into registers (in chunks of KC entries, so long
@@ -16,36 +20,46 @@
 // the same element, so every LDS read is a broadcast.
 //
 // Reference tetrahedron {xi, eta, zeta >= -1, xi + eta + zeta <= -1};
-// faces 0..3 = zeta = -1, eta = -1, xi = -1, the slanted face; each face
-// slot holds the N_t triangle-node values of its face (slot stride (p+1)^2).
+// faces 0..3 = zeta = -1, eta = -1, xi = -1, the slanted face.  Reference
+// pyramid: base [-1,1]^2 at zeta = -1 (face 0, GL(n)^2 points), apex (0,0,1),
+// triangles 1..4.  A face slot holds the face's values (the N_t triangle
+// nodes, or the n^2 base points; slot stride (p+1)^2).
 #include "fr_device.h"
 #include "fr_kernels.h"
 
 namespace fr {
 
-template <int P>
-struct TetCfg {
+// ET: 2 tetrahedron, 3 pyramid
+template <int ET, int P>
+struct DenseCfg {
+  static constexpr bool PYR = ET == 3;
   static constexpr int n = P + 1;
-  static constexpr int NU = (P + 1) * (P + 2) * (P + 3) / 6;  // solution points
-  static constexpr int NTN = (P + 1) * (P + 2) / 2;           // points per face
-  static constexpr int NF = 4 * NTN;                          // flux points
-  static constexpr int NQ = (P + 1) * (P + 1) * (P + 1);      // quadrature points
-  static constexpr int NFPS = n * n;                          // face slot stride
-  static constexpr int KG = NU + NF;                          // gradient operator row
+  static constexpr int NU = PYR ? n * (n + 1) * (2 * n + 1) / 6 : n * (n + 1) * (n + 2) / 6;  // solution points
+  static constexpr int NFACE = PYR ? 5 : 4;
+  static constexpr int NTN = n * (n + 1) / 2;            // points per triangle
+  static constexpr int NB = PYR ? n * n : 0;              // points on the pyramid base
+  static constexpr int NF = NB + 4 * NTN;                 // flux points
+  static constexpr int NQ = n * n * n;                    // quadrature points
+  static constexpr int NFPS = n * n;                      // face slot stride
+  static constexpr int KG = NU + NF;                      // gradient operator row
   // device table (working precision), row-major blocks
   static constexpr int O_M0 = 0;                 // [NF][NU]
   static constexpr int O_G = O_M0 + NF * NU;     // [3][NU][KG]
   static constexpr int O_M7 = O_G + 3 * NU * KG; // [NQ][NU]
   static constexpr int O_AP = O_M7 + NQ * NU;    // [3][NU][NQ]
   static constexpr int O_M3 = O_AP + 3 * NU * NQ;  // [NU][NF]
-  static constexpr int O_N = O_M3 + NU * NF;       // [4][3] reference unit normals
-  static constexpr int SIZE = O_N + 12;
+  static constexpr int O_N = O_M3 + NU * NF;       // [NFACE][3] reference unit normals
+  static constexpr int O_KU = O_N + 3 * NFACE;      // pyramids: [3][NU][NU] AP_d M7
+  static constexpr int SIZE = O_KU + (PYR ? 3 * NU * NU : 0);
   // LDS per element of the volume kernel: state + gradients [20][NU]
   // (later the partial divergences [3][5][NU]), neighbour values then jumps
   // [5][NF], the transformed flux at the quadrature points [3][5][FQS]
   static constexpr int FQS = NQ + 1;  // odd stride: the three components' rows hit different banks
   static constexpr int SZ_X = 20 * NU, SZ_J = 5 * NF, SZ_F = 15 * FQS;
   static constexpr int PER_ELEM = SZ_X + SZ_J + SZ_F;
+  // face f and point t within the face of flux point fp
+  __host__ __device__ static constexpr int face_of(int fp) { return fp < NB ? 0 : PYR + (fp - NB) / NTN; }
+  __host__ __device__ static constexpr int point_of(int fp) { return fp < NB ? fp : (fp - NB) % NTN; }
 };
 
 // acc[c] += sum_k A[k] B[c * ldb + k] (k < K, c < NC): a row A of a dense
@@ -69,11 +83,11 @@ __device__ __forceinline__ void row_cols(const R* __restrict__ A, const R* B, in
 }
 
 // ----------------------------------------------------------------- disu
-template <int P, typename R, int EB, int NT>
-__global__ void __launch_bounds__(NT) tet_disu(const Seg sg, const bool from_ust, const R* __restrict__ ops,
+template <int ET, int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_ust, const R* __restrict__ ops,
                                                const double eref) {
-  using C = TetCfg<P>;
-  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NFPS = C::NFPS;
+  using C = DenseCfg<ET, P>;
+  constexpr int NU = C::NU, NF = C::NF, NFPS = C::NFPS, NFACE = C::NFACE;
   __shared__ R sU[EB * 5 * NU];
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -90,8 +104,8 @@ __global__ void __launch_bounds__(NT) tet_disu(const Seg sg, const bool from_ust
     if (e >= E) continue;
     R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
     row_cols<NU, 5>(ops + C::O_M0 + fp * NU, sU + le * 5 * NU, NU, acc);
-    const int f = fp / NTN, t = fp - f * NTN;
-    const size_t slot = (size_t)(sg.slot_base + e * 4 + f);
+    const int f = C::face_of(fp), t = C::point_of(fp);
+    const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Uf[slot * 5 * NFPS + v * NFPS + t] = acc[v];
   }
@@ -101,16 +115,16 @@ __global__ void __launch_bounds__(NT) tet_disu(const Seg sg, const bool from_ust
 // AA: flux anti-aliasing; without it the flux is evaluated at the solution
 // points and the divergence takes the strong form (M1 - M3 M2) F~:
 // sum_d D_d F~_d - M3 (nhat . M0 F~)
-template <int P, typename R, int EB, int NT, bool AA>
-__global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_ust, const R* __restrict__ ops,
+template <int ET, int P, typename R, int EB, int NT, bool AA>
+__global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from_ust, const R* __restrict__ ops,
                                                  const Gas<R> g, const double eref) {
-  using C = TetCfg<P>;
-  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, FQS = C::FQS;
+  using C = DenseCfg<ET, P>;
+  constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, FQS = C::FQS, NFACE = C::NFACE;
   constexpr int PE = C::PER_ELEM;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
-  __shared__ FaceRec sFR[EB * 4];
-  __shared__ R sFG[EB * 4][4];
+  __shared__ FaceRec sFR[EB * NFACE];
+  __shared__ R sFG[EB * NFACE][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -125,8 +139,8 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
 
   // phase 0: face records, geometry, permutations and metrics to LDS, the
   // state (reference form), then the neighbour face values
-  for (int it = tid; it < EB * 4; it += NT) {
-    const int slot = sg.slot_base + (e0 + it / 4 < E ? e0 * 4 + it : 0);
+  for (int it = tid; it < EB * NFACE; it += NT) {
+    const int slot = sg.slot_base + (e0 + it / NFACE < E ? e0 * NFACE + it : 0);
     sFR[it] = sg.faces[slot];
 #pragma unroll
     for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
@@ -145,8 +159,8 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
   lds_barrier();
   for (int it = tid; it < EB * 5 * NF; it += NT) {
     const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
-    const int f = fp / NTN, t = fp - f * NTN;
-    const FaceRec fr = sFR[le * 4 + f];
+    const int f = C::face_of(fp), t = C::point_of(fp);
+    const FaceRec fr = sFR[le * NFACE + f];
     JS(le)[r0] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
   }
   lds_barrier();
@@ -158,7 +172,7 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
     const int le = it / NF, fp = it - le * NF;
     R uf[5] = {R(0), R(0), R(0), R(0), R(0)};
     row_cols<NU, 5>(ops + C::O_M0 + fp * NU, XS(le), NU, uf);
-    const bool left = sFR[le * 4 + fp / NTN].info & 1;
+    const bool left = sFR[le * NFACE + C::face_of(fp)].info & 1;
     const R w = left ? R(0.5) + g.beta : R(0.5) - g.beta;
 #pragma unroll
     for (int v = 0; v < 5; ++v) JS(le)[v * NF + fp] = w * (JS(le)[v * NF + fp] - uf[v]);
@@ -201,7 +215,7 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
 #pragma unroll
     for (int k = 0; k < 20; ++k) w[k] = R(0);
     row_cols<NU, 20>(ops + C::O_M0 + fp * NU, XS(le), NU, w);
-    const int f = fp / NTN, t = fp - f * NTN, lf = le * 4 + f;
+    const int f = C::face_of(fp), t = C::point_of(fp), lf = le * NFACE + f;
     const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
     const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
     R u[5], q[3][5], V[4];
@@ -212,7 +226,7 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
     normal_viscous(u, q, nn, g, V);
-    const size_t slot = (size_t)(sg.slot_base + e * 4 + f);
+    const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
 #pragma unroll
     for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
   }
@@ -240,11 +254,26 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
               dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
     }
     lds_barrier();
+    if constexpr (C::PYR) {
+      // weak form without anti-aliasing: sum_d Ku_d F~_d (the lifting of the
+      // interior normal flux is part of the weak form)
+      for (int it = tid; it < EB * NU; it += NT) {
+        const int le = it / NU, s = it - le * NU, e = e0 + le;
+        if (e >= E) continue;
+        R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          row_cols<NU, 5>(ops + C::O_KU + (d * NU + s) * NU, FQ(le) + d * 5 * FQS, FQS, acc);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[v];
+      }
+      return;
+    }
     // M2 F~: reference normal flux at the own flux points, into the jump
     // region (free since the gradient phase)
     for (int it = tid; it < EB * NF; it += NT) {
       const int le = it / NF, fp = it - le * NF;
-      const R* nh = ops + C::O_N + 3 * (fp / NTN);
+      const R* nh = ops + C::O_N + 3 * C::face_of(fp);
       R nf[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -323,11 +352,11 @@ __global__ void __launch_bounds__(NT) tet_volume(const Seg sg, const bool from_u
 // comm_flux at every own flux point (both sides of a pair evaluate the same
 // expression on the same inputs and normal; each side scales by its own area
 // factor), then tdivtconf (M3) + negdivconf and the RK4 stage store
-template <int P, typename R, int EB, int NT>
-__global__ void __launch_bounds__(NT) tet_surface(const Seg sg, const int rk, const R* __restrict__ ops,
+template <int ET, int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, const R* __restrict__ ops,
                                                   const Gas<R> g) {
-  using C = TetCfg<P>;
-  constexpr int NU = C::NU, NTN = C::NTN, NF = C::NF, NFPS = C::NFPS;
+  using C = DenseCfg<ET, P>;
+  constexpr int NU = C::NU, NF = C::NF, NFPS = C::NFPS, NFACE = C::NFACE;
   __shared__ R sD[EB * 5 * NF];
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -337,8 +366,8 @@ __global__ void __launch_bounds__(NT) tet_surface(const Seg sg, const int rk, co
   for (int it = tid; it < EB * NF; it += NT) {
     const int le = it / NF, fp = it - le * NF, e = e0 + le;
     if (e >= E) continue;
-    const int f = fp / NTN, t = fp - f * NTN;
-    const int slot = sg.slot_base + e * 4 + f;
+    const int f = C::face_of(fp), t = C::point_of(fp);
+    const int slot = sg.slot_base + e * NFACE + f;
     const FaceRec fr = sg.faces[slot];
     const int rr = sg.perms[(fr.info >> 1) * NFPS + t];
     const bool left = fr.info & 1;
@@ -378,44 +407,59 @@ __global__ void __launch_bounds__(NT) tet_surface(const Seg sg, const int rk, co
 }
 
 // ------------------------------------------------------------ host side
-template <int P, typename R>
-static void pack_tet(const RefElem& r, R* o) {
-  using C = TetCfg<P>;
-  constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NTN = C::NTN, KG = C::KG;
+template <int ET, int P, typename R>
+static void pack_dense(const RefElem& r, R* o) {
+  using C = DenseCfg<ET, P>;
+  constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, KG = C::KG;
   for (int f = 0; f < NF; ++f)
     for (int u = 0; u < NU; ++u) o[C::O_M0 + f * NU + u] = R(r.M0[f * NU + u]);
   for (int d = 0; d < 3; ++d)
     for (int s = 0; s < NU; ++s) {
       R* row = o + C::O_G + (d * NU + s) * KG;
       for (int u = 0; u < NU; ++u) row[u] = R(r.Dg[(d * NU + s) * NU + u]);
-      for (int f = 0; f < NF; ++f) row[NU + f] = R(r.face_normal[3 * (f / NTN) + d] * r.M3[s * NF + f]);
+      for (int f = 0; f < NF; ++f) row[NU + f] = R(r.face_normal[3 * C::face_of(f) + d] * r.M3[s * NF + f]);
     }
   for (int q = 0; q < NQ; ++q)
     for (int u = 0; u < NU; ++u) o[C::O_M7 + q * NU + u] = R(r.M7[q * NU + u]);
   for (int i = 0; i < 3 * NU * NQ; ++i) o[C::O_AP + i] = R(r.APd[i]);
   for (int i = 0; i < NU * NF; ++i) o[C::O_M3 + i] = R(r.M3[i]);
-  for (int i = 0; i < 12; ++i) o[C::O_N + i] = R(r.face_normal[i]);
+  for (int i = 0; i < 3 * C::NFACE; ++i) o[C::O_N + i] = R(r.face_normal[i]);
+  if constexpr (C::PYR)
+    for (int i = 0; i < 3 * NU * NU; ++i) o[C::O_KU + i] = R(r.Ku[i]);
 }
 
-size_t tet_ops_bytes(int p, int prec) {
-  const size_t rs = prec == 0 ? 8 : 4;
+template <int ET>
+static size_t dense_size(int p) {
   switch (p) {
-    case 1: return rs * TetCfg<1>::SIZE;
-    case 2: return rs * TetCfg<2>::SIZE;
-    case 3: return rs * TetCfg<3>::SIZE;
-    case 4: return rs * TetCfg<4>::SIZE;
+    case 1: return DenseCfg<ET, 1>::SIZE;
+    case 2: return DenseCfg<ET, 2>::SIZE;
+    case 3: return DenseCfg<ET, 3>::SIZE;
+    case 4: return DenseCfg<ET, 4>::SIZE;
   }
   return 0;
 }
 
-void tet_ops_pack(const RefElem& r, int prec, void* dst) {
-  const bool d = prec == 0;
+size_t dense_ops_bytes(int etype, int p, int prec) {
+  const size_t rs = prec == 0 ? 8 : 4;
+  return rs * (etype == 3 ? dense_size<3>(p) : etype == 2 ? dense_size<2>(p) : 0);
+}
+
+template <int ET, typename R>
+static void pack_dense_p(const RefElem& r, R* dst) {
   switch (r.p) {
-    case 1: d ? pack_tet<1>(r, (double*)dst) : pack_tet<1>(r, (float*)dst); break;
-    case 2: d ? pack_tet<2>(r, (double*)dst) : pack_tet<2>(r, (float*)dst); break;
-    case 3: d ? pack_tet<3>(r, (double*)dst) : pack_tet<3>(r, (float*)dst); break;
-    case 4: d ? pack_tet<4>(r, (double*)dst) : pack_tet<4>(r, (float*)dst); break;
+    case 1: pack_dense<ET, 1>(r, dst); break;
+    case 2: pack_dense<ET, 2>(r, dst); break;
+    case 3: pack_dense<ET, 3>(r, dst); break;
+    case 4: pack_dense<ET, 4>(r, dst); break;
   }
+}
+
+void dense_ops_pack(const RefElem& r, int prec, void* dst) {
+  const bool d = prec == 0;
+  if (r.etype == 2)
+    d ? pack_dense_p<2>(r, (double*)dst) : pack_dense_p<2>(r, (float*)dst);
+  else if (r.etype == 3)
+    d ? pack_dense_p<3>(r, (double*)dst) : pack_dense_p<3>(r, (float*)dst);
 }
 
 template <typename R>
@@ -435,46 +479,53 @@ static Gas<R> make_gas_t(const GasHost& gh) {
 
 // elements per workgroup of the volume kernel: about one quadrature point per
 // thread (256 threads)
-template <int P>
-struct TetLaunch {
-  static constexpr int NQ = TetCfg<P>::NQ;
+template <int ET, int P>
+struct DenseLaunch {
+  static constexpr int NQ = DenseCfg<ET, P>::NQ;
   static constexpr int EB = NQ >= 256 ? 1 : (256 / NQ > 16 ? 16 : 256 / NQ);
 };
-constexpr int TET_DISU_EB = 8, TET_SURF_EB = 8;
+constexpr int DENSE_DISU_EB = 8, DENSE_SURF_EB = 8;
 
-template <int P, typename R>
-static hipError_t tet_rhs_t(const TypeArgs& a, hipStream_t st) {
+template <int ET, int P, typename R>
+static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
   const R* ops = (const R*)a.dops;
   const Gas<R> g = make_gas_t<R>(*a.gas);
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   const int E = a.one.E;
-  constexpr int EB = TetLaunch<P>::EB;
+  constexpr int EB = DenseLaunch<ET, P>::EB;
   if ((a.stage & 1) && E > 0)
-    hipLaunchKernelGGL((tet_disu<P, R, TET_DISU_EB, 256>), dim3((E + TET_DISU_EB - 1) / TET_DISU_EB), dim3(256), 0,
-                       st, a.one, a.from_ust, ops, eref);
+    hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
+                       dim3(256), 0, st, a.one, a.from_ust, ops, eref);
   if ((a.stage & 2) && E > 0) {
     if (a.aa)
-      hipLaunchKernelGGL((tet_volume<P, R, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
                          a.from_ust, ops, g, eref);
     else
-      hipLaunchKernelGGL((tet_volume<P, R, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
-                         a.from_ust, ops, g, eref);
+      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st,
+                         a.one, a.from_ust, ops, g, eref);
   }
   if ((a.stage & 4) && E > 0)
-    hipLaunchKernelGGL((tet_surface<P, R, TET_SURF_EB, 256>), dim3((E + TET_SURF_EB - 1) / TET_SURF_EB), dim3(256),
-                       0, st, a.one, a.rk, ops, g);
+    hipLaunchKernelGGL((dense_surface<ET, P, R, DENSE_SURF_EB, 256>), dim3((E + DENSE_SURF_EB - 1) / DENSE_SURF_EB),
+                       dim3(256), 0, st, a.one, a.rk, ops, g);
   return hipGetLastError();
 }
 
-hipError_t tet_rhs(const TypeArgs& a, int prec, hipStream_t st) {
-  if (!a.dops) return hipErrorInvalidValue;
+template <int ET>
+static hipError_t dense_rhs_e(const TypeArgs& a, int prec, hipStream_t st) {
   const bool d = prec == 0;
   switch (a.p) {
-    case 1: return d ? tet_rhs_t<1, double>(a, st) : tet_rhs_t<1, float>(a, st);
-    case 2: return d ? tet_rhs_t<2, double>(a, st) : tet_rhs_t<2, float>(a, st);
-    case 3: return d ? tet_rhs_t<3, double>(a, st) : tet_rhs_t<3, float>(a, st);
-    case 4: return d ? tet_rhs_t<4, double>(a, st) : tet_rhs_t<4, float>(a, st);
+    case 1: return d ? dense_rhs_t<ET, 1, double>(a, st) : dense_rhs_t<ET, 1, float>(a, st);
+    case 2: return d ? dense_rhs_t<ET, 2, double>(a, st) : dense_rhs_t<ET, 2, float>(a, st);
+    case 3: return d ? dense_rhs_t<ET, 3, double>(a, st) : dense_rhs_t<ET, 3, float>(a, st);
+    case 4: return d ? dense_rhs_t<ET, 4, double>(a, st) : dense_rhs_t<ET, 4, float>(a, st);
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t dense_rhs(int etype, const TypeArgs& a, int prec, hipStream_t st) {
+  if (!a.dops) return hipErrorInvalidValue;
+  if (etype == 2) return dense_rhs_e<2>(a, prec, st);
+  if (etype == 3) return dense_rhs_e<3>(a, prec, st);
   return hipErrorInvalidValue;
 }
 

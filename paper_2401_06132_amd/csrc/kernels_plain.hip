@@ -191,8 +191,15 @@ void build_plain_ops(const RefElem& r, PlainOps& o) {
   mat_mul_ld(M6ld.data(), 3 * nu, nf, r.M0.data(), nu, M6M0.data());
   o.G1.assign(3 * nu * nu, 0.0);
   for (int k = 0; k < 3 * nu * nu; ++k) o.G1[k] = (double)((long double)r.Dg[k] - M6M0[k]);
-  // K = (M1 - M3 M2) M9: for component d, (Dg_d - M3 N_d M0) M8, columns (d, q)
+  // K = (M1 - M3 M2) M9: for component d, (Dg_d - M3 N_d M0) M8, columns (d, q).
+  // Pyramids (space not closed under differentiation): the weak form AP_d.
   o.K.assign((size_t)nu * 3 * nq, 0.0);
+  if (r.etype == 3) {
+    for (int d = 0; d < 3; ++d)
+      for (int s = 0; s < nu; ++s)
+        for (int q = 0; q < nq; ++q) o.K[(size_t)s * 3 * nq + d * nq + q] = r.APd[((size_t)d * nu + s) * nq + q];
+    return;
+  }
   std::vector<long double> Ad(nu * nu), M3NM0(nu * nu), Kd(nu * nq), M3ld(r.M3.begin(), r.M3.end());
   std::vector<double> NM0(nf * nu);
   for (int d = 0; d < 3; ++d) {

@@ -15,7 +15,14 @@
 // swapped where that gives a negative Jacobian).  Opposite cell faces are cut
 // along parallel diagonals (conforming across cells and the period), and the
 // y faces along the prisms' diagonal (prism triangles meet tetrahedra in the
-// prism/tet mesh, prisms below y = 0).
+// prism/tet mesh, prisms below y = 0).  A pyramid cell holds six pyramids,
+// one on each cell face f (x-, x+, y-, y+, z-, z+), apex at the cell centre C:
+// reference (xi, eta, zeta) maps to B + xi e1 + eta e2 + (1+zeta)/2 (C - B),
+// B the face centre, e1, e2 the face's half edges ordered so that e1 x e2
+// points into the cell (x-: y, z; x+: z, y; y-: z, x; y+: x, z; z-: x, y;
+// z+: y, x).  Bases meet hexahedron faces or other bases; the triangles meet
+// the neighbouring pyramids of the same cell (hexahedra below z = 0 in the
+// hex/pyramid mesh).
 //
 // Connectivity: faces are paired by their centroids modulo the period, then
 // the points of each face pair are matched by coordinates (section 2.1: paired
@@ -60,8 +67,10 @@ static int parallel_chunks(int64_t n, F body) {
 
 // element type of cell (j, k): kind 2 has hexahedra where the cell centre
 // has z < 0 and prisms elsewhere; kind 4 prisms where y < 0, tetrahedra
-// elsewhere
+// elsewhere; kind 9 hexahedra where z < 0, pyramids elsewhere
 static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kind) {
+  if (kind == 8) return 3;
+  if (kind == 9) return cell_type(j, k, ny, nz, lo, hi, 2) == 0 ? 0 : 3;
   if (kind == 2) {
     const double hz = (hi - lo) / nz;
     return (lo + k * hz) + 0.5 * hz < 0.0 ? 0 : 1;
@@ -74,7 +83,7 @@ static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kin
   return kind == 3 ? 2 : (kind >= 5 ? kind - 5 : kind);
 }
 
-static constexpr int kPerCell[NTYPES] = {1, 2, 6};
+static constexpr int kPerCell[NTYPES] = {1, 2, 6, 6};
 
 void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t nel[NTYPES]) {
   for (int t = 0; t < NTYPES; ++t) nel[t] = 0;
@@ -186,7 +195,21 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
         double x0[3] = {lo + i * h[0], lo + j * h[1], lo + k * h[2]};
         int t = cell_type(j, k, ny, nz, lo, hi, kind);
         double c[3] = {x0[0] + 0.5 * h[0], x0[1] + 0.5 * h[1], x0[2] + 0.5 * h[2]};
-        if (t == 2) {
+        if (t == 3) {
+          for (int ax = 0; ax < 3; ++ax)
+            for (int sg = 0; sg < 2; ++sg) {
+              int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+              // e1 x e2 along the inward normal -(2 sg - 1) e_ax
+              if ((sg == 0) != (ax != 1)) std::swap(t1, t2);
+              double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+              J[3 * t1 + 0] = 0.5 * h[t1];
+              J[3 * t2 + 1] = 0.5 * h[t2];
+              J[3 * ax + 2] = (sg ? -0.25 : 0.25) * h[ax];  // (C - B)/2
+              for (int d = 0; d < 3; ++d) M.org[3].push_back(c[d] + (d == ax ? (sg ? 0.25 : -0.25) * h[ax] : 0.0));
+              M.jac[3].insert(M.jac[3].end(), J, J + 9);
+              M.gid[3].push_back(g++);
+            }
+        } else if (t == 2) {
           double P[6][4][3];
           kuhn_tets(x0, h, P);
           for (int o = 0; o < 6; ++o) {

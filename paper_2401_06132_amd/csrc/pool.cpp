@@ -75,7 +75,7 @@ class Arena {
 
 // byte offsets of one request's arrays inside its arena block
 struct Layout {
-  int64_t nel[fr::NTYPES] = {0, 0, 0}, nu[2] = {0, 0}, n_state = 0, nslots = 0, nfp = 0;
+  int64_t nel[fr::NTYPES] = {}, nu[2] = {0, 0}, n_state = 0, nslots = 0, nfp = 0;
   size_t state = 0, ust = 0, acc = 0, Rp = 0, Uf = 0, Vf = 0, faces = 0, fgeo = 0, perms = 0;
   size_t met[2] = {0, 0}, detj[2] = {0, 0}, total = 0;
 };
@@ -282,7 +282,7 @@ fr_status check_request(fr_pool* P, const fr_request* q) {
   if (!q) return pfail(P, FR_EINVAL, "null request");
   if (q->nx < 1 || q->ny < 1 || q->nz < 1 || !(q->hi > q->lo) || q->kind < 0 || q->kind >= fr::kNumKinds)
     return pfail(P, FR_EINVAL, "bad mesh size");
-  if (q->kind == FR_MESH_TET || q->kind == FR_MESH_PRISM_TET || fr::kind_curved(q->kind))
+  if (fr::kind_dense(q->kind) || fr::kind_curved(q->kind))
     return pfail(P, FR_EUNSUPPORTED, "the pool serves affine hexahedra and prisms");
   if (q->p < 1 || q->p > 4) return pfail(P, FR_EUNSUPPORTED, "order must be 1..4");
   if (q->nsteps < 0 || !std::isfinite(q->dt)) return pfail(P, FR_EINVAL, "bad step");
@@ -343,7 +343,7 @@ void worker_main(fr_pool* P) {
     P->prep_q.pop_front();
     P->in_flight = id;
     const fr_request q = P->reqs.at(id)->q;
-    const fr::RefElem* refs[fr::NTYPES] = {&P->ref[0][q.p], &P->ref[1][q.p], nullptr};
+    const fr::RefElem* refs[fr::NTYPES] = {&P->ref[0][q.p], &P->ref[1][q.p], nullptr, nullptr};
     const int rs = P->rs;
     lk.unlock();
     std::shared_ptr<Prepared> r = prepare(q, refs, rs, P->ph.surface_aa != 0);
@@ -373,7 +373,7 @@ std::shared_ptr<Prepared> take_prepared(fr_pool* P, int64_t id) {
     auto qi = std::find(P->prep_q.begin(), P->prep_q.end(), id);
     if (qi != P->prep_q.end()) P->prep_q.erase(qi);
     const fr_request q = P->reqs.at(id)->q;
-    const fr::RefElem* refs[fr::NTYPES] = {&P->ref[0][q.p], &P->ref[1][q.p], nullptr};
+    const fr::RefElem* refs[fr::NTYPES] = {&P->ref[0][q.p], &P->ref[1][q.p], nullptr, nullptr};
     const int rs = P->rs;
     lk.unlock();
     return prepare(q, refs, rs, P->ph.surface_aa != 0);

@@ -321,6 +321,11 @@ static const double kTetV[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, 
 // faces: the vertices the reference triangle's (-1,-1), (1,-1), (-1,1) map to
 static const int kTetFace[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
 
+// Pyramid: square base [-1,1]^2 at zeta = -1 (face 0), apex (0,0,1); the
+// triangles (faces 1..4) run round the base counter-clockwise seen from above
+static const double kPyrV[5][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1}, {0, 0, 1}};
+static const int kPyrFace[4][3] = {{0, 1, 4}, {1, 2, 4}, {2, 3, 4}, {3, 0, 4}};
+
 // solution points: barycentric Blyth-Pozrikidis-type construction on the GL
 // master grid v = (1 + GL(p+1))/2: for i + j + k + l = p,
 // lambda_a = (1 + 4 v_a - (v_i + v_j + v_k + v_l))/4 (l for V0, i, j, k for V1..V3)
@@ -415,21 +420,107 @@ static void tet_basis(int p, const xreal* y, xreal* v, xreal* g0, xreal* g1, xre
       }
 }
 
-static void build_tet(int p, RefElem& r) {
+// pyramid solution points (a reading; the paper prints none): p+1 layers at
+// the Gauss-Legendre(p+1) heights zeta_l in increasing order, layer l holding
+// the tensor Gauss-Legendre(p+1-l) grid of the collapsed coordinates
+// (a, b) = (2 xi, 2 eta)/(1 - zeta); every layer is unisolvent for Q_{p-l} in
+// (a, b), which makes the set unisolvent for the pyramid space
+static void pyr_nodes(int p, std::vector<double>& x) {
+  x.clear();
+  std::vector<double> t, tw;
+  gauss_legendre(p + 1, t, tw);
+  for (int l = 0; l <= p; ++l) {
+    std::vector<double> g, gw;
+    gauss_legendre(p + 1 - l, g, gw);
+    const double s = 0.5 * (1.0 - t[l]);
+    for (int j = 0; j <= p - l; ++j)
+      for (int i = 0; i <= p - l; ++i) {
+        x.push_back(g[i] * s);
+        x.push_back(g[j] * s);
+        x.push_back(t[l]);
+      }
+  }
+}
+
+// basis of the pyramid space (rational; Bergot, Cohen and Durufle 2010): in
+// the collapsed coordinates a = 2 xi/(1-zeta), b = 2 eta/(1-zeta), c = zeta,
+// P_i(a) P_j(b) (1-c)^max(i,j) P_k(c) for i, j <= p, k <= p - max(i,j).  It
+// contains P_p, its trace is Q_p on the base and P_p on each triangle.  Its
+// gradient by the chain rule: d a/d xi = 2/(1-c), d a/d zeta = a/(1-c), and
+// likewise for b.  Never evaluated at the apex.
+static void pyr_basis(int p, const xreal* y, xreal* v, xreal* g0, xreal* g1, xreal* g2) {
+  const xreal om = 1.0L - y[2], a = 2.0L * y[0] / om, b = 2.0L * y[1] / om;
+  xreal Pa[8], dPa[8], Pb[8], dPb[8], Pc[8], dPc[8];
+  legendre_x(p, a, Pa, dPa);
+  legendre_x(p, b, Pb, dPb);
+  legendre_x(p, y[2], Pc, dPc);
+  int k = 0;
+  for (int j = 0; j <= p; ++j)
+    for (int i = 0; i <= p; ++i) {
+      const int mu = std::max(i, j);
+      xreal omu = 1.0L;
+      for (int e = 0; e < mu; ++e) omu *= om;
+      for (int l = 0; l + mu <= p; ++l) {
+        const xreal C = omu * Pc[l];
+        const xreal dC = omu * dPc[l] - (mu > 0 ? mu * (omu / om) * Pc[l] : 0.0L);
+        v[k] = Pa[i] * Pb[j] * C;
+        g0[k] = dPa[i] * Pb[j] * C * 2.0L / om;
+        g1[k] = Pa[i] * dPb[j] * C * 2.0L / om;
+        g2[k] = (dPa[i] * a * Pb[j] + Pa[i] * dPb[j] * b) * C / om + Pa[i] * Pb[j] * dC;
+        ++k;
+      }
+    }
+}
+
+// Lagrange polynomial j through the nodes x, at y (extended precision)
+static xreal lagrange_x(const std::vector<double>& x, int j, xreal y) {
+  xreal v = 1.0L;
+  for (size_t k = 0; k < x.size(); ++k)
+    if ((int)k != j) v *= (y - (xreal)x[k]) / ((xreal)x[j] - (xreal)x[k]);
+  return v;
+}
+
+// Tetrahedra (etype 2) and pyramids (etype 3): no tensor structure, so the
+// operators are dense, from the Vandermonde inverse of the element's basis.
+// Pyramid faces: the base (GL(n)^2 flux points, index a + n b over
+// (xi, eta)) and four triangles; tetrahedron faces: four triangles; each
+// triangle carries the triangle nodes mapped from the reference triangle's
+// (-1,-1), (1,-1), (-1,1) to the face's listed vertices.  AP_d is the weak
+// form -Mass^-1 Dq_d^T W_q; for tetrahedra it equals (M1 - M3 M2) M9, for
+// pyramids (whose space is not closed under differentiation) it is the
+// divergence by definition, and Ku_d = AP_d M7 is its form without
+// anti-aliasing.
+static void build_dense(int etype, int p, RefElem& r) {
   build_tri(p, r.line, r.tri);
   const Tri& T = r.tri;
-  const int nt = T.nt, nu = (p + 1) * (p + 2) * (p + 3) / 6;
+  const Line1D& L = r.line;
+  const bool pyr = etype == 3;
+  const int n = p + 1, nt = T.nt;
+  const int nu = pyr ? n * (n + 1) * (2 * n + 1) / 6 : n * (n + 1) * (n + 2) / 6;
+  const int ntri = 4;
   r.nu = nu;
-  r.nfaces = 4;
-  r.nfp_max = nt;
-  tet_nodes(p, r.upts);
-  for (int f = 0; f < 4; ++f) {
-    const double* A = kTetV[kTetFace[f][0]];
-    const double* B = kTetV[kTetFace[f][1]];
-    const double* C = kTetV[kTetFace[f][2]];
+  r.nfaces = pyr ? 5 : 4;
+  r.nfp_max = pyr ? n * n : nt;
+  if (pyr)
+    pyr_nodes(p, r.upts);
+  else
+    tet_nodes(p, r.upts);
+  const double cen[3] = {pyr ? 0.0 : -0.5, pyr ? 0.0 : -0.5, -0.5};  // reference centroid
+  if (pyr) {
+    r.face_start.push_back(0);
+    r.face_npts.push_back(n * n);
+    r.face_normal.insert(r.face_normal.end(), {0.0, 0.0, -1.0});
+    r.face_jac.push_back(1.0);
+    for (int b = 0; b < n; ++b)
+      for (int a = 0; a < n; ++a) r.fpts.insert(r.fpts.end(), {L.x[a], L.x[b], -1.0});
+  }
+  for (int f = 0; f < ntri; ++f) {
+    const double* A = pyr ? kPyrV[kPyrFace[f][0]] : kTetV[kTetFace[f][0]];
+    const double* B = pyr ? kPyrV[kPyrFace[f][1]] : kTetV[kTetFace[f][1]];
+    const double* C = pyr ? kPyrV[kPyrFace[f][2]] : kTetV[kTetFace[f][2]];
     r.face_start.push_back((int)r.fpts.size() / 3);
     r.face_npts.push_back(nt);
-    // outward unit normal: (B - A) x (C - A), oriented away from the opposite vertex
+    // outward unit normal: (B - A) x (C - A), oriented away from the centroid
     double e1[3], e2[3], nr[3];
     for (int d = 0; d < 3; ++d) {
       e1[d] = B[d] - A[d];
@@ -439,9 +530,8 @@ static void build_tet(int p, RefElem& r) {
     nr[1] = e1[2] * e2[0] - e1[0] * e2[2];
     nr[2] = e1[0] * e2[1] - e1[1] * e2[0];
     const double len = std::sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
-    const int opp = 6 - kTetFace[f][0] - kTetFace[f][1] - kTetFace[f][2];
     double side = 0;
-    for (int d = 0; d < 3; ++d) side += nr[d] * (kTetV[opp][d] - A[d]);
+    for (int d = 0; d < 3; ++d) side += nr[d] * (cen[d] - A[d]);
     const double sgn = side > 0 ? -1.0 : 1.0;
     for (int d = 0; d < 3; ++d) r.face_normal.push_back(sgn * nr[d] / len);
     r.face_jac.push_back(0.25 * len);  // face area / reference triangle area (2)
@@ -451,7 +541,7 @@ static void build_tet(int p, RefElem& r) {
       for (int d = 0; d < 3; ++d) r.fpts.push_back(la * A[d] + lb * B[d] + lc * C[d]);
     }
   }
-  // conical-product rule with (p+1)^3 points (degree 2p+1)
+  // conical-product rules with (p+1)^3 points (degree 2p+1)
   {
     const int k = p + 1;
     std::vector<double> a, wa, b, wb, c, wc;
@@ -461,26 +551,39 @@ static void build_tet(int p, RefElem& r) {
     for (int l = 0; l < k; ++l)
       for (int j = 0; j < k; ++j)
         for (int i = 0; i < k; ++i) {
-          r.qpts.push_back(0.25 * (1 + a[i]) * (1 - b[j]) * (1 - c[l]) - 1.0);
-          r.qpts.push_back(0.5 * (1 + b[j]) * (1 - c[l]) - 1.0);
-          r.qpts.push_back(c[l]);
-          r.qwts.push_back(wa[i] * wb[j] * wc[l] / 8.0);
+          if (pyr) {
+            // xi = a (1-c)/2, eta = b (1-c)/2, zeta = c; dV = (1-c)^2/4
+            const double s = 0.5 * (1 - c[l]);
+            r.qpts.insert(r.qpts.end(), {a[i] * s, a[j] * s, c[l]});
+            r.qwts.push_back(wa[i] * wa[j] * wc[l] / 4.0);
+          } else {
+            r.qpts.push_back(0.25 * (1 + a[i]) * (1 - b[j]) * (1 - c[l]) - 1.0);
+            r.qpts.push_back(0.5 * (1 + b[j]) * (1 - c[l]) - 1.0);
+            r.qpts.push_back(c[l]);
+            r.qwts.push_back(wa[i] * wb[j] * wc[l] / 8.0);
+          }
         }
   }
   r.nf = (int)r.fpts.size() / 3;
   r.nq = (int)r.qwts.size();
   const int nf = r.nf, nq = r.nq;
+  auto basis = [&](const xreal* y, xreal* v, xreal* g0, xreal* g1, xreal* g2) {
+    if (pyr)
+      pyr_basis(p, y, v, g0, g1, g2);
+    else
+      tet_basis(p, y, v, g0, g1, g2);
+  };
   // nodal basis l_u(y) = sum_k psi_k(y) Vi[k][u]
   std::vector<xreal> V(nu * nu), v(nu), g0(nu), g1(nu), g2(nu);
   for (int u = 0; u < nu; ++u) {
     const xreal y[3] = {r.upts[3 * u], r.upts[3 * u + 1], r.upts[3 * u + 2]};
-    tet_basis(p, y, v.data(), g0.data(), g1.data(), g2.data());
+    basis(y, v.data(), g0.data(), g1.data(), g2.data());
     for (int k = 0; k < nu; ++k) V[u * nu + k] = v[k];
   }
   const std::vector<xreal> Vi = inverse_x(V, nu);
   auto nodal = [&](const double* yd, xreal* l, xreal* d0, xreal* d1, xreal* d2) {
     const xreal y[3] = {yd[0], yd[1], yd[2]};
-    tet_basis(p, y, v.data(), g0.data(), g1.data(), g2.data());
+    basis(y, v.data(), g0.data(), g1.data(), g2.data());
     for (int u = 0; u < nu; ++u) {
       xreal s = 0, s0 = 0, s1 = 0, s2 = 0;
       for (int k = 0; k < nu; ++k) {
@@ -518,7 +621,7 @@ static void build_tet(int p, RefElem& r) {
   r.mass = rounded(mass);
   const std::vector<xreal> Mi = inverse_x(mass, nu);
   r.M8.assign(nu * nq, 0);
-  r.APd.assign(3 * nu * nq, 0);
+  std::vector<xreal> AP(3 * nu * nq);
   std::vector<xreal> wu(nu, 0.0L);
   for (int u = 0; u < nu; ++u) {
     for (int q = 0; q < nq; ++q) {
@@ -532,32 +635,59 @@ static void build_tet(int p, RefElem& r) {
       }
       const xreal wq = r.qwts[q];
       r.M8[u * nq + q] = (double)(s * wq);
-      r.APd[(0 * nu + u) * nq + q] = (double)(-s0 * wq);
-      r.APd[(1 * nu + u) * nq + q] = (double)(-s1 * wq);
-      r.APd[(2 * nu + u) * nq + q] = (double)(-s2 * wq);
+      AP[(0 * nu + u) * nq + q] = -s0 * wq;
+      AP[(1 * nu + u) * nq + q] = -s1 * wq;
+      AP[(2 * nu + u) * nq + q] = -s2 * wq;
       wu[u] += M7[q * nu + u] * wq;
     }
   }
+  r.APd = rounded(AP);
   r.wu = rounded(wu);
+  if (pyr) {
+    r.Ku.assign(3 * nu * nu, 0);
+    for (int d = 0; d < 3; ++d)
+      for (int s = 0; s < nu; ++s)
+        for (int u = 0; u < nu; ++u) {
+          xreal acc = 0;
+          for (int q = 0; q < nq; ++q) acc += AP[(d * nu + s) * nq + q] * M7[q * nu + u];
+          r.Ku[(d * nu + s) * nu + u] = (double)acc;
+        }
+  }
   // DG lifting: E[u, f] = int_face l_u l^face_f dS_ref, with the triangle
-  // rule mapped onto each face; M3 = Mass^-1 E
+  // rule mapped onto each triangle and GL(n+1)^2 on the base; M3 = Mass^-1 E
   std::vector<xreal> Ef(nu * nf, 0.0L), lf(nu);
-  for (int f = 0; f < 4; ++f) {
-    const double* A = kTetV[kTetFace[f][0]];
-    const double* B = kTetV[kTetFace[f][1]];
-    const double* C = kTetV[kTetFace[f][2]];
+  const int f0 = pyr ? 1 : 0;
+  for (int f = 0; f < ntri; ++f) {
+    const double* A = pyr ? kPyrV[kPyrFace[f][0]] : kTetV[kTetFace[f][0]];
+    const double* B = pyr ? kPyrV[kPyrFace[f][1]] : kTetV[kTetFace[f][1]];
+    const double* C = pyr ? kPyrV[kPyrFace[f][2]] : kTetV[kTetFace[f][2]];
     for (int q = 0; q < T.ntq; ++q) {
       const double s = T.qp[2 * q], u = T.qp[2 * q + 1];
       const double la = -(s + u) / 2.0, lb = (1.0 + s) / 2.0, lc = (1.0 + u) / 2.0;
       double y[3];
       for (int d = 0; d < 3; ++d) y[d] = la * A[d] + lb * B[d] + lc * C[d];
       nodal(y, lf.data(), nullptr, nullptr, nullptr);
-      const xreal w = (xreal)T.qw[q] * (xreal)r.face_jac[f];
+      const xreal w = (xreal)T.qw[q] * (xreal)r.face_jac[f0 + f];
       for (int t = 0; t < nt; ++t) {
         const xreal wt = w * (xreal)T.Tq[q * nt + t];
-        for (int uu = 0; uu < nu; ++uu) Ef[uu * nf + r.face_start[f] + t] += lf[uu] * wt;
+        for (int uu = 0; uu < nu; ++uu) Ef[uu * nf + r.face_start[f0 + f] + t] += lf[uu] * wt;
       }
     }
+  }
+  if (pyr) {
+    std::vector<double> g, gw;
+    gauss_legendre(n + 1, g, gw);
+    for (int qb = 0; qb <= n; ++qb)
+      for (int qa = 0; qa <= n; ++qa) {
+        const double y[3] = {g[qa], g[qb], -1.0};
+        nodal(y, lf.data(), nullptr, nullptr, nullptr);
+        const xreal w = (xreal)gw[qa] * (xreal)gw[qb];
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            const xreal wt = w * lagrange_x(L.x, a, g[qa]) * lagrange_x(L.x, b, g[qb]);
+            for (int uu = 0; uu < nu; ++uu) Ef[uu * nf + a + n * b] += lf[uu] * wt;
+          }
+      }
   }
   r.M3.assign(nu * nf, 0);
   for (int u = 0; u < nu; ++u)
@@ -589,8 +719,8 @@ void build_ref(int etype, int p, RefElem& r) {
   r.face_npts.clear();
   r.face_normal.clear();
   r.face_jac.clear();
-  if (etype == 2) {
-    build_tet(p, r);
+  if (etype >= 2) {
+    build_dense(etype, p, r);
     return;
   }
   if (etype == 0) {

@@ -90,7 +90,8 @@ def test_rhs_parity(dims, p, kind, prec):
 
 
 @pytest.mark.parametrize("dims,p,kind", [((4, 4, 4), 3, "hex"), ((2, 2, 2), 3, "prism"), ((2, 2, 4), 2, "mixed"),
-                                         ((2, 3, 3), 4, "hex"), ((2, 2, 2), 3, "tet"), ((2, 3, 2), 2, "prism_tet")])
+                                         ((2, 3, 3), 4, "hex"), ((2, 2, 2), 3, "tet"), ((2, 3, 2), 2, "prism_tet"),
+                                         ((2, 2, 2), 3, "pyr"), ((2, 3, 2), 2, "hex_pyr")])
 def test_plain_path_parity(dims, p, kind):
     """The unfused FP64 comparison path (dense operators, library GEMMs)."""
     _need_gpu()
@@ -105,7 +106,7 @@ def test_plain_path_parity(dims, p, kind):
     assert np.all(err < tol), (err, tol)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "pyr", "hex_pyr"])
 def test_fused_matches_plain_on_gpu(kind):
     """Fused and plain GPU paths on a medium mesh (several workgroups and a
     ragged last block), FP64."""
@@ -174,7 +175,8 @@ def test_rhs_is_deterministic():
 NOAA_CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"), ((2, 3, 3), 4, "hex"),
               ((1, 1, 1), 3, "hex"), ((5, 1, 2), 2, "hex"), ((2, 2, 2), 3, "prism"), ((3, 2, 2), 1, "prism"),
               ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"), ((2, 2, 4), 3, "mixed"), ((2, 1, 2), 2, "mixed"),
-              ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"), ((2, 2, 2), 1, "tet"), ((2, 3, 2), 2, "prism_tet")]
+              ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"), ((2, 2, 2), 1, "tet"), ((2, 3, 2), 2, "prism_tet"),
+              ((2, 2, 2), 3, "pyr"), ((1, 2, 2), 4, "pyr"), ((2, 2, 2), 1, "pyr"), ((2, 3, 2), 2, "hex_pyr")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -275,18 +277,20 @@ def test_full_aa_free_stream_conservation_and_rk4(kind):
 
 
 
-TET_CASES = [((2, 2, 2), 1, "tet"), ((2, 2, 2), 2, "tet"), ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"),
-             ((3, 2, 1), 3, "tet"), ((1, 1, 1), 2, "tet"), ((2, 2, 2), 3, "prism_tet"), ((2, 3, 2), 2, "prism_tet"),
-             ((1, 2, 1), 4, "prism_tet")]
+DENSE_CASES = [((2, 2, 2), 1, "tet"), ((2, 2, 2), 2, "tet"), ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"),
+               ((3, 2, 1), 3, "tet"), ((1, 1, 1), 2, "tet"), ((2, 2, 2), 3, "prism_tet"), ((2, 3, 2), 2, "prism_tet"),
+               ((1, 2, 1), 4, "prism_tet"), ((2, 2, 2), 1, "pyr"), ((2, 2, 2), 2, "pyr"), ((2, 2, 2), 3, "pyr"),
+               ((1, 2, 2), 4, "pyr"), ((3, 2, 1), 3, "pyr"), ((1, 1, 1), 2, "pyr"), ((2, 2, 4), 3, "hex_pyr"),
+               ((2, 3, 2), 2, "hex_pyr"), ((1, 2, 2), 4, "hex_pyr")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("dims,p,kind", TET_CASES)
-def test_rhs_parity_tetrahedra(dims, p, kind, prec):
-    """Tetrahedral and prism/tetrahedron meshes (dense-operator kernels)
-    against the oracle; same tolerances."""
+@pytest.mark.parametrize("dims,p,kind", DENSE_CASES)
+def test_rhs_parity_tets_and_pyramids(dims, p, kind, prec):
+    """Tetrahedral, pyramid and mixed prism/tetrahedron and hexahedron/pyramid
+    meshes (dense-operator kernels) against the oracle; same tolerances."""
     _need_gpu()
-    print("tet case", dims, p, kind, prec, flush=True)
+    print("dense case", dims, p, kind, prec, flush=True)
     m, U = _case(dims, p, kind)
     r64, rld = _references(m, U)
     got, _ = _gpu_rhs(dims, p, kind, prec, U)
@@ -299,8 +303,8 @@ def test_rhs_parity_tetrahedra(dims, p, kind, prec):
     assert np.all(err < tol), (err, tol)
 
 
-@pytest.mark.parametrize("kind", ["tet", "prism_tet"])
-def test_tet_free_stream_conservation_and_rk4(kind):
+@pytest.mark.parametrize("kind", ["tet", "prism_tet", "pyr", "hex_pyr"])
+def test_dense_free_stream_conservation_and_rk4(kind):
     _need_gpu()
     dims, p = (2, 2, 2), 3
     s = frmi.Solver(dims, p, kind, pref=inputs.P0)
@@ -319,7 +323,7 @@ def test_tet_free_stream_conservation_and_rk4(kind):
     for got, t, x in zip(s.split(s.get_state()), m.types, U):
         d_ref = Uo[t] - x
         err = np.abs((got - x) - d_ref).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
-        print("tet rk4 rel err of the state change", t, err)
+        print(kind, "rk4 rel err of the state change", t, err)
         assert np.all(err < 1e-11)
     c1 = s.integrals()
     assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max())

@@ -35,20 +35,23 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(frmi.SYMBOLS)
 
 
-@pytest.mark.parametrize("etype,name", [(0, "hex"), (1, "prism"), (2, "tet")])
+@pytest.mark.parametrize("etype,name", [(0, "hex"), (1, "prism"), (2, "tet"), (3, "pyr")])
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_reference_operators_match_oracle(etype, name, p):
     _lib_or_skip()
     r = RefElement(name, p)
     pairs = [("upts", r.upts), ("fpts", r.fpts), ("qpts", r.qpts), ("qwts", r.qwts), ("M0", r.M0), ("M3", r.M3),
              ("M7", r.M7), ("M8", r.M8), ("wu", r.wu), ("Dxi", r.Dg[0]), ("Deta", r.Dg[1]), ("Dzeta", r.Dg[2])]
+    if name == "pyr":
+        pairs += [("APd", r.Kq), ("Ku", r.Ku)]
     for key, ref in pairs:
         got = frmi.ref_operator(etype, p, key).reshape(ref.shape)
         scale = max(1.0, np.abs(ref).max())
         np.testing.assert_allclose(got, ref, atol=5e-14 * scale, err_msg=key)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp", "prism_warp", "mixed_warp"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp", "prism_warp", "mixed_warp",
+                                  "pyr", "hex_pyr"])
 def test_mesh_coordinates_and_connectivity_match_oracle(kind):
     _lib_or_skip()
     dims = (3, 2, 4)
@@ -88,8 +91,9 @@ def test_surface_aa_rejected_where_not_built():
             frmi.Solver((2, 2, 2), 3, kind, aa=False)
         with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
             frmi.Solver((2, 2, 2), 3, kind, form="plain")
-    with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
-        frmi.Solver((2, 2, 2), 3, "tet", surface_aa=True)
+    for kind in ("tet", "pyr", "hex_pyr"):
+        with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
+            frmi.Solver((2, 2, 2), 3, kind, surface_aa=True)
     frmi.Solver((2, 2, 2), 3, "tet", aa=False)
     frmi.Solver((2, 2, 2), 3, "prism_tet", form="plain")
     with pytest.raises(frmi.FrError, match="FR_EUNSUPPORTED"):
@@ -98,16 +102,16 @@ def test_surface_aa_rejected_where_not_built():
         frmi.Solver((2, 2, 2), 3, kind, surface_aa=True)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "pyr", "hex_pyr"])
 def test_element_counts_match_oracle(kind):
-    """The library's element counts per type (hexahedra, prisms, tetrahedra)
-    and its pairing match the oracle's."""
+    """The library's element counts per type (hexahedra, prisms, tetrahedra,
+    pyramids) and its pairing match the oracle's."""
     _lib_or_skip()
     dims = (2, 3, 2)
     s = frmi.Solver(dims, 2, kind)
     m = Mesh(*dims, 2, kind)
-    counts = {"hex": s.n_hex, "prism": s.n_prism, "tet": s.n_tet}
-    for t in ("hex", "prism", "tet"):
+    counts = {"hex": s.n_hex, "prism": s.n_prism, "tet": s.n_tet, "pyr": s.n_pyr}
+    for t in ("hex", "prism", "tet", "pyr"):
         assert counts[t] == m.nelem.get(t, 0)
     nbr, isl = s.connectivity()
     np.testing.assert_array_equal(nbr, m.partner)

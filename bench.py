@@ -112,7 +112,7 @@ def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex
         torch.cuda.synchronize()
         vol_ms = e0.elapsed_time(e1) / steps
     ok = bool(torch.isfinite(du).all().item())
-    res = dict(n_dof=s.n_state, n_elem=s.n_hex + s.n_prism + s.n_tet, wall_s=wall, ms_per_step=wall * 1e3 / steps,
+    res = dict(n_dof=s.n_state, n_elem=s.n_hex + s.n_prism + s.n_tet + s.n_pyr, wall_s=wall, ms_per_step=wall * 1e3 / steps,
                p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), vol_ms=vol_ms,
                finite=ok)
     del s, u, du
@@ -149,7 +149,7 @@ def run_rk(frmi, torch, kind, n, p, prec, nsteps, dt):
     scale = np.array([abs(c0[0]), abs(c0[0]), abs(c0[0]), abs(c0[0]), abs(c0[4])])
     out = dict(workload="Taylor-Green vortex, %d^3-cell periodic box, %s, p=%d, %s, %d RK4 steps of dt=%g"
                % (n, kind, p, prec, nsteps + 1, dt),
-               elements=s.n_hex + s.n_prism + s.n_tet, n_hex=s.n_hex, n_prism=s.n_prism, dof=s.n_state,
+               elements=s.n_hex + s.n_prism + s.n_tet + s.n_pyr, n_hex=s.n_hex, n_prism=s.n_prism, dof=s.n_state,
                ms_per_step=wall * 1e3 / nsteps, p50_step_ms=float(np.percentile(per, 50)),
                p99_step_ms=float(np.percentile(per, 99)),
                gdof_rhs_s=s.n_state * 4 * nsteps / wall / 1e9, finite=finite,
@@ -319,6 +319,9 @@ def main():
         ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
         ("fp64", 4, "fullaa", "hex"), ("fp32", 3, "fullaa", "prism"), ("fp32", 4, "fullaa", "prism"),
         ("fp32", 3, "fused", "tet"), ("fp64", 3, "fused", "tet"), ("fp32", 4, "fused", "tet"),
+        ("fp32", 3, "noaa", "tet"), ("fp64", 3, "plain", "tet"),
+        ("fp32", 3, "fused", "pyr"), ("fp64", 3, "fused", "pyr"), ("fp32", 4, "fused", "pyr"),
+        ("fp32", 3, "noaa", "pyr"), ("fp64", 3, "plain", "pyr"),
         ("fp32", 3, "fused", "hex_warp"), ("fp64", 3, "fused", "hex_warp"), ("fp32", 4, "fused", "hex_warp"),
         ("fp32", 3, "fused", "prism_warp"), ("fp32", 4, "fused", "prism_warp")]
     for prec, p, form, kind in order:

@@ -58,13 +58,23 @@ struct DenseCfg {
   static constexpr int SZ_X = 20 * NU, SZ_J = 5 * NF, SZ_F = 15 * FQS;
   static constexpr int PER_ELEM = SZ_X + SZ_J + SZ_F;
   // face f and point t within the face of flux point fp
-  __host__ __device__ static constexpr int face_of(int fp) { return fp < NB ? 0 : PYR + (fp - NB) / NTN; }
-  __host__ __device__ static constexpr int point_of(int fp) { return fp < NB ? fp : (fp - NB) % NTN; }
+  // (branch-free: with a select here the compiler kept the operator loops of
+  // both cases live in the callers, tripling their registers)
+  __host__ __device__ static constexpr int face_of(int fp) {
+    const int g = fp - NB, base = g >> 31;  // -1 on the base, 0 on a triangle
+    return (int(PYR) + g / NTN) & ~base;
+  }
+  __host__ __device__ static constexpr int point_of(int fp) {
+    const int g = fp - NB, base = g >> 31;
+    return (fp & base) | ((g % NTN) & ~base);
+  }
 };
 
 // acc[c] += sum_k A[k] B[c * ldb + k] (k < K, c < NC): a row A of a dense
 // operator (device memory, read KC entries at a time) against NC columns of
-// one element in LDS
+// one element in LDS.  The scheduling barrier after each column stops the
+// compiler from hoisting the LDS reads of all columns ahead of their use,
+// which spilled registers for the longer rows.
 template <int K, int NC, typename R>
 __device__ __forceinline__ void row_cols(const R* __restrict__ A, const R* B, int ldb, R (&acc)[NC]) {
   constexpr int KC = 32;
@@ -75,10 +85,12 @@ __device__ __forceinline__ void row_cols(const R* __restrict__ A, const R* B, in
     for (int k = 0; k < KC; ++k)
       if (k0 + k < K) a[k] = A[k0 + k];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
       for (int k = 0; k < KC; ++k)
         if (k0 + k < K) acc[c] += a[k] * B[c * ldb + k0 + k];
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -399,7 +411,18 @@ __global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, 
     R acc[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) acc[v] = Rp[(size_t)e * 5 * NU + v * NU + s];
-    row_cols<NF, 5>(ops + C::O_M3 + s * NF, sD + le * 5 * NF, NF, acc);
+    {
+      // lifting row (a plain partly unrolled loop: the fully unrolled product
+      // ahead of the RK store needed all registers)
+      const R* Arow = ops + C::O_M3 + s * NF;
+      const R* Bv = sD + le * 5 * NF;
+#pragma unroll 4
+      for (int k = 0; k < NF; ++k) {
+        const R w = Arow[k];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += w * Bv[v * NF + k];
+      }
+    }
     const double dj = sg.detj[e];
 #pragma unroll
     for (int v = 0; v < 5; ++v) rk_store(sg, rk, (size_t)e * 5 * NU + v * NU + s, -double(acc[v]) / dj);
@@ -477,12 +500,19 @@ static Gas<R> make_gas_t(const GasHost& gh) {
   return o;
 }
 
-// elements per workgroup of the volume kernel: about one quadrature point per
-// thread (256 threads)
+// elements per workgroup of the volume kernel: about one quadrature point
+// per thread at 256 threads; the workgroup then takes enough threads for one
+// item per thread in every phase ((point, direction) rows, quadrature points,
+// flux points), since a second pass made the compiler keep the operands of
+// both passes live
 template <int ET, int P>
 struct DenseLaunch {
-  static constexpr int NQ = DenseCfg<ET, P>::NQ;
+  using C = DenseCfg<ET, P>;
+  static constexpr int NQ = C::NQ;
   static constexpr int EB = NQ >= 256 ? 1 : (256 / NQ > 16 ? 16 : 256 / NQ);
+  static constexpr int MX0 = EB * 3 * C::NU > EB * NQ ? EB * 3 * C::NU : EB * NQ;
+  static constexpr int MX = MX0 > EB * C::NF ? MX0 : EB * C::NF;
+  static constexpr int NT = (MX + 63) / 64 * 64;
 };
 constexpr int DENSE_DISU_EB = 8, DENSE_SURF_EB = 8;
 
@@ -492,16 +522,16 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
   const Gas<R> g = make_gas_t<R>(*a.gas);
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   const int E = a.one.E;
-  constexpr int EB = DenseLaunch<ET, P>::EB;
+  constexpr int EB = DenseLaunch<ET, P>::EB, NTV = DenseLaunch<ET, P>::NT;
   if ((a.stage & 1) && E > 0)
     hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
                        dim3(256), 0, st, a.one, a.from_ust, ops, eref);
   if ((a.stage & 2) && E > 0) {
     if (a.aa)
-      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, true>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st, a.one,
                          a.from_ust, ops, g, eref);
     else
-      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st,
+      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
                          a.one, a.from_ust, ops, g, eref);
   }
   if ((a.stage & 4) && E > 0)

@@ -24,6 +24,8 @@
 // pyramid: base [-1,1]^2 at zeta = -1 (face 0, GL(n)^2 points), apex (0,0,1),
 // triangles 1..4.  A face slot holds the face's values (the N_t triangle
 // nodes, or the n^2 base points; slot stride (p+1)^2).
+#include <type_traits>
+
 #include "fr_device.h"
 #include "fr_kernels.h"
 
@@ -50,13 +52,32 @@ struct DenseCfg {
   static constexpr int O_M3 = O_AP + 3 * NU * NQ;  // [NU][NF]
   static constexpr int O_N = O_M3 + NU * NF;       // [NFACE][3] reference unit normals
   static constexpr int O_KU = O_N + 3 * NFACE;      // pyramids: [3][NU][NU] AP_d M7
-  static constexpr int SIZE = O_KU + (PYR ? 3 * NU * NU : 0);
+  // matrix-core (FP32) copies of the volume operators: 16-row tiles, k in
+  // steps of 4, each (tile, step) a block of 64 values in lane order (lane l:
+  // row 16 mt + l % 16, column 4 ks + l / 16), zero padded
+  static constexpr int KSU = (NU + 3) / 4, KSF = (NF + 3) / 4, KSQ = (NQ + 3) / 4;
+  static constexpr int MTF = (NF + 15) / 16, MTG = (3 * NU + 15) / 16, MTQ = (NQ + 15) / 16, MTU = (NU + 15) / 16;
+  static constexpr int O_PM0 = O_KU + (PYR ? 3 * NU * NU : 0);  // M0: MTF x KSU
+  static constexpr int O_PG = O_PM0 + MTF * KSU * 64;            // [D_d | n_d M3]: MTG x (KSU + KSF)
+  static constexpr int O_PM7 = O_PG + MTG * (KSU + KSF) * 64;    // M7: MTQ x KSU
+  static constexpr int O_PAP = O_PM7 + MTQ * KSU * 64;           // [AP_0 | AP_1 | AP_2]: MTU x 3 KSQ
+  static constexpr int SIZE = O_PAP + MTU * 3 * KSQ * 64;
   // LDS per element of the volume kernel: state + gradients [20][NU]
   // (later the partial divergences [3][5][NU]), neighbour values then jumps
   // [5][NF], the transformed flux at the quadrature points [3][5][FQS]
   static constexpr int FQS = NQ + 1;  // odd stride: the three components' rows hit different banks
   static constexpr int SZ_X = 20 * NU, SZ_J = 5 * NF, SZ_F = 15 * FQS;
   static constexpr int PER_ELEM = SZ_X + SZ_J + SZ_F;
+  // LDS per element of the matrix-core volume kernel: state + gradients
+  // [20][NU], then one region holding in turn the jumps [5][NF], the face
+  // values [NF][LDW] and the quadrature values, later the transformed flux,
+  // [NQ][LDW] (odd row stride: a thread's row reads spread over the banks)
+  // (each region padded so that reads of the zero-weighted k-step padding stay
+  // inside it: the matrix-core products read B without bounds checks)
+  static constexpr int LDW = 21;
+  static constexpr int U2A = 5 * NF + 4, U2B = LDW * (NF + 4), U2C = LDW * (NQ + 4);
+  static constexpr int SZ_U2 = U2A > U2B ? (U2A > U2C ? U2A : U2C) : (U2B > U2C ? U2B : U2C);
+  static constexpr int PE_MF = SZ_X + 4 + SZ_U2;
   // face f and point t within the face of flux point fp
   // (branch-free: with a select here the compiler kept the operator loops of
   // both cases live in the callers, tripling their registers)
@@ -360,6 +381,254 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 #undef FQ
 }
 
+// ------------------------------------------------- volume, matrix cores
+// The FP32 volume group with every dense product on the matrix cores
+// (v_mfma_f32_16x16x4f32: D(16x16) += A(16x4) B(4x16) per wave; lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + r][l % 16], r < 4).  A product C = A B runs over 16 x 16
+// output tiles: rows are operator rows, columns the (element, field) pairs
+// of the workgroup; the waves take tiles in turn.  A comes from the packed
+// operator copy (one coalesced 64-value load per k-step), B from the
+// element's columns in LDS.  Products that feed point-wise physics (face and
+// quadrature values) go through LDS rows; the three directions of the
+// projection-divergence are one product with K concatenated.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// acc += A B over KS k-steps: A a packed tile (its KS values of this lane
+// loaded up front), B the column of this lane at bcol with stride bs in k.
+// The packed A is zero past the operator's K, and the B reads there stay in
+// finite (zero-initialised or written) LDS, so no bounds checks are needed.
+template <int KS>
+__device__ __forceinline__ void mf_acc(mf4& acc, const float* __restrict__ Ap, const float* bcol, int bs, int lane) {
+  float a[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a[ks] = Ap[ks * 64 + lane];
+  const float* b = bcol + (lane >> 4) * bs;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[4 * ks * bs], acc, 0, 0, 0);
+}
+
+template <int ET, int P, int EB, int NT>
+__global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const float* __restrict__ ops,
+                                                      const Gas<float> g, const double eref) {
+  using C = DenseCfg<ET, P>;
+  using R = float;
+  constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, NFACE = C::NFACE, LDW = C::LDW;
+  constexpr int PE = C::PE_MF, NW = NT / 64;
+  __shared__ R smem[EB * PE];
+  __shared__ R sMet[EB][10];
+  __shared__ FaceRec sFR[EB * NFACE];
+  __shared__ R sFG[EB * NFACE][4];
+  __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
+  const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double* __restrict__ U = from_ust ? sg.ust : sg.U;
+  const R* __restrict__ Uf = (const R*)sg.Uf;
+  R* __restrict__ Vf = (R*)sg.Vf;
+  R* __restrict__ Rp = (R*)sg.Rp;
+  const R* __restrict__ met = (const R*)sg.met;
+  const R* __restrict__ fgeo = (const R*)sg.fgeo;
+#define XS(le) (smem + (le)*PE)              /* [20][NU] */
+#define U2(le) (smem + (le)*PE + C::SZ_X + 4) /* [5][NF] | [NF][LDW] | [NQ][LDW] */
+  for (int it = tid; it < EB * PE; it += NT) smem[it] = R(0);
+  lds_barrier();
+
+  // phase 0: as in dense_volume (neighbour face values into U2 as [5][NF])
+  for (int it = tid; it < EB * NFACE; it += NT) {
+    const int slot = sg.slot_base + (e0 + it / NFACE < E ? e0 * NFACE + it : 0);
+    sFR[it] = sg.faces[slot];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
+  }
+  for (int it = tid; it < sg.nperm * NFPS; it += NT) sPerm[it] = sg.perms[it];
+  for (int it = tid; it < EB * 10; it += NT) {
+    const int le = it / 10, k = it - le * 10;
+    sMet[le][k] = met[e0 + le < E ? (size_t)(e0 + le) * 10 + k : 0];
+  }
+  for (int it = tid; it < EB * 5 * NU; it += NT) {
+    const int le = it / (5 * NU), r = it - le * (5 * NU);
+    double x = U[e0 + le < E ? (size_t)e0 * 5 * NU + it : 0];
+    if (r >= 4 * NU) x -= eref;
+    XS(le)[r] = R(x);
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * 5 * NF; it += NT) {
+    const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
+    const int f = C::face_of(fp), t = C::point_of(fp);
+    const FaceRec fr = sFR[le * NFACE + f];
+    U2(le)[r0] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+  }
+  lds_barrier();
+
+  // phase 1: jumps (eq. FR-conu), M0 on the matrix cores, in place over the
+  // neighbour values: columns (element, variable)
+  {
+    constexpr int NTL = (5 * EB + 15) / 16;
+    for (int t = wave; t < C::MTF * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 5 * EB;
+      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + v * NU, 1, lane);
+      if (ok)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int fp = mt * 16 + 4 * (lane >> 4) + r;
+          if (fp < NF) {
+            const bool left = sFR[le * NFACE + C::face_of(fp)].info & 1;
+            const R w = left ? R(0.5) + g.beta : R(0.5) - g.beta;
+            R* J = U2(le) + v * NF + fp;
+            *J = w * (*J - acc[r]);
+          }
+        }
+    }
+  }
+  lds_barrier();
+
+  // phase 2: corrected reference gradient (eq. FR-qfinal): rows (direction,
+  // point) of [D_d | n_d M3] against [u; jumps]
+  {
+    constexpr int NTL = (5 * EB + 15) / 16;
+    for (int t = wave; t < C::MTG * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 5 * EB;
+      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      const R* Ap = ops + C::O_PG + mt * (C::KSU + C::KSF) * 64;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      mf_acc<C::KSU>(acc, Ap, XS(le) + v * NU, 1, lane);
+      mf_acc<C::KSF>(acc, Ap + C::KSU * 64, U2(le) + v * NF, 1, lane);
+      if (ok)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mt * 16 + 4 * (lane >> 4) + r;
+          if (row < 3 * NU) {
+            const int d = row / NU, s = row - d * NU;
+            XS(le)[(5 + d * 5 + v) * NU + s] = acc[r];
+          }
+        }
+    }
+  }
+  lds_barrier();
+
+  // phase 3: physical gradient q = J^-T q~ (eq. FR-gradcoru), in place
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU;
+    R* X = XS(le);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+    }
+  }
+  lds_barrier();
+
+  // phase 3a: state and gradient at the flux points (M0, 20 columns per
+  // element) into U2 rows, then the own normal viscous flux per flux point
+  {
+    constexpr int NTL = (20 * EB + 15) / 16;
+    for (int t = wave; t < C::MTF * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 20 * EB;
+      const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
+      if (ok)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int fp = mt * 16 + 4 * (lane >> 4) + r;
+          if (fp < NF) U2(le)[fp * LDW + c] = acc[r];
+        }
+    }
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * NF; it += NT) {
+    const int le = it / NF, fp = it - le * NF, e = e0 + le;
+    if (e >= E) continue;
+    const R* w = U2(le) + fp * LDW;
+    const int f = C::face_of(fp), t = C::point_of(fp), lf = le * NFACE + f;
+    const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
+    const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+    R u[5], q[3][5], V[4];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = w[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
+    }
+    normal_viscous(u, q, nn, g, V);
+    const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
+  }
+  lds_barrier();
+
+  // phase 4: state and gradient at the quadrature points (M7) into U2 rows,
+  // then tdisf per point (eq. FR-tdisfq), F~_d of variable v in place into
+  // column 5 d + v of the point's row
+  {
+    constexpr int NTL = (20 * EB + 15) / 16;
+    for (int t = wave; t < C::MTQ * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 20 * EB;
+      const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      mf_acc<C::KSU>(acc, ops + C::O_PM7 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
+      if (ok)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q0 = mt * 16 + 4 * (lane >> 4) + r;
+          if (q0 < NQ) U2(le)[q0 * LDW + c] = acc[r];
+        }
+    }
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * NQ; it += NT) {
+    const int le = it / NQ, q0 = it - le * NQ;
+    R* w = U2(le) + q0 * LDW;
+    R u[5], q[3][5], f[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      u[v] = w[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
+    }
+    point_flux(u, q, g, f);
+    const R dj = sMet[le][9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+  }
+  lds_barrier();
+
+  // phase 5: projection-divergence, sum_d AP_d F~_d as one product over the
+  // concatenated K = (direction, quadrature point)
+  {
+    constexpr int NTL = (5 * EB + 15) / 16;
+    for (int t = wave; t < C::MTU * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 5 * EB;
+      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      const R* Ap = ops + C::O_PAP + mt * 3 * C::KSQ * 64;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        mf_acc<C::KSQ>(acc, Ap + d * C::KSQ * 64, U2(le) + d * 5 + v, LDW, lane);
+      const int e = e0 + le;
+      if (ok && e < E)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int s = mt * 16 + 4 * (lane >> 4) + r;
+          if (s < NU) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[r];
+        }
+    }
+  }
+#undef XS
+#undef U2
+}
+
 // -------------------------------------------------------------- surface
 // comm_flux at every own flux point (both sides of a pair evaluate the same
 // expression on the same inputs and normal; each side scales by its own area
@@ -449,6 +718,25 @@ static void pack_dense(const RefElem& r, R* o) {
   for (int i = 0; i < 3 * C::NFACE; ++i) o[C::O_N + i] = R(r.face_normal[i]);
   if constexpr (C::PYR)
     for (int i = 0; i < 3 * NU * NU; ++i) o[C::O_KU + i] = R(r.Ku[i]);
+  // matrix-core copies (lane order, zero padded)
+  auto tiles = [&](int off, int MT, int KS, auto val) {
+    for (int mt = 0; mt < MT; ++mt)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int l = 0; l < 64; ++l) o[off + (mt * KS + ks) * 64 + l] = R(val(mt * 16 + l % 16, ks * 4 + l / 16));
+  };
+  tiles(C::O_PM0, C::MTF, C::KSU, [&](int row, int k) { return row < NF && k < NU ? r.M0[row * NU + k] : 0.0; });
+  tiles(C::O_PG, C::MTG, C::KSU + C::KSF, [&](int row, int k) {
+    if (row >= 3 * NU) return 0.0;
+    const int d = row / NU, s = row % NU;
+    if (k < 4 * C::KSU) return k < NU ? r.Dg[(d * NU + s) * NU + k] : 0.0;
+    const int f = k - 4 * C::KSU;
+    return f < NF ? r.face_normal[3 * C::face_of(f) + d] * r.M3[s * NF + f] : 0.0;
+  });
+  tiles(C::O_PM7, C::MTQ, C::KSU, [&](int row, int k) { return row < NQ && k < NU ? r.M7[row * NU + k] : 0.0; });
+  tiles(C::O_PAP, C::MTU, 3 * C::KSQ, [&](int row, int k) {
+    const int d = k / (4 * C::KSQ), q = k % (4 * C::KSQ);
+    return row < NU && q < NQ ? r.APd[(d * NU + row) * NQ + q] : 0.0;
+  });
 }
 
 template <int ET>
@@ -527,12 +815,25 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
                        dim3(256), 0, st, a.one, a.from_ust, ops, eref);
   if ((a.stage & 2) && E > 0) {
-    if (a.aa)
-      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, true>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st, a.one,
-                         a.from_ust, ops, g, eref);
-    else
-      hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
-                         a.one, a.from_ust, ops, g, eref);
+    // FP32 with anti-aliasing at p >= 3 on the matrix cores (measured at 48^3
+    // cells: 14-42% faster than the VALU kernel; at p <= 2 the tiles are too
+    // small and the VALU kernel is faster)
+    constexpr bool MF = std::is_same<R, float>::value && P >= 3;
+    if constexpr (MF) {
+      if (a.aa)
+        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+                           a.from_ust, ops, g, eref);
+      else
+        hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
+                           a.one, a.from_ust, ops, g, eref);
+    } else {
+      if (a.aa)
+        hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, true>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
+                           a.one, a.from_ust, ops, g, eref);
+      else
+        hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
+                           a.one, a.from_ust, ops, g, eref);
+    }
   }
   if ((a.stage & 4) && E > 0)
     hipLaunchKernelGGL((dense_surface<ET, P, R, DENSE_SURF_EB, 256>), dim3((E + DENSE_SURF_EB - 1) / DENSE_SURF_EB),

@@ -67,7 +67,8 @@ typedef enum {
   FR_MESH_PRISM_WARP = 6,
   FR_MESH_MIXED_WARP = 7,
   FR_MESH_PYR = 8,        /* six pyramids per cell */
-  FR_MESH_HEX_PYR = 9     /* hexahedra where z < 0, pyramids elsewhere */
+  FR_MESH_HEX_PYR = 9,    /* hexahedra where z < 0, pyramids elsewhere */
+  FR_MESH_HEX_PYR_TET = 10 /* hexahedra, transition cells (pyramid + tetrahedra), tetrahedra */
 } fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
@@ -136,7 +137,11 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * elsewhere; prism triangles meet tetrahedron faces), FR_MESH_PYR (six
  * pyramids per cell, one on each cell face with the apex at the cell centre)
  * and FR_MESH_HEX_PYR (hexahedra where the cell centre has z < 0, pyramids
- * elsewhere; pyramid bases meet hexahedron faces).  Tetrahedra and pyramids
+ * elsewhere; pyramid bases meet hexahedron faces) and FR_MESH_HEX_PYR_TET (nz
+ * >= 3: hexahedra in the layers k < nz/2, tetrahedron cells between, and in
+ * layer nz/2 and the last layer transition cells of one pyramid on the face
+ * towards the hexahedra and ten tetrahedra cut along the tetrahedron cells'
+ * face diagonals).  Tetrahedra and pyramids
  * have no tensor-product structure (the paper's factorisation does not
  * apply) and run on dense-operator kernels; they support the fused form with
  * or without flux anti-aliasing and the plain form, but not surface-flux
@@ -146,7 +151,8 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * divergence (equal to (M1 - M3 M2) M9 for the other types).  Host-side only: device buffers
  * are allocated and uploaded by the first call that needs them.  Element
  * numbering: cells in index order i + nx(j + ny k); a prism cell yields two
- * elements, a tetrahedron or pyramid cell six.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,
+ * elements, a tetrahedron or pyramid cell six, a transition cell its pyramid
+ * then ten tetrahedra.  FR_MESH_HEX_WARP, FR_MESH_PRISM_WARP,
  * FR_MESH_MIXED_WARP: the hex, prism and mixed meshes with curved
  * (non-affine) elements; every grid vertex x moves to
  * x + 0.2 h (sin y cos z, sin z cos x, sin x cos y) (h the cell size per

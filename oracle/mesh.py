@@ -35,6 +35,21 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                  neighbouring pyramids of the same cell.
   kind "hex_pyr" : hexahedra in cells whose centre has z < 0, pyramids
                  elsewhere.
+  kind "hex_pyr_tet" : hexahedra, pyramids and tetrahedra (nz >= 3).  Layers
+                 k < nz // 2 hold hexahedra and layers between nz // 2 and
+                 nz - 1 tetrahedra (the Kuhn cells of "tet").  Layer nz // 2
+                 and the last layer hold transition cells: one pyramid on the
+                 cell face towards the hexahedra (z- in layer nz // 2, z+ in
+                 the last layer, which meets the first hexahedron layer
+                 across the period) and ten tetrahedra.  Those are the
+                 pyramids of the five other faces with the apex at the cell
+                 centre, each cut in two along the face diagonal that the
+                 Kuhn cells use there: the diagonal joining the face's
+                 corners with the smallest and the largest sum of the unit
+                 coordinates u.  Element order in a transition cell: the
+                 pyramid, then two tetrahedra per face in face order, the
+                 face's two other corners taken in lexicographic order of
+                 (x, y, z).
   kinds "hex_warp", "prism_warp", "mixed_warp" : the curved (non-affine)
                  forms of "hex", "prism" and "mixed": every grid vertex x is
                  moved to x + warp h (sin y cos z, sin z cos x, sin x cos y)
@@ -56,7 +71,8 @@ and (E,)); curved meshes give them per point through metrics(t, ref_pts).
 surf_aa=True builds the reference elements with surface-flux
 anti-aliasing (flux points at the face quadrature points).
 Element numbering: cells in index order; a prism cell yields A then B, a
-pyramid cell its six pyramids in face order.  The
+pyramid cell its six pyramids in face order, a transition cell its pyramid
+then its ten tetrahedra.  The
 position in that sequence is the global element id; each element type keeps
 its own elements in order of appearance.
 
@@ -98,6 +114,55 @@ def _kuhn_tets(x0, h):
     return out
 
 
+def _pyramid_on_face(x0, h, ax, sg):
+    """Jacobian and origin of the pyramid on the face (ax, sg) of the cell at
+    x0 with its apex at the cell centre (the map of kind "pyr")."""
+    C = x0 + 0.5 * h
+    t1, t2 = [a for a in range(3) if a != ax]
+    if (sg < 0) != (ax != 1):
+        t1, t2 = t2, t1
+    e1, e2 = np.zeros(3), np.zeros(3)
+    e1[t1], e2[t2] = 0.5 * h[t1], 0.5 * h[t2]
+    B = C.copy()
+    B[ax] += sg * 0.5 * h[ax]
+    return np.stack([e1, e2, 0.5 * (C - B)], axis=1), B + 0.5 * (C - B)
+
+
+def _transition_tets(x0, h, base):
+    """Vertices (4, 3) of the ten tetrahedra of a transition cell whose
+    pyramid sits on the face base = (axis, sign): for each other face, its
+    corners D0, D1 with the smallest and largest sum of the Kuhn unit
+    coordinates u = ((x0+h-x)/h, (y-y0)/h, (z-z0)/h) and the cell centre C,
+    with each of the two remaining corners; positive orientation."""
+    C = x0 + 0.5 * h
+    out = []
+    for ax in range(3):
+        for sg in (-1.0, 1.0):
+            if (ax, sg) == base:
+                continue
+            corners = []
+            for a in (0.0, 1.0):
+                for b in (0.0, 1.0):
+                    u = np.zeros(3)
+                    u[ax] = 0.0 if sg < 0 else 1.0
+                    o = [d for d in range(3) if d != ax]
+                    u[o[0]], u[o[1]] = a, b
+                    # the face is sg along axis ax in x; u_x runs against x
+                    if ax == 0:
+                        u[0] = 1.0 - u[0]
+                    corners.append(u)
+            corners.sort(key=lambda u: u.sum())
+            X = [x0 + h * np.array([1.0 - u[0], u[1], u[2]]) for u in corners]
+            D0, D1 = X[0], X[3]
+            # the two other corners in lexicographic order of (x, y, z)
+            for O in sorted((X[1], X[2]), key=lambda x: tuple(x)):
+                P = [D0, D1, O, C]
+                if np.linalg.det(np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1)) < 0:
+                    P[1], P[2] = P[2], P[1]
+                out.append(P)
+    return out
+
+
 class Mesh:
     def __init__(self, nx, ny, nz, p, kind="hex", lo=-np.pi, hi=np.pi, m=None, tri_nodes=None, surf_aa=False,
                  warp=0.2):
@@ -113,7 +178,10 @@ class Mesh:
             if kind not in ("hex", "prism", "mixed"):
                 raise ValueError("warped meshes: hex, prism or mixed")
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
-                 "prism_tet": ["prism", "tet"], "pyr": ["pyr"], "hex_pyr": ["hex", "pyr"]}[kind]
+                 "prism_tet": ["prism", "tet"], "pyr": ["pyr"], "hex_pyr": ["hex", "pyr"],
+                 "hex_pyr_tet": ["hex", "tet", "pyr"]}[kind]
+        if kind == "hex_pyr_tet" and nz < 3:
+            raise ValueError("hex_pyr_tet needs nz >= 3")
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -133,9 +201,26 @@ class Mesh:
                         ctype = "prism" if yc < 0.0 else "tet"
                     elif kind == "hex_pyr":
                         ctype = "hex" if zc < 0.0 else "pyr"
+                    elif kind == "hex_pyr_tet":
+                        kh = nz // 2
+                        ctype = "hex" if k < kh else ("trans_down" if k == kh else
+                                                      ("trans_up" if k == nz - 1 else "tet"))
                     else:
                         ctype = kind
-                    if ctype == "pyr":
+                    if ctype in ("trans_down", "trans_up"):
+                        base = (2, -1.0) if ctype == "trans_down" else (2, 1.0)
+                        Jp, op = _pyramid_on_face(x0, h, *base)
+                        org["pyr"].append(op)
+                        A["pyr"].append(Jp)
+                        gid["pyr"].append(g)
+                        g += 1
+                        for P in _transition_tets(x0, h, base):
+                            Jt = np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1) / 2.0
+                            org["tet"].append(P[0] + Jt @ np.ones(3))
+                            A["tet"].append(Jt)
+                            gid["tet"].append(g)
+                            g += 1
+                    elif ctype == "pyr":
                         C = x0 + 0.5 * h
                         for ax in range(3):
                             for sg in (-1.0, 1.0):

@@ -22,7 +22,16 @@
 // points into the cell (x-: y, z; x+: z, y; y-: z, x; y+: x, z; z-: x, y;
 // z+: y, x).  Bases meet hexahedron faces or other bases; the triangles meet
 // the neighbouring pyramids of the same cell (hexahedra below z = 0 in the
-// hex/pyramid mesh).
+// hex/pyramid mesh).  The hexahedron/pyramid/tetrahedron mesh (nz >= 3) has
+// hexahedra in layers k < nz/2, Kuhn tetrahedron cells in the layers between
+// nz/2 and nz-1, and transition cells in layer nz/2 and the last layer: a
+// pyramid on the face towards the hexahedra (z-, or z+ in the last layer,
+// which meets the first layer across the period) and the pyramids of the
+// five other faces cut into two tetrahedra each along the face diagonal the
+// Kuhn cells use (joining the corners with the smallest and the largest sum
+// of the unit coordinates u); element order: the pyramid, then two
+// tetrahedra per face in face order (the face's two other corners in
+// lexicographic order of (x, y, z)).
 //
 // Connectivity: faces are paired by their centroids modulo the period, then
 // the points of each face pair are matched by coordinates (section 2.1: paired
@@ -68,7 +77,11 @@ static int parallel_chunks(int64_t n, F body) {
 // element type of cell (j, k): kind 2 has hexahedra where the cell centre
 // has z < 0 and prisms elsewhere; kind 4 prisms where y < 0, tetrahedra
 // elsewhere; kind 9 hexahedra where z < 0, pyramids elsewhere
+// Cell codes: 0..3 one element type per cell; 4, 5 transition cells with the
+// pyramid on the z- / z+ face.
+constexpr int kTransDown = 4, kTransUp = 5;
 static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kind) {
+  if (kind == 10) return k < nz / 2 ? 0 : (k == nz / 2 ? kTransDown : (k == nz - 1 ? kTransUp : 2));
   if (kind == 8) return 3;
   if (kind == 9) return cell_type(j, k, ny, nz, lo, hi, 2) == 0 ? 0 : 3;
   if (kind == 2) {
@@ -90,7 +103,12 @@ void box_counts(int nx, int ny, int nz, double lo, double hi, int kind, int64_t 
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j) {
       const int t = cell_type(j, k, ny, nz, lo, hi, kind);
-      nel[t] += (int64_t)nx * kPerCell[t];
+      if (t >= kTransDown) {
+        nel[3] += nx;
+        nel[2] += (int64_t)nx * 10;
+      } else {
+        nel[t] += (int64_t)nx * kPerCell[t];
+      }
     }
 }
 
@@ -195,19 +213,83 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
         double x0[3] = {lo + i * h[0], lo + j * h[1], lo + k * h[2]};
         int t = cell_type(j, k, ny, nz, lo, hi, kind);
         double c[3] = {x0[0] + 0.5 * h[0], x0[1] + 0.5 * h[1], x0[2] + 0.5 * h[2]};
+        // the pyramid on cell face (ax, sg) (sg = 0: minus side), apex at c
+        auto pyramid = [&](int ax, int sg) {
+          int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+          // e1 x e2 along the inward normal -(2 sg - 1) e_ax
+          if ((sg == 0) != (ax != 1)) std::swap(t1, t2);
+          double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          J[3 * t1 + 0] = 0.5 * h[t1];
+          J[3 * t2 + 1] = 0.5 * h[t2];
+          J[3 * ax + 2] = (sg ? -0.25 : 0.25) * h[ax];  // (C - B)/2
+          for (int d = 0; d < 3; ++d) M.org[3].push_back(c[d] + (d == ax ? (sg ? 0.25 : -0.25) * h[ax] : 0.0));
+          M.jac[3].insert(M.jac[3].end(), J, J + 9);
+          M.gid[3].push_back(g++);
+        };
+        // a tetrahedron of vertices P (positive orientation enforced)
+        auto tetra = [&](double P[4][3]) {
+          double a[3], b[3], cc[3];
+          for (int d = 0; d < 3; ++d) {
+            a[d] = P[1][d] - P[0][d];
+            b[d] = P[2][d] - P[0][d];
+            cc[d] = P[3][d] - P[0][d];
+          }
+          const double det = a[0] * (b[1] * cc[2] - b[2] * cc[1]) - a[1] * (b[0] * cc[2] - b[2] * cc[0]) +
+                             a[2] * (b[0] * cc[1] - b[1] * cc[0]);
+          if (det < 0)
+            for (int d = 0; d < 3; ++d) std::swap(P[1][d], P[2][d]);
+          // x = P0 + J (xi + 1): columns (P_v - P0)/2; origin at xi = 0
+          double J[9];
+          for (int d = 0; d < 3; ++d)
+            for (int v = 0; v < 3; ++v) J[3 * d + v] = 0.5 * (P[v + 1][d] - P[0][d]);
+          for (int d = 0; d < 3; ++d) M.org[2].push_back(P[0][d] + J[3 * d] + J[3 * d + 1] + J[3 * d + 2]);
+          M.jac[2].insert(M.jac[2].end(), J, J + 9);
+          M.gid[2].push_back(g++);
+        };
         if (t == 3) {
           for (int ax = 0; ax < 3; ++ax)
+            for (int sg = 0; sg < 2; ++sg) pyramid(ax, sg);
+        } else if (t >= kTransDown) {
+          const int bsg = t == kTransUp ? 1 : 0;
+          pyramid(2, bsg);
+          for (int ax = 0; ax < 3; ++ax)
             for (int sg = 0; sg < 2; ++sg) {
-              int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
-              // e1 x e2 along the inward normal -(2 sg - 1) e_ax
-              if ((sg == 0) != (ax != 1)) std::swap(t1, t2);
-              double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-              J[3 * t1 + 0] = 0.5 * h[t1];
-              J[3 * t2 + 1] = 0.5 * h[t2];
-              J[3 * ax + 2] = (sg ? -0.25 : 0.25) * h[ax];  // (C - B)/2
-              for (int d = 0; d < 3; ++d) M.org[3].push_back(c[d] + (d == ax ? (sg ? 0.25 : -0.25) * h[ax] : 0.0));
-              M.jac[3].insert(M.jac[3].end(), J, J + 9);
-              M.gid[3].push_back(g++);
+              if (ax == 2 && sg == bsg) continue;
+              // the face's corners in Kuhn unit coordinates u (u_x = (x0 + h - x)/h),
+              // ordered by the sum of u: the diagonal joins the first and last
+              double u[4][3];
+              for (int q = 0; q < 4; ++q) {
+                int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+                double w[3];
+                w[ax] = sg ? 1.0 : 0.0;
+                w[o0] = q & 1;
+                w[o1] = (q >> 1) & 1;
+                u[q][0] = 1.0 - w[0];  // w: unit coordinates along +x, +y, +z
+                u[q][1] = w[1];
+                u[q][2] = w[2];
+              }
+              int ord[4] = {0, 1, 2, 3};
+              std::sort(ord, ord + 4, [&](int a, int b) {
+                return u[a][0] + u[a][1] + u[a][2] < u[b][0] + u[b][1] + u[b][2];
+              });
+              auto X = [&](int q, double* x) {
+                x[0] = x0[0] + h[0] * (1.0 - u[q][0]);
+                x[1] = x0[1] + h[1] * u[q][1];
+                x[2] = x0[2] + h[2] * u[q][2];
+              };
+              // the two other corners in lexicographic order of (x, y, z)
+              double m1[3], m2[3];
+              X(ord[1], m1);
+              X(ord[2], m2);
+              if (std::lexicographical_compare(m2, m2 + 3, m1, m1 + 3)) std::swap(ord[1], ord[2]);
+              for (int other = 1; other <= 2; ++other) {
+                double P[4][3];
+                X(ord[0], P[0]);
+                X(ord[3], P[1]);
+                X(ord[other], P[2]);
+                for (int d = 0; d < 3; ++d) P[3][d] = c[d];
+                tetra(P);
+              }
             }
         } else if (t == 2) {
           double P[6][4][3];

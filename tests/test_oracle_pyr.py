@@ -206,10 +206,10 @@ def test_pyramid_weak_divergence(p):
         assert np.abs(np.asarray(r.wu @ r.Kq[d], float)).max() < 1e-14 * np.abs(np.asarray(r.Kq[d], float)).max()
 
 
-@pytest.mark.parametrize("kind", ["pyr", "hex_pyr"])
+@pytest.mark.parametrize("kind", ["pyr", "hex_pyr", "hex_pyr_tet"])
 @pytest.mark.parametrize("p", [1, 3])
 def test_free_stream_and_conservation(kind, p):
-    m = Mesh(2, 2, 2, p, kind)
+    m = Mesh(2, 2, 3, p, kind)
     U = {t: u for t, u in zip(m.types, inputs.uniform_state([(m.nelem[t], m.refs[t].nu) for t in m.types]))}
     for pref in (0.0, inputs.P0):
         for aa in (True, False):
@@ -223,12 +223,31 @@ def test_free_stream_and_conservation(kind, p):
         assert np.all(np.abs(tot) <= 1e-13 * scale)
 
 
-@pytest.mark.parametrize("kind", ["pyr", "hex_pyr"])
-def test_entropy_wave_convergence(kind):
+def test_transition_cells():
+    """hex_pyr_tet: the element counts of the layering (hexahedra below, one
+    pyramid and ten tetrahedra per transition cell, six tetrahedra per Kuhn
+    cell), every element of positive volume and the cells filled exactly."""
+    nx, ny, nz = 2, 3, 5
+    m = Mesh(nx, ny, nz, 1, "hex_pyr_tet")
+    kh = nz // 2
+    cells = nx * ny
+    assert m.nelem["hex"] == cells * kh
+    assert m.nelem["pyr"] == cells * 2
+    assert m.nelem["tet"] == cells * (2 * 10 + 6 * (nz - kh - 2))
+    vol = {"hex": 8.0, "tet": 4.0 / 3.0, "pyr": 8.0 / 3.0}
+    total = sum(vol[t] * m.detJ[t].sum() for t in m.types)
+    assert np.all(np.concatenate([m.detJ[t] for t in m.types]) > 0)
+    assert abs(total - (2 * np.pi) ** 3) < 1e-10
+    with pytest.raises(ValueError):
+        Mesh(2, 2, 2, 1, "hex_pyr_tet")
+
+
+@pytest.mark.parametrize("kind,sizes", [("pyr", (2, 4)), ("hex_pyr", (2, 4)), ("hex_pyr_tet", (3, 6))])
+def test_entropy_wave_convergence(kind, sizes):
     """Euler entropy wave: the RHS error falls at about the design rate."""
     p = 2
     errs = []
-    for N in (2, 4):
+    for N in sizes:
         m = Mesh(N, N, N, p, kind)
         U = {t: np.ascontiguousarray(np.moveaxis(_entropy_wave(m.upts_coords(t))[0], -1, 1)) for t in m.types}
         ex = {t: np.ascontiguousarray(np.moveaxis(_entropy_wave(m.upts_coords(t))[1], -1, 1)) for t in m.types}

@@ -322,7 +322,7 @@ def main():
         ("fp32", 3, "noaa", "tet"), ("fp64", 3, "plain", "tet"),
         ("fp32", 3, "fused", "pyr"), ("fp64", 3, "fused", "pyr"), ("fp32", 4, "fused", "pyr"),
         ("fp32", 3, "noaa", "pyr"), ("fp64", 3, "plain", "pyr"), ("fp32", 3, "fused", "hex_pyr"),
-        ("fp32", 3, "fused", "hex_pyr_tet"),
+        ("fp32", 3, "fused", "hex_pyr_tet"), ("fp32", 3, "fused", "hex_prism_pyr_tet"),
         ("fp32", 3, "fused", "hex_warp"), ("fp64", 3, "fused", "hex_warp"), ("fp32", 4, "fused", "hex_warp"),
         ("fp32", 3, "fused", "prism_warp"), ("fp32", 4, "fused", "prism_warp")]
     for prec, p, form, kind in order:

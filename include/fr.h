@@ -68,7 +68,8 @@ typedef enum {
   FR_MESH_MIXED_WARP = 7,
   FR_MESH_PYR = 8,        /* six pyramids per cell */
   FR_MESH_HEX_PYR = 9,    /* hexahedra where z < 0, pyramids elsewhere */
-  FR_MESH_HEX_PYR_TET = 10 /* hexahedra, transition cells (pyramid + tetrahedra), tetrahedra */
+  FR_MESH_HEX_PYR_TET = 10, /* hexahedra, transition cells (pyramid + tetrahedra), tetrahedra */
+  FR_MESH_HEX_PRISM_PYR_TET = 11 /* FR_MESH_HEX_PYR_TET with prisms where y < 0 above the hexahedra */
 } fr_mesh_kind;
 typedef enum { FR_PREC_FP64 = 0, FR_PREC_FP32 = 1 } fr_precision;
 typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
@@ -141,7 +142,9 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * >= 3: hexahedra in the layers k < nz/2, tetrahedron cells between, and in
  * layer nz/2 and the last layer transition cells of one pyramid on the face
  * towards the hexahedra and ten tetrahedra cut along the tetrahedron cells'
- * face diagonals).  Tetrahedra and pyramids
+ * face diagonals), FR_MESH_HEX_PRISM_PYR_TET (all four types: that mesh where
+ * the cell centre has y >= 0; where y < 0 hexahedra in the layers k < nz/2
+ * and prisms above).  Tetrahedra and pyramids
  * have no tensor-product structure (the paper's factorisation does not
  * apply) and run on dense-operator kernels; they support the fused form with
  * or without flux anti-aliasing and the plain form, but not surface-flux

@@ -50,6 +50,12 @@ Box [lo, hi]^3 split into nx*ny*nz cells, cell index c = i + nx (j + ny k).
                  pyramid, then two tetrahedra per face in face order, the
                  face's two other corners taken in lexicographic order of
                  (x, y, z).
+  kind "hex_prism_pyr_tet" : all four types (nz >= 3): "hex_pyr_tet" where
+                 the cell centre has y >= 0; where y < 0, hexahedra in the
+                 layers k < nz // 2 and prism cells above (their z faces are
+                 full quadrilaterals and their y faces are cut like the Kuhn
+                 cells', so they meet hexahedra, transition cells and
+                 tetrahedra conformingly).
   kinds "hex_warp", "prism_warp", "mixed_warp" : the curved (non-affine)
                  forms of "hex", "prism" and "mixed": every grid vertex x is
                  moved to x + warp h (sin y cos z, sin z cos x, sin x cos y)
@@ -179,9 +185,9 @@ class Mesh:
                 raise ValueError("warped meshes: hex, prism or mixed")
         types = {"hex": ["hex"], "prism": ["prism"], "mixed": ["hex", "prism"], "tet": ["tet"],
                  "prism_tet": ["prism", "tet"], "pyr": ["pyr"], "hex_pyr": ["hex", "pyr"],
-                 "hex_pyr_tet": ["hex", "tet", "pyr"]}[kind]
-        if kind == "hex_pyr_tet" and nz < 3:
-            raise ValueError("hex_pyr_tet needs nz >= 3")
+                 "hex_pyr_tet": ["hex", "tet", "pyr"], "hex_prism_pyr_tet": ["hex", "prism", "tet", "pyr"]}[kind]
+        if kind in ("hex_pyr_tet", "hex_prism_pyr_tet") and nz < 3:
+            raise ValueError(kind + " needs nz >= 3")
         self.refs = {}
         for t in types:
             self.refs[t] = RefElement(t, p, m, tri_nodes=tri_nodes, surf_aa=surf_aa)
@@ -201,10 +207,12 @@ class Mesh:
                         ctype = "prism" if yc < 0.0 else "tet"
                     elif kind == "hex_pyr":
                         ctype = "hex" if zc < 0.0 else "pyr"
-                    elif kind == "hex_pyr_tet":
+                    elif kind in ("hex_pyr_tet", "hex_prism_pyr_tet"):
                         kh = nz // 2
                         ctype = "hex" if k < kh else ("trans_down" if k == kh else
                                                       ("trans_up" if k == nz - 1 else "tet"))
+                        if kind == "hex_prism_pyr_tet" and yc < 0.0 and k >= kh:
+                            ctype = "prism"
                     else:
                         ctype = kind
                     if ctype in ("trans_down", "trans_up"):

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libfrmi.so")
 
 FR_HEX, FR_PRISM = 0, 1
 MESH_KIND = {"hex": 0, "prism": 1, "mixed": 2, "tet": 3, "prism_tet": 4, "hex_warp": 5, "prism_warp": 6,
-             "mixed_warp": 7, "pyr": 8, "hex_pyr": 9, "hex_pyr_tet": 10}
+             "mixed_warp": 7, "pyr": 8, "hex_pyr": 9, "hex_pyr_tet": 10,
+             "hex_prism_pyr_tet": 11}
 PREC = {"fp64": 0, "fp32": 1}
 FORM = {"fused": 0, "plain": 1}
 _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE", -5: "FR_EUNSUPPORTED"}

@@ -364,7 +364,8 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   if (nx < 1 || ny < 1 || nz < 1 || !(hi > lo) || kind < 0 || kind >= fr::kNumKinds)
     return fail(c, FR_EINVAL, "bad mesh size");
   if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
-  if (kind == FR_MESH_HEX_PYR_TET && nz < 3) return fail(c, FR_EINVAL, "hexahedron/pyramid/tetrahedron mesh: nz >= 3");
+  if ((kind == FR_MESH_HEX_PYR_TET || kind == FR_MESH_HEX_PRISM_PYR_TET) && nz < 3)
+    return fail(c, FR_EINVAL, "meshes with transition cells: nz >= 3");
   if (fr::kind_dense(kind) && c->ph.surface_aa)
     return fail(c, FR_EUNSUPPORTED, "tetrahedra and pyramids: no surface-flux anti-aliasing");
   if (fr::kind_curved(kind) && (c->ph.form != FR_FORM_FUSED || !c->ph.flux_aa || c->ph.surface_aa))

@@ -78,8 +78,8 @@ constexpr int kFacesOf[NTYPES] = {6, 5, 4, 5};
 // box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
 // 4 prism (y < 0) + tet; 5, 6, 7: kinds 0, 1, 2 on the warped grid (curved);
 // 8 pyramid (six per cell), 9 hex (z < 0) + pyramid, 10 hex + pyramid +
-// tetrahedron (transition cells, nz >= 3)
-constexpr int kNumKinds = 11;
+// tetrahedron (transition cells, nz >= 3), 11 kind 10 with prisms where y < 0
+constexpr int kNumKinds = 12;
 inline bool kind_curved(int kind) { return kind >= 5 && kind <= 7; }
 // kinds with tetrahedra or pyramids (dense-operator element types)
 inline bool kind_dense(int kind) { return kind == 3 || kind == 4 || kind >= 8; }

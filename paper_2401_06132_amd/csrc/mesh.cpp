@@ -31,7 +31,10 @@
 // Kuhn cells use (joining the corners with the smallest and the largest sum
 // of the unit coordinates u); element order: the pyramid, then two
 // tetrahedra per face in face order (the face's two other corners in
-// lexicographic order of (x, y, z)).
+// lexicographic order of (x, y, z)).  The four-type mesh is that one where
+// the cell centre has y >= 0; where y < 0 it has hexahedra in the layers
+// k < nz/2 and prism cells above (their z faces are full quadrilaterals, their
+// y faces cut like the Kuhn cells').
 //
 // Connectivity: faces are paired by their centroids modulo the period, then
 // the points of each face pair are matched by coordinates (section 2.1: paired
@@ -82,6 +85,11 @@ static int parallel_chunks(int64_t n, F body) {
 constexpr int kTransDown = 4, kTransUp = 5;
 static int cell_type(int j, int k, int ny, int nz, double lo, double hi, int kind) {
   if (kind == 10) return k < nz / 2 ? 0 : (k == nz / 2 ? kTransDown : (k == nz - 1 ? kTransUp : 2));
+  if (kind == 11) {
+    const double hy = (hi - lo) / ny;
+    if ((lo + j * hy) + 0.5 * hy < 0.0) return k < nz / 2 ? 0 : 1;
+    return cell_type(j, k, ny, nz, lo, hi, 10);
+  }
   if (kind == 8) return 3;
   if (kind == 9) return cell_type(j, k, ny, nz, lo, hi, 2) == 0 ? 0 : 3;
   if (kind == 2) {

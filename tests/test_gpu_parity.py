@@ -92,7 +92,7 @@ def test_rhs_parity(dims, p, kind, prec):
 @pytest.mark.parametrize("dims,p,kind", [((4, 4, 4), 3, "hex"), ((2, 2, 2), 3, "prism"), ((2, 2, 4), 2, "mixed"),
                                          ((2, 3, 3), 4, "hex"), ((2, 2, 2), 3, "tet"), ((2, 3, 2), 2, "prism_tet"),
                                          ((2, 2, 2), 3, "pyr"), ((2, 3, 2), 2, "hex_pyr"),
-                                         ((1, 2, 4), 3, "hex_pyr_tet")])
+                                         ((1, 2, 4), 3, "hex_pyr_tet"), ((2, 2, 3), 2, "hex_prism_pyr_tet")])
 def test_plain_path_parity(dims, p, kind):
     """The unfused FP64 comparison path (dense operators, library GEMMs)."""
     _need_gpu()
@@ -107,7 +107,7 @@ def test_plain_path_parity(dims, p, kind):
     assert np.all(err < tol), (err, tol)
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "pyr", "hex_pyr", "hex_pyr_tet"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "pyr", "hex_pyr", "hex_pyr_tet", "hex_prism_pyr_tet"])
 def test_fused_matches_plain_on_gpu(kind):
     """Fused and plain GPU paths on a medium mesh (several workgroups and a
     ragged last block), FP64."""
@@ -178,7 +178,7 @@ NOAA_CASES = [((4, 4, 4), 3, "hex"), ((3, 3, 3), 1, "hex"), ((3, 2, 4), 2, "hex"
               ((2, 3, 1), 2, "prism"), ((2, 2, 2), 4, "prism"), ((2, 2, 4), 3, "mixed"), ((2, 1, 2), 2, "mixed"),
               ((2, 2, 2), 3, "tet"), ((1, 2, 2), 4, "tet"), ((2, 2, 2), 1, "tet"), ((2, 3, 2), 2, "prism_tet"),
               ((2, 2, 2), 3, "pyr"), ((1, 2, 2), 4, "pyr"), ((2, 2, 2), 1, "pyr"), ((2, 3, 2), 2, "hex_pyr"),
-              ((2, 2, 3), 3, "hex_pyr_tet")]
+              ((2, 2, 3), 3, "hex_pyr_tet"), ((2, 2, 3), 3, "hex_prism_pyr_tet")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -284,7 +284,8 @@ DENSE_CASES = [((2, 2, 2), 1, "tet"), ((2, 2, 2), 2, "tet"), ((2, 2, 2), 3, "tet
                ((1, 2, 1), 4, "prism_tet"), ((2, 2, 2), 1, "pyr"), ((2, 2, 2), 2, "pyr"), ((2, 2, 2), 3, "pyr"),
                ((1, 2, 2), 4, "pyr"), ((3, 2, 1), 3, "pyr"), ((1, 1, 1), 2, "pyr"), ((2, 2, 4), 3, "hex_pyr"),
                ((2, 3, 2), 2, "hex_pyr"), ((1, 2, 2), 4, "hex_pyr"), ((2, 2, 3), 2, "hex_pyr_tet"),
-               ((1, 2, 4), 3, "hex_pyr_tet"), ((1, 1, 3), 4, "hex_pyr_tet")]
+               ((1, 2, 4), 3, "hex_pyr_tet"), ((1, 1, 3), 4, "hex_pyr_tet"), ((2, 2, 3), 2, "hex_prism_pyr_tet"),
+               ((1, 2, 4), 3, "hex_prism_pyr_tet"), ((1, 2, 3), 4, "hex_prism_pyr_tet")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -306,10 +307,10 @@ def test_rhs_parity_tets_and_pyramids(dims, p, kind, prec):
     assert np.all(err < tol), (err, tol)
 
 
-@pytest.mark.parametrize("kind", ["tet", "prism_tet", "pyr", "hex_pyr", "hex_pyr_tet"])
+@pytest.mark.parametrize("kind", ["tet", "prism_tet", "pyr", "hex_pyr", "hex_pyr_tet", "hex_prism_pyr_tet"])
 def test_dense_free_stream_conservation_and_rk4(kind):
     _need_gpu()
-    dims, p = (2, 2, 3 if kind == "hex_pyr_tet" else 2), 3
+    dims, p = (2, 2, 3 if kind.endswith("pyr_tet") else 2), 3
     s = frmi.Solver(dims, p, kind, pref=inputs.P0)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()

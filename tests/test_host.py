@@ -51,7 +51,7 @@ def test_reference_operators_match_oracle(etype, name, p):
 
 
 @pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "hex_warp", "prism_warp", "mixed_warp",
-                                  "pyr", "hex_pyr", "hex_pyr_tet"])
+                                  "pyr", "hex_pyr", "hex_pyr_tet", "hex_prism_pyr_tet"])
 def test_mesh_coordinates_and_connectivity_match_oracle(kind):
     _lib_or_skip()
     dims = (3, 2, 4)
@@ -104,12 +104,13 @@ def test_surface_aa_rejected_where_not_built():
         frmi.Solver((2, 2, 2), 3, "hex_pyr_tet")
 
 
-@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "pyr", "hex_pyr", "hex_pyr_tet"])
+@pytest.mark.parametrize("kind", ["hex", "prism", "mixed", "tet", "prism_tet", "pyr", "hex_pyr", "hex_pyr_tet",
+                                  "hex_prism_pyr_tet"])
 def test_element_counts_match_oracle(kind):
     """The library's element counts per type (hexahedra, prisms, tetrahedra,
     pyramids) and its pairing match the oracle's."""
     _lib_or_skip()
-    dims = (2, 3, 3) if kind == "hex_pyr_tet" else (2, 3, 2)
+    dims = (2, 3, 3) if kind.endswith("pyr_tet") else (2, 3, 2)
     s = frmi.Solver(dims, 2, kind)
     m = Mesh(*dims, 2, kind)
     counts = {"hex": s.n_hex, "prism": s.n_prism, "tet": s.n_tet, "pyr": s.n_pyr}

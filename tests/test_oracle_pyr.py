@@ -206,7 +206,7 @@ def test_pyramid_weak_divergence(p):
         assert np.abs(np.asarray(r.wu @ r.Kq[d], float)).max() < 1e-14 * np.abs(np.asarray(r.Kq[d], float)).max()
 
 
-@pytest.mark.parametrize("kind", ["pyr", "hex_pyr", "hex_pyr_tet"])
+@pytest.mark.parametrize("kind", ["pyr", "hex_pyr", "hex_pyr_tet", "hex_prism_pyr_tet"])
 @pytest.mark.parametrize("p", [1, 3])
 def test_free_stream_and_conservation(kind, p):
     m = Mesh(2, 2, 3, p, kind)
@@ -242,7 +242,8 @@ def test_transition_cells():
         Mesh(2, 2, 2, 1, "hex_pyr_tet")
 
 
-@pytest.mark.parametrize("kind,sizes", [("pyr", (2, 4)), ("hex_pyr", (2, 4)), ("hex_pyr_tet", (3, 6))])
+@pytest.mark.parametrize("kind,sizes", [("pyr", (2, 4)), ("hex_pyr", (2, 4)), ("hex_pyr_tet", (3, 6)),
+                                        ("hex_prism_pyr_tet", (3, 6))])
 def test_entropy_wave_convergence(kind, sizes):
     """Euler entropy wave: the RHS error falls at about the design rate."""
     p = 2

@@ -17,6 +17,8 @@
 // solution point t + NT k; faces 0/1 = zeta -1/+1 (triangle nodes), faces
 // 2/3/4 = edges eta=-1, xi+eta=0, xi=-1 (GL points along the edge x GL in zeta,
 // index i + n k).
+#include <type_traits>
+
 #include "fr_device.h"
 #include "fr_kernels.h"
 
@@ -32,14 +34,21 @@ struct PrismOps {
 };
 
 template <int P, typename R>
-struct PrismTri {
+struct PrismTriOps {
   static constexpr int n = P + 1, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
   R Tq[NTQ][NT];              // triangle nodal basis at the conical quadrature points
   R Dxi[NT][NT], Deta[NT][NT];  // triangle derivatives at the nodes
   R PT[NT][NTQ], APxi[NT][NTQ], APeta[NT][NTQ];
   R Tedge[3][n][NT];          // nodal basis at the GL points of each edge
   R LiftEdge[3][NT][n];       // DG lifting of an edge point into the plane
-  R nodes[NT][2], qp[NTQ][2];  // triangle nodes and conical quadrature points
+};
+// the device table: the operators, then the triangle nodes and conical
+// quadrature points (needed by curved prisms only; the volume kernel stages
+// them in LDS only then, so the affine kernels keep their LDS size)
+template <int P, typename R>
+struct PrismTri : PrismTriOps<P, R> {
+  static constexpr int NT = PrismTriOps<P, R>::NT, NTQ = PrismTriOps<P, R>::NTQ;
+  R nodes[NT][2], qp[NTQ][2];
 };
 
 // Curved prisms: the map of the six vertices X (vertex t + 3c at triangle
@@ -239,7 +248,8 @@ __global__ void __launch_bounds__(NT_)
   constexpr bool PL = sizeof(R) == 4 && P <= 3;
   constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + (PL ? C::SZ_JE : C::SZ_J);
   static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
-  __shared__ PrismTri<P, R> tri;
+  using TriL = typename std::conditional<WARP, PrismTri<P, R>, PrismTriOps<P, R>>::type;
+  __shared__ TriL tri;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   int e0;
@@ -261,7 +271,7 @@ __global__ void __launch_bounds__(NT_)
 
   // phase 0: operator tables, state (reference form), metrics, neighbour states
   {
-    constexpr int NW = sizeof(PrismTri<P, R>) / sizeof(R);
+    constexpr int NW = sizeof(TriL) / sizeof(R);
     const R* src = reinterpret_cast<const R*>(tri_g);
     R* dst = reinterpret_cast<R*>(&tri);
     for (int it = tid; it < NW; it += NT_) dst[it] = src[it];
@@ -956,7 +966,11 @@ __global__ void __launch_bounds__(NT_)
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int c = 0; c < 3; ++c) S[d][c] = dj * sMet[cle][3 * d + c];
-    const R cqx = WARP ? tri.qp[ctq][0] : R(0), cqy = WARP ? tri.qp[ctq][1] : R(0);
+    R cqx = R(0), cqy = R(0);
+    if constexpr (WARP) {
+      cqx = tri.qp[ctq][0];
+      cqy = tri.qp[ctq][1];
+    }
     // thread `half` takes zeta level kq = 2j + half; the operator entries are
     // selected per lane (no divergent branch); for odd m the surplus level of
     // the odd thread repeats level 2j with zero projection weights

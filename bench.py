@@ -319,7 +319,7 @@ def main():
         ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
         ("fp64", 4, "fullaa", "hex"), ("fp32", 3, "fullaa", "prism"), ("fp32", 4, "fullaa", "prism"),
         ("fp32", 3, "fused", "tet"), ("fp64", 3, "fused", "tet"), ("fp32", 4, "fused", "tet"),
-        ("fp32", 3, "noaa", "tet"), ("fp64", 3, "plain", "tet"),
+        ("fp32", 3, "noaa", "tet"), ("fp32", 4, "noaa", "tet"), ("fp64", 3, "plain", "tet"),
         ("fp32", 3, "fused", "pyr"), ("fp64", 3, "fused", "pyr"), ("fp32", 4, "fused", "pyr"),
         ("fp32", 3, "noaa", "pyr"), ("fp64", 3, "plain", "pyr"), ("fp32", 3, "fused", "hex_pyr"),
         ("fp32", 3, "fused", "hex_pyr_tet"), ("fp32", 3, "fused", "hex_prism_pyr_tet"),

@@ -223,7 +223,9 @@ fr_status fr_integrals(fr_ctx* c, double* out5);
  *   "M0" (N_f x N_u), "M3" (N_u x N_f), "M7" (N_q x N_u), "M8" (N_u x N_q),
  *   "Dxi", "Deta", "Dzeta" (N_u x N_u)   dense operators of section 2.2;
  *   "APd" (3 x N_u x N_q)   tetrahedra, pyramids: -Mass^-1 Dq_d^T W_q
- *   "Ku" (3 x N_u x N_u)    pyramids: APd_d M7 (empty otherwise).
+ *   "Ku" (3 x N_u x N_u)    pyramids: APd_d M7 (empty otherwise);
+ *   "K0" (3 x N_u x N_u)    tetrahedra, pyramids: the divergence of a flux at
+ *                           the solution points (D_d - M3 n_d M0; pyramids Ku).
  * etype: fr_etype.  Errors: FR_EINVAL (unknown name or etype, cap too
  * small). */
 fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count);

@@ -572,6 +572,27 @@ fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64
   else if (nm == "wu") v = &r.wu;
   else if (nm == "APd") v = &r.APd;
   else if (nm == "Ku") v = &r.Ku;
+  else if (nm == "K0" && etype >= 2) {
+    // divergence of a flux held at the solution points (no anti-aliasing):
+    // tetrahedra D_d - M3 n_d M0, pyramids Ku_d; 3 x N_u x N_u
+    if (etype == 3) {
+      tmp = r.Ku;
+    } else {
+      tmp.assign((size_t)3 * r.nu * r.nu, 0.0);
+      for (int d = 0; d < 3; ++d)
+        for (int s = 0; s < r.nu; ++s)
+          for (int u = 0; u < r.nu; ++u) {
+            long double acc = r.Dg[((size_t)d * r.nu + s) * r.nu + u];
+            for (int f = 0; f < r.nf; ++f) {
+              int face = 0;
+              while (face + 1 < r.nfaces && f >= r.face_start[face + 1]) ++face;
+              acc -= (long double)r.M3[(size_t)s * r.nf + f] * r.face_normal[3 * face + d] * r.M0[(size_t)f * r.nu + u];
+            }
+            tmp[((size_t)d * r.nu + s) * r.nu + u] = (double)acc;
+          }
+    }
+    v = &tmp;
+  }
   else if (nm == "Dxi" || nm == "Deta" || nm == "Dzeta") {
     int d = nm == "Dxi" ? 0 : (nm == "Deta" ? 1 : 2);
     tmp.assign(r.Dg.begin() + (size_t)d * r.nu * r.nu, r.Dg.begin() + (size_t)(d + 1) * r.nu * r.nu);

@@ -61,7 +61,11 @@ struct DenseCfg {
   static constexpr int O_PG = O_PM0 + MTF * KSU * 64;            // [D_d | n_d M3]: MTG x (KSU + KSF)
   static constexpr int O_PM7 = O_PG + MTG * (KSU + KSF) * 64;    // M7: MTQ x KSU
   static constexpr int O_PAP = O_PM7 + MTQ * KSU * 64;           // [AP_0 | AP_1 | AP_2]: MTU x 3 KSQ
-  static constexpr int SIZE = O_PAP + MTU * 3 * KSQ * 64;
+  // without anti-aliasing the divergence of the flux at the solution points,
+  // [K0_0 | K0_1 | K0_2]: MTU x 3 KSU, K0_d = D_d - M3 n_d M0 for tetrahedra
+  // (the strong form (M1 - M3 M2) in one operator), Ku_d for pyramids
+  static constexpr int O_PK0 = O_PAP + MTU * 3 * KSQ * 64;
+  static constexpr int SIZE = O_PK0 + MTU * 3 * KSU * 64;
   // LDS per element of the volume kernel: state + gradients [20][NU]
   // (later the partial divergences [3][5][NU]), neighbour values then jumps
   // [5][NF], the transformed flux at the quadrature points [3][5][FQS]
@@ -408,7 +412,7 @@ __device__ __forceinline__ void mf_acc(mf4& acc, const float* __restrict__ Ap, c
   for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[4 * ks * bs], acc, 0, 0, 0);
 }
 
-template <int ET, int P, int EB, int NT>
+template <int ET, int P, int EB, int NT, bool AA>
 __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const float* __restrict__ ops,
                                                       const Gas<float> g, const double eref) {
   using C = DenseCfg<ET, P>;
@@ -562,6 +566,50 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
   }
   lds_barrier();
+
+  if constexpr (!AA) {
+    // tdisf at the solution points, F~_d of variable v into column 5 d + v of
+    // the point's U2 row, then the divergence [K0_0 | K0_1 | K0_2] F~ as one
+    // product over K = (direction, solution point)
+    for (int it = tid; it < EB * NU; it += NT) {
+      const int le = it / NU, s0 = it - le * NU;
+      const R* X = XS(le);
+      R u[5], q[3][5], f[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        u[v] = X[v * NU + s0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[c][v] = X[(5 + c * 5 + v) * NU + s0];
+      }
+      point_flux(u, q, g, f);
+      const R dj = sMet[le][9];
+      R* w = U2(le) + s0 * LDW;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+    }
+    lds_barrier();
+    constexpr int NTL = (5 * EB + 15) / 16;
+    for (int t = wave; t < C::MTU * NTL; t += NW) {
+      const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
+      const bool ok = j < 5 * EB;
+      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      const R* Ap = ops + C::O_PK0 + mt * 3 * C::KSU * 64;
+      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) mf_acc<C::KSU>(acc, Ap + d * C::KSU * 64, U2(le) + d * 5 + v, LDW, lane);
+      const int e = e0 + le;
+      if (ok && e < E)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int s0 = mt * 16 + 4 * (lane >> 4) + r;
+          if (s0 < NU) Rp[(size_t)e * 5 * NU + v * NU + s0] = acc[r];
+        }
+    }
+    return;
+  }
 
   // phase 4: state and gradient at the quadrature points (M7) into U2 rows,
   // then tdisf per point (eq. FR-tdisfq), F~_d of variable v in place into
@@ -737,6 +785,15 @@ static void pack_dense(const RefElem& r, R* o) {
     const int d = k / (4 * C::KSQ), q = k % (4 * C::KSQ);
     return row < NU && q < NQ ? r.APd[(d * NU + row) * NQ + q] : 0.0;
   });
+  tiles(C::O_PK0, C::MTU, 3 * C::KSU, [&](int row, int k) {
+    const int d = k / (4 * C::KSU), u = k % (4 * C::KSU);
+    if (row >= NU || u >= NU) return 0.0;
+    if (C::PYR) return r.Ku[(d * NU + row) * NU + u];
+    long double acc = r.Dg[(d * NU + row) * NU + u];
+    for (int f = 0; f < NF; ++f)
+      acc -= (long double)r.M3[row * NF + f] * r.face_normal[3 * C::face_of(f) + d] * r.M0[f * NU + u];
+    return (double)acc;
+  });
 }
 
 template <int ET>
@@ -815,16 +872,16 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
                        dim3(256), 0, st, a.one, a.from_ust, ops, eref);
   if ((a.stage & 2) && E > 0) {
-    // FP32 with anti-aliasing at p >= 3 on the matrix cores (measured at 48^3
-    // cells: 14-42% faster than the VALU kernel; at p <= 2 the tiles are too
+    // FP32 at p >= 3 on the matrix cores (with anti-aliasing measured at 48^3
+    // cells 14-42% faster than the VALU kernel; at p <= 2 the tiles are too
     // small and the VALU kernel is faster)
     constexpr bool MF = std::is_same<R, float>::value && P >= 3;
     if constexpr (MF) {
       if (a.aa)
-        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
+        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
                            a.from_ust, ops, g, eref);
       else
-        hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
+        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st,
                            a.one, a.from_ust, ops, g, eref);
     } else {
       if (a.aa)

@@ -43,7 +43,11 @@ def test_reference_operators_match_oracle(etype, name, p):
     pairs = [("upts", r.upts), ("fpts", r.fpts), ("qpts", r.qpts), ("qwts", r.qwts), ("M0", r.M0), ("M3", r.M3),
              ("M7", r.M7), ("M8", r.M8), ("wu", r.wu), ("Dxi", r.Dg[0]), ("Deta", r.Dg[1]), ("Dzeta", r.Dg[2])]
     if name == "pyr":
-        pairs += [("APd", r.Kq), ("Ku", r.Ku)]
+        pairs += [("APd", r.Kq), ("Ku", r.Ku), ("K0", r.Ku)]
+    if name == "tet":
+        # no anti-aliasing: the strong form (M1 - M3 M2) as one operator per direction
+        k0 = np.stack([r.Dg[d] - r.M3 @ (r.fnorm[:, d][:, None] * r.M0) for d in range(3)])
+        pairs += [("K0", k0)]
     for key, ref in pairs:
         got = frmi.ref_operator(etype, p, key).reshape(ref.shape)
         scale = max(1.0, np.abs(ref).max())

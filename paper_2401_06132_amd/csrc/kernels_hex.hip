@@ -167,7 +167,12 @@ struct HexVol {
   static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
   static constexpr int SZ_X = 20 * NU, SZ_Y = 10 * m * n * n;
   static constexpr int SZ_A = SZ_X > SZ_Y ? SZ_X : SZ_Y;
-  static constexpr int SZ_T1 = 20 * m * n * n, SZ_Z = 15 * m * m * n, SZ_J = 30 * NFP;
+  // x-interpolated fields T1 [20][m][TPS]; at p = 4 the rows of n^2 are
+  // padded to n^2 + 1 so that the quadrature columns of a wave read
+  // different banks (measured at 48^3: 1% faster in FP32, 4% in FP64; at
+  // p = 3 the unpadded rows are faster)
+  static constexpr int TPS = P >= 4 ? NFP + 1 : NFP;
+  static constexpr int SZ_T1 = 20 * m * TPS, SZ_Z = 15 * m * m * n, SZ_J = 30 * NFP;
   static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
   static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
@@ -611,13 +616,13 @@ __global__ void __launch_bounds__(NT)
     R x[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * r];
-    R* T = TS(le) + (fld * m) * NFP + j * n + l;
+    R* T = TS(le) + (fld * m) * C::TPS + j * n + l;
 #pragma unroll
     for (int a = 0; a < m; ++a) {
       R s = R(0);
 #pragma unroll
       for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
-      T[a * NFP] = s;
+      T[a * C::TPS] = s;
     }
   }
   lds_barrier();
@@ -633,7 +638,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int j = 0; j < n; ++j) Ib[j] = sI[cb][j];
     R t2[20][n];
-    const R* T = TS(cle) + ca * NFP;
+    const R* T = TS(cle) + ca * C::TPS;
 #pragma unroll
     for (int fld = 0; fld < 20; ++fld) {
 #pragma unroll
@@ -641,7 +646,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int j = 0; j < n; ++j)
 #pragma unroll
-        for (int l = 0; l < n; ++l) t2[fld][l] += Ib[j] * T[fld * m * NFP + j * n + l];
+        for (int l = 0; l < n; ++l) t2[fld][l] += Ib[j] * T[fld * m * C::TPS + j * n + l];
     }
     R S[3][3];
     const R dj = sMet[cle][9];

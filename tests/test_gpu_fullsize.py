@@ -5,7 +5,10 @@ launch configuration as bench.py); the oracle evaluates the RHS of a random
 sample of elements (rhs_subset: the two-hop neighbourhood of each sampled
 element), in extended precision.  Tolerances as in test_gpu_parity.py:
 fused FP64 1e-12, plain FP64 2e-12, FP32 1e-3 (per variable, relative to the
-sample's max).
+sample's max).  Besides the benchmark configurations (hexahedra, prisms,
+the mixed mesh), the tetrahedron, pyramid and four-type meshes that the
+benchmark also times run here at 48^3 cells in FP32 (the matrix-core volume
+kernels, with and without flux anti-aliasing).
 """
 
 import numpy as np
@@ -32,7 +35,8 @@ def _mesh(kind, n, p):
 
 CASES = [("hex", 48, 3, "fp32"), ("hex", 48, 3, "fp64"), ("hex", 48, 4, "fp32"), ("hex", 48, 4, "fp64"),
          ("prism", 48, 3, "fp32"), ("prism", 48, 3, "fp64"), ("prism", 48, 4, "fp32"),
-         ("mixed", 64, 4, "fp32"), ("hex", 48, 3, "plain")]
+         ("mixed", 64, 4, "fp32"), ("hex", 48, 3, "plain"), ("tet", 48, 3, "fp32"), ("tet", 48, 3, "fp32_noaa"),
+         ("pyr", 48, 3, "fp32"), ("hex_prism_pyr_tet", 48, 3, "fp32")]
 
 
 @pytest.mark.timeout(600)
@@ -44,7 +48,9 @@ def test_fullsize_sampled_parity(kind, n, p, prec):
     m = _mesh(kind, n, p)
     U = inputs.element_state([m.upts_coords(t) for t in m.types], seed=0)
     form = "plain" if prec == "plain" else "fused"
-    s = frmi.Solver(n, p, kind, prec="fp64" if prec == "plain" else prec, form=form, pref=inputs.P0)
+    aa = not prec.endswith("_noaa")
+    prec = prec.replace("_noaa", "")
+    s = frmi.Solver(n, p, kind, prec="fp64" if prec == "plain" else prec, form=form, pref=inputs.P0, aa=aa)
     lib_xyz = s.upts_coords()
     for t, x in zip(m.types, lib_xyz):
         np.testing.assert_allclose(x[::997], m.upts_coords(t)[::997], atol=1e-12)
@@ -57,7 +63,7 @@ def test_fullsize_sampled_parity(kind, n, p, prec):
     rng = np.random.default_rng(12345)
     sel = {t: np.sort(rng.choice(m.nelem[t], size=96, replace=False)) for t in m.types}
     Uo = {t: x for t, x in zip(m.types, U)}
-    ref = rhs_subset(m, {t: x.astype(np.longdouble) for t, x in Uo.items()}, Params(pref=inputs.P0), sel,
+    ref = rhs_subset(m, {t: x.astype(np.longdouble) for t, x in Uo.items()}, Params(pref=inputs.P0, aa=aa), sel,
                      dtype=np.longdouble)
     # the plain comparison path applies the dense (M1 - M3 M2) M9 operator,
     # summing 3 N_q terms of the ~250-magnitude energy flux per output; its

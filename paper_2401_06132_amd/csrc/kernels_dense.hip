@@ -386,10 +386,11 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 }
 
 // ------------------------------------------------- volume, matrix cores
-// The FP32 volume group with every dense product on the matrix cores
-// (v_mfma_f32_16x16x4f32: D(16x16) += A(16x4) B(4x16) per wave; lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-// D[4 (l / 16) + r][l % 16], r < 4).  A product C = A B runs over 16 x 16
+// The volume group with every dense product on the matrix cores
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64: D(16x16) += A(16x4)
+// B(4x16) per wave; lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds, for r < 4, D[4 (l / 16) + r][l % 16] in FP32 and
+// D[l / 16 + 4 r][l % 16] in FP64).  A product C = A B runs over 16 x 16
 // output tiles: rows are operator rows, columns the (element, field) pairs
 // of the workgroup; the waves take tiles in turn.  A comes from the packed
 // operator copy (one coalesced 64-value load per k-step), B from the
@@ -397,26 +398,45 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 // quadrature values) go through LDS rows; the three directions of the
 // projection-divergence are one product with K concatenated.
 typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct MfVec;
+template <>
+struct MfVec<float> {
+  typedef mf4 T;
+  // output row of value r of this lane within the 16-row tile
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  __device__ static mf4 mfma(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct MfVec<double> {
+  typedef md4 T;
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  __device__ static md4 mfma(double a, double b, md4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
 
 // acc += A B over KS k-steps: A a packed tile (its KS values of this lane
 // loaded up front), B the column of this lane at bcol with stride bs in k.
 // The packed A is zero past the operator's K, and the B reads there stay in
 // finite (zero-initialised or written) LDS, so no bounds checks are needed.
-template <int KS>
-__device__ __forceinline__ void mf_acc(mf4& acc, const float* __restrict__ Ap, const float* bcol, int bs, int lane) {
-  float a[KS];
+template <int KS, typename R>
+__device__ __forceinline__ void mf_acc(typename MfVec<R>::T& acc, const R* __restrict__ Ap, const R* bcol, int bs,
+                                       int lane) {
+  R a[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) a[ks] = Ap[ks * 64 + lane];
-  const float* b = bcol + (lane >> 4) * bs;
+  const R* b = bcol + (lane >> 4) * bs;
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[4 * ks * bs], acc, 0, 0, 0);
+  for (int ks = 0; ks < KS; ++ks) acc = MfVec<R>::mfma(a[ks], b[4 * ks * bs], acc);
 }
 
-template <int ET, int P, int EB, int NT, bool AA>
-__global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const float* __restrict__ ops,
-                                                      const Gas<float> g, const double eref) {
+template <int ET, int P, typename R, int EB, int NT, bool AA>
+__global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const R* __restrict__ ops,
+                                                      const Gas<R> g, const double eref) {
   using C = DenseCfg<ET, P>;
-  using R = float;
+  using V4 = typename MfVec<R>::T;
   constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, NFACE = C::NFACE, LDW = C::LDW;
   constexpr int PE = C::PE_MF, NW = NT / 64;
   __shared__ R smem[EB * PE];
@@ -471,12 +491,12 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
       mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + v * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int fp = mt * 16 + 4 * (lane >> 4) + r;
+          const int fp = mt * 16 + MfVec<R>::row(lane, r);
           if (fp < NF) {
             const bool left = sFR[le * NFACE + C::face_of(fp)].info & 1;
             const R w = left ? R(0.5) + g.beta : R(0.5) - g.beta;
@@ -497,13 +517,13 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
       const R* Ap = ops + C::O_PG + mt * (C::KSU + C::KSF) * 64;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
       mf_acc<C::KSU>(acc, Ap, XS(le) + v * NU, 1, lane);
       mf_acc<C::KSF>(acc, Ap + C::KSU * 64, U2(le) + v * NF, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = mt * 16 + 4 * (lane >> 4) + r;
+          const int row = mt * 16 + MfVec<R>::row(lane, r);
           if (row < 3 * NU) {
             const int d = row / NU, s = row - d * NU;
             XS(le)[(5 + d * 5 + v) * NU + s] = acc[r];
@@ -535,12 +555,12 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 20 * EB;
       const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
       mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int fp = mt * 16 + 4 * (lane >> 4) + r;
+          const int fp = mt * 16 + MfVec<R>::row(lane, r);
           if (fp < NF) U2(le)[fp * LDW + c] = acc[r];
         }
     }
@@ -597,14 +617,14 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
       const R* Ap = ops + C::O_PK0 + mt * 3 * C::KSU * 64;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) mf_acc<C::KSU>(acc, Ap + d * C::KSU * 64, U2(le) + d * 5 + v, LDW, lane);
       const int e = e0 + le;
       if (ok && e < E)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int s0 = mt * 16 + 4 * (lane >> 4) + r;
+          const int s0 = mt * 16 + MfVec<R>::row(lane, r);
           if (s0 < NU) Rp[(size_t)e * 5 * NU + v * NU + s0] = acc[r];
         }
     }
@@ -620,12 +640,12 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 20 * EB;
       const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
       mf_acc<C::KSU>(acc, ops + C::O_PM7 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int q0 = mt * 16 + 4 * (lane >> 4) + r;
+          const int q0 = mt * 16 + MfVec<R>::row(lane, r);
           if (q0 < NQ) U2(le)[q0 * LDW + c] = acc[r];
         }
     }
@@ -660,7 +680,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
       const R* Ap = ops + C::O_PAP + mt * 3 * C::KSQ * 64;
-      mf4 acc = {0.f, 0.f, 0.f, 0.f};
+      V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         mf_acc<C::KSQ>(acc, Ap + d * C::KSQ * 64, U2(le) + d * 5 + v, LDW, lane);
@@ -668,7 +688,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       if (ok && e < E)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int s = mt * 16 + 4 * (lane >> 4) + r;
+          const int s = mt * 16 + MfVec<R>::row(lane, r);
           if (s < NU) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[r];
         }
     }
@@ -872,16 +892,20 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
                        dim3(256), 0, st, a.one, a.from_ust, ops, eref);
   if ((a.stage & 2) && E > 0) {
-    // FP32 at p >= 3 on the matrix cores (with anti-aliasing measured at 48^3
-    // cells 14-42% faster than the VALU kernel; at p <= 2 the tiles are too
-    // small and the VALU kernel is faster)
-    constexpr bool MF = std::is_same<R, float>::value && P >= 3;
+    // p >= 3 on the matrix cores.  With anti-aliasing at 48^3 cells the
+    // volume group runs 14-42% faster than the VALU kernel in FP32 and
+    // 1.3-2.4x faster in FP64, except FP64 tetrahedra at p = 4 (21.7 ms
+    // against 16.7 on the VALU).  At p <= 2 the tiles are too small and the
+    // VALU kernel is faster.
+    constexpr bool MF = P >= 3 && !(sizeof(R) == 8 && !DenseCfg<ET, P>::PYR && P >= 4);
+    // FP64 doubles the LDS per element: half the elements per workgroup
+    constexpr int EBM = sizeof(R) == 8 ? (EB > 1 ? EB / 2 : 1) : EB;
     if constexpr (MF) {
       if (a.aa)
-        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256, true>), dim3((E + EB - 1) / EB), dim3(256), 0, st, a.one,
-                           a.from_ust, ops, g, eref);
+        hipLaunchKernelGGL((dense_volume_mf<ET, P, R, EBM, 256, true>), dim3((E + EBM - 1) / EBM), dim3(256), 0, st,
+                           a.one, a.from_ust, ops, g, eref);
       else
-        hipLaunchKernelGGL((dense_volume_mf<ET, P, EB, 256, false>), dim3((E + EB - 1) / EB), dim3(256), 0, st,
+        hipLaunchKernelGGL((dense_volume_mf<ET, P, R, EBM, 256, false>), dim3((E + EBM - 1) / EBM), dim3(256), 0, st,
                            a.one, a.from_ust, ops, g, eref);
     } else {
       if (a.aa)

@@ -159,9 +159,14 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
 
 // --------------------------------------------------------------- volume
 // LDS per element: region A holds the state + gradients (20 fields at the
-// solution points), later the y-projected residual; region B holds the
-// neighbour face states, then the x-interpolated fields T1, then the
-// z-projected flux Z (written only after every column has read T1).
+// solution points); region B, after it, holds the neighbour face states,
+// then the x-interpolated fields T1.  The state and gradients are dead once
+// T1 is formed, so the z-projected flux Z (written only after every column
+// has read T1) starts at offset 0 across both regions, and the y-projected
+// residual Y follows Z.  The footprint is the larger of the two pairs
+// (p = 3: 3200 values instead of 3440; measured at 48^3 with EB unchanged:
+// p = 4 volume kernel 4% faster in FP32 and 10-13% in FP64, p = 3 within
+// noise).
 template <int P>
 struct HexVol {
   static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
@@ -173,14 +178,14 @@ struct HexVol {
   // p = 3 the unpadded rows are faster)
   static constexpr int TPS = P >= 4 ? NFP + 1 : NFP;
   static constexpr int SZ_T1 = 20 * m * TPS, SZ_Z = 15 * m * m * n, SZ_J = 30 * NFP;
-  static constexpr int SZ_B0 = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
-  static constexpr int SZ_B = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
-  static constexpr int PER_ELEM = SZ_A + SZ_B;
   // surface-flux anti-aliasing, per axis: face values interpolated along the
   // first tangential axis [2][20][m][n], viscous flux at the face
   // quadrature points [2][4][m][m]
   static constexpr int SZ_ST = 2 * 20 * m * n, SZ_S = SZ_ST + 2 * 4 * m * m;
-  static_assert(SZ_S <= SZ_B, "face quadrature staging fits region B");
+  static constexpr int SZ_B0 = SZ_T1 > SZ_J ? SZ_T1 : SZ_J;
+  static constexpr int SZ_B = SZ_B0 > SZ_S ? SZ_B0 : SZ_S;
+  static constexpr int SZ_ZY = SZ_Z + SZ_Y;
+  static constexpr int PER_ELEM = SZ_A + SZ_B > SZ_ZY ? SZ_A + SZ_B : SZ_ZY;
 };
 
 // Loads of one batch of EB elements, held in registers: the state, face
@@ -324,10 +329,10 @@ __global__ void __launch_bounds__(NT)
   const R* __restrict__ met = (const R*)sg.met;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
-#define YS(le) (smem + (le)*PE)            /* [2][5][m][n][n]              */
+#define YS(le) (smem + (le)*PE + C::SZ_Z)  /* [2][5][m][n][n]              */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
 #define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][m][n][n]                */
-#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][m][m][n]              */
+#define ZS(le) (smem + (le)*PE)            /* [3][5][m][m][n]              */
 #define SS(le) (smem + (le)*PE + C::SZ_A)  /* [2][20][m][n], [2][4][m][m]  */
 
   // phase 0: state (reference form), metrics, neighbour states at own

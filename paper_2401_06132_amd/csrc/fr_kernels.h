@@ -81,7 +81,7 @@ struct TypeArgs {
 hipError_t hex_rhs(const TypeArgs& a, int prec, hipStream_t st);
 hipError_t prism_rhs(const TypeArgs& a, int prec, hipStream_t st);
 // elements per workgroup of kernel k (K_DISU, K_VOLUME, K_SURFACE)
-int hex_block_elems(int p, int prec, int k, bool saa);
+int hex_block_elems(int p, int prec, int k, bool aa, bool saa);
 int prism_block_elems(int p, int prec, int k, bool saa);
 // size in bytes of the prism operator table for order p and precision prec,
 // and its packing into host memory (uploaded once per context)

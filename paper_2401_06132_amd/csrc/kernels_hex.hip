@@ -158,15 +158,23 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
 }
 
 // --------------------------------------------------------------- volume
-// LDS per element: region A holds the state + gradients (20 fields at the
-// solution points); region B, after it, holds the neighbour face states,
-// then the x-interpolated fields T1.  The state and gradients are dead once
-// T1 is formed, so the z-projected flux Z (written only after every column
-// has read T1) starts at offset 0 across both regions, and the y-projected
-// residual Y follows Z.  The footprint is the larger of the two pairs
-// (p = 3: 3200 values instead of 3440; measured at 48^3 with EB unchanged:
-// p = 4 volume kernel 4% faster in FP32 and 10-13% in FP64, p = 3 within
-// noise).
+// LDS per element, in the order the phases use it:
+//   region A, offset 0: the state + gradients (20 fields at the solution
+//     points); region B, after A: the neighbour face states (and the
+//     surface-flux AA staging);
+//   offset 0: the x-interpolated fields T1, written over A and B once every
+//     thread holds its x rows in registers (the state and gradients are dead
+//     after the x sweep);
+//   offset 0: the z-projected flux Z, written after every column has read
+//     T1; the y-projected residual Y is written inside Z, each thread into
+//     the Z entries that only it reads.
+// The footprint is the largest of A + B, T1 and Z (p = 3: 2160 values
+// instead of 3440 with separate regions).  Measured at 48^3 (volume group):
+// FP32 p = 3 with 7 elements per workgroup 0.736 -> 0.627 ms, FP32 p = 4
+// 1.51 -> 1.24 ms, FP64 p = 3 1.89 -> 1.51 ms.  At p = 4 in FP64, with
+// surface-flux AA or curved, T1 stays after region A and Y after Z (the
+// footprint is the larger of A + B + T1 and Z + Y): the x rows held in
+// registers there spill (FP64: 4.29 -> 4.54 ms).
 template <int P>
 struct HexVol {
   static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
@@ -182,10 +190,18 @@ struct HexVol {
   // first tangential axis [2][20][m][n], viscous flux at the face
   // quadrature points [2][4][m][m]
   static constexpr int SZ_ST = 2 * 20 * m * n, SZ_S = SZ_ST + 2 * 4 * m * m;
-  static constexpr int SZ_B0 = SZ_T1 > SZ_J ? SZ_T1 : SZ_J;
-  static constexpr int SZ_B = SZ_B0 > SZ_S ? SZ_B0 : SZ_S;
-  static constexpr int SZ_ZY = SZ_Z + SZ_Y;
-  static constexpr int PER_ELEM = SZ_A + SZ_B > SZ_ZY ? SZ_A + SZ_B : SZ_ZY;
+  // T1 over region A and Y inside Z (TOX), or T1 after region A and Y after
+  // Z; at p = 4 in FP64, with surface-flux AA (SAA) or curved (WARP) the
+  // registers that hold the x rows across the barrier spill
+  template <typename R, bool SAA, bool WARP>
+  static constexpr bool tox() { return !(P >= 4 && (sizeof(R) == 8 || SAA || WARP)); }
+  // per element with flux anti-aliasing; SAA: with surface-flux AA staging
+  static constexpr int per_elem(bool SAA, bool TOX) {
+    const int b0 = SAA && SZ_S > SZ_J ? SZ_S : SZ_J;
+    const int b = TOX || b0 > SZ_T1 ? b0 : SZ_T1;
+    const int t = TOX ? (SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z) : SZ_Z + SZ_Y;
+    return SZ_A + b > t ? SZ_A + b : t;
+  }
 };
 
 // Loads of one batch of EB elements, held in registers: the state, face
@@ -309,7 +325,8 @@ __global__ void __launch_bounds__(NT)
   using C = HexVol<P>;
   constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
   constexpr int SZ_BN = SAA && C::SZ_S > C::SZ_J ? C::SZ_S : C::SZ_J;  // region B without AA
-  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + SZ_BN;
+  constexpr bool TOX = C::template tox<R, SAA, WARP>();
+  constexpr int PE = AA ? C::per_elem(SAA, TOX) : C::SZ_A + SZ_BN;
   static_assert(EB * m * m <= NT, "one quadrature column per thread");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
@@ -329,9 +346,9 @@ __global__ void __launch_bounds__(NT)
   const R* __restrict__ met = (const R*)sg.met;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
-#define YS(le) (smem + (le)*PE + C::SZ_Z)  /* [2][5][m][n][n]              */
+#define YS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_Z)) /* [2][5][m][YB][n]  */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
-#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][m][n][n]                */
+#define TS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [20][m][TPS]      */
 #define ZS(le) (smem + (le)*PE)            /* [3][5][m][m][n]              */
 #define SS(le) (smem + (le)*PE + C::SZ_A)  /* [2][20][m][n], [2][4][m][m]  */
 
@@ -614,20 +631,53 @@ __global__ void __launch_bounds__(NT)
     }
     return;
   }
-  // phase 3b: x interpolation of the 20 fields (first factor of M7 / M10)
-  for (int it = tid; it < EB * 20 * NFP; it += NT) {
-    const int le = it / (20 * NFP), r0 = it - le * (20 * NFP), fld = r0 / NFP, r = r0 - fld * NFP;
-    const int j = r % n, l = r / n;
-    R x[n];
+  // phase 3b: x interpolation of the 20 fields (first factor of M7 / M10).
+  // Over region A (TOX) every thread reads its x rows into registers before
+  // a barrier and writes T1 after it.
+  if constexpr (TOX) {
+    constexpr int NIT = (EB * 20 * NFP + NT - 1) / NT;
+    R x[NIT][n];
 #pragma unroll
-    for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * r];
-    R* T = TS(le) + (fld * m) * C::TPS + j * n + l;
+    for (int k = 0; k < NIT; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 20 * NFP) {
+        const int le = it / (20 * NFP), r0 = it - le * (20 * NFP), fld = r0 / NFP, r = r0 - fld * NFP;
 #pragma unroll
-    for (int a = 0; a < m; ++a) {
-      R s = R(0);
+        for (int i = 0; i < n; ++i) x[k][i] = XS(le)[fld * NU + i + n * r];
+      }
+    }
+    lds_barrier();
 #pragma unroll
-      for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
-      T[a * C::TPS] = s;
+    for (int k = 0; k < NIT; ++k) {
+      const int it = tid + k * NT;
+      if (it < EB * 20 * NFP) {
+        const int le = it / (20 * NFP), r0 = it - le * (20 * NFP), fld = r0 / NFP, r = r0 - fld * NFP;
+        const int j = r % n, l = r / n;
+        R* T = TS(le) + (fld * m) * C::TPS + j * n + l;
+#pragma unroll
+        for (int a = 0; a < m; ++a) {
+          R s = R(0);
+#pragma unroll
+          for (int i = 0; i < n; ++i) s += op.I[a][i] * x[k][i];
+          T[a * C::TPS] = s;
+        }
+      }
+    }
+  } else {
+    for (int it = tid; it < EB * 20 * NFP; it += NT) {
+      const int le = it / (20 * NFP), r0 = it - le * (20 * NFP), fld = r0 / NFP, r = r0 - fld * NFP;
+      const int j = r % n, l = r / n;
+      R x[n];
+#pragma unroll
+      for (int i = 0; i < n; ++i) x[i] = XS(le)[fld * NU + i + n * r];
+      R* T = TS(le) + (fld * m) * C::TPS + j * n + l;
+#pragma unroll
+      for (int a = 0; a < m; ++a) {
+        R s = R(0);
+#pragma unroll
+        for (int i = 0; i < n; ++i) s += op.I[a][i] * x[i];
+        T[a * C::TPS] = s;
+      }
     }
   }
   lds_barrier();
@@ -706,7 +756,10 @@ __global__ void __launch_bounds__(NT)
   }
   lds_barrier();
 
-  // phase 5: y projection: X' = P_y X, Y' = AP_y Y + P_y Z
+  // phase 5: y projection: X' = P_y X, Y' = AP_y Y + P_y Z.  Inside Z
+  // (TOX), Y[d][v][a][j][l] takes the place of Z[d][v][a][j][l], which only
+  // this thread reads (into registers, before it writes).
+  constexpr int YB = TOX ? m : n;
   for (int it = tid; it < EB * 5 * m * n; it += NT) {
     const int le = it / (5 * m * n), r0 = it - le * (5 * m * n);
     const int v = r0 / (m * n), r1 = r0 - v * (m * n), a = r1 / n, l = r1 - a * n;
@@ -727,8 +780,8 @@ __global__ void __launch_bounds__(NT)
         sx += op.Pj[j][b] * zx[b];
         sy += op.AP[j][b] * zy[b] + op.Pj[j][b] * zz[b];
       }
-      Y[(((0 * 5 + v) * m + a) * n + j) * n + l] = sx;
-      Y[(((1 * 5 + v) * m + a) * n + j) * n + l] = sy;
+      Y[(((0 * 5 + v) * m + a) * YB + j) * n + l] = sx;
+      Y[(((1 * 5 + v) * m + a) * YB + j) * n + l] = sy;
     }
   }
   lds_barrier();
@@ -742,8 +795,8 @@ __global__ void __launch_bounds__(NT)
     R y0[m], y1[m];
 #pragma unroll
     for (int a = 0; a < m; ++a) {
-      y0[a] = Y[(((0 * 5 + v) * m + a) * n + j) * n + l];
-      y1[a] = Y[(((1 * 5 + v) * m + a) * n + j) * n + l];
+      y0[a] = Y[(((0 * 5 + v) * m + a) * YB + j) * n + l];
+      y1[a] = Y[(((1 * 5 + v) * m + a) * YB + j) * n + l];
     }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
@@ -1068,6 +1121,13 @@ template <> struct HexLaunch<2, true> { static constexpr int EB = 2, NT = 64; };
 template <> struct HexLaunch<3, true> { static constexpr int EB = 1, NT = 64; };    // 36
 template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 49
 
+// with flux anti-aliasing (AA) the footprint of the overlaid LDS regions
+// fits 7 elements per 256-thread workgroup at p = 3 in FP32 (252 quadrature
+// columns instead of 180; two workgroups per CU)
+template <int P, bool DBL, bool AA>
+struct HexVolLaunch : HexLaunch<P, DBL> {};
+template <> struct HexVolLaunch<3, false, true> { static constexpr int EB = 7, NT = 256; };
+
 // elements per workgroup of the disu kernel (256 threads)
 constexpr int HEX_DISU_EB = 8;
 // elements per workgroup of the interface kernel (256 threads): at most two
@@ -1084,7 +1144,7 @@ template <int P, typename R, bool BT, bool DIAG, bool AA, bool SAA, bool WARP = 
 static void hex_volume_launch(const TypeArgs& a, int nb, const HexOps<P, R>& op, const Gas<R>& g, double eref,
                               hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  constexpr int EB = HexLaunch<P, dbl>::EB, NT = HexLaunch<P, dbl>::NT;
+  constexpr int EB = HexVolLaunch<P, dbl, AA>::EB, NT = HexVolLaunch<P, dbl, AA>::NT;
   hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA, WARP>), dim3(nb), dim3(NT), 0, st, a.one,
                      a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
 }
@@ -1142,7 +1202,7 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
 template <int P, typename R>
 static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {HEX_DISU_EB, HexLaunch<P, dbl>::EB,
+  const int ebs[3] = {HEX_DISU_EB, a.aa ? HexVolLaunch<P, dbl, true>::EB : HexVolLaunch<P, dbl, false>::EB,
                       a.saa ? HexSurf<P, dbl, true>::EB : HexSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
@@ -1160,7 +1220,13 @@ static int hex_surf_elems(bool d, bool saa) {
            : (saa ? HexSurf<P, false, true>::EB : HexSurf<P, false>::EB);
 }
 
-int hex_block_elems(int p, int prec, int k, bool saa) {
+template <int P>
+static int hex_vol_elems(bool d, bool aa) {
+  return d ? (aa ? HexVolLaunch<P, true, true>::EB : HexVolLaunch<P, true, false>::EB)
+           : (aa ? HexVolLaunch<P, false, true>::EB : HexVolLaunch<P, false, false>::EB);
+}
+
+int hex_block_elems(int p, int prec, int k, bool aa, bool saa) {
   if (k == K_DISU) return HEX_DISU_EB;
   const bool d = prec == 0;
   if (k == K_SURFACE) {
@@ -1173,10 +1239,10 @@ int hex_block_elems(int p, int prec, int k, bool saa) {
     return 0;
   }
   switch (p) {
-    case 1: return d ? HexLaunch<1, true>::EB : HexLaunch<1, false>::EB;
-    case 2: return d ? HexLaunch<2, true>::EB : HexLaunch<2, false>::EB;
-    case 3: return d ? HexLaunch<3, true>::EB : HexLaunch<3, false>::EB;
-    case 4: return d ? HexLaunch<4, true>::EB : HexLaunch<4, false>::EB;
+    case 1: return hex_vol_elems<1>(d, aa);
+    case 2: return hex_vol_elems<2>(d, aa);
+    case 3: return hex_vol_elems<3>(d, aa);
+    case 4: return hex_vol_elems<4>(d, aa);
   }
   return 0;
 }

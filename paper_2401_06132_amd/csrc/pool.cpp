@@ -476,7 +476,7 @@ fr_status rebuild_tables(fr_pool* P) {
       V.segs.push_back(R.seg[t]);
       for (int k = 0; k < 3; ++k) {
         const bool saa = P->ph.surface_aa != 0;
-        const int eb = t == 0 ? fr::hex_block_elems(R.q.p, P->ph.prec, k, saa)
+        const int eb = t == 0 ? fr::hex_block_elems(R.q.p, P->ph.prec, k, P->ph.flux_aa != 0, saa)
                               : fr::prism_block_elems(R.q.p, P->ph.prec, k, saa);
         for (int32_t e0 = 0; e0 < R.seg[t].E; e0 += eb) V.bt[k].push_back({si, e0});
       }

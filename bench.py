@@ -33,7 +33,7 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from
 # a 1 GiB copy), profiles/hex_fused_fp32_p3_tgv48.md.  Valid for the kernel as
 # profiled; None once the kernel changes.
-HEX_VOL_P3_FP32_TRAFFIC = (272346.0 * 2 + 304128.0) * 1024
+HEX_VOL_P3_FP32_TRAFFIC = (270601.6 * 2 + 304128.0) * 1024
 
 
 def volume_model(p, bytes_real):

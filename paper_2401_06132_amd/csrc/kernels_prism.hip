@@ -182,8 +182,15 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
 
 // --------------------------------------------------------------- volume
 // LDS per element: region A = state + gradients at the solution points;
-// region B = neighbour face states / jumps, then the triangle-interpolated
-// fields T1, then the line-projected flux Z (after a barrier).  The triangle
+// region B = neighbour face states / jumps and face fields.  The
+// triangle-interpolated fields T1 are written from offset 0 over both once
+// every thread holds its plane values in registers (the state and gradients
+// are dead after the plane sweep), then the line-projected flux Z (after a
+// barrier).  The footprint is the largest of A + B, T1 and Z (p = 3: 1780
+// values instead of 2160).  Measured at 48^3 (volume group): FP32 p = 4
+// 4.92 -> 4.62 ms (7 one-wave workgroups per CU instead of 6), FP64 p = 3
+// 4.36 -> 3.43 ms (4 instead of 3); FP32 p = 3 is bound by registers and
+// unchanged.  FP64 at p = 4 keeps T1 and Z after region A.  The triangle
 // operator tables are staged in LDS once per workgroup so that every
 // triangle-plane product can run one output point per thread.
 template <int P>
@@ -202,6 +209,12 @@ struct PrismVol {
   static constexpr int SZ_B1 = SZ_B0 > SZ_J ? SZ_B0 : SZ_J;
   static constexpr int SZ_B = SZ_B1 > SZ_EF ? SZ_B1 : SZ_EF;
   static constexpr int PER_ELEM = SZ_A + SZ_B;
+  // with T1 and Z over region A (TOX): the largest of A + (J, EF, S), T1, Z
+  static constexpr int per_elem_tox(bool SAA) {
+    const int b0 = SAA && SZ_S > SZ_JE ? SZ_S : SZ_JE;
+    const int t = SZ_T1 > SZ_Z ? SZ_T1 : SZ_Z;
+    return SZ_A + b0 > t ? SZ_A + b0 : t;
+  }
   // surface-flux anti-aliasing, one round per face kind: the 20 fields at
   // the two triangles' nodes [2][20][NTN] or along one quadrilateral's first
   // axis at GL(m) [20][m][n] (offset 0); the viscous flux at the face
@@ -246,7 +259,11 @@ __global__ void __launch_bounds__(NT_)
   // thread with broadcast operator reads (enough planes fill the workgroup);
   // otherwise one output point per thread
   constexpr bool PL = sizeof(R) == 4 && P <= 3;
-  constexpr int PE = AA ? C::PER_ELEM : C::SZ_A + (PL ? C::SZ_JE : C::SZ_J);
+  // with flux AA, T1 and Z start at offset 0 over the state and gradients,
+  // which are dead after the plane sweep (FP64 at p = 4 keeps them after
+  // region A: the plane values held in registers across the barrier spill)
+  constexpr bool TOX = !(P >= 4 && sizeof(R) == 8);
+  constexpr int PE = AA ? (TOX ? C::per_elem_tox(SAA) : C::PER_ELEM) : C::SZ_A + (PL ? C::SZ_JE : C::SZ_J);
   static_assert(2 * EB * NTQ <= NT_, "two threads per quadrature column");
   using TriL = typename std::conditional<WARP, PrismTri<P, R>, PrismTriOps<P, R>>::type;
   __shared__ TriL tri;
@@ -265,8 +282,8 @@ __global__ void __launch_bounds__(NT_)
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                 */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
-#define TS(le) (smem + (le)*PE + C::SZ_A)  /* [20][n][TQS]             */
-#define ZS(le) (smem + (le)*PE + C::SZ_A)  /* [3][5][ZVS: NTQ][n]      */
+#define TS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [20][n][TQS]  */
+#define ZS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [3][5][ZVS][n] */
 #define SS(le) (smem + (le)*PE + C::SZ_A)  /* face quadrature staging   */
 
   // phase 0: operator tables, state (reference form), metrics, neighbour states
@@ -920,13 +937,8 @@ __global__ void __launch_bounds__(NT_)
   // (at high order SPL threads share a plane, taking alternate outputs, so
   // that more lanes are busy)
   constexpr int SPL = P >= 4 ? 2 : 1;
-  for (int it = tid; it < EB * 20 * n * SPL; it += NT_) {
+  auto plane_sweep = [&](const int it, const R* xv) {
     const int le = it / (20 * n * SPL), r0 = it - le * (20 * n * SPL), fk = r0 / SPL, h = r0 - fk * SPL;
-    const int fld = fk / n, k = fk - fld * n;
-    const R* x = XS(le) + fld * NU + NTN * k;
-    R xv[NTN];
-#pragma unroll
-    for (int t = 0; t < NTN; ++t) xv[t] = x[t];
     R* T = TS(le) + fk * C::TQS;  // [fld][k][tq]
 #pragma unroll
     for (int j = 0; j < (NTQ + SPL - 1) / SPL; ++j) {
@@ -936,6 +948,46 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
         for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * xv[t];
         T[tq] = s;
+      }
+    }
+  };
+  auto plane_rows = [&](const int it, R* xv) {
+    const int le = it / (20 * n * SPL), r0 = it - le * (20 * n * SPL), fk = r0 / SPL;
+    const int fld = fk / n, k = fk - fld * n;
+    const R* x = XS(le) + fld * NU + NTN * k;
+#pragma unroll
+    for (int t = 0; t < NTN; ++t) xv[t] = x[t];
+  };
+  if constexpr (TOX) {
+    // T1 overwrites the state and gradients: every thread reads its plane
+    // values into registers before a barrier and writes T1 after it
+    constexpr int NIT = (EB * 20 * n * SPL + NT_ - 1) / NT_;
+    R xv[NIT][NTN];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k)
+      if (tid + k * NT_ < EB * 20 * n * SPL) plane_rows(tid + k * NT_, xv[k]);
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NIT; ++k)
+      if (tid + k * NT_ < EB * 20 * n * SPL) plane_sweep(tid + k * NT_, xv[k]);
+  } else {
+    for (int it = tid; it < EB * 20 * n * SPL; it += NT_) {
+      const int le = it / (20 * n * SPL), r0 = it - le * (20 * n * SPL), fk = r0 / SPL, h = r0 - fk * SPL;
+      const int fld = fk / n, k = fk - fld * n;
+      const R* x = XS(le) + fld * NU + NTN * k;
+      R xv[NTN];
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) xv[t] = x[t];
+      R* T = TS(le) + fk * C::TQS;  // [fld][k][tq]
+#pragma unroll
+      for (int j = 0; j < (NTQ + SPL - 1) / SPL; ++j) {
+        const int tq = SPL * j + h;
+        if (tq < NTQ) {
+          R s = R(0);
+#pragma unroll
+          for (int t = 0; t < NTN; ++t) s += tri.Tq[tq][t] * xv[t];
+          T[tq] = s;
+        }
       }
     }
   }

@@ -80,7 +80,7 @@ def time_variant(frmi, torch, n, p, prec, steps, warmup, form="fused", kind="hex
         # the fused path without flux anti-aliasing (the paper's "AA off"), or
         # with flux and surface-flux anti-aliasing (its "full AA")
         aa, surface_aa, form = form == "fullaa", form == "fullaa", "fused"
-    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, form=form, aa=aa, surface_aa=surface_aa)
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0, form=form, aa=aa, surface_aa=surface_aa)
     coords = s.upts_coords()
     U = inputs.element_state(coords, seed=0)
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
@@ -124,7 +124,7 @@ def run_rk(frmi, torch, kind, n, p, prec, nsteps, dt):
     """nsteps RK4 steps on the internal state; per-step HIP-event times and
     the drift of the conserved integrals."""
     from paper_2401_06132_amd import inputs
-    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0)
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
     U = inputs.element_state(s.upts_coords(), seed=0)
     s.set_state(np.concatenate([x.reshape(-1) for x in U]))
     del U
@@ -175,7 +175,7 @@ def run_serving(frmi, torch, budget_gib=64.0, max_active=64, nreq=512, seed=0, c
     from paper_2401_06132_amd import inputs
     reqs = inputs.serving_requests(n=nreq, seed=seed)
     budget = int(budget_gib * (1 << 30))
-    pool = frmi.Pool(budget, max_active=max_active, prec="fp32", pref=inputs.P0)
+    pool = frmi.Pool(budget, max_active=max_active, prec="fp32", pref=inputs.P0, rho_ref=inputs.RHO0)
     outs, t_arr, t_adm, t_fin, dof_req = {}, {}, {}, {}, {}
     step_ms, step_dof, active, launches = [], [], [], []
     peak_bytes, nxt, done, work = 0, 0, 0, 0

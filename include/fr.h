@@ -84,10 +84,29 @@ typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
  *                        momentum flux is dropped (it has zero discrete
  *                        divergence); mathematically identical, it removes
  *                        the low-Mach cancellation.  0 = textbook form.
+ *   rho_ref            : constant reference density (0 = none).  The
+ *                        density is operated on as rho - rho_ref.  With
+ *                        rho_ref > 0 the fused kernels on affine elements
+ *                        also split the energy flux exactly as
+ *                        v (E + p) = v (E' + p' - kap (rho - rho_ref))
+ *                                    + kap rho v,
+ *                        kap = gamma pref / ((gamma - 1) rho_ref): the first
+ *                        part is O(1) at low Mach, the second is linear in
+ *                        the state and its DG divergence is formed in double
+ *                        precision (the same operator gives the mass-flux
+ *                        divergence).  Mathematically identical; with
+ *                        FR_PREC_FP32 it keeps single-precision rounding off
+ *                        the O(gamma pref/(gamma-1)) energy flux.  Curved
+ *                        elements use the shift only.
  *   prec               : FR_PREC_FP64: every step in double precision.
- *                        FR_PREC_FP32: state, reference subtraction, final
- *                        RHS and RK accumulation in double; interpolation,
- *                        fluxes, projections and interface exchange in float.
+ *                        FR_PREC_FP32: state, reference subtraction, the
+ *                        solution at the flux points, the mass-flux
+ *                        divergence L(rho v), final RHS and RK accumulation
+ *                        in double; the corrected gradients, anti-aliased
+ *                        fluxes, projections and interface fluxes in float,
+ *                        with face states exchanged as a float base per
+ *                        face plus float deviations (so that face jumps
+ *                        keep their digits).
  *   form               : FR_FORM_FUSED: three fused kernels per element type
  *                        (disu | volume group | interface group).
  *                        FR_FORM_PLAIN: the paper's unfused kernel sequence
@@ -111,6 +130,7 @@ typedef enum { FR_FORM_FUSED = 0, FR_FORM_PLAIN = 1 } fr_form;
  *                        0 (default): interface fluxes at the flux points. */
 typedef struct {
   double gamma, prandtl, mu, ldg_beta, ldg_tau, pref;
+  double rho_ref;  /* reference density, 0 = none */
   int prec;        /* fr_precision */
   int form;        /* fr_form */
   int flux_aa;     /* 1 (default) or 0 */
@@ -118,8 +138,8 @@ typedef struct {
 } fr_physics;
 
 /* Fill *ph with the Taylor-Green defaults: gamma 1.4, Pr 0.71, mu 1/1600,
- * beta 0.5, tau 0.1, pref 0, FP64, fused, flux anti-aliasing on, surface-flux
- * anti-aliasing off. */
+ * beta 0.5, tau 0.1, pref 0, rho_ref 0, FP64, fused, flux anti-aliasing on,
+ * surface-flux anti-aliasing off. */
 void fr_physics_default(fr_physics* ph);
 
 /* Create a context.  hip_stream: a hipStream_t or NULL (null stream).  No

@@ -35,7 +35,7 @@ SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_ty
 class FrPhysics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
                 ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("pref", ctypes.c_double),
-                ("prec", ctypes.c_int), ("form", ctypes.c_int), ("flux_aa", ctypes.c_int),
+                ("rho_ref", ctypes.c_double), ("prec", ctypes.c_int), ("form", ctypes.c_int), ("flux_aa", ctypes.c_int),
                 ("surface_aa", ctypes.c_int)]
 
 
@@ -103,11 +103,12 @@ def load_library(path=None):
     return lib
 
 
-def physics(gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0, prec="fp64", form="fused",
-            aa=True, surface_aa=False):
-    """aa: flux anti-aliasing; surface_aa: surface-flux anti-aliasing as well
-    (the paper's "full AA" with aa=True)."""
-    return FrPhysics(gamma, prandtl, mu, beta, tau, pref, PREC[prec], FORM[form], 1 if aa else 0,
+def physics(gamma=1.4, prandtl=0.71, mu=1.0 / 1600.0, beta=0.5, tau=0.1, pref=0.0, rho_ref=0.0, prec="fp64",
+            form="fused", aa=True, surface_aa=False):
+    """pref, rho_ref: reference pressure and density of the reference-state
+    form; aa: flux anti-aliasing; surface_aa: surface-flux anti-aliasing as
+    well (the paper's "full AA" with aa=True)."""
+    return FrPhysics(gamma, prandtl, mu, beta, tau, pref, rho_ref, PREC[prec], FORM[form], 1 if aa else 0,
                      1 if surface_aa else 0)
 
 

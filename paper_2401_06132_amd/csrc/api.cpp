@@ -31,12 +31,14 @@ struct fr_ctx {
   double* d_state = nullptr;  // internal state
   double* d_rk = nullptr;     // RK buffers: stage state, accumulator (+ stage derivative, plain form)
   void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
+  float* d_Ub = nullptr;  // single precision: face bases [slot][5]
   fr::FaceRec* d_faces = nullptr;
   uint8_t* d_perms = nullptr;
   void* d_met[fr::NTYPES] = {};
   double* d_detj[fr::NTYPES] = {};
   void* d_pops = nullptr;  // prism triangle tables
   void* d_dops[fr::NTYPES] = {};  // dense operator tables (tetrahedra, pyramids)
+  float* d_fbar[fr::NTYPES] = {};  // single precision, dense types: constant transformed flux [E][12]
   void* d_verts[2] = {nullptr, nullptr};  // curved meshes: element vertices [E][nv][3]
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
 };
@@ -78,15 +80,10 @@ fr_status setup_plain(fr_ctx* c) {
   if (!fr::plain_create_handle(&P->blas)) return fail(c, FR_EDEVICE, "rocblas_create_handle failed");
   P->beta = c->ph.ldg_beta;
   P->eref = c->ph.pref / (c->ph.gamma - 1.0);
-  P->gas.gamma = c->ph.gamma;
-  P->gas.gm1 = c->ph.gamma - 1.0;
-  P->gas.mu = c->ph.mu;
-  P->gas.muh = c->ph.mu * c->ph.gamma / c->ph.prandtl;
-  P->gas.pref = c->ph.pref;
-  P->gas.eref = P->eref;
-  P->gas.href = c->ph.gamma * c->ph.pref / (c->ph.gamma - 1.0);
-  P->gas.beta = c->ph.ldg_beta;
-  P->gas.tau = c->ph.ldg_tau;
+  // the plain path takes the same reference state and energy-flux split as
+  // the fused kernels (its mass flux stays in the dense products)
+  P->rho0 = c->gas.rho_ref;
+  P->gas = fr::make_gas<double>(c->gas, true);
   int64_t nftot = 0, nqmax = 0;
   for (int t = 0; t < fr::NTYPES; ++t) {
     P->ty.E[t] = M.nel[t];
@@ -102,8 +99,8 @@ fr_status setup_plain(fr_ctx* c) {
     struct {
       double** d;
       const std::vector<double>* h;
-    } up[] = {{&P->dM0[t], &o.M0}, {&P->dG1[t], &o.G1}, {&P->dM6[t], &o.M6},
-              {&P->dM7[t], &o.M7}, {&P->dK[t], &o.K},   {&P->dM3[t], &o.M3}};
+    } up[] = {{&P->dM0[t], &o.M0}, {&P->dG1[t], &o.G1}, {&P->dM6[t], &o.M6}, {&P->dM7[t], &o.M7},
+              {&P->dK[t], &o.K},   {&P->dM3[t], &o.M3},  {&P->dLV[t], &o.LV}};
     for (auto& x : up) {
       HIPCHK(hipMalloc(x.d, sizeof(double) * x.h->size()));
       HIPCHK(hipMemcpy(*x.d, x.h->data(), sizeof(double) * x.h->size(), hipMemcpyHostToDevice));
@@ -166,7 +163,7 @@ void free_plain(fr_ctx* c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int t = 0; t < fr::NTYPES; ++t) {
-    void* tb[] = {P->dM0[t], P->dG1[t], P->dM6[t], P->dM7[t], P->dK[t], P->dM3[t], P->jinv[t], P->detj[t]};
+    void* tb[] = {P->dM0[t], P->dG1[t], P->dM6[t], P->dM7[t], P->dK[t], P->dM3[t], P->dLV[t], P->jinv[t], P->detj[t]};
     for (void* b : tb)
       if (b) (void)hipFree(b);
   }
@@ -197,6 +194,7 @@ fr_status ensure_device(fr_ctx* c) {
   HIPCHK(hipMalloc(&c->d_Uf, rs * S * 5 * nfp));
   HIPCHK(hipMalloc(&c->d_Vf, rs * S * 4 * nfp));
   HIPCHK(hipMalloc(&c->d_Rp, rs * c->n_state));
+  if (rs == 4) HIPCHK(hipMalloc(&c->d_Ub, sizeof(float) * S * 5));
   // faces
   std::vector<fr::FaceRec> fr(S);
   std::vector<double> geo(4 * S);
@@ -253,6 +251,7 @@ fr_status ensure_device(fr_ctx* c) {
     fr::dense_ops_pack(c->ref[t], c->ph.prec, pb.data());
     HIPCHK(hipMalloc(&c->d_dops[t], nb));
     HIPCHK(hipMemcpy(c->d_dops[t], pb.data(), nb, hipMemcpyHostToDevice));
+    if (rs == 4) HIPCHK(hipMalloc(&c->d_fbar[t], sizeof(float) * 12 * M.nel[t]));
   }
   c->dev_ok = true;
   return FR_OK;
@@ -268,6 +267,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.ust = c->d_rk + o;
   s.acc = c->d_rk + c->n_state + o;
   s.Uf = c->d_Uf;
+  s.Ub = c->d_Ub;
   s.Vf = c->d_Vf;
   s.Rp = (char*)c->d_Rp + rsize(c) * o;
   s.faces = c->d_faces;
@@ -279,6 +279,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.slot_base = (int32_t)c->M.slot_base[t];
   s.nperm = (int32_t)c->M.perms.size();
   s.verts = t < 2 ? c->d_verts[t] : nullptr;
+  s.fbar = c->d_fbar[t];
   return s;
 }
 
@@ -333,6 +334,7 @@ void fr_physics_default(fr_physics* ph) {
   ph->ldg_beta = 0.5;
   ph->ldg_tau = 0.1;
   ph->pref = 0.0;
+  ph->rho_ref = 0.0;
   ph->prec = FR_PREC_FP64;
   ph->form = FR_FORM_FUSED;
   ph->flux_aa = 1;
@@ -343,7 +345,8 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
   if (!ph || !out) return FR_EINVAL;
   *out = nullptr;
   if (!(ph->gamma > 1.0) || !(ph->prandtl > 0.0) || !(ph->mu >= 0.0) || !(ph->ldg_tau >= 0.0) ||
-      !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
+      !std::isfinite(ph->ldg_beta) || !std::isfinite(ph->pref) || !(ph->rho_ref >= 0.0) ||
+      !std::isfinite(ph->rho_ref) || ph->prec < 0 || ph->prec > 1 || ph->form < 0 ||
       ph->form > 1 || ph->flux_aa < 0 || ph->flux_aa > 1 || ph->surface_aa < 0 || ph->surface_aa > 1)
     return FR_EINVAL;
   if (ph->form == FR_FORM_PLAIN && ph->prec != FR_PREC_FP64) return FR_EUNSUPPORTED;
@@ -353,7 +356,7 @@ fr_status fr_create(const fr_physics* ph, void* stream, fr_ctx** out) {
   if (!c) return FR_ENOMEM;
   c->ph = *ph;
   c->st = (hipStream_t)stream;
-  c->gas = {ph->gamma, ph->prandtl, ph->mu, ph->pref, ph->ldg_beta, ph->ldg_tau};
+  c->gas = {ph->gamma, ph->prandtl, ph->mu, ph->pref, ph->ldg_beta, ph->ldg_tau, ph->rho_ref};
   *out = c;
   return FR_OK;
 }
@@ -648,12 +651,12 @@ void fr_destroy(fr_ctx* c) {
   if (!c) return;
   if (c->dev_ok || c->d_state) {
     (void)hipStreamSynchronize(c->st);
-    void* bufs[] = {c->d_state, c->d_rk,    c->d_Uf,       c->d_Vf,      c->d_Rp, c->d_fgeo,
-                    c->d_faces, c->d_perms, c->d_pops, c->d_verts[0], c->d_verts[1]};
+    void* bufs[] = {c->d_state, c->d_rk,    c->d_Uf,   c->d_Vf,       c->d_Rp,       c->d_fgeo,
+                    c->d_faces, c->d_perms, c->d_pops, c->d_verts[0], c->d_verts[1], c->d_Ub};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     for (int t = 0; t < fr::NTYPES; ++t) {
-      void* tb[] = {c->d_met[t], c->d_detj[t], c->d_dops[t]};
+      void* tb[] = {c->d_met[t], c->d_detj[t], c->d_dops[t], c->d_fbar[t]};
       for (void* b : tb)
         if (b) (void)hipFree(b);
     }

@@ -1,9 +1,19 @@
 // Device-side physics shared by the fused and plain kernels: point-wise
 // inviscid and viscous fluxes (eqs. fluxe, fluxv), the LDG common solution
 // (eq. FR-conu) and the common normal interface flux (eq. FR-comm_flux,
-// Rusanov + LDG), in the reference-state form: the energy slot holds
-// E' = E - pref/(gamma-1), the momentum flux carries p' = p - pref and the
-// energy flux v (E' + p' + gamma pref/(gamma-1)) = v (E + p).
+// Rusanov + LDG), in the reference-state form: the density slot holds
+// rho' = rho - rho0, the energy slot E' = E - pref/(gamma-1), the momentum
+// flux carries p' = p - pref and the energy flux v (E + p).
+//
+// Energy-flux split (fused kernels, rho0 > 0 on affine meshes).  With
+// kap = gamma pref / ((gamma - 1) rho0) the energy flux is written exactly as
+//   v (E + p) = v (E' + p' - kap rho') + kap (rho v),
+// so the part evaluated point-wise is O(1) instead of O(gamma pref/(gamma-1))
+// (~250 at Mach 0.1).  The remainder kap (rho v) is linear in the state: its
+// DG divergence kap L(rho v) is formed in double precision from the state
+// itself (the disu kernels), L being the central DG divergence of the mass
+// flux.  The mass equation then needs no point-wise flux at all: its
+// residual is L(rho v) plus the lifted dissipation of the common flux.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +27,9 @@ struct Gas {
   R gamma, gm1, mu, muh;  // muh = mu gamma / Pr  (c_p grad T = gamma grad e)
   R pref, eref, href;     // reference pressure, pref/(gamma-1), gamma pref/(gamma-1)
   R beta, tau;            // LDG parameters
+  R rho0;                 // reference density (rho = u[0] + rho0)
+  R kap, hc0;             // split energy flux: H = E' + p' + hc0 - kap rho'
+                          // (kap = href/rho0, hc0 = 0; unsplit: kap = 0, hc0 = href)
 };
 
 template <typename R>
@@ -43,13 +56,14 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Physical flux f = f^e - f^v at one point.  u: 5 conserved (reference
 // form), q[d][v]: physical gradients d/dx_d of the conserved variables.
-// f[d][v]: component d of the flux of variable v.
+// f[d][v]: component d of the flux of variable v; the energy component is
+// the split form (v H with H = E' + p' + hc0 - kap rho').
 template <typename R>
 __device__ __forceinline__ void point_flux(const R u[5], const R q[3][5], const Gas<R>& g, R f[3][5]) {
-  const R rho = u[0], ir = rcp(rho);
+  const R rho = u[0] + g.rho0, ir = rcp(rho);
   const R v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
   const R pp = g.gm1 * (u[4] - R(0.5) * (u[1] * v[0] + u[2] * v[1] + u[3] * v[2]));
-  const R H = u[4] + pp + g.href;
+  const R H = u[4] + pp + g.hc0 - g.kap * u[0];
   // velocity gradient gv[d][i] = d v_i / d x_d
   R gv[3][3];
 #pragma unroll
@@ -81,7 +95,7 @@ __device__ __forceinline__ void point_flux(const R u[5], const R q[3][5], const 
 template <typename R>
 __device__ __forceinline__ void normal_viscous(const R u[5], const R q[3][5], const R n[3], const Gas<R>& g,
                                                R V[4]) {
-  const R rho = u[0], ir = rcp(rho);
+  const R rho = u[0] + g.rho0, ir = rcp(rho);
   const R v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
   R gv[3][3];
 #pragma unroll
@@ -108,38 +122,34 @@ __device__ __forceinline__ void normal_viscous(const R u[5], const R q[3][5], co
   V[3] = v[0] * tn[0] + v[1] * tn[1] + v[2] * tn[2] + hn;
 }
 
+// Normal inviscid flux f^e . n and the wave-speed bound |v.n| + c at one
+// point (reference-state form; the energy component in the split form).
+template <typename R>
+__device__ __forceinline__ void euler_normal(const R u[5], const R n[3], const Gas<R>& g, R f[5], R& s) {
+  const R ir = rcp(u[0] + g.rho0);
+  const R mn = u[1] * n[0] + u[2] * n[1] + u[3] * n[2];
+  const R vn = mn * ir;
+  const R pp = g.gm1 * (u[4] - R(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir);
+  f[0] = mn;
+  f[1] = u[1] * vn + pp * n[0];
+  f[2] = u[2] * vn + pp * n[1];
+  f[3] = u[3] * vn + pp * n[2];
+  f[4] = vn * (u[4] + pp + g.hc0 - g.kap * u[0]);
+  s = fabs(vn) + sqrt(g.gamma * (pp + g.pref) * ir);
+}
+
 // Common normal flux w.r.t. the unit normal n of the L side (per unit area):
 //   F = 1/2 (f^e_L + f^e_R).n + 1/2 s (uL - uR)          (Rusanov)
 //       - [(1/2 + beta) VL - (1/2 - beta) VR]            (LDG, VR = n_R . f^v_R)
 //       + tau (uL - uR)                                   (penalty)
-// with s = max(|vL.n| + cL, |vR.n| + cR).  Both sides of a pair evaluate the
-// same expression on the same inputs, so the two results are bitwise equal.
+// with s = max(|vL.n| + cL, |vR.n| + cR).  Used by the unsplit plain path
+// (kap = 0).
 template <typename R>
 __device__ __forceinline__ void common_flux(const R uL[5], const R uR[5], const R VL[4], const R VR[4],
                                             const R n[3], const Gas<R>& g, R F[5]) {
   R fl[5], fr[5], sl, sr;
-  {
-    const R ir = rcp(uL[0]);
-    const R vn = (uL[1] * n[0] + uL[2] * n[1] + uL[3] * n[2]) * ir;
-    const R pp = g.gm1 * (uL[4] - R(0.5) * (uL[1] * uL[1] + uL[2] * uL[2] + uL[3] * uL[3]) * ir);
-    fl[0] = uL[0] * vn;
-    fl[1] = uL[1] * vn + pp * n[0];
-    fl[2] = uL[2] * vn + pp * n[1];
-    fl[3] = uL[3] * vn + pp * n[2];
-    fl[4] = vn * (uL[4] + pp + g.href);
-    sl = fabs(vn) + sqrt(g.gamma * (pp + g.pref) * ir);
-  }
-  {
-    const R ir = rcp(uR[0]);
-    const R vn = (uR[1] * n[0] + uR[2] * n[1] + uR[3] * n[2]) * ir;
-    const R pp = g.gm1 * (uR[4] - R(0.5) * (uR[1] * uR[1] + uR[2] * uR[2] + uR[3] * uR[3]) * ir);
-    fr[0] = uR[0] * vn;
-    fr[1] = uR[1] * vn + pp * n[0];
-    fr[2] = uR[2] * vn + pp * n[1];
-    fr[3] = uR[3] * vn + pp * n[2];
-    fr[4] = vn * (uR[4] + pp + g.href);
-    sr = fabs(vn) + sqrt(g.gamma * (pp + g.pref) * ir);
-  }
+  euler_normal(uL, n, g, fl, sl);
+  euler_normal(uR, n, g, fr, sr);
   const R s = sl > sr ? sl : sr;
   const R a = R(0.5) * s + g.tau;
   const R bl = R(0.5) + g.beta, br = R(0.5) - g.beta;
@@ -149,41 +159,84 @@ __device__ __forceinline__ void common_flux(const R uL[5], const R uR[5], const 
     F[1 + k] = R(0.5) * (fl[1 + k] + fr[1 + k]) + a * (uL[1 + k] - uR[1 + k]) - (bl * VL[k] - br * VR[k]);
 }
 
-// The two parts of common_flux, for surface-flux anti-aliasing, where the
-// nonlinear Rusanov part is evaluated at the face quadrature points and the
-// part that is linear in the two sides' values at the flux points:
-//   rusanov_flux : 1/2 (f^e_L + f^e_R).n + 1/2 s (uL - uR)
-//   linear_flux  : tau (uL - uR) - [(1/2 + beta) VL - (1/2 - beta) VR]
-template <typename R>
-__device__ __forceinline__ void euler_normal(const R u[5], const R n[3], const Gas<R>& g, R f[5], R& s) {
-  const R ir = rcp(u[0]);
-  const R vn = (u[1] * n[0] + u[2] * n[1] + u[3] * n[2]) * ir;
-  const R pp = g.gm1 * (u[4] - R(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir);
-  f[0] = u[0] * vn;
-  f[1] = u[1] * vn + pp * n[0];
-  f[2] = u[2] * vn + pp * n[1];
-  f[3] = u[3] * vn + pp * n[2];
-  f[4] = vn * (u[4] + pp + g.href);
-  s = fabs(vn) + sqrt(g.gamma * (pp + g.pref) * ir);
+// The fused kernels' interface flux at one own flux point, for the own side:
+// D such that mag * D is the own element's transformed common normal flux
+// (eq. FR-comm_flux; mag = own area factor).
+//   uo, un : own and neighbour states; j = un - uo, formed from the stored
+//            face base and deviations, so it keeps the digits that uo and un
+//            lose to their O(1) magnitude;
+//   nL     : the L side's unit normal; left: this side is L.
+// Momentum and energy: sg F with sg = +-1 and F as in common_flux (with
+// uL - uR taken from j), so the two sides' values are bitwise opposite.
+// LIN: the central part of the mass flux and the linear part kap (rho v) of
+// the energy flux are handed to the double-precision L(rho v) of the volume
+// term; here remains only their strong-form interface term
+// 1/2 (m_nbr - m_own) . n_own (the own-trace part is inside L), and the mass
+// flux keeps its dissipation.
+template <typename R, bool LIN>
+__device__ __forceinline__ void face_flux(const R uo[5], const R un[5], const R j[5], const R Vo[4], const R Vn[4],
+                                          const R nL[3], bool left, const Gas<R>& g, R D[5]) {
+  R fo[5], fn[5], so, sn;
+  euler_normal(uo, nL, g, fo, so);
+  euler_normal(un, nL, g, fn, sn);
+  const R a = R(0.5) * (so > sn ? so : sn) + g.tau;
+  const R sg = left ? R(1) : R(-1);
+  const R bo = left ? R(0.5) + g.beta : R(0.5) - g.beta;  // weight of the own viscous flux
+  const R bn = left ? R(0.5) - g.beta : R(0.5) + g.beta;
+#pragma unroll
+  for (int k = 1; k < 5; ++k) {
+    // uL - uR = -sg j; the L side's viscous flux enters with (1/2 + beta)
+    const R jl = left ? -j[k] : j[k];
+    const R vv = left ? bo * Vo[k - 1] - bn * Vn[k - 1] : bn * Vn[k - 1] - bo * Vo[k - 1];
+    D[k] = sg * (R(0.5) * (left ? fo[k] + fn[k] : fn[k] + fo[k]) + a * jl - vv);
+  }
+  if constexpr (LIN) {
+    const R jn = R(0.5) * sg * (j[1] * nL[0] + j[2] * nL[1] + j[3] * nL[2]);
+    D[0] = jn - a * j[0];
+    D[4] += g.kap * jn;
+  } else {
+    const R jl = left ? -j[0] : j[0];
+    D[0] = sg * (R(0.5) * (left ? fo[0] + fn[0] : fn[0] + fo[0]) + a * jl);
+  }
 }
 
-template <typename R>
-__device__ __forceinline__ void rusanov_flux(const R uL[5], const R uR[5], const R n[3], const Gas<R>& g, R F[5]) {
-  R fl[5], fr[5], sl, sr;
+// Surface-flux anti-aliasing splits face_flux in two: the part linear in
+// the two sides' values (penalty, LDG viscous flux, and with LIN the
+// interface terms of L(rho v)), evaluated at the flux points, and the
+// Rusanov part, evaluated at the face quadrature points from the L state
+// and the jump jl = uL - uR interpolated there.
+template <typename R, bool LIN>
+__device__ __forceinline__ void face_flux_linear(const R j[5], const R Vo[4], const R Vn[4], const R nL[3],
+                                                 bool left, const Gas<R>& g, R D[5]) {
+  const R sg = left ? R(1) : R(-1);
+  const R bo = left ? R(0.5) + g.beta : R(0.5) - g.beta;
+  const R bn = left ? R(0.5) - g.beta : R(0.5) + g.beta;
+#pragma unroll
+  for (int k = 1; k < 5; ++k) {
+    const R jl = left ? -j[k] : j[k];
+    const R vv = left ? bo * Vo[k - 1] - bn * Vn[k - 1] : bn * Vn[k - 1] - bo * Vo[k - 1];
+    D[k] = sg * (g.tau * jl - vv);
+  }
+  D[0] = -g.tau * j[0];
+  if constexpr (LIN) {
+    const R jn = R(0.5) * sg * (j[1] * nL[0] + j[2] * nL[1] + j[3] * nL[2]);
+    D[0] += jn;
+    D[4] += g.kap * jn;
+  }
+}
+
+// Rusanov flux w.r.t. nL from the L state and jl = uL - uR: the mass
+// component is the dissipation only when LIN (its central part is in L).
+template <typename R, bool LIN>
+__device__ __forceinline__ void rusanov_jump(const R uL[5], const R jl[5], const R n[3], const Gas<R>& g, R F[5]) {
+  R uR[5], fl[5], fr[5], sl, sr;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) uR[v] = uL[v] - jl[v];
   euler_normal(uL, n, g, fl, sl);
   euler_normal(uR, n, g, fr, sr);
   const R a = R(0.5) * (sl > sr ? sl : sr);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) F[v] = R(0.5) * (fl[v] + fr[v]) + a * (uL[v] - uR[v]);
-}
-
-template <typename R>
-__device__ __forceinline__ void linear_flux(const R uL[5], const R uR[5], const R VL[4], const R VR[4],
-                                            const Gas<R>& g, R F[5]) {
-  const R bl = R(0.5) + g.beta, br = R(0.5) - g.beta;
-  F[0] = g.tau * (uL[0] - uR[0]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) F[1 + k] = g.tau * (uL[1 + k] - uR[1 + k]) - (bl * VL[k] - br * VR[k]);
+  for (int v = 0; v < 5; ++v) F[v] = (LIN && v == 0 ? R(0) : R(0.5) * (fl[v] + fr[v])) + a * jl[v];
 }
 
 // Per-slot face record shared by the fused kernels.

@@ -21,7 +21,31 @@ struct HostOps {
 
 struct GasHost {
   double gamma, prandtl, mu, pref, beta, tau;
+  double rho_ref = 0.0;  // reference density (0: none)
 };
+
+// Device constants of the physics.  lin: the element type takes the mass
+// flux and the linear energy-flux part from the double-precision L(rho v)
+// (affine elements); the energy split needs a reference density.
+template <typename R>
+inline Gas<R> make_gas(const GasHost& g, bool lin) {
+  Gas<R> o;
+  o.gamma = R(g.gamma);
+  o.gm1 = R(g.gamma - 1.0);
+  o.mu = R(g.mu);
+  o.muh = R(g.mu * g.gamma / g.prandtl);
+  o.pref = R(g.pref);
+  o.eref = R(g.pref / (g.gamma - 1.0));
+  const double href = g.gamma * g.pref / (g.gamma - 1.0);
+  o.href = R(href);
+  o.beta = R(g.beta);
+  o.tau = R(g.tau);
+  o.rho0 = R(g.rho_ref);
+  const bool split = lin && g.rho_ref > 0.0;
+  o.kap = split ? R(href / g.rho_ref) : R(0);
+  o.hc0 = split ? R(0) : R(href);
+  return o;
+}
 
 // One segment: the elements of one type of one mesh, with every per-mesh
 // array the kernels touch.  A launch covers either a single segment (passed
@@ -32,7 +56,12 @@ struct Seg {
   double* ust = nullptr;  // RK stage state (input of stages 2-4)
   double* acc = nullptr;  // RK accumulator
   double* du = nullptr;   // right-hand side output (plain evaluation)
-  void* Uf = nullptr;     // face states [slot][5][n^2] (precision R), per mesh
+  void* Uf = nullptr;     // face states [slot][5][n^2] (precision R), per mesh;
+                          // single precision: deviations from the face base
+  float* Ub = nullptr;    // single precision: face bases [slot][5] (value at
+                          // the face's first flux point); null in double
+  float* fbar = nullptr;  // single precision, tetrahedra and pyramids: the
+                          // element's constant transformed flux [E][3][4]
   void* Vf = nullptr;     // normal viscous fluxes [slot][4][n^2], per mesh
   void* Rp = nullptr;     // volume divergence [E][5][N_u] (precision R)
   const FaceRec* faces = nullptr;

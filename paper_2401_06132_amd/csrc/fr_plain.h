@@ -20,6 +20,8 @@ struct PlainOps {
   std::vector<double> M7;  // nq x nu                 qptsu, gradcoru_qpts
   std::vector<double> K;   // nu x 3nq   (M1 - M3 M2) M9   tdivpcorf
   std::vector<double> M3;  // nu x nf                 tdivtconf
+  std::vector<double> LV;  // nu x 3nu   [Lv_0 | Lv_1 | Lv_2]: the divergence L(rho v)
+                           //            of the linear energy-flux part
 };
 
 // per own flux point: the paired point and which side is L
@@ -49,12 +51,12 @@ struct PlainCtx {
   PlainOps ops[NTYPES];
   PlainTypes ty;
   Gas<double> gas;
-  double beta = 0.5, eref = 0.0;
+  double beta = 0.5, eref = 0.0, rho0 = 0.0;
   int64_t state_off[NTYPES] = {};
   void* blas = nullptr;
   // device
   double *dM0[NTYPES] = {}, *dG1[NTYPES] = {}, *dM6[NTYPES] = {};
-  double *dM7[NTYPES] = {}, *dK[NTYPES] = {}, *dM3[NTYPES] = {};
+  double *dM7[NTYPES] = {}, *dK[NTYPES] = {}, *dM3[NTYPES] = {}, *dLV[NTYPES] = {};
   double *W = nullptr, *Uf = nullptr, *Cf = nullptr, *Q = nullptr, *Qf = nullptr, *Uq = nullptr, *Qq = nullptr;
   double *Df = nullptr, *fgeo = nullptr;
   double *jinv[NTYPES] = {}, *detj[NTYPES] = {};

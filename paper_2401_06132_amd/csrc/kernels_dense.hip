@@ -119,32 +119,125 @@ __device__ __forceinline__ void row_cols(const R* __restrict__ A, const R* B, in
   }
 }
 
+// Single precision works relative to a per-element base state u_b (the
+// base of the element's first face): the volume kernels hold the state as
+// u - u_b, so the linear operators (face values, gradients, quadrature
+// values) round the variation within the element instead of the O(1)
+// values, and add u_b back where the point-wise physics needs u.  Likewise
+// the constant transformed flux Fc[d][v] = det J sum_c (J^-1)_dc f^e_c(u_b)
+// (v = 1..4) is subtracted from the transformed flux before the divergence
+// product.  The constant's own
+// divergence is minus the lift of its reference normal component (a
+// constant flux has zero DG divergence; the free-stream pins fix this
+// identity for both element types), so the interface kernel subtracts
+// n^ . Fc from the transformed common flux: the sum is unchanged.
+template <typename R>
+__device__ __forceinline__ void const_flux(const float* __restrict__ ub, const R* met, const Gas<R>& g, R* out) {
+  R u[5], q[3][5] = {}, f[3][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = ub[v];
+  point_flux(u, q, g, f);  // zero gradient: the inviscid flux
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int v = 1; v < 5; ++v)
+      out[d * 4 + v - 1] = met[9] * (met[3 * d] * f[0][v] + met[3 * d + 1] * f[1][v] + met[3 * d + 2] * f[2][v]);
+}
+
 // ----------------------------------------------------------------- disu
-template <int ET, int P, typename R, int EB, int NT>
-__global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_ust, const R* __restrict__ ops,
-                                               const double eref) {
+// Double-precision operators of the disu kernel, stored after the working-
+// precision table: M0 and the operator of the mass-flux divergence,
+//   L(rho v) = sum_d Lv_d (S m)_d,  Lv_d = D_d (tetrahedra: the strong form
+//   (M1 - M3 M2) plus the lift of the own trace), Lv_d = Ku_d + M3 n_d M0
+//   (pyramids: their weak form plus the lift of the own trace).
+template <int ET, int P>
+struct DenseDisu {
   using C = DenseCfg<ET, P>;
+  static constexpr int O_M0 = 0, O_LV = C::NF * C::NU, SIZE = O_LV + 3 * C::NU * C::NU;
+};
+
+// byte offset of the double-precision block behind the table
+template <int ET, int P>
+constexpr size_t dense_disu_offset(size_t rs) {
+  return (rs * DenseCfg<ET, P>::SIZE + 255) / 256 * 256;
+}
+
+// Group 1 (eq. FR-disu) in double precision, as for hexahedra and prisms:
+// single precision stores a float base per face (its value at the face's
+// first flux point) and the deviations.  LIN: L(rho v) to row 0 of the
+// volume residual.
+template <int ET, int P, typename R, int EB, int NT>
+__global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_ust, const double* __restrict__ ops,
+                                               const double eref, const double rho0, const bool lin) {
+  using C = DenseCfg<ET, P>;
+  using DD = DenseDisu<ET, P>;
   constexpr int NU = C::NU, NF = C::NF, NFPS = C::NFPS, NFACE = C::NFACE;
-  __shared__ R sU[EB * 5 * NU];
+  constexpr bool FB = sizeof(R) == 4;
+  __shared__ double sU[EB * 5 * NU];
+  __shared__ double sF[EB * 5 * NF];
+  __shared__ double sS[EB][9];
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   R* __restrict__ Uf = (R*)sg.Uf;
+  if (lin && tid < EB * 9) {
+    const int le = tid / 9, k = tid - le * 9;
+    const R* __restrict__ met = (const R*)sg.met;
+    const size_t e = e0 + le < E ? (size_t)(e0 + le) : 0;
+    sS[le][k] = double(met[e * 10 + 9]) * double(met[e * 10 + k]);
+  }
   for (int it = tid; it < EB * 5 * NU; it += NT) {
     const bool ok = e0 + it / (5 * NU) < E;
     double x = U[ok ? (size_t)e0 * 5 * NU + it : 0];
-    if (it % (5 * NU) >= 4 * NU) x -= eref;
-    sU[it] = R(x);
+    const int r = it % (5 * NU);
+    if (r >= 4 * NU) x -= eref;
+    if (r < NU) x -= rho0;
+    sU[it] = x;
   }
   lds_barrier();
   for (int it = tid; it < EB * NF; it += NT) {
-    const int le = it / NF, fp = it - le * NF, e = e0 + le;
+    const int le = it / NF, fp = it - le * NF;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    row_cols<NU, 5>(ops + DD::O_M0 + fp * NU, sU + le * 5 * NU, NU, acc);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sF[(le * 5 + v) * NF + fp] = acc[v];
+  }
+  lds_barrier();
+  for (int it = tid; it < EB * 5 * NF; it += NT) {
+    const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF, e = e0 + le;
     if (e >= E) continue;
-    R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
-    row_cols<NU, 5>(ops + C::O_M0 + fp * NU, sU + le * 5 * NU, NU, acc);
     const int f = C::face_of(fp), t = C::point_of(fp);
     const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
+    const double x = sF[(le * 5 + v) * NF + fp];
+    if constexpr (FB) {
+      // the face's first flux point: the base square's first point, or a
+      // triangle's first node
+      const int fp0 = (C::PYR && f == 0) ? 0 : C::NB + (f - int(C::PYR)) * C::NTN;
+      const float b = float(sF[(le * 5 + v) * NF + fp0]);
+      Uf[slot * 5 * NFPS + v * NFPS + t] = R(x - double(b));
+      if (t == 0) sg.Ub[slot * 5 + v] = b;
+    } else {
+      Uf[slot * 5 * NFPS + v * NFPS + t] = R(x);
+    }
+  }
+  if (!lin) return;
+  // (S m)_d in place over the momentum (each point by one thread)
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU;
+    double* M = sU + le * 5 * NU + NU;
+    const double m0 = M[s], m1 = M[NU + s], m2 = M[2 * NU + s];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Uf[slot * 5 * NFPS + v * NFPS + t] = acc[v];
+    for (int d = 0; d < 3; ++d) M[d * NU + s] = sS[le][3 * d] * m0 + sS[le][3 * d + 1] * m1 + sS[le][3 * d + 2] * m2;
+  }
+  lds_barrier();
+  R* __restrict__ Rp = (R*)sg.Rp;
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU, e = e0 + le;
+    if (e >= E) continue;
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      row_cols<NU, 1>(ops + DD::O_LV + (d * NU + s) * NU, sU + le * 5 * NU + (1 + d) * NU, NU, acc);
+    Rp[(size_t)e * 5 * NU + s] = R(acc[0]);
   }
 }
 
@@ -154,15 +247,22 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
 // sum_d D_d F~_d - M3 (nhat . M0 F~)
 template <int ET, int P, typename R, int EB, int NT, bool AA>
 __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from_ust, const R* __restrict__ ops,
-                                                 const Gas<R> g, const double eref) {
+                                                 const Gas<R> g, const double eref, const double rho0) {
   using C = DenseCfg<ET, P>;
   constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, FQS = C::FQS, NFACE = C::NFACE;
+  // the mass flux's divergence and the linear energy-flux part come from the
+  // disu kernel's L(rho v): the fluxes of the other four variables are
+  // projected
+  constexpr int NVF = 4, V0 = 1;
+  constexpr bool FC = sizeof(R) == 4;  // constant-flux subtraction (single precision)
   constexpr int PE = C::PER_ELEM;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   __shared__ FaceRec sFR[EB * NFACE];
   __shared__ R sFG[EB * NFACE][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
+  __shared__ R sFc[EB][12];
+  __shared__ R sUb[EB][5];  // single precision: the element's base state
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -191,6 +291,14 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     const int le = it / (5 * NU), r = it - le * (5 * NU);
     double x = U[e0 + le < E ? (size_t)e0 * 5 * NU + it : 0];
     if (r >= 4 * NU) x -= eref;
+    if (r < NU) x -= rho0;
+    if constexpr (FC) {
+      // the state as deviations from the element's base state u_b (the base
+      // of its first face): the linear operators then round the variation
+      // within the element instead of the O(1) values
+      const int e = e0 + le < E ? e0 + le : 0;
+      x -= double(sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + r / NU]);
+    }
     XS(le)[r] = R(x);
   }
   lds_barrier();
@@ -198,7 +306,22 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
     const FaceRec fr = sFR[le * NFACE + f];
-    JS(le)[r0] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    R x = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    if constexpr (FC) {
+      // neighbour value relative to this element's base state
+      const int e = e0 + le < E ? e0 + le : 0;
+      x += sg.Ub[(size_t)fr.nbr * 5 + v] - sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+    }
+    JS(le)[r0] = x;
+  }
+  if (FC && tid < EB) {
+    const int e = e0 + tid < E ? e0 + tid : 0;
+    const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, &sMet[tid][0], g, &sFc[tid][0]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sUb[tid][v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+    if (e0 + tid < E)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sg.fbar[(size_t)e * 12 + k] = sFc[tid][k];
   }
   lds_barrier();
 
@@ -258,7 +381,7 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     R u[5], q[3][5], V[4];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v];
+      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
@@ -276,7 +399,7 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
       R u[5], q[3][5], f[3][5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        u[v] = X[v * NU + s];
+        u[v] = X[v * NU + s] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
         for (int c = 0; c < 3; ++c) q[c][v] = X[(5 + c * 5 + v) * NU + s];
       }
@@ -286,9 +409,10 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
+        for (int v = V0; v < 5; ++v)
           F[(d * 5 + v) * FQS + s] =
-              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+              (FC ? sFc[le][d * 4 + v - 1] : R(0));
     }
     lds_barrier();
     if constexpr (C::PYR) {
@@ -297,12 +421,13 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
       for (int it = tid; it < EB * NU; it += NT) {
         const int le = it / NU, s = it - le * NU, e = e0 + le;
         if (e >= E) continue;
-        R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
+        R acc[NVF] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          row_cols<NU, 5>(ops + C::O_KU + (d * NU + s) * NU, FQ(le) + d * 5 * FQS, FQS, acc);
+          row_cols<NU, NVF>(ops + C::O_KU + (d * NU + s) * NU, FQ(le) + (d * 5 + V0) * FQS, FQS, acc);
+        acc[NVF - 1] += g.kap * Rp[(size_t)e * 5 * NU + s];  // kap L(rho v)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[v];
+        for (int v = 0; v < NVF; ++v) Rp[(size_t)e * 5 * NU + (V0 + v) * NU + s] = acc[v];
       }
       return;
     }
@@ -311,28 +436,30 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     for (int it = tid; it < EB * NF; it += NT) {
       const int le = it / NF, fp = it - le * NF;
       const R* nh = ops + C::O_N + 3 * C::face_of(fp);
-      R nf[5] = {R(0), R(0), R(0), R(0), R(0)};
+      R nf[NVF] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        R a[5] = {R(0), R(0), R(0), R(0), R(0)};
-        row_cols<NU, 5>(ops + C::O_M0 + fp * NU, FQ(le) + d * 5 * FQS, FQS, a);
+        R a[NVF] = {R(0), R(0), R(0), R(0)};
+        row_cols<NU, NVF>(ops + C::O_M0 + fp * NU, FQ(le) + (d * 5 + V0) * FQS, FQS, a);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) nf[v] += nh[d] * a[v];
+        for (int v = 0; v < NVF; ++v) nf[v] += nh[d] * a[v];
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) JS(le)[v * NF + fp] = nf[v];
+      for (int v = 0; v < NVF; ++v) JS(le)[v * NF + fp] = nf[v];
     }
     lds_barrier();
     // (M1 - M3 M2) F~ = sum_d D_d F~_d - M3 (M2 F~)
     for (int it = tid; it < EB * NU; it += NT) {
       const int le = it / NU, s = it - le * NU, e = e0 + le;
       if (e >= E) continue;
-      R acc[5] = {R(0), R(0), R(0), R(0), R(0)}, lift[5] = {R(0), R(0), R(0), R(0), R(0)};
+      R acc[NVF] = {R(0), R(0), R(0), R(0)}, lift[NVF] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int d = 0; d < 3; ++d) row_cols<NU, 5>(ops + C::O_G + (d * NU + s) * C::KG, FQ(le) + d * 5 * FQS, FQS, acc);
-      row_cols<NF, 5>(ops + C::O_M3 + s * NF, JS(le), NF, lift);
+      for (int d = 0; d < 3; ++d)
+        row_cols<NU, NVF>(ops + C::O_G + (d * NU + s) * C::KG, FQ(le) + (d * 5 + V0) * FQS, FQS, acc);
+      row_cols<NF, NVF>(ops + C::O_M3 + s * NF, JS(le), NF, lift);
+      acc[NVF - 1] += g.kap * Rp[(size_t)e * 5 * NU + s];  // kap L(rho v)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[v] - lift[v];
+      for (int v = 0; v < NVF; ++v) Rp[(size_t)e * 5 * NU + (V0 + v) * NU + s] = acc[v] - lift[v];
     }
     return;
   }
@@ -347,7 +474,7 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     R u[5], q[3][5], f[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v];
+      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
@@ -357,9 +484,10 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
+      for (int v = V0; v < 5; ++v)
         F[(d * 5 + v) * FQS + q0] =
-            dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+            dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+            (FC ? sFc[le][d * 4 + v - 1] : R(0));
   }
   lds_barrier();  // every face and quadrature point has read the state and gradients
 
@@ -368,17 +496,19 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
   // state slots
   for (int it = tid; it < EB * 3 * NU; it += NT) {
     const int le = it / (3 * NU), r0 = it - le * (3 * NU), d = r0 / NU, s = r0 - d * NU;
-    R acc[5] = {R(0), R(0), R(0), R(0), R(0)};
-    row_cols<NQ, 5>(ops + C::O_AP + (d * NU + s) * NQ, FQ(le) + d * 5 * FQS, FQS, acc);
+    R acc[NVF] = {R(0), R(0), R(0), R(0)};
+    row_cols<NQ, NVF>(ops + C::O_AP + (d * NU + s) * NQ, FQ(le) + (d * 5 + V0) * FQS, FQS, acc);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) XS(le)[(d * 5 + v) * NU + s] = acc[v];
+    for (int v = 0; v < NVF; ++v) XS(le)[(d * 5 + V0 + v) * NU + s] = acc[v];
   }
   lds_barrier();
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const int le = it / (5 * NU), r0 = it - le * (5 * NU), e = e0 + le;
+  for (int it = tid; it < EB * NVF * NU; it += NT) {
+    const int le = it / (NVF * NU), r0 = V0 * NU + it - le * (NVF * NU), e = e0 + le;
     if (e >= E) continue;
     const R* X = XS(le);
-    Rp[(size_t)e * 5 * NU + r0] = X[r0] + X[5 * NU + r0] + X[10 * NU + r0];
+    R s = X[r0] + X[5 * NU + r0] + X[10 * NU + r0];
+    if (r0 >= 4 * NU) s += g.kap * Rp[(size_t)e * 5 * NU + r0 - 4 * NU];  // kap L(rho v)
+    Rp[(size_t)e * 5 * NU + r0] = s;
   }
 #undef XS
 #undef JS
@@ -434,16 +564,23 @@ __device__ __forceinline__ void mf_acc(typename MfVec<R>::T& acc, const R* __res
 
 template <int ET, int P, typename R, int EB, int NT, bool AA>
 __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const R* __restrict__ ops,
-                                                      const Gas<R> g, const double eref) {
+                                                      const Gas<R> g, const double eref, const double rho0) {
   using C = DenseCfg<ET, P>;
   using V4 = typename MfVec<R>::T;
   constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, NFACE = C::NFACE, LDW = C::LDW;
+  // the mass flux's divergence and the linear energy-flux part come from the
+  // disu kernel's L(rho v): the fluxes of the other four variables are
+  // projected
+  constexpr int NVF = 4, V0 = 1;
+  constexpr bool FC = sizeof(R) == 4;  // constant-flux subtraction (single precision)
   constexpr int PE = C::PE_MF, NW = NT / 64;
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   __shared__ FaceRec sFR[EB * NFACE];
   __shared__ R sFG[EB * NFACE][4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
+  __shared__ R sFc[EB][12];
+  __shared__ R sUb[EB][5];  // single precision: the element's base state
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -472,6 +609,14 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int le = it / (5 * NU), r = it - le * (5 * NU);
     double x = U[e0 + le < E ? (size_t)e0 * 5 * NU + it : 0];
     if (r >= 4 * NU) x -= eref;
+    if (r < NU) x -= rho0;
+    if constexpr (FC) {
+      // the state as deviations from the element's base state u_b (the base
+      // of its first face): the linear operators then round the variation
+      // within the element instead of the O(1) values
+      const int e = e0 + le < E ? e0 + le : 0;
+      x -= double(sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + r / NU]);
+    }
     XS(le)[r] = R(x);
   }
   lds_barrier();
@@ -479,7 +624,22 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
     const FaceRec fr = sFR[le * NFACE + f];
-    U2(le)[r0] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    R x = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    if constexpr (FC) {
+      // neighbour value relative to this element's base state
+      const int e = e0 + le < E ? e0 + le : 0;
+      x += sg.Ub[(size_t)fr.nbr * 5 + v] - sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+    }
+    U2(le)[r0] = x;
+  }
+  if (FC && tid < EB) {
+    const int e = e0 + tid < E ? e0 + tid : 0;
+    const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, &sMet[tid][0], g, &sFc[tid][0]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sUb[tid][v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+    if (e0 + tid < E)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sg.fbar[(size_t)e * 12 + k] = sFc[tid][k];
   }
   lds_barrier();
 
@@ -576,7 +736,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     R u[5], q[3][5], V[4];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v];
+      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
@@ -597,7 +757,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       R u[5], q[3][5], f[3][5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        u[v] = X[v * NU + s0];
+        u[v] = X[v * NU + s0] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
         for (int c = 0; c < 3; ++c) q[c][v] = X[(5 + c * 5 + v) * NU + s0];
       }
@@ -607,15 +767,16 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
-          w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+        for (int v = V0; v < 5; ++v)
+          w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+                         (FC ? sFc[le][d * 4 + v - 1] : R(0));
     }
     lds_barrier();
-    constexpr int NTL = (5 * EB + 15) / 16;
+    constexpr int NTL = (NVF * EB + 15) / 16;
     for (int t = wave; t < C::MTU * NTL; t += NW) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
-      const bool ok = j < 5 * EB;
-      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      const bool ok = j < NVF * EB;
+      const int le = ok ? j / NVF : EB - 1, v = ok ? V0 + j % NVF : V0;
       const R* Ap = ops + C::O_PK0 + mt * 3 * C::KSU * 64;
       V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
@@ -625,7 +786,11 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int s0 = mt * 16 + MfVec<R>::row(lane, r);
-          if (s0 < NU) Rp[(size_t)e * 5 * NU + v * NU + s0] = acc[r];
+          if (s0 < NU) {
+            R x = acc[r];
+            if (v == 4) x += g.kap * Rp[(size_t)e * 5 * NU + s0];  // kap L(rho v)
+            Rp[(size_t)e * 5 * NU + v * NU + s0] = x;
+          }
         }
     }
     return;
@@ -657,7 +822,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     R u[5], q[3][5], f[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v];
+      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
@@ -666,19 +831,20 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
+      for (int v = V0; v < 5; ++v)
+        w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+                       (FC ? sFc[le][d * 4 + v - 1] : R(0));
   }
   lds_barrier();
 
   // phase 5: projection-divergence, sum_d AP_d F~_d as one product over the
   // concatenated K = (direction, quadrature point)
   {
-    constexpr int NTL = (5 * EB + 15) / 16;
+    constexpr int NTL = (NVF * EB + 15) / 16;
     for (int t = wave; t < C::MTU * NTL; t += NW) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
-      const bool ok = j < 5 * EB;
-      const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      const bool ok = j < NVF * EB;
+      const int le = ok ? j / NVF : EB - 1, v = ok ? V0 + j % NVF : V0;
       const R* Ap = ops + C::O_PAP + mt * 3 * C::KSQ * 64;
       V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
@@ -689,7 +855,11 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int s = mt * 16 + MfVec<R>::row(lane, r);
-          if (s < NU) Rp[(size_t)e * 5 * NU + v * NU + s] = acc[r];
+          if (s < NU) {
+            R x = acc[r];
+            if (v == 4) x += g.kap * Rp[(size_t)e * 5 * NU + s];  // kap L(rho v)
+            Rp[(size_t)e * 5 * NU + v * NU + s] = x;
+          }
         }
     }
   }
@@ -720,11 +890,24 @@ __global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, 
     const FaceRec fr = sg.faces[slot];
     const int rr = sg.perms[(fr.info >> 1) * NFPS + t];
     const bool left = fr.info & 1;
-    R uo[5], un[5], Vo[4], Vn[4], F[5];
+    R uo[5], un[5], jn[5], Vo[4], Vn[4], F[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       uo[v] = Uf[(size_t)slot * 5 * NFPS + v * NFPS + t];
       un[v] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + rr];
+    }
+    // u_nbr - u_own from the face bases and deviations (single precision),
+    // before the states themselves are formed
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      if constexpr (sizeof(R) == 4) {
+        const float bo = sg.Ub[(size_t)slot * 5 + v], bn = sg.Ub[(size_t)fr.nbr * 5 + v];
+        jn[v] = (bn - bo) + (un[v] - uo[v]);
+        uo[v] += bo;
+        un[v] += bn;
+      } else {
+        jn[v] = un[v] - uo[v];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -733,13 +916,19 @@ __global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, 
     }
     const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
     const R mag = fgeo[4 * slot + 3];
-    if (left)
-      common_flux(uo, un, Vo, Vn, nL, g, F);
-    else
-      common_flux(un, uo, Vn, Vo, nL, g, F);
-    const R sc = left ? mag : -mag;
+    face_flux<R, true>(uo, un, jn, Vo, Vn, nL, left, g, F);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sD[(le * 5 + v) * NF + fp] = sc * F[v];
+    for (int v = 0; v < 5; ++v) F[v] *= mag;
+    if constexpr (sizeof(R) == 4) {
+      // the element's constant transformed flux, taken out of the volume
+      // product, leaves through its reference normal component here
+      const R* nh = ops + C::O_N + 3 * f;
+      const float* fc = sg.fbar + (size_t)e * 12;
+#pragma unroll
+      for (int v = 1; v < 5; ++v) F[v] -= nh[0] * fc[v - 1] + nh[1] * fc[4 + v - 1] + nh[2] * fc[8 + v - 1];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sD[(le * 5 + v) * NF + fp] = F[v];
   }
   lds_barrier();
   for (int it = tid; it < EB * NU; it += NT) {
@@ -827,18 +1016,64 @@ static size_t dense_size(int p) {
   return 0;
 }
 
+// the double-precision disu block: M0 and Lv_d (long double on the host)
+template <int ET, int P>
+static void pack_disu(const RefElem& r, double* o) {
+  using C = DenseCfg<ET, P>;
+  using DD = DenseDisu<ET, P>;
+  constexpr int NU = C::NU, NF = C::NF;
+  for (int i = 0; i < NF * NU; ++i) o[DD::O_M0 + i] = r.M0[i];
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < NU; ++s)
+      for (int u = 0; u < NU; ++u) {
+        long double acc;
+        if (C::PYR) {
+          acc = r.Ku[(d * NU + s) * NU + u];
+          for (int f = 0; f < NF; ++f)
+            acc += (long double)r.M3[s * NF + f] * r.face_normal[3 * C::face_of(f) + d] * r.M0[f * NU + u];
+        } else {
+          acc = r.Dg[(d * NU + s) * NU + u];
+        }
+        o[DD::O_LV + (d * NU + s) * NU + u] = (double)acc;
+      }
+}
+
+template <int ET, int P>
+static size_t dense_bytes_t(size_t rs) {
+  return dense_disu_offset<ET, P>(rs) + sizeof(double) * DenseDisu<ET, P>::SIZE;
+}
+
+template <int ET>
+static size_t dense_bytes_e(int p, size_t rs) {
+  switch (p) {
+    case 1: return dense_bytes_t<ET, 1>(rs);
+    case 2: return dense_bytes_t<ET, 2>(rs);
+    case 3: return dense_bytes_t<ET, 3>(rs);
+    case 4: return dense_bytes_t<ET, 4>(rs);
+  }
+  return 0;
+}
+
+// the device table: the operators in the working precision, then the
+// double-precision disu block
 size_t dense_ops_bytes(int etype, int p, int prec) {
   const size_t rs = prec == 0 ? 8 : 4;
-  return rs * (etype == 3 ? dense_size<3>(p) : etype == 2 ? dense_size<2>(p) : 0);
+  return etype == 3 ? dense_bytes_e<3>(p, rs) : etype == 2 ? dense_bytes_e<2>(p, rs) : 0;
+}
+
+template <int ET, int P, typename R>
+static void pack_dense_t(const RefElem& r, R* dst) {
+  pack_dense<ET, P>(r, dst);
+  pack_disu<ET, P>(r, (double*)((char*)dst + dense_disu_offset<ET, P>(sizeof(R))));
 }
 
 template <int ET, typename R>
 static void pack_dense_p(const RefElem& r, R* dst) {
   switch (r.p) {
-    case 1: pack_dense<ET, 1>(r, dst); break;
-    case 2: pack_dense<ET, 2>(r, dst); break;
-    case 3: pack_dense<ET, 3>(r, dst); break;
-    case 4: pack_dense<ET, 4>(r, dst); break;
+    case 1: pack_dense_t<ET, 1>(r, dst); break;
+    case 2: pack_dense_t<ET, 2>(r, dst); break;
+    case 3: pack_dense_t<ET, 3>(r, dst); break;
+    case 4: pack_dense_t<ET, 4>(r, dst); break;
   }
 }
 
@@ -850,20 +1085,6 @@ void dense_ops_pack(const RefElem& r, int prec, void* dst) {
     d ? pack_dense_p<3>(r, (double*)dst) : pack_dense_p<3>(r, (float*)dst);
 }
 
-template <typename R>
-static Gas<R> make_gas_t(const GasHost& gh) {
-  Gas<R> o;
-  o.gamma = R(gh.gamma);
-  o.gm1 = R(gh.gamma - 1.0);
-  o.mu = R(gh.mu);
-  o.muh = R(gh.mu * gh.gamma / gh.prandtl);
-  o.pref = R(gh.pref);
-  o.eref = R(gh.pref / (gh.gamma - 1.0));
-  o.href = R(gh.gamma * gh.pref / (gh.gamma - 1.0));
-  o.beta = R(gh.beta);
-  o.tau = R(gh.tau);
-  return o;
-}
 
 // elements per workgroup of the volume kernel: about one quadrature point
 // per thread at 256 threads; the workgroup then takes enough threads for one
@@ -884,13 +1105,16 @@ constexpr int DENSE_DISU_EB = 8, DENSE_SURF_EB = 8;
 template <int ET, int P, typename R>
 static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
   const R* ops = (const R*)a.dops;
-  const Gas<R> g = make_gas_t<R>(*a.gas);
-  const double eref = a.gas->pref / (a.gas->gamma - 1.0);
+  const double* dops = (const double*)((const char*)a.dops + dense_disu_offset<ET, P>(sizeof(R)));
+  // tetrahedra and pyramids are affine: the mass flux and the linear
+  // energy-flux part come from the double-precision L(rho v)
+  const Gas<R> g = make_gas<R>(*a.gas, true);
+  const double eref = a.gas->pref / (a.gas->gamma - 1.0), rho0 = a.gas->rho_ref;
   const int E = a.one.E;
   constexpr int EB = DenseLaunch<ET, P>::EB, NTV = DenseLaunch<ET, P>::NT;
   if ((a.stage & 1) && E > 0)
     hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
-                       dim3(256), 0, st, a.one, a.from_ust, ops, eref);
+                       dim3(256), 0, st, a.one, a.from_ust, dops, eref, rho0, true);
   if ((a.stage & 2) && E > 0) {
     // p >= 3 on the matrix cores.  With anti-aliasing at 48^3 cells the
     // volume group runs 14-42% faster than the VALU kernel in FP32 and
@@ -903,17 +1127,17 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     if constexpr (MF) {
       if (a.aa)
         hipLaunchKernelGGL((dense_volume_mf<ET, P, R, EBM, 256, true>), dim3((E + EBM - 1) / EBM), dim3(256), 0, st,
-                           a.one, a.from_ust, ops, g, eref);
+                           a.one, a.from_ust, ops, g, eref, rho0);
       else
         hipLaunchKernelGGL((dense_volume_mf<ET, P, R, EBM, 256, false>), dim3((E + EBM - 1) / EBM), dim3(256), 0, st,
-                           a.one, a.from_ust, ops, g, eref);
+                           a.one, a.from_ust, ops, g, eref, rho0);
     } else {
       if (a.aa)
         hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, true>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
-                           a.one, a.from_ust, ops, g, eref);
+                           a.one, a.from_ust, ops, g, eref, rho0);
       else
         hipLaunchKernelGGL((dense_volume<ET, P, R, EB, NTV, false>), dim3((E + EB - 1) / EB), dim3(NTV), 0, st,
-                           a.one, a.from_ust, ops, g, eref);
+                           a.one, a.from_ust, ops, g, eref, rho0);
     }
   }
   if ((a.stage & 4) && E > 0)

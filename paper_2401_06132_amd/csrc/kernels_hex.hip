@@ -108,13 +108,35 @@ __device__ __forceinline__ R sel(const R (&v)[N], int idx) {
 }
 
 // ----------------------------------------------------------------- disu
+// Operators of the disu kernel, always in double precision.
+template <int P>
+struct HexDisuOps {
+  static constexpr int n = P + 1;
+  double lb[n], rb[n];  // l_i(-1), l_i(+1)
+  double D[n][n];       // l_j' at the solution points
+};
+
+// Group 1: the solution at the flux points (eq. FR-disu), interpolated in
+// double precision from the state in reference form.  Single precision
+// stores each face as a base (its value at the face's first flux point,
+// rounded to float) and the deviations from it, so that a face jump
+// u_nbr - u_own = (b_nbr - b_own) + (d_nbr - d_own) keeps the digits that
+// the O(1) values themselves lose.
+// LIN: also the central DG divergence of the mass flux in double precision,
+//   L(rho v) = sum_d D_d (S m)_d,  S = det J J^-1,
+// the strong form (M1 - M3 M2) (S m) plus the lift of the own trace (exact
+// for affine elements: the projected polynomial flux is itself), written
+// to row 0 of the volume residual.
 template <int P, typename R, int EB, int NT, bool BT>
 __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __restrict__ bt,
                                                const Seg* __restrict__ segs, const bool from_ust,
-                                               const HexOps<P, R> op, const double eref) {
+                                               const HexDisuOps<P> op, const double eref, const double rho0,
+                                               const bool lin) {
   using C = HexCfg<P>;
   constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
-  __shared__ R sU[EB * 5 * NU];
+  constexpr bool FB = sizeof(R) == 4;
+  __shared__ double sU[EB * 5 * NU];
+  __shared__ double sS[EB][9];
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -128,6 +150,13 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
     const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
     xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
+  if (lin && tid < EB * 9) {
+    // S = det J J^-1 from the element metrics [J^-1 (row-major), det J]
+    const int le = tid / 9, k = tid - le * 9;
+    const R* __restrict__ met = (const R*)sg.met;
+    const size_t e = e0 + le < E ? (size_t)(e0 + le) : 0;
+    sS[le][k] = double(met[e * 10 + 9]) * double(met[e * 10 + k]);
+  }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int it = tid + k * NT;
@@ -135,7 +164,8 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
       const int r = it % (5 * NU);
       double x = xs[k];
       if (r >= 4 * NU) x -= eref;
-      sU[it] = R(x);
+      if (r < NU) x -= rho0;
+      sU[it] = x;
     }
   }
   lds_barrier();
@@ -144,16 +174,55 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
     const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
     const int a = r % n, b = r / n, e = e0 + le;
     if (e >= E) continue;
-    R xm = R(0), xp = R(0);
+    const double* X = sU + le * 5 * NU + v * NU;
+    double xm = 0.0, xp = 0.0;
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-      const R x = sU[le * 5 * NU + v * NU + hex_pt<n>(ax, i, a, b)];
+      const double x = X[hex_pt<n>(ax, i, a, b)];
       xm += op.lb[i] * x;
       xp += op.rb[i] * x;
     }
     const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
-    Uf[s0 * 5 * NFP + v * NFP + r] = xm;
-    Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = xp;
+    if constexpr (FB) {
+      // the face base: the value at the first flux point (a = b = 0)
+      double bm = 0.0, bp = 0.0;
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const double x = X[hex_pt<n>(ax, i, 0, 0)];
+        bm += op.lb[i] * x;
+        bp += op.rb[i] * x;
+      }
+      const float fm = float(bm), fp = float(bp);
+      Uf[s0 * 5 * NFP + v * NFP + r] = R(xm - double(fm));
+      Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = R(xp - double(fp));
+      if (r == 0) {
+        sg.Ub[s0 * 5 + v] = fm;
+        sg.Ub[(s0 + 1) * 5 + v] = fp;
+      }
+    } else {
+      Uf[s0 * 5 * NFP + v * NFP + r] = R(xm);
+      Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = R(xp);
+    }
+  }
+  if (!lin) return;
+  R* __restrict__ Rp = (R*)sg.Rp;
+  for (int it = tid; it < EB * NU; it += NT) {
+    const int le = it / NU, s = it - le * NU, e = e0 + le;
+    if (e >= E) continue;
+    const int ix[3] = {s % n, (s / n) % n, s / (n * n)};
+    const double* M = sU + le * 5 * NU + NU;  // momentum components
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int a = ix[d == 0 ? 1 : 0], b = ix[d == 2 ? 1 : 2];
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        const int pt = hex_pt<n>(d, q, a, b);
+        const double sm = sS[le][3 * d] * M[pt] + sS[le][3 * d + 1] * M[NU + pt] + sS[le][3 * d + 2] * M[2 * NU + pt];
+        acc += op.D[ix[d]][q] * sm;
+      }
+    }
+    Rp[(size_t)e * 5 * NU + s] = R(acc);
   }
 }
 
@@ -175,17 +244,20 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
 // surface-flux AA or curved, T1 stays after region A and Y after Z (the
 // footprint is the larger of A + B + T1 and Z + Y): the x rows held in
 // registers there spill (FP64: 4.29 -> 4.54 ms).
-template <int P>
+template <int P, bool LIN>
 struct HexVol {
   static constexpr int n = P + 1, m = P + 3, NU = n * n * n, NFP = n * n;
-  static constexpr int SZ_X = 20 * NU, SZ_Y = 10 * m * n * n;
+  // variables whose flux is projected: LIN leaves out the mass flux (its
+  // divergence is L(rho v), formed by the disu kernel)
+  static constexpr int NVF = LIN ? 4 : 5, V0 = 5 - NVF;
+  static constexpr int SZ_X = 20 * NU, SZ_Y = 2 * NVF * m * n * n;
   static constexpr int SZ_A = SZ_X > SZ_Y ? SZ_X : SZ_Y;
   // x-interpolated fields T1 [20][m][TPS]; at p = 4 the rows of n^2 are
   // padded to n^2 + 1 so that the quadrature columns of a wave read
   // different banks (measured at 48^3: 1% faster in FP32, 4% in FP64; at
   // p = 3 the unpadded rows are faster)
   static constexpr int TPS = P >= 4 ? NFP + 1 : NFP;
-  static constexpr int SZ_T1 = 20 * m * TPS, SZ_Z = 15 * m * m * n, SZ_J = 30 * NFP;
+  static constexpr int SZ_T1 = 20 * m * TPS, SZ_Z = 3 * NVF * m * m * n, SZ_J = 30 * NFP;
   // surface-flux anti-aliasing, per axis: face values interpolated along the
   // first tangential axis [2][20][m][n], viscous flux at the face
   // quadrature points [2][4][m][m]
@@ -208,9 +280,9 @@ struct HexVol {
 // records, face geometry and metrics first (independent loads), then the
 // neighbour face states (gathered through face records in LDS).  Every
 // thread issues all of its loads before the first use.
-template <int P, typename R, int EB, int NT>
+template <int P, typename R, int EB, int NT, bool LIN>
 struct HexVolLoads {
-  using C = HexVol<P>;
+  using C = HexVol<P, LIN>;
   static constexpr int NU = C::NU, NFP = C::NFP;
   static constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
   static constexpr int NG = (EB * 30 * NFP + NT - 1) / NT;
@@ -263,8 +335,11 @@ struct HexVolLoads {
     }
   }
   // face records of out-of-range elements are those of a valid slot, so
-  // every gathered address is valid; only in-range values are ever used
-  __device__ __forceinline__ void gather(const R* __restrict__ Uf, const FaceRec* sFR, const uint8_t* sPerm, int tid) {
+  // every gathered address is valid; only in-range values are ever used.
+  // Single precision adds the neighbour face's base.
+  __device__ __forceinline__ void gather(const R* __restrict__ Uf, const float* __restrict__ Ub,
+                                         const FaceRec* sFR, const uint8_t* sPerm, int tid) {
+    R gb[NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
       const int it = tid + k * NT;
@@ -273,11 +348,17 @@ struct HexVolLoads {
       const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
       const FaceRec q = sFR[le * 6 + f];
       gv[k] = Uf[(size_t)q.nbr * 5 * NFP + v * NFP + sPerm[(q.info >> 1) * NFP + r]];
+      if constexpr (sizeof(R) == 4) gb[k] = Ub[(size_t)q.nbr * 5 + v];
+    }
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int k = 0; k < NG; ++k) gv[k] += gb[k];
     }
   }
   // state in reference form, metrics and neighbour states to LDS (pe: LDS
   // values per element)
-  __device__ __forceinline__ void put_elems(R* smem, R (*sMet)[10], double eref, int pe, int tid) const {
+  __device__ __forceinline__ void put_elems(R* smem, R (*sMet)[10], double eref, double rho0, int pe,
+                                            int tid) const {
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
       const int it = tid + k * NT;
@@ -290,6 +371,7 @@ struct HexVolLoads {
         const int le = it / (5 * NU), r = it - le * (5 * NU);
         double x = xs[k];
         if (r >= 4 * NU) x -= eref;
+        if (r < NU) x -= rho0;
         smem[le * pe + r] = R(x);
       }
     }
@@ -321,9 +403,12 @@ struct HexVolLoads {
 template <int P, typename R, int EB, int NT, bool DIAG, bool BT, bool AA, bool SAA, bool WARP>
 __global__ void __launch_bounds__(NT)
     hex_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
-               const HexOps<P, R> op, const Gas<R> g, const double eref) {
-  using C = HexVol<P>;
-  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
+               const HexOps<P, R> op, const Gas<R> g, const double eref, const double rho0) {
+  // LIN: the mass flux's divergence and the linear energy-flux part come
+  // from the disu kernel's L(rho v) (affine elements only)
+  constexpr bool LIN = !WARP;
+  using C = HexVol<P, LIN>;
+  constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP, NVF = C::NVF, V0 = C::V0;
   constexpr int SZ_BN = SAA && C::SZ_S > C::SZ_J ? C::SZ_S : C::SZ_J;  // region B without AA
   constexpr bool TOX = C::template tox<R, SAA, WARP>();
   constexpr int PE = AA ? C::per_elem(SAA, TOX) : C::SZ_A + SZ_BN;
@@ -346,10 +431,10 @@ __global__ void __launch_bounds__(NT)
   const R* __restrict__ met = (const R*)sg.met;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                     */
-#define YS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_Z)) /* [2][5][m][YB][n]  */
+#define YS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_Z)) /* [2][NVF][m][YB][n] */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [6][5][NFP] neighbour u^f    */
 #define TS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [20][m][TPS]      */
-#define ZS(le) (smem + (le)*PE)            /* [3][5][m][m][n]              */
+#define ZS(le) (smem + (le)*PE)            /* [3][NVF][m][m][n]            */
 #define SS(le) (smem + (le)*PE + C::SZ_A)  /* [2][20][m][n], [2][4][m][m]  */
 
   // phase 0: state (reference form), metrics, neighbour states at own
@@ -357,7 +442,7 @@ __global__ void __launch_bounds__(NT)
   // first, so the neighbour gather is one global load per value.
   for (int it = tid; it < sg.nperm * NFP; it += NT) sPerm[it] = sg.perms[it];
   if (tid < m * n) sI[tid / n][tid % n] = op.I[tid / n][tid % n];
-  HexVolLoads<P, R, EB, NT> ld;
+  HexVolLoads<P, R, EB, NT, LIN> ld;
   ld.load(U, faces, fgeo, met, e0, E, slot_base, tid);
   ld.put_faces(sFR, sFG, tid);
   if constexpr (WARP) {
@@ -368,8 +453,8 @@ __global__ void __launch_bounds__(NT)
     }
   }
   lds_barrier();
-  ld.gather(Uf, sFR, sPerm, tid);
-  ld.put_elems(smem, sMet, eref, PE, tid);
+  ld.gather(Uf, sg.Ub, sFR, sPerm, tid);
+  ld.put_elems(smem, sMet, eref, rho0, PE, tid);
   lds_barrier();
   const FaceRec* cFR = sFR;
   const R (*cFG)[4] = sFG;
@@ -608,26 +693,28 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
+        for (int v = V0; v < 5; ++v) {
           const R ft = DIAG ? sMet[le][4 * d] * f[d][v]
                             : sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v];
           X[(5 + d * 5 + v) * NU + s] = dj * ft;
         }
     }
     lds_barrier();
-    for (int it = tid; it < EB * 5 * NU; it += NT) {
-      const int le = it / (5 * NU), r0 = it - le * (5 * NU), v = r0 / NU, s = r0 - v * NU, e = e0 + le;
+    for (int it = tid; it < EB * NVF * NU; it += NT) {
+      const int le = it / (NVF * NU), r1 = it - le * (NVF * NU), v = V0 + r1 / NU, s = r1 - (v - V0) * NU;
+      const int e = e0 + le;
       if (e >= E) continue;
       const int i = s % n, j = (s / n) % n, k = s / (n * n);
       const R* F = XS(le) + 5 * NU + v * NU;  // component d at F + d * 5 NU
       R acc = R(0);
+      if (LIN && v == 4) acc = g.kap * Rp[(size_t)e * 5 * NU + s];  // kap L(rho v)
 #pragma unroll
       for (int c = 0; c < n; ++c) {
         acc += sAPu[i][c] * F[0 * 5 * NU + c + n * (j + n * k)];
         acc += sAPu[j][c] * F[1 * 5 * NU + i + n * (c + n * k)];
         acc += sAPu[k][c] * F[2 * 5 * NU + i + n * (j + n * c)];
       }
-      Rp[(size_t)e * 5 * NU + r0] = acc;
+      Rp[(size_t)e * 5 * NU + v * NU + s] = acc;
     }
     return;
   }
@@ -687,7 +774,7 @@ __global__ void __launch_bounds__(NT)
   // (tdisf, eq. FR-tdisfq) and the z factor of the projection-divergence
   const bool col = tid < EB * m * m;
   const int cle = tid / (m * m), cr = tid - cle * (m * m), ca = cr / m, cb = cr - ca * m;
-  R acc[3][5][n];
+  R acc[3][NVF][n];
   if (col) {
     R Ib[n];
 #pragma unroll
@@ -713,7 +800,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
+      for (int v = 0; v < NVF; ++v)
 #pragma unroll
         for (int l = 0; l < n; ++l) acc[d][v][l] = R(0);
 #pragma unroll
@@ -737,10 +824,10 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
+        for (int v = V0; v < 5; ++v) {
           const R ft = DIAG ? S[d][d] * f[d][v] : S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
 #pragma unroll
-          for (int l = 0; l < n; ++l) acc[d][v][l] += (d == 2 ? op.AP[l][kq] : op.Pj[l][kq]) * ft;
+          for (int l = 0; l < n; ++l) acc[d][v - V0][l] += (d == 2 ? op.AP[l][kq] : op.Pj[l][kq]) * ft;
         }
     }
   }
@@ -750,9 +837,9 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
+      for (int v = 0; v < NVF; ++v)
 #pragma unroll
-        for (int l = 0; l < n; ++l) Z[(((d * 5 + v) * m + ca) * m + cb) * n + l] = acc[d][v][l];
+        for (int l = 0; l < n; ++l) Z[(((d * NVF + v) * m + ca) * m + cb) * n + l] = acc[d][v][l];
   }
   lds_barrier();
 
@@ -760,16 +847,16 @@ __global__ void __launch_bounds__(NT)
   // (TOX), Y[d][v][a][j][l] takes the place of Z[d][v][a][j][l], which only
   // this thread reads (into registers, before it writes).
   constexpr int YB = TOX ? m : n;
-  for (int it = tid; it < EB * 5 * m * n; it += NT) {
-    const int le = it / (5 * m * n), r0 = it - le * (5 * m * n);
+  for (int it = tid; it < EB * NVF * m * n; it += NT) {
+    const int le = it / (NVF * m * n), r0 = it - le * (NVF * m * n);
     const int v = r0 / (m * n), r1 = r0 - v * (m * n), a = r1 / n, l = r1 - a * n;
     const R* Z = ZS(le);
     R zx[m], zy[m], zz[m];
 #pragma unroll
     for (int b = 0; b < m; ++b) {
-      zx[b] = Z[(((0 * 5 + v) * m + a) * m + b) * n + l];
-      zy[b] = Z[(((1 * 5 + v) * m + a) * m + b) * n + l];
-      zz[b] = Z[(((2 * 5 + v) * m + a) * m + b) * n + l];
+      zx[b] = Z[(((0 * NVF + v) * m + a) * m + b) * n + l];
+      zy[b] = Z[(((1 * NVF + v) * m + a) * m + b) * n + l];
+      zz[b] = Z[(((2 * NVF + v) * m + a) * m + b) * n + l];
     }
     R* Y = YS(le);
 #pragma unroll
@@ -780,30 +867,37 @@ __global__ void __launch_bounds__(NT)
         sx += op.Pj[j][b] * zx[b];
         sy += op.AP[j][b] * zy[b] + op.Pj[j][b] * zz[b];
       }
-      Y[(((0 * 5 + v) * m + a) * YB + j) * n + l] = sx;
-      Y[(((1 * 5 + v) * m + a) * YB + j) * n + l] = sy;
+      Y[(((0 * NVF + v) * m + a) * YB + j) * n + l] = sx;
+      Y[(((1 * NVF + v) * m + a) * YB + j) * n + l] = sy;
     }
   }
   lds_barrier();
 
-  // phase 6: x projection: R_vol = AP_x X' + P_x Y'
-  for (int it = tid; it < EB * 5 * NFP; it += NT) {
-    const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), v = r0 / NFP, r = r0 - v * NFP;
+  // phase 6: x projection: R_vol = AP_x X' + P_x Y'; LIN: the energy
+  // residual takes kap L(rho v) (row 0, from the disu kernel), which also
+  // is the mass residual
+  for (int it = tid; it < EB * NVF * NFP; it += NT) {
+    const int le = it / (NVF * NFP), r0 = it - le * (NVF * NFP), v = r0 / NFP, r = r0 - v * NFP;
     const int j = r % n, l = r / n, e = e0 + le;
     if (e >= E) continue;
+    R lin[n];
+    if (LIN && v + V0 == 4) {
+#pragma unroll
+      for (int i = 0; i < n; ++i) lin[i] = Rp[(size_t)e * 5 * NU + i + n * (j + n * l)];
+    }
     const R* Y = YS(le);
     R y0[m], y1[m];
 #pragma unroll
     for (int a = 0; a < m; ++a) {
-      y0[a] = Y[(((0 * 5 + v) * m + a) * YB + j) * n + l];
-      y1[a] = Y[(((1 * 5 + v) * m + a) * YB + j) * n + l];
+      y0[a] = Y[(((0 * NVF + v) * m + a) * YB + j) * n + l];
+      y1[a] = Y[(((1 * NVF + v) * m + a) * YB + j) * n + l];
     }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-      R s = R(0);
+      R s = (LIN && v + V0 == 4) ? g.kap * lin[i] : R(0);
 #pragma unroll
       for (int a = 0; a < m; ++a) s += op.AP[i][a] * y0[a] + op.Pj[i][a] * y1[a];
-      Rp[(size_t)e * 5 * NU + v * NU + i + n * (j + n * l)] = s;
+      Rp[(size_t)e * 5 * NU + (v + V0) * NU + i + n * (j + n * l)] = s;
     }
   }
 #undef XS
@@ -836,9 +930,11 @@ __global__ void __launch_bounds__(NT)
   constexpr int n = C::n, m = C::m, NU = C::NU, NFP = C::NFP;
   constexpr int NI = (EB * 6 * NFP + NT - 1) / NT;  // flux points per thread
   constexpr int NL = (EB * 5 * NU + NT - 1) / NT;   // solution values per thread
-  // SAA staging per face: the pair of states at the flux points [10][NFP],
-  // later the Rusanov flux at the quadrature points [5][m][m] (sW); the
-  // states interpolated along the first tangential axis [10][m][n] (sT)
+  constexpr bool LIN = !WARP, FB = sizeof(R) == 4;
+  // SAA staging per face: the L state and the jump uL - uR at the flux
+  // points [10][NFP], later the Rusanov flux at the quadrature points
+  // [5][m][m] (sW); both interpolated along the first tangential axis
+  // [10][m][n] (sT)
   constexpr int SW = 10 * NFP > 5 * m * m ? 10 * NFP : 5 * m * m, ST = 10 * m * n;
   __shared__ R sD[EB * 30 * NFP];
   __shared__ R sW[SAA ? EB * 6 * SW : 1];
@@ -893,9 +989,11 @@ __global__ void __launch_bounds__(NT)
     rp[k] = Rp[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
   lds_barrier();
-  // comm_flux: common normal flux at every own flux point, times +-mag
+  // comm_flux: common normal flux at every own flux point, times mag.  The
+  // jump u_nbr - u_own comes from the face bases and deviations (single
+  // precision) before the states themselves are formed.
   {
-    R uo[NI][5], un[NI][5], Vo[NI][4], Vn[NI][4];
+    R uo[NI][5], un[NI][5], jn[NI][5], Vo[NI][4], Vn[NI][4];
 #pragma unroll
     for (int q = 0; q < NI; ++q) {
       const int it = tid + q * NT;
@@ -908,6 +1006,19 @@ __global__ void __launch_bounds__(NT)
       for (int v = 0; v < 5; ++v) {
         uo[q][v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
         un[q][v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+      }
+      if constexpr (FB) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) jn[q][v] = sg.Ub[(size_t)fr.nbr * 5 + v];  // neighbour base
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const float bo = sg.Ub[(size_t)slot * 5 + v];
+          const R d = un[q][v] - uo[q][v];
+          const R bn = jn[q][v];
+          jn[q][v] = (bn - bo) + d;
+          uo[q][v] += bo;
+          un[q][v] += bn;
+        }
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -922,6 +1033,10 @@ __global__ void __launch_bounds__(NT)
       const int le = it / (6 * NFP), r0 = it - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP;
       const int lf = le * 6 + f;
       const bool left = sFR[lf].info & 1;
+      if constexpr (!FB) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) jn[q][v] = un[q][v] - uo[q][v];
+      }
       R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
       R mag = sFG[lf][3];
       if constexpr (WARP) {
@@ -936,27 +1051,22 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
         for (int c = 0; c < 3; ++c) nL[c] = im * S[ax][c];
       }
-      R F[5];
-      const R sc = left ? mag : -mag;
+      R D[5];
       if constexpr (SAA) {
-        if (left)
-          linear_flux(uo[q], un[q], Vo[q], Vn[q], g, F);
-        else
-          linear_flux(un[q], uo[q], Vn[q], Vo[q], g, F);
+        face_flux_linear<R, LIN>(jn[q], Vo[q], Vn[q], nL, left, g, D);
+        // stage the L state and uL - uR for the Rusanov flux at the face
+        // quadrature points
         R* W = sW + lf * SW + r;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           W[v * NFP] = left ? uo[q][v] : un[q][v];
-          W[(5 + v) * NFP] = left ? un[q][v] : uo[q][v];
+          W[(5 + v) * NFP] = left ? -jn[q][v] : jn[q][v];
         }
       } else {
-        if (left)
-          common_flux(uo[q], un[q], Vo[q], Vn[q], nL, g, F);
-        else
-          common_flux(un[q], uo[q], Vn[q], Vo[q], nL, g, F);
+        face_flux<R, LIN>(uo[q], un[q], jn[q], Vo[q], Vn[q], nL, left, g, D);
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sD[lf * 5 * NFP + v * NFP + r] = sc * F[v];
+      for (int v = 0; v < 5; ++v) sD[lf * 5 * NFP + v * NFP + r] = mag * D[v];
     }
   }
   if constexpr (WARP) {
@@ -996,21 +1106,21 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
       const R* T = sT + lf * ST + a2 * n;
-      R uL[5], uR[5];
+      R uL[5], jl[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        R sl = R(0), sr = R(0);
+        R sl = R(0), sj = R(0);
 #pragma unroll
         for (int b = 0; b < n; ++b) {
           sl += Ib[b] * T[v * m * n + b];
-          sr += Ib[b] * T[(5 + v) * m * n + b];
+          sj += Ib[b] * T[(5 + v) * m * n + b];
         }
         uL[v] = sl;
-        uR[v] = sr;
+        jl[v] = sj;
       }
       const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
       R F[5];
-      rusanov_flux(uL, uR, nL, g, F);
+      rusanov_jump<R, true>(uL, jl, nL, g, F);
       R* FQ = sW + lf * SW + a2 * m + b2;
 #pragma unroll
       for (int v = 0; v < 5; ++v) FQ[v * m * m] = F[v];
@@ -1089,20 +1199,6 @@ static HexOps<P, R> make_hex_ops(const HostOps& h) {
   return o;
 }
 
-template <typename R>
-static Gas<R> make_gas(const GasHost& g) {
-  Gas<R> o;
-  o.gamma = R(g.gamma);
-  o.gm1 = R(g.gamma - 1.0);
-  o.mu = R(g.mu);
-  o.muh = R(g.mu * g.gamma / g.prandtl);
-  o.pref = R(g.pref);
-  o.eref = R(g.pref / (g.gamma - 1.0));
-  o.href = R(g.gamma * g.pref / (g.gamma - 1.0));
-  o.beta = R(g.beta);
-  o.tau = R(g.tau);
-  return o;
-}
 
 // launch shapes of the volume kernel: EB elements per workgroup, NT threads,
 // with EB * m^2 <= NT (one quadrature column per thread); the LDS footprint
@@ -1146,7 +1242,7 @@ static void hex_volume_launch(const TypeArgs& a, int nb, const HexOps<P, R>& op,
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = HexVolLaunch<P, dbl, AA>::EB, NT = HexVolLaunch<P, dbl, AA>::NT;
   hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA, WARP>), dim3(nb), dim3(NT), 0, st, a.one,
-                     a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref);
+                     a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref, a.gas->rho_ref);
 }
 
 // surface-flux anti-aliasing is built together with flux anti-aliasing only
@@ -1162,16 +1258,31 @@ static void hex_volume_dispatch(const TypeArgs& a, int nb, const HexOps<P, R>& o
     hex_volume_launch<P, R, BT, DIAG, false, false>(a, nb, op, g, eref, st);
 }
 
+template <int P>
+static HexDisuOps<P> make_disu_ops(const HostOps& h) {
+  HexDisuOps<P> o;
+  constexpr int n = P + 1;
+  for (int i = 0; i < n; ++i) {
+    o.lb[i] = h.lb[i];
+    o.rb[i] = h.rb[i];
+    for (int j = 0; j < n; ++j) o.D[i][j] = h.D[i * n + j];
+  }
+  return o;
+}
+
 template <int P, typename R, bool BT>
 static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const HexOps<P, R> op = make_hex_ops<P, R>(*a.ops);
-  const Gas<R> g = make_gas<R>(*a.gas);
+  // affine elements take the mass flux and the linear energy-flux part from
+  // the double-precision L(rho v) of the disu kernel
+  const bool lin = !a.warp;
+  const Gas<R> g = make_gas<R>(*a.gas, lin);
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EBA = HEX_DISU_EB, NTA = 256, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
-                       a.segs, a.from_ust, op, eref);
+                       a.segs, a.from_ust, make_disu_ops<P>(*a.ops), eref, a.gas->rho_ref, lin);
   // curved hexahedra (single meshes only; flux anti-aliasing, general metric)
   if constexpr (!BT) {
     if (a.warp) {

@@ -19,6 +19,14 @@
 //  12 tdivtconf     R~  += M3 D~
 //  13 negdivconf    R    = -R~ / det J
 //
+// With a reference density the energy flux is split exactly as in the fused
+// kernels: v (E + p) = v (E' + p' - kap rho') + kap rho v.  Steps 9-12 carry
+// the first part; the linear part adds kap L(rho v) to the volume residual
+// (L = sum_d Lv_d (S m)_d, a GEMM on the transformed momentum at the
+// solution points) and kap mag 1/2 (m_nbr - m_own) . n_own to the common
+// energy flux.  The O(gamma pref/(gamma-1)) energy flux then never enters the
+// dense (M1 - M3 M2) M9 product, whose long sums would round it at ~1e-12.
+//
 // Layouts: per element type, element-major: U [E][5][N_u] is the
 // column-major matrix N_u x 5E; Q [E][5][3][N_u] is 3N_u x 5E (rows (d,s)) and
 // also N_u x 15E; the same holds at flux and quadrature points.
@@ -120,8 +128,14 @@ __global__ void comm_flux_kernel(int64_t nftot, const double* __restrict__ Uf,
     else
       common_flux(un, uo, Vn, Vo, nL, g, Fc);
     const double sc = F.is_left ? mag : -mag;
+    double D[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Df[ty.off_f[t] + (e * 5 + v) * ty.nf[t] + f] = sc * Fc[v];
+    for (int v = 0; v < 5; ++v) D[v] = sc * Fc[v];
+    // the linear energy-flux part: its strong-form interface term
+    const double* no = F.is_left ? nL : nR;
+    D[4] += g.kap * mag * 0.5 * ((un[1] - uo[1]) * no[0] + (un[2] - uo[2]) * no[1] + (un[3] - uo[3]) * no[2]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Df[ty.off_f[t] + (e * 5 + v) * ty.nf[t] + f] = D[v];
   }
 }
 
@@ -131,12 +145,30 @@ __global__ void negdivconf_kernel(int64_t E, int nu, double* __restrict__ R, con
     R[i] = -R[i] / detj[i / (5 * nu)];
 }
 
-// E' = E - pref/(gamma-1) (reference-state form) into a scratch copy of U
-__global__ void refstate_kernel(int64_t E, int nu, const double* __restrict__ U, double* __restrict__ W, double eref) {
+// rho' = rho - rho0, E' = E - pref/(gamma-1) (reference-state form) into a
+// scratch copy of U
+__global__ void refstate_kernel(int64_t E, int nu, const double* __restrict__ U, double* __restrict__ W, double eref,
+                                double rho0) {
   const int64_t n = E * 5 * nu;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int v = int((i / nu) % 5);
-    W[i] = v == 4 ? U[i] - eref : U[i];
+    W[i] = v == 4 ? U[i] - eref : (v == 0 ? U[i] - rho0 : U[i]);
+  }
+}
+
+// the transformed momentum (S m)_d = det J sum_c (J^-1)_dc m_c at the solution
+// points: SM [E][3][N_u], the columns of the L(rho v) product
+__global__ void sm_kernel(int64_t E, int nu, const double* __restrict__ W, double* __restrict__ SM,
+                          const double* __restrict__ jinv, const double* __restrict__ detj) {
+  const int64_t n = E * nu;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / nu, s = i - e * nu;
+    const double* m = W + (e * 5 + 1) * nu + s;
+    const double m0 = m[0], m1 = m[nu], m2 = m[2 * nu];
+    const double* B = jinv + 9 * e;
+    const double dj = detj[e];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) SM[(e * 3 + d) * nu + s] = dj * (B[3 * d] * m0 + B[3 * d + 1] * m1 + B[3 * d + 2] * m2);
   }
 }
 
@@ -191,6 +223,26 @@ void build_plain_ops(const RefElem& r, PlainOps& o) {
   mat_mul_ld(M6ld.data(), 3 * nu, nf, r.M0.data(), nu, M6M0.data());
   o.G1.assign(3 * nu * nu, 0.0);
   for (int k = 0; k < 3 * nu * nu; ++k) o.G1[k] = (double)((long double)r.Dg[k] - M6M0[k]);
+  // LV = [Lv_0 | Lv_1 | Lv_2] (rows s, columns (d, u)): Lv_d = D_d (the strong
+  // form plus the lift of the own trace); pyramids Ku_d + M3 n_d M0 (their
+  // weak form plus the lift of the own trace)
+  o.LV.assign((size_t)nu * 3 * nu, 0.0);
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < nu; ++s)
+      for (int u = 0; u < nu; ++u) {
+        long double acc;
+        if (r.etype == 3) {
+          acc = r.Ku[((size_t)d * nu + s) * nu + u];
+          for (int f = 0; f < nf; ++f) {
+            int face = 0;
+            while (face + 1 < r.nfaces && f >= r.face_start[face + 1]) ++face;
+            acc += (long double)r.M3[s * nf + f] * r.face_normal[3 * face + d] * r.M0[f * nu + u];
+          }
+        } else {
+          acc = r.Dg[((size_t)d * nu + s) * nu + u];
+        }
+        o.LV[(size_t)s * 3 * nu + d * nu + u] = (double)acc;
+      }
   // K = (M1 - M3 M2) M9: for component d, (Dg_d - M3 N_d M0) M8, columns (d, q).
   // Pyramids (space not closed under differentiation): the weak form AP_d.
   o.K.assign((size_t)nu * 3 * nq, 0.0);
@@ -214,6 +266,14 @@ void build_plain_ops(const RefElem& r, PlainOps& o) {
     for (int s = 0; s < nu; ++s)
       for (int q = 0; q < nq; ++q) o.K[(size_t)s * 3 * nq + d * nq + q] = (double)Kd[s * nq + q];
   }
+}
+
+// C (M x N, col-major, leading dimension ldc) = alpha A B + beta C, A row-major
+// (M x K), B col-major (K x N)
+static rocblas_status gemm_ld(rocblas_handle h, const double* A, int M, int K, const double* B, int64_t N, double* C,
+                              int64_t ldc, double alpha, double beta) {
+  return rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, M, (rocblas_int)N, K, &alpha, A, K, B,
+                       K, &beta, C, (rocblas_int)ldc);
 }
 
 static rocblas_status gemm(rocblas_handle h, const double* A, int M, int K, const double* B, int64_t N, double* C,
@@ -241,7 +301,8 @@ hipError_t plain_rhs(PlainCtx& P, const double* U, double* du, hipStream_t st) {
     const PlainOps& o = P.ops[t];
     const double* Ut = U + P.state_off[t];
     double* W = P.W + P.state_off[t];
-    hipLaunchKernelGGL(refstate_kernel, grid_for(ty.E[t] * 5 * o.nu), dim3(256), 0, st, ty.E[t], o.nu, Ut, W, P.eref);
+    hipLaunchKernelGGL(refstate_kernel, grid_for(ty.E[t] * 5 * o.nu), dim3(256), 0, st, ty.E[t], o.nu, Ut, W, P.eref,
+                       P.rho0);
     if (gemm(h, P.dM0[t], o.nf, o.nu, W, 5 * ty.E[t], P.Uf + ty.off_f[t], 0.0) != rocblas_status_success)
       return hipErrorUnknown;  // 1 disu
   }
@@ -267,6 +328,14 @@ hipError_t plain_rhs(PlainCtx& P, const double* U, double* du, hipStream_t st) {
                        g);  // 9 tdisf
     if (gemm(h, P.dK[t], o.nu, 3 * o.nq, P.Qq, 5 * E, du + P.state_off[t], 0.0) != rocblas_status_success)
       return hipErrorUnknown;  // 10 tdivpcorf
+    if (g.kap != 0.0) {
+      // kap L(rho v) onto the energy rows (columns 5 e + 4 of N_u x 5E): the
+      // transformed momentum into the (free) quadrature-point scratch first
+      hipLaunchKernelGGL(sm_kernel, grid_for(E * o.nu), dim3(256), 0, st, E, o.nu, W, P.Uq, P.jinv[t], P.detj[t]);
+      if (gemm_ld(h, P.dLV[t], o.nu, 3 * o.nu, P.Uq, E, du + P.state_off[t] + 4 * o.nu, 5 * o.nu, g.kap, 1.0) !=
+          rocblas_status_success)
+        return hipErrorUnknown;
+    }
   }
   hipLaunchKernelGGL(comm_flux_kernel, grid_for(nftot), dim3(256), 0, st, nftot, P.Uf, P.Qf, P.Df, P.faces,
                      P.fgeo, ty, g);  // 11 comm_flux

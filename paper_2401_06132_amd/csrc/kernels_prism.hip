@@ -114,14 +114,38 @@ __device__ __forceinline__ R psel(const R (&v)[N], int idx) {
 }
 
 // ----------------------------------------------------------------- disu
+// Double-precision operators of the disu kernel, stored after the prism
+// table in the same device allocation.
+template <int P>
+struct PrismDisuTab {
+  static constexpr int n = P + 1, NT = (P + 1) * (P + 2) / 2;
+  double lb[n], rb[n], D[n][n];   // line: l_k(-1), l_k(+1), l_j' at the GL points
+  double Tedge[3][n][NT];         // nodal basis at the GL points of each edge
+  double Dxi[NT][NT], Deta[NT][NT];
+};
+
+// byte offset of the disu table behind the prism table
+template <int P, typename R>
+constexpr size_t prism_disu_offset() {
+  return (sizeof(PrismTri<P, R>) + 255) / 256 * 256;
+}
+
+// Group 1 (eq. FR-disu) in double precision, as for hexahedra: triangle
+// faces by the zeta lines, quadrilateral faces by the edge interpolation of
+// each triangle plane; single precision stores a float base per face (the
+// value at its first flux point) and the deviations.  LIN: the mass-flux
+// divergence L(rho v) = D_xi (S m)_xi + D_eta (S m)_eta + D_zeta (S m)_zeta
+// to row 0 of the volume residual.
 template <int P, typename R, int EB, int NT_, bool BT>
 __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* __restrict__ bt,
                                                   const Seg* __restrict__ segs, const bool from_ust,
-                                                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri,
-                                                  const double eref) {
+                                                  const PrismDisuTab<P>* __restrict__ tab, const double eref,
+                                                  const double rho0, const bool lin) {
   using C = PrismCfg<P>;
   constexpr int n = C::n, NT = C::NT, NU = C::NU, NFP = C::NFP;
-  __shared__ R sU[EB * 5 * NU];
+  constexpr bool FB = sizeof(R) == 4;
+  __shared__ double sU[EB * 5 * NU];
+  __shared__ double sS[EB][9];
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
@@ -135,6 +159,12 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
     const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
     xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
+  if (lin && tid < EB * 9) {
+    const int le = tid / 9, k = tid - le * 9;
+    const R* __restrict__ met = (const R*)sg.met;
+    const size_t e = e0 + le < E ? (size_t)(e0 + le) : 0;
+    sS[le][k] = double(met[e * 10 + 9]) * double(met[e * 10 + k]);
+  }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int it = tid + k * NT_;
@@ -142,7 +172,8 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
       const int r = it % (5 * NU);
       double x = xs[k];
       if (r >= 4 * NU) x -= eref;
-      sU[it] = R(x);
+      if (r < NU) x -= rho0;
+      sU[it] = x;
     }
   }
   lds_barrier();
@@ -150,33 +181,79 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
   for (int it = tid; it < EB * 5 * NT; it += NT_) {
     const int le = it / (5 * NT), r = it - le * (5 * NT), v = r / NT, t = r - v * NT, e = e0 + le;
     if (e >= E) continue;
-    R xm = R(0), xp = R(0);
+    const double* X = sU + le * 5 * NU + v * NU;
+    double xm = 0.0, xp = 0.0, bm = 0.0, bp = 0.0;
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      const R x = sU[le * 5 * NU + v * NU + t + NT * k];
-      xm += op.lb[k] * x;
-      xp += op.rb[k] * x;
+      xm += tab->lb[k] * X[t + NT * k];
+      xp += tab->rb[k] * X[t + NT * k];
+      bm += tab->lb[k] * X[NT * k];
+      bp += tab->rb[k] * X[NT * k];
     }
     const size_t s0 = (size_t)(slot_base + e * 5);
-    Uf[s0 * 5 * NFP + v * NFP + t] = xm;
-    Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = xp;
+    if constexpr (FB) {
+      const float fm = float(bm), fp = float(bp);
+      Uf[s0 * 5 * NFP + v * NFP + t] = R(xm - double(fm));
+      Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = R(xp - double(fp));
+      if (t == 0) {
+        sg.Ub[s0 * 5 + v] = fm;
+        sg.Ub[(s0 + 1) * 5 + v] = fp;
+      }
+    } else {
+      Uf[s0 * 5 * NFP + v * NFP + t] = R(xm);
+      Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = R(xp);
+    }
   }
-  // quadrilateral faces: triangle-plane interpolation to the edge points
+  // quadrilateral faces: triangle-plane interpolation to the edge points;
+  // the base of edge face ed is its value at (i, k) = (0, 0)
   for (int it = tid; it < EB * 5 * n; it += NT_) {
     const int le = it / (5 * n), r = it - le * (5 * n), v = r / n, k = r - v * n, e = e0 + le;
     if (e >= E) continue;
-    R x[NT];
+    const double* X = sU + le * 5 * NU + v * NU;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) x[t] = sU[le * 5 * NU + v * NU + t + NT * k];
+    for (int ed = 0; ed < 3; ++ed) {
+      const size_t slot = (size_t)(slot_base + e * 5 + 2 + ed);
+      float fb = 0.0f;
+      if constexpr (FB) {
+        double b0 = 0.0;
 #pragma unroll
-    for (int ed = 0; ed < 3; ++ed)
+        for (int t = 0; t < NT; ++t) b0 += tab->Tedge[ed][0][t] * X[t];
+        fb = float(b0);
+        if (k == 0) sg.Ub[slot * 5 + v] = fb;
+      }
 #pragma unroll
       for (int i = 0; i < n; ++i) {
-        R s = R(0);
+        double s = 0.0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) s += tri->Tedge[ed][i][t] * x[t];
-        Uf[(size_t)(slot_base + e * 5 + 2 + ed) * 5 * NFP + v * NFP + i + n * k] = s;
+        for (int t = 0; t < NT; ++t) s += tab->Tedge[ed][i][t] * X[t + NT * k];
+        Uf[slot * 5 * NFP + v * NFP + i + n * k] = R(FB ? s - double(fb) : s);
       }
+    }
+  }
+  if (!lin) return;
+  lds_barrier();
+  // the transformed mass flux (S m)_d at every point, in place over the
+  // momentum (each point is read and written by one thread)
+  for (int it = tid; it < EB * NU; it += NT_) {
+    const int le = it / NU, s = it - le * NU;
+    double* M = sU + le * 5 * NU + NU;
+    const double m0 = M[s], m1 = M[NU + s], m2 = M[2 * NU + s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) M[d * NU + s] = sS[le][3 * d] * m0 + sS[le][3 * d + 1] * m1 + sS[le][3 * d + 2] * m2;
+  }
+  lds_barrier();
+  R* __restrict__ Rp = (R*)sg.Rp;
+  for (int it = tid; it < EB * NU; it += NT_) {
+    const int le = it / NU, s = it - le * NU, e = e0 + le;
+    if (e >= E) continue;
+    const int k = s / NT, t = s - k * NT;
+    const double* M = sU + le * 5 * NU + NU;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc += tab->Dxi[t][c] * M[c + NT * k] + tab->Deta[t][c] * M[NU + c + NT * k];
+#pragma unroll
+    for (int q = 0; q < n; ++q) acc += tab->D[k][q] * M[2 * NU + t + NT * q];
+    Rp[(size_t)e * 5 * NU + s] = R(acc);
   }
 }
 
@@ -193,15 +270,18 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
 // unchanged.  FP64 at p = 4 keeps T1 and Z after region A.  The triangle
 // operator tables are staged in LDS once per workgroup so that every
 // triangle-plane product can run one output point per thread.
-template <int P>
+template <int P, bool LIN>
 struct PrismVol {
   static constexpr int n = P + 1, m = P + 3, NTN = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
   static constexpr int NU = NTN * n, NFP = n * n;
+  // variables whose flux is projected: LIN leaves out the mass flux (its
+  // divergence is L(rho v), formed by the disu kernel)
+  static constexpr int NVF = LIN ? 4 : 5, V0 = 5 - NVF;
   static constexpr int SZ_A = 20 * NU;
   // padded strides keep the LDS accesses of both writer and reader free of
   // bank conflicts: T1 rows of NTQ + 1, Z variables NTQ n + 4 apart
   static constexpr int TQS = NTQ + 1, ZVS = NTQ * n + 4;
-  static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * TQS, SZ_Z = 15 * ZVS;
+  static constexpr int SZ_J = 25 * NFP, SZ_T1 = 20 * n * TQS, SZ_Z = 3 * NVF * ZVS;
   static constexpr int EFS = 3 * NFP + 1;  // the 20 fields at the quadrilateral-face points,
   static constexpr int SZ_EF = 20 * EFS;   // odd stride per field (no bank conflicts)
   static constexpr int SZ_JE = SZ_J > SZ_EF ? SZ_J : SZ_EF;
@@ -252,9 +332,13 @@ template <int P, typename R, int EB, int NT_, bool BT, bool AA, bool SAA, bool W
 __global__ void __launch_bounds__(NT_)
     prism_volume(const Seg one, const BlkRef* __restrict__ bt, const Seg* __restrict__ segs, const bool from_ust,
                  const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri_g, const Gas<R> g,
-                 const double eref) {
-  using C = PrismVol<P>;
+                 const double eref, const double rho0) {
+  // LIN: the mass flux's divergence and the linear energy-flux part come
+  // from the disu kernel's L(rho v) (affine elements only)
+  constexpr bool LIN = !WARP;
+  using C = PrismVol<P, LIN>;
   constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
+  constexpr int NVF = C::NVF, V0 = C::V0;
   // single precision up to p = 3: triangle-plane work one (field, plane) per
   // thread with broadcast operator reads (enough planes fill the workgroup);
   // otherwise one output point per thread
@@ -283,7 +367,7 @@ __global__ void __launch_bounds__(NT_)
 #define XS(le) (smem + (le)*PE)            /* [20][NU]                 */
 #define JS(le) (smem + (le)*PE + C::SZ_A)  /* [5][5][NFP]              */
 #define TS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [20][n][TQS]  */
-#define ZS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [3][5][ZVS][n] */
+#define ZS(le) (smem + (le)*PE + (TOX ? 0 : C::SZ_A)) /* [3][NVF][ZVS] */
 #define SS(le) (smem + (le)*PE + C::SZ_A)  /* face quadrature staging   */
 
   // phase 0: operator tables, state (reference form), metrics, neighbour states
@@ -342,6 +426,7 @@ __global__ void __launch_bounds__(NT_)
     const int rr = (f >= 2 || r < NTN) ? r : 0;
     const FaceRec fr = sFR[le * 5 + f];
     gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + rr]];
+    if constexpr (sizeof(R) == 4) gv[k] += sg.Ub[(size_t)fr.nbr * 5 + v];  // the face base
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -350,6 +435,7 @@ __global__ void __launch_bounds__(NT_)
       const int le = it / (5 * NU), r = it - le * (5 * NU);
       double x = xs[k];
       if (r >= 4 * NU) x -= eref;
+      if (r < NU) x -= rho0;
       XS(le)[r] = R(x);
     }
   }
@@ -803,7 +889,7 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
+        for (int v = V0; v < 5; ++v)
           X[(5 + d * 5 + v) * NU + s] =
               dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]);
     }
@@ -811,13 +897,13 @@ __global__ void __launch_bounds__(NT_)
     // M2 F~: reference normal flux at the own flux points (JS region, free
     // since the gradient phase): triangle faces from the zeta lines,
     // quadrilateral faces from the triangle planes (per plane where PL)
-    constexpr int NQF = PL ? 5 * n : 5 * 3 * n * n;
-    for (int it = tid; it < EB * (5 * NTN + NQF); it += NT_) {
-      const int le = it / (5 * NTN + NQF), r0 = it - le * (5 * NTN + NQF);
+    constexpr int NQF = PL ? NVF * n : NVF * 3 * n * n;
+    for (int it = tid; it < EB * (NVF * NTN + NQF); it += NT_) {
+      const int le = it / (NVF * NTN + NQF), r0 = it - le * (NVF * NTN + NQF);
       const R* F = XS(le) + 5 * NU;  // component d of variable v at F[(d * 5 + v) * NU]
       R* NF = JS(le);
-      if (r0 < 5 * NTN) {
-        const int v = r0 / NTN, t = r0 - v * NTN;
+      if (r0 < NVF * NTN) {
+        const int v = V0 + r0 / NTN, t = r0 - (v - V0) * NTN;
         R fm = R(0), fp = R(0);
 #pragma unroll
         for (int k = 0; k < n; ++k) {
@@ -828,7 +914,7 @@ __global__ void __launch_bounds__(NT_)
         NF[(0 * 5 + v) * NFP + t] = -fm;  // zeta = -1: outward normal -e_zeta
         NF[(1 * 5 + v) * NFP + t] = fp;
       } else if constexpr (PL) {
-        const int r1 = r0 - 5 * NTN, v = r1 / n, k = r1 - v * n;
+        const int r1 = r0 - NVF * NTN, v = V0 + r1 / n, k = r1 - (v - V0) * n;
         R fx[NTN], fy[NTN];
 #pragma unroll
         for (int t = 0; t < NTN; ++t) {
@@ -851,8 +937,8 @@ __global__ void __launch_bounds__(NT_)
           }
         }
       } else {
-        const int r1 = r0 - 5 * NTN, v = r1 / (3 * n * n), r2 = r1 - v * (3 * n * n), ed = r2 / (n * n);
-        const int r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
+        const int r1 = r0 - NVF * NTN, v = V0 + r1 / (3 * n * n), r2 = r1 - (v - V0) * (3 * n * n);
+        const int ed = r2 / (n * n), r3 = r2 - ed * (n * n), k = r3 / n, i = r3 - k * n;
         R sx = R(0), sy = R(0);
 #pragma unroll
         for (int t = 0; t < NTN; ++t) {
@@ -867,8 +953,8 @@ __global__ void __launch_bounds__(NT_)
     lds_barrier();
     // (M1 - M3 M2) F~: the zeta derivative and triangle-face lifting per
     // line, accumulated over the state slots (dead since the flux phase) ...
-    for (int it = tid; it < EB * 5 * NTN; it += NT_) {
-      const int le = it / (5 * NTN), r0 = it - le * (5 * NTN), v = r0 / NTN, t = r0 - v * NTN;
+    for (int it = tid; it < EB * NVF * NTN; it += NT_) {
+      const int le = it / (NVF * NTN), r0 = it - le * (NVF * NTN), v = V0 + r0 / NTN, t = r0 - (v - V0) * NTN;
       const R* F = XS(le) + 5 * NU;
       const R* NF = JS(le);
       R z[n];
@@ -885,14 +971,14 @@ __global__ void __launch_bounds__(NT_)
     }
     lds_barrier();
     // ... then the (xi, eta) derivative blocks and quadrilateral-face lifting
-    constexpr int NDV = PL ? 5 * n : 5 * NU;
+    constexpr int NDV = PL ? NVF * n : NVF * NU;
     for (int it = tid; it < EB * NDV; it += NT_) {
       const int le = it / NDV, r0 = it - le * NDV, e = e0 + le;
       if (e >= E) continue;
       const R* F = XS(le) + 5 * NU;
       const R* NF = JS(le);
       if constexpr (PL) {
-        const int v = r0 / n, k = r0 - v * n;
+        const int v = V0 + r0 / n, k = r0 - (v - V0) * n;
         R fx[NTN], fy[NTN], nq[3][n];
 #pragma unroll
         for (int c = 0; c < NTN; ++c) {
@@ -906,6 +992,7 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
         for (int t = 0; t < NTN; ++t) {
           R acc = XS(le)[v * NU + t + NTN * k];
+          if (LIN && v == 4) acc += g.kap * Rp[(size_t)e * 5 * NU + t + NTN * k];  // kap L(rho v)
 #pragma unroll
           for (int c = 0; c < NTN; ++c) acc += tri.Dxi[t][c] * fx[c] + tri.Deta[t][c] * fy[c];
 #pragma unroll
@@ -915,8 +1002,9 @@ __global__ void __launch_bounds__(NT_)
           Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = acc;
         }
       } else {
-        const int v = r0 / NU, s = r0 - v * NU, k = s / NTN, t = s - k * NTN;
-        R acc = XS(le)[r0];
+        const int v = V0 + r0 / NU, s = r0 - (v - V0) * NU, k = s / NTN, t = s - k * NTN;
+        R acc = XS(le)[v * NU + s];
+        if (LIN && v == 4) acc += g.kap * Rp[(size_t)e * 5 * NU + s];  // kap L(rho v)
 #pragma unroll
         for (int c = 0; c < NTN; ++c)
           acc += tri.Dxi[t][c] * F[(0 * 5 + v) * NU + c + NTN * k] + tri.Deta[t][c] * F[(1 * 5 + v) * NU + c + NTN * k];
@@ -924,7 +1012,7 @@ __global__ void __launch_bounds__(NT_)
         for (int ed = 0; ed < 3; ++ed)
 #pragma unroll
           for (int i = 0; i < n; ++i) acc -= tri.LiftEdge[ed][t][i] * NF[((2 + ed) * 5 + v) * NFP + i + n * k];
-        Rp[(size_t)e * 5 * NU + r0] = acc;
+        Rp[(size_t)e * 5 * NU + v * NU + s] = acc;
       }
     }
     return;
@@ -998,11 +1086,11 @@ __global__ void __launch_bounds__(NT_)
   // the line part of the projection-divergence; the pair sum completes it
   const bool col = tid < 2 * EB * NTQ;
   const int cc = tid >> 1, half = tid & 1, cle = cc / NTQ, ctq = cc - cle * NTQ;
-  R acc[3][5][n];
+  R acc[3][NVF][n];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int v = 0; v < NVF; ++v)
 #pragma unroll
       for (int k = 0; k < n; ++k) acc[d][v][k] = R(0);
   if (col) {
@@ -1056,17 +1144,17 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
+        for (int v = V0; v < 5; ++v) {
           const R ft = S[d][0] * f[0][v] + S[d][1] * f[1][v] + S[d][2] * f[2][v];
 #pragma unroll
-          for (int k = 0; k < n; ++k) acc[d][v][k] += (d == 2 ? wA[k] : wP[k]) * ft;
+          for (int k = 0; k < n; ++k) acc[d][v - V0][k] += (d == 2 ? wA[k] : wP[k]) * ft;
         }
     }
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int v = 0; v < NVF; ++v)
 #pragma unroll
       for (int k = 0; k < n; ++k) acc[d][v][k] = pair_sum(acc[d][v][k]);
   lds_barrier();  // every column has read T1; Z may now overwrite it
@@ -1076,33 +1164,34 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
+      for (int v = 0; v < NVF; ++v)
 #pragma unroll
         for (int k = 0; k < n; ++k)
-          if (((d * 5 + v) * n + k) % 2 == half) Z[(d * 5 + v) * C::ZVS + ctq * n + k] = acc[d][v][k];
+          if (((d * NVF + v) * n + k) % 2 == half) Z[(d * NVF + v) * C::ZVS + ctq * n + k] = acc[d][v][k];
   }
   lds_barrier();
 
   // phase 6: triangle-plane projection-divergence: one (variable, plane) per
   // thread, its 3 N_tq line-projected flux values in registers, operator
-  // entries read from the LDS copy at wave-uniform addresses
-  for (int it = tid; it < EB * 5 * n * SPL; it += NT_) {
-    const int le = it / (5 * n * SPL), r0 = it - le * (5 * n * SPL), vk = r0 / SPL, h = r0 - vk * SPL;
-    const int v = vk / n, k = vk - v * n, e = e0 + le;
+  // entries read from the LDS copy at wave-uniform addresses; LIN: the
+  // energy residual takes kap L(rho v) (row 0, from the disu kernel)
+  for (int it = tid; it < EB * NVF * n * SPL; it += NT_) {
+    const int le = it / (NVF * n * SPL), r0 = it - le * (NVF * n * SPL), vk = r0 / SPL, h = r0 - vk * SPL;
+    const int vv = vk / n, k = vk - vv * n, e = e0 + le, v = vv + V0;
     if (e >= E) continue;
     const R* Z = ZS(le);
     R z0[NTQ], z1[NTQ], z2[NTQ];
 #pragma unroll
     for (int tq = 0; tq < NTQ; ++tq) {
-      z0[tq] = Z[(0 * 5 + v) * C::ZVS + tq * n + k];
-      z1[tq] = Z[(1 * 5 + v) * C::ZVS + tq * n + k];
-      z2[tq] = Z[(2 * 5 + v) * C::ZVS + tq * n + k];
+      z0[tq] = Z[(0 * NVF + vv) * C::ZVS + tq * n + k];
+      z1[tq] = Z[(1 * NVF + vv) * C::ZVS + tq * n + k];
+      z2[tq] = Z[(2 * NVF + vv) * C::ZVS + tq * n + k];
     }
 #pragma unroll
     for (int j = 0; j < (NTN + SPL - 1) / SPL; ++j) {
       const int t = SPL * j + h;
       if (t < NTN) {
-        R s = R(0);
+        R s = (LIN && v == 4) ? g.kap * Rp[(size_t)e * 5 * NU + t + NTN * k] : R(0);
 #pragma unroll
         for (int tq = 0; tq < NTQ; ++tq)
           s += tri.APxi[t][tq] * z0[tq] + tri.APeta[t][tq] * z1[tq] + tri.PT[t][tq] * z2[tq];
@@ -1132,7 +1221,8 @@ __global__ void __launch_bounds__(NT_)
                   const PrismOps<P, R> op, const PrismTri<P, R>* __restrict__ tri, const Gas<R> g) {
   using C = PrismCfg<P>;
   constexpr int n = C::n, m = C::m, NT = C::NT, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
-  // SAA staging per face: the pair of states [10][NFP], later the Rusanov
+  constexpr bool LIN = !WARP, FB = sizeof(R) == 4;
+  // SAA staging per face: the L state and uL - uR [10][NFP], later the Rusanov
   // flux at a quadrilateral's quadrature points [5][m][m] (sW); a
   // quadrilateral's states along its first axis at GL(m) [10][m][n] (sT);
   // the Rusanov flux at a triangle's quadrature points [5][NTQ] (sFt)
@@ -1190,11 +1280,24 @@ __global__ void __launch_bounds__(NT_)
     const FaceRec fr = faces[slot];
     const int rr = perms[(fr.info >> 1) * NFP + r];
     const bool left = fr.info & 1;
-    R uo[5], un[5], Vo[4], Vn[4], F[5];
+    R uo[5], un[5], jn[5], Vo[4], Vn[4], F[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       uo[v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
       un[v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+    }
+    // u_nbr - u_own from the face bases and deviations (single precision),
+    // before the states themselves are formed
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      if constexpr (FB) {
+        const float bo = sg.Ub[(size_t)slot * 5 + v], bn = sg.Ub[(size_t)fr.nbr * 5 + v];
+        jn[v] = (bn - bo) + (un[v] - uo[v]);
+        uo[v] += bo;
+        un[v] += bn;
+      } else {
+        jn[v] = un[v] - uo[v];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1225,15 +1328,12 @@ __global__ void __launch_bounds__(NT_)
       for (int c = 0; c < 3; ++c) nL[c] = im * vv[c];
     }
     if constexpr (SAA) {
-      if (left)
-        linear_flux(uo, un, Vo, Vn, g, F);
-      else
-        linear_flux(un, uo, Vn, Vo, g, F);
+      face_flux_linear<R, LIN>(jn, Vo, Vn, nL, left, g, F);
       R* W = sW + (le * 5 + f) * SW + r;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         W[v * NFP] = left ? uo[v] : un[v];
-        W[(5 + v) * NFP] = left ? un[v] : uo[v];
+        W[(5 + v) * NFP] = left ? -jn[v] : jn[v];
       }
       if (r == 0) {
         sInfo[le * 5 + f] = fr.info;
@@ -1242,14 +1342,10 @@ __global__ void __launch_bounds__(NT_)
         sFG[le * 5 + f][3] = mag;
       }
     } else {
-      if (left)
-        common_flux(uo, un, Vo, Vn, nL, g, F);
-      else
-        common_flux(un, uo, Vn, Vo, nL, g, F);
+      face_flux<R, LIN>(uo, un, jn, Vo, Vn, nL, left, g, F);
     }
-    const R sc = left ? mag : -mag;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sD[(le * 5 + f) * 5 * NFP + v * NFP + r] = sc * F[v];
+    for (int v = 0; v < 5; ++v) sD[(le * 5 + f) * 5 * NFP + v * NFP + r] = mag * F[v];
   }
   if constexpr (SAA) {
     __syncthreads();
@@ -1262,21 +1358,21 @@ __global__ void __launch_bounds__(NT_)
       if (r0 < 2 * NTQ) {
         const int f = r0 / NTQ, q = r0 - f * NTQ, lf = le * 5 + f;
         const R* W = sW + lf * SW;
-        R uL[5], uR[5];
+        R uL[5], jl[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          R sl = R(0), sr = R(0);
+          R sl = R(0), sj = R(0);
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             sl += sTq[q][t] * W[v * NFP + t];
-            sr += sTq[q][t] * W[(5 + v) * NFP + t];
+            sj += sTq[q][t] * W[(5 + v) * NFP + t];
           }
           uL[v] = sl;
-          uR[v] = sr;
+          jl[v] = sj;
         }
         const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
         R F[5];
-        rusanov_flux(uL, uR, nL, g, F);
+        rusanov_jump<R, true>(uL, jl, nL, g, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFt[(le * 2 + f) * SF + v * NTQ + q] = F[v];
       } else {
@@ -1318,21 +1414,21 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
         for (int j = 0; j < n; ++j) Ib[j] = sI[b2][j];
         const R* T = sT + (le * 3 + ed) * ST + a2 * n;
-        R uL[5], uR[5];
+        R uL[5], jl[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          R sl = R(0), sr = R(0);
+          R sl = R(0), sj = R(0);
 #pragma unroll
           for (int k = 0; k < n; ++k) {
             sl += Ib[k] * T[v * m * n + k];
-            sr += Ib[k] * T[(5 + v) * m * n + k];
+            sj += Ib[k] * T[(5 + v) * m * n + k];
           }
           uL[v] = sl;
-          uR[v] = sr;
+          jl[v] = sj;
         }
         const R nL[3] = {sFG[lf][0], sFG[lf][1], sFG[lf][2]};
         R F[5];
-        rusanov_flux(uL, uR, nL, g, F);
+        rusanov_jump<R, true>(uL, jl, nL, g, F);
         R* FQ = sW + lf * SW + a2 * m + b2;
 #pragma unroll
         for (int v = 0; v < 5; ++v) FQ[v * m * m] = F[v];
@@ -1445,13 +1541,45 @@ static void pack_tri(const Tri& T, PrismTri<P, R>* o) {
     for (int d = 0; d < 2; ++d) o->qp[q][d] = R(T.qp[2 * q + d]);
 }
 
+template <int P>
+static void pack_disu(const RefElem& r, PrismDisuTab<P>* o) {
+  constexpr int n = P + 1, NT = (P + 1) * (P + 2) / 2;
+  const Tri& T = r.tri;
+  for (int i = 0; i < n; ++i) {
+    o->lb[i] = r.line.lb[i];
+    o->rb[i] = r.line.rb[i];
+    for (int j = 0; j < n; ++j) o->D[i][j] = r.line.D[i * n + j];
+  }
+  for (int e = 0; e < 3; ++e)
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < NT; ++t) o->Tedge[e][i][t] = T.Tedge[(e * n + i) * NT + t];
+  for (int a = 0; a < NT; ++a)
+    for (int b = 0; b < NT; ++b) {
+      o->Dxi[a][b] = T.Dxi[a * NT + b];
+      o->Deta[a][b] = T.Deta[a * NT + b];
+    }
+}
+
+template <int P, typename R>
+static size_t prism_bytes_t() {
+  return prism_disu_offset<P, R>() + sizeof(PrismDisuTab<P>);
+}
+
+template <int P, typename R>
+static void prism_pack_t(const RefElem& r, void* dst) {
+  pack_tri<P, R>(r.tri, (PrismTri<P, R>*)dst);
+  pack_disu<P>(r, (PrismDisuTab<P>*)((char*)dst + prism_disu_offset<P, R>()));
+}
+
+// the device table of one order and precision: the prism operators in the
+// working precision, then the double-precision disu operators
 size_t prism_ops_bytes(int p, int prec) {
   const bool d = prec == 0;
   switch (p) {
-    case 1: return d ? sizeof(PrismTri<1, double>) : sizeof(PrismTri<1, float>);
-    case 2: return d ? sizeof(PrismTri<2, double>) : sizeof(PrismTri<2, float>);
-    case 3: return d ? sizeof(PrismTri<3, double>) : sizeof(PrismTri<3, float>);
-    case 4: return d ? sizeof(PrismTri<4, double>) : sizeof(PrismTri<4, float>);
+    case 1: return d ? prism_bytes_t<1, double>() : prism_bytes_t<1, float>();
+    case 2: return d ? prism_bytes_t<2, double>() : prism_bytes_t<2, float>();
+    case 3: return d ? prism_bytes_t<3, double>() : prism_bytes_t<3, float>();
+    case 4: return d ? prism_bytes_t<4, double>() : prism_bytes_t<4, float>();
   }
   return 0;
 }
@@ -1459,26 +1587,11 @@ size_t prism_ops_bytes(int p, int prec) {
 void prism_ops_pack(const RefElem& r, int prec, void* dst) {
   const bool d = prec == 0;
   switch (r.p) {
-    case 1: d ? pack_tri<1, double>(r.tri, (PrismTri<1, double>*)dst) : pack_tri<1, float>(r.tri, (PrismTri<1, float>*)dst); break;
-    case 2: d ? pack_tri<2, double>(r.tri, (PrismTri<2, double>*)dst) : pack_tri<2, float>(r.tri, (PrismTri<2, float>*)dst); break;
-    case 3: d ? pack_tri<3, double>(r.tri, (PrismTri<3, double>*)dst) : pack_tri<3, float>(r.tri, (PrismTri<3, float>*)dst); break;
-    case 4: d ? pack_tri<4, double>(r.tri, (PrismTri<4, double>*)dst) : pack_tri<4, float>(r.tri, (PrismTri<4, float>*)dst); break;
+    case 1: d ? prism_pack_t<1, double>(r, dst) : prism_pack_t<1, float>(r, dst); break;
+    case 2: d ? prism_pack_t<2, double>(r, dst) : prism_pack_t<2, float>(r, dst); break;
+    case 3: d ? prism_pack_t<3, double>(r, dst) : prism_pack_t<3, float>(r, dst); break;
+    case 4: d ? prism_pack_t<4, double>(r, dst) : prism_pack_t<4, float>(r, dst); break;
   }
-}
-
-template <typename R>
-static Gas<R> make_gas_p(const GasHost& g) {
-  Gas<R> o;
-  o.gamma = R(g.gamma);
-  o.gm1 = R(g.gamma - 1.0);
-  o.mu = R(g.mu);
-  o.muh = R(g.mu * g.gamma / g.prandtl);
-  o.pref = R(g.pref);
-  o.eref = R(g.pref / (g.gamma - 1.0));
-  o.href = R(g.gamma * g.pref / (g.gamma - 1.0));
-  o.beta = R(g.beta);
-  o.tau = R(g.tau);
-  return o;
 }
 
 // launch shapes of the volume kernel: two threads per quadrature column
@@ -1507,21 +1620,25 @@ struct PrismSurf {
 template <int P, typename R, bool BT>
 static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   const PrismOps<P, R> op = make_prism_ops<P, R>(*a.ops);
-  const Gas<R> g = make_gas_p<R>(*a.gas);
+  // affine prisms take the mass flux and the linear energy-flux part from
+  // the double-precision L(rho v) of the disu kernel
+  const bool lin = !a.warp;
+  const Gas<R> g = make_gas<R>(*a.gas, lin);
   const PrismTri<P, R>* tri = (const PrismTri<P, R>*)a.dops;
+  const PrismDisuTab<P>* dtab = (const PrismDisuTab<P>*)((const char*)a.dops + prism_disu_offset<P, R>());
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EB = PrismLaunch<P, dbl>::EB, NT = PrismLaunch<P, dbl>::NT;
   constexpr int EBA = PRISM_DISU_EB, NTA = 256, EBC = PrismSurf<P, dbl>::EB, NTC = 256;
-  const double eref = a.gas->pref / (a.gas->gamma - 1.0);
+  const double eref = a.gas->pref / (a.gas->gamma - 1.0), rho0 = a.gas->rho_ref;
   if ((a.stage & 1) && grid[K_DISU] > 0)
     hipLaunchKernelGGL((prism_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
-                       a.segs, a.from_ust, op, tri, eref);
+                       a.segs, a.from_ust, dtab, eref, rho0, lin);
   // curved prisms (single meshes only; flux anti-aliasing, general metric)
   if constexpr (!BT) {
     if (a.warp) {
       if ((a.stage & 2) && grid[K_VOLUME] > 0)
         hipLaunchKernelGGL((prism_volume<P, R, EB, NT, false, true, false, true>), dim3(grid[K_VOLUME]), dim3(NT), 0,
-                           st, a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+                           st, a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref, rho0);
       if ((a.stage & 4) && grid[K_SURFACE] > 0)
         hipLaunchKernelGGL((prism_surface<P, R, EBC, NTC, false, false, true>), dim3(grid[K_SURFACE]), dim3(NTC), 0,
                            st, a.one, a.bt[K_SURFACE], a.segs, a.rk, op, tri, g);
@@ -1533,13 +1650,13 @@ static void prism_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
     // only (the paper's "full AA"); the library rejects it without
     if (a.saa)
       hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, true, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref, rho0);
     else if (a.aa)
       hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, true, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st, a.one,
-                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+                         a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref, rho0);
     else
       hipLaunchKernelGGL((prism_volume<P, R, EB, NT, BT, false, false, false>), dim3(grid[K_VOLUME]), dim3(NT), 0, st,
-                         a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref);
+                         a.one, a.bt[K_VOLUME], a.segs, a.from_ust, op, tri, g, eref, rho0);
   }
   if ((a.stage & 4) && grid[K_SURFACE] > 0) {
     if (a.saa)

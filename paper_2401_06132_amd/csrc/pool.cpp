@@ -76,7 +76,7 @@ class Arena {
 // byte offsets of one request's arrays inside its arena block
 struct Layout {
   int64_t nel[fr::NTYPES] = {}, nu[2] = {0, 0}, n_state = 0, nslots = 0, nfp = 0;
-  size_t state = 0, ust = 0, acc = 0, Rp = 0, Uf = 0, Vf = 0, faces = 0, fgeo = 0, perms = 0;
+  size_t state = 0, ust = 0, acc = 0, Rp = 0, Uf = 0, Ub = 0, Vf = 0, faces = 0, fgeo = 0, perms = 0;
   size_t met[2] = {0, 0}, detj[2] = {0, 0}, total = 0;
 };
 
@@ -100,6 +100,7 @@ Layout make_layout(const fr_request& q, int rs) {
   L.acc = take(8 * L.n_state);
   L.Rp = take((size_t)rs * L.n_state);
   L.Uf = take((size_t)rs * L.nslots * 5 * L.nfp);
+  if (rs == 4) L.Ub = take(sizeof(float) * 5 * L.nslots);  // single precision: face bases
   L.Vf = take((size_t)rs * L.nslots * 4 * L.nfp);
   L.faces = take(sizeof(fr::FaceRec) * L.nslots);
   L.fgeo = take((size_t)rs * 4 * L.nslots);
@@ -420,6 +421,7 @@ fr_status admit(fr_pool* P, Req& R) {
     g.acc = (double*)(b + L.acc) + off;
     g.du = nullptr;
     g.Uf = b + L.Uf;
+    g.Ub = P->rs == 4 ? (float*)(b + L.Ub) : nullptr;
     g.Vf = b + L.Vf;
     g.Rp = b + L.Rp + (size_t)P->rs * off;
     g.faces = (const fr::FaceRec*)(b + L.faces);
@@ -576,7 +578,7 @@ fr_status fr_pool_create(const fr_physics* ph, void* stream, int64_t budget_byte
   P->budget = budget_bytes;
   P->max_active = max_active;
   P->rs = ph->prec == FR_PREC_FP64 ? 8 : 4;
-  P->gas = {ph->gamma, ph->prandtl, ph->mu, ph->pref, ph->ldg_beta, ph->ldg_tau};
+  P->gas = {ph->gamma, ph->prandtl, ph->mu, ph->pref, ph->ldg_beta, ph->ldg_tau, ph->rho_ref};
   *out = P;
   return FR_OK;
 }

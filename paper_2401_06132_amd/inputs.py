@@ -22,6 +22,7 @@ import numpy as np
 GAMMA = 1.4
 MACH = 0.1
 P0 = 1.0 / (GAMMA * MACH * MACH)
+RHO0 = 1.0  # mean density of the vortex
 
 
 def tgv_state(xyz, gamma=GAMMA, p0=P0):

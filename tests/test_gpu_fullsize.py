@@ -4,7 +4,7 @@ The full right-hand side is computed on the GPU (same library call and
 launch configuration as bench.py); the oracle evaluates the RHS of a random
 sample of elements (rhs_subset: the two-hop neighbourhood of each sampled
 element), in extended precision.  Tolerances as in test_gpu_parity.py:
-fused FP64 1e-12, plain FP64 2e-12, FP32 1e-3 (per variable, relative to the
+fused and plain FP64 1e-12, FP32 2e-5 (per variable, relative to the
 sample's max).  Besides the benchmark configurations (hexahedra, prisms,
 the mixed mesh), the tetrahedron, pyramid and four-type meshes that the
 benchmark also times run here at 48^3 cells in FP32 (the matrix-core volume
@@ -50,7 +50,7 @@ def test_fullsize_sampled_parity(kind, n, p, prec):
     form = "plain" if prec == "plain" else "fused"
     aa = not prec.endswith("_noaa")
     prec = prec.replace("_noaa", "")
-    s = frmi.Solver(n, p, kind, prec="fp64" if prec == "plain" else prec, form=form, pref=inputs.P0, aa=aa)
+    s = frmi.Solver(n, p, kind, prec="fp64" if prec == "plain" else prec, form=form, pref=inputs.P0, rho_ref=inputs.RHO0, aa=aa)
     lib_xyz = s.upts_coords()
     for t, x in zip(m.types, lib_xyz):
         np.testing.assert_allclose(x[::997], m.upts_coords(t)[::997], atol=1e-12)
@@ -65,11 +65,7 @@ def test_fullsize_sampled_parity(kind, n, p, prec):
     Uo = {t: x for t, x in zip(m.types, U)}
     ref = rhs_subset(m, {t: x.astype(np.longdouble) for t, x in Uo.items()}, Params(pref=inputs.P0, aa=aa), sel,
                      dtype=np.longdouble)
-    # the plain comparison path applies the dense (M1 - M3 M2) M9 operator,
-    # summing 3 N_q terms of the ~250-magnitude energy flux per output; its
-    # float64 rounding reaches ~1.1e-12 on the energy equation (measured), so
-    # it is held to 2e-12; the fused FP64 path is held to 1e-12
-    tol = 1e-3 if prec == "fp32" else (2e-12 if prec == "plain" else 1e-12)
+    tol = 2e-5 if prec == "fp32" else 1e-12
     for t, g in zip(m.types, got):
         r = ref[t]
         err = (np.abs(g[sel[t]] - r).max(axis=(0, 2)) / np.abs(r).max(axis=(0, 2))).astype(np.float64)

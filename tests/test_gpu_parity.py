@@ -5,10 +5,12 @@ Tolerances (per conserved variable, ||du_gpu - du_ref||_inf / ||du_ref||_inf),
 where du_ref is the oracle evaluated in extended precision (longdouble):
   * FP64: 1e-12 flat, on every mesh and order.  The oracle's own float64
     evaluation is printed beside the GPU error for comparison only.
-  * FP32: 1e-3.  Derived from the arithmetic: the 1e-3 noise makes the RHS
-    ~1e3 times smaller than flux magnitude times derivative-operator norm, so
-    single-precision rounding (6e-8) is amplified to ~1e-4; the oracle run in
-    float32 lands at 3e-5..4e-4 (tests/test_oracle_rhs.py).
+  * FP32: 2e-5 (the single-precision bulk with double-precision state,
+    reference subtraction, face values, mass-flux divergence L(rho v) and
+    final division).  Curved elements keep the unsplit energy flux (the
+    linear part's divergence is not a polynomial identity there), so their
+    FP32 energy error is set by the ~250-magnitude energy flux in single
+    precision: measured 4.8e-5 at most, held to 1e-4.
 """
 
 import numpy as np
@@ -22,7 +24,8 @@ from paper_2401_06132_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-3}
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+TOL_CURVED_FP32 = 1e-4
 
 
 def _need_gpu():
@@ -44,8 +47,8 @@ def _rel_err(got, ref):
     return np.max(out, axis=0)
 
 
-def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0, form="fused", aa=True, surface_aa=False):
-    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref, form=form, aa=aa, surface_aa=surface_aa)
+def _gpu_rhs(dims, p, kind, prec, U, pref=inputs.P0, rho_ref=inputs.RHO0, form="fused", aa=True, surface_aa=False):
+    s = frmi.Solver(dims, p, kind, prec=prec, pref=pref, rho_ref=rho_ref, form=form, aa=aa, surface_aa=surface_aa)
     flat = np.concatenate([u.reshape(-1) for u in U])
     u = torch.from_numpy(flat).cuda()
     du = torch.empty_like(u)
@@ -107,12 +110,12 @@ def test_fused_matches_plain_on_gpu(kind):
     ragged last block), FP64."""
     _need_gpu()
     dims = (5, 3, 4)
-    s = frmi.Solver(dims, 3, kind, pref=inputs.P0)
+    s = frmi.Solver(dims, 3, kind, pref=inputs.P0, rho_ref=inputs.RHO0)
     U = inputs.element_state(s.upts_coords(), seed=3)
     flat = torch.from_numpy(np.concatenate([u.reshape(-1) for u in U])).cuda()
     a, b = torch.empty_like(flat), torch.empty_like(flat)
     s.rhs(flat, a)
-    sp = frmi.Solver(dims, 3, kind, pref=inputs.P0, form="plain")
+    sp = frmi.Solver(dims, 3, kind, pref=inputs.P0, rho_ref=inputs.RHO0, form="plain")
     sp.rhs(flat, b)
     torch.cuda.synchronize()
     for x, y in zip(s.split(a.cpu().numpy()), s.split(b.cpu().numpy())):
@@ -124,7 +127,7 @@ def test_fused_matches_plain_on_gpu(kind):
 def test_free_stream_and_conservation_gpu():
     _need_gpu()
     dims, p = (3, 2, 2), 3
-    s = frmi.Solver(dims, p, "hex", pref=inputs.P0)
+    s = frmi.Solver(dims, p, "hex", pref=inputs.P0, rho_ref=inputs.RHO0)
     U = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U])).cuda()
     du = torch.empty_like(u)
@@ -145,7 +148,7 @@ def test_rk4_parity_tgv_c1(form):
     Uo = {"hex": U[0]}
     for _ in range(10):
         Uo = oracle_rk4(m, Uo, par, 1e-3)
-    s = frmi.Solver(dims, p, "hex", pref=inputs.P0, form=form)
+    s = frmi.Solver(dims, p, "hex", pref=inputs.P0, rho_ref=inputs.RHO0, form=form)
     s.set_state(U[0])
     c0 = s.integrals()
     s.rk4(1e-3, 10)
@@ -246,7 +249,7 @@ def test_full_aa_free_stream_conservation_and_rk4(kind):
     common flux in its own frame, so conservation holds to rounding)."""
     _need_gpu()
     dims, p = (3, 2, 2), 3
-    s = frmi.Solver(dims, p, kind, pref=inputs.P0, surface_aa=True)
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0, rho_ref=inputs.RHO0, surface_aa=True)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
     du = torch.empty_like(u)
@@ -299,7 +302,7 @@ def test_rhs_parity_tets_and_pyramids(dims, p, kind, prec):
 def test_dense_free_stream_conservation_and_rk4(kind):
     _need_gpu()
     dims, p = (2, 2, 3 if kind.endswith("pyr_tet") else 2), 3
-    s = frmi.Solver(dims, p, kind, pref=inputs.P0)
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0, rho_ref=inputs.RHO0)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
     du = torch.empty_like(u)
@@ -341,7 +344,7 @@ def test_rhs_parity_curved_elements(dims, p, kind, prec):
     got, _ = _gpu_rhs(dims, p, kind, prec, U)
     err = _rel_err(got, rld).astype(np.float64)
     own = _rel_err(r64, rld).astype(np.float64)
-    tol = TOL[prec]
+    tol = TOL_CURVED_FP32 if prec == "fp32" else TOL[prec]
     print("rel err per variable", err, "oracle float64 rounding", own, flush=True)
     assert np.all(err < tol), (err, tol)
 
@@ -350,7 +353,7 @@ def test_rhs_parity_curved_elements(dims, p, kind, prec):
 def test_curved_free_stream_conservation_and_rk4(kind):
     _need_gpu()
     dims, p = (3, 2, 3), 3
-    s = frmi.Solver(dims, p, kind, pref=inputs.P0)
+    s = frmi.Solver(dims, p, kind, pref=inputs.P0, rho_ref=inputs.RHO0)
     U0 = inputs.uniform_state([(E, nu) for _, E, nu in s.blocks()])
     u = torch.from_numpy(np.concatenate([x.reshape(-1) for x in U0])).cuda()
     du = torch.empty_like(u)

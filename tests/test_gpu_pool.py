@@ -50,7 +50,7 @@ def _drain(pool, budget=None, max_active=None):
 def test_pool_tgv_initial_state(kind, n, p):
     _need_gpu()
     print("pool tgv init", kind, n, p, flush=True)
-    pool = frmi.Pool(1 << 28, prec="fp64", pref=inputs.P0)
+    pool = frmi.Pool(1 << 28, prec="fp64", pref=inputs.P0, rho_ref=inputs.RHO0)
     _, ns = pool.footprint(n=n, p=p, kind=kind, tgv_p0=inputs.P0)
     out = np.full(ns, np.nan)
     pool.submit(n=n, p=p, kind=kind, nsteps=0, tgv_p0=inputs.P0, u_out=out)
@@ -68,11 +68,11 @@ def test_pool_equals_rk4_step(kind, n, p, prec):
     print("pool vs rk4", kind, n, p, prec, flush=True)
     u0 = _init(n, p, kind, seed=3)
     dt, steps = 2e-4, 5
-    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0)
+    s = frmi.Solver(n, p, kind, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
     s.set_state(u0)
     s.rk4(dt, steps)
     ref = s.get_state()
-    pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0)
+    pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
     out = np.empty_like(u0)
     pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
     _drain(pool)
@@ -98,7 +98,7 @@ def test_pool_solo_equals_batched(prec):
     solo = []
     for i, ((n, p, kind, steps), u0) in enumerate(zip(mix, inits)):
         print("solo", i, n, p, kind, steps, prec, flush=True)
-        pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0)
+        pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
         out = np.empty_like(u0)
         pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
         _drain(pool)
@@ -106,12 +106,12 @@ def test_pool_solo_equals_batched(prec):
     # batched: a budget that holds about a third of the mix and 4 slots, so
     # requests queue and are admitted as others finish; half the requests are
     # submitted after the first rounds (arrivals while others run)
-    pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0)
+    pool = frmi.Pool(1 << 28, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
     fp = [pool.footprint(n=n, p=p, kind=kind, tgv_p0=1.0)[0] for n, p, kind, _ in mix]
     budget = max(max(fp), sum(fp) // 3)
     max_active = 4
     print("batched", prec, "budget", budget, flush=True)
-    pool = frmi.Pool(budget, max_active=max_active, prec=prec, pref=inputs.P0)
+    pool = frmi.Pool(budget, max_active=max_active, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0)
     outs = [np.full_like(u, np.nan) for u in inits]
     half = len(mix) // 2
     for i in range(half):
@@ -140,7 +140,7 @@ def test_pool_matches_oracle():
     for _ in range(steps):
         Uo = oracle_rk4(m, Uo, par, dt)
     u0 = np.concatenate([u.reshape(-1) for u in U])
-    pool = frmi.Pool(1 << 28, prec="fp64", pref=inputs.P0)
+    pool = frmi.Pool(1 << 28, prec="fp64", pref=inputs.P0, rho_ref=inputs.RHO0)
     out = np.empty_like(u0)
     pool.submit(n=dims, p=p, kind="mixed", nsteps=steps, dt=dt, u_init=u0, u_out=out)
     _drain(pool)
@@ -160,11 +160,11 @@ def test_pool_without_anti_aliasing_equals_rk4_step(kind):
     _need_gpu()
     n, p, steps, dt = (3, 2, 4), 3, 4, 2e-4
     u0 = _init(n, p, kind, seed=4)
-    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, aa=False)
+    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, rho_ref=inputs.RHO0, aa=False)
     s.set_state(u0)
     s.rk4(dt, steps)
     ref = s.get_state()
-    pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, aa=False)
+    pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, rho_ref=inputs.RHO0, aa=False)
     out = np.empty_like(u0)
     pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
     _drain(pool)
@@ -180,11 +180,11 @@ def test_pool_full_anti_aliasing_equals_rk4_step(kind):
     _need_gpu()
     n, p, steps, dt = (3, 2, 4), 3, 4, 2e-4
     u0 = _init(n, p, kind, seed=5)
-    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, surface_aa=True)
+    s = frmi.Solver(n, p, kind, prec="fp32", pref=inputs.P0, rho_ref=inputs.RHO0, surface_aa=True)
     s.set_state(u0)
     s.rk4(dt, steps)
     ref = s.get_state()
-    pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, surface_aa=True)
+    pool = frmi.Pool(1 << 28, prec="fp32", pref=inputs.P0, rho_ref=inputs.RHO0, surface_aa=True)
     out = np.empty_like(u0)
     pool.submit(n=n, p=p, kind=kind, nsteps=steps, dt=dt, u_init=u0, u_out=out)
     pool.submit(n=(2, 3, 2), p=2, kind="prism", nsteps=3, dt=dt, tgv_p0=inputs.P0)

@@ -178,27 +178,21 @@ def test_reference_state_form_is_the_accurate_one(kind):
     operators.  Against an extended-precision evaluation (longdouble
     arithmetic; both forms are the same function), the float64
     reference-state form is accurate to < 5e-13 relative per variable while
-    the float64 textbook form is several times worse.  The same comparison
-    in float32 measures what single-precision arithmetic can reach on this
-    input: ~1e-4, set by the 1e-3 noise (the RHS is ~1e3 times smaller than
-    flux times derivative-operator norm), so no float32 evaluation of this
-    algorithm meets 2e-5."""
+    the float64 textbook form is several times worse.  (What single precision
+    reaches is measured with the kernels' own split in test_fp32_split.py.)"""
     m = Mesh(2, 2, 2, 2, kind)
     U = {t: u for t, u in zip(m.types, inputs.element_state([m.upts_coords(t) for t in m.types]))}
     ref = rhs(m, {t: U[t].astype(np.longdouble) for t in m.types}, Params(pref=inputs.P0), dtype=np.longdouble)
     good = rhs(m, U, Params(pref=inputs.P0))
     plain = rhs(m, U, Params(pref=0.0))
-    single = rhs(m, U, Params(pref=inputs.P0), dtype=np.float32)
-    eg, ep, es = [], [], []
+    eg, ep = [], []
     for t in m.types:
         sc = np.abs(ref[t]).max(axis=(0, 2))
         eg.append((np.abs(good[t] - ref[t]).max(axis=(0, 2)) / sc).astype(np.float64))
         ep.append((np.abs(plain[t] - ref[t]).max(axis=(0, 2)) / sc).astype(np.float64))
-        es.append((np.abs(single[t] - ref[t]).max(axis=(0, 2)) / sc).astype(np.float64))
-    eg, ep, es = np.max(eg), np.max(ep), np.max(es)
+    eg, ep = np.max(eg), np.max(ep)
     assert eg < 5e-13
     assert ep > 3 * eg
-    assert 2e-5 < es < 1e-3
 
 
 def test_rk4_fourth_order_in_time():

@@ -19,6 +19,8 @@ def _expected_bytes(n, p, kind, rs):
     slots = 6 * ne[0] + 5 * ne[1]
     parts = [8 * ns, 8 * ns, 8 * ns, rs * ns, rs * slots * 5 * k * k, rs * slots * 4 * k * k, 8 * slots,
              rs * 4 * slots, 16 * k * k]
+    if rs == 4:
+        parts.append(4 * 5 * slots)  # single precision: one float base per face and variable
     for t in range(2):
         parts += [rs * 10 * ne[t], 8 * ne[t]]
     return sum(al(x) for x in parts), ns

@@ -188,6 +188,39 @@ fr_status fr_create(const fr_physics* ph, void* hip_stream, fr_ctx** out);
  * built). */
 fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, int p, int kind);
 
+/* Build a general conforming mesh of affine elements from caller vertices
+ * (section 2.1: every element is the image of its reference element under
+ * its own mapping, eqs. transall and govqtrans; here an affine one, fitted
+ * to the element's vertices).  Faces are paired by their centroids modulo
+ * the period lattice and their flux points by coordinates (paired flux
+ * points coincide in physical space); of each pair, L is the element earlier
+ * in library order, and for an element paired with itself the face with the
+ * lexicographically smaller centroid.
+ *   p        order 1..4
+ *   n_elem   4 counts: hexahedra, prisms, tetrahedra, pyramids (each >= 0,
+ *            total > 0); the library order of the state is this order
+ *   verts    4 pointers (host), verts[t] = n_elem[t] x nv x 3 doubles
+ *            (row-major), may be NULL where n_elem[t] = 0.  Vertex orders:
+ *              hexahedron (nv 8): vertex a + 2b + 4c at reference corner
+ *                (2a-1, 2b-1, 2c-1);
+ *              prism (nv 6): vertex t + 3c at triangle vertex t of
+ *                (-1,-1), (1,-1), (-1,1) and zeta = 2c-1;
+ *              tetrahedron (nv 4): (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1);
+ *              pyramid (nv 5): base corners a + 2b at (2a-1, 2b-1, -1), then
+ *                the apex (0, 0, 1).
+ *   period   9 doubles (host), the three period vectors of a periodic mesh
+ *            (row-major, one vector per row), or NULL for no periodicity.
+ * Copied; the caller keeps ownership.  Host-side only, like fr_mesh_box.
+ * Errors: FR_EINVAL (null pointers, negative counts, an element that is not
+ * the affine image of its reference element or has a non-positive Jacobian,
+ * a face that pairs with no other face or with more than one, flux points
+ * that do not coincide), FR_EUNSUPPORTED (p outside 1..4, surface-flux
+ * anti-aliasing with tetrahedra or pyramids or with prism triangle faces
+ * that are not aligned, more than 16 distinct face-point permutations),
+ * FR_ESTATE (mesh already built). */
+fr_status fr_mesh_elements(fr_ctx* c, int p, const int64_t* n_elem, const double* const* verts,
+                           const double* period);
+
 /* Sizes of the library layout: number of hexahedra, of prisms, and the total
  * number of doubles of a state vector.  Any pointer may be NULL. */
 fr_status fr_layout(const fr_ctx* c, int64_t* n_hex, int64_t* n_prism, int64_t* n_state);

@@ -102,6 +102,69 @@ _REF_VERTS = {
 }
 
 
+# reference vertices of the affine element types, in the order in which a
+# general mesh lists an element's vertices (hexahedra and prisms as above;
+# tetrahedra V0..V3; pyramids the base corners a + 2b at (2a-1, 2b-1, -1),
+# then the apex)
+REF_VERTS = {
+    "hex": _REF_VERTS["hex"],
+    "prism": _REF_VERTS["prism"],
+    "tet": np.array([[-1.0, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]]),
+    "pyr": np.array([[-1.0, -1, -1], [1, -1, -1], [-1, 1, -1], [1, 1, -1], [0, 0, 1]]),
+}
+
+
+def elements_mesh(p, verts, lattice=None, surf_aa=False):
+    """A conforming mesh of affine elements from their vertices (section 2.1:
+    each element is the image of its reference element under its own
+    mapping, eqs. transall / govqtrans; here an affine one per element).
+
+    verts: dict type -> (E_t, nv, 3) vertex coordinates in the order of
+    REF_VERTS; element order (and so the global id that decides L/R) is
+    hexahedra, prisms, tetrahedra, pyramids, each in the given order.
+    lattice: (3, 3) period vectors (rows) of a periodic mesh, or None.  A
+    vertex set that is not the affine image of the reference element raises
+    ValueError, as does a face that pairs with no other."""
+    types = [t for t in ("hex", "prism", "tet", "pyr") if t in verts and len(verts[t])]
+    m = Mesh.__new__(Mesh)
+    m.p, m.kind, m.curved = p, "elements", False
+    allv = np.concatenate([np.asarray(verts[t], float).reshape(-1, 3) for t in types])
+    m.lo = allv.min(axis=0)
+    m.hi = allv.max(axis=0)
+    if lattice is None:
+        # no period: a lattice far larger than the mesh never wraps a face
+        lattice = np.diag(4.0 * (m.hi - m.lo) + 1.0)
+    m.lattice = np.asarray(lattice, float)
+    m.period = None
+    m.refs = {t: RefElement(t, p, None, surf_aa=surf_aa) for t in types}
+    m.types = types
+    m.org, m.J, m.gid, m.nelem = {}, {}, {}, {}
+    g = 0
+    hmin = np.inf
+    for t in types:
+        X = np.asarray(verts[t], float)
+        ref = REF_VERTS[t]
+        A = np.concatenate([np.ones((len(ref), 1)), ref], axis=1)  # [1, xi]
+        coef = np.einsum("ij,ejk->eik", np.linalg.pinv(A), X)  # (E, 4, 3): org, then J^T rows
+        org, J = coef[:, 0, :], np.transpose(coef[:, 1:, :], (0, 2, 1))
+        fit = org[:, None, :] + np.einsum("eij,vj->evi", J, ref)
+        size = np.linalg.norm(X.max(axis=1) - X.min(axis=1), axis=1)
+        if np.any(np.abs(fit - X).max(axis=(1, 2)) > 1e-10 * size):
+            raise ValueError("elements must be affine images of the reference element")
+        m.org[t], m.J[t] = org, J
+        m.gid[t] = g + np.arange(len(X))
+        g += len(X)
+        m.nelem[t] = len(X)
+        hmin = min(hmin, float(np.linalg.norm(J, axis=1).min()))
+    m.h = np.full(3, hmin)
+    m.detJ = {t: np.linalg.det(m.J[t]) for t in types}
+    m.Jinv = {t: np.linalg.inv(m.J[t]) for t in types}
+    if any(np.any(m.detJ[t] <= 0) for t in types):
+        raise ValueError("non-positive Jacobian")
+    m._pair()
+    return m
+
+
 def _kuhn_tets(x0, h):
     """Vertices (4, 3) of the six tetrahedra of the cell at x0 (see the
     module header), each with a positive orientation."""
@@ -176,6 +239,7 @@ class Mesh:
         self.lo, self.hi = lo, hi
         L = hi - lo
         self.period = np.array([L, L, L])
+        self.lattice = np.diag(self.period)  # period vectors (rows)
         h = np.array([L / nx, L / ny, L / nz])
         self.h = h
         self.curved = kind.endswith("_warp")
@@ -361,16 +425,19 @@ class Mesh:
         # per flat flux point: element type index and element
         self.ftype = np.concatenate([np.full(self.nelem[t] * self.refs[t].nf, i) for i, t in enumerate(self.types)])
         self.felem = np.concatenate([np.repeat(np.arange(self.nelem[t]), self.refs[t].nf) for t in self.types])
-        # faces: match by centroid modulo the period, then points within a face pair
+        # faces: match by centroid modulo the period lattice (rows of
+        # self.lattice; coordinates taken in lattice units), then points
+        # within a face pair
         fkeys, finfo, fcent = [], [], []
         Qk = 1 << 24
+        Binv = np.linalg.inv(self.lattice.T)  # physical -> lattice coordinates
         for ti, t in enumerate(self.types):
             r = self.refs[t]
             E = self.nelem[t]
             c = np.stack([self.phys(t, r.fpts[r.fface == f]).mean(axis=1) for f in range(r.nfaces)],
                          axis=1).reshape(-1, 3)
             fcent.append(c)
-            fkeys.append(np.mod(np.rint((c - self.lo) / self.period * Qk).astype(np.int64), Qk))
+            fkeys.append(np.mod(np.rint(((c - self.lo) @ Binv.T) * Qk).astype(np.int64), Qk))
             finfo.append(np.stack([np.full(E * r.nfaces, ti), np.repeat(np.arange(E), r.nfaces),
                                    np.tile(np.arange(r.nfaces), E), np.repeat(self.gid[t], r.nfaces)], axis=1))
         key, info, cent = np.concatenate(fkeys), np.concatenate(finfo), np.concatenate(fcent)
@@ -417,7 +484,8 @@ class Mesh:
                 j = np.empty_like(oL)
                 np.put_along_axis(j, oL, oR, axis=1)
                 d = XL - np.take_along_axis(XR, j[:, :, None], axis=1)
-                d -= self.period * np.rint(d / self.period)
+                dl = d @ Binv.T
+                d = (dl - np.rint(dl)) @ self.lattice
                 if np.abs(d).max() > 1e-9 * self.h.min():
                     raise ValueError("flux points of paired faces do not coincide")
                 iL.append((self.foff[tL] + eL[:, None] * rL.nf + pl[None, :]).reshape(-1))

@@ -26,7 +26,7 @@ FORM = {"fused": 0, "plain": 1}
 _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE", -5: "FR_EUNSUPPORTED"}
 
 # every symbol the header declares
-SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
+SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_mesh_elements", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
            "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
            "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
            "fr_pool_events", "fr_pool_query", "fr_pool_last_error", "fr_pool_destroy"]
@@ -73,6 +73,7 @@ def load_library(path=None):
         "fr_physics_default": (None, [ctypes.POINTER(FrPhysics)]),
         "fr_create": (I, [ctypes.POINTER(FrPhysics), P, ctypes.POINTER(P)]),
         "fr_mesh_box": (I, [P, I, I, I, D, D, I, I]),
+        "fr_mesh_elements": (I, [P, I, P, P, P]),
         "fr_layout": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "fr_type_count": (I, [P, I, ctypes.POINTER(I64)]),
         "fr_upts_coords": (I, [P, P]),
@@ -132,16 +133,31 @@ def _check(ctx, st, pool=False):
 class Solver:
     """One flux-reconstruction context (mesh + operators + device buffers)."""
 
-    def __init__(self, n, p, kind="hex", prec="fp64", form="fused", lo=-np.pi, hi=np.pi, stream=None, **phys):
+    def __init__(self, n, p, kind="hex", prec="fp64", form="fused", lo=-np.pi, hi=np.pi, stream=None, verts=None,
+                 period=None, **phys):
+        """A periodic box (n cells per axis, or (nx, ny, nz), of mesh kind
+        `kind`), or with kind="elements" a general affine mesh: verts = dict
+        type name -> (E, nv, 3) vertex array (hex, prism, tet, pyr; vertex
+        orders as in fr_mesh_elements), period = (3, 3) period vectors or
+        None."""
         self.lib = load_library()
-        nx, ny, nz = (n, n, n) if np.isscalar(n) else n
         ph = physics(prec=prec, form=form, **phys)
         c = ctypes.c_void_p()
         st = None if stream is None else ctypes.c_void_p(stream)
         _check(None, self.lib.fr_create(ctypes.byref(ph), st, ctypes.byref(c)))
         self.ctx = c
         self.p, self.kind, self.prec = p, kind, prec
-        _check(self.ctx, self.lib.fr_mesh_box(self.ctx, nx, ny, nz, lo, hi, p, MESH_KIND[kind]))
+        if kind == "elements":
+            names = ("hex", "prism", "tet", "pyr")
+            arrs = [np.ascontiguousarray(verts[t], dtype=np.float64) if t in verts else None for t in names]
+            counts = (ctypes.c_int64 * 4)(*[0 if a is None else a.shape[0] for a in arrs])
+            ptrs = (ctypes.c_void_p * 4)(*[None if a is None else a.ctypes.data for a in arrs])
+            per = None if period is None else np.ascontiguousarray(period, dtype=np.float64).reshape(9)
+            _check(self.ctx, self.lib.fr_mesh_elements(self.ctx, p, counts, ptrs,
+                                                       None if per is None else per.ctypes.data))
+        else:
+            nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+            _check(self.ctx, self.lib.fr_mesh_box(self.ctx, nx, ny, nz, lo, hi, p, MESH_KIND[kind]))
         nh, npr, ns = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self.ctx, self.lib.fr_layout(self.ctx, ctypes.byref(nh), ctypes.byref(npr), ctypes.byref(ns)))
         self.n_hex, self.n_prism, self.n_state = nh.value, npr.value, ns.value

@@ -322,6 +322,41 @@ fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int r
   return FR_OK;
 }
 
+// operator pointers, per-type flags and the state layout of a new mesh
+fr_status setup_ctx_mesh(fr_ctx* c) {
+  for (int t = 0; t < fr::NTYPES; ++t) {
+    c->has[t] = c->M.nel[t] > 0;
+    const fr::RefElem& r = c->ref[t];
+    fr::HostOps& h = c->hops[t];
+    h.I = r.line.I.data();
+    h.D = r.line.D.data();
+    h.P = r.line.P.data();
+    h.AP = r.line.AP.data();
+    h.APu = r.line.APu.data();
+    h.lb = r.line.lb.data();
+    h.rb = r.line.rb.data();
+    h.liftL = r.line.liftL.data();
+    h.liftR = r.line.liftR.data();
+    h.tri = &r.tri;
+    h.ref = &r;
+    h.x = r.line.x.data();
+    h.xq = r.line.xq.data();
+  }
+  for (int t = 0; t < fr::NTYPES; ++t) {
+    bool d = c->has[t] && !c->M.curved;
+    for (int64_t e = 0; e < c->M.nel[t] && d; ++e) {
+      const double* A = &c->M.jac[t][9 * e];
+      d = A[1] == 0 && A[2] == 0 && A[3] == 0 && A[5] == 0 && A[6] == 0 && A[7] == 0;
+    }
+    c->diag[t] = d;
+  }
+  c->off[0] = 0;
+  for (int t = 1; t < fr::NTYPES; ++t) c->off[t] = c->off[t - 1] + c->M.nel[t - 1] * 5 * c->ref[t - 1].nu;
+  c->n_state = c->off[fr::NTYPES - 1] + c->M.nel[fr::NTYPES - 1] * 5 * c->ref[fr::NTYPES - 1].nu;
+  c->mesh_ok = true;
+  return FR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -385,37 +420,37 @@ fr_status fr_mesh_box(fr_ctx* c, int nx, int ny, int nz, double lo, double hi, i
   } catch (const std::exception& ex) {
     return fail(c, FR_EINVAL, ex.what());
   }
+  return setup_ctx_mesh(c);
+}
+
+fr_status fr_mesh_elements(fr_ctx* c, int p, const int64_t* n_elem, const double* const* verts,
+                           const double* period) {
+  if (!c) return FR_EINVAL;
+  if (c->mesh_ok) return fail(c, FR_ESTATE, "mesh already built");
+  if (!n_elem || !verts) return fail(c, FR_EINVAL, "null argument");
+  if (p < 1 || p > 4) return fail(c, FR_EUNSUPPORTED, "order must be 1..4");
+  int64_t total = 0;
   for (int t = 0; t < fr::NTYPES; ++t) {
-    c->has[t] = c->M.nel[t] > 0;
-    const fr::RefElem& r = c->ref[t];
-    fr::HostOps& h = c->hops[t];
-    h.I = r.line.I.data();
-    h.D = r.line.D.data();
-    h.P = r.line.P.data();
-    h.AP = r.line.AP.data();
-    h.APu = r.line.APu.data();
-    h.lb = r.line.lb.data();
-    h.rb = r.line.rb.data();
-    h.liftL = r.line.liftL.data();
-    h.liftR = r.line.liftR.data();
-    h.tri = &r.tri;
-    h.ref = &r;
-    h.x = r.line.x.data();
-    h.xq = r.line.xq.data();
+    if (n_elem[t] < 0 || (n_elem[t] > 0 && !verts[t])) return fail(c, FR_EINVAL, "bad element count or vertex array");
+    if (n_elem[t] > ((int64_t)1 << 30)) return fail(c, FR_EINVAL, "too many elements");
+    total += n_elem[t];
   }
-  for (int t = 0; t < fr::NTYPES; ++t) {
-    bool d = c->has[t] && !c->M.curved;
-    for (int64_t e = 0; e < c->M.nel[t] && d; ++e) {
-      const double* A = &c->M.jac[t][9 * e];
-      d = A[1] == 0 && A[2] == 0 && A[3] == 0 && A[5] == 0 && A[6] == 0 && A[7] == 0;
-    }
-    c->diag[t] = d;
+  if (total == 0) return fail(c, FR_EINVAL, "no elements");
+  if ((n_elem[2] > 0 || n_elem[3] > 0) && c->ph.surface_aa)
+    return fail(c, FR_EUNSUPPORTED, "tetrahedra and pyramids: no surface-flux anti-aliasing");
+  try {
+    c->p = p;
+    for (int t = 0; t < fr::NTYPES; ++t) fr::build_ref(t, p, c->ref[t]);
+    const fr::RefElem* refs[fr::NTYPES] = {&c->ref[0], &c->ref[1], &c->ref[2], &c->ref[3]};
+    std::string e = fr::build_element_mesh(p, n_elem, verts, period, refs, c->M);
+    if (!e.empty()) return fail(c, FR_EINVAL, e);
+    if ((int)c->M.perms.size() > fr::MAX_PERMS) return fail(c, FR_EUNSUPPORTED, "too many face permutations");
+    if (c->ph.surface_aa && !fr::prism_tri_faces_aligned(c->M))
+      return fail(c, FR_EUNSUPPORTED, "surface-flux anti-aliasing needs aligned prism triangle faces");
+  } catch (const std::exception& ex) {
+    return fail(c, FR_EINVAL, ex.what());
   }
-  c->off[0] = 0;
-  for (int t = 1; t < fr::NTYPES; ++t) c->off[t] = c->off[t - 1] + c->M.nel[t - 1] * 5 * c->ref[t - 1].nu;
-  c->n_state = c->off[fr::NTYPES - 1] + c->M.nel[fr::NTYPES - 1] * 5 * c->ref[fr::NTYPES - 1].nu;
-  c->mesh_ok = true;
-  return FR_OK;
+  return setup_ctx_mesh(c);
 }
 
 fr_status fr_layout(const fr_ctx* c, int64_t* nh, int64_t* np, int64_t* ns) {

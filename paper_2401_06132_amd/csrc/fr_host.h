@@ -88,7 +88,7 @@ constexpr double kWarp = 0.2;
 
 // Periodic box mesh with face connectivity.
 struct Mesh {
-  int nx = 0, ny = 0, nz = 0, p = 0, kind = 0;
+  int nx = 0, ny = 0, nz = 0, p = 0, kind = 0;  // kind -1: a mesh from element vertices
   double lo = 0, hi = 0;
   int64_t nel[NTYPES] = {};
   std::vector<double> org[NTYPES];    // element origin (x at reference 0)
@@ -130,5 +130,12 @@ bool prism_tri_faces_aligned(const Mesh& m);
 // Build the box mesh and its connectivity; returns an error string or "".
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
                            const RefElem* refs[NTYPES], Mesh& m);
+
+// Build a conforming mesh of affine elements from their vertices (n_elem[t]
+// elements of type t, verts[t] of n_elem[t] x nv x 3 doubles, the vertex
+// orders of fr_mesh_elements) with an optional period lattice (9 doubles, the
+// rows the period vectors; null: no period); returns an error string or "".
+std::string build_element_mesh(int p, const int64_t n_elem[NTYPES], const double* const verts[NTYPES],
+                               const double* period, const RefElem* refs[NTYPES], Mesh& m);
 
 }  // namespace fr

@@ -202,6 +202,9 @@ void jac_point(const Mesh& m, int t, int64_t e, const double* xi, double J[9]) {
   for (int k = 0; k < 9; ++k) J[k] = m.jac[t][9 * e + k];
 }
 
+static std::string finish_mesh(Mesh& M, const RefElem* refs[NTYPES], const double lat[9], const double lo3[3],
+                               double hmin);
+
 std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, int kind,
                            const RefElem* refs[NTYPES], Mesh& M) {
   M = Mesh();
@@ -362,6 +365,18 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
         }
     }
   }
+  const double lat[9] = {Lx, 0, 0, 0, Lx, 0, 0, 0, Lx};
+  const double lo3[3] = {lo, lo, lo};
+  return finish_mesh(M, refs, lat, lo3, std::min(h[0], std::min(h[1], h[2])));
+}
+
+// Metrics, face slots, face pairing by centroid modulo the period lattice
+// (lattice coordinates quantised to 2^-24 of a period), L/R, point
+// permutations and normals of a mesh whose elements are set (org, jac, gid,
+// verts).  lat: period vectors (rows); lo3: an origin of the quantisation;
+// hmin: the smallest element size (tolerances).
+static std::string finish_mesh(Mesh& M, const RefElem* refs[NTYPES], const double lat[9], const double lo3[3],
+                               double hmin) {
   for (int t = 0; t < NTYPES; ++t) {
     M.nel[t] = (int64_t)M.gid[t].size();
     M.jinv[t].resize(9 * M.nel[t]);
@@ -389,6 +404,25 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
   M.nslots = M.slot_base[NTYPES - 1] + M.nel[NTYPES - 1] * kFacesOf[NTYPES - 1];
   const int64_t S = M.nslots;
 
+  // lattice coordinates: c_lat = B (c - lo), B the inverse of the matrix
+  // whose columns are the period vectors
+  double B[9];
+  {
+    const double* L = lat;  // rows: period vectors; the matrix A = L^T
+    const double a0 = L[0], a1 = L[3], a2 = L[6], b0 = L[1], b1 = L[4], b2 = L[7], c0 = L[2], c1 = L[5], c2 = L[8];
+    // A = [[a0 a1 a2], [b0 b1 b2], [c0 c1 c2]] (columns = period vectors)
+    const double det = a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+    if (!(std::fabs(det) > 0)) return "degenerate period lattice";
+    B[0] = (b1 * c2 - b2 * c1) / det;
+    B[1] = (a2 * c1 - a1 * c2) / det;
+    B[2] = (a1 * b2 - a2 * b1) / det;
+    B[3] = (b2 * c0 - b0 * c2) / det;
+    B[4] = (a0 * c2 - a2 * c0) / det;
+    B[5] = (a2 * b0 - a0 * b2) / det;
+    B[6] = (b0 * c1 - b1 * c0) / det;
+    B[7] = (a1 * c0 - a0 * c1) / det;
+    B[8] = (a0 * b1 - a1 * b0) / det;
+  }
   // physical face points and centroids
   auto phys = [&](int t, int64_t e, const double* xi, double* x) { map_point(M, t, e, xi, x); };
   std::vector<double> cent(3 * S);
@@ -415,9 +449,10 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
       for (int d = 0; d < 3; ++d) c[d] += x[d] / R.face_npts[f];
     }
     std::array<int64_t, 4> k;
+    for (int d = 0; d < 3; ++d) cent[3 * s + d] = c[d];
     for (int d = 0; d < 3; ++d) {
-      cent[3 * s + d] = c[d];
-      int64_t v = (int64_t)std::llround((c[d] - lo) / Lx * Q);
+      const double cl = B[3 * d] * (c[0] - lo3[0]) + B[3 * d + 1] * (c[1] - lo3[1]) + B[3 * d + 2] * (c[2] - lo3[2]);
+      int64_t v = (int64_t)std::llround(cl * Q);
       v %= (int64_t)Q;
       if (v < 0) v += (int64_t)Q;
       k[d] = v;
@@ -497,15 +532,20 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
         double x[3], y[3];
         phys(t, e, &R.fpts[3 * (R.face_start[f] + q)], x);
         phys(to, eo, &RO.fpts[3 * (RO.face_start[fo] + r)], y);
+        // minimum image in lattice coordinates
+        double dl[3];
+        for (int d = 0; d < 3; ++d) {
+          dl[d] = B[3 * d] * (x[0] - y[0]) + B[3 * d + 1] * (x[1] - y[1]) + B[3 * d + 2] * (x[2] - y[2]);
+          dl[d] -= std::nearbyint(dl[d]);
+        }
         double d2 = 0;
         for (int d = 0; d < 3; ++d) {
-          double dd = x[d] - y[d];
-          dd -= Lx * std::nearbyint(dd / Lx);
+          const double dd = lat[d] * dl[0] + lat[3 + d] * dl[1] + lat[6 + d] * dl[2];
           d2 += dd * dd;
         }
         return d2;
       };
-      const double tol = 1e-9 * std::min(h[0], std::min(h[1], h[2])), tol2 = tol * tol;
+      const double tol = 1e-9 * hmin, tol2 = tol * tol;
       const int cls = ((t * 8 + f) * NTYPES + to) * 8 + fo;
       int pid = cls < (int)last.size() ? last[cls] : -1;
       if (pid >= 0) {
@@ -590,6 +630,103 @@ std::string build_box_mesh(int nx, int ny, int nz, double lo, double hi, int p, 
   }
   });
   return "";
+}
+
+// reference vertices of the affine element types, in the order in which
+// fr_mesh_elements lists an element's vertices
+static const double kElemRefV[NTYPES][8][3] = {
+    {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}, {1, 1, 1}},
+    {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}},
+    {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}},
+    {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}, {0, 0, 1}}};
+static constexpr int kElemNV[NTYPES] = {8, 6, 4, 5};
+
+std::string build_element_mesh(int p, const int64_t n_elem[NTYPES], const double* const verts[NTYPES],
+                               const double* period, const RefElem* refs[NTYPES], Mesh& M) {
+  M = Mesh();
+  M.p = p;
+  M.kind = -1;
+  double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+  double hmin = 1e300;
+  int64_t g = 0;
+  for (int t = 0; t < NTYPES; ++t) {
+    const int nv = kElemNV[t];
+    const double(*rv)[3] = kElemRefV[t];
+    // the affine fit x = org + J xi: least squares over the vertices (the
+    // normal equations of [1, xi] are exact here), then every vertex checked
+    double G[4][4] = {}, Gi[4][4];
+    for (int v = 0; v < nv; ++v) {
+      const double a[4] = {1, rv[v][0], rv[v][1], rv[v][2]};
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) G[i][j] += a[i] * a[j];
+    }
+    // Gauss-Jordan inverse of the 4x4 Gram matrix
+    double W[4][8];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 8; ++j) W[i][j] = j < 4 ? G[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 4; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 4; ++r)
+        if (std::fabs(W[r][c]) > std::fabs(W[piv][c])) piv = r;
+      for (int j = 0; j < 8; ++j) std::swap(W[c][j], W[piv][j]);
+      const double d = W[c][c];
+      for (int j = 0; j < 8; ++j) W[c][j] /= d;
+      for (int r = 0; r < 4; ++r)
+        if (r != c) {
+          const double f = W[r][c];
+          for (int j = 0; j < 8; ++j) W[r][j] -= f * W[c][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) Gi[i][j] = W[i][4 + j];
+    const int64_t E = n_elem[t];
+    for (int64_t e = 0; e < E; ++e) {
+      const double* X = verts[t] + (size_t)e * nv * 3;
+      double c[4][3] = {};  // rows: org, then the columns of J
+      for (int v = 0; v < nv; ++v) {
+        const double a[4] = {1, rv[v][0], rv[v][1], rv[v][2]};
+        for (int i = 0; i < 4; ++i) {
+          double w = 0;
+          for (int j = 0; j < 4; ++j) w += Gi[i][j] * a[j];
+          for (int d = 0; d < 3; ++d) c[i][d] += w * X[3 * v + d];
+        }
+      }
+      double size = 0, mis = 0;
+      for (int v = 0; v < nv; ++v)
+        for (int u = 0; u < nv; ++u) {
+          double d2 = 0;
+          for (int d = 0; d < 3; ++d) d2 += (X[3 * v + d] - X[3 * u + d]) * (X[3 * v + d] - X[3 * u + d]);
+          size = std::max(size, std::sqrt(d2));
+        }
+      for (int v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) {
+          const double x = c[0][d] + c[1][d] * rv[v][0] + c[2][d] * rv[v][1] + c[3][d] * rv[v][2];
+          mis = std::max(mis, std::fabs(x - X[3 * v + d]));
+          lo3[d] = std::min(lo3[d], X[3 * v + d]);
+          hi3[d] = std::max(hi3[d], X[3 * v + d]);
+        }
+      if (!(size > 0) || !std::isfinite(mis)) return "degenerate element";
+      if (mis > 1e-10 * size) return "element is not the affine image of the reference element";
+      for (int d = 0; d < 3; ++d) M.org[t].push_back(c[0][d]);
+      double J[9];
+      for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < 3; ++k) J[3 * d + k] = c[1 + k][d];
+      M.jac[t].insert(M.jac[t].end(), J, J + 9);
+      M.gid[t].push_back(g++);
+      for (int k = 0; k < 3; ++k)
+        hmin = std::min(hmin, std::sqrt(J[k] * J[k] + J[3 + k] * J[3 + k] + J[6 + k] * J[6 + k]));
+    }
+  }
+  if (g == 0) return "no elements";
+  double lat[9];
+  if (period) {
+    for (int k = 0; k < 9; ++k) lat[k] = period[k];
+  } else {
+    // no period: a lattice far larger than the mesh never wraps a face
+    for (int k = 0; k < 9; ++k) lat[k] = 0;
+    for (int d = 0; d < 3; ++d) lat[4 * d] = 4.0 * (hi3[d] - lo3[d]) + 1.0;
+  }
+  return finish_mesh(M, refs, lat, lo3, hmin);
 }
 
 bool prism_tri_faces_aligned(const Mesh& m) {

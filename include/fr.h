@@ -241,6 +241,23 @@ fr_status fr_upts_coords(const fr_ctx* c, double* xyz_host);
  * FR_EINVAL (null), FR_EDEVICE. */
 fr_status fr_rhs(fr_ctx* c, const double* u_dev, double* du_dev);
 
+/* du = R(u) like fr_rhs, allocating nothing: for callers that cannot call
+ * hipMalloc (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The per-call work buffers of the fused form
+ * (face values, face fluxes, residual partials, single-precision face bases
+ * and constant fluxes) live in a static device array of FR_NOALLOC_MAX_BYTES
+ * bytes, one copy per GPU, held until the process ends; its address is looked
+ * up on the first call on each device.  Meshes whose work buffers exceed it
+ * are rejected (FR_EINVAL; fr_last_error gives the need).  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU (several contexts
+ * or streams) race and must be serialised by the caller.  The mesh data must
+ * already be on the device: any earlier fr_set_state (or fr_rhs) uploads it;
+ * otherwise FR_ESTATE.  Fused form only (FR_EUNSUPPORTED for the plain
+ * form).  u_dev, du_dev as for fr_rhs; asynchronous on the context stream on
+ * the current device.  Other errors as fr_rhs. */
+#define FR_NOALLOC_MAX_BYTES (64LL << 20)
+fr_status fr_rhs_noalloc(fr_ctx* c, const double* u_dev, double* du_dev);
+
 /* Profiling aid: enqueue only some kernel groups of fr_rhs on the context
  * stream.  mask bit 0: disu (solution at flux points), bit 1: volume group
  * (common solution, corrected gradients, anti-aliased flux, projection and

@@ -27,7 +27,7 @@ _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "
 
 # every symbol the header declares
 SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_mesh_elements", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
-           "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
+           "fr_rhs_noalloc", "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
            "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
            "fr_pool_events", "fr_pool_query", "fr_pool_last_error", "fr_pool_destroy"]
 
@@ -67,6 +67,14 @@ def load_library(path=None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise FrError("libfrmi.so not built; run paper_2401_06132_amd.build.build()")
+    try:
+        # torch ships its own HIP runtime; loaded first, it is the one the
+        # library binds to as well, so both share one runtime and device
+        # pointers pass between them.  Loaded after the library, a second
+        # runtime would come up beside the first and see no device.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -78,6 +86,7 @@ def load_library(path=None):
         "fr_type_count": (I, [P, I, ctypes.POINTER(I64)]),
         "fr_upts_coords": (I, [P, P]),
         "fr_rhs": (I, [P, P, P]),
+        "fr_rhs_noalloc": (I, [P, P, P]),
         "fr_rhs_stages": (I, [P, P, P, I]),
         "fr_set_state": (I, [P, P, I]),
         "fr_get_state": (I, [P, P, I]),
@@ -225,6 +234,11 @@ class Solver:
 
     def rhs(self, u, du):
         _check(self.ctx, self.lib.fr_rhs(self.ctx, self._dev(u, self.n_state), self._dev(du, self.n_state)))
+
+    def rhs_noalloc(self, u, du):
+        """du = R(u) with the work buffers in the library's static device
+        scratch (no allocation); the mesh must be on the device already."""
+        _check(self.ctx, self.lib.fr_rhs_noalloc(self.ctx, self._dev(u, self.n_state), self._dev(du, self.n_state)))
 
     def rhs_stages(self, u, du, mask):
         _check(self.ctx, self.lib.fr_rhs_stages(self.ctx, self._dev(u, self.n_state), self._dev(du, self.n_state),

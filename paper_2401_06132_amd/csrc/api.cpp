@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,6 +14,16 @@
 #include "fr_host.h"
 #include "fr_kernels.h"
 #include "fr_plain.h"
+
+// Per-call work buffers of the fused form: face values Uf [slot][5][nfp],
+// transformed face fluxes Vf [slot][4][nfp], residual partials Rp (state
+// layout) and, in single precision, the face bases Ub [slot][5] and the
+// constant transformed flux fbar [E][12] of the dense types.  None needs to
+// start at any particular value: every call writes each before reading it.
+struct Work {
+  enum { UF, VF, RP, UB, FBAR, N = FBAR + fr::NTYPES };
+  void* ptr[N] = {};
+};
 
 struct fr_ctx {
   fr_physics ph;
@@ -30,18 +41,24 @@ struct fr_ctx {
   // device buffers
   double* d_state = nullptr;  // internal state
   double* d_rk = nullptr;     // RK buffers: stage state, accumulator (+ stage derivative, plain form)
-  void *d_Uf = nullptr, *d_Vf = nullptr, *d_Rp = nullptr, *d_fgeo = nullptr;
-  float* d_Ub = nullptr;  // single precision: face bases [slot][5]
+  void* d_fgeo = nullptr;
   fr::FaceRec* d_faces = nullptr;
   uint8_t* d_perms = nullptr;
   void* d_met[fr::NTYPES] = {};
   double* d_detj[fr::NTYPES] = {};
   void* d_pops = nullptr;  // prism triangle tables
   void* d_dops[fr::NTYPES] = {};  // dense operator tables (tetrahedra, pyramids)
-  float* d_fbar[fr::NTYPES] = {};  // single precision, dense types: constant transformed flux [E][12]
   void* d_verts[2] = {nullptr, nullptr};  // curved meshes: element vertices [E][nv][3]
   fr::PlainCtx* plain = nullptr;  // unfused comparison path
+  Work w;  // per-call work buffers of the fused form (allocated on first use)
+  bool work_ok = false;
 };
+
+// Work buffers of fr_rhs_noalloc: one copy of this array per GPU, held from
+// the library's load until the process ends.  In host code the name is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, once
+// per device (scratch_on_device below), and only that address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[FR_NOALLOC_MAX_BYTES];
 
 namespace {
 
@@ -185,16 +202,11 @@ fr_status ensure_device(fr_ctx* c) {
     return FR_OK;
   }
   const fr::Mesh& M = c->M;
-  const int n = c->p + 1, nfp = n * n;
-  const size_t rs = rsize(c);
+  const int nfp = (c->p + 1) * (c->p + 1);
   const int64_t S = M.nslots;
   HIPCHK(hipMalloc(&c->d_state, sizeof(double) * c->n_state));
   HIPCHK(hipMemsetAsync(c->d_state, 0, sizeof(double) * c->n_state, c->st));
   HIPCHK(hipMalloc(&c->d_rk, sizeof(double) * c->n_state * 2));  // stage state, accumulator
-  HIPCHK(hipMalloc(&c->d_Uf, rs * S * 5 * nfp));
-  HIPCHK(hipMalloc(&c->d_Vf, rs * S * 4 * nfp));
-  HIPCHK(hipMalloc(&c->d_Rp, rs * c->n_state));
-  if (rs == 4) HIPCHK(hipMalloc(&c->d_Ub, sizeof(float) * S * 5));
   // faces
   std::vector<fr::FaceRec> fr(S);
   std::vector<double> geo(4 * S);
@@ -251,25 +263,73 @@ fr_status ensure_device(fr_ctx* c) {
     fr::dense_ops_pack(c->ref[t], c->ph.prec, pb.data());
     HIPCHK(hipMalloc(&c->d_dops[t], nb));
     HIPCHK(hipMemcpy(c->d_dops[t], pb.data(), nb, hipMemcpyHostToDevice));
-    if (rs == 4) HIPCHK(hipMalloc(&c->d_fbar[t], sizeof(float) * 12 * M.nel[t]));
   }
   c->dev_ok = true;
   return FR_OK;
 }
 
+// Sizes in bytes of the fused form's per-call work buffers (slot k of
+// Work::ptr): face values, transformed face fluxes, residual partials and,
+// in single precision, the face bases and the dense types' constant
+// transformed flux.  Returns the total with every buffer 256-byte aligned.
+int64_t work_bytes(const fr_ctx* c, int64_t bytes[Work::N]) {
+  const int64_t rs = (int64_t)rsize(c), nfp = (int64_t)(c->p + 1) * (c->p + 1), S = c->M.nslots;
+  bytes[Work::UF] = rs * S * 5 * nfp;
+  bytes[Work::VF] = rs * S * 4 * nfp;
+  bytes[Work::RP] = rs * c->n_state;
+  bytes[Work::UB] = rs == 4 ? (int64_t)sizeof(float) * S * 5 : 0;
+  for (int t = 0; t < fr::NTYPES; ++t)
+    bytes[Work::FBAR + t] = rs == 4 && t >= 2 ? (int64_t)sizeof(float) * 12 * c->M.nel[t] : 0;
+  int64_t tot = 0;
+  for (int k = 0; k < Work::N; ++k) tot += (bytes[k] + 255) / 256 * 256;
+  return tot;
+}
+
+// the device address of `scratch` on the current device, looked up on the
+// first call there and kept per device ordinal
+hipError_t scratch_on_device(void** out) {
+  static std::mutex mu;
+  static void* addr[256] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+// the context's own work buffers, allocated on first use
+fr_status ensure_work(fr_ctx* c) {
+  if (c->work_ok) return FR_OK;
+  int64_t b[Work::N];
+  work_bytes(c, b);
+  for (int k = 0; k < Work::N; ++k)
+    if (b[k] > 0) HIPCHK(hipMalloc(&c->w.ptr[k], (size_t)b[k]));
+  c->work_ok = true;
+  return FR_OK;
+}
+
 // the segment of element type t: caller's u/du for a plain evaluation, the
-// internal state and RK buffers otherwise
-fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
+// internal state and RK buffers otherwise; work buffers from w
+fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du, const Work& w) {
   fr::Seg s;
   const int64_t o = c->off[t];
   s.U = const_cast<double*>(u ? u : c->d_state) + o;
   s.du = du ? du + o : nullptr;
   s.ust = c->d_rk + o;
   s.acc = c->d_rk + c->n_state + o;
-  s.Uf = c->d_Uf;
-  s.Ub = c->d_Ub;
-  s.Vf = c->d_Vf;
-  s.Rp = (char*)c->d_Rp + rsize(c) * o;
+  s.Uf = w.ptr[Work::UF];
+  s.Ub = (float*)w.ptr[Work::UB];
+  s.Vf = w.ptr[Work::VF];
+  s.Rp = (char*)w.ptr[Work::RP] + rsize(c) * o;
   s.faces = c->d_faces;
   s.fgeo = c->d_fgeo;
   s.perms = c->d_perms;
@@ -279,7 +339,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du) {
   s.slot_base = (int32_t)c->M.slot_base[t];
   s.nperm = (int32_t)c->M.perms.size();
   s.verts = t < 2 ? c->d_verts[t] : nullptr;
-  s.fbar = c->d_fbar[t];
+  s.fbar = (float*)w.ptr[Work::FBAR + t];
   return s;
 }
 
@@ -297,18 +357,24 @@ fr::TypeArgs type_args(fr_ctx* c, int t, const fr::Seg& s, int stage) {
 }
 
 // one right-hand side (rk < 0: du = R(u)) or one fused RK4 stage rk on the
-// internal state (u, du unused)
-fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int rk = -1, double dt = 0.0) {
+// internal state (u, du unused); work buffers from w, else the context's own
+fr_status launch_rhs(fr_ctx* c, const double* u, double* du, int mask = 7, int rk = -1, double dt = 0.0,
+                     const Work* w = nullptr) {
   if (c->ph.form == FR_FORM_PLAIN) {
     hipError_t e = fr::plain_rhs(*c->plain, u, du, c->st);
     if (e != hipSuccess) return fail(c, FR_EDEVICE, std::string("plain path: ") + hipGetErrorString(e));
     return FR_OK;
   }
+  if (!w) {
+    fr_status s = ensure_work(c);
+    if (s != FR_OK) return s;
+    w = &c->w;
+  }
   for (int stage = 1; stage <= 4; stage <<= 1)
     if (mask & stage)
     for (int t = 0; t < fr::NTYPES; ++t) {
       if (!c->has[t]) continue;
-      fr::TypeArgs a = type_args(c, t, seg_of_type(c, t, rk < 0 ? u : nullptr, rk < 0 ? du : nullptr), stage);
+      fr::TypeArgs a = type_args(c, t, seg_of_type(c, t, rk < 0 ? u : nullptr, rk < 0 ? du : nullptr, *w), stage);
       a.one.dt = dt;
       a.rk = rk;
       a.from_ust = rk > 0;
@@ -490,6 +556,32 @@ fr_status fr_rhs(fr_ctx* c, const double* u, double* du) {
   fr_status s = ensure_device(c);
   if (s != FR_OK) return s;
   return launch_rhs(c, u, du);
+}
+
+fr_status fr_rhs_noalloc(fr_ctx* c, const double* u, double* du) {
+  if (!c) return FR_EINVAL;
+  if (!u || !du) return fail(c, FR_EINVAL, "null buffer");
+  if (u == du) return fail(c, FR_EINVAL, "u and du must not alias");
+  if (!c->mesh_ok) return fail(c, FR_ESTATE, "no mesh");
+  if (c->ph.form != FR_FORM_FUSED)
+    return fail(c, FR_EUNSUPPORTED, "fr_rhs_noalloc: the plain form keeps its work buffers in the context");
+  int64_t b[Work::N];
+  const int64_t need = work_bytes(c, b);
+  if (need > (int64_t)FR_NOALLOC_MAX_BYTES)
+    return fail(c, FR_EINVAL, "fr_rhs_noalloc: this mesh needs " + std::to_string(need) +
+                                  " bytes of work buffers; the static scratch holds " +
+                                  std::to_string((long long)FR_NOALLOC_MAX_BYTES));
+  if (!c->dev_ok)
+    return fail(c, FR_ESTATE, "fr_rhs_noalloc: mesh data not on the device yet (fr_set_state uploads it)");
+  void* base = nullptr;
+  HIPCHK(scratch_on_device(&base));
+  Work w;
+  char* q = (char*)base;
+  for (int k = 0; k < Work::N; ++k) {
+    w.ptr[k] = b[k] > 0 ? q : nullptr;
+    q += (b[k] + 255) / 256 * 256;
+  }
+  return launch_rhs(c, u, du, 7, -1, 0.0, &w);
 }
 
 fr_status fr_rhs_stages(fr_ctx* c, const double* u, double* du, int mask) {
@@ -686,12 +778,14 @@ void fr_destroy(fr_ctx* c) {
   if (!c) return;
   if (c->dev_ok || c->d_state) {
     (void)hipStreamSynchronize(c->st);
-    void* bufs[] = {c->d_state, c->d_rk,    c->d_Uf,   c->d_Vf,       c->d_Rp,       c->d_fgeo,
-                    c->d_faces, c->d_perms, c->d_pops, c->d_verts[0], c->d_verts[1], c->d_Ub};
+    void* bufs[] = {c->d_state, c->d_rk,   c->d_fgeo,     c->d_faces,
+                    c->d_perms, c->d_pops, c->d_verts[0], c->d_verts[1]};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
+    for (void* b : c->w.ptr)
+      if (b) (void)hipFree(b);
     for (int t = 0; t < fr::NTYPES; ++t) {
-      void* tb[] = {c->d_met[t], c->d_detj[t], c->d_dops[t], c->d_fbar[t]};
+      void* tb[] = {c->d_met[t], c->d_detj[t], c->d_dops[t]};
       for (void* b : tb)
         if (b) (void)hipFree(b);
     }

@@ -25,52 +25,124 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GDoF-RHS/s NS+AA FR (fused FP32 vs plain FP64), % HBM roofline; p99 step ms"
 HBM_PEAK_GBS = 8000.0
-# vector ALU peak from unit counts: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
-# FP64 FMA runs at full rate; FP32 reaches twice this only with packed math,
-# which this build does not emit.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# HBM bytes per launch of hex_volume<3, float> on the 48^3 workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from
-# a 1 GiB copy), profiles/hex_fused_fp32_p3_tgv48.md.  Valid for the kernel as
-# profiled; None once the kernel changes.
-HEX_VOL_P3_FP32_TRAFFIC = (270601.6 * 2 + 304128.0) * 1024
+# published MI355X vector peaks: FP32 157.3 TFLOP/s (with packed FP32 math),
+# FP64 78.6 TFLOP/s.  Without packed math the FP32 vector rate equals the
+# FP64 one: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s,
+# reported beside it as the non-packed rate (this build emits no packed FP32).
+VALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# HBM bytes per launch of the headline volume kernel (hex_volume<3, float> on
+# the 48^3 workload), from two rocprofv3 --pmc runs (FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000, factors from a 1 GiB copy), recorded in the profile
+# summary of that kernel.  Valid for the kernel as profiled; None once the
+# kernel changes.
+HEX_VOL_P3_FP32_TRAFFIC = None
+
+# FLOP counts of the point-wise physics (multiplies, adds and fused
+# multiply-adds as 2; reciprocal and square root as 1), from the code of the
+# device functions: the point flux f = f^e - f^v with the split energy
+# component, the normal viscous flux, the interface flux of one own flux
+# point (both sides' inviscid fluxes, Rusanov, LDG, the jump terms)
+PF_FLOP, NV_FLOP, CF_FLOP = 147, 120, 140
+
+NTYPE_PTS = {  # (N_u, flux points, quadrature points, faces) per element
+    "hex": lambda n, m: (n ** 3, 6 * n * n, m ** 3, 6),
+    "prism": lambda n, m: (n * n * (n + 1) // 2, n * (n + 1) + 3 * n * n, (n * n) * m, 5),
+    "tet": lambda n, m: (n * (n + 1) * (n + 2) // 6, 2 * n * (n + 1), n ** 3, 4),
+    "pyr": lambda n, m: (n * (n + 1) * (2 * n + 1) // 6, n * n + 2 * n * (n + 1), n ** 3, 5),
+}
 
 
-def volume_model(p, bytes_real):
+def volume_model(kind, p, prec, aa=True, diag=True):
     """Algorithmic HBM bytes and FLOPs of one element in the fused volume
-    kernel (hex).  Bytes: state read (5 N_u doubles), neighbour face states
-    (5 N_f reals), normal viscous flux written (4 N_f reals), volume residual
-    written (5 N_u reals), face records + per-element metrics (small).
-    FLOPs: the sum-factorised sweeps, gradient, the point-wise flux at the
-    m^3 quadrature points (about 130 flops each) and the face viscous fluxes."""
+    kernel, counted from the kernel's loops (not the MFMA tile padding).
+    Bytes: state read (5 N_u doubles), neighbour face states (5 N_f reals,
+    single precision with one float base per face and variable), normal
+    viscous flux written (4 N_f reals), the four projected residual rows
+    written and the mass-flux divergence L(rho v) read (N_u reals), face
+    records, geometry and metrics.  FLOPs: the products of each phase
+    (2 per multiply-add) and the point-wise physics (PF/NV_FLOP)."""
+    rb = 4 if prec == "fp32" else 8
     n, m = p + 1, p + 3
-    nu, nf = n ** 3, 6 * n * n
-    byts = 5 * nu * 8 + 5 * nf * bytes_real + 4 * nf * bytes_real + 5 * nu * bytes_real + 6 * 8 + 10 * bytes_real
+    nu, nf, nq, nfc = NTYPE_PTS[kind](n, m)
+    nvf = 4  # mass flux from L(rho v)
+    byts = 5 * nu * 8 + 5 * nf * rb + 4 * nf * rb + nvf * nu * rb + nu * rb + nfc * (8 + 4 * rb) + 10 * rb
+    if rb == 4:
+        byts += nfc * 5 * 4
+    S = 1 if diag else 3  # terms per transformed-flux component
     fl = 0
-    fl += 2 * 5 * 3 * n * n * n * 2                      # own face values (lb, rb)
-    fl += 2 * 15 * nu * (n + 2)                           # corrected gradient
-    fl += 2 * 15 * nu * 3                                 # J^-T
-    fl += 2 * 20 * 3 * n * n * n * 2 + 3 * n * n * 2 * 60  # face interpolation + viscous normal flux
-    fl += 2 * 20 * m * n * n * n                          # x sweep
-    fl += 2 * 20 * m * m * n * n                          # y interpolation per column
-    fl += 2 * 20 * m * m * m * n                          # z interpolation on the fly
-    fl += m ** 3 * (130 + 2 * 45)                          # point flux + transformed flux
-    fl += 2 * 15 * m ** 3 * n                             # z projection
-    fl += 2 * 5 * m * n * (m * 3) * n                     # y projection
-    fl += 2 * 5 * n * n * (2 * m) * n                     # x projection
+    if kind == "hex":
+        fl += 3 * 5 * n * n * (4 * n + 4 + n * (2 * n + 3 + 1))   # face values, jumps, corrected gradient
+        if not diag:
+            fl += 5 * nu * 15                                       # J^-T
+        fl += 3 * n * n * (80 * n + 2 * NV_FLOP)                   # face states + normal viscous flux
+        if aa:
+            fl += 40 * m * n ** 3                                   # x interpolation
+            fl += m * m * 40 * n * n                                # y interpolation per column
+            fl += m ** 3 * (40 * n + PF_FLOP + 3 * nvf * (2 * S - 1) + 3 * nvf * 2 * n)  # z, flux, z projection
+            fl += nvf * m * n * n * 6 * m                           # y projection
+            fl += nvf * n * n * n * 4 * m + 2 * n ** 3              # x projection, kap L
+        else:
+            fl += nu * (PF_FLOP + 3 * nvf * (2 * S - 1)) + nvf * nu * 3 * n * 2 + 2 * nu
+    elif kind == "prism":
+        nt, ntq = n * (n + 1) // 2, n * n
+        fl += 5 * nt * (4 * n + 4) + 5 * n * 3 * n * (2 * nt + 2)  # face values and jumps
+        fl += 5 * nt * n * (2 * n + 3) + 5 * n * nt * (4 * nt + 3 * (2 * n + 4))  # corrected gradient
+        fl += 5 * nu * 15                                           # J^-T (general metric)
+        fl += nt * (80 * n + 2 * NV_FLOP) + 3 * n * n * (40 * nt + NV_FLOP)  # face states + viscous flux
+        if aa:
+            fl += 20 * n * ntq * 2 * nt                              # triangle-plane interpolation
+            fl += ntq * m * (40 * n + PF_FLOP + 3 * nvf * 5 + 3 * nvf * 2 * n)  # line columns
+            fl += nvf * n * nt * 3 * ntq * 2 + 2 * nu                # triangle-plane projection, kap L
+        else:
+            fl += nu * (PF_FLOP + 3 * nvf * 5) + nvf * nu * 2 * (n + 2 * nt + 3 * n) + 2 * nu
+    else:  # tetrahedra, pyramids: dense products
+        fl += 2 * nf * nu * 5 + 5 * nf * 3                          # own face values, jumps
+        fl += 2 * 3 * nu * (nu + nf) * 5 + 5 * nu * 15               # corrected gradient, J^-T
+        fl += 2 * nf * nu * 20 + nf * NV_FLOP                       # face states + viscous flux
+        if aa:
+            fl += 2 * nq * nu * 20 + nq * (PF_FLOP + 3 * nvf * 6)     # quadrature values + flux
+            fl += 2 * nu * 3 * nq * nvf + 2 * nu                      # projection-divergence, kap L
+        else:
+            fl += nu * (PF_FLOP + 3 * nvf * 6) + 2 * nu * 3 * nu * nvf + 2 * nu
     return byts, fl
 
 
-def rhs_bytes_model(p, bytes_real):
-    """Algorithmic bytes of one full fused RHS per element (hex): disu reads
-    U and writes U^f; the volume group reads U and the neighbour U^f and
-    writes V^f and the volume residual; the interface group reads the
-    residual, own and neighbour U^f and V^f, and writes du."""
-    n = p + 1
-    nu, nf = n ** 3, 6 * n * n
-    b = 5 * nu * 8 + 5 * nf * bytes_real
-    b += 5 * nu * 8 + 5 * nf * bytes_real + 4 * nf * bytes_real + 5 * nu * bytes_real
-    b += 5 * nu * bytes_real + 2 * 5 * nf * bytes_real + 2 * 4 * nf * bytes_real + 5 * nu * 8
+def rhs_bytes_model(kind, p, prec):
+    """Algorithmic bytes of one full fused RHS per element: disu reads U and
+    writes U^f (+ face bases in single precision) and L(rho v); the volume
+    group reads U, the neighbour U^f and L(rho v), writes V^f and the volume
+    residual; the interface group reads the residual, own and neighbour U^f
+    and V^f, and writes du.  Face records and metrics are not counted."""
+    rb = 4 if prec == "fp32" else 8
+    n, m = p + 1, p + 3
+    nu, nf, _, nfc = NTYPE_PTS[kind](n, m)
+    fb = nfc * 5 * 4 if rb == 4 else 0
+    b = 5 * nu * 8 + 5 * nf * rb + fb + nu * rb
+    b += 5 * nu * 8 + 5 * nf * rb + fb + nu * rb + 4 * nf * rb + 4 * nu * rb
+    b += 5 * nu * rb + 2 * (5 * nf * rb + fb) + 2 * 4 * nf * rb + 5 * nu * 8
+    return b
+
+
+def plain_bytes_model(kind, p):
+    """Algorithmic bytes per element of the plain FP64 path (every
+    intermediate array in HBM, each written once and read once by the next
+    kernel): W, U^f, C, Q~/Q, Q^f, U^q, Q^q/F~^q, R, D~."""
+    n, m = p + 1, p + 3
+    nu, nf, nq, _ = NTYPE_PTS[kind](n, m)
+    w = 8
+    b = 5 * nu * w * 2          # U read, W written
+    b += 5 * nu * w + 5 * nf * w  # disu
+    b += 2 * 5 * nf * w + 5 * nf * w  # con_u (own + neighbour read, C written)
+    b += 5 * nu * w + 15 * nu * w + 5 * nf * w + 15 * nu * w  # tgradpcoru + tgradcoru
+    b += 2 * 15 * nu * w        # gradcoru
+    b += 15 * nu * w + 15 * nf * w  # gradcoru_fpts
+    b += 15 * nu * w + 15 * nq * w + 5 * nu * w + 5 * nq * w  # gradcoru_qpts, qptsu
+    b += 2 * 20 * nq * w         # tdisf (reads 20, writes 15; counted 20 + 20)
+    b += 15 * nq * w + 5 * nu * w  # tdivtpcorf
+    b += 2 * (5 + 15) * nf * w + 5 * nf * w  # comm_flux
+    b += 5 * nf * w + 2 * 5 * nu * w  # tdivtconf
+    b += 2 * 5 * nu * w          # negdivconf
     return b
 
 
@@ -306,6 +378,10 @@ def main():
         kind, prec, p, form = args.only.split(":")
         r = time_variant(frmi, torch, args.n, int(p), prec, args.steps, args.warmup, form, kind)
         r["gdof_s"] = r["n_dof"] * args.steps / r["wall_s"] / 1e9
+        if kind in NTYPE_PTS and form in ("fused", "noaa"):
+            vb, vf = volume_model(kind, int(p), prec, aa=form == "fused")
+            r["vol_TFLOPs"] = vf * r["n_elem"] / (r["vol_ms"] * 1e-3) / 1e12
+            r["vol_GBs"] = vb * r["n_elem"] / (r["vol_ms"] * 1e-3) / 1e9
         print(json.dumps({"variant": args.only, **{k: (round(v, 4) if isinstance(v, float) else v)
                                                    for k, v in r.items()}}), flush=True)
         return
@@ -313,7 +389,7 @@ def main():
         ("fp32", 3, "fused", "hex"), ("fp64", 3, "fused", "hex"), ("fp64", 3, "plain", "hex"),
         ("fp32", 4, "fused", "hex"), ("fp64", 4, "fused", "hex"), ("fp64", 4, "plain", "hex"),
         ("fp32", 3, "fused", "prism"), ("fp64", 3, "fused", "prism"), ("fp64", 3, "plain", "prism"),
-        ("fp32", 4, "fused", "prism"),
+        ("fp32", 4, "fused", "prism"), ("fp64", 4, "fused", "prism"), ("fp64", 4, "plain", "prism"),
         ("fp32", 3, "noaa", "hex"), ("fp64", 3, "noaa", "hex"), ("fp32", 4, "noaa", "hex"),
         ("fp32", 3, "noaa", "prism"), ("fp32", 4, "noaa", "prism"),
         ("fp32", 3, "fullaa", "hex"), ("fp64", 3, "fullaa", "hex"), ("fp32", 4, "fullaa", "hex"),
@@ -328,37 +404,47 @@ def main():
     for prec, p, form, kind in order:
         ksteps = args.steps if kind == "hex" else max(5, args.steps // 3)
         r = time_variant(frmi, torch, args.n, p, prec, ksteps, args.warmup, form, kind)
-        br = 4 if prec == "fp32" else 8
-        vb, vf = volume_model(p, br)
         E = r["n_elem"]
         r["gdof_s"] = r["n_dof"] * ksteps / r["wall_s"] / 1e9
-        if kind == "hex":
-            r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
-            r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12 if form == "fused" else float("nan")
-            r["rhs_GBs"] = rhs_bytes_model(p, br) * E * ksteps / r["wall_s"] / 1e9
-        else:
-            r["vol_GBs"] = r["vol_TFLOPs"] = r["rhs_GBs"] = float("nan")
+        r["vol_GBs"] = r["vol_TFLOPs"] = r["vol_frac"] = r["rhs_GBs"] = float("nan")
+        if kind in NTYPE_PTS:
+            # single-type affine meshes: the volume kernel's position against
+            # its roof, and the whole RHS against HBM
+            if form in ("fused", "noaa"):
+                vb, vf = volume_model(kind, p, prec, aa=form == "fused")
+                r["vol_GBs"] = vb * E / (r["vol_ms"] * 1e-3) / 1e9
+                r["vol_TFLOPs"] = vf * E / (r["vol_ms"] * 1e-3) / 1e12
+                r["vol_frac"] = r["vol_TFLOPs"] / VALU_PEAK_TFLOPS[prec]
+            if form in ("fused", "noaa", "fullaa"):
+                r["rhs_GBs"] = rhs_bytes_model(kind, p, prec) * E * ksteps / r["wall_s"] / 1e9
+            elif form == "plain":
+                r["rhs_GBs"] = plain_bytes_model(kind, p) * E * ksteps / r["wall_s"] / 1e9
         variants["%s%s%s_p%d" % ("" if kind == "hex" else kind + "_", "" if form == "fused" else form + "_", prec,
                                   p)] = r
-        print("variant", form, prec, p, json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
+        print("variant", kind, form, prec, p,
+              json.dumps({k: round(v, 4) if isinstance(v, float) else v for k, v in r.items()}),
               file=sys.stderr, flush=True)
     head = variants["fp32_p3"]
-    for pre in ("", "prism_"):
+    for pre in ("", "prism_", "tet_", "pyr_"):
         for p in (3, 4):
             a, b = "%sfp32_p%d" % (pre, p), "%splain_fp64_p%d" % (pre, p)
             if a in variants and b in variants:
                 variants[a]["speedup_vs_plain_fp64"] = variants[a]["gdof_s"] / variants[b]["gdof_s"]
-    vb, vf = volume_model(3, 4)
+    vb, vf = volume_model("hex", 3, "fp32")
     ai = vf / vb
-    ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    peak = VALU_PEAK_TFLOPS["fp32"]
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai > ridge:
-        roof = {"bound": "alu", "achieved": round(head["vol_TFLOPs"], 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(head["vol_TFLOPs"] / VALU_PEAK_TFLOPS, 4)}
+        roof = {"bound": "alu", "achieved": round(head["vol_TFLOPs"], 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(head["vol_TFLOPs"] / peak, 4),
+                "peak_nonpacked": round(VALU_NONPACKED_TFLOPS, 1),
+                "frac_nonpacked": round(head["vol_TFLOPs"] / VALU_NONPACKED_TFLOPS, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(head["vol_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4)}
     traffic = HEX_VOL_P3_FP32_TRAFFIC if args.n == 48 else None
-    roof.update({"kernel": "hex_volume<3,float>", "traffic": traffic, "traffic_unit": "bytes per launch",
+    roof.update({"traffic": traffic, "kernel": "hex_volume<3,float> (diagonal metric)",
+                 "traffic_unit": "bytes per launch", "flop_per_elem": vf, "bytes_per_elem": vb,
                  "algorithmic_bytes": vb * head["n_elem"], "hbm_GBs": round(head["vol_GBs"], 1),
                  "hbm_frac": round(head["vol_GBs"] / HBM_PEAK_GBS, 4), "flop_per_byte": round(ai, 2),
                  "avg_ms": round(head["vol_ms"], 4)})
@@ -375,7 +461,9 @@ def main():
         "hbm_frac_rhs": round(head["rhs_GBs"] / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "variants": {k: {"gdof_s": _r(v["gdof_s"]), "p99_step_ms": _r(v["p99_ms"]), "vol_ms": _r(v["vol_ms"]),
-                         "hbm_frac_rhs": _r(v["rhs_GBs"] / HBM_PEAK_GBS), "finite": v["finite"],
+                         "vol_TFLOPs": _r(v["vol_TFLOPs"]), "vol_GBs": _r(v["vol_GBs"]),
+                         "vol_frac": _r(v["vol_frac"]), "hbm_frac_rhs": _r(v["rhs_GBs"] / HBM_PEAK_GBS),
+                         "finite": v["finite"],
                          "speedup_vs_plain_fp64": _r(v.get("speedup_vs_plain_fp64", float("nan")))}
                      for k, v in variants.items()},
     }

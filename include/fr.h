@@ -325,7 +325,7 @@ void fr_destroy(fr_ctx* c);
  * pool.  A request leaves the pool after its last step; its final state is
  * copied to u_out (if given) and its memory is reused by later admissions.
  * The RHS is the fused form of section 6.1 at the pool's precision; the
- * Taylor-Green initial condition is the test case of section 7.2.
+ * Taylor-Green initial condition is the test case of section 6.
  * ---------------------------------------------------------------------- */
 typedef struct fr_pool fr_pool;
 
@@ -380,18 +380,30 @@ fr_status fr_pool_submit(fr_pool* pool, const fr_request* r, int64_t* id);
 /* One scheduling round: enqueue one RK4 step of every admitted request, then
  * admit queued requests (host mesh set-up overlaps the GPU work), wait for
  * the stream, and retire requests that completed their steps.  Synchronous.
- * stats may be NULL.  After FR_EDEVICE the pool is unusable: destroy it. */
+ * A queued request whose host set-up fails (mesh or table construction)
+ * does not stop the round: it leaves the queue with status 3 (failed),
+ * never runs, holds no memory, is listed among the round's finished ids,
+ * and fr_pool_last_error names it and the reason; the round's step,
+ * admissions and accounting go on.  stats may be NULL.  After FR_EDEVICE
+ * the pool is unusable: destroy it. */
 fr_status fr_pool_step(fr_pool* pool, fr_pool_stats* stats);
 
-/* Ids admitted and finished by the last fr_pool_step (arrays of cap
- * entries, either may be NULL; counts always written).  FR_EINVAL if a list
+/* Ids admitted and finished (completed or failed) by the last fr_pool_step
+ * (arrays of cap entries, either may be NULL; counts always written).  FR_EINVAL if a list
  * does not fit. */
 fr_status fr_pool_events(const fr_pool* pool, int64_t* admitted, int* n_admitted, int64_t* finished,
                          int* n_finished, int cap);
 
-/* Status of a request: 0 queued, 1 admitted, 2 done; steps completed.
+/* Status of a request: 0 queued, 1 admitted, 2 done, 3 failed (never ran);
+ * steps completed.
  * FR_EINVAL for an unknown id. */
 fr_status fr_pool_query(const fr_pool* pool, int64_t id, int* status, int* steps_done);
+
+/* Testing aid: the host set-up of queued request id will fail at its
+ * admission, as a mesh-building error would, so that callers can exercise
+ * the failure path of fr_pool_step.  Host only.  FR_EINVAL if id is not a
+ * queued request. */
+fr_status fr_pool_inject_prepare_error(fr_pool* pool, int64_t id);
 
 const char* fr_pool_last_error(const fr_pool* pool);
 /* Synchronises the pool stream and frees all device memory of the pool. */

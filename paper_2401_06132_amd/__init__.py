@@ -29,7 +29,7 @@ _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "
 SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_mesh_elements", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
            "fr_rhs_noalloc", "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
            "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
-           "fr_pool_events", "fr_pool_query", "fr_pool_last_error", "fr_pool_destroy"]
+           "fr_pool_events", "fr_pool_query", "fr_pool_inject_prepare_error", "fr_pool_last_error", "fr_pool_destroy"]
 
 
 class FrPhysics(ctypes.Structure):
@@ -102,6 +102,7 @@ def load_library(path=None):
         "fr_pool_step": (I, [P, ctypes.POINTER(FrPoolStats)]),
         "fr_pool_events": (I, [P, P, ctypes.POINTER(I), P, ctypes.POINTER(I), I]),
         "fr_pool_query": (I, [P, I64, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "fr_pool_inject_prepare_error": (I, [P, I64]),
         "fr_pool_last_error": (ctypes.c_char_p, [P]),
         "fr_pool_destroy": (None, [P]),
     }
@@ -279,7 +280,7 @@ class Pool:
     kept referenced here until the request is done.
     """
 
-    QUEUED, ACTIVE, DONE = 0, 1, 2
+    QUEUED, ACTIVE, DONE, FAILED = 0, 1, 2, 3
 
     def __init__(self, budget_bytes, max_active=64, prec="fp32", stream=None, **phys):
         self.lib = load_library()
@@ -343,6 +344,13 @@ class Pool:
             self._keep.pop(int(i), None)
         stats = {k: getattr(s, k) for k, _ in FrPoolStats._fields_}
         return stats, adm[:na.value].tolist(), fin[:nf.value].tolist()
+
+    def inject_prepare_error(self, rid):
+        """Testing aid: make the host set-up of queued request rid fail."""
+        _check(self.pool, self.lib.fr_pool_inject_prepare_error(self.pool, int(rid)), pool=True)
+
+    def last_error(self):
+        return self.lib.fr_pool_last_error(self.pool).decode()
 
     def query(self, rid):
         st, sd = ctypes.c_int(), ctypes.c_int()

@@ -30,7 +30,7 @@ hipError_t rk_stage(int64_t n, const double* u0, const double* k, double* acc, d
   return hipGetLastError();
 }
 
-// Taylor-Green vortex (the paper's test case, section 7.2) at the solution
+// Taylor-Green vortex (the paper's test case, section 6) at the solution
 // points: v = (sin x cos y cos z, -cos x sin y cos z, 0),
 // p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16, rho = p/p0 (rho0 = U0 = 1),
 // E = p/(gamma-1) + rho |v|^2/2.  One thread per solution point.

@@ -200,7 +200,7 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[f
   return out;
 }
 
-enum { Q_QUEUED = 0, Q_ACTIVE = 1, Q_DONE = 2 };
+enum { Q_QUEUED = 0, Q_ACTIVE = 1, Q_DONE = 2, Q_FAILED = 3 };
 // requests prepared ahead of admission by the worker thread
 constexpr int kLookahead = 4;
 
@@ -209,6 +209,7 @@ struct Req {
   fr_request q{};
   Layout L;
   int status = Q_QUEUED, steps_done = 0;
+  bool inject_err = false;  // testing aid: its host set-up fails at admission
   size_t off = 0;
   char* base = nullptr;
   bool has[2] = {false, false}, diag[2] = {false, false};
@@ -394,6 +395,7 @@ fr_status admit(fr_pool* P, Req& R) {
   fr_status s = ensure_device_ops(P, q.p);
   if (s != FR_OK) return s;
   std::shared_ptr<Prepared> pr = take_prepared(P, R.id);
+  if (R.inject_err) return pfail(P, FR_EINVAL, "injected preparation error");
   if (!pr->err.empty()) return pfail(P, FR_EINVAL, pr->err);
   const Prepared& M = *pr;
   P->staged_preps.push_back(pr);
@@ -557,6 +559,35 @@ fr_status finish(fr_pool* P, Req& R) {
   return FR_OK;
 }
 
+// the request at the head of the queue leaves it as failed: it never ran
+// and holds no memory; it is reported among the finished ids of this round
+void fail_head(fr_pool* P, Req& R, const std::string& why) {
+  P->queue.pop_front();
+  R.status = Q_FAILED;
+  P->err = "request " + std::to_string(R.id) + ": " + why;
+  P->last_finished.push_back(R.id);
+}
+
+// queued requests at the head whose host set-up has already failed leave
+// the queue before any device work (host only; does not wait for the
+// preparation worker: a request still being prepared is left to admission)
+void screen_queue(fr_pool* P) {
+  while (!P->queue.empty()) {
+    Req& R = *P->reqs.at(P->queue.front());
+    std::string why;
+    {
+      std::lock_guard<std::mutex> lk(P->mu);
+      auto it = P->ready.find(R.id);
+      if (it == P->ready.end()) return;
+      why = R.inject_err ? std::string("injected preparation error") : it->second->err;
+      if (why.empty()) return;
+      P->ready.erase(it);
+      P->cv.notify_all();
+    }
+    fail_head(P, R, why);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -623,6 +654,7 @@ fr_status fr_pool_step(fr_pool* P, fr_pool_stats* stats) {
   std::memset(&S, 0, sizeof(S));
   P->last_admitted.clear();
   P->last_finished.clear();
+  screen_queue(P);
   if (!P->d_arena) {
     PHIP(hipMalloc(&P->d_arena, (size_t)P->budget));
     P->arena.reset((size_t)P->budget);
@@ -652,7 +684,10 @@ fr_status fr_pool_step(fr_pool* P, fr_pool_stats* stats) {
     if (s != FR_OK) {
       P->arena.release(off, R.L.total);
       R.base = nullptr;
-      return s;
+      if (s != FR_EINVAL) return s;  // a device error: the pool is unusable
+      // the request's own set-up failed: it leaves the queue, the round goes on
+      fail_head(P, R, std::string(P->err));
+      continue;
     }
     P->queue.pop_front();
     P->active.push_back(R.id);
@@ -694,6 +729,15 @@ fr_status fr_pool_events(const fr_pool* P, int64_t* admitted, int* n_admitted, i
   if ((admitted && na > cap) || (finished && nf > cap)) return FR_EINVAL;
   if (admitted) std::copy(P->last_admitted.begin(), P->last_admitted.end(), admitted);
   if (finished) std::copy(P->last_finished.begin(), P->last_finished.end(), finished);
+  return FR_OK;
+}
+
+fr_status fr_pool_inject_prepare_error(fr_pool* P, int64_t id) {
+  if (!P) return FR_EINVAL;
+  auto it = P->reqs.find(id);
+  if (it == P->reqs.end() || it->second->status != Q_QUEUED) return pfail(P, FR_EINVAL, "no such queued request");
+  std::lock_guard<std::mutex> lk(P->mu);
+  it->second->inject_err = true;
   return FR_OK;
 }
 

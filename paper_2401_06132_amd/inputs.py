@@ -4,7 +4,7 @@ coordinates.  This module holds no flux-reconstruction arithmetic; it is
 shared by the library's benchmarks and by the tests (which feed the same
 arrays to the reference oracle and to the GPU path).
 
-Taylor-Green vortex (section 5 of the paper), with rho0 = U0 = L = 1 and
+Taylor-Green vortex (section 6 of the paper), with rho0 = U0 = L = 1 and
 Mach 0.1 based on U0:
     v_x =  sin x cos y cos z,  v_y = -cos x sin y cos z,  v_z = 0
     p   =  p0 + (cos 2x + cos 2y)(cos 2z + 2) / 16,   p0 = 1 / (gamma Ma^2)

@@ -5,8 +5,8 @@ launch configuration as bench.py); the oracle evaluates the RHS of a random
 sample of elements (rhs_subset: the two-hop neighbourhood of each sampled
 element), in extended precision.  Tolerances as in test_gpu_parity.py:
 fused and plain FP64 1e-12, FP32 2e-5 (per variable, relative to the
-sample's max).  Besides the benchmark configurations (hexahedra, prisms,
-the mixed mesh), the tetrahedron, pyramid and four-type meshes that the
+sample's max).  Besides the benchmark configurations (hexahedra and prisms
+at p = 3 and 4 in FP32, FP64 and the plain FP64 form, the mixed mesh), the tetrahedron, pyramid and four-type meshes that the
 benchmark also times run here at 48^3 cells in FP32 (the matrix-core volume
 kernels, with and without flux anti-aliasing).
 """
@@ -33,9 +33,10 @@ def _mesh(kind, n, p):
     return _MESH[key]
 
 
-CASES = [("hex", 48, 3, "fp32"), ("hex", 48, 3, "fp64"), ("hex", 48, 4, "fp32"), ("hex", 48, 4, "fp64"),
-         ("prism", 48, 3, "fp32"), ("prism", 48, 3, "fp64"), ("prism", 48, 4, "fp32"),
-         ("mixed", 64, 4, "fp32"), ("hex", 48, 3, "plain"), ("tet", 48, 3, "fp32"), ("tet", 48, 3, "fp32_noaa"),
+CASES = [("hex", 48, 3, "fp32"), ("hex", 48, 3, "fp64"), ("hex", 48, 3, "plain"), ("hex", 48, 4, "fp32"),
+         ("hex", 48, 4, "fp64"), ("hex", 48, 4, "plain"), ("prism", 48, 3, "fp32"), ("prism", 48, 3, "fp64"),
+         ("prism", 48, 4, "fp32"), ("prism", 48, 4, "fp64"), ("prism", 48, 4, "plain"),
+         ("mixed", 64, 4, "fp32"), ("tet", 48, 3, "fp32"), ("tet", 48, 3, "fp32_noaa"),
          ("pyr", 48, 3, "fp32"), ("hex_prism_pyr_tet", 48, 3, "fp32")]
 
 

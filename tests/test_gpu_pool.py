@@ -190,3 +190,35 @@ def test_pool_full_anti_aliasing_equals_rk4_step(kind):
     pool.submit(n=(2, 3, 2), p=2, kind="prism", nsteps=3, dt=dt, tgv_p0=inputs.P0)
     _drain(pool)
     assert np.array_equal(out, ref)
+
+
+def test_pool_failed_admission_does_not_disturb_the_round():
+    """A request whose host set-up fails (injected) leaves the queue as
+    failed; the requests admitted beside it and the ones already running
+    take exactly their own steps and end bit-identical to fr_rk4_step."""
+    _need_gpu()
+    print("pool failed admission", flush=True)
+    n, p, kind, dt = 3, 2, "hex", 2e-4
+    u0 = _init(n, p, kind, seed=5)
+    pool = frmi.Pool(1 << 28, max_active=4, prec="fp64", pref=inputs.P0, rho_ref=inputs.RHO0)
+    outs, steps = {}, {}
+    first = pool.submit(n=n, p=p, kind=kind, nsteps=4, dt=dt, u_init=u0, u_out=np.empty_like(u0))
+    outs[first], steps[first] = pool._keep[first][1], 4
+    pool.step()  # the first request is admitted and runs from the next round
+    bad = pool.submit(n=n, p=p, kind=kind, nsteps=3, dt=dt, u_init=u0)
+    pool.inject_prepare_error(bad)
+    last = pool.submit(n=n, p=p, kind=kind, nsteps=2, dt=dt, u_init=u0, u_out=np.empty_like(u0))
+    outs[last], steps[last] = pool._keep[last][1], 2
+    finished = []
+    for _ in range(100):
+        st, _, fin = pool.step()
+        finished += fin
+        if st["n_active"] == 0 and st["n_queued"] == 0 and st["n_admitted"] == 0:
+            break
+    assert bad in finished and pool.query(bad) == (frmi.Pool.FAILED, 0)
+    for rid, out in outs.items():
+        assert pool.query(rid) == (frmi.Pool.DONE, steps[rid])
+        s = frmi.Solver(n, p, kind, prec="fp64", pref=inputs.P0, rho_ref=inputs.RHO0)
+        s.set_state(u0)
+        s.rk4(dt, steps[rid])
+        assert np.array_equal(out, s.get_state())

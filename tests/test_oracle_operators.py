@@ -259,3 +259,40 @@ def test_prism_operators_factor_into_triangle_times_line(refs, p):
     Mt = T.T @ (tqw[:, None] * T)
     PT = np.linalg.solve(Mt.astype(np.float64), (T.T * tqw[None, :]).astype(np.float64))
     np.testing.assert_allclose(r.M8, np.kron(PL, PT), atol=1e-12)
+
+
+@pytest.mark.parametrize("p,key", [(2, "ws2"), (3, "ws3")])
+def test_prism_rhs_independent_of_the_triangle_point_set(p, key):
+    """With flux and surface-flux anti-aliasing on affine prisms every term
+    of the RHS is a projection or a DG lift of quantities evaluated at fixed
+    quadrature points, so du as a polynomial does not depend on where the
+    solution and flux points sit in the triangle.  The oracle on the
+    triangle points the paper prints (section 2.1 and section 4.1 figures)
+    and on its own point set must give the same polynomial: this pins the
+    prism's nodal basis, interpolation, projection and lifting operators
+    against a second point set that the oracle did not construct."""
+    from oracle.mesh import Mesh
+    from oracle.rhs import Params, rhs
+    from paper_2401_06132_amd import inputs
+
+    ws = _golden()[key].reshape(-1, 2)
+    assert len(ws) == (p + 1) * (p + 2) // 2
+    mb = Mesh(2, 2, 2, p, "prism", surf_aa=True)
+    mw = Mesh(2, 2, 2, p, "prism", tri_nodes=ws, surf_aa=True)
+    rb, rw = mb.refs["prism"], mw.refs["prism"]
+    Ub = inputs.element_state([mb.upts_coords("prism")], seed=4)[0]
+    L_bw, _ = basis.nodal("prism", p, rb.upts, rw.upts)  # own basis at the paper's points
+    L_wb, _ = basis.nodal("prism", p, rw.upts, rb.upts)
+    Uw = np.einsum("wu,evu->evw", np.asarray(L_bw, float), Ub)
+    par = Params(pref=inputs.P0, aa=True)
+    db = rhs(mb, {"prism": Ub}, par)["prism"]
+    dw = rhs(mw, {"prism": Uw}, par)["prism"]
+    got = np.einsum("bw,evw->evb", np.asarray(L_wb, float), dw)
+    err = np.abs(got - db).max(axis=(0, 2)) / np.abs(db).max(axis=(0, 2))
+    assert np.all(err < 1e-12), err
+    # without surface-flux anti-aliasing the interface flux is collocated
+    # at the flux points, which differ: the two results must differ
+    mb0 = Mesh(2, 2, 2, p, "prism")
+    mw0 = Mesh(2, 2, 2, p, "prism", tri_nodes=ws)
+    d0 = np.einsum("bw,evw->evb", np.asarray(L_wb, float), rhs(mw0, {"prism": Uw}, par)["prism"])
+    assert np.abs(d0 - rhs(mb0, {"prism": Ub}, par)["prism"]).max() > 1e-6

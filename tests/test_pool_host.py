@@ -77,3 +77,29 @@ def test_preparation_worker_starts_and_joins():
             pool.submit(n=n, p=p, kind=kind, nsteps=2, tgv_p0=1.0)
         time.sleep(wait)
         del pool
+
+
+def test_failed_preparation_leaves_the_queue():
+    """A request whose host set-up fails leaves the queue as failed before
+    any device work of the round, and the requests behind it stay queued.
+    Here the round's device work then fails for want of a GPU (or runs, on
+    a GPU machine); the request states are what is checked."""
+    import time
+
+    pool = frmi.Pool(64 << 20, max_active=4, prec="fp64")
+    ids = [pool.submit(n=3, p=2, kind="hex", nsteps=2, tgv_p0=1.0) for _ in range(3)]
+    pool.inject_prepare_error(ids[0])
+    with pytest.raises(frmi.FrError, match="FR_EINVAL"):
+        pool.inject_prepare_error(99)
+    for _ in range(200):  # until the preparation worker has reached request 0
+        try:
+            pool.step()
+        except frmi.FrError:
+            pass
+        if pool.query(ids[0])[0] == frmi.Pool.FAILED:
+            break
+        time.sleep(0.01)
+    assert pool.query(ids[0]) == (frmi.Pool.FAILED, 0)
+    assert pool.query(ids[1])[0] in (frmi.Pool.QUEUED, frmi.Pool.ACTIVE)
+    with pytest.raises(frmi.FrError, match="FR_EINVAL"):
+        pool.inject_prepare_error(ids[0])  # no longer queued

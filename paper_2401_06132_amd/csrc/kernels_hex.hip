@@ -126,23 +126,31 @@ struct HexDisuOps {
 //   L(rho v) = sum_d D_d (S m)_d,  S = det J J^-1,
 // the strong form (M1 - M3 M2) (S m) plus the lift of the own trace (exact
 // for affine elements: the projected polynomial flux is itself), written
-// to row 0 of the volume residual.
-template <int P, typename R, int EB, int NT, bool BT>
+// to row 0 of the volume residual.  DIAG (diagonal metric): (S m)_d is
+// S_dd m_d, n terms per point instead of 3n.
+// LDS: the state with its x lines padded to an odd length (n even), so that
+// the lanes of a wave walking x lines hit different banks.
+template <int P, typename R, int EB, int NT, bool BT, bool DIAG>
 __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __restrict__ bt,
                                                const Seg* __restrict__ segs, const bool from_ust,
                                                const HexDisuOps<P> op, const double eref, const double rho0,
                                                const bool lin) {
   using C = HexCfg<P>;
   constexpr int n = C::n, NU = C::NU, NFP = C::NFP;
+  constexpr int LX = n + 1 - (n & 1), NUP = LX * n * n;  // padded x line, padded field
   constexpr bool FB = sizeof(R) == 4;
-  __shared__ double sU[EB * 5 * NU];
+  __shared__ double sU[EB * 5 * NUP];
   __shared__ double sS[EB][9];
+  __shared__ double sB[FB ? EB : 1][6][5];  // single precision: the face bases, rounded
+  __shared__ double sD[n][n];  // D, read with a per-thread row index
   int e0;
   const Seg sg = seg_of<BT>(one, bt, segs, EB, e0);
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   R* __restrict__ Uf = (R*)sg.Uf;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
   constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
+  // point (i, a, b) of field v of element le in LDS
+  auto at = [](int le, int v, int i, int a, int b) { return (le * 5 + v) * NUP + i + LX * (a + n * b); };
   double xs[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -150,6 +158,7 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
     const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
     xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
   }
+  if (tid < n * n) sD[tid / n][tid % n] = op.D[tid / n][tid % n];
   if (lin && tid < EB * 9) {
     // S = det J J^-1 from the element metrics [J^-1 (row-major), det J]
     const int le = tid / 9, k = tid - le * 9;
@@ -161,47 +170,61 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
   for (int k = 0; k < NS; ++k) {
     const int it = tid + k * NT;
     if (it < EB * 5 * NU) {
-      const int r = it % (5 * NU);
+      const int le = it / (5 * NU), r = it - le * (5 * NU), v = r / NU, pt = r - v * NU;
       double x = xs[k];
-      if (r >= 4 * NU) x -= eref;
-      if (r < NU) x -= rho0;
-      sU[it] = x;
+      if (v == 4) x -= eref;
+      if (v == 0) x -= rho0;
+      sU[at(le, v, pt % n, (pt / n) % n, pt / (n * n))] = x;
     }
   }
   lds_barrier();
-  for (int it = tid; it < EB * 15 * NFP; it += NT) {
-    const int le = it / (15 * NFP), r0 = it - le * (15 * NFP);
-    const int ax = r0 / (5 * NFP), r1 = r0 - ax * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-    const int a = r % n, b = r / n, e = e0 + le;
-    if (e >= E) continue;
-    const double* X = sU + le * 5 * NU + v * NU;
-    double xm = 0.0, xp = 0.0;
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      const double x = X[hex_pt<n>(ax, i, a, b)];
-      xm += op.lb[i] * x;
-      xp += op.rb[i] * x;
-    }
-    const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
-    if constexpr (FB) {
-      // the face base: the value at the first flux point (a = b = 0)
+  if constexpr (FB) {
+    // the face bases: the values at the first flux point (a = b = 0)
+    for (int it = tid; it < EB * 15; it += NT) {
+      const int le = it / 15, r0 = it - le * 15, ax = r0 / 5, v = r0 - ax * 5, e = e0 + le;
       double bm = 0.0, bp = 0.0;
 #pragma unroll
       for (int i = 0; i < n; ++i) {
-        const double x = X[hex_pt<n>(ax, i, 0, 0)];
+        const double x = sU[ax == 0 ? at(le, v, i, 0, 0) : (ax == 1 ? at(le, v, 0, i, 0) : at(le, v, 0, 0, i))];
         bm += op.lb[i] * x;
         bp += op.rb[i] * x;
       }
       const float fm = float(bm), fp = float(bp);
-      Uf[s0 * 5 * NFP + v * NFP + r] = R(xm - double(fm));
-      Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = R(xp - double(fp));
-      if (r == 0) {
+      sB[le][2 * ax][v] = double(fm);
+      sB[le][2 * ax + 1][v] = double(fp);
+      if (e < E) {
+        const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
         sg.Ub[s0 * 5 + v] = fm;
         sg.Ub[(s0 + 1) * 5 + v] = fp;
       }
-    } else {
-      Uf[s0 * 5 * NFP + v * NFP + r] = R(xm);
-      Uf[(s0 + 1) * 5 * NFP + v * NFP + r] = R(xp);
+    }
+    lds_barrier();
+  }
+  // one line (axis, flux point) per item, all five fields along it
+  for (int it = tid; it < EB * 3 * NFP; it += NT) {
+    const int le = it / (3 * NFP), r0 = it - le * (3 * NFP), ax = r0 / NFP, r = r0 - ax * NFP;
+    const int a = r % n, b = r / n, e = e0 + le;
+    if (e >= E) continue;
+    const int si = ax == 0 ? 1 : (ax == 1 ? LX : LX * n);
+    const double* X = sU + le * 5 * NUP + (ax == 0 ? LX * (a + n * b) : (ax == 1 ? a + LX * n * b : a + LX * b));
+    const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
+    R* __restrict__ um = Uf + s0 * 5 * NFP + r;
+    R* __restrict__ up = um + 5 * NFP;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double xm = 0.0, xp = 0.0;
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const double x = X[v * NUP + i * si];
+        xm += op.lb[i] * x;
+        xp += op.rb[i] * x;
+      }
+      if constexpr (FB) {
+        xm -= sB[le][2 * ax][v];
+        xp -= sB[le][2 * ax + 1][v];
+      }
+      um[v * NFP] = R(xm);
+      up[v * NFP] = R(xp);
     }
   }
   if (!lin) return;
@@ -209,18 +232,26 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
   for (int it = tid; it < EB * NU; it += NT) {
     const int le = it / NU, s = it - le * NU, e = e0 + le;
     if (e >= E) continue;
-    const int ix[3] = {s % n, (s / n) % n, s / (n * n)};
-    const double* M = sU + le * 5 * NU + NU;  // momentum components
+    const int i = s % n, j = (s / n) % n, k = s / (n * n);
+    const int ix[3] = {i, j, k};
+    // the line through the point along each axis: start and stride in LDS
+    const int lb[3] = {LX * (j + n * k), i + LX * n * k, i + LX * j}, ls[3] = {1, LX, LX * n};
+    const double* M = sU + le * 5 * NUP + NUP;  // momentum components
     double acc = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int a = ix[d == 0 ? 1 : 0], b = ix[d == 2 ? 1 : 2];
+      double ad = 0.0;
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        const int pt = hex_pt<n>(d, q, a, b);
-        const double sm = sS[le][3 * d] * M[pt] + sS[le][3 * d + 1] * M[NU + pt] + sS[le][3 * d + 2] * M[2 * NU + pt];
-        acc += op.D[ix[d]][q] * sm;
+        const int o = lb[d] + q * ls[d];
+        if constexpr (DIAG) {
+          ad += sD[ix[d]][q] * M[d * NUP + o];
+        } else {
+          const double sm = sS[le][3 * d] * M[o] + sS[le][3 * d + 1] * M[NUP + o] + sS[le][3 * d + 2] * M[2 * NUP + o];
+          ad += sD[ix[d]][q] * sm;
+        }
       }
+      acc += DIAG ? sS[le][4 * d] * ad : ad;
     }
     Rp[(size_t)e * 5 * NU + s] = R(acc);
   }
@@ -1280,9 +1311,14 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
   constexpr int EBA = HEX_DISU_EB, NTA = 256, NTC = 256;
   const double eref = a.gas->pref / (a.gas->gamma - 1.0);
-  if ((a.stage & 1) && grid[K_DISU] > 0)
-    hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one, a.bt[K_DISU],
-                       a.segs, a.from_ust, make_disu_ops<P>(*a.ops), eref, a.gas->rho_ref, lin);
+  if ((a.stage & 1) && grid[K_DISU] > 0) {
+    if (a.diag && !a.warp)
+      hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT, true>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one,
+                         a.bt[K_DISU], a.segs, a.from_ust, make_disu_ops<P>(*a.ops), eref, a.gas->rho_ref, lin);
+    else
+      hipLaunchKernelGGL((hex_disu<P, R, EBA, NTA, BT, false>), dim3(grid[K_DISU]), dim3(NTA), 0, st, a.one,
+                         a.bt[K_DISU], a.segs, a.from_ust, make_disu_ops<P>(*a.ops), eref, a.gas->rho_ref, lin);
+  }
   // curved hexahedra (single meshes only; flux anti-aliasing, general metric)
   if constexpr (!BT) {
     if (a.warp) {

@@ -310,17 +310,21 @@ struct HexVol {
 // Loads of one batch of EB elements, held in registers: the state, face
 // records, face geometry and metrics first (independent loads), then the
 // neighbour face states (gathered through face records in LDS).  Every
-// thread issues all of its loads before the first use.
+// thread issues all of its loads before the first use.  The state is
+// loaded element by element (item r = tid + k NT of each element), so the
+// LDS position and the reference-state shift of an item follow from tid and
+// compile-time constants; the gather takes one neighbour flux point per item
+// with its five fields.
 template <int P, typename R, int EB, int NT, bool LIN>
 struct HexVolLoads {
   using C = HexVol<P, LIN>;
   static constexpr int NU = C::NU, NFP = C::NFP;
-  static constexpr int NS = (EB * 5 * NU + NT - 1) / NT;
-  static constexpr int NG = (EB * 30 * NFP + NT - 1) / NT;
+  static constexpr int NR = (5 * NU + NT - 1) / NT;         // state items per element
+  static constexpr int NG = (EB * 6 * NFP + NT - 1) / NT;   // neighbour flux points
   static constexpr int NF = (EB * 6 + NT - 1) / NT;
   static constexpr int NM = (EB * 10 + NT - 1) / NT;
-  double xs[NS];
-  R gv[NG];
+  double xs[EB][NR];
+  R gv[NG][5];
   FaceRec fr[NF];
   R fg[NF][4];
   R mt[NM];
@@ -332,10 +336,11 @@ struct HexVolLoads {
   __device__ __forceinline__ void load(const double* __restrict__ U, const FaceRec* __restrict__ faces,
                                        const R* __restrict__ fgeo, const R* __restrict__ met, int e0, int E,
                                        int slot_base, int tid) {
+    const int nv = E - e0 < EB ? E - e0 : EB;  // valid elements of the batch
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const int it = tid + k * NT;
-      const bool ok = it < EB * 6 && e0 + it / 6 < E;
+      const bool ok = it < nv * 6;
       const int slot = slot_base + (ok ? e0 * 6 + it : 0);
       fr[k] = faces[slot];
 #pragma unroll
@@ -344,15 +349,15 @@ struct HexVolLoads {
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
       const int it = tid + k * NT;
-      const bool ok = it < EB * 10 && e0 + it / 10 < E;
-      mt[k] = met[ok ? (size_t)e0 * 10 + it : 0];
+      mt[k] = met[it < nv * 10 ? (size_t)e0 * 10 + it : 0];
     }
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const int it = tid + k * NT;
-      const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
-      xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
-    }
+    for (int le = 0; le < EB; ++le)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int r = tid + k * NT;
+        xs[le][k] = U[le < nv && r < 5 * NU ? (size_t)(e0 + le) * 5 * NU + r : 0];
+      }
   }
   __device__ __forceinline__ void put_faces(FaceRec* sFR, R (*sFG)[4], int tid) const {
 #pragma unroll
@@ -370,20 +375,26 @@ struct HexVolLoads {
   // Single precision adds the neighbour face's base.
   __device__ __forceinline__ void gather(const R* __restrict__ Uf, const float* __restrict__ Ub,
                                          const FaceRec* sFR, const uint8_t* sPerm, int tid) {
-    R gb[NG];
+    R gb[NG][5];
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
       const int it = tid + k * NT;
-      const int itc = it < EB * 30 * NFP ? it : 0;
-      const int le = itc / (30 * NFP), r0 = itc - le * (30 * NFP);
-      const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-      const FaceRec q = sFR[le * 6 + f];
-      gv[k] = Uf[(size_t)q.nbr * 5 * NFP + v * NFP + sPerm[(q.info >> 1) * NFP + r]];
-      if constexpr (sizeof(R) == 4) gb[k] = Ub[(size_t)q.nbr * 5 + v];
+      const int itc = it < EB * 6 * NFP ? it : 0;
+      const int lf = itc / NFP, r = itc - lf * NFP;  // lf = le * 6 + f
+      const FaceRec q = sFR[lf];
+      const R* __restrict__ src = Uf + (size_t)q.nbr * 5 * NFP + sPerm[(q.info >> 1) * NFP + r];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) gv[k][v] = src[v * NFP];
+      if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gb[k][v] = Ub[(size_t)q.nbr * 5 + v];
+      }
     }
     if constexpr (sizeof(R) == 4) {
 #pragma unroll
-      for (int k = 0; k < NG; ++k) gv[k] += gb[k];
+      for (int k = 0; k < NG; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gv[k][v] += gb[k][v];
     }
   }
   // state in reference form, metrics and neighbour states to LDS (pe: LDS
@@ -396,22 +407,22 @@ struct HexVolLoads {
       if (it < EB * 10) sMet[it / 10][it % 10] = mt[k];
     }
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const int it = tid + k * NT;
-      if (it < EB * 5 * NU) {
-        const int le = it / (5 * NU), r = it - le * (5 * NU);
-        double x = xs[k];
-        if (r >= 4 * NU) x -= eref;
-        if (r < NU) x -= rho0;
-        smem[le * pe + r] = R(x);
+    for (int k = 0; k < NR; ++k) {
+      const int r = tid + k * NT;
+      if (r < 5 * NU) {
+        const double sh = r < NU ? rho0 : (r >= 4 * NU ? eref : 0.0);
+#pragma unroll
+        for (int le = 0; le < EB; ++le) smem[le * pe + r] = R(xs[le][k] - sh);
       }
     }
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
       const int it = tid + k * NT;
-      if (it < EB * 30 * NFP) {
-        const int le = it / (30 * NFP), r0 = it - le * (30 * NFP);
-        smem[le * pe + C::SZ_A + r0] = gv[k];
+      if (it < EB * 6 * NFP) {
+        const int lf = it / NFP, r = it - lf * NFP, le = lf / 6, f = lf - le * 6;
+        R* dst = smem + le * pe + C::SZ_A + f * 5 * NFP + r;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dst[v * NFP] = gv[k][v];
       }
     }
   }
@@ -896,7 +907,8 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int b = 0; b < m; ++b) {
         sx += op.Pj[j][b] * zx[b];
-        sy += op.AP[j][b] * zy[b] + op.Pj[j][b] * zz[b];
+        sy += op.AP[j][b] * zy[b];
+        sy += op.Pj[j][b] * zz[b];
       }
       Y[(((0 * NVF + v) * m + a) * YB + j) * n + l] = sx;
       Y[(((1 * NVF + v) * m + a) * YB + j) * n + l] = sy;
@@ -927,7 +939,10 @@ __global__ void __launch_bounds__(NT)
     for (int i = 0; i < n; ++i) {
       R s = (LIN && v + V0 == 4) ? g.kap * lin[i] : R(0);
 #pragma unroll
-      for (int a = 0; a < m; ++a) s += op.AP[i][a] * y0[a] + op.Pj[i][a] * y1[a];
+      for (int a = 0; a < m; ++a) {
+        s += op.AP[i][a] * y0[a];
+        s += op.Pj[i][a] * y1[a];
+      }
       Rp[(size_t)e * 5 * NU + (v + V0) * NU + i + n * (j + n * l)] = s;
     }
   }

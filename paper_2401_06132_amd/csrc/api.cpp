@@ -15,8 +15,8 @@
 #include "fr_kernels.h"
 #include "fr_plain.h"
 
-// Per-call work buffers of the fused form: face values Uf [slot][5][nfp],
-// transformed face fluxes Vf [slot][4][nfp], residual partials Rp (state
+// Per-call work buffers of the fused form: face values Uf [slot][5][points],
+// transformed face fluxes Vf [slot][4][points], residual partials Rp (state
 // layout) and, in single precision, the face bases Ub [slot][5] and the
 // constant transformed flux fbar [E][12] of the dense types.  None needs to
 // start at any particular value: every call writes each before reading it.
@@ -213,6 +213,8 @@ fr_status ensure_device(fr_ctx* c) {
   for (int64_t s = 0; s < S; ++s) {
     fr[s].nbr = (int32_t)M.nbr_slot[s];
     fr[s].info = (M.perm_id[s] << 1) | (M.is_left[s] ? 1 : 0);
+    fr[s].npo = (int32_t)M.slot_po[M.nbr_slot[s]];
+    fr[s].pad = 0;
     for (int d = 0; d < 3; ++d) geo[4 * s + d] = M.nrm[3 * s + d];
     geo[4 * s + 3] = M.mag[s];
   }
@@ -273,9 +275,9 @@ fr_status ensure_device(fr_ctx* c) {
 // in single precision, the face bases and the dense types' constant
 // transformed flux.  Returns the total with every buffer 256-byte aligned.
 int64_t work_bytes(const fr_ctx* c, int64_t bytes[Work::N]) {
-  const int64_t rs = (int64_t)rsize(c), nfp = (int64_t)(c->p + 1) * (c->p + 1), S = c->M.nslots;
-  bytes[Work::UF] = rs * S * 5 * nfp;
-  bytes[Work::VF] = rs * S * 4 * nfp;
+  const int64_t rs = (int64_t)rsize(c), S = c->M.nslots, NP = c->M.npts;
+  bytes[Work::UF] = rs * 5 * NP;
+  bytes[Work::VF] = rs * 4 * NP;
   bytes[Work::RP] = rs * c->n_state;
   bytes[Work::UB] = rs == 4 ? (int64_t)sizeof(float) * S * 5 : 0;
   for (int t = 0; t < fr::NTYPES; ++t)
@@ -337,6 +339,7 @@ fr::Seg seg_of_type(fr_ctx* c, int t, const double* u, double* du, const Work& w
   s.detj = c->d_detj[t];
   s.E = (int32_t)c->M.nel[t];
   s.slot_base = (int32_t)c->M.slot_base[t];
+  s.po_base = c->M.nel[t] > 0 ? (int32_t)c->M.slot_po[c->M.slot_base[t]] : 0;
   s.nperm = (int32_t)c->M.perms.size();
   s.verts = t < 2 ? c->d_verts[t] : nullptr;
   s.fbar = (float*)w.ptr[Work::FBAR + t];
@@ -419,6 +422,9 @@ fr_status setup_ctx_mesh(fr_ctx* c) {
   c->off[0] = 0;
   for (int t = 1; t < fr::NTYPES; ++t) c->off[t] = c->off[t - 1] + c->M.nel[t - 1] * 5 * c->ref[t - 1].nu;
   c->n_state = c->off[fr::NTYPES - 1] + c->M.nel[fr::NTYPES - 1] * 5 * c->ref[fr::NTYPES - 1].nu;
+  // the kernels index slots, face points and elements with 32-bit integers
+  if (c->M.nslots >= (int64_t)1 << 31 || c->M.npts >= (int64_t)1 << 31)
+    return fail(c, FR_EINVAL, "mesh too large: face slots or face points exceed 2^31");
   c->mesh_ok = true;
   return FR_OK;
 }

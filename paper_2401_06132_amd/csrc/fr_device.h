@@ -243,6 +243,8 @@ __device__ __forceinline__ void rusanov_jump(const R uL[5], const R jl[5], const
 struct FaceRec {
   int32_t nbr;   // paired slot
   int32_t info;  // (permutation id << 1) | is_left
+  int32_t npo;   // the paired slot's first point in the face arrays
+  int32_t pad;
 };
 
 }  // namespace fr

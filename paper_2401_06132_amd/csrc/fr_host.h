@@ -75,6 +75,14 @@ void build_ref(int etype, int p, RefElem& r);
 // element types of a mesh: 0 hexahedra, 1 prisms, 2 tetrahedra, 3 pyramids
 constexpr int NTYPES = 4;
 constexpr int kFacesOf[NTYPES] = {6, 5, 4, 5};
+// flux points of face f of type t at order p: n^2 on a quadrilateral
+// (hexahedron faces, prism faces 2..4, the pyramid base), n(n+1)/2 on a
+// triangle (prism faces 0, 1, tetrahedron faces, pyramid faces 1..4)
+inline int face_npts(int t, int f, int p) {
+  const int n = p + 1;
+  const bool quad = t == 0 || (t == 1 && f >= 2) || (t == 3 && f == 0);
+  return quad ? n * n : n * (n + 1) / 2;
+}
 // box mesh kinds: 0 hex, 1 prism, 2 hex (z < 0) + prism, 3 tet,
 // 4 prism (y < 0) + tet; 5, 6, 7: kinds 0, 1, 2 on the warped grid (curved);
 // 8 pyramid (six per cell), 9 hex (z < 0) + pyramid, 10 hex + pyramid +
@@ -100,6 +108,10 @@ struct Mesh {
   int64_t slot_base[NTYPES] = {};
   int64_t nslots = 0;
   std::vector<int64_t> nbr_slot;  // paired slot
+  // face data (states, viscous fluxes) are stored per slot with the slot's
+  // own number of points: slot s starts at point slot_po[s]; npts in all
+  std::vector<int64_t> slot_po;
+  int64_t npts = 0;
   std::vector<int32_t> perm_id;   // own point r -> neighbour point perms[perm_id][r]
   std::vector<uint8_t> is_left;
   // curved meshes: the vertices of every element, [E][nv][3] per type

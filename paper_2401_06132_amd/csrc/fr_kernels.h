@@ -56,13 +56,17 @@ struct Seg {
   double* ust = nullptr;  // RK stage state (input of stages 2-4)
   double* acc = nullptr;  // RK accumulator
   double* du = nullptr;   // right-hand side output (plain evaluation)
-  void* Uf = nullptr;     // face states [slot][5][n^2] (precision R), per mesh;
-                          // single precision: deviations from the face base
+  void* Uf = nullptr;     // face states (precision R), per mesh: slot s holds
+                          // [5][npts(s)] from value 5 po(s), po(s) the slot's
+                          // first point (npts: n^2 on quadrilaterals, n(n+1)/2
+                          // on triangles); single precision: deviations from
+                          // the face base
   float* Ub = nullptr;    // single precision: face bases [slot][5] (value at
                           // the face's first flux point); null in double
   float* fbar = nullptr;  // single precision, tetrahedra and pyramids: the
                           // element's constant transformed flux [E][3][4]
-  void* Vf = nullptr;     // normal viscous fluxes [slot][4][n^2], per mesh
+  void* Vf = nullptr;     // normal viscous fluxes, per mesh: [4][npts(s)] from
+                          // value 4 po(s)
   void* Rp = nullptr;     // volume divergence [E][5][N_u] (precision R)
   const FaceRec* faces = nullptr;
   const void* fgeo = nullptr;      // [slot][4]: L-side unit normal, own area factor (R)
@@ -72,6 +76,7 @@ struct Seg {
   double dt = 0.0;                 // RK time step of this mesh
   int32_t E = 0;                   // elements in the segment
   int32_t slot_base = 0;           // first face slot of this type in the mesh
+  int32_t po_base = 0;             // first point of that slot in the face arrays
   int32_t nperm = 0;               // face-point permutations in perms (<= MAX_PERMS)
   const void* verts = nullptr;     // curved hexahedra: [E][8][3] element vertices (R)
 };

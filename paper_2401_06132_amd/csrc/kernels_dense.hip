@@ -42,7 +42,10 @@ struct DenseCfg {
   static constexpr int NB = PYR ? n * n : 0;              // points on the pyramid base
   static constexpr int NF = NB + 4 * NTN;                 // flux points
   static constexpr int NQ = n * n * n;                    // quadrature points
-  static constexpr int NFPS = n * n;                      // face slot stride
+  static constexpr int NFPS = n * n;                      // permutation table stride
+  // face arrays: an element's faces are stored in flux-point order with
+  // their own point counts; face f has fsz(f) points
+  __host__ __device__ static constexpr int fsz(int f) { return (PYR && f == 0) ? NB : NTN; }
   static constexpr int KG = NU + NF;                      // gradient operator row
   // device table (working precision), row-major blocks
   static constexpr int O_M0 = 0;                 // [NF][NU]
@@ -171,7 +174,7 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
                                                const double eref, const double rho0, const bool lin) {
   using C = DenseCfg<ET, P>;
   using DD = DenseDisu<ET, P>;
-  constexpr int NU = C::NU, NF = C::NF, NFPS = C::NFPS, NFACE = C::NFACE;
+  constexpr int NU = C::NU, NF = C::NF, NFACE = C::NFACE;
   constexpr bool FB = sizeof(R) == 4;
   __shared__ double sU[EB * 5 * NU];
   __shared__ double sF[EB * 5 * NF];
@@ -213,10 +216,10 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
       // triangle's first node
       const int fp0 = (C::PYR && f == 0) ? 0 : C::NB + (f - int(C::PYR)) * C::NTN;
       const float b = float(sF[(le * 5 + v) * NF + fp0]);
-      Uf[slot * 5 * NFPS + v * NFPS + t] = R(x - double(b));
+      Uf[(size_t)(sg.po_base + e * NF + fp - t) * 5 + v * C::fsz(f) + t] = R(x - double(b));
       if (t == 0) sg.Ub[slot * 5 + v] = b;
     } else {
-      Uf[slot * 5 * NFPS + v * NFPS + t] = R(x);
+      Uf[(size_t)(sg.po_base + e * NF + fp - t) * 5 + v * C::fsz(f) + t] = R(x);
     }
   }
   if (!lin) return;
@@ -306,7 +309,7 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
     const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
     const FaceRec fr = sFR[le * NFACE + f];
-    R x = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    R x = Uf[(size_t)fr.npo * 5 + v * C::fsz(f) + sPerm[(fr.info >> 1) * NFPS + t]];
     if constexpr (FC) {
       // neighbour value relative to this element's base state
       const int e = e0 + le < E ? e0 + le : 0;
@@ -386,9 +389,9 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
     normal_viscous(u, q, nn, g, V);
-    const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
+    const size_t po = (size_t)(sg.po_base + e * NF + fp - t);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
+    for (int k = 0; k < 4; ++k) Vf[po * 4 + k * C::fsz(f) + t] = V[k];
   }
 
   if constexpr (!AA) {
@@ -624,7 +627,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
     const FaceRec fr = sFR[le * NFACE + f];
-    R x = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + sPerm[(fr.info >> 1) * NFPS + t]];
+    R x = Uf[(size_t)fr.npo * 5 + v * C::fsz(f) + sPerm[(fr.info >> 1) * NFPS + t]];
     if constexpr (FC) {
       // neighbour value relative to this element's base state
       const int e = e0 + le < E ? e0 + le : 0;
@@ -741,9 +744,9 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
     normal_viscous(u, q, nn, g, V);
-    const size_t slot = (size_t)(sg.slot_base + e * NFACE + f);
+    const size_t po = (size_t)(sg.po_base + e * NF + fp - t);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Vf[slot * 4 * NFPS + k * NFPS + t] = V[k];
+    for (int k = 0; k < 4; ++k) Vf[po * 4 + k * C::fsz(f) + t] = V[k];
   }
   lds_barrier();
 
@@ -890,11 +893,13 @@ __global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, 
     const FaceRec fr = sg.faces[slot];
     const int rr = sg.perms[(fr.info >> 1) * NFPS + t];
     const bool left = fr.info & 1;
+    const size_t po = (size_t)(sg.po_base + e * NF + fp - t);
+    const int fs = C::fsz(f);
     R uo[5], un[5], jn[5], Vo[4], Vn[4], F[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      uo[v] = Uf[(size_t)slot * 5 * NFPS + v * NFPS + t];
-      un[v] = Uf[(size_t)fr.nbr * 5 * NFPS + v * NFPS + rr];
+      uo[v] = Uf[po * 5 + v * fs + t];
+      un[v] = Uf[(size_t)fr.npo * 5 + v * fs + rr];
     }
     // u_nbr - u_own from the face bases and deviations (single precision),
     // before the states themselves are formed
@@ -911,8 +916,8 @@ __global__ void __launch_bounds__(NT) dense_surface(const Seg sg, const int rk, 
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Vo[k] = Vf[(size_t)slot * 4 * NFPS + k * NFPS + t];
-      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFPS + k * NFPS + rr];
+      Vo[k] = Vf[po * 4 + k * fs + t];
+      Vn[k] = Vf[(size_t)fr.npo * 4 + k * fs + rr];
     }
     const R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
     const R mag = fgeo[4 * slot + 3];
@@ -1100,7 +1105,7 @@ struct DenseLaunch {
   static constexpr int MX = MX0 > EB * C::NF ? MX0 : EB * C::NF;
   static constexpr int NT = (MX + 63) / 64 * 64;
 };
-constexpr int DENSE_DISU_EB = 8, DENSE_SURF_EB = 8;
+constexpr int DENSE_DISU_EB = 8, DENSE_DISU_NT = 256, DENSE_SURF_EB = 8;
 
 template <int ET, int P, typename R>
 static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
@@ -1113,8 +1118,9 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
   const int E = a.one.E;
   constexpr int EB = DenseLaunch<ET, P>::EB, NTV = DenseLaunch<ET, P>::NT;
   if ((a.stage & 1) && E > 0)
-    hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, 256>), dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB),
-                       dim3(256), 0, st, a.one, a.from_ust, dops, eref, rho0, true);
+    hipLaunchKernelGGL((dense_disu<ET, P, R, DENSE_DISU_EB, DENSE_DISU_NT>),
+                       dim3((E + DENSE_DISU_EB - 1) / DENSE_DISU_EB), dim3(DENSE_DISU_NT), 0, st, a.one, a.from_ust,
+                       dops, eref, rho0, true);
   if ((a.stage & 2) && E > 0) {
     // p >= 3 on the matrix cores.  With anti-aliasing at 48^3 cells the
     // volume group runs 14-42% faster than the VALU kernel in FP32 and

@@ -207,8 +207,7 @@ __global__ void __launch_bounds__(NT) hex_disu(const Seg one, const BlkRef* __re
     if (e >= E) continue;
     const int si = ax == 0 ? 1 : (ax == 1 ? LX : LX * n);
     const double* X = sU + le * 5 * NUP + (ax == 0 ? LX * (a + n * b) : (ax == 1 ? a + LX * n * b : a + LX * b));
-    const size_t s0 = (size_t)(slot_base + e * 6 + 2 * ax);
-    R* __restrict__ um = Uf + s0 * 5 * NFP + r;
+    R* __restrict__ um = Uf + (size_t)(sg.po_base + (e * 6 + 2 * ax) * NFP) * 5 + r;
     R* __restrict__ up = um + 5 * NFP;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -382,7 +381,7 @@ struct HexVolLoads {
       const int itc = it < EB * 6 * NFP ? it : 0;
       const int lf = itc / NFP, r = itc - lf * NFP;  // lf = le * 6 + f
       const FaceRec q = sFR[lf];
-      const R* __restrict__ src = Uf + (size_t)q.nbr * 5 * NFP + sPerm[(q.info >> 1) * NFP + r];
+      const R* __restrict__ src = Uf + (size_t)q.npo * 5 + sPerm[(q.info >> 1) * NFP + r];
 #pragma unroll
       for (int v = 0; v < 5; ++v) gv[k][v] = src[v * NFP];
       if constexpr (sizeof(R) == 4) {
@@ -649,13 +648,13 @@ __global__ void __launch_bounds__(NT)
           for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * VQ[a2 * m + b2];
           z[a2] = s;
         }
-        const size_t slot = (size_t)(slot_base + e * 6 + 2 * ax + side);
+        const size_t po = (size_t)(sg.po_base + (e * 6 + 2 * ax + side) * NFP);
 #pragma unroll
         for (int a = 0; a < n; ++a) {
           R s = R(0);
 #pragma unroll
           for (int a2 = 0; a2 < m; ++a2) s += op.Pj[a][a2] * z[a2];
-          Vf[slot * 4 * NFP + k * NFP + a + n * b] = s;
+          Vf[po * 4 + k * NFP + a + n * b] = s;
         }
       }
     }
@@ -685,7 +684,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const R* w = side ? fp : fm;
-      const int lf = le * 6 + 2 * ax + side, slot = slot_base + e * 6 + 2 * ax + side;
+      const int lf = le * 6 + 2 * ax + side, po = sg.po_base + (e * 6 + 2 * ax + side) * NFP;
       R nn[3];
       if constexpr (WARP) {
         // own outward unit normal at this flux point: +-S_ax / |S_ax|
@@ -709,7 +708,7 @@ __global__ void __launch_bounds__(NT)
       }
       normal_viscous(u, q, nn, g, V);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Vf[(size_t)slot * 4 * NFP + k * NFP + r] = V[k];
+      for (int k = 0; k < 4; ++k) Vf[(size_t)po * 4 + k * NFP + r] = V[k];
     }
   }
   }
@@ -1045,13 +1044,14 @@ __global__ void __launch_bounds__(NT)
       const int it = tid + q * NT;
       const int itc = it < EB * 6 * NFP ? it : 0;
       const int le = itc / (6 * NFP), r0 = itc - le * (6 * NFP), f = r0 / NFP, r = r0 - f * NFP;
-      const int slot = slot_base + (e0 + le < E ? (e0 + le) * 6 + f : 0);
+      const int ls = e0 + le < E ? (e0 + le) * 6 + f : 0, slot = slot_base + ls;
+      const size_t po = (size_t)(sg.po_base + ls * NFP);
       const FaceRec fr = sFR[le * 6 + f];
       const int rr = sPerm[(fr.info >> 1) * NFP + r];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        uo[q][v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
-        un[q][v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+        uo[q][v] = Uf[po * 5 + v * NFP + r];
+        un[q][v] = Uf[(size_t)fr.npo * 5 + v * NFP + rr];
       }
       if constexpr (FB) {
 #pragma unroll
@@ -1068,8 +1068,8 @@ __global__ void __launch_bounds__(NT)
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        Vo[q][k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
-        Vn[q][k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
+        Vo[q][k] = Vf[po * 4 + k * NFP + r];
+        Vn[q][k] = Vf[(size_t)fr.npo * 4 + k * NFP + rr];
       }
     }
 #pragma unroll

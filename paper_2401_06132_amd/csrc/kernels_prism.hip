@@ -89,6 +89,11 @@ template <int P>
 struct PrismCfg {
   static constexpr int n = P + 1, m = P + 3, NT = (P + 1) * (P + 2) / 2, NTQ = (P + 1) * (P + 1);
   static constexpr int NU = NT * n, NFP = n * n;
+  // face arrays: an element's faces are stored with their own point counts,
+  // the two triangles (NT points) then the three quadrilaterals (n^2)
+  static constexpr int PPE = 2 * NT + 3 * NFP;
+  __host__ __device__ static constexpr int fsz(int f) { return f < 2 ? NT : NFP; }
+  __host__ __device__ static constexpr int foff(int f) { return f < 2 ? f * NT : 2 * NT + (f - 2) * NFP; }
   static constexpr int SZ_X = 20 * NU;
   static constexpr int SZ_J = 25 * NFP;  // 5 faces x 5 variables
   static constexpr int SZ_Z = 15 * NTQ * n;
@@ -191,17 +196,19 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
       bp += tab->rb[k] * X[NT * k];
     }
     const size_t s0 = (size_t)(slot_base + e * 5);
+    R* __restrict__ um = Uf + (size_t)(sg.po_base + e * C::PPE) * 5 + v * NT + t;  // face 0
+    R* __restrict__ up = um + 5 * NT;                                               // face 1
     if constexpr (FB) {
       const float fm = float(bm), fp = float(bp);
-      Uf[s0 * 5 * NFP + v * NFP + t] = R(xm - double(fm));
-      Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = R(xp - double(fp));
+      *um = R(xm - double(fm));
+      *up = R(xp - double(fp));
       if (t == 0) {
         sg.Ub[s0 * 5 + v] = fm;
         sg.Ub[(s0 + 1) * 5 + v] = fp;
       }
     } else {
-      Uf[s0 * 5 * NFP + v * NFP + t] = R(xm);
-      Uf[(s0 + 1) * 5 * NFP + v * NFP + t] = R(xp);
+      *um = R(xm);
+      *up = R(xp);
     }
   }
   // quadrilateral faces: triangle-plane interpolation to the edge points;
@@ -226,7 +233,7 @@ __global__ void __launch_bounds__(NT_) prism_disu(const Seg one, const BlkRef* _
         double s = 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) s += tab->Tedge[ed][i][t] * X[t + NT * k];
-        Uf[slot * 5 * NFP + v * NFP + i + n * k] = R(FB ? s - double(fb) : s);
+        Uf[(size_t)(sg.po_base + e * C::PPE + C::foff(2 + ed)) * 5 + v * NFP + i + n * k] = R(FB ? s - double(fb) : s);
       }
     }
   }
@@ -339,6 +346,7 @@ __global__ void __launch_bounds__(NT_)
   using C = PrismVol<P, LIN>;
   constexpr int n = C::n, m = C::m, NTN = C::NTN, NTQ = C::NTQ, NU = C::NU, NFP = C::NFP;
   constexpr int NVF = C::NVF, V0 = C::V0;
+  using F = PrismCfg<P>;  // face array layout
   // single precision up to p = 3: triangle-plane work one (field, plane) per
   // thread with broadcast operator reads (enough planes fill the workgroup);
   // otherwise one output point per thread
@@ -405,46 +413,64 @@ __global__ void __launch_bounds__(NT_)
     const int le = it / 10, k = it - le * 10, e = e0 + le;
     sMet[le][k] = met[e < E ? (size_t)e * 10 + k : 0];
   }
-  constexpr int NS = (EB * 5 * NU + NT_ - 1) / NT_;
-  double xs[NS];
+  // the state element by element (item r = tid + k NT_ of each element: its
+  // LDS position and reference-state shift follow from tid and constants)
+  const int nv = E - e0 < EB ? E - e0 : EB;  // valid elements of the batch
+  constexpr int NR = (5 * NU + NT_ - 1) / NT_;
+  double xs[EB][NR];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int it = tid + k * NT_;
-    const bool ok = it < EB * 5 * NU && e0 + it / (5 * NU) < E;
-    xs[k] = U[ok ? (size_t)e0 * 5 * NU + it : 0];
-  }
+  for (int le = 0; le < EB; ++le)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = tid + k * NT_;
+      xs[le][k] = U[le < nv && r < 5 * NU ? (size_t)(e0 + le) * 5 * NU + r : 0];
+    }
   lds_barrier();
-  constexpr int NG = (EB * 25 * NFP + NT_ - 1) / NT_;
-  R gv[NG];
+  // neighbour face values: one own flux point per item with its five fields
+  // (the element's points in face-array order: two triangles, three
+  // quadrilaterals); out-of-range items read the first item's addresses
+  constexpr int NG = (EB * F::PPE + NT_ - 1) / NT_;
+  R gv[NG][5], gb[NG][5];
+  auto face_point = [](int q, int& f, int& r) {
+    f = q < 2 * NTN ? q / NTN : 2 + (q - 2 * NTN) / NFP;
+    r = q - F::foff(f);
+  };
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
     const int it = tid + k * NT_;
-    const int itc = it < EB * 25 * NFP ? it : 0;
-    const int le = itc / (25 * NFP), r0 = itc - le * (25 * NFP);
-    const int f = r0 / (5 * NFP), r1 = r0 - f * (5 * NFP), v = r1 / NFP, r = r1 - v * NFP;
-    // triangle faces have NTN < NFP points: the unused tail reads point 0
-    const int rr = (f >= 2 || r < NTN) ? r : 0;
+    const int itc = it < EB * F::PPE ? it : 0;
+    const int le = itc / F::PPE;
+    int f, r;
+    face_point(itc - le * F::PPE, f, r);
     const FaceRec fr = sFR[le * 5 + f];
-    gv[k] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + sPerm[(fr.info >> 1) * NFP + rr]];
-    if constexpr (sizeof(R) == 4) gv[k] += sg.Ub[(size_t)fr.nbr * 5 + v];  // the face base
+    const R* __restrict__ src = Uf + (size_t)fr.npo * 5 + sPerm[(fr.info >> 1) * NFP + r];
+    const int fs = F::fsz(f);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gv[k][v] = src[v * fs];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) gb[k][v] = sg.Ub[(size_t)fr.nbr * 5 + v];  // the face base
+    }
   }
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int it = tid + k * NT_;
-    if (it < EB * 5 * NU) {
-      const int le = it / (5 * NU), r = it - le * (5 * NU);
-      double x = xs[k];
-      if (r >= 4 * NU) x -= eref;
-      if (r < NU) x -= rho0;
-      XS(le)[r] = R(x);
+  for (int k = 0; k < NR; ++k) {
+    const int r = tid + k * NT_;
+    if (r < 5 * NU) {
+      const double sh = r < NU ? rho0 : (r >= 4 * NU ? eref : 0.0);
+#pragma unroll
+      for (int le = 0; le < EB; ++le) XS(le)[r] = R(xs[le][k] - sh);
     }
   }
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
     const int it = tid + k * NT_;
-    if (it < EB * 25 * NFP) {
-      const int le = it / (25 * NFP), r0 = it - le * (25 * NFP);
-      JS(le)[r0] = gv[k];
+    if (it < EB * F::PPE) {
+      const int le = it / F::PPE;
+      int f, r;
+      face_point(it - le * F::PPE, f, r);
+      R* dst = JS(le) + f * 5 * NFP + r;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) dst[v * NFP] = sizeof(R) == 4 ? gv[k][v] + gb[k][v] : gv[k][v];
     }
   }
   lds_barrier();
@@ -669,7 +695,7 @@ __global__ void __launch_bounds__(NT_)
       R s = R(0);
 #pragma unroll
       for (int q = 0; q < NTQ; ++q) s += tri.PT[t][q] * VT[q];
-      Vf[(size_t)(slot_base + e * 5 + side) * 4 * NFP + k * NFP + t] = s;
+      Vf[(size_t)(sg.po_base + e * F::PPE + side * NTN) * 4 + k * NTN + t] = s;
     }
     // quadrilateral rounds: their S1 overwrites the triangle-node fields (read
     // before the last barrier) and their S2 the triangle viscous fluxes (read
@@ -745,13 +771,13 @@ __global__ void __launch_bounds__(NT_)
           for (int b2 = 0; b2 < m; ++b2) s += pb[b2] * VQ[a2 * m + b2];
           z[a2] = s;
         }
-        const size_t slot = (size_t)(slot_base + e * 5 + 2 + ed);
+        const size_t po = (size_t)(sg.po_base + e * F::PPE + F::foff(2 + ed));
 #pragma unroll
         for (int i = 0; i < n; ++i) {
           R s = R(0);
 #pragma unroll
           for (int a2 = 0; a2 < m; ++a2) s += op.Pj[i][a2] * z[a2];
-          Vf[slot * 4 * NFP + k * NFP + i + n * b] = s;
+          Vf[po * 4 + k * NFP + i + n * b] = s;
         }
       }
     }
@@ -804,7 +830,7 @@ __global__ void __launch_bounds__(NT_)
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const R* w = side ? fp : fm;
-        const int lf = le * 5 + side, slot = slot_base + e * 5 + side;
+        const int lf = le * 5 + side, po = sg.po_base + e * F::PPE + side * NTN;
         R nn[3];
         if constexpr (WARP) {
           // own outward unit normal: +-S_zeta / |S_zeta| at the triangle node
@@ -827,11 +853,11 @@ __global__ void __launch_bounds__(NT_)
         }
         normal_viscous(u, q, nn, g, V);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + t] = V[kk];
+        for (int kk = 0; kk < 4; ++kk) Vf[(size_t)po * 4 + kk * NTN + t] = V[kk];
       }
     } else {
       const int r1 = r0 - NV_TRI, ed = r1 / (n * n), r2 = r1 - ed * (n * n), k = r2 / n, i = r2 - k * n;
-      const int lf = le * 5 + 2 + ed, slot = slot_base + e * 5 + 2 + ed;
+      const int lf = le * 5 + 2 + ed, po = sg.po_base + e * F::PPE + F::foff(2 + ed);
       R nn[3];
       if constexpr (WARP) {
         // own outward unit normal: (nx S_xi + ny S_eta) normalised at the edge point
@@ -867,7 +893,7 @@ __global__ void __launch_bounds__(NT_)
       }
       normal_viscous(u, q, nn, g, V);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) Vf[(size_t)slot * 4 * NFP + kk * NFP + i + n * k] = V[kk];
+      for (int kk = 0; kk < 4; ++kk) Vf[(size_t)po * 4 + kk * NFP + i + n * k] = V[kk];
     }
   }
   }
@@ -1193,8 +1219,11 @@ __global__ void __launch_bounds__(NT_)
       if (t < NTN) {
         R s = (LIN && v == 4) ? g.kap * Rp[(size_t)e * 5 * NU + t + NTN * k] : R(0);
 #pragma unroll
-        for (int tq = 0; tq < NTQ; ++tq)
-          s += tri.APxi[t][tq] * z0[tq] + tri.APeta[t][tq] * z1[tq] + tri.PT[t][tq] * z2[tq];
+        for (int tq = 0; tq < NTQ; ++tq) {
+          s += tri.APxi[t][tq] * z0[tq];
+          s += tri.APeta[t][tq] * z1[tq];
+          s += tri.PT[t][tq] * z2[tq];
+        }
         Rp[(size_t)e * 5 * NU + v * NU + t + NTN * k] = s;
       }
     }
@@ -1250,7 +1279,6 @@ __global__ void __launch_bounds__(NT_)
   const uint8_t* __restrict__ perms = sg.perms;
   const double* __restrict__ detj = sg.detj;
   const int E = sg.E, slot_base = sg.slot_base, tid = threadIdx.x;
-  const int fnp[5] = {NT, NT, NFP, NFP, NFP};
   // edge lifting table, staged in LDS for the per-point lift below
   for (int it = tid; it < 3 * NT * n; it += NT_) (&sLift[0][0][0])[it] = (&tri->LiftEdge[0][0][0])[it];
   if constexpr (WARP) {
@@ -1273,18 +1301,24 @@ __global__ void __launch_bounds__(NT_)
   }
   // comm_flux: common normal flux at every own flux point, times +-mag
   // (with SAA: its linear part, and the pair of states to LDS)
-  for (int it = tid; it < EB * 5 * NFP; it += NT_) {
-    const int le = it / (5 * NFP), r0 = it - le * (5 * NFP), f = r0 / NFP, r = r0 - f * NFP, e = e0 + le;
-    if (e >= E || r >= fnp[f]) continue;
+  // one own flux point per item, the element's points in face-array order
+  // (two triangles, three quadrilaterals)
+  for (int it = tid; it < EB * C::PPE; it += NT_) {
+    const int le = it / C::PPE, q = it - le * C::PPE, e = e0 + le;
+    if (e >= E) continue;
+    const int f = q < 2 * NT ? q / NT : 2 + (q - 2 * NT) / NFP, r = q - C::foff(f);
     const int slot = slot_base + e * 5 + f;
     const FaceRec fr = faces[slot];
     const int rr = perms[(fr.info >> 1) * NFP + r];
     const bool left = fr.info & 1;
+    // this face's points in the face arrays: own and paired
+    const int fs = C::fsz(f);
+    const size_t po = (size_t)(sg.po_base + e * C::PPE + q - r);
     R uo[5], un[5], jn[5], Vo[4], Vn[4], F[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      uo[v] = Uf[(size_t)slot * 5 * NFP + v * NFP + r];
-      un[v] = Uf[(size_t)fr.nbr * 5 * NFP + v * NFP + rr];
+      uo[v] = Uf[po * 5 + v * fs + r];
+      un[v] = Uf[(size_t)fr.npo * 5 + v * fs + rr];
     }
     // u_nbr - u_own from the face bases and deviations (single precision),
     // before the states themselves are formed
@@ -1301,8 +1335,8 @@ __global__ void __launch_bounds__(NT_)
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Vo[k] = Vf[(size_t)slot * 4 * NFP + k * NFP + r];
-      Vn[k] = Vf[(size_t)fr.nbr * 4 * NFP + k * NFP + rr];
+      Vo[k] = Vf[po * 4 + k * fs + r];
+      Vn[k] = Vf[(size_t)fr.npo * 4 + k * fs + rr];
     }
     R nL[3] = {fgeo[4 * slot], fgeo[4 * slot + 1], fgeo[4 * slot + 2]};
     R mag = fgeo[4 * slot + 3];

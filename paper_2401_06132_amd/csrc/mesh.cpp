@@ -403,6 +403,17 @@ static std::string finish_mesh(Mesh& M, const RefElem* refs[NTYPES], const doubl
   for (int t = 1; t < NTYPES; ++t) M.slot_base[t] = M.slot_base[t - 1] + M.nel[t - 1] * kFacesOf[t - 1];
   M.nslots = M.slot_base[NTYPES - 1] + M.nel[NTYPES - 1] * kFacesOf[NTYPES - 1];
   const int64_t S = M.nslots;
+  M.slot_po.resize(S);
+  {
+    int64_t po = 0, s = 0;
+    for (int t = 0; t < NTYPES; ++t)
+      for (int64_t e = 0; e < M.nel[t]; ++e)
+        for (int f = 0; f < kFacesOf[t]; ++f) {
+          M.slot_po[s++] = po;
+          po += face_npts(t, f, M.p);
+        }
+    M.npts = po;
+  }
 
   // lattice coordinates: c_lat = B (c - lo), B the inverse of the matrix
   // whose columns are the period vectors

@@ -75,7 +75,7 @@ class Arena {
 
 // byte offsets of one request's arrays inside its arena block
 struct Layout {
-  int64_t nel[fr::NTYPES] = {}, nu[2] = {0, 0}, n_state = 0, nslots = 0, nfp = 0;
+  int64_t nel[fr::NTYPES] = {}, nu[2] = {0, 0}, n_state = 0, nslots = 0, nfp = 0, npts = 0;
   size_t state = 0, ust = 0, acc = 0, Rp = 0, Uf = 0, Ub = 0, Vf = 0, faces = 0, fgeo = 0, perms = 0;
   size_t met[2] = {0, 0}, detj[2] = {0, 0}, total = 0;
 };
@@ -89,6 +89,9 @@ Layout make_layout(const fr_request& q, int rs) {
   L.nfp = (int64_t)n * n;
   L.n_state = 5 * (L.nel[0] * L.nu[0] + L.nel[1] * L.nu[1]);
   L.nslots = 6 * L.nel[0] + 5 * L.nel[1];
+  // face points: six quadrilaterals per hexahedron, two triangles and three
+  // quadrilaterals per prism
+  L.npts = 6 * L.nfp * L.nel[0] + (n * (n + 1) + 3 * L.nfp) * L.nel[1];
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -99,9 +102,9 @@ Layout make_layout(const fr_request& q, int rs) {
   L.ust = take(8 * L.n_state);
   L.acc = take(8 * L.n_state);
   L.Rp = take((size_t)rs * L.n_state);
-  L.Uf = take((size_t)rs * L.nslots * 5 * L.nfp);
+  L.Uf = take((size_t)rs * 5 * L.npts);
   if (rs == 4) L.Ub = take(sizeof(float) * 5 * L.nslots);  // single precision: face bases
-  L.Vf = take((size_t)rs * L.nslots * 4 * L.nfp);
+  L.Vf = take((size_t)rs * 4 * L.npts);
   L.faces = take(sizeof(fr::FaceRec) * L.nslots);
   L.fgeo = take((size_t)rs * 4 * L.nslots);
   L.perms = take((size_t)fr::MAX_PERMS * L.nfp);
@@ -118,7 +121,7 @@ Layout make_layout(const fr_request& q, int rs) {
 // state) element origins and Jacobians.  Built off the critical path.
 struct Prepared {
   std::string err;  // non-empty: the mesh could not be built
-  int64_t nel[2] = {0, 0}, slot_base[2] = {0, 0}, nslots = 0;
+  int64_t nel[2] = {0, 0}, slot_base[2] = {0, 0}, po_base[2] = {0, 0}, nslots = 0, npts = 0;
   int nperm = 0;
   bool diag[2] = {false, false};
   std::vector<fr::FaceRec> faces;
@@ -155,10 +158,13 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[f
   }
   const int64_t S = M.nslots;
   R.nslots = S;
+  R.npts = M.npts;
   R.faces.resize(S);
   std::vector<double> geo(4 * S);
   for (int64_t i = 0; i < S; ++i) {
     R.faces[i].nbr = (int32_t)M.nbr_slot[i];
+    R.faces[i].npo = (int32_t)M.slot_po[M.nbr_slot[i]];
+    R.faces[i].pad = 0;
     R.faces[i].info = (M.perm_id[i] << 1) | (M.is_left[i] ? 1 : 0);
     for (int d = 0; d < 3; ++d) geo[4 * i + d] = M.nrm[3 * i + d];
     geo[4 * i + 3] = M.mag[i];
@@ -175,6 +181,7 @@ std::shared_ptr<Prepared> prepare(const fr_request& q, const fr::RefElem* refs[f
     const int64_t E = M.nel[t];
     R.nel[t] = E;
     R.slot_base[t] = M.slot_base[t];
+    R.po_base[t] = E > 0 ? M.slot_po[M.slot_base[t]] : 0;
     std::vector<double> met(10 * E);
     bool d = true;
     for (int64_t e = 0; e < E; ++e) {
@@ -400,7 +407,7 @@ fr_status admit(fr_pool* P, Req& R) {
   const Prepared& M = *pr;
   P->staged_preps.push_back(pr);
   const Layout& L = R.L;
-  if (M.nel[0] != L.nel[0] || M.nel[1] != L.nel[1] || M.nslots != L.nslots)
+  if (M.nel[0] != L.nel[0] || M.nel[1] != L.nel[1] || M.nslots != L.nslots || M.npts != L.npts)
     return pfail(P, FR_EINVAL, "mesh sizes differ from the footprint layout");
   char* b = R.base;
   s = upload_raw(P, b + L.faces, M.faces.data(), sizeof(fr::FaceRec) * M.faces.size());
@@ -434,6 +441,7 @@ fr_status admit(fr_pool* P, Req& R) {
     g.dt = q.dt;
     g.E = (int32_t)E;
     g.slot_base = (int32_t)M.slot_base[t];
+    g.po_base = (int32_t)M.po_base[t];
     g.nperm = M.nperm;
     if (!q.u_init) {
       // Taylor-Green state from element origins, Jacobians and reference points

@@ -17,7 +17,8 @@ def _expected_bytes(n, p, kind, rs):
     nu = [k ** 3, k * k * (k + 1) // 2]
     ns = 5 * (ne[0] * nu[0] + ne[1] * nu[1])
     slots = 6 * ne[0] + 5 * ne[1]
-    parts = [8 * ns, 8 * ns, 8 * ns, rs * ns, rs * slots * 5 * k * k, rs * slots * 4 * k * k, 8 * slots,
+    pts = 6 * k * k * ne[0] + (k * (k + 1) + 3 * k * k) * ne[1]  # quadrilateral and triangle faces
+    parts = [8 * ns, 8 * ns, 8 * ns, rs * ns, rs * 5 * pts, rs * 4 * pts, 16 * slots,
              rs * 4 * slots, 16 * k * k]
     if rs == 4:
         parts.append(4 * 5 * slots)  # single precision: one float base per face and variable

@@ -596,7 +596,24 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   for (int it = tid; it < EB * PE; it += NT) smem[it] = R(0);
   lds_barrier();
 
-  // phase 0: as in dense_volume (neighbour face values into U2 as [5][NF])
+  // phase 0: as in dense_volume (neighbour face values into U2 as [5][NF]).
+  // Every thread issues its state loads before the first barrier and its
+  // gather loads after it, each set before the first use, so that a
+  // thread's loads are in flight together; out-of-range items read valid
+  // addresses and are not stored.
+  const int nv = E - e0 < EB ? E - e0 : EB;  // valid elements of the workgroup
+  constexpr int NSL = (EB * 5 * NU + NT - 1) / NT, NGL = (EB * 5 * NF + NT - 1) / NT;
+  double xs[NSL];
+  float xb[FC ? NSL : 1];
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int it = tid + k * NT;
+    const bool ok = it < nv * 5 * NU;
+    const int itc = ok ? it : 0, le = itc / (5 * NU), r = itc - le * (5 * NU);
+    xs[k] = U[(size_t)e0 * 5 * NU + itc];
+    // single precision: the element's base state (the base of its first face)
+    if constexpr (FC) xb[k] = sg.Ub[(size_t)(sg.slot_base + (e0 + le) * NFACE) * 5 + r / NU];
+  }
   for (int it = tid; it < EB * NFACE; it += NT) {
     const int slot = sg.slot_base + (e0 + it / NFACE < E ? e0 * NFACE + it : 0);
     sFR[it] = sg.faces[slot];
@@ -608,32 +625,46 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int le = it / 10, k = it - le * 10;
     sMet[le][k] = met[e0 + le < E ? (size_t)(e0 + le) * 10 + k : 0];
   }
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const int le = it / (5 * NU), r = it - le * (5 * NU);
-    double x = U[e0 + le < E ? (size_t)e0 * 5 * NU + it : 0];
-    if (r >= 4 * NU) x -= eref;
-    if (r < NU) x -= rho0;
-    if constexpr (FC) {
-      // the state as deviations from the element's base state u_b (the base
-      // of its first face): the linear operators then round the variation
-      // within the element instead of the O(1) values
-      const int e = e0 + le < E ? e0 + le : 0;
-      x -= double(sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + r / NU]);
-    }
-    XS(le)[r] = R(x);
-  }
   lds_barrier();
-  for (int it = tid; it < EB * 5 * NF; it += NT) {
-    const int le = it / (5 * NF), r0 = it - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
+  R gx[NGL];
+  float gn[FC ? NGL : 1], go[FC ? NGL : 1];
+#pragma unroll
+  for (int k = 0; k < NGL; ++k) {
+    const int it = tid + k * NT;
+    const int itc = it < EB * 5 * NF ? it : 0;
+    const int le = itc / (5 * NF), r0 = itc - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
     const FaceRec fr = sFR[le * NFACE + f];
-    R x = Uf[(size_t)fr.npo * 5 + v * C::fsz(f) + sPerm[(fr.info >> 1) * NFPS + t]];
+    gx[k] = Uf[(size_t)fr.npo * 5 + v * C::fsz(f) + sPerm[(fr.info >> 1) * NFPS + t]];
     if constexpr (FC) {
       // neighbour value relative to this element's base state
-      const int e = e0 + le < E ? e0 + le : 0;
-      x += sg.Ub[(size_t)fr.nbr * 5 + v] - sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+      const int e = le < nv ? e0 + le : e0;
+      gn[k] = sg.Ub[(size_t)fr.nbr * 5 + v];
+      go[k] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
     }
-    U2(le)[r0] = x;
+  }
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 5 * NU) {
+      const int le = it / (5 * NU), r = it - le * (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      if (r < NU) x -= rho0;
+      // single precision: the state as deviations from the element's base
+      // state u_b: the linear operators then round the variation within the
+      // element instead of the O(1) values
+      if constexpr (FC) x -= double(xb[k]);
+      XS(le)[r] = R(x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NGL; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 5 * NF) {
+      const int le = it / (5 * NF), r0 = it - le * (5 * NF);
+      U2(le)[r0] = FC ? gx[k] + (gn[k] - go[k]) : gx[k];
+    }
   }
   if (FC && tid < EB) {
     const int e = e0 + tid < E ? e0 + tid : 0;

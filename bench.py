@@ -36,7 +36,7 @@ VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # WRITE_SIZE x 1.000, factors from a 1 GiB copy), recorded in the profile
 # summary of that kernel.  Valid for the kernel as profiled; None once the
 # kernel changes.
-HEX_VOL_P3_FP32_TRAFFIC = None
+HEX_VOL_P3_FP32_TRAFFIC = (309292 * 2 + 276480) * 1024
 
 # FLOP counts of the point-wise physics (multiplies, adds and fused
 # multiply-adds as 2; reciprocal and square root as 1), from the code of the
@@ -66,7 +66,7 @@ def volume_model(kind, p, prec, aa=True, diag=True):
     n, m = p + 1, p + 3
     nu, nf, nq, nfc = NTYPE_PTS[kind](n, m)
     nvf = 4  # mass flux from L(rho v)
-    byts = 5 * nu * 8 + 5 * nf * rb + 4 * nf * rb + nvf * nu * rb + nu * rb + nfc * (8 + 4 * rb) + 10 * rb
+    byts = 5 * nu * 8 + 5 * nf * rb + 4 * nf * rb + nvf * nu * rb + nu * rb + nfc * (16 + 4 * rb) + 10 * rb
     if rb == 4:
         byts += nfc * 5 * 4
     S = 1 if diag else 3  # terms per transformed-flux component

@@ -188,13 +188,25 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
     const size_t e = e0 + le < E ? (size_t)(e0 + le) : 0;
     sS[le][k] = double(met[e * 10 + 9]) * double(met[e * 10 + k]);
   }
-  for (int it = tid; it < EB * 5 * NU; it += NT) {
-    const bool ok = e0 + it / (5 * NU) < E;
-    double x = U[ok ? (size_t)e0 * 5 * NU + it : 0];
-    const int r = it % (5 * NU);
-    if (r >= 4 * NU) x -= eref;
-    if (r < NU) x -= rho0;
-    sU[it] = x;
+  // the state: every thread issues its loads before the first use
+  constexpr int NSL = (EB * 5 * NU + NT - 1) / NT;
+  const int nvs = (E - e0 < EB ? E - e0 : EB) * 5 * NU;
+  double xs[NSL];
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int it = tid + k * NT;
+    xs[k] = U[(size_t)e0 * 5 * NU + (it < nvs ? it : 0)];
+  }
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int it = tid + k * NT;
+    if (it < EB * 5 * NU) {
+      const int r = it % (5 * NU);
+      double x = xs[k];
+      if (r >= 4 * NU) x -= eref;
+      if (r < NU) x -= rho0;
+      sU[it] = x;
+    }
   }
   lds_barrier();
   for (int it = tid; it < EB * NF; it += NT) {

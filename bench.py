@@ -36,7 +36,7 @@ VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # WRITE_SIZE x 1.000, factors from a 1 GiB copy), recorded in the profile
 # summary of that kernel.  Valid for the kernel as profiled; None once the
 # kernel changes.
-HEX_VOL_P3_FP32_TRAFFIC = (309292 * 2 + 276480) * 1024
+HEX_VOL_P3_FP32_TRAFFIC = (286902 * 2 + 276480) * 1024
 
 # FLOP counts of the point-wise physics (multiplies, adds and fused
 # multiply-adds as 2; reciprocal and square root as 1), from the code of the

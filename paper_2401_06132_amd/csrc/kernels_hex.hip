@@ -844,11 +844,13 @@ __global__ void __launch_bounds__(NT)
       for (int v = 0; v < NVF; ++v)
 #pragma unroll
         for (int l = 0; l < n; ++l) acc[d][v][l] = R(0);
-    // double precision up to p = 3: the z levels in a loop, so that the
-    // operator entries of one level are live at a time (fully unrolled, the
-    // FP64 constants of all levels spill out of the scalar registers: 1.81
-    // -> 1.49 ms at p = 3, 48^3; at p = 4 the loop was 5% slower)
-    constexpr int KQ_UNROLL = sizeof(R) == 8 && P <= 3 ? 1 : m;
+    // the z levels in a loop (not unrolled), so that the operator entries of
+    // one level are live at a time.  Fully unrolled, the FP64 constants of
+    // all levels spill out of the scalar registers (p = 3 at 48^3: 1.81 ->
+    // 1.49 ms as a loop); in single precision the loop is 2% faster at p = 3
+    // and 4 (smaller code).  FP64 at p = 4 stays unrolled (the loop was 5%
+    // slower there).
+    constexpr int KQ_UNROLL = sizeof(R) == 8 && P >= 4 ? m : 1;
 #pragma unroll KQ_UNROLL
     for (int kq = 0; kq < m; ++kq) {
       R u[5], q[3][5], f[3][5];
@@ -1269,11 +1271,19 @@ template <> struct HexLaunch<3, true> { static constexpr int EB = 1, NT = 64; };
 template <> struct HexLaunch<4, true> { static constexpr int EB = 1, NT = 64; };    // 49
 
 // with flux anti-aliasing (AA) the footprint of the overlaid LDS regions
-// fits 7 elements per 256-thread workgroup at p = 3 in FP32 (252 quadrature
-// columns instead of 180; two workgroups per CU)
-template <int P, bool DBL, bool AA>
+// fits more elements per workgroup in FP32.  BASE: the affine kernel without
+// surface-flux AA.  p = 3: 6 elements per 256 threads (216 quadrature
+// columns); at 168 VGPRs and 48 KB of LDS three workgroups share a CU (three
+// waves per SIMD): 0.59 -> 0.51 ms at 48^3 against 7 elements (two
+// workgroups per CU; 5 elements: 0.54 ms).  p = 4: 5 elements per 256
+// threads (245 columns): 1.18 -> 1.13 ms against one-element one-wave
+// groups.  The surface-AA and curved kernels keep 7 elements (p = 3) and
+// one-wave groups (p = 4).
+template <int P, bool DBL, bool AA, bool BASE = true>
 struct HexVolLaunch : HexLaunch<P, DBL> {};
-template <> struct HexVolLaunch<3, false, true> { static constexpr int EB = 7, NT = 256; };
+template <> struct HexVolLaunch<3, false, true, true> { static constexpr int EB = 6, NT = 256; };
+template <> struct HexVolLaunch<3, false, true, false> { static constexpr int EB = 7, NT = 256; };
+template <> struct HexVolLaunch<4, false, true, true> { static constexpr int EB = 5, NT = 256; };
 
 // elements per workgroup of the disu kernel (256 threads)
 constexpr int HEX_DISU_EB = 8;
@@ -1291,7 +1301,8 @@ template <int P, typename R, bool BT, bool DIAG, bool AA, bool SAA, bool WARP = 
 static void hex_volume_launch(const TypeArgs& a, int nb, const HexOps<P, R>& op, const Gas<R>& g, double eref,
                               hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  constexpr int EB = HexVolLaunch<P, dbl, AA>::EB, NT = HexVolLaunch<P, dbl, AA>::NT;
+  using L = HexVolLaunch<P, dbl, AA, !SAA && !WARP>;
+  constexpr int EB = L::EB, NT = L::NT;
   hipLaunchKernelGGL((hex_volume<P, R, EB, NT, DIAG, BT, AA, SAA, WARP>), dim3(nb), dim3(NT), 0, st, a.one,
                      a.bt[K_VOLUME], a.segs, a.from_ust, op, g, eref, a.gas->rho_ref);
 }
@@ -1369,7 +1380,9 @@ static void hex_launch(const TypeArgs& a, const int grid[3], hipStream_t st) {
 template <int P, typename R>
 static hipError_t hex_rhs_t(const TypeArgs& a, hipStream_t st) {
   constexpr bool dbl = sizeof(R) == 8;
-  const int ebs[3] = {HEX_DISU_EB, a.aa ? HexVolLaunch<P, dbl, true>::EB : HexVolLaunch<P, dbl, false>::EB,
+  const int ebs[3] = {HEX_DISU_EB,
+                      a.aa ? (a.saa || a.warp ? HexVolLaunch<P, dbl, true, false>::EB : HexVolLaunch<P, dbl, true>::EB)
+                           : HexVolLaunch<P, dbl, false>::EB,
                       a.saa ? HexSurf<P, dbl, true>::EB : HexSurf<P, dbl>::EB};
   const bool bt = a.bt[0] && a.bt[1] && a.bt[2] && a.segs;
   int grid[3];
@@ -1388,9 +1401,10 @@ static int hex_surf_elems(bool d, bool saa) {
 }
 
 template <int P>
-static int hex_vol_elems(bool d, bool aa) {
-  return d ? (aa ? HexVolLaunch<P, true, true>::EB : HexVolLaunch<P, true, false>::EB)
-           : (aa ? HexVolLaunch<P, false, true>::EB : HexVolLaunch<P, false, false>::EB);
+static int hex_vol_elems(bool d, bool aa, bool saa) {
+  if (!aa) return d ? HexVolLaunch<P, true, false>::EB : HexVolLaunch<P, false, false>::EB;
+  return d ? (saa ? HexVolLaunch<P, true, true, false>::EB : HexVolLaunch<P, true, true>::EB)
+           : (saa ? HexVolLaunch<P, false, true, false>::EB : HexVolLaunch<P, false, true>::EB);
 }
 
 int hex_block_elems(int p, int prec, int k, bool aa, bool saa) {
@@ -1406,10 +1420,10 @@ int hex_block_elems(int p, int prec, int k, bool aa, bool saa) {
     return 0;
   }
   switch (p) {
-    case 1: return hex_vol_elems<1>(d, aa);
-    case 2: return hex_vol_elems<2>(d, aa);
-    case 3: return hex_vol_elems<3>(d, aa);
-    case 4: return hex_vol_elems<4>(d, aa);
+    case 1: return hex_vol_elems<1>(d, aa, saa);
+    case 2: return hex_vol_elems<2>(d, aa, saa);
+    case 3: return hex_vol_elems<3>(d, aa, saa);
+    case 4: return hex_vol_elems<4>(d, aa, saa);
   }
   return 0;
 }

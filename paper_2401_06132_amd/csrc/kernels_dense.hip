@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
   }
   lds_barrier();
   for (int it = tid; it < EB * NF; it += NT) {
-    const int le = it / NF, fp = it - le * NF;
+    // element fastest: the lanes of a wave share operator rows (EB lanes a row)
+    const int fp = it / EB, le = it - fp * EB;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     row_cols<NU, 5>(ops + DD::O_M0 + fp * NU, sU + le * 5 * NU, NU, acc);
 #pragma unroll
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__(NT) dense_disu(const Seg sg, const bool from_u
   lds_barrier();
   R* __restrict__ Rp = (R*)sg.Rp;
   for (int it = tid; it < EB * NU; it += NT) {
-    const int le = it / NU, s = it - le * NU, e = e0 + le;
+    const int s = it / EB, le = it - s * EB, e = e0 + le;
     if (e >= E) continue;
     double acc[1] = {0.0};
 #pragma unroll

@@ -578,6 +578,29 @@ __device__ __forceinline__ void mf_acc(typename MfVec<R>::T& acc, const R* __res
   for (int ks = 0; ks < KS; ++ks) acc = MfVec<R>::mfma(a[ks], b[4 * ks * bs], acc);
 }
 
+// The same product in two steps, for a wave that applies one operator tile
+// to several column tiles: the tile's KS values of this lane into
+// registers, then the k-steps against one column
+template <int KS, typename R>
+__device__ __forceinline__ void mf_load(R (&a)[KS], const R* __restrict__ Ap, int lane) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a[ks] = Ap[ks * 64 + lane];
+}
+template <int KS, typename R>
+__device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[KS], const R* bcol, int bs, int lane) {
+  const R* b = bcol + (lane >> 4) * bs;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) acc = MfVec<R>::mfma(a[ks], b[4 * ks * bs], acc);
+}
+// The tiles t = mt NTL + nt (operator row tile mt, column tile nt) of a
+// product, in one contiguous range per wave: a wave reloads its operator
+// tile only where mt changes, so each tile is read from the device table
+// about once per wave instead of once per (mt, nt)
+__device__ __forceinline__ void wave_tiles(int T, int NW, int wave, int& t0, int& t1) {
+  t0 = wave * T / NW;
+  t1 = (wave + 1) * T / NW;
+}
+
 template <int ET, int P, typename R, int EB, int NT, bool AA>
 __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const R* __restrict__ ops,
                                                       const Gas<R> g, const double eref, const double rho0) {
@@ -694,12 +717,19 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // neighbour values: columns (element, variable)
   {
     constexpr int NTL = (5 * EB + 15) / 16;
-    for (int t = wave; t < C::MTF * NTL; t += NW) {
+    int t0, t1, amt = -1;
+    wave_tiles(C::MTF * NTL, NW, wave, t0, t1);
+    R a[C::KSU];
+    for (int t = t0; t < t1; ++t) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
+      if (mt != amt) {
+        mf_load<C::KSU>(a, ops + C::O_PM0 + mt * C::KSU * 64, lane);
+        amt = mt;
+      }
       V4 acc = {R(0), R(0), R(0), R(0)};
-      mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + v * NU, 1, lane);
+      mf_run<C::KSU>(acc, a, XS(le) + v * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -719,14 +749,22 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // point) of [D_d | n_d M3] against [u; jumps]
   {
     constexpr int NTL = (5 * EB + 15) / 16;
-    for (int t = wave; t < C::MTG * NTL; t += NW) {
+    int t0, t1, amt = -1;
+    wave_tiles(C::MTG * NTL, NW, wave, t0, t1);
+    R au[C::KSU], af[C::KSF];
+    for (int t = t0; t < t1; ++t) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 5 * EB;
       const int le = ok ? j / 5 : EB - 1, v = ok ? j % 5 : 0;
-      const R* Ap = ops + C::O_PG + mt * (C::KSU + C::KSF) * 64;
+      if (mt != amt) {
+        const R* Ap = ops + C::O_PG + mt * (C::KSU + C::KSF) * 64;
+        mf_load<C::KSU>(au, Ap, lane);
+        mf_load<C::KSF>(af, Ap + C::KSU * 64, lane);
+        amt = mt;
+      }
       V4 acc = {R(0), R(0), R(0), R(0)};
-      mf_acc<C::KSU>(acc, Ap, XS(le) + v * NU, 1, lane);
-      mf_acc<C::KSF>(acc, Ap + C::KSU * 64, U2(le) + v * NF, 1, lane);
+      mf_run<C::KSU>(acc, au, XS(le) + v * NU, 1, lane);
+      mf_run<C::KSF>(acc, af, U2(le) + v * NF, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -758,12 +796,19 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // element) into U2 rows, then the own normal viscous flux per flux point
   {
     constexpr int NTL = (20 * EB + 15) / 16;
-    for (int t = wave; t < C::MTF * NTL; t += NW) {
+    int t0, t1, amt = -1;
+    wave_tiles(C::MTF * NTL, NW, wave, t0, t1);
+    R a[C::KSU];
+    for (int t = t0; t < t1; ++t) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 20 * EB;
       const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
+      if (mt != amt) {
+        mf_load<C::KSU>(a, ops + C::O_PM0 + mt * C::KSU * 64, lane);
+        amt = mt;
+      }
       V4 acc = {R(0), R(0), R(0), R(0)};
-      mf_acc<C::KSU>(acc, ops + C::O_PM0 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
+      mf_run<C::KSU>(acc, a, XS(le) + c * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -848,12 +893,19 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // column 5 d + v of the point's row
   {
     constexpr int NTL = (20 * EB + 15) / 16;
-    for (int t = wave; t < C::MTQ * NTL; t += NW) {
+    int t0, t1, amt = -1;
+    wave_tiles(C::MTQ * NTL, NW, wave, t0, t1);
+    R a[C::KSU];
+    for (int t = t0; t < t1; ++t) {
       const int mt = t / NTL, nt = t - mt * NTL, j = nt * 16 + (lane & 15);
       const bool ok = j < 20 * EB;
       const int le = ok ? j / 20 : EB - 1, c = ok ? j % 20 : 0;
+      if (mt != amt) {
+        mf_load<C::KSU>(a, ops + C::O_PM7 + mt * C::KSU * 64, lane);
+        amt = mt;
+      }
       V4 acc = {R(0), R(0), R(0), R(0)};
-      mf_acc<C::KSU>(acc, ops + C::O_PM7 + mt * C::KSU * 64, XS(le) + c * NU, 1, lane);
+      mf_run<C::KSU>(acc, a, XS(le) + c * NU, 1, lane);
       if (ok)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {

@@ -613,6 +613,8 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   constexpr int NVF = 4, V0 = 1;
   constexpr bool FC = sizeof(R) == 4;  // constant-flux subtraction (single precision)
   constexpr int PE = C::PE_MF, NW = NT / 64;
+  static_assert(NU * LDW >= 5 * NF + 4 && NQ + 4 <= C::SZ_U2 / LDW && NU + 4 <= C::SZ_U2 / LDW,
+                "padding rows lie after the jumps and inside the element's region");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
   __shared__ FaceRec sFR[EB * NFACE];
@@ -629,8 +631,24 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   const R* __restrict__ fgeo = (const R*)sg.fgeo;
 #define XS(le) (smem + (le)*PE)              /* [20][NU] */
 #define U2(le) (smem + (le)*PE + C::SZ_X + 4) /* [5][NF] | [NF][LDW] | [NQ][LDW] */
-  for (int it = tid; it < EB * PE; it += NT) smem[it] = R(0);
-  lds_barrier();
+  // The products read past a column's end into the next column or into the
+  // padding when a k range is not a multiple of 4; the operator's zero
+  // padding weights those reads, which therefore have to be finite.  Data
+  // regions are always written before they are read; the padding (after the
+  // state and gradients, after the jumps, and the four rows after the
+  // solution-point and quadrature-point rows) is set to zero here.  These
+  // writes touch no location that phase 0 writes, and the barriers before
+  // the first product order them.
+  {
+    constexpr int NZ = 4 + 4 + 8 * LDW;
+    for (int it = tid; it < EB * NZ; it += NT) {
+      const int le = it / NZ, k = it - le * NZ;
+      R* z = k < 4 ? XS(le) + C::SZ_X + k
+                   : (k < 8 ? U2(le) + 5 * NF + (k - 4)
+                            : (k < 8 + 4 * LDW ? U2(le) + NU * LDW + (k - 8) : U2(le) + NQ * LDW + (k - 8 - 4 * LDW)));
+      *z = R(0);
+    }
+  }
 
   // phase 0: as in dense_volume (neighbour face values into U2 as [5][NF]).
   // Every thread issues its state loads before the first barrier and its

@@ -82,7 +82,10 @@ struct DenseCfg {
   // (each region padded so that reads of the zero-weighted k-step padding stay
   // inside it: the matrix-core products read B without bounds checks)
   static constexpr int LDW = 21;
-  static constexpr int U2A = 5 * NF + 4, U2B = LDW * (NF + 4), U2C = LDW * (NQ + 4);
+  // the row layouts hold NF face rows, and the products read 4 KSQ
+  // quadrature rows and 4 KSU solution-point rows (the rows past NQ and NU
+  // are zero padding)
+  static constexpr int U2A = 5 * NF + 4, U2B = LDW * NF, U2C = LDW * 4 * (KSQ > KSU ? KSQ : KSU);
   static constexpr int SZ_U2 = U2A > U2B ? (U2A > U2C ? U2A : U2C) : (U2B > U2C ? U2B : U2C);
   static constexpr int PE_MF = SZ_X + 4 + SZ_U2;
   // face f and point t within the face of flux point fp
@@ -613,7 +616,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   constexpr int NVF = 4, V0 = 1;
   constexpr bool FC = sizeof(R) == 4;  // constant-flux subtraction (single precision)
   constexpr int PE = C::PE_MF, NW = NT / 64;
-  static_assert(NU * LDW >= 5 * NF + 4 && NQ + 4 <= C::SZ_U2 / LDW && NU + 4 <= C::SZ_U2 / LDW,
+  static_assert(NU * LDW >= 5 * NF + 4 && 4 * C::KSQ <= C::SZ_U2 / LDW && 4 * C::KSU <= C::SZ_U2 / LDW,
                 "padding rows lie after the jumps and inside the element's region");
   __shared__ R smem[EB * PE];
   __shared__ R sMet[EB][10];
@@ -635,17 +638,17 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // padding when a k range is not a multiple of 4; the operator's zero
   // padding weights those reads, which therefore have to be finite.  Data
   // regions are always written before they are read; the padding (after the
-  // state and gradients, after the jumps, and the four rows after the
-  // solution-point and quadrature-point rows) is set to zero here.  These
-  // writes touch no location that phase 0 writes, and the barriers before
-  // the first product order them.
+  // state and gradients, after the jumps, and the rows from NU to 4 KSU and
+  // from NQ to 4 KSQ) is set to zero here.  These writes touch no location
+  // that phase 0 writes, and the barriers before the first product order
+  // them.
   {
-    constexpr int NZ = 4 + 4 + 8 * LDW;
+    constexpr int ZU = (4 * C::KSU - NU) * LDW, ZQ = (4 * C::KSQ - NQ) * LDW, NZ = 8 + ZU + ZQ;
     for (int it = tid; it < EB * NZ; it += NT) {
       const int le = it / NZ, k = it - le * NZ;
       R* z = k < 4 ? XS(le) + C::SZ_X + k
                    : (k < 8 ? U2(le) + 5 * NF + (k - 4)
-                            : (k < 8 + 4 * LDW ? U2(le) + NU * LDW + (k - 8) : U2(le) + NQ * LDW + (k - 8 - 4 * LDW)));
+                            : (k < 8 + ZU ? U2(le) + NU * LDW + (k - 8) : U2(le) + NQ * LDW + (k - 8 - ZU)));
       *z = R(0);
     }
   }

@@ -13,11 +13,15 @@
 // groups are those of the hexahedral and prism kernels: disu | volume group
 // | interface group.
 //
-// Dense products C = A B run one operator row per thread: the row is read
-// from the device table into registers (in chunks of KC entries, so long
-// rows at p = 4 stay within the register budget) and applied to the
-// columns of one element held in LDS.  The lanes of a wave work on rows of
-// the same element, so every LDS read is a broadcast.
+// Dense products C = A B on the vector units run one operator row per
+// thread: the row is read from the device table into registers (in chunks
+// of KC entries, so long rows at p = 4 stay within the register budget) and
+// applied to the columns of one element held in LDS.  In the volume and
+// interface kernels the lanes of a wave work on rows of the same element,
+// so every LDS read is a broadcast; the disu kernel runs the element index
+// fastest instead, so that the lanes of a wave share an operator row.  At
+// p >= 3 the volume group runs its products on the matrix cores
+// (dense_volume_mf).
 //
 // Reference tetrahedron {xi, eta, zeta >= -1, xi + eta + zeta <= -1};
 // faces 0..3 = zeta = -1, eta = -1, xi = -1, the slanted face.  Reference
@@ -541,8 +545,11 @@ __global__ void __launch_bounds__(NT) dense_volume(const Seg sg, const bool from
 // and holds, for r < 4, D[4 (l / 16) + r][l % 16] in FP32 and
 // D[l / 16 + 4 r][l % 16] in FP64).  A product C = A B runs over 16 x 16
 // output tiles: rows are operator rows, columns the (element, field) pairs
-// of the workgroup; the waves take tiles in turn.  A comes from the packed
-// operator copy (one coalesced 64-value load per k-step), B from the
+// of the workgroup.  M0, the gradient operator and M7 give each wave a
+// contiguous range of tiles (row tile major), so that a wave loads an
+// operator tile once for its column tiles; the projection-divergence (two
+// or three tiles at p = 3 and 4) gives the waves its tiles in turn.  A comes from the
+// packed operator copy (one coalesced 64-value load per k-step), B from the
 // element's columns in LDS.  Products that feed point-wise physics (face and
 // quadrature values) go through LDS rows; the three directions of the
 // projection-divergence are one product with K concatenated.

@@ -311,6 +311,14 @@ fr_status fr_connectivity(const fr_ctx* c, int64_t* nbr, int8_t* is_left, int64_
 const char* fr_last_error(const fr_ctx* c);
 void fr_destroy(fr_ctx* c);
 
+/* fr_fill_lds: fill the local data share of the current device with `value`
+ * (every CU's 160 KB, by workgroups of 32 KB launched on the HIP stream
+ * hip_stream, NULL for the null stream; asynchronous).  For tests only: it
+ * is for the callers that check that no kernel of this library reads LDS it
+ * has not written, by running them after a fill with NaN.  Errors:
+ * FR_EDEVICE (a HIP call failed). */
+fr_status fr_fill_lds(void* hip_stream, float value);
+
 /* ------------------------------------------------------------------------
  * Serving pool: continuous batching of independent solves.
  *

@@ -28,7 +28,7 @@ _STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "
 # every symbol the header declares
 SYMBOLS = ["fr_physics_default", "fr_create", "fr_mesh_box", "fr_mesh_elements", "fr_layout", "fr_type_count", "fr_upts_coords", "fr_rhs",
            "fr_rhs_noalloc", "fr_rhs_stages", "fr_set_state", "fr_get_state", "fr_rk4_step", "fr_integrals", "fr_ref_operator", "fr_connectivity",
-           "fr_last_error", "fr_destroy", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
+           "fr_last_error", "fr_destroy", "fr_fill_lds", "fr_pool_create", "fr_pool_footprint", "fr_pool_submit", "fr_pool_step",
            "fr_pool_events", "fr_pool_query", "fr_pool_inject_prepare_error", "fr_pool_last_error", "fr_pool_destroy"]
 
 
@@ -96,6 +96,7 @@ def load_library(path=None):
         "fr_connectivity": (I, [P, P, P, ctypes.POINTER(I64)]),
         "fr_last_error": (ctypes.c_char_p, [P]),
         "fr_destroy": (None, [P]),
+        "fr_fill_lds": (I, [P, ctypes.c_float]),
         "fr_pool_create": (I, [ctypes.POINTER(FrPhysics), P, I64, I, ctypes.POINTER(P)]),
         "fr_pool_footprint": (I, [P, ctypes.POINTER(FrRequest), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
         "fr_pool_submit": (I, [P, ctypes.POINTER(FrRequest), ctypes.POINTER(I64)]),
@@ -131,6 +132,15 @@ def ref_operator(etype, p, name):
     out = np.empty(cnt.value, dtype=np.float64)
     _check(None, lib.fr_ref_operator(etype, p, name.encode(), out.ctypes.data, cnt.value, ctypes.byref(cnt)))
     return out
+
+
+def fill_lds(value, stream=None):
+    """Fill the device's LDS with `value` (asynchronous on the HIP stream
+    handle `stream`, default the null stream).  Test support: running the
+    kernels after a fill with NaN shows that none reads LDS it has not
+    written."""
+    lib = load_library()
+    _check(None, lib.fr_fill_lds(stream, float(value)))
 
 
 def _check(ctx, st, pool=False):

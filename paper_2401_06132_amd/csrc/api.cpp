@@ -685,6 +685,10 @@ fr_status fr_integrals(fr_ctx* c, double* out5) {
   return FR_OK;
 }
 
+fr_status fr_fill_lds(void* hip_stream, float value) {
+  return fr::lds_fill(value, (hipStream_t)hip_stream) == hipSuccess ? FR_OK : FR_EDEVICE;
+}
+
 fr_status fr_ref_operator(int etype, int p, const char* name, double* out, int64_t cap, int64_t* count) {
   if (!name || etype < 0 || etype >= fr::NTYPES) return FR_EINVAL;
   if (p < 1 || p > 4) return FR_EUNSUPPORTED;

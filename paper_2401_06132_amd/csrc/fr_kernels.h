@@ -132,6 +132,9 @@ hipError_t dense_rhs(int etype, const TypeArgs& a, int prec, hipStream_t st);
 hipError_t rk_stage(int64_t n, const double* u0, const double* k, double* acc, double* ust, double a, double b,
                     int first, hipStream_t st);
 
+// fills the device's LDS with v (test support: see fr_fill_lds)
+hipError_t lds_fill(float v, hipStream_t st);
+
 // Taylor-Green initial state at the solution points of E affine elements:
 // x = org_e + J_e xi_u (geo: [E][12] = org, J row-major; ref: [N_u][3])
 hipError_t tgv_init(int64_t E, int nu, const double* geo, const double* ref, double gamma, double p0, double* U,

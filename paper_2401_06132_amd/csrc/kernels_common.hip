@@ -66,4 +66,27 @@ hipError_t tgv_init(int64_t E, int nu, const double* geo, const double* ref, dou
   return hipGetLastError();
 }
 
+// Fills the device's LDS with one value: workgroups of 32 KB each (five
+// share a CU's 160 KB), twenty per CU, written through a volatile pointer so
+// that the stores stay.  Kernels launched afterwards then find that value
+// wherever they read LDS that they have not written: tests use it to show
+// that no kernel depends on what earlier kernels left in LDS.
+__global__ void __launch_bounds__(256) lds_fill_kernel(float v) {
+  constexpr int N = 8192;
+  __shared__ float buf[N];
+  volatile float* b = buf;
+  for (int i = threadIdx.x; i < N; i += 256) b[i] = v;
+}
+
+hipError_t lds_fill(float v, hipStream_t st) {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (cus < 1) cus = 1;
+  hipLaunchKernelGGL(lds_fill_kernel, dim3(20 * cus), dim3(256), 0, st, v);
+  return hipGetLastError();
+}
+
 }  // namespace fr

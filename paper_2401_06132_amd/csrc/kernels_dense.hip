@@ -643,19 +643,31 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #define U2(le) (smem + (le)*PE + C::SZ_X + 4) /* [5][NF] | [NF][LDW] | [NQ][LDW] */
   // The products read past a column's end into the next column or into the
   // padding when a k range is not a multiple of 4; the operator's zero
-  // padding weights those reads, which therefore have to be finite.  Data
-  // regions are always written before they are read; the padding (after the
-  // state and gradients, after the jumps, and the rows from NU to 4 KSU and
-  // from NQ to 4 KSQ) is set to zero here.  These writes touch no location
-  // that phase 0 writes, and the barriers before the first product order
-  // them.
+  // padding weights those reads, which therefore have to be finite.  LDS
+  // holds whatever earlier kernels left there, so every location a product
+  // reads is either written before that product or set to zero here:
+  //  * the 4 KSU - NU entries after the state, which the state columns'
+  //    products (phases 1 and 2) read before phase 2 writes the gradients
+  //    there (a gradient written meanwhile is finite as well),
+  //  * the padding after the state and gradients and after the jumps,
+  //  * the rows from NU to 4 KSU and from NQ to 4 KSQ.
+  // These writes touch no location that phase 0 writes, and the barriers
+  // before the first product order them.
   {
-    constexpr int ZU = (4 * C::KSU - NU) * LDW, ZQ = (4 * C::KSQ - NQ) * LDW, NZ = 8 + ZU + ZQ;
+    constexpr int ZX = 4 * C::KSU - NU, ZU = ZX * LDW, ZQ = (4 * C::KSQ - NQ) * LDW, NZ = 8 + ZX + ZU + ZQ;
     for (int it = tid; it < EB * NZ; it += NT) {
       const int le = it / NZ, k = it - le * NZ;
-      R* z = k < 4 ? XS(le) + C::SZ_X + k
-                   : (k < 8 ? U2(le) + 5 * NF + (k - 4)
-                            : (k < 8 + ZU ? U2(le) + NU * LDW + (k - 8) : U2(le) + NQ * LDW + (k - 8 - ZU)));
+      R* z;
+      if (k < 4)
+        z = XS(le) + C::SZ_X + k;
+      else if (k < 8)
+        z = U2(le) + 5 * NF + (k - 4);
+      else if (k < 8 + ZX)
+        z = XS(le) + 5 * NU + (k - 8);
+      else if (k < 8 + ZX + ZU)
+        z = U2(le) + NU * LDW + (k - 8 - ZX);
+      else
+        z = U2(le) + NQ * LDW + (k - 8 - ZX - ZU);
       *z = R(0);
     }
   }

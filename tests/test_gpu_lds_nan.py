@@ -55,3 +55,28 @@ def test_rhs_after_lds_filled_with_nan(dims, p, kind, prec, aa):
                   for g, t in zip(s.split(du), m.types)], axis=0)
     print("rel err per variable", err, flush=True)
     assert np.all(err < TOL[prec]), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,p,kind,saa", [((2, 2, 2), 3, "hex", True), ((2, 2, 2), 4, "hex", True),
+                                              ((2, 2, 2), 3, "prism", True), ((2, 2, 2), 4, "prism", True),
+                                              ((2, 2, 2), 3, "hex_warp", False), ((2, 2, 2), 4, "hex_warp", False),
+                                              ((2, 2, 2), 3, "prism_warp", False)])
+def test_surface_aa_and_curved_after_lds_filled_with_nan(dims, p, kind, saa, prec):
+    """The same for the surface-flux anti-aliasing and curved-element kernels
+    (curved FP32 held to 1e-4, as in test_gpu_parity.py)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("lds-nan case", dims, p, kind, prec, "saa" if saa else "", flush=True)
+    m = Mesh(*dims, p, kind, surf_aa=saa)
+    U = inputs.element_state([m.upts_coords(t) for t in m.types], seed=4)
+    ref = oracle_rhs(m, {t: u.astype(np.longdouble) for t, u in zip(m.types, U)}, Params(pref=inputs.P0),
+                     dtype=np.longdouble)
+    s = frmi.Solver(dims, p, kind, prec=prec, pref=inputs.P0, rho_ref=inputs.RHO0, surface_aa=saa)
+    du = _staged_rhs_after_nan_fills(s, np.concatenate([x.reshape(-1) for x in U]))
+    assert np.all(np.isfinite(du)), "non-finite output"
+    err = np.max([(np.abs(g - ref[t]).max(axis=(0, 2)) / np.abs(ref[t]).max(axis=(0, 2))).astype(np.float64)
+                  for g, t in zip(s.split(du), m.types)], axis=0)
+    tol = 1e-4 if (prec == "fp32" and "warp" in kind) else TOL[prec]
+    print("rel err per variable", err, flush=True)
+    assert np.all(err < tol), err

@@ -625,13 +625,25 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   constexpr int PE = C::PE_MF, NW = NT / 64;
   static_assert(NU * LDW >= 5 * NF + 4 && 4 * C::KSQ <= C::SZ_U2 / LDW && 4 * C::KSU <= C::SZ_U2 / LDW,
                 "padding rows lie after the jumps and inside the element's region");
-  __shared__ R smem[EB * PE];
+  // RIN: the face records and face geometry of each element sit in its U2
+  // region after the NF face rows (16-byte aligned), where nothing is
+  // written before the quadrature values (phase 4), after their last reads
+  // (phase 3a); the zero padding rows lie elsewhere (NU rows below NF, NQ
+  // rows above)
+  constexpr int AL = 16 / (int)sizeof(R), ROFF = (C::SZ_X + 4 + NF * LDW + AL - 1) / AL * AL;
+  constexpr int RSZ = NFACE * (16 + 4 * (int)sizeof(R)) / (int)sizeof(R);
+  constexpr bool RIN = PE % AL == 0 && ROFF + RSZ <= PE && ROFF + RSZ <= C::SZ_X + 4 + NQ * LDW &&
+                       4 * C::KSU <= NF;
+  __shared__ __align__(16) R smem[EB * PE];
   __shared__ R sMet[EB][10];
-  __shared__ FaceRec sFR[EB * NFACE];
-  __shared__ R sFG[EB * NFACE][4];
+  __shared__ FaceRec sFRA[RIN ? 1 : EB * NFACE];
+  __shared__ R sFGA[RIN ? 1 : EB * NFACE * 4];
   __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
   __shared__ R sFc[EB][12];
   __shared__ R sUb[EB][5];  // single precision: the element's base state
+#define FRQ(le, f) (RIN ? ((FaceRec*)(smem + (le)*PE + ROFF))[f] : sFRA[(le)*NFACE + (f)])
+#define FGQ(le, f, k) (RIN ? (smem + (le)*PE + ROFF + NFACE * 16 / (int)sizeof(R))[4 * (f) + (k)] \
+                           : sFGA[((le)*NFACE + (f)) * 4 + (k)])
   const int e0 = blockIdx.x * EB, E = sg.E, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const double* __restrict__ U = from_ust ? sg.ust : sg.U;
   const R* __restrict__ Uf = (const R*)sg.Uf;
@@ -692,9 +704,10 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   }
   for (int it = tid; it < EB * NFACE; it += NT) {
     const int slot = sg.slot_base + (e0 + it / NFACE < E ? e0 * NFACE + it : 0);
-    sFR[it] = sg.faces[slot];
+    const int le = it / NFACE, f = it - le * NFACE;
+    FRQ(le, f) = sg.faces[slot];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sFG[it][k] = fgeo[4 * slot + k];
+    for (int k = 0; k < 4; ++k) FGQ(le, f, k) = fgeo[4 * slot + k];
   }
   for (int it = tid; it < sg.nperm * NFPS; it += NT) sPerm[it] = sg.perms[it];
   for (int it = tid; it < EB * 10; it += NT) {
@@ -710,7 +723,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int itc = it < EB * 5 * NF ? it : 0;
     const int le = itc / (5 * NF), r0 = itc - le * (5 * NF), v = r0 / NF, fp = r0 - v * NF;
     const int f = C::face_of(fp), t = C::point_of(fp);
-    const FaceRec fr = sFR[le * NFACE + f];
+    const FaceRec fr = FRQ(le, f);
     gx[k] = Uf[(size_t)fr.npo * 5 + v * C::fsz(f) + sPerm[(fr.info >> 1) * NFPS + t]];
     if constexpr (FC) {
       // neighbour value relative to this element's base state
@@ -775,7 +788,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
         for (int r = 0; r < 4; ++r) {
           const int fp = mt * 16 + MfVec<R>::row(lane, r);
           if (fp < NF) {
-            const bool left = sFR[le * NFACE + C::face_of(fp)].info & 1;
+            const bool left = FRQ(le, C::face_of(fp)).info & 1;
             const R w = left ? R(0.5) + g.beta : R(0.5) - g.beta;
             R* J = U2(le) + v * NF + fp;
             *J = w * (*J - acc[r]);
@@ -862,9 +875,9 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     const int le = it / NF, fp = it - le * NF, e = e0 + le;
     if (e >= E) continue;
     const R* w = U2(le) + fp * LDW;
-    const int f = C::face_of(fp), t = C::point_of(fp), lf = le * NFACE + f;
-    const R sgn = (sFR[lf].info & 1) ? R(1) : R(-1);
-    const R nn[3] = {sgn * sFG[lf][0], sgn * sFG[lf][1], sgn * sFG[lf][2]};
+    const int f = C::face_of(fp), t = C::point_of(fp);
+    const R sgn = (FRQ(le, f).info & 1) ? R(1) : R(-1);
+    const R nn[3] = {sgn * FGQ(le, f, 0), sgn * FGQ(le, f, 1), sgn * FGQ(le, f, 2)};
     R u[5], q[3][5], V[4];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -1004,6 +1017,8 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   }
 #undef XS
 #undef U2
+#undef FRQ
+#undef FGQ
 }
 
 // -------------------------------------------------------------- surface

@@ -361,12 +361,23 @@ def main():
     import paper_2401_06132_amd as frmi
     torch.cuda.set_device(0)
     if args.copy_probe:
+        # a 1 GiB device-to-device copy: calibrates the HBM byte counters and
+        # gives the copy bandwidth (bytes read + written per second), the
+        # practical ceiling of a streaming kernel
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        t1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "copies": 3}))
+        ms = t0.elapsed_time(t1) / 10
+        nb = src.numel() * 4
+        print(json.dumps({"copy_probe_bytes_each_way": nb, "copies": 13, "ms_per_copy": round(ms, 4),
+                          "copy_GBs": round(2 * nb / (ms * 1e-3) / 1e9, 1)}))
         return
     if args.serving_only:
         sv = run_serving(frmi, torch, args.serving_budget_gib, args.serving_slots, args.serving_requests)

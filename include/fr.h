@@ -258,12 +258,15 @@ fr_status fr_rhs(fr_ctx* c, const double* u_dev, double* du_dev);
 #define FR_NOALLOC_MAX_BYTES (64LL << 20)
 fr_status fr_rhs_noalloc(fr_ctx* c, const double* u_dev, double* du_dev);
 
-/* Profiling aid: enqueue only some kernel groups of fr_rhs on the context
- * stream.  mask bit 0: disu (solution at flux points), bit 1: volume group
- * (common solution, corrected gradients, anti-aliased flux, projection and
- * divergence), bit 2: interface group (common flux, lifting, final scaling).
- * A run without all three bits leaves du incomplete; it exists so that a
- * benchmark can time one group in the launch configuration of fr_rhs.
+/* Profiling and test aid: enqueue only some kernel groups of fr_rhs on the
+ * context stream.  mask bit 0: disu (solution at flux points), bit 1: volume
+ * group (common solution, corrected gradients, anti-aliased flux, projection
+ * and divergence), bit 2: interface group (common flux, lifting, final
+ * scaling).  A run without all three bits leaves du incomplete; it exists so
+ * that a benchmark can time one group in the launch configuration of fr_rhs,
+ * and so that a test can run the groups one at a time (calls with masks 1, 2
+ * and 4 in turn give fr_rhs's result: the work buffers persist between
+ * calls).
  * Errors as fr_rhs; FR_EINVAL if mask is 0 or > 7. */
 fr_status fr_rhs_stages(fr_ctx* c, const double* u_dev, double* du_dev, int mask);
 

@@ -82,10 +82,15 @@ struct DenseCfg {
   // LDS per element of the matrix-core volume kernel: state + gradients
   // [20][NU], then one region holding in turn the jumps [5][NF], the face
   // values [NF][LDW] and the quadrature values, later the transformed flux,
-  // [NQ][LDW] (odd row stride: a thread's row reads spread over the banks)
+  // [NQ][LDW].  Rows of 20 values, 16-byte aligned: a thread reads its row as
+  // 16-byte words (five per row, consecutive rows 80 bytes apart, so a
+  // wave's reads spread over the banks), and the matrix-core outputs, four
+  // rows apart per lane group, land 320 bytes apart (disjoint banks).  The
+  // transformed flux F~_d of variable v (1..4) overwrites the row's columns
+  // 4 d + v - 1.
   // (each region padded so that reads of the zero-weighted k-step padding stay
   // inside it: the matrix-core products read B without bounds checks)
-  static constexpr int LDW = 21;
+  static constexpr int LDW = 20;
   // the row layouts hold NF face rows, and the products read 4 KSQ
   // quadrature rows and 4 KSU solution-point rows (the rows past NQ and NU
   // are zero padding)
@@ -625,6 +630,8 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   constexpr int PE = C::PE_MF, NW = NT / 64;
   static_assert(NU * LDW >= 5 * NF + 4 && 4 * C::KSQ <= C::SZ_U2 / LDW && 4 * C::KSU <= C::SZ_U2 / LDW,
                 "padding rows lie after the jumps and inside the element's region");
+  static_assert((LDW * sizeof(R)) % 16 == 0 && ((C::SZ_X + 4) * sizeof(R)) % 16 == 0 && (PE * sizeof(R)) % 16 == 0,
+                "rows start on 16-byte boundaries");
   // RIN: the face records and face geometry of each element sit in its U2
   // region after the NF face rows (16-byte aligned), where nothing is
   // written before the quadrature values (phase 4), after their last reads
@@ -874,7 +881,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   for (int it = tid; it < EB * NF; it += NT) {
     const int le = it / NF, fp = it - le * NF, e = e0 + le;
     if (e >= E) continue;
-    const R* w = U2(le) + fp * LDW;
+    const R* w = (const R*)__builtin_assume_aligned(U2(le) + fp * LDW, 16);
     const int f = C::face_of(fp), t = C::point_of(fp);
     const R sgn = (FRQ(le, f).info & 1) ? R(1) : R(-1);
     const R nn[3] = {sgn * FGQ(le, f, 0), sgn * FGQ(le, f, 1), sgn * FGQ(le, f, 2)};
@@ -908,13 +915,14 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       }
       point_flux(u, q, g, f);
       const R dj = sMet[le][9];
-      R* w = U2(le) + s0 * LDW;
+      R* w = (R*)__builtin_assume_aligned(U2(le) + s0 * LDW, 16);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = V0; v < 5; ++v)
-          w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
-                         (FC ? sFc[le][d * 4 + v - 1] : R(0));
+          w[4 * d + v - 1] =
+              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+              (FC ? sFc[le][d * 4 + v - 1] : R(0));
     }
     lds_barrier();
     constexpr int NTL = (NVF * EB + 15) / 16;
@@ -925,7 +933,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const R* Ap = ops + C::O_PK0 + mt * 3 * C::KSU * 64;
       V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int d = 0; d < 3; ++d) mf_acc<C::KSU>(acc, Ap + d * C::KSU * 64, U2(le) + d * 5 + v, LDW, lane);
+      for (int d = 0; d < 3; ++d) mf_acc<C::KSU>(acc, Ap + d * C::KSU * 64, U2(le) + 4 * d + v - 1, LDW, lane);
       const int e = e0 + le;
       if (ok && e < E)
 #pragma unroll
@@ -970,7 +978,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   lds_barrier();
   for (int it = tid; it < EB * NQ; it += NT) {
     const int le = it / NQ, q0 = it - le * NQ;
-    R* w = U2(le) + q0 * LDW;
+    R* w = (R*)__builtin_assume_aligned(U2(le) + q0 * LDW, 16);
     R u[5], q[3][5], f[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -984,8 +992,8 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int v = V0; v < 5; ++v)
-        w[d * 5 + v] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
-                       (FC ? sFc[le][d * 4 + v - 1] : R(0));
+        w[4 * d + v - 1] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
+                           (FC ? sFc[le][d * 4 + v - 1] : R(0));
   }
   lds_barrier();
 
@@ -1001,7 +1009,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       V4 acc = {R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        mf_acc<C::KSQ>(acc, Ap + d * C::KSQ * 64, U2(le) + d * 5 + v, LDW, lane);
+        mf_acc<C::KSQ>(acc, Ap + d * C::KSQ * 64, U2(le) + 4 * d + v - 1, LDW, lane);
       const int e = e0 + le;
       if (ok && e < E)
 #pragma unroll

@@ -96,7 +96,10 @@ struct DenseCfg {
   // are zero padding)
   static constexpr int U2A = 5 * NF + 4, U2B = LDW * NF, U2C = LDW * 4 * (KSQ > KSU ? KSQ : KSU);
   static constexpr int SZ_U2 = U2A > U2B ? (U2A > U2C ? U2A : U2C) : (U2B > U2C ? U2B : U2C);
-  static constexpr int PE_MF = SZ_X + 4 + SZ_U2;
+  // the padding after the state and gradients that the last column's
+  // k range reads (a multiple of 4 values, so that U2 stays 16-byte aligned)
+  static constexpr int XPAD = (4 * KSU - NU + 3) / 4 * 4;
+  static constexpr int PE_MF = SZ_X + XPAD + SZ_U2;
   // face f and point t within the face of flux point fp
   // (branch-free: with a select here the compiler kept the operator loops of
   // both cases live in the callers, tripling their registers)
@@ -607,6 +610,21 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) acc = MfVec<R>::mfma(a[ks], b[4 * ks * bs], acc);
 }
+// LEAN: the matrix-core volume kernel keeps the element metrics, base
+// states, constant fluxes and the permutation table out of its own LDS
+// arrays (global reads, the permutations in element 0's region, the rest
+// copied into the dead state region once the quadrature values are
+// formed), so that its LDS is the element regions alone; and it asks for
+// six waves per SIMD (at most 80 VGPRs).  Single-precision tetrahedra at
+// p = 3 with flux anti-aliasing: 4 elements x 1680 values = 26 880 bytes,
+// exactly 21 of the CU's 128 LDS allocation blocks of 1280 bytes, so six
+// workgroups share a CU instead of five.
+template <int ET, int P, typename R, bool AA>
+struct MfLean {
+  static constexpr bool value = ET == 2 && P == 3 && sizeof(R) == 4 && AA;
+  static constexpr int min_waves = value ? 6 : 1;
+};
+
 // The tiles t = mt NTL + nt (operator row tile mt, column tile nt) of a
 // product, in one contiguous range per wave: a wave reloads its operator
 // tile only where mt changes, so each tile is read from the device table
@@ -617,8 +635,9 @@ __device__ __forceinline__ void wave_tiles(int T, int NW, int wave, int& t0, int
 }
 
 template <int ET, int P, typename R, int EB, int NT, bool AA>
-__global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool from_ust, const R* __restrict__ ops,
-                                                      const Gas<R> g, const double eref, const double rho0) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MfLean<ET, P, R, AA>::min_waves)))
+    dense_volume_mf(const Seg sg, const bool from_ust, const R* __restrict__ ops, const Gas<R> g,
+                    const double eref, const double rho0) {
   using C = DenseCfg<ET, P>;
   using V4 = typename MfVec<R>::T;
   constexpr int NU = C::NU, NF = C::NF, NQ = C::NQ, NFPS = C::NFPS, NFACE = C::NFACE, LDW = C::LDW;
@@ -630,24 +649,33 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   constexpr int PE = C::PE_MF, NW = NT / 64;
   static_assert(NU * LDW >= 5 * NF + 4 && 4 * C::KSQ <= C::SZ_U2 / LDW && 4 * C::KSU <= C::SZ_U2 / LDW,
                 "padding rows lie after the jumps and inside the element's region");
-  static_assert((LDW * sizeof(R)) % 16 == 0 && ((C::SZ_X + 4) * sizeof(R)) % 16 == 0 && (PE * sizeof(R)) % 16 == 0,
+  static_assert((LDW * sizeof(R)) % 16 == 0 && ((C::SZ_X + C::XPAD) * sizeof(R)) % 16 == 0 &&
+                    (PE * sizeof(R)) % 16 == 0,
                 "rows start on 16-byte boundaries");
+  constexpr bool LEAN = MfLean<ET, P, R, AA>::value;
   // RIN: the face records and face geometry of each element sit in its U2
   // region after the NF face rows (16-byte aligned), where nothing is
   // written before the quadrature values (phase 4), after their last reads
   // (phase 3a); the zero padding rows lie elsewhere (NU rows below NF, NQ
   // rows above)
-  constexpr int AL = 16 / (int)sizeof(R), ROFF = (C::SZ_X + 4 + NF * LDW + AL - 1) / AL * AL;
+  constexpr int AL = 16 / (int)sizeof(R), ROFF = (C::SZ_X + C::XPAD + NF * LDW + AL - 1) / AL * AL;
   constexpr int RSZ = NFACE * (16 + 4 * (int)sizeof(R)) / (int)sizeof(R);
-  constexpr bool RIN = PE % AL == 0 && ROFF + RSZ <= PE && ROFF + RSZ <= C::SZ_X + 4 + NQ * LDW &&
+  constexpr bool RIN = PE % AL == 0 && ROFF + RSZ <= PE && ROFF + RSZ <= C::SZ_X + C::XPAD + NQ * LDW &&
                        4 * C::KSU <= NF;
+  // LEAN: the permutation table after element 0's face records (read by
+  // the gather of phase 0 only); the metrics, base state and constant flux
+  // of element le at XS(le) + [0, 27) once the quadrature values are formed
+  constexpr int POFF = ROFF + RSZ;
+  static_assert(!LEAN || (RIN && FC && AA && POFF + MAX_PERMS * NFPS / (int)sizeof(R) <= C::SZ_X + C::XPAD + NQ * LDW),
+                "the lean layout's permutation table fits before the quadrature rows are written");
   __shared__ __align__(16) R smem[EB * PE];
-  __shared__ R sMet[EB][10];
+  __shared__ R sMetA[LEAN ? 1 : EB][10];
   __shared__ FaceRec sFRA[RIN ? 1 : EB * NFACE];
   __shared__ R sFGA[RIN ? 1 : EB * NFACE * 4];
-  __shared__ uint8_t sPerm[MAX_PERMS * NFPS];
-  __shared__ R sFc[EB][12];
-  __shared__ R sUb[EB][5];  // single precision: the element's base state
+  __shared__ uint8_t sPermA[LEAN ? 1 : MAX_PERMS * NFPS];
+  __shared__ R sFcA[LEAN ? 1 : EB][12];
+  __shared__ R sUbA[LEAN ? 1 : EB][5];  // single precision: the element's base state
+  uint8_t* const sPerm = LEAN ? (uint8_t*)(smem + POFF) : sPermA;
 #define FRQ(le, f) (RIN ? ((FaceRec*)(smem + (le)*PE + ROFF))[f] : sFRA[(le)*NFACE + (f)])
 #define FGQ(le, f, k) (RIN ? (smem + (le)*PE + ROFF + NFACE * 16 / (int)sizeof(R))[4 * (f) + (k)] \
                            : sFGA[((le)*NFACE + (f)) * 4 + (k)])
@@ -659,7 +687,18 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   const R* __restrict__ met = (const R*)sg.met;
   const R* __restrict__ fgeo = (const R*)sg.fgeo;
 #define XS(le) (smem + (le)*PE)              /* [20][NU] */
-#define U2(le) (smem + (le)*PE + C::SZ_X + 4) /* [5][NF] | [NF][LDW] | [NQ][LDW] */
+#define U2(le) (smem + (le)*PE + C::SZ_X + C::XPAD) /* [5][NF] | [NF][LDW] | [NQ][LDW] */
+  // metrics, base state and constant flux of element le: LDS arrays, or
+  // (LEAN) global reads before the quadrature phase and XS(le) + [0, 27)
+  // from it on (QP: the quadrature-phase copy)
+  auto ec = [&](int le) { return (size_t)(e0 + le < E ? e0 + le : e0); };
+  auto metg = [&](int le, int k) -> R { return LEAN ? met[ec(le) * 10 + k] : sMetA[LEAN ? 0 : le][k]; };
+  auto ubg = [&](int le, int v) -> R {
+    return LEAN ? R(sg.Ub[(size_t)(sg.slot_base + ec(le) * NFACE) * 5 + v]) : sUbA[LEAN ? 0 : le][v];
+  };
+#define METQ(le, k) (LEAN ? XS(le)[k] : sMetA[LEAN ? 0 : (le)][k])
+#define UBQ(le, v) (LEAN ? XS(le)[10 + (v)] : sUbA[LEAN ? 0 : (le)][v])
+#define FCQ(le, k) (LEAN ? XS(le)[15 + (k)] : sFcA[LEAN ? 0 : (le)][k])
   // The products read past a column's end into the next column or into the
   // padding when a k range is not a multiple of 4; the operator's zero
   // padding weights those reads, which therefore have to be finite.  LDS
@@ -673,20 +712,21 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   // These writes touch no location that phase 0 writes, and the barriers
   // before the first product order them.
   {
-    constexpr int ZX = 4 * C::KSU - NU, ZU = ZX * LDW, ZQ = (4 * C::KSQ - NQ) * LDW, NZ = 8 + ZX + ZU + ZQ;
+    constexpr int XP = C::XPAD, ZX = 4 * C::KSU - NU, ZU = ZX * LDW, ZQ = (4 * C::KSQ - NQ) * LDW;
+    constexpr int NZ = XP + 4 + ZX + ZU + ZQ;
     for (int it = tid; it < EB * NZ; it += NT) {
       const int le = it / NZ, k = it - le * NZ;
       R* z;
-      if (k < 4)
+      if (k < XP)
         z = XS(le) + C::SZ_X + k;
-      else if (k < 8)
-        z = U2(le) + 5 * NF + (k - 4);
-      else if (k < 8 + ZX)
-        z = XS(le) + 5 * NU + (k - 8);
-      else if (k < 8 + ZX + ZU)
-        z = U2(le) + NU * LDW + (k - 8 - ZX);
+      else if (k < XP + 4)
+        z = U2(le) + 5 * NF + (k - XP);
+      else if (k < XP + 4 + ZX)
+        z = XS(le) + 5 * NU + (k - XP - 4);
+      else if (k < XP + 4 + ZX + ZU)
+        z = U2(le) + NU * LDW + (k - XP - 4 - ZX);
       else
-        z = U2(le) + NQ * LDW + (k - 8 - ZX - ZU);
+        z = U2(le) + NQ * LDW + (k - XP - 4 - ZX - ZU);
       *z = R(0);
     }
   }
@@ -717,10 +757,11 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     for (int k = 0; k < 4; ++k) FGQ(le, f, k) = fgeo[4 * slot + k];
   }
   for (int it = tid; it < sg.nperm * NFPS; it += NT) sPerm[it] = sg.perms[it];
-  for (int it = tid; it < EB * 10; it += NT) {
-    const int le = it / 10, k = it - le * 10;
-    sMet[le][k] = met[e0 + le < E ? (size_t)(e0 + le) * 10 + k : 0];
-  }
+  if constexpr (!LEAN)
+    for (int it = tid; it < EB * 10; it += NT) {
+      const int le = it / 10, k = it - le * 10;
+      sMetA[le][k] = met[e0 + le < E ? (size_t)(e0 + le) * 10 + k : 0];
+    }
   lds_barrier();
   R gx[NGL];
   float gn[FC ? NGL : 1], go[FC ? NGL : 1];
@@ -764,12 +805,20 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
   }
   if (FC && tid < EB) {
     const int e = e0 + tid < E ? e0 + tid : 0;
-    const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, &sMet[tid][0], g, &sFc[tid][0]);
+    if constexpr (LEAN) {
+      R fc[12];
+      const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, met + (size_t)e * 10, g, fc);
+      if (e0 + tid < E)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sUb[tid][v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
-    if (e0 + tid < E)
+        for (int k = 0; k < 12; ++k) sg.fbar[(size_t)e * 12 + k] = fc[k];
+    } else {
+      const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, &sMetA[tid][0], g, &sFcA[tid][0]);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) sg.fbar[(size_t)e * 12 + k] = sFc[tid][k];
+      for (int v = 0; v < 5; ++v) sUbA[tid][v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+      if (e0 + tid < E)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sg.fbar[(size_t)e * 12 + k] = sFcA[tid][k];
+    }
   }
   lds_barrier();
 
@@ -847,7 +896,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       const R g0 = X[(5 + v) * NU + s], g1 = X[(10 + v) * NU + s], g2 = X[(15 + v) * NU + s];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        X[(5 + c * 5 + v) * NU + s] = sMet[le][c] * g0 + sMet[le][3 + c] * g1 + sMet[le][6 + c] * g2;
+        X[(5 + c * 5 + v) * NU + s] = metg(le, c) * g0 + metg(le, 3 + c) * g1 + metg(le, 6 + c) * g2;
     }
   }
   lds_barrier();
@@ -888,7 +937,7 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     R u[5], q[3][5], V[4];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
+      u[v] = w[v] + (FC ? ubg(le, v) : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
@@ -909,20 +958,20 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
       R u[5], q[3][5], f[3][5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        u[v] = X[v * NU + s0] + (FC ? sUb[le][v] : R(0));
+        u[v] = X[v * NU + s0] + (FC ? UBQ(le, v) : R(0));
 #pragma unroll
         for (int c = 0; c < 3; ++c) q[c][v] = X[(5 + c * 5 + v) * NU + s0];
       }
       point_flux(u, q, g, f);
-      const R dj = sMet[le][9];
+      const R dj = METQ(le, 9);
       R* w = (R*)__builtin_assume_aligned(U2(le) + s0 * LDW, 16);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int v = V0; v < 5; ++v)
           w[4 * d + v - 1] =
-              dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
-              (FC ? sFc[le][d * 4 + v - 1] : R(0));
+              dj * (METQ(le, 3 * d) * f[0][v] + METQ(le, 3 * d + 1) * f[1][v] + METQ(le, 3 * d + 2) * f[2][v]) -
+              (FC ? FCQ(le, d * 4 + v - 1) : R(0));
     }
     lds_barrier();
     constexpr int NTL = (NVF * EB + 15) / 16;
@@ -976,24 +1025,38 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
     }
   }
   lds_barrier();
+  if constexpr (LEAN) {
+    // the state region is dead now: element le's metrics, base state and
+    // constant flux go to XS(le) + [0, 27) for the flux of every point
+    if (tid < EB) {
+      R* x = XS(tid);
+      const size_t e = ec(tid);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) x[k] = met[e * 10 + k];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[10 + v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+      const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, met + e * 10, g, x + 15);
+    }
+    lds_barrier();
+  }
   for (int it = tid; it < EB * NQ; it += NT) {
     const int le = it / NQ, q0 = it - le * NQ;
     R* w = (R*)__builtin_assume_aligned(U2(le) + q0 * LDW, 16);
     R u[5], q[3][5], f[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      u[v] = w[v] + (FC ? sUb[le][v] : R(0));
+      u[v] = w[v] + (FC ? UBQ(le, v) : R(0));
 #pragma unroll
       for (int c = 0; c < 3; ++c) q[c][v] = w[5 + c * 5 + v];
     }
     point_flux(u, q, g, f);
-    const R dj = sMet[le][9];
+    const R dj = METQ(le, 9);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int v = V0; v < 5; ++v)
-        w[4 * d + v - 1] = dj * (sMet[le][3 * d] * f[0][v] + sMet[le][3 * d + 1] * f[1][v] + sMet[le][3 * d + 2] * f[2][v]) -
-                           (FC ? sFc[le][d * 4 + v - 1] : R(0));
+        w[4 * d + v - 1] = dj * (METQ(le, 3 * d) * f[0][v] + METQ(le, 3 * d + 1) * f[1][v] + METQ(le, 3 * d + 2) * f[2][v]) -
+                           (FC ? FCQ(le, d * 4 + v - 1) : R(0));
   }
   lds_barrier();
 
@@ -1027,6 +1090,9 @@ __global__ void __launch_bounds__(NT) dense_volume_mf(const Seg sg, const bool f
 #undef U2
 #undef FRQ
 #undef FGQ
+#undef METQ
+#undef UBQ
+#undef FCQ
 }
 
 // -------------------------------------------------------------- surface

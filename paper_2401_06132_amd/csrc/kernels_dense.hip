@@ -621,7 +621,7 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 // workgroups share a CU instead of five.
 template <int ET, int P, typename R, bool AA>
 struct MfLean {
-  static constexpr bool value = ET == 2 && P == 3 && sizeof(R) == 4 && AA;
+  static constexpr bool value = P == 3 && sizeof(R) == 4 && AA;
   static constexpr int min_waves = value ? 6 : 1;
 };
 
@@ -1354,7 +1354,7 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     // VALU kernel is faster.
     constexpr bool MF = P >= 3 && !(sizeof(R) == 8 && !DenseCfg<ET, P>::PYR && P >= 4);
     // FP64 doubles the LDS per element: half the elements per workgroup
-    constexpr int EBM = sizeof(R) == 8 ? (EB > 1 ? EB / 2 : 1) : EB;
+    constexpr int EBM = sizeof(R) == 8 ? (EB > 1 ? EB / 2 : 1) : (DenseCfg<ET, P>::PYR && P == 3 ? 3 : EB);
     if constexpr (MF) {
       if (a.aa)
         hipLaunchKernelGGL((dense_volume_mf<ET, P, R, EBM, 256, true>), dim3((E + EBM - 1) / EBM), dim3(256), 0, st,

@@ -615,10 +615,13 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 // arrays (global reads, the permutations in element 0's region, the rest
 // copied into the dead state region once the quadrature values are
 // formed), so that its LDS is the element regions alone; and it asks for
-// six waves per SIMD (at most 80 VGPRs).  Single-precision tetrahedra at
-// p = 3 with flux anti-aliasing: 4 elements x 1680 values = 26 880 bytes,
-// exactly 21 of the CU's 128 LDS allocation blocks of 1280 bytes, so six
-// workgroups share a CU instead of five.
+// six waves per SIMD (at most 80 VGPRs).  Single precision at p = 3 with
+// flux anti-aliasing; the CU's LDS is allocated in 128 blocks of 1280 bytes:
+//  * tetrahedra, 4 elements x 1680 values = 26 880 bytes, exactly 21
+//    blocks: six workgroups share a CU instead of five;
+//  * pyramids, 3 elements per workgroup (dense_rhs_t) x 1884 values =
+//    22 608 bytes (18 blocks) at 65 VGPRs: seven workgroups instead of five
+//    of four elements.
 template <int ET, int P, typename R, bool AA>
 struct MfLean {
   static constexpr bool value = P == 3 && sizeof(R) == 4 && AA;
@@ -1353,7 +1356,8 @@ static hipError_t dense_rhs_t(const TypeArgs& a, hipStream_t st) {
     // against 16.7 on the VALU).  At p <= 2 the tiles are too small and the
     // VALU kernel is faster.
     constexpr bool MF = P >= 3 && !(sizeof(R) == 8 && !DenseCfg<ET, P>::PYR && P >= 4);
-    // FP64 doubles the LDS per element: half the elements per workgroup
+    // FP64 doubles the LDS per element: half the elements per workgroup;
+    // FP32 pyramids at p = 3: three (seven workgroups per CU, MfLean)
     constexpr int EBM = sizeof(R) == 8 ? (EB > 1 ? EB / 2 : 1) : (DenseCfg<ET, P>::PYR && P == 3 ? 3 : EB);
     if constexpr (MF) {
       if (a.aa)

@@ -615,16 +615,18 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 // arrays (global reads, the permutations in element 0's region, the rest
 // copied into the dead state region once the quadrature values are
 // formed), so that its LDS is the element regions alone; and it asks for
-// six waves per SIMD (at most 80 VGPRs).  Single precision at p = 3 with
-// flux anti-aliasing; the CU's LDS is allocated in 128 blocks of 1280 bytes:
+// six waves per SIMD (at most 80 VGPRs).  At p = 3 with flux anti-aliasing;
+// the CU's LDS is allocated in 128 blocks of 1280 bytes:
 //  * tetrahedra, 4 elements x 1680 values = 26 880 bytes, exactly 21
 //    blocks: six workgroups share a CU instead of five;
 //  * pyramids, 3 elements per workgroup (dense_rhs_t) x 1884 values =
 //    22 608 bytes (18 blocks) at 65 VGPRs: seven workgroups instead of five
-//    of four elements.
+//    of four elements;
+//  * double-precision tetrahedra, 2 elements x 1680 values x 8 bytes =
+//    26 880 bytes: six workgroups instead of five.
 template <int ET, int P, typename R, bool AA>
 struct MfLean {
-  static constexpr bool value = P == 3 && sizeof(R) == 4 && AA;
+  static constexpr bool value = P == 3 && AA && (sizeof(R) == 4 || ET == 2);
   static constexpr int min_waves = value ? 6 : 1;
 };
 
@@ -669,7 +671,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MfLean<
   // the gather of phase 0 only); the metrics, base state and constant flux
   // of element le at XS(le) + [0, 27) once the quadrature values are formed
   constexpr int POFF = ROFF + RSZ;
-  static_assert(!LEAN || (RIN && FC && AA && POFF + MAX_PERMS * NFPS / (int)sizeof(R) <= C::SZ_X + C::XPAD + NQ * LDW),
+  static_assert(!LEAN || (RIN && AA && POFF + MAX_PERMS * NFPS / (int)sizeof(R) <= C::SZ_X + C::XPAD + NQ * LDW),
                 "the lean layout's permutation table fits before the quadrature rows are written");
   __shared__ __align__(16) R smem[EB * PE];
   __shared__ R sMetA[LEAN ? 1 : EB][10];
@@ -1036,9 +1038,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MfLean<
       const size_t e = ec(tid);
 #pragma unroll
       for (int k = 0; k < 10; ++k) x[k] = met[e * 10 + k];
+      if constexpr (FC) {  // single precision: base state and constant flux
 #pragma unroll
-      for (int v = 0; v < 5; ++v) x[10 + v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
-      const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, met + e * 10, g, x + 15);
+        for (int v = 0; v < 5; ++v) x[10 + v] = sg.Ub[(size_t)(sg.slot_base + e * NFACE) * 5 + v];
+        const_flux(sg.Ub + (size_t)(sg.slot_base + e * NFACE) * 5, met + e * 10, g, x + 15);
+      }
     }
     lds_barrier();
   }

@@ -100,6 +100,11 @@ struct DenseCfg {
   // k range reads (a multiple of 4 values, so that U2 stays 16-byte aligned)
   static constexpr int XPAD = (4 * KSU - NU + 3) / 4 * 4;
   static constexpr int PE_MF = SZ_X + XPAD + SZ_U2;
+  // without anti-aliasing there are no quadrature rows: U2 holds the jumps,
+  // the NF face rows and the 4 KSU solution-point rows of the flux
+  static constexpr int U2D = LDW * 4 * KSU;
+  static constexpr int SZ_U2_NOAA = U2A > U2B ? (U2A > U2D ? U2A : U2D) : (U2B > U2D ? U2B : U2D);
+  static constexpr int PE_MF_NOAA = SZ_X + XPAD + SZ_U2_NOAA;
   // face f and point t within the face of flux point fp
   // (branch-free: with a select here the compiler kept the operator loops of
   // both cases live in the callers, tripling their registers)
@@ -627,7 +632,9 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 template <int ET, int P, typename R, bool AA>
 struct MfLean {
   static constexpr bool value = P == 3 && AA && (sizeof(R) == 4 || ET == 2);
-  static constexpr int min_waves = value ? 6 : 1;
+  // without anti-aliasing the element regions hold no quadrature rows and
+  // the LDS allows more than six workgroups; six waves per SIMD all the same
+  static constexpr int min_waves = P == 3 && (sizeof(R) == 4 || ET == 2) ? 6 : 1;
 };
 
 // The tiles t = mt NTL + nt (operator row tile mt, column tile nt) of a
@@ -651,8 +658,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MfLean<
   // projected
   constexpr int NVF = 4, V0 = 1;
   constexpr bool FC = sizeof(R) == 4;  // constant-flux subtraction (single precision)
-  constexpr int PE = C::PE_MF, NW = NT / 64;
-  static_assert(NU * LDW >= 5 * NF + 4 && 4 * C::KSQ <= C::SZ_U2 / LDW && 4 * C::KSU <= C::SZ_U2 / LDW,
+  constexpr int PE = AA ? C::PE_MF : C::PE_MF_NOAA, NW = NT / 64;
+  static_assert(NU * LDW >= 5 * NF + 4 && (!AA || 4 * C::KSQ <= C::SZ_U2 / LDW) &&
+                    4 * C::KSU * LDW <= PE - C::SZ_X - C::XPAD,
                 "padding rows lie after the jumps and inside the element's region");
   static_assert((LDW * sizeof(R)) % 16 == 0 && ((C::SZ_X + C::XPAD) * sizeof(R)) % 16 == 0 &&
                     (PE * sizeof(R)) % 16 == 0,
@@ -717,7 +725,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MfLean<
   // These writes touch no location that phase 0 writes, and the barriers
   // before the first product order them.
   {
-    constexpr int XP = C::XPAD, ZX = 4 * C::KSU - NU, ZU = ZX * LDW, ZQ = (4 * C::KSQ - NQ) * LDW;
+    constexpr int XP = C::XPAD, ZX = 4 * C::KSU - NU, ZU = ZX * LDW, ZQ = AA ? (4 * C::KSQ - NQ) * LDW : 0;
     constexpr int NZ = XP + 4 + ZX + ZU + ZQ;
     for (int it = tid; it < EB * NZ; it += NT) {
       const int le = it / NZ, k = it - le * NZ;

@@ -628,13 +628,18 @@ __device__ __forceinline__ void mf_run(typename MfVec<R>::T& acc, const R (&a)[K
 //    22 608 bytes (18 blocks) at 65 VGPRs: seven workgroups instead of five
 //    of four elements;
 //  * double-precision tetrahedra, 2 elements x 1680 values x 8 bytes =
-//    26 880 bytes: six workgroups instead of five.
+//    26 880 bytes: six workgroups instead of five;
+//  * double-precision pyramids, 2 elements x 1884 values x 8 bytes =
+//    30 144 bytes (24 blocks) at most 96 VGPRs: five workgroups instead of
+//    four.
 template <int ET, int P, typename R, bool AA>
 struct MfLean {
-  static constexpr bool value = P == 3 && AA && (sizeof(R) == 4 || ET == 2);
+  static constexpr bool value = P == 3 && AA;
   // without anti-aliasing the element regions hold no quadrature rows and
-  // the LDS allows more than six workgroups; six waves per SIMD all the same
-  static constexpr int min_waves = P == 3 && (sizeof(R) == 4 || ET == 2) ? 6 : 1;
+  // the LDS allows more than six workgroups; six waves per SIMD all the
+  // same.  Double-precision pyramids (2 elements, 30 144 bytes: five
+  // workgroups) ask for five.
+  static constexpr int min_waves = P != 3 ? 1 : (sizeof(R) == 8 && ET == 3 ? 5 : 6);
 };
 
 // The tiles t = mt NTL + nt (operator row tile mt, column tile nt) of a
